@@ -1,0 +1,194 @@
+"""Python face of the CPU FP64 reference for exact Reverse k-MIPS.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the benchmark's
+CPU-baseline leg, never by the product path.  It shares no code with the GPU
+library; it receives the same seeded input arrays and computes every result from
+its definition (see rkmips_oracle.c for the definitions and the readings taken).
+
+Functions (all inputs are numpy arrays in storage format: float32, uint16 BF16 bits
+or uint8 FP8 e4m3 codes with float32 per-row scales):
+
+* ``lambda_table``   lambda_u^(j), j = 1..k_max, per user (Def. 1; Alg. 4)
+* ``member``         membership of user u in R_k(q)   (Def. 1, ">=" tie reading)
+* ``count_beating``  #{p : s(u,p) > s(u,q)}           (Def. 1, count form)
+* ``item_order``     canonical squared norms and descending order (Alg. 4 / Alg. 1)
+* ``partitions``, ``saalsh_index``, ``user_codes``, ``saalsh_decide``  (Alg. 1, 2)
+* ``rkmips``         per-query ascending user-ID lists
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rkmips_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liborc.so")
+_DT = {"f32": 0, "bf16": 1, "fp8": 2}
+_lib = None
+
+NTHREADS = int(os.environ.get("RKMIPS_ORACLE_THREADS", "0")) or (os.cpu_count() or 1)
+
+
+def build(force: bool = False) -> str:
+    """Compile the reference with gcc (strict IEEE: no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+                               "-std=c99", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _lib.orc_e4m3_value.restype = C.c_double
+        _lib.orc_e4m3_value.argtypes = [C.c_uint8]
+        _lib.orc_score.restype = C.c_double
+        _lib.orc_norm2.restype = C.c_double
+    return _lib
+
+
+def _p(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _c(a, dt=None):
+    if a is None:
+        return None
+    return np.ascontiguousarray(a if dt is None else a.astype(dt, copy=False))
+
+
+def _sel(user_idx, m):
+    if user_idx is None:
+        return None, m
+    ui = _c(np.asarray(user_idx), np.int64)
+    return ui, len(ui)
+
+
+def e4m3_value(code: int) -> float:
+    return _L().orc_e4m3_value(code)
+
+
+def score(dtype, a, a_scales, ra, b, b_scales, rb) -> float:
+    a, b = _c(a), _c(b)
+    return _L().orc_score(_DT[dtype], a.shape[1], _p(a), _p(_c(a_scales, np.float32)), C.c_int64(ra),
+                          _p(b), _p(_c(b_scales, np.float32)), C.c_int64(rb))
+
+
+def lambda_table(dtype, P, P_scales, U, U_scales, k_max, user_idx=None, nthreads=None):
+    """float64 [k_max x m_sel] (k-major): row j is lambda^(j+1) of each selected user."""
+    P, U = _c(P), _c(U)
+    ui, ms = _sel(user_idx, U.shape[0])
+    lam = np.empty((k_max, ms), dtype=np.float64)
+    r = _L().orc_lambda(_DT[dtype], P.shape[1], _p(P), _p(_c(P_scales, np.float32)),
+                        C.c_int64(P.shape[0]), _p(U), _p(_c(U_scales, np.float32)), _p(ui),
+                        C.c_int64(ms), k_max, _p(lam), nthreads or NTHREADS)
+    if r:
+        raise MemoryError("oracle lambda table")
+    return lam
+
+
+def member(dtype, U, U_scales, Q, Q_scales, ks, lam, user_idx=None, nthreads=None):
+    """uint8 [nq x m_sel]: 1 iff s(u,q) >= lambda_u^(k_q)."""
+    U, Q = _c(U), _c(Q)
+    ui, ms = _sel(user_idx, U.shape[0])
+    ks = _c(np.asarray(ks), np.int32)
+    lam = _c(lam, np.float64)
+    out = np.empty((Q.shape[0], ms), dtype=np.uint8)
+    r = _L().orc_member(_DT[dtype], U.shape[1], _p(U), _p(_c(U_scales, np.float32)), _p(ui),
+                        C.c_int64(ms), _p(Q), _p(_c(Q_scales, np.float32)), C.c_int64(Q.shape[0]),
+                        _p(ks), _p(lam), lam.shape[0], _p(out), nthreads or NTHREADS)
+    if r:
+        raise ValueError("k outside [1, k_max]")
+    return out
+
+
+def count_beating(dtype, P, P_scales, U, U_scales, Q, Q_scales, user_idx=None, nthreads=None):
+    """int64 [nq x m_sel]: #{p in P : s(u,p) > s(u,q)}."""
+    P, U, Q = _c(P), _c(U), _c(Q)
+    ui, ms = _sel(user_idx, U.shape[0])
+    out = np.empty((Q.shape[0], ms), dtype=np.int64)
+    _L().orc_count_beating(_DT[dtype], P.shape[1], _p(P), _p(_c(P_scales, np.float32)),
+                           C.c_int64(P.shape[0]), _p(U), _p(_c(U_scales, np.float32)), _p(ui),
+                           C.c_int64(ms), _p(Q), _p(_c(Q_scales, np.float32)),
+                           C.c_int64(Q.shape[0]), _p(out), nthreads or NTHREADS)
+    return out
+
+
+def rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, nthreads=None):
+    """Per-query ascending user-ID lists plus the lambda table."""
+    lam = lambda_table(dtype, P, P_scales, U, U_scales, k_max, nthreads=nthreads)
+    mem = member(dtype, U, U_scales, Q, Q_scales, ks, lam, nthreads=nthreads)
+    return [np.flatnonzero(row).astype(np.int32) for row in mem], lam
+
+
+def item_order(dtype, P, P_scales):
+    """(norm2 float64 [n], order int64 [n]): canonical n2 and descending order."""
+    P = _c(P)
+    n = P.shape[0]
+    n2 = np.empty(n, dtype=np.float64)
+    order = np.empty(n, dtype=np.int64)
+    _L().orc_item_order(_DT[dtype], P.shape[1], _p(P), _p(_c(P_scales, np.float32)),
+                        C.c_int64(n), _p(n2), _p(order))
+    return n2, order
+
+
+def partitions(norm2, order, b):
+    """int64 partition starts into ``order`` (length t+1)."""
+    norm2, order = _c(norm2, np.float64), _c(order, np.int64)
+    n = len(order)
+    ps = np.empty(n + 2, dtype=np.int64)
+    t = _L().orc_partitions(_p(norm2), _p(order), C.c_int64(n), C.c_float(b), _p(ps), n + 1)
+    return ps[: t + 1].copy()
+
+
+def saalsh_index(dtype, P, P_scales, order, part_start, A):
+    """(centroid [t x d] f64, radius [t] f64, codes uint32 [n x K/32]) of Alg. 1."""
+    P = _c(P)
+    A = _c(A, np.float32)
+    order, part_start = _c(order, np.int64), _c(part_start, np.int64)
+    n, d = P.shape
+    K = A.shape[1]
+    t = len(part_start) - 1
+    cen = np.empty((t, d), dtype=np.float64)
+    rad = np.empty(t, dtype=np.float64)
+    codes = np.empty((n, K // 32), dtype=np.uint32)
+    _L().orc_saalsh_index(_DT[dtype], d, _p(P), _p(_c(P_scales, np.float32)), C.c_int64(n),
+                          _p(order), _p(part_start), t, _p(A), K, _p(cen), _p(rad), _p(codes))
+    return cen, rad, codes
+
+
+def user_codes(dtype, U, U_scales, A):
+    U = _c(U)
+    A = _c(A, np.float32)
+    m, d = U.shape
+    K = A.shape[1]
+    codes = np.empty((m, K // 32), dtype=np.uint32)
+    _L().orc_user_codes(_DT[dtype], d, _p(U), _p(_c(U_scales, np.float32)), C.c_int64(m),
+                        _p(A), K, _p(codes))
+    return codes
+
+
+def saalsh_decide(dtype, P, P_scales, norm2, order, part_start, item_codes, ucode, beta,
+                  U, U_scales, u, Q, Q_scales, qi, k):
+    """(answer 0/1, phi) of Alg. 2 for user u, query qi and k."""
+    P, U, Q = _c(P), _c(U), _c(Q)
+    phi = C.c_double(0.0)
+    ucode = _c(np.asarray(ucode), np.uint32)
+    K = ucode.shape[-1] * 32
+    r = _L().orc_saalsh_decide(_DT[dtype], P.shape[1], _p(P), _p(_c(P_scales, np.float32)),
+                               _p(_c(norm2, np.float64)), _p(_c(order, np.int64)),
+                               _p(_c(part_start, np.int64)), len(part_start) - 1,
+                               _p(_c(item_codes, np.uint32)), _p(ucode), K, C.c_float(beta),
+                               _p(U), _p(_c(U_scales, np.float32)), C.c_int64(u),
+                               _p(Q), _p(_c(Q_scales, np.float32)), C.c_int64(qi), k,
+                               C.byref(phi))
+    if r < 0:
+        raise MemoryError("oracle saalsh_decide")
+    return r, phi.value
