@@ -1,0 +1,454 @@
+// C ABI of the exact RkMIPS library: argument validation, the index object and the
+// orchestration of the build and query kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "index.h"
+#include "internal.h"
+#include "query.h"
+
+namespace rk {
+
+static thread_local std::string g_last_error;
+
+void fail(rkmips_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) fail(RKMIPS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int elt_bytes(int dtype) { return dtype == RKMIPS_F32 ? 4 : dtype == RKMIPS_BF16 ? 2 : 1; }
+
+int padded_dim(int d, int /*dtype*/)
+{
+    for (int p : {32, 64, 128, 256})
+        if (d <= p) return p;
+    return -1;
+}
+
+// ---------------------------------------------------------------- device buffers
+DevBuf::~DevBuf() { reset(); }
+void DevBuf::reset()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+void DevBuf::alloc(size_t b)
+{
+    reset();
+    if (b == 0) b = 16;
+    if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        fail(RKMIPS_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+}
+
+// Error bound of the fast scores relative to ||u|| ||x||: twice the classical
+// gamma_{d+2} = (d+2)u / (1 - (d+2)u), u = 2^-24 (the factor 2 covers the matrix
+// cores' unspecified summation order and rounding), plus the FP64 canonical form's own
+// gamma_d at u = 2^-53.
+double fast_err_rel(int d)
+{
+    const double u = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    const double g = (d + 2) * u / (1.0 - (d + 2) * u);
+    const double g64 = d * u64 / (1.0 - d * u64);
+    return 2.0 * g + g64;
+}
+
+static float ev_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms;
+}
+
+struct Events {
+    std::vector<hipEvent_t> ev;
+    explicit Events(int k)
+    {
+        ev.resize(k, nullptr);
+        for (auto& e : ev) HIPC(hipEventCreate(&e));
+    }
+    ~Events()
+    {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// ---------------------------------------------------------------- build
+static void validate_params(const rkmips_params& p)
+{
+    if (p.k_max < 1 || p.k_max > 256) fail(RKMIPS_EINVAL, "k_max must be in [1, 256]");
+    if (p.leaf_size < 1 || p.leaf_size > 64) fail(RKMIPS_EINVAL, "leaf_size must be in [1, 64]");
+    if (p.num_hash < 32 || p.num_hash > 256 || p.num_hash % 32) fail(RKMIPS_EINVAL, "num_hash must be 32..256, a multiple of 32");
+    if (p.topk_slack < 0 || p.topk_slack > 256) fail(RKMIPS_EINVAL, "topk_slack must be in [0, 256]");
+    if (!(p.b > 0.f && p.b < 1.f)) fail(RKMIPS_EINVAL, "b must be in (0, 1)");
+    if (!(p.probe_frac > 0.f && p.probe_frac <= 1.f)) fail(RKMIPS_EINVAL, "probe_frac must be in (0, 1]");
+    if (p.mode != 0) fail(RKMIPS_EINVAL, "mode must be 0 (exact)");
+}
+
+// Candidate buffer geometry of the lambda pass.
+static void choose_topk(Index& x)
+{
+    int C = x.prm.k_max + x.prm.topk_slack;
+    x.C = C;
+    int gpl = 2;
+    while (gpl * 64 < 2 * C || gpl * 64 < C + 32) gpl *= 2;
+    if (gpl > 8) fail(RKMIPS_EINVAL, "k_max + topk_slack too large (at most 224)");
+    x.G = gpl * 64;
+    // item segments: enough workgroups to cover the chip a few times
+    const int upb = topk_users_per_block(x.dtype, x.ld);
+    const int64_t tiles = (x.m + upb - 1) / upb;
+    int nseg = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+    nseg = std::min(nseg, std::max(1, 512 / C));
+    nseg = (int)std::min<int64_t>(nseg, std::max<int64_t>(1, x.n / 256));
+    nseg = std::min(nseg, 8);
+    int64_t seg_len = (x.n + nseg - 1) / nseg;
+    seg_len = (seg_len + 63) / 64 * 64;
+    nseg = (int)((x.n + seg_len - 1) / seg_len);
+    x.nseg = nseg;
+    x.seg_len = seg_len;
+}
+
+static void build_lambda(Index& x, hipStream_t s)
+{
+    choose_topk(x);
+    const int64_t m = x.m;
+    DevBuf buf, cnt, tau, fail_list, fail_count, errbits;
+    buf.alloc(sizeof(uint2) * (size_t)m * x.nseg * x.G);
+    cnt.alloc(sizeof(int) * (size_t)m * x.nseg);
+    tau.alloc(sizeof(float) * (size_t)m * x.nseg);
+    fail_list.alloc(sizeof(int) * (size_t)m);
+    fail_count.alloc(sizeof(int));
+    errbits.alloc(2 * sizeof(unsigned long long));
+    HIPC(hipMemsetAsync(fail_count.p, 0, sizeof(int), s));
+    HIPC(hipMemsetAsync(errbits.p, 0, 2 * sizeof(unsigned long long), s));
+    x.lam64.alloc(sizeof(double) * (size_t)x.prm.k_max * m);
+    x.lam32.alloc(sizeof(float) * (size_t)x.prm.k_max * m);
+
+    TopkArgs ta{};
+    ta.items = x.items.p; ta.item_scales = x.item_scales.f(); ta.n = x.n;
+    ta.users = x.users.p; ta.user_scales = x.user_scales.f(); ta.m = m;
+    ta.d = x.d; ta.ld = x.ld; ta.nseg = x.nseg; ta.seg_len = x.seg_len; ta.C = x.C; ta.G = x.G;
+    ta.buf = (uint2*)buf.p; ta.cnt = (int*)cnt.p; ta.tau = (float*)tau.p;
+    Events ev(3);
+    HIPC(hipEventRecord(ev.ev[0], s));
+    launch_topk(x.dtype, ta, s);
+    HIPC(hipEventRecord(ev.ev[1], s));
+
+    RefineArgs ra{};
+    ra.items = x.items.p; ra.item_scales = x.item_scales.f(); ra.n = x.n;
+    ra.users = x.users.p; ra.user_scales = x.user_scales.f(); ra.m = m;
+    ra.d = x.d; ra.ld = x.ld; ra.nseg = x.nseg; ra.C = x.C; ra.G = x.G; ra.k_max = x.prm.k_max;
+    ra.buf = (const uint2*)buf.p; ra.cnt = (const int*)cnt.p; ra.tau = (const float*)tau.p;
+    ra.item_n2_sorted = x.item_n2.d(); ra.seg_len = x.seg_len; ra.user_n2 = x.user_n2.d();
+    ra.force_fail = (x.prm.flags & RKMIPS_FLAG_NO_CERT) ? 1 : 0;
+    ra.lam64 = x.lam64.d(); ra.lam32 = x.lam32.f();
+    ra.fail_list = (int*)fail_list.p; ra.fail_count = (int*)fail_count.p;
+    ra.max_raw_err_bits = (unsigned long long*)errbits.p;
+    ra.err_rel = fast_err_rel(x.d);
+    launch_refine(x.dtype, ra, s);
+    int nfail = 0;
+    HIPC(hipMemcpyAsync(&nfail, fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    x.cert_failures = nfail;
+    if (nfail > 0) {
+        const int64_t rows = std::min<int64_t>(nfail, 256);
+        DevBuf scratch;
+        scratch.alloc(sizeof(double) * (size_t)rows * x.n);
+        launch_fallback(x.dtype, ra, nfail, scratch.d(), rows, s);
+        HIPC(hipStreamSynchronize(s));
+    }
+    launch_lambda32_err(x.lam64.d(), x.lam32.f(), (int64_t)x.prm.k_max * m,
+                        (unsigned long long*)errbits.p + 1, s);
+    HIPC(hipEventRecord(ev.ev[2], s));
+    unsigned long long eb[2];
+    HIPC(hipMemcpyAsync(eb, errbits.p, sizeof eb, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    double e0, e1;
+    std::memcpy(&e0, &eb[0], 8);
+    std::memcpy(&e1, &eb[1], 8);
+    x.max_rel_err_raw = e0;
+    x.max_rel_err_l32 = e1;
+    x.ms_lambda = ev_ms(ev.ev[0], ev.ev[1]);
+    x.ms_refine = ev_ms(ev.ev[1], ev.ev[2]);
+    // keep the raw candidates for inspection (per leaf-order user)
+    x.cand.swap(buf);
+    x.cand_cnt.swap(cnt);
+    x.cand_tau.swap(tau);
+}
+
+static void build_index(Index& x, const void* items, const float* item_scales, const void* users,
+                        const float* user_scales, const float* srp, hipStream_t s)
+{
+    const int64_t n = x.n, m = x.m;
+    const int eb = elt_bytes(x.dtype);
+    Events ev(4);
+    HIPC(hipEventRecord(ev.ev[0], s));
+    // ---- validation + canonical norms of the caller's arrays
+    DevBuf bad, n2_items_orig, n2_users_orig;
+    bad.alloc(sizeof(int));
+    n2_items_orig.alloc(sizeof(double) * n);
+    n2_users_orig.alloc(sizeof(double) * m);
+    HIPC(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    launch_norm2(x.dtype, items, item_scales, n, x.d, x.d, n2_items_orig.d(), (int*)bad.p, s);
+    launch_norm2(x.dtype, users, user_scales, m, x.d, x.d, n2_users_orig.d(), (int*)bad.p, s);
+    int hbad = 0;
+    HIPC(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hbad) fail(RKMIPS_EINVAL, "non-finite value (or NaN code / non-finite scale) in items or users");
+    range_check(x, n2_items_orig.d(), n, n2_users_orig.d(), m, s);
+
+    // ---- item order (descending canonical norm, ties by index)
+    int64_t cap = 2;
+    while (cap < n) cap <<= 1;
+    DevBuf keys, vals;
+    keys.alloc(sizeof(uint64_t) * cap);
+    vals.alloc(sizeof(uint32_t) * cap);
+    launch_norm_keys(n2_items_orig.d(), n, cap, (uint64_t*)keys.p, (uint32_t*)vals.p, s);
+    sort_pairs((uint64_t*)keys.p, (uint32_t*)vals.p, n, cap, s);
+    x.item_order.alloc(sizeof(uint32_t) * n);
+    HIPC(hipMemcpyAsync(x.item_order.p, vals.p, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+    x.item_n2.alloc(sizeof(double) * n);
+    launch_permute_f64(n2_items_orig.d(), x.item_order.u32(), n, x.item_n2.d(), s);
+    x.items.alloc((size_t)n * x.ld * eb);
+    if (x.dtype == RKMIPS_FP8_E4M3) x.item_scales.alloc(sizeof(float) * n);
+    launch_gather_rows(x.dtype, items, x.d, item_scales, x.item_order.u32(), n, x.d, x.items.p, x.ld,
+                       x.item_scales.f(), s);
+    HIPC(hipEventRecord(ev.ev[1], s));
+
+    // ---- Cone-Tree over user directions; users are stored in leaf order
+    build_cone(x, users, user_scales, n2_users_orig.d(), s);
+    HIPC(hipEventRecord(ev.ev[2], s));
+
+    // ---- exact lambda table
+    build_lambda(x, s);
+
+    // ---- per-block quantities that need lambda (L^j(B)) and the SA-ALSH index
+    finish_blocks(x, s);
+    build_saalsh(x, srp, s);
+    HIPC(hipEventRecord(ev.ev[3], s));
+    HIPC(hipStreamSynchronize(s));
+    x.ms_norms = ev_ms(ev.ev[0], ev.ev[1]);
+    x.ms_cone = ev_ms(ev.ev[1], ev.ev[2]);
+    x.ms_total = ev_ms(ev.ev[0], ev.ev[3]);
+}
+
+// Refuse magnitudes where the FP32 fast path could overflow or lose the error model.
+void range_check(Index& x, const double* n2i, int64_t n, const double* n2u, int64_t m, hipStream_t s)
+{
+    std::vector<double> a(n), b(m);
+    HIPC(hipMemcpyAsync(a.data(), n2i, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(b.data(), n2u, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    double mi = 0, mu = 0, lo = INFINITY;
+    for (double v : a) { mi = std::max(mi, v); if (v > 0) lo = std::min(lo, v); }
+    for (double v : b) { mu = std::max(mu, v); if (v > 0) lo = std::min(lo, v); }
+    if (std::sqrt(mi) * std::sqrt(mu) > 1e30) fail(RKMIPS_ERANGE, "max||u|| * max||p|| exceeds 1e30");
+    if (lo < 1e-60) fail(RKMIPS_ERANGE, "a non-zero vector norm is below 1e-30");
+    x.max_item_norm = std::sqrt(mi);
+    x.max_user_norm = std::sqrt(mu);
+}
+
+Index::~Index()
+{
+    (void)hipDeviceSynchronize();
+}
+
+}  // namespace rk
+
+using namespace rk;
+
+template <typename F>
+static rkmips_status guarded(F&& f)
+{
+    try {
+        g_last_error.clear();
+        f();
+        return RKMIPS_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return RKMIPS_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return RKMIPS_EDEVICE;
+    }
+}
+
+namespace rk {
+rkmips_status guarded_call(void (*fn)(void*), void* ctx)
+{
+    return guarded([&] { fn(ctx); });
+}
+}  // namespace rk
+
+extern "C" {
+
+void rkmips_default_params(rkmips_params* p)
+{
+    if (!p) return;
+    p->k_max = 50;
+    p->leaf_size = 64;
+    p->num_hash = 128;
+    p->topk_slack = 14;
+    p->b = 0.5f;
+    p->probe_frac = 0.1f;
+    p->seed = 221112751ull;
+    p->mode = 0;
+    p->flags = 0;
+}
+
+const char* rkmips_last_error(void) { return g_last_error.c_str(); }
+
+rkmips_status rkmips_build_index(const void* items, const float* item_scales, int64_t n, const void* users,
+                                 const float* user_scales, int64_t m, int32_t d, int32_t dtype,
+                                 const float* srp_proj, const rkmips_params* p, void* stream,
+                                 rkmips_index** out)
+{
+    return guarded([&] {
+        if (!out) fail(RKMIPS_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!items || !users) fail(RKMIPS_EINVAL, "items/users is NULL");
+        if (n < 1 || m < 1) fail(RKMIPS_EINVAL, "n and m must be >= 1");
+        if (n > (int64_t)1 << 30 || m > (int64_t)1 << 30) fail(RKMIPS_EINVAL, "n and m must be <= 2^30");
+        if (d < 1 || d > 256) fail(RKMIPS_EINVAL, "d must be in [1, 256]");
+        if (dtype != RKMIPS_F32 && dtype != RKMIPS_BF16 && dtype != RKMIPS_FP8_E4M3)
+            fail(RKMIPS_EINVAL, "unknown dtype");
+        const bool fp8 = dtype == RKMIPS_FP8_E4M3;
+        if (fp8 && (!item_scales || !user_scales)) fail(RKMIPS_EINVAL, "FP8 data needs item and user scales");
+        if (!fp8 && (item_scales || user_scales)) fail(RKMIPS_EINVAL, "scales are only for FP8 data");
+        rkmips_params prm;
+        if (p) prm = *p;
+        else rkmips_default_params(&prm);
+        validate_params(prm);
+        std::unique_ptr<Index> x(new Index());
+        x->n = n; x->m = m; x->d = d; x->dtype = dtype; x->prm = prm;
+        x->ld = padded_dim(d, dtype);
+        HIPC(hipGetDevice(&x->device));
+        build_index(*x, items, item_scales, users, user_scales, srp_proj, (hipStream_t)stream);
+        *out = (rkmips_index*)x.release();
+    });
+}
+
+void rkmips_index_free(rkmips_index* idx) { delete (Index*)idx; }
+
+rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
+{
+    return guarded([&] {
+        if (!idx || !o) fail(RKMIPS_EINVAL, "NULL argument");
+        const Index& x = *(const Index*)idx;
+        std::memset(o, 0, sizeof *o);
+        o->n = x.n; o->m = x.m; o->d = x.d; o->dtype = x.dtype; o->k_max = x.prm.k_max;
+        o->cand_per_user = x.C * x.nseg; o->num_hash = x.prm.num_hash; o->leaf_size = x.prm.leaf_size;
+        o->num_partitions = x.t; o->num_blocks = x.nblocks; o->cert_failures = x.cert_failures;
+        o->max_rel_err_raw = x.max_rel_err_raw; o->max_rel_err_lambda32 = x.max_rel_err_l32;
+        o->ms_norms = x.ms_norms; o->ms_lambda = x.ms_lambda; o->ms_refine = x.ms_refine;
+        o->ms_saalsh = x.ms_saalsh; o->ms_cone = x.ms_cone; o->ms_total = x.ms_total;
+        o->device_bytes = x.device_bytes();
+    });
+}
+
+rkmips_status rkmips_get_lambda(const rkmips_index* idx, int32_t k, double* out_m)
+{
+    return guarded([&] {
+        if (!idx || !out_m) fail(RKMIPS_EINVAL, "NULL argument");
+        const Index& x = *(const Index*)idx;
+        if (k < 1 || k > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
+        std::vector<double> row(x.m);
+        std::vector<uint32_t> perm(x.m);
+        HIPC(hipMemcpy(row.data(), x.lam64.d() + (int64_t)(k - 1) * x.m, sizeof(double) * x.m, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < x.m; i++) out_m[perm[i]] = row[i];
+    });
+}
+
+rkmips_status rkmips_get_lambda32(const rkmips_index* idx, int32_t k, float* out_m)
+{
+    return guarded([&] {
+        if (!idx || !out_m) fail(RKMIPS_EINVAL, "NULL argument");
+        const Index& x = *(const Index*)idx;
+        if (k < 1 || k > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
+        std::vector<float> row(x.m);
+        std::vector<uint32_t> perm(x.m);
+        HIPC(hipMemcpy(row.data(), x.lam32.f() + (int64_t)(k - 1) * x.m, sizeof(float) * x.m, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < x.m; i++) out_m[perm[i]] = row[i];
+    });
+}
+
+rkmips_status rkmips_get_item_order(const rkmips_index* idx, int64_t* order, double* norm2)
+{
+    return guarded([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
+        const Index& x = *(const Index*)idx;
+        if (order) {
+            std::vector<uint32_t> o(x.n);
+            HIPC(hipMemcpy(o.data(), x.item_order.p, sizeof(uint32_t) * x.n, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < x.n; i++) order[i] = o[i];
+        }
+        if (norm2) HIPC(hipMemcpy(norm2, x.item_n2.p, sizeof(double) * x.n, hipMemcpyDeviceToHost));
+    });
+}
+
+rkmips_status rkmips_get_candidates(const rkmips_index* idx, int32_t* ids, float* scores, float* tau)
+{
+    return guarded([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
+        const Index& x = *(const Index*)idx;
+        if (!x.cand.p) fail(RKMIPS_EINVAL, "candidates are not kept by this index");
+        const int64_t per = (int64_t)x.nseg * x.G;
+        std::vector<uint2> buf((size_t)x.m * per);
+        std::vector<int> cnt((size_t)x.m * x.nseg);
+        std::vector<float> tt((size_t)x.m * x.nseg);
+        std::vector<uint32_t> perm(x.m), iorder(x.n);
+        HIPC(hipMemcpy(buf.data(), x.cand.p, sizeof(uint2) * buf.size(), hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(cnt.data(), x.cand_cnt.p, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(tt.data(), x.cand_tau.p, sizeof(float) * tt.size(), hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(iorder.data(), x.item_order.p, sizeof(uint32_t) * x.n, hipMemcpyDeviceToHost));
+        const int CP = x.C * x.nseg;
+        for (int64_t u = 0; u < x.m; u++) {
+            const int64_t ou = perm[u];
+            int k = 0;
+            float tmax = -INFINITY;
+            for (int s = 0; s < x.nseg; s++) {
+                const int c = cnt[u * x.nseg + s];
+                tmax = std::max(tmax, tt[u * x.nseg + s]);
+                for (int i = 0; i < c; i++, k++) {
+                    const uint2 e = buf[(u * x.nseg + s) * x.G + i];
+                    uint32_t o = e.x;
+                    uint32_t bits = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+                    float f;
+                    std::memcpy(&f, &bits, 4);
+                    if (ids) ids[ou * CP + k] = (int32_t)iorder[e.y];
+                    if (scores) scores[ou * CP + k] = f;
+                }
+            }
+            for (; k < CP; k++) {
+                if (ids) ids[ou * CP + k] = -1;
+                if (scores) scores[ou * CP + k] = -INFINITY;
+            }
+            if (tau) tau[ou] = tmax;
+        }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// The index object behind rkmips_index (host side; all arrays live in device memory).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/rkmips.h"
+
+namespace rk {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    void alloc(size_t b);
+    void reset();
+    void swap(DevBuf& o)
+    {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
+    float* f() const { return (float*)p; }
+    double* d() const { return (double*)p; }
+    int* i() const { return (int*)p; }
+    uint32_t* u32() const { return (uint32_t*)p; }
+    int64_t* i64() const { return (int64_t*)p; }
+};
+
+struct Workspace;
+
+struct Index {
+    int device = 0;
+    int64_t n = 0, m = 0;
+    int d = 0, ld = 0, dtype = 0;
+    rkmips_params prm{};
+
+    // items, sorted by descending canonical norm (Alg. 4 / Alg. 1 first step)
+    DevBuf items, item_scales;   // [n x ld] storage dtype, [n]
+    DevBuf item_order;           // uint32 [n] sorted position -> original item
+    DevBuf item_n2;              // double [n] canonical squared norms, sorted order
+    double max_item_norm = 0, max_user_norm = 0;
+
+    // users in Cone-Tree leaf order
+    DevBuf users, user_scales;   // [m x ld], [m]
+    DevBuf user_perm;            // uint32 [m] leaf position -> original user
+    DevBuf user_n2;              // double [m] leaf order
+    DevBuf unorm, cos_t, sin_t;  // float [m] leaf order
+    DevBuf user_block;           // int [m]
+
+    // blocks (Cone-Tree leaves)
+    int64_t nblocks = 0;
+    DevBuf block_start;          // int64 [nblocks+1]
+    std::vector<int64_t> block_start_h;
+    DevBuf center;               // float [nblocks x ld] unit centres
+    DevBuf cos_w, sin_w, block_ok;
+    DevBuf block_lb;             // float [k_max x nblocks]
+
+    // exact lambda table (leaf order, k-major)
+    DevBuf lam64, lam32;
+    int C = 0, G = 0, nseg = 1;
+    int64_t seg_len = 0;
+    DevBuf cand, cand_cnt, cand_tau;  // raw candidates of the lambda pass
+    int64_t cert_failures = 0;
+    double max_rel_err_raw = 0, max_rel_err_l32 = 0;
+
+    // SA-ALSH (Alg. 1)
+    int t = 0;
+    std::vector<int64_t> part_start_h;
+    DevBuf part_start;           // int64 [t+1]
+    DevBuf centroid;             // float [t x ld]
+    DevBuf radius;               // float [t]
+    DevBuf srp;                  // float [(d+1) x K]
+    DevBuf item_codes;           // uint32 [n x K/32] sorted order
+    DevBuf user_codes;           // uint32 [m x K/32] leaf order
+
+    // reusable query workspaces (one per in-flight batch)
+    std::mutex ws_mu;
+    std::vector<std::unique_ptr<Workspace>> ws_all;
+    std::vector<Workspace*> ws_free;
+    Workspace* take_ws();
+    void give_ws(Workspace* w);
+    ~Index();
+
+    double ms_norms = 0, ms_lambda = 0, ms_refine = 0, ms_saalsh = 0, ms_cone = 0, ms_total = 0;
+
+    int64_t device_bytes() const
+    {
+        const DevBuf* all[] = {&items, &item_scales, &item_order, &item_n2, &users, &user_scales,
+                               &user_perm, &user_n2, &unorm, &cos_t, &sin_t, &user_block,
+                               &block_start, &center, &cos_w, &sin_w, &block_ok, &block_lb,
+                               &lam64, &lam32, &cand, &cand_cnt, &cand_tau, &part_start,
+                               &centroid, &radius, &srp, &item_codes, &user_codes};
+        int64_t s = 0;
+        for (auto* b : all) s += (int64_t)b->bytes;
+        return s;
+    }
+};
+
+double fast_err_rel(int d);
+void range_check(Index& x, const double* n2i, int64_t n, const double* n2u, int64_t m, hipStream_t s);
+void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
+                hipStream_t s);
+void finish_blocks(Index& x, hipStream_t s);
+void build_saalsh(Index& x, const float* srp, hipStream_t s);
+
+}  // namespace rk

@@ -1,0 +1,186 @@
+// Host-side declarations shared by the C-ABI implementation and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/rkmips.h"
+
+namespace rk {
+
+// Thrown inside the library only; the C entry points convert it into a status code.
+struct Error {
+    rkmips_status st;
+    std::string msg;
+};
+[[noreturn]] void fail(rkmips_status st, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define HIPC(x) ::rk::hip_check((x), #x)
+
+// Padded row length (elements) used for the stored copies of all vector sets.
+int padded_dim(int d, int dtype);
+int elt_bytes(int dtype);
+
+// ---------------------------------------------------------------- prep (k_prep.hip)
+// n2[r] = canonical FP64 <x_r, x_r>; sets *bad (device int) non-zero on a
+// non-finite element/scale.  rows use leading dimension ld (elements).
+void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, int d, int ld,
+                  double* n2, int* bad, hipStream_t s);
+// Sort (key, val) pairs ascending by key then val; n <= 2^31.  Scratch-free (in place,
+// arrays must have room for the next power of two, padded by the caller or here).
+void sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int64_t cap, hipStream_t s);
+// Sort uint64 keys ascending in place (cap >= next power of two of n).
+void sort_keys(uint64_t* keys, int64_t n, int64_t cap, hipStream_t s);
+// dst[r] = src[perm[r]] row copy from leading dim ld_src to ld_dst (zero padded).
+void launch_gather_rows(int dtype, const void* src, int ld_src, const float* src_scales,
+                        const uint32_t* perm, int64_t rows, int d, void* dst, int ld_dst,
+                        float* dst_scales, hipStream_t s);
+// keys[i] = ~bits(n2[i]) (ascending = descending norm), vals[i] = i, padded to cap.
+void launch_norm_keys(const double* n2, int64_t n, int64_t cap, uint64_t* keys, uint32_t* vals,
+                      hipStream_t s);
+void launch_permute_f64(const double* src, const uint32_t* perm, int64_t n, double* dst,
+                        hipStream_t s);
+// U_unit[r] = u_r / sqrt(n2_r) (FP32, 0 row for a zero vector), ld = ldu.
+void launch_unit_rows(int dtype, const void* X, const float* scales, const double* n2,
+                      int64_t rows, int d, int ld, float* out, hipStream_t s);
+
+// ---------------------------------------------------------------- lambda build
+struct TopkArgs {
+    const void* items;      // sorted by norm, [n x ld]
+    const float* item_scales;
+    int64_t n;
+    const void* users;      // leaf order, [m x ld]
+    const float* user_scales;
+    int64_t m;
+    int d, ld;
+    int nseg;               // item segments
+    int64_t seg_len;        // items per segment (multiple of the item tile)
+    int C;                  // candidates kept per (user, segment)
+    int G;                  // buffer capacity per (user, segment)
+    uint2* buf;             // [m x nseg x G] {ord(score), item position}
+    int* cnt;               // [m x nseg]
+    float* tau;             // [m x nseg]
+};
+void launch_topk(int dtype, const TopkArgs& a, hipStream_t s);
+int topk_users_per_block(int dtype, int ld);
+
+struct RefineArgs {
+    const void* items; const float* item_scales; int64_t n;
+    const void* users; const float* user_scales; int64_t m;
+    int d, ld, nseg, C, G, k_max;
+    const uint2* buf; const int* cnt; const float* tau;
+    const double* item_n2_sorted;   // canonical squared norms, sorted order
+    int64_t seg_len;
+    const double* user_n2;          // leaf order
+    int force_fail;
+    double* lam64;                  // [k_max x m]
+    float* lam32;                   // [k_max x m]
+    int* fail_list; int* fail_count;
+    unsigned long long* max_raw_err_bits;
+    double err_rel;                 // relative error bound of the fast scores
+};
+void launch_refine(int dtype, const RefineArgs& a, hipStream_t s);
+// Full FP64 rescoring of the users in fail_list (device count at fail_count, host copy nfail).
+void launch_fallback(int dtype, const RefineArgs& a, int64_t nfail, double* scratch,
+                     int64_t scratch_rows, hipStream_t s);
+void launch_lambda32_err(const double* lam64, const float* lam32, int64_t count,
+                         unsigned long long* max_err_bits, hipStream_t s);
+
+// ---------------------------------------------------------------- cone tree
+struct ConeLevelArgs {
+    const float* unit;     // [m x ld] unit users (original order)
+    int ld, d;
+    const uint32_t* perm;  // position -> user
+    const int64_t* seg_start;  // [nseg+1] all current segments (sorted)
+    const int* seg_active;     // [nseg]
+    const int64_t* seg_pivot;  // [nseg] position of the random point v
+    int64_t nseg, m;
+    unsigned long long* key1; unsigned long long* key2;  // [nseg]
+    float* dot_l;          // [m] per position
+    int* left;             // [m] per position
+    int* nleft;            // [nseg]
+};
+void cone_level_pivots(const ConeLevelArgs& a, hipStream_t s);
+void cone_level_split(const ConeLevelArgs& a, hipStream_t s);
+// positions: new_perm[newpos(p)] = perm[p] given exclusive scan of left flags.
+void cone_level_scatter(const ConeLevelArgs& a, const int* left_scan, const int* degenerate,
+                        uint32_t* new_perm, hipStream_t s);
+void exclusive_scan_i32(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
+int64_t scan_tmp_elems(int64_t n);
+
+struct LeafArgs {
+    int dtype;
+    const void* users;       // leaf order [m x ld]
+    const float* user_scales;
+    const double* user_n2;   // leaf order
+    const float* unit;       // original order unit rows [m x ld]
+    const uint32_t* perm;    // leaf position -> original user
+    const int64_t* block_start;
+    int64_t nblocks, m;
+    int d, ld, k_max;
+    const double* lam64;     // [k_max x m] leaf order
+    float* center;           // [nblocks x ld] unit centres
+    float* cos_w; float* sin_w; int* block_ok;   // [nblocks]
+    float* unorm; float* cos_t; float* sin_t;    // [m] leaf order
+    int* user_block;                             // [m]
+    float* block_lb;                             // [k_max x nblocks]
+};
+void launch_leaf_stats(const LeafArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- SA-ALSH
+struct SaIndexArgs {
+    int dtype;
+    const void* items; const float* item_scales;   // sorted order
+    int64_t n; int d, ld;
+    const double* n2_sorted;
+    float b;
+    int K;
+    const float* A;          // [(d+1) x K]
+    int64_t* part_start;     // [max_parts+1] device
+    int* num_parts;          // device
+    int max_parts;
+};
+void launch_partitions(const SaIndexArgs& a, hipStream_t s);
+// centroids (FP64 accumulation, deterministic), radii, item codes
+void launch_saalsh_items(const SaIndexArgs& a, const int64_t* part_start_host, int t,
+                         double* cen64, float* cen32, float* radius, double* pieces,
+                         uint32_t* item_codes, hipStream_t s);
+void launch_user_codes(int dtype, const void* users, const float* user_scales, int64_t m, int d,
+                       int ld, const float* A, int K, uint32_t* codes, hipStream_t s);
+
+// ---------------------------------------------------------------- query
+struct QueryArgs {
+    int dtype;
+    const void* users; const float* user_scales;     // leaf order [m x ld]
+    int64_t m; int d, ld;
+    const float* unorm; const float* cos_t; const float* sin_t;
+    const int* user_block;
+    const float* center; const float* cos_w; const float* sin_w; const int* block_ok;
+    const float* block_lb; int64_t nblocks;
+    const uint32_t* perm;                            // leaf -> original
+    const float* lam32; const double* lam64; int k_max;
+    const void* queries; const float* query_scales; int64_t nq;   // padded copy [nq x ld]
+    const float* qnorm;                              // [nq]
+    const int* qslot;                                // [nq] slot of the query's k
+    const uint32_t* qorig;                           // [nq] k-sorted position -> caller index
+    const int* qk;                                   // [nq] k of each (k-sorted) query
+    int* bad;                                        // query validation flags
+    const int* slot_k;                               // [nslots]
+    int nslots;
+    int flags;
+    double err_rel;                                  // relative error bound of the fast score
+    float err_phi;                                   // error bound of the FP32 cos(phi)
+    float bound_slack;                               // relative slack of the bounds
+    unsigned long long* pool; unsigned long long* pool_count; int64_t pool_cap;
+    unsigned long long* amb; unsigned long long* amb_count; int64_t amb_cap;
+    unsigned long long* stats;                       // [8]
+};
+void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, int ld,
+                  float* qnorm, int* bad, hipStream_t s);
+void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
+void launch_recheck(const QueryArgs& a, int64_t namb, hipStream_t s);
+void launch_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets,
+                    int32_t* ids, hipStream_t s);
+
+}  // namespace rk

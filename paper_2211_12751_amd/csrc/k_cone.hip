@@ -1,0 +1,356 @@
+// Cone-Tree blocking of the users (Alg. 3), built level-synchronously on the GPU, and
+// the per-block / per-user quantities of the node-level (Lemma 2) and vector-level
+// (Lemma 3) upper bounds, plus the block lower bounds L^j(B) of Alg. 4.
+//
+// All splits of one tree level run together: every position of the current user
+// permutation knows its segment (node); per node the random point v (a counter-based
+// draw), u_l = argmin <u, v> and u_r = argmin <u, u_l> are found with 64-bit atomicMin
+// on (orderable dot, position) keys -- ties take the lowest position -- and the node is
+// split stably by cos(u, u_l) >= cos(u, u_r) (ties go left).  A split that leaves one
+// side empty splits the node in index halves.  Nodes of at most N0 users are leaves.
+// Users are unit-normalised first (Fact 2: the norm of u does not change its MIPS
+// result), so inner products are cosines.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "index.h"
+#include "internal.h"
+
+namespace rk {
+
+__device__ __forceinline__ int64_t seg_of(const int64_t* starts, int64_t nseg, int64_t p)
+{
+    int64_t lo = 0, hi = nseg - 1;   // largest s with starts[s] <= p
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Group of LPR lanes computes <a, b> of two unit rows (float4 per lane).
+template <int LPR>
+__device__ __forceinline__ float group_dot(const float* a, const float* b, int ld, int gl)
+{
+    float acc = 0.f;
+    for (int c = gl * 4; c < ld; c += LPR * 4) {
+        const f32x4 x = *(const f32x4*)(a + c), y = *(const f32x4*)(b + c);
+        acc += x[0] * y[0] + x[1] * y[1] + x[2] * y[2] + x[3] * y[3];
+    }
+    for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    return acc;
+}
+
+// phase 0: argmin <u, v> -> key1;  phase 1: dot_l and argmin <u, u_l> -> key2;
+// phase 2: side flags and left counts.
+template <int LPR>
+__global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
+{
+    constexpr int RPW = 64 / LPR;
+    const int l = lane_id();
+    const int gl = l % LPR;
+    const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + l / LPR;
+    const bool in = p < a.m;
+    const int64_t s = in ? seg_of(a.seg_start, a.nseg, p) : 0;
+    const bool act = in && a.seg_active[s];
+    // groups whose position is out of range or inactive skip the dot (whole group agrees)
+    if (!act) {
+        if (phase == 2 && in && gl == 0) a.left[p] = 0;
+        return;
+    }
+    const float* up = a.unit + (int64_t)a.perm[p] * a.ld;
+    if (phase == 0) {
+        const float* v = a.unit + (int64_t)a.perm[a.seg_pivot[s]] * a.ld;
+        const float dv = group_dot<LPR>(up, v, a.ld, gl);
+        if (gl == 0) atomicMin(&a.key1[s], ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p);
+    } else if (phase == 1) {
+        const int64_t pl = (int64_t)(a.key1[s] & 0xffffffffull);
+        const float dl = group_dot<LPR>(up, a.unit + (int64_t)a.perm[pl] * a.ld, a.ld, gl);
+        if (gl == 0) {
+            a.dot_l[p] = dl;
+            atomicMin(&a.key2[s], ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p);
+        }
+    } else {
+        const int64_t pr = (int64_t)(a.key2[s] & 0xffffffffull);
+        const float dr = group_dot<LPR>(up, a.unit + (int64_t)a.perm[pr] * a.ld, a.ld, gl);
+        if (gl == 0) {
+            const int lf = a.dot_l[p] >= dr ? 1 : 0;
+            a.left[p] = lf;
+            if (lf) atomicAdd(&a.nleft[s], 1);
+        }
+    }
+}
+
+__global__ void k_cone_scatter(ConeLevelArgs a, const int* lscan, const int* degenerate, uint32_t* new_perm)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.m) return;
+    const int64_t s = seg_of(a.seg_start, a.nseg, p);
+    int64_t np = p;
+    if (a.seg_active[s] && !degenerate[s]) {
+        const int64_t st = a.seg_start[s];
+        const int64_t lb = lscan[p] - lscan[st];
+        np = a.left[p] ? st + lb : st + a.nleft[s] + (p - st - lb);
+    }
+    new_perm[np] = a.perm[p];
+}
+
+__global__ void k_iota(uint32_t* v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (uint32_t)i;
+}
+
+template <int DT>
+__global__ void k_unit(const void* X, const float* scales, const double* n2, int64_t rows, int d, int ld,
+                       float* out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * ld) return;
+    const int64_t r = t / ld;
+    const int i = (int)(t - r * ld);
+    float v = 0.f;
+    if (i < d && n2[r] > 0.0) {
+        double x = (double)elem_f32<DT>(X, r * d + i);
+        if constexpr (DT == DT_FP8) x *= (double)scales[r];
+        v = (float)(x / sqrt(n2[r]));
+    }
+    out[t] = v;
+}
+
+// Per block (one wave, one user per lane): unit centre (FP64 mean of the unit user
+// rows, normalised), per-user cos/sin of the angle theta_u between u and the centre
+// (FP64 from the stored values), and cos/sin of a cone angle omega >= max theta_u.
+template <int DT>
+__global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
+{
+    __shared__ float cen[4][256];
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    const int64_t b = (int64_t)blockIdx.x * 4 + w;
+    if (b >= a.nblocks) return;
+    const int64_t st = a.block_start[b], en = a.block_start[b + 1];
+    const int sz = (int)(en - st);
+    const bool mine = l < sz;
+    const int64_t p = st + l;
+    const uint32_t ou = mine ? a.perm[p] : 0u;
+    double cn2 = 0.0;
+    for (int i = 0; i < a.d; i++) {
+        double v = mine ? (double)a.unit[(int64_t)ou * a.ld + i] : 0.0;
+        v = wave_sum(v) / (double)sz;
+        cn2 += v * v;
+        if (l == 0) cen[w][i] = (float)v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double cnorm = sqrt(cn2);
+    bool ok = cnorm > 1e-6;
+    for (int i = l; i < a.ld; i += 64) {
+        const float c = (i < a.d && ok) ? (float)((double)cen[w][i] / cnorm) : 0.f;
+        cen[w][i] = c;
+        a.center[b * a.ld + i] = c;
+    }
+    __builtin_amdgcn_wave_barrier();
+    double ct = 1.0;
+    bool zero_user = false;
+    if (mine) {
+        const double un2 = a.user_n2[p];
+        zero_user = !(un2 > 0.0);
+        const float su = DT == DT_FP8 ? a.user_scales[p] : 1.f;
+        double acc = 0.0;
+        for (int i = 0; i < a.d; i++) acc = __fma_rn((double)elem_f32<DT>(a.users, p * a.ld + i), (double)cen[w][i], acc);
+        if constexpr (DT == DT_FP8) acc *= (double)su;
+        const double un = sqrt(un2);
+        ct = zero_user ? 1.0 : acc / un;
+        ct = ct > 1.0 ? 1.0 : (ct < -1.0 ? -1.0 : ct);
+        a.unorm[p] = (float)un;
+        a.cos_t[p] = (float)ct;
+        a.sin_t[p] = (float)sqrt(fmax(0.0, 1.0 - ct * ct));
+        a.user_block[p] = (int)b;
+    }
+    ok = ok && !(ballot64(zero_user));
+    double cw = wave_min(mine ? ct : 2.0);
+    // widen the cone a little so rounding of the stored pairs cannot make it too narrow
+    cw = cw - 1e-6;
+    if (cw < -1.0) cw = -1.0;
+    if (l == 0) {
+        a.cos_w[b] = ok ? (float)cw : -1.f;
+        a.sin_w[b] = ok ? (float)sqrt(fmax(0.0, 1.0 - cw * cw)) : 0.f;
+        a.block_ok[b] = ok ? 1 : 0;
+    }
+}
+
+// L^j(B) = min over the block of lambda_u^(j) / ||u||, rounded down to FP32 (-inf for a
+// block without usable angles, so it is never pruned).
+__global__ void k_block_lb(const double* lam64, const double* user_n2, const int64_t* block_start,
+                           const int* block_ok, int64_t nblocks, int64_t m, int k_max, float* lb)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblocks * k_max) return;
+    const int64_t b = t % nblocks;
+    const int j = (int)(t / nblocks);
+    float out = -__builtin_inff();
+    if (block_ok[b]) {
+        double mn = __builtin_inf();
+        for (int64_t p = block_start[b]; p < block_start[b + 1]; p++) {
+            const double v = lam64[(int64_t)j * m + p] / sqrt(user_n2[p]);
+            mn = v < mn ? v : mn;
+        }
+        float f = (float)mn;
+        if ((double)f > mn) {   // step one ulp towards -inf
+            const uint32_t u = __float_as_uint(f);
+            f = f == 0.f ? -__uint_as_float(1u) : __uint_as_float(f > 0.f ? u - 1u : u + 1u);
+        }
+        out = f;
+    }
+    lb[(int64_t)j * nblocks + b] = out;
+}
+
+// ------------------------------------------------------------------ host orchestration
+void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s)
+{
+    const int64_t m = x.m;
+    const int ld = x.ld;
+    DevBuf unit, perm_a, perm_b, dot_l, left, lscan, scan_tmp;
+    unit.alloc(sizeof(float) * (size_t)m * ld);
+    {
+        const int64_t tot = m * ld;
+        dim3 g((unsigned)((tot + 255) / 256)), b(256);
+        if (x.dtype == DT_F32) hipLaunchKernelGGL(k_unit<DT_F32>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.f());
+        else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_unit<DT_BF16>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.f());
+        else hipLaunchKernelGGL(k_unit<DT_FP8>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.f());
+    }
+    perm_a.alloc(sizeof(uint32_t) * m);
+    perm_b.alloc(sizeof(uint32_t) * m);
+    dot_l.alloc(sizeof(float) * m);
+    left.alloc(sizeof(int) * m);
+    lscan.alloc(sizeof(int) * m);
+    scan_tmp.alloc(sizeof(int) * scan_tmp_elems(m));
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, perm_a.u32(), m);
+
+    const int N0 = x.prm.leaf_size;
+    std::vector<int64_t> starts{0, m};   // segment boundaries (sorted), last = m
+    std::vector<int> active;
+    DevBuf d_starts, d_active, d_pivot, d_key1, d_key2, d_nleft, d_degen;
+    int level = 0;
+    for (;;) {
+        const int64_t nseg = (int64_t)starts.size() - 1;
+        active.assign(nseg, 0);
+        std::vector<int64_t> pivot(nseg, 0);
+        bool any = false;
+        for (int64_t i = 0; i < nseg; i++) {
+            const int64_t sz = starts[i + 1] - starts[i];
+            if (sz > N0) {
+                active[i] = 1;
+                any = true;
+                const uint64_t r = splitmix64(x.prm.seed ^ splitmix64(((uint64_t)level << 40) ^ (uint64_t)starts[i]));
+                pivot[i] = starts[i] + (int64_t)(r % (uint64_t)sz);
+            }
+        }
+        if (!any) break;
+        d_starts.alloc(sizeof(int64_t) * (nseg + 1));
+        d_active.alloc(sizeof(int) * nseg);
+        d_pivot.alloc(sizeof(int64_t) * nseg);
+        d_key1.alloc(sizeof(uint64_t) * nseg);
+        d_key2.alloc(sizeof(uint64_t) * nseg);
+        d_nleft.alloc(sizeof(int) * nseg);
+        d_degen.alloc(sizeof(int) * nseg);
+        HIPC(hipMemcpyAsync(d_starts.p, starts.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(d_active.p, active.data(), sizeof(int) * nseg, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(d_pivot.p, pivot.data(), sizeof(int64_t) * nseg, hipMemcpyHostToDevice, s));
+        HIPC(hipMemsetAsync(d_key1.p, 0xff, sizeof(uint64_t) * nseg, s));
+        HIPC(hipMemsetAsync(d_key2.p, 0xff, sizeof(uint64_t) * nseg, s));
+        HIPC(hipMemsetAsync(d_nleft.p, 0, sizeof(int) * nseg, s));
+        ConeLevelArgs a{};
+        a.unit = unit.f(); a.ld = ld; a.d = x.d; a.perm = perm_a.u32();
+        a.seg_start = d_starts.i64(); a.seg_active = d_active.i(); a.seg_pivot = d_pivot.i64();
+        a.nseg = nseg; a.m = m;
+        a.key1 = (unsigned long long*)d_key1.p; a.key2 = (unsigned long long*)d_key2.p;
+        a.dot_l = dot_l.f(); a.left = left.i(); a.nleft = d_nleft.i();
+        const int lpr = std::min(64, ld / 4);
+        const int rpw = 64 / lpr;
+        const unsigned grid = (unsigned)((m + 4 * rpw - 1) / (4 * rpw));
+        for (int ph = 0; ph < 3; ph++) {
+            switch (lpr) {
+            case 8: hipLaunchKernelGGL(k_cone_phase<8>, dim3(grid), dim3(256), 0, s, a, ph); break;
+            case 16: hipLaunchKernelGGL(k_cone_phase<16>, dim3(grid), dim3(256), 0, s, a, ph); break;
+            case 32: hipLaunchKernelGGL(k_cone_phase<32>, dim3(grid), dim3(256), 0, s, a, ph); break;
+            default: hipLaunchKernelGGL(k_cone_phase<64>, dim3(grid), dim3(256), 0, s, a, ph); break;
+            }
+            HIPC(hipGetLastError());
+        }
+        std::vector<int> nleft(nseg), degen(nseg, 0);
+        HIPC(hipMemcpyAsync(nleft.data(), d_nleft.p, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        std::vector<int64_t> next;
+        next.reserve(2 * starts.size());
+        for (int64_t i = 0; i < nseg; i++) {
+            next.push_back(starts[i]);
+            if (!active[i]) continue;
+            const int64_t sz = starts[i + 1] - starts[i];
+            int64_t nl = nleft[i];
+            if (nl == 0 || nl == sz) {
+                degen[i] = 1;
+                nl = sz / 2;
+            }
+            next.push_back(starts[i] + nl);
+        }
+        next.push_back(m);
+        HIPC(hipMemcpyAsync(d_degen.p, degen.data(), sizeof(int) * nseg, hipMemcpyHostToDevice, s));
+        exclusive_scan_i32(left.i(), lscan.i(), m, scan_tmp.i(), s);
+        hipLaunchKernelGGL(k_cone_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a,
+                           (const int*)lscan.i(), (const int*)d_degen.i(), perm_b.u32());
+        HIPC(hipGetLastError());
+        perm_a.swap(perm_b);
+        HIPC(hipStreamSynchronize(s));   // host vectors above are freed at scope end
+        starts.swap(next);
+        level++;
+    }
+
+    // ---- leaves are the blocks; users move into leaf order
+    x.nblocks = (int64_t)starts.size() - 1;
+    x.block_start_h = starts;
+    x.block_start.alloc(sizeof(int64_t) * starts.size());
+    HIPC(hipMemcpyAsync(x.block_start.p, starts.data(), sizeof(int64_t) * starts.size(), hipMemcpyHostToDevice, s));
+    x.user_perm.swap(perm_a);
+    const int eb = elt_bytes(x.dtype);
+    x.users.alloc((size_t)m * ld * eb);
+    if (x.dtype == RKMIPS_FP8_E4M3) x.user_scales.alloc(sizeof(float) * m);
+    launch_gather_rows(x.dtype, users, x.d, user_scales, x.user_perm.u32(), m, x.d, x.users.p, ld,
+                       x.user_scales.f(), s);
+    x.user_n2.alloc(sizeof(double) * m);
+    launch_permute_f64(n2_orig, x.user_perm.u32(), m, x.user_n2.d(), s);
+
+    x.center.alloc(sizeof(float) * (size_t)x.nblocks * ld);
+    x.cos_w.alloc(sizeof(float) * x.nblocks);
+    x.sin_w.alloc(sizeof(float) * x.nblocks);
+    x.block_ok.alloc(sizeof(int) * x.nblocks);
+    x.unorm.alloc(sizeof(float) * m);
+    x.cos_t.alloc(sizeof(float) * m);
+    x.sin_t.alloc(sizeof(float) * m);
+    x.user_block.alloc(sizeof(int) * m);
+    LeafArgs la{};
+    la.dtype = x.dtype; la.users = x.users.p; la.user_scales = x.user_scales.f(); la.user_n2 = x.user_n2.d();
+    la.unit = unit.f(); la.perm = x.user_perm.u32(); la.block_start = x.block_start.i64();
+    la.nblocks = x.nblocks; la.m = m; la.d = x.d; la.ld = ld; la.k_max = x.prm.k_max;
+    la.center = x.center.f(); la.cos_w = x.cos_w.f(); la.sin_w = x.sin_w.f(); la.block_ok = x.block_ok.i();
+    la.unorm = x.unorm.f(); la.cos_t = x.cos_t.f(); la.sin_t = x.sin_t.f(); la.user_block = x.user_block.i();
+    dim3 g((unsigned)((x.nblocks + 3) / 4)), b(256);
+    if (x.dtype == DT_F32) hipLaunchKernelGGL(k_leaf_stats<DT_F32>, g, b, 0, s, la);
+    else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_leaf_stats<DT_BF16>, g, b, 0, s, la);
+    else hipLaunchKernelGGL(k_leaf_stats<DT_FP8>, g, b, 0, s, la);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+}
+
+void finish_blocks(Index& x, hipStream_t s)
+{
+    const int64_t tot = x.nblocks * x.prm.k_max;
+    x.block_lb.alloc(sizeof(float) * tot);
+    hipLaunchKernelGGL(k_block_lb, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x.lam64.d(),
+                       x.user_n2.d(), x.block_start.i64(), x.block_ok.i(), x.nblocks, x.m, x.prm.k_max,
+                       x.block_lb.f());
+    HIPC(hipGetLastError());
+}
+
+}  // namespace rk

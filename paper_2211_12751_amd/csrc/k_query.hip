@@ -1,0 +1,405 @@
+// Query side of Alg. 5 with exact decisions, for a batch of queries at once.
+//
+// k_verify fuses, per (user tile, query sub-tile of 32):
+//   * the node-level bound of Lemma 2 per (block, query): ||q|| cos({phi - omega}_+)
+//     against L^k(B) (Alg. 5, block test);
+//   * the vector-level bound of Lemma 3 per (user, query): ||q|| ||u|| cos|phi - theta_u|
+//     against lambda_u^(k) (Alg. 5, user test);
+//   * <u, q> on the matrix cores for the pairs that survive, compared with lambda_u^(k)
+//     (Alg. 5, inner-product test): a margin beyond the derived error bound decides in
+//     the fast arithmetic, anything closer is queued for the canonical FP64 recheck.
+// Users stay resident in registers for the whole query chunk; a 32x32 output block
+// whose pairs are all pruned skips its matrix-core work.  Answers are appended with one
+// atomic per wave and output block (ballot/prefix-sum compaction).
+//
+// Soundness of the bounds under rounding: phi comes from an FP32 dot product whose cosine
+// is known within +-e; the bound functions are 1-Lipschitz in the angle, so the angle
+// uncertainty Delta_phi is added to the cosine factor; a relative slack covers the
+// FP32 evaluation and the stored cos/sin pairs.  Pruning is only ever a strict "<".
+#include <algorithm>
+
+#include "common.h"
+#include "internal.h"
+
+namespace rk {
+
+static constexpr int VF_WAVES = 4;
+static constexpr int VF_MAXB = 32;     // blocks with angle data per workgroup
+static constexpr int VF_MAXSLOT = 8;   // distinct k values per launch
+
+template <int DT>
+__device__ __forceinline__ float row_elem(const uint8_t* row, int i)
+{
+    if constexpr (DT == DT_F32) return ((const float*)row)[i];
+    else if constexpr (DT == DT_BF16) return bf16_to_f32(((const uint16_t*)row)[i]);
+    else return e4m3_to_f32(row[i]);
+}
+
+template <int DT, int DPT, int UBW>
+__global__ __launch_bounds__(256) void k_verify(QueryArgs a, int64_t q_begin, int64_t q_end)
+{
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int ROWB = DPT * EB;
+    constexpr int LROW = ROWB + 16;
+    constexpr int KSTEPS = ROWB / 32;
+    constexpr int UT = VF_WAVES * UBW * 32;
+    __shared__ __attribute__((aligned(16))) uint8_t qt[32 * LROW];
+    __shared__ float qn_s[32], qs_s[32];
+    __shared__ int qslot_s[32], qk_s[32];
+    __shared__ f32x4 phi_s[VF_MAXB][32];
+    __shared__ float lam_s[VF_MAXSLOT][UT];
+
+    const int l = lane_id(), w = threadIdx.x >> 6, h = l >> 5;
+    const int64_t u0 = (int64_t)blockIdx.x * UT;
+    const int64_t ulast = (u0 + UT - 1 < a.m - 1) ? u0 + UT - 1 : a.m - 1;
+    const int bfirst = a.user_block[u0];
+    const int nb = a.user_block[ulast] - bfirst + 1;
+    const bool use_bounds = !(a.flags & RKMIPS_FLAG_NO_BOUNDS);
+    const bool use_vec = use_bounds && !(a.flags & RKMIPS_FLAG_NO_VECTOR_BOUND);
+    const bool force = (a.flags & RKMIPS_FLAG_FORCE_RECHECK) != 0;
+
+    for (int e = threadIdx.x; e < a.nslots * UT; e += 256) {
+        const int sl = e / UT, ul = e % UT;
+        const int64_t u = u0 + ul;
+        lam_s[sl][ul] = u < a.m ? a.lam32[(int64_t)(a.slot_k[sl] - 1) * a.m + u] : 0.f;
+    }
+
+    i32x4 bfrag[UBW][KSTEPS];
+    float un[UBW], ct[UBW], st[UBW], su[UBW];
+    int bl[UBW], ul_[UBW];
+    uint32_t ouid[UBW];
+    bool uok[UBW];
+#pragma unroll
+    for (int cb = 0; cb < UBW; cb++) {
+        ul_[cb] = (w * UBW + cb) * 32 + (l & 31);
+        const int64_t u = u0 + ul_[cb];
+        uok[cb] = u < a.m;
+        const int64_t uu = uok[cb] ? u : u0;
+        const uint8_t* row = (const uint8_t*)a.users + uu * ROWB;
+#pragma unroll
+        for (int t = 0; t < KSTEPS; t++) {
+            i32x4 z = {0, 0, 0, 0};
+            bfrag[cb][t] = uok[cb] ? *(const i32x4*)(row + t * 32 + h * 16) : z;
+        }
+        un[cb] = a.unorm[uu];
+        ct[cb] = a.cos_t[uu];
+        st[cb] = a.sin_t[uu];
+        su[cb] = DT == DT_FP8 ? a.user_scales[uu] : 1.f;
+        bl[cb] = a.user_block[uu] - bfirst;
+        ouid[cb] = a.perm[uu];
+    }
+
+    unsigned long long n_node = 0, n_vec = 0, n_scored = 0, n_amb = 0;
+
+    for (int64_t qb = q_begin; qb < q_end; qb += 32) {
+        __syncthreads();
+        for (int c = threadIdx.x; c < 32 * (ROWB / 16); c += 256) {
+            const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
+            const int64_t q = qb + r;
+            i32x4 v = {0, 0, 0, 0};
+            if (q < q_end) v = *(const i32x4*)((const uint8_t*)a.queries + q * ROWB + c16 * 16);
+            *(i32x4*)(qt + r * LROW + c16 * 16) = v;
+        }
+        if (threadIdx.x < 32) {
+            const int64_t q = qb + threadIdx.x;
+            const bool ok = q < q_end;
+            qn_s[threadIdx.x] = ok ? a.qnorm[q] : 0.f;
+            qs_s[threadIdx.x] = (ok && DT == DT_FP8) ? a.query_scales[q] : 1.f;
+            const int sl = ok ? a.qslot[q] : 0;
+            qslot_s[threadIdx.x] = sl;
+            qk_s[threadIdx.x] = ok ? a.slot_k[sl] : 0;
+        }
+        __syncthreads();
+        // node-level data per (block, query)
+        const int nbb = nb < VF_MAXB ? nb : VF_MAXB;
+        for (int e = threadIdx.x; e < nbb * 32; e += 256) {
+            const int b = e >> 5, qi = e & 31;
+            const int bg = bfirst + b;
+            f32x4 out = {1.f, 0.f, 0.f, 2.f};     // w = 2: no angle data, never prune
+            if (use_bounds && a.block_ok[bg] && qb + qi < q_end && qn_s[qi] > 0.f) {
+                const float* cen = a.center + (int64_t)bg * a.ld;
+                const uint8_t* qrow = qt + qi * LROW;
+                float dot = 0.f;
+                for (int i = 0; i < a.d; i++) dot += row_elem<DT>(qrow, i) * cen[i];
+                if constexpr (DT == DT_FP8) dot *= qs_s[qi];
+                float c = dot / qn_s[qi];
+                c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
+                const float s = sqrtf(fmaxf(0.f, 1.f - c * c));
+                const float ce = fabsf(c) + a.err_phi;
+                const float rem = 1.f - ce * ce;
+                const float dphi = rem > 4.f * a.err_phi ? a.err_phi / sqrtf(rem) : 2.f * sqrtf(2.f * a.err_phi) + a.err_phi;
+                const float cw = a.cos_w[bg], sw = a.sin_w[bg];
+                const float fnode = c >= cw ? 1.f : c * cw + s * sw;
+                const float ub = qn_s[qi] * (fnode + dphi + a.bound_slack);
+                const float lb = a.block_lb[(int64_t)(qk_s[qi] - 1) * a.nblocks + bg];
+                out = f32x4{c, s, dphi, ub < lb ? 1.f : 0.f};
+            }
+            phi_s[b][qi] = out;
+        }
+        __syncthreads();
+
+        // per-lane survival masks
+        uint32_t live[UBW];
+        bool any = false;
+#pragma unroll
+        for (int cb = 0; cb < UBW; cb++) {
+            uint32_t lm = 0u;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int qi = mfma32_row(r, l);
+                if (!uok[cb] || qb + qi >= q_end) continue;
+                const f32x4 ph = bl[cb] < VF_MAXB ? phi_s[bl[cb]][qi] : f32x4{1.f, 0.f, 0.f, 2.f};
+                if (ph[3] == 1.f) { n_node++; continue; }
+                if (use_vec && ph[3] == 0.f) {
+                    const float lam = lam_s[qslot_s[qi]][ul_[cb]];
+                    const float ubv = qn_s[qi] * un[cb] * (ph[0] * ct[cb] + ph[1] * st[cb] + ph[2] + a.bound_slack);
+                    if (ubv < lam - fabsf(lam) * 0x1p-22f) { n_vec++; continue; }
+                }
+                lm |= 1u << r;
+            }
+            live[cb] = lm;
+            any |= lm != 0u;
+        }
+        if (!ballot64(any)) continue;
+
+        f32x16 acc[UBW];
+#pragma unroll
+        for (int cb = 0; cb < UBW; cb++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[cb][r] = 0.f;
+        const uint8_t* arow = qt + (l & 31) * LROW + h * 16;
+#pragma unroll
+        for (int t = 0; t < KSTEPS; t++) {
+            const i32x4 af = *(const i32x4*)(arow + t * 32);
+            if constexpr (DT == DT_F32) {
+                const f32x4 a4 = __builtin_bit_cast(f32x4, af);
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+#pragma unroll
+                    for (int cb = 0; cb < UBW; cb++)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], __builtin_bit_cast(f32x4, bfrag[cb][t])[e], acc[cb], 0, 0, 0);
+            } else if constexpr (DT == DT_BF16) {
+                const bf16x8 a8 = __builtin_bit_cast(bf16x8, af);
+#pragma unroll
+                for (int cb = 0; cb < UBW; cb++)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, __builtin_bit_cast(bf16x8, bfrag[cb][t]), acc[cb], 0, 0, 0);
+            } else {
+                const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[0], af[1]});
+                const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[2], af[3]});
+#pragma unroll
+                for (int cb = 0; cb < UBW; cb++) {
+                    const i32x4 bf = bfrag[cb][t];
+                    const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[0], bf[1]});
+                    const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[2], bf[3]});
+                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc[cb], 0, 0, 0);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc[cb], 0, 0, 0);
+                }
+            }
+        }
+
+#pragma unroll
+        for (int cb = 0; cb < UBW; cb++) {
+            uint32_t yes = 0u, amb = 0u;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                if (!(live[cb] & (1u << r))) continue;
+                const int qi = mfma32_row(r, l);
+                float x = acc[cb][r];
+                if constexpr (DT == DT_FP8) x = (su[cb] * qs_s[qi]) * x;
+                const float lam = lam_s[qslot_s[qi]][ul_[cb]];
+                if (lam == -__builtin_inff()) { yes |= 1u << r; continue; }
+                const float e = (float)a.err_rel * un[cb] * qn_s[qi] + fabsf(lam) * 0x1p-23f + (float)a.d * 0x1p-120f;
+                const float diff = x - lam;
+                if (force || !(diff > e || diff < -e)) amb |= 1u << r;
+                else if (diff > e) yes |= 1u << r;
+            }
+            n_scored += __popc(live[cb]);
+            n_amb += __popc(amb);
+            // wave-aggregated appends
+            const int ny = __popc(yes), na = __popc(amb);
+            const int iy = wave_incl_scan(ny), ia = wave_incl_scan(na);
+            const int ty = __shfl(iy, 63), ta = __shfl(ia, 63);
+            unsigned long long by = 0, ba = 0;
+            if (l == 0) {
+                if (ty) by = atomicAdd(a.pool_count, (unsigned long long)ty);
+                if (ta) ba = atomicAdd(a.amb_count, (unsigned long long)ta);
+            }
+            by = __shfl(by, 0);
+            ba = __shfl(ba, 0);
+            int64_t py = (int64_t)by + iy - ny, pa = (int64_t)ba + ia - na;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int64_t q = qb + mfma32_row(r, l);
+                if (yes & (1u << r)) {
+                    if (py < a.pool_cap) a.pool[py] = ((unsigned long long)a.qorig[q] << 32) | ouid[cb];
+                    py++;
+                }
+                if (amb & (1u << r)) {
+                    if (pa < a.amb_cap) a.amb[pa] = ((unsigned long long)q << 32) | (uint32_t)(u0 + ul_[cb]);
+                    pa++;
+                }
+            }
+        }
+    }
+    n_node = wave_sum(n_node);
+    n_vec = wave_sum(n_vec);
+    n_scored = wave_sum(n_scored);
+    n_amb = wave_sum(n_amb);
+    if (l == 0) {
+        if (n_node) atomicAdd(&a.stats[0], n_node);
+        if (n_vec) atomicAdd(&a.stats[1], n_vec);
+        if (n_scored) atomicAdd(&a.stats[2], n_scored);
+        if (n_amb) atomicAdd(&a.stats[3], n_amb);
+    }
+}
+
+template <int DT, int DPT>
+static void verify_g(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
+{
+    constexpr int UBW = (DT == DT_F32 && DPT >= 256) ? 1 : 2;
+    constexpr int UT = VF_WAVES * UBW * 32;
+    const int64_t tiles = (a.m + UT - 1) / UT;
+    // split the queries so that the grid covers the chip several times
+    const int64_t nq = q1 - q0;
+    int64_t nchunk = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, tiles));
+    nchunk = std::min<int64_t>(nchunk, (nq + 31) / 32);
+    int64_t clen = (nq + nchunk - 1) / nchunk;
+    clen = (clen + 31) / 32 * 32;
+    nchunk = (nq + clen - 1) / clen;
+    for (int64_t c = 0; c < nchunk; c++) {
+        const int64_t qb = q0 + c * clen, qe = std::min(q1, qb + clen);
+        hipLaunchKernelGGL((k_verify<DT, DPT, UBW>), dim3((unsigned)tiles), dim3(256), 0, s, a, qb, qe);
+    }
+}
+
+template <int DT>
+static void verify_d(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
+{
+    switch (a.ld) {
+    case 32: verify_g<DT, 32>(a, q0, q1, s); break;
+    case 64: verify_g<DT, 64>(a, q0, q1, s); break;
+    case 128: verify_g<DT, 128>(a, q0, q1, s); break;
+    case 256: verify_g<DT, 256>(a, q0, q1, s); break;
+    default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
+    }
+}
+
+void launch_verify_range(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
+{
+    if (q1 <= q0 || a.m <= 0) return;
+    if (a.nslots > VF_MAXSLOT) fail(RKMIPS_EINVAL, "internal: too many distinct k in one launch");
+    if (a.dtype == DT_F32) verify_d<DT_F32>(a, q0, q1, s);
+    else if (a.dtype == DT_BF16) verify_d<DT_BF16>(a, q0, q1, s);
+    else verify_d<DT_FP8>(a, q0, q1, s);
+    HIPC(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ canonical FP64 recheck
+template <int DT>
+__device__ double canon_dot2(const void* A, int64_t ra, int lda, float sa, const void* B, int64_t rb, int ldb, float sb, int d)
+{
+    double acc = 0.0;
+    for (int i = 0; i < d; i++)
+        acc = __fma_rn((double)elem_f32<DT>(A, ra * lda + i), (double)elem_f32<DT>(B, rb * ldb + i), acc);
+    if constexpr (DT == DT_FP8) acc = ((double)sa * (double)sb) * acc;
+    return acc;
+}
+
+template <int DT>
+__global__ void k_recheck(QueryArgs a, int64_t namb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= namb) return;
+    const unsigned long long key = a.amb[i];
+    const int64_t q = (int64_t)(key >> 32);
+    const int64_t u = (int64_t)(key & 0xffffffffull);
+    const int k = a.qk[q];
+    const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
+    const float sq = DT == DT_FP8 ? a.query_scales[q] : 1.f;
+    const double s = canon_dot2<DT>(a.users, u, a.ld, su, a.queries, q, a.ld, sq, a.d);
+    if (s >= a.lam64[(int64_t)(k - 1) * a.m + u]) {
+        const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
+        if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)a.qorig[q] << 32) | a.perm[u];
+    }
+}
+
+void launch_recheck(const QueryArgs& a, int64_t namb, hipStream_t s)
+{
+    if (namb <= 0) return;
+    dim3 g((unsigned)((namb + 255) / 256)), b(256);
+    if (a.dtype == DT_F32) hipLaunchKernelGGL(k_recheck<DT_F32>, g, b, 0, s, a, namb);
+    else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_recheck<DT_BF16>, g, b, 0, s, a, namb);
+    else hipLaunchKernelGGL(k_recheck<DT_FP8>, g, b, 0, s, a, namb);
+    HIPC(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ query norms
+template <int DT>
+__global__ void k_qnorm(const void* Q, const float* qs, int64_t nq, int d, int ld, float* qnorm, int* bad)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    double acc = 0.0;
+    bool ok = true;
+    for (int i = 0; i < d; i++) {
+        const float v = elem_f32<DT>(Q, q * ld + i);
+        ok &= (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
+        acc = __fma_rn((double)v, (double)v, acc);
+    }
+    if constexpr (DT == DT_FP8) {
+        const float s = qs[q];
+        ok &= (__float_as_uint(s) & 0x7f800000u) != 0x7f800000u;
+        acc *= (double)s * (double)s;
+    }
+    if constexpr (DT == DT_FP8) {
+        // NaN codes decode to finite magnitudes above 448 only through exponent 15 mantissa 7
+        for (int i = 0; i < d; i++) ok &= (((const uint8_t*)Q)[q * ld + i] & 0x7fu) != 0x7fu;
+    }
+    const double nr = sqrt(acc);
+    qnorm[q] = (float)nr;
+    if (!ok) atomicOr(bad, 1);
+    else if (nr > 1e30 || (nr > 0.0 && nr < 1e-30)) atomicOr(bad, 2);
+}
+
+void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, int ld, float* qnorm, int* bad,
+                  hipStream_t s)
+{
+    if (nq <= 0) return;
+    dim3 g((unsigned)((nq + 255) / 256)), b(256);
+    if (dtype == DT_F32) hipLaunchKernelGGL(k_qnorm<DT_F32>, g, b, 0, s, Q, qs, nq, d, ld, qnorm, bad);
+    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_qnorm<DT_BF16>, g, b, 0, s, Q, qs, nq, d, ld, qnorm, bad);
+    else hipLaunchKernelGGL(k_qnorm<DT_FP8>, g, b, 0, s, Q, qs, nq, d, ld, qnorm, bad);
+    HIPC(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ result lists
+// keys sorted ascending; offsets[q] = first key >= q << 32; ids = low halves.
+__global__ void k_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > nq) return;
+    const uint64_t t = (uint64_t)q << 32;
+    int64_t lo = 0, hi = count;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    offsets[q] = lo;
+}
+
+__global__ void k_ids(const uint64_t* keys, int64_t count, int32_t* ids)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) ids[i] = (int32_t)(keys[i] & 0xffffffffull);
+}
+
+void launch_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets, int32_t* ids, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_offsets, dim3((unsigned)((nq + 1 + 255) / 256)), dim3(256), 0, s, keys, count, nq, offsets);
+    if (count > 0)
+        hipLaunchKernelGGL(k_ids, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, keys, count, ids);
+    HIPC(hipGetLastError());
+}
+
+}  // namespace rk

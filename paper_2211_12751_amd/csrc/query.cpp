@@ -1,0 +1,437 @@
+// Query batches: workspaces, the enqueue side (rkmips_query_batch) and the completion
+// side (rkmips_result_wait: FP64 recheck of the close calls, sorted result lists).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "index.h"
+#include "internal.h"
+#include "query.h"
+
+namespace rk {
+
+static const int kMaxSlots = 8;
+
+PinBuf::~PinBuf() { reset(); }
+void PinBuf::reset()
+{
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+void PinBuf::alloc(size_t b)
+{
+    reset();
+    if (b == 0) b = 16;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        fail(RKMIPS_ENOMEM, "pinned host allocation failed");
+    }
+    bytes = b;
+}
+
+static int64_t pow2ceil64(int64_t n)
+{
+    int64_t p = 2;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+Workspace::Workspace() {}
+Workspace::~Workspace()
+{
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (ev_ctr) (void)hipEventDestroy(ev_ctr);
+}
+
+int64_t Workspace::bytes_for(const Index& x, int64_t nq, int64_t pool_cap, int64_t amb_cap)
+{
+    const int64_t eb = elt_bytes(x.dtype);
+    return nq * x.ld * eb + nq * 4 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4) + amb_cap * 8 + 256;
+}
+
+void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t amb_cap_req)
+{
+    if (!ev0) {
+        HIPC(hipEventCreate(&ev0));
+        HIPC(hipEventCreate(&ev1));
+        HIPC(hipEventCreateWithFlags(&ev_ctr, hipEventDisableTiming));
+    }
+    if (nq > nq_cap) {
+        const int64_t c = std::max<int64_t>(nq, 64);
+        qpad.alloc((size_t)c * x.ld * elt_bytes(x.dtype));
+        if (x.dtype == RKMIPS_FP8_E4M3) qsc.alloc(sizeof(float) * c);
+        qnorm.alloc(sizeof(float) * c);
+        qslot.alloc(sizeof(int) * c);
+        qorig.alloc(sizeof(uint32_t) * c);
+        qk.alloc(sizeof(int) * c);
+        h_qk.alloc(sizeof(int) * c);
+        offsets.alloc(sizeof(int64_t) * (c + 1));
+        h_qslot.alloc(sizeof(int) * c);
+        h_qorig.alloc(sizeof(uint32_t) * c);
+        h_offsets.alloc(sizeof(int64_t) * (c + 1));
+        slotk.alloc(sizeof(int) * kMaxSlots * (c + 1));
+        h_slotk.alloc(sizeof(int) * kMaxSlots * (c + 1));
+        nq_cap = c;
+    }
+    const int64_t pc = pow2ceil64(std::max<int64_t>(pool_cap_req, 1 << 12));
+    if (pc > pool_cap) {
+        pool.alloc(sizeof(uint64_t) * pc);
+        ids.alloc(sizeof(int32_t) * pc);
+        h_ids.alloc(sizeof(int32_t) * pc);
+        pool_cap = pc;
+    }
+    const int64_t ac = std::max<int64_t>(amb_cap_req, 1 << 12);
+    if (ac > amb_cap) {
+        amb.alloc(sizeof(uint64_t) * ac);
+        amb_cap = ac;
+    }
+    if (!ctr.p) {
+        ctr.alloc(sizeof(unsigned long long) * 16);
+        h_ctr.alloc(sizeof(unsigned long long) * 16);
+    }
+}
+
+Workspace* Index::take_ws()
+{
+    std::lock_guard<std::mutex> g(ws_mu);
+    if (!ws_free.empty()) {
+        Workspace* w = ws_free.back();
+        ws_free.pop_back();
+        return w;
+    }
+    ws_all.emplace_back(new Workspace());
+    return ws_all.back().get();
+}
+void Index::give_ws(Workspace* w)
+{
+    std::lock_guard<std::mutex> g(ws_mu);
+    ws_free.push_back(w);
+}
+
+// bound constants
+static float phi_err(int d) { return (float)(fast_err_rel(d) + 2e-6); }
+static const float kBoundSlack = 4e-6f;
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static void fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    HIPC(hipGetLastError());
+}
+
+QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
+{
+    QueryArgs a{};
+    a.dtype = x.dtype;
+    a.users = x.users.p; a.user_scales = x.user_scales.f(); a.m = x.m; a.d = x.d; a.ld = x.ld;
+    a.unorm = x.unorm.f(); a.cos_t = x.cos_t.f(); a.sin_t = x.sin_t.f(); a.user_block = x.user_block.i();
+    a.center = x.center.f(); a.cos_w = x.cos_w.f(); a.sin_w = x.sin_w.f(); a.block_ok = x.block_ok.i();
+    a.block_lb = x.block_lb.f(); a.nblocks = x.nblocks; a.perm = x.user_perm.u32();
+    a.lam32 = x.lam32.f(); a.lam64 = x.lam64.d(); a.k_max = x.prm.k_max;
+    a.queries = w.qpad.p; a.query_scales = w.qsc.f(); a.nq = nq; a.qnorm = w.qnorm.f();
+    a.qslot = w.qslot.i(); a.qorig = w.qorig.u32(); a.qk = w.qk.i(); a.slot_k = w.slotk.i();
+    a.flags = flags | x.prm.flags;
+    a.err_rel = fast_err_rel(x.d);
+    a.err_phi = phi_err(x.d);
+    a.bound_slack = kBoundSlack;
+    unsigned long long* c = (unsigned long long*)w.ctr.p;
+    a.pool = (unsigned long long*)w.pool.p; a.pool_count = c + 0; a.pool_cap = w.pool_cap;
+    a.amb = (unsigned long long*)w.amb.p; a.amb_count = c + 1; a.amb_cap = w.amb_cap;
+    a.bad = (int*)(c + 2);
+    a.stats = c + 8;
+    return a;
+}
+
+// Enqueue query prep and the fused bound/verify kernels for a batch whose host side
+// (h_qorig, h_qslot, h_slotk, groups) is already filled.
+void enqueue_batch(const Index& x, Workspace& w, const void* queries, const float* qscales, int64_t nq,
+                   int flags, hipStream_t s)
+{
+    HIPC(hipMemsetAsync(w.ctr.p, 0, sizeof(unsigned long long) * 16, s));
+    if (nq > 0) {
+        HIPC(hipMemcpyAsync(w.qorig.p, w.h_qorig.p, sizeof(uint32_t) * nq, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(w.qslot.p, w.h_qslot.p, sizeof(int) * nq, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(w.qk.p, w.h_qk.p, sizeof(int) * nq, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(w.slotk.p, w.h_slotk.p, sizeof(int) * kMaxSlots * w.groups.size(),
+                            hipMemcpyHostToDevice, s));
+        launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig.u32(), nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
+        QueryArgs a = make_query_args(x, w, nq, flags);
+        launch_qnorm(x.dtype, w.qpad.p, w.qsc.f(), nq, x.d, x.ld, w.qnorm.f(), a.bad, s);
+        for (size_t g = 0; g < w.groups.size(); g++) {
+            QueryArgs ag = a;
+            ag.slot_k = w.slotk.i() + kMaxSlots * g;
+            ag.nslots = w.groups[g].nslots;
+            launch_verify_range(ag, w.groups[g].begin, w.groups[g].end, s);
+        }
+    }
+    HIPC(hipMemcpyAsync(w.h_ctr.p, w.ctr.p, sizeof(unsigned long long) * 16, hipMemcpyDeviceToHost, s));
+    HIPC(hipEventRecord(w.ev_ctr, s));
+}
+
+// Host side of a batch: sort queries by k, split into groups of <= 8 distinct k.
+void plan_batch(const Index& x, Workspace& w, const int32_t* ks, int64_t nq)
+{
+    std::vector<int64_t> ord(nq);
+    for (int64_t i = 0; i < nq; i++) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return ks[a] < ks[b]; });
+    w.groups.clear();
+    uint32_t* qo = (uint32_t*)w.h_qorig.p;
+    int* qsl = (int*)w.h_qslot.p;
+    int* qkk = (int*)w.h_qk.p;
+    int* sk = (int*)w.h_slotk.p;
+    int64_t i = 0;
+    while (i < nq) {
+        Group g{};
+        g.begin = i;
+        g.nslots = 0;
+        int* tab = sk + kMaxSlots * w.groups.size();
+        while (i < nq) {
+            const int k = ks[ord[i]];
+            if (g.nslots == 0 || tab[g.nslots - 1] != k) {
+                if (g.nslots == kMaxSlots) break;
+                tab[g.nslots++] = k;
+            }
+            qo[i] = (uint32_t)ord[i];
+            qsl[i] = g.nslots - 1;
+            qkk[i] = k;
+            i++;
+        }
+        g.end = i;
+        w.groups.push_back(g);
+    }
+    (void)x;
+}
+
+// Completion: overflow handling, FP64 recheck, sorted per-query lists, host copies.
+void finish_batch(Index& x, Workspace& w, const void* queries, const float* qscales, int64_t nq, int flags,
+                  hipStream_t s, std::vector<int64_t>& offsets, std::vector<int32_t>& ids, rkmips_query_stats& st)
+{
+    HIPC(hipEventSynchronize(w.ev_ctr));
+    unsigned long long* hc = (unsigned long long*)w.h_ctr.p;
+    if (hc[2] & 1ull) fail(RKMIPS_EINVAL, "non-finite value (or NaN code / non-finite scale) in the queries");
+    if (hc[2] & 2ull) fail(RKMIPS_ERANGE, "a query norm is outside [1e-30, 1e30]");
+    int64_t cnt = (int64_t)hc[0], namb = (int64_t)hc[1];
+    if (cnt + namb > w.pool_cap || namb > w.amb_cap) {
+        // the result pool was too small: grow it and run the batch again
+        w.ensure(x, nq, 2 * (cnt + namb) + 1, 2 * namb + 1);
+        enqueue_batch(x, w, queries, qscales, nq, flags, s);
+        HIPC(hipEventSynchronize(w.ev_ctr));
+        cnt = (int64_t)hc[0];
+        namb = (int64_t)hc[1];
+        if (cnt + namb > w.pool_cap || namb > w.amb_cap) fail(RKMIPS_ENOMEM, "result pool overflow");
+    }
+    st = rkmips_query_stats{};
+    st.pairs_total = nq * x.m;
+    st.pairs_block_pruned = (int64_t)hc[8];
+    st.pairs_vector_pruned = (int64_t)hc[9];
+    st.pairs_scored = (int64_t)hc[10];
+    st.pairs_rechecked = namb;
+    QueryArgs a = make_query_args(x, w, nq, flags);
+    fill_u64((unsigned long long*)w.pool.p + cnt, namb, ~0ull, s);
+    if (namb > 0) launch_recheck(a, namb, s);
+    const int64_t span = cnt + namb;
+    if (span > 1) sort_keys((uint64_t*)w.pool.p, span, w.pool_cap, s);
+    launch_offsets((const uint64_t*)w.pool.p, std::max<int64_t>(span, 0), nq, w.offsets.i64(), (int32_t*)w.ids.p, s);
+    HIPC(hipMemcpyAsync(w.h_offsets.p, w.offsets.p, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    const int64_t* ho = (const int64_t*)w.h_offsets.p;
+    const int64_t total = ho[nq];
+    if (total > 0) {
+        HIPC(hipMemcpyAsync(w.h_ids.p, w.ids.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
+    }
+    HIPC(hipEventRecord(w.ev1, s));
+    HIPC(hipStreamSynchronize(s));
+    offsets.assign(ho, ho + nq + 1);
+    ids.assign((const int32_t*)w.h_ids.p, (const int32_t*)w.h_ids.p + total);
+    st.results = total;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, w.ev0, w.ev1) != hipSuccess) (void)hipGetLastError();
+    st.ms_total = ms;
+}
+
+}  // namespace rk
+
+using namespace rk;
+
+struct rkmips_result {
+    Index* idx = nullptr;
+    Workspace* ws = nullptr;
+    hipStream_t s = nullptr;
+    int64_t nq = 0;
+    int flags = 0;
+    const void* queries = nullptr;
+    const float* qscales = nullptr;
+    bool done = false;
+    rkmips_status status = RKMIPS_OK;
+    std::string err;
+    std::vector<int64_t> offsets;
+    std::vector<int32_t> ids;
+    rkmips_query_stats st{};
+};
+
+namespace rk {
+rkmips_status guarded_call(void (*fn)(void*), void* ctx);
+}
+
+template <typename F>
+static rkmips_status qguard(F&& f)
+{
+    struct Ctx { F* f; } c{&f};
+    return rk::guarded_call([](void* p) { (*((Ctx*)p)->f)(); }, &c);
+}
+
+extern "C" {
+
+rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const float* query_scales, int64_t nq,
+                                 const int32_t* ks, int32_t flags, void* stream, rkmips_result** out)
+{
+    return qguard([&] {
+        if (!out) fail(RKMIPS_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!idx) fail(RKMIPS_EINVAL, "index is NULL");
+        Index& x = *(Index*)idx;
+        if (nq < 0 || nq > ((int64_t)1 << 31) - 2) fail(RKMIPS_EINVAL, "nq out of range");
+        if (nq > 0 && (!queries || !ks)) fail(RKMIPS_EINVAL, "queries/ks is NULL");
+        const bool fp8 = x.dtype == RKMIPS_FP8_E4M3;
+        if (nq > 0 && fp8 && !query_scales) fail(RKMIPS_EINVAL, "FP8 queries need scales");
+        if (!fp8 && query_scales) fail(RKMIPS_EINVAL, "scales are only for FP8 data");
+        for (int64_t i = 0; i < nq; i++)
+            if (ks[i] < 1 || ks[i] > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
+        std::unique_ptr<rkmips_result> r(new rkmips_result());
+        r->idx = &x;
+        r->s = (hipStream_t)stream;
+        r->nq = nq;
+        r->flags = flags;
+        r->queries = queries;
+        r->qscales = query_scales;
+        Workspace* w = x.take_ws();
+        try {
+            w->ensure(x, nq, std::max<int64_t>(1 << 16, 8 * nq * std::max(1, x.prm.k_max)), std::max<int64_t>(1 << 14, 4 * nq));
+            plan_batch(x, *w, ks, nq);
+            HIPC(hipEventRecord(w->ev0, r->s));
+            enqueue_batch(x, *w, queries, query_scales, nq, flags | x.prm.flags, r->s);
+        } catch (...) {
+            x.give_ws(w);
+            throw;
+        }
+        r->ws = w;
+        *out = r.release();
+    });
+}
+
+rkmips_status rkmips_result_wait(rkmips_result* r)
+{
+    if (!r) return RKMIPS_EINVAL;
+    if (r->done) return r->status;
+    rkmips_status st = qguard([&] {
+        finish_batch(*r->idx, *r->ws, r->queries, r->qscales, r->nq, r->flags | r->idx->prm.flags, r->s, r->offsets,
+                     r->ids, r->st);
+    });
+    r->done = true;
+    r->status = st;
+    if (st != RKMIPS_OK) {
+        r->offsets.assign(r->nq + 1, 0);
+        r->ids.clear();
+    }
+    r->idx->give_ws(r->ws);
+    r->ws = nullptr;
+    return st;
+}
+
+rkmips_status rkmips_result_view(const rkmips_result* r, int64_t* nq, const int64_t** offsets, const int32_t** ids)
+{
+    if (!r) return RKMIPS_EINVAL;
+    if (!r->done) return RKMIPS_EBUSY;
+    if (r->status != RKMIPS_OK) return r->status;
+    if (nq) *nq = r->nq;
+    if (offsets) *offsets = r->offsets.data();
+    if (ids) *ids = r->ids.data();
+    return RKMIPS_OK;
+}
+
+rkmips_status rkmips_result_stats(const rkmips_result* r, rkmips_query_stats* out)
+{
+    if (!r || !out) return RKMIPS_EINVAL;
+    if (!r->done) return RKMIPS_EBUSY;
+    *out = r->st;
+    return r->status;
+}
+
+void rkmips_result_free(rkmips_result* r)
+{
+    if (!r) return;
+    if (!r->done) (void)rkmips_result_wait(r);
+    delete r;
+}
+
+rkmips_status rkmips_get_saalsh(const rkmips_index* idx, int64_t* part_start, float* centroid, float* radius,
+                                uint32_t* item_codes, uint32_t* user_codes)
+{
+    return qguard([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
+        const Index& x = *(const Index*)idx;
+        const int W = x.prm.num_hash / 32;
+        if (part_start) std::memcpy(part_start, x.part_start_h.data(), sizeof(int64_t) * (x.t + 1));
+        if (centroid) {
+            std::vector<float> c((size_t)x.t * x.ld);
+            HIPC(hipMemcpy(c.data(), x.centroid.p, sizeof(float) * c.size(), hipMemcpyDeviceToHost));
+            for (int j = 0; j < x.t; j++) std::memcpy(centroid + (int64_t)j * x.d, &c[(size_t)j * x.ld], sizeof(float) * x.d);
+        }
+        if (radius) HIPC(hipMemcpy(radius, x.radius.p, sizeof(float) * x.t, hipMemcpyDeviceToHost));
+        if (item_codes) {
+            std::vector<uint32_t> c((size_t)x.n * W), o(x.n);
+            HIPC(hipMemcpy(c.data(), x.item_codes.p, sizeof(uint32_t) * c.size(), hipMemcpyDeviceToHost));
+            HIPC(hipMemcpy(o.data(), x.item_order.p, sizeof(uint32_t) * x.n, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < x.n; i++) std::memcpy(item_codes + (int64_t)o[i] * W, &c[(size_t)i * W], 4 * W);
+        }
+        if (user_codes) {
+            std::vector<uint32_t> c((size_t)x.m * W), o(x.m);
+            HIPC(hipMemcpy(c.data(), x.user_codes.p, sizeof(uint32_t) * c.size(), hipMemcpyDeviceToHost));
+            HIPC(hipMemcpy(o.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < x.m; i++) std::memcpy(user_codes + (int64_t)o[i] * W, &c[(size_t)i * W], 4 * W);
+        }
+    });
+}
+
+rkmips_status rkmips_get_blocks(const rkmips_index* idx, int32_t* leaf_users, int64_t* block_start, float* center,
+                                float* cos_omega, float* sin_omega, float* cos_theta, float* sin_theta,
+                                float* block_lb)
+{
+    return qguard([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
+        const Index& x = *(const Index*)idx;
+        if (leaf_users) {
+            std::vector<uint32_t> o(x.m);
+            HIPC(hipMemcpy(o.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < x.m; i++) leaf_users[i] = (int32_t)o[i];
+        }
+        if (block_start) std::memcpy(block_start, x.block_start_h.data(), sizeof(int64_t) * (x.nblocks + 1));
+        if (center) {
+            std::vector<float> c((size_t)x.nblocks * x.ld);
+            HIPC(hipMemcpy(c.data(), x.center.p, sizeof(float) * c.size(), hipMemcpyDeviceToHost));
+            for (int64_t b = 0; b < x.nblocks; b++) std::memcpy(center + b * x.d, &c[(size_t)b * x.ld], sizeof(float) * x.d);
+        }
+        if (cos_omega) HIPC(hipMemcpy(cos_omega, x.cos_w.p, sizeof(float) * x.nblocks, hipMemcpyDeviceToHost));
+        if (sin_omega) HIPC(hipMemcpy(sin_omega, x.sin_w.p, sizeof(float) * x.nblocks, hipMemcpyDeviceToHost));
+        if (cos_theta) HIPC(hipMemcpy(cos_theta, x.cos_t.p, sizeof(float) * x.m, hipMemcpyDeviceToHost));
+        if (sin_theta) HIPC(hipMemcpy(sin_theta, x.sin_t.p, sizeof(float) * x.m, hipMemcpyDeviceToHost));
+        if (block_lb) HIPC(hipMemcpy(block_lb, x.block_lb.p, sizeof(float) * x.nblocks * x.prm.k_max, hipMemcpyDeviceToHost));
+    });
+}
+
+}  // extern "C"

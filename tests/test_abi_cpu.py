@@ -1,0 +1,73 @@
+"""The C ABI library loads on a machine without a GPU, exports every entry point that
+include/rkmips.h declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rkmips.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rkmips_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2211_12751_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    from paper_2211_12751_amd import rkmips
+    return rkmips
+
+
+def test_every_declared_symbol_is_exported(R):
+    names = _declared()
+    assert len(names) >= 17
+    for nm in names:
+        assert hasattr(R._lib, nm), nm
+        assert nm in R.EXPORTED, f"binding lacks {nm}"
+
+
+def test_default_params(R):
+    p = R.rkmips_default_params()
+    assert (p.k_max, p.leaf_size, p.num_hash, p.topk_slack) == (50, 64, 128, 14)
+    assert abs(p.b - 0.5) < 1e-7 and p.seed == 221112751
+
+
+def test_argument_errors_before_device_work(R):
+    p = R.rkmips_default_params()
+    h = C.c_void_p()
+    st = R._lib.rkmips_build_index(None, None, 10, None, None, 10, 8, 0, None, C.byref(p), None, C.byref(h))
+    assert st == -1 and "NULL" in R.rkmips_last_error()
+    dummy = C.c_void_p(16)
+    for bad in (dict(n=0), dict(m=0), dict(d=0), dict(d=300), dict(dtype=7)):
+        a = dict(n=10, m=10, d=8, dtype=0)
+        a.update(bad)
+        st = R._lib.rkmips_build_index(dummy, None, a["n"], dummy, None, a["m"], a["d"], a["dtype"], None,
+                                       C.byref(p), None, C.byref(h))
+        assert st == -1, bad
+    for field, val in (("k_max", 0), ("k_max", 300), ("leaf_size", 65), ("num_hash", 48), ("b", 1.0),
+                       ("probe_frac", 0.0), ("mode", 1)):
+        q = R.rkmips_default_params()
+        setattr(q, field, val)
+        st = R._lib.rkmips_build_index(dummy, None, 10, dummy, None, 10, 8, 0, None, C.byref(q), None, C.byref(h))
+        assert st == -1, field
+    # FP8 without scales, scales without FP8
+    st = R._lib.rkmips_build_index(dummy, None, 10, dummy, None, 10, 8, 2, None, C.byref(p), None, C.byref(h))
+    assert st == -1
+    st = R._lib.rkmips_build_index(dummy, dummy, 10, dummy, None, 10, 8, 0, None, C.byref(p), None, C.byref(h))
+    assert st == -1
+    r = C.c_void_p()
+    ks = np.ones(4, np.int32)
+    st = R._lib.rkmips_query_batch(None, dummy, None, 4, ks.ctypes.data, 0, None, C.byref(r))
+    assert st == -1
+    assert R._lib.rkmips_result_wait(None) == -1
+    assert R._lib.rkmips_result_view(None, None, None, None) == -1
+    R._lib.rkmips_result_free(None)
+    R._lib.rkmips_index_free(None)
