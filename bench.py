@@ -1,0 +1,206 @@
+"""Benchmark of the exact RkMIPS hot path on one MI355X.
+
+One step = the whole path over one batch: build the index from items and users that
+are already resident in HBM (item norms and order, exact lambda table through the
+fused U.P^T matrix-core pass + FP64 refine, SA-ALSH codes, Cone-Tree blocks), then
+answer one batch of queries of mixed k (bounds, matrix-core inner products, FP64
+recheck, sorted result lists) and free the index.
+
+Default workload (20,000 x 100,000 x 64, FP32): items |N(0,1)|+0.3, users
+N(0,I) directions with log-normal(0, 0.7) norms, 1,000 fresh item draws as queries
+with k cycling through {1, 5, 10, 20, 50}, k_max = 50.
+
+Prints one JSON line (see README of the contract in the design doc): value = queries/s of
+the whole step, plus the lambda-index TFLOP/s, the roofline of the dominant kernel
+(the fused U.P^T + top-k pass, timed with HIP events on its stream), and the CPU FP64
+reference timed on a bounded user sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RkMIPS queries/s (exact set vs oracle) + λ_u index TFLOP/s + p99 latency"
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, dense
+PEAK_BF16_MFMA = 2500.0
+PEAK_FP8_MFMA = 5000.0
+PEAK_HBM = 8000.0        # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--cpu-sample-users", type=int, default=0,
+                    help="users in the CPU reference sample (0: size it to ~15 s)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size before timing (counter scale)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2211_12751_amd import inputs as I
+    from paper_2211_12751_amd import rkmips as R
+
+    torch.cuda.set_device(0)
+    w = I.make(args.config)
+    k_max = w.k_max
+    dtype = R.DTYPES[w.dtype]
+    items = R.to_device(w.items)
+    users = R.to_device(w.users)
+    queries = R.to_device(w.queries)
+    isc = R.to_device(w.item_scales)
+    usc = R.to_device(w.user_scales)
+    qsc = R.to_device(w.query_scales)
+    ks = np.ascontiguousarray(w.ks)
+    stream = torch.cuda.current_stream()
+    prm = R.rkmips_default_params()
+    prm.k_max = k_max
+
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step():
+        h = R.rkmips_build_index(items, isc, w.n, users, usc, w.m, w.d, dtype, None, prm, stream)
+        info = R.rkmips_get_info(h)
+        t0 = time.perf_counter()
+        r = R.rkmips_query_batch(h, queries, qsc, w.nq, ks, 0, stream)
+        R.rkmips_result_wait(r)
+        t1 = time.perf_counter()
+        st = R.rkmips_result_stats(r)
+        off, ids = R.rkmips_result_view(r)
+        R.rkmips_result_free(r)
+        R.rkmips_index_free(h)
+        return info, st, (t1 - t0), off, ids
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos, sts, qlat = [], [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        info, st, ql, off, ids = step()
+        infos.append(info)
+        sts.append(st)
+        qlat.append(ql)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+
+    ms_step = 1e3 * t_total / args.steps
+    value = args.steps * w.nq / t_total
+    flop_lambda = 2.0 * w.m * w.n * w.d
+    ms_lambda = float(np.mean([i["ms_lambda"] for i in infos]))
+    ms_build = float(np.mean([i["ms_total"] for i in infos]))
+    peak = {"f32": PEAK_FP32_MFMA, "bf16": PEAK_BF16_MFMA, "fp8": PEAK_FP8_MFMA}[w.dtype]
+    achieved = flop_lambda / (ms_lambda * 1e-3) / 1e12
+    q_ms = float(np.mean([s["ms_total"] for s in sts]))
+
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"traffic_{args.config}.json")
+    if os.path.exists(tf):
+        with open(tf) as f:
+            traffic = json.load(f).get("k_topk_bytes_per_launch")
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[w.dtype],
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: n={w.n} items, m={w.m} users, d={w.d}, {w.dtype}, "
+                               f"{w.nq} queries, k in {list(w.k_values)}, k_max={k_max}",
+                   "n": w.n, "m": w.m, "d": w.d, "nq": w.nq, "k_max": k_max},
+        "index_tflops": round(flop_lambda / (ms_build * 1e-3) / 1e12, 3),
+        "lambda_kernel_tflops": round(achieved, 3),
+        "query_only_qps": round(w.nq / (q_ms * 1e-3), 1),
+        "p99_latency_ms": round(float(np.percentile(np.array(qlat) * 1e3, 99)), 4),
+        "phase_ms": {k: round(float(np.mean([i[k] for i in infos])), 4)
+                     for k in ("ms_norms", "ms_cone", "ms_lambda", "ms_refine", "ms_saalsh", "ms_total")},
+        "query_ms": round(q_ms, 4),
+        "query_stats": {k: int(sts[-1][k]) for k in ("pairs_total", "pairs_block_pruned",
+                                                      "pairs_vector_pruned", "pairs_scored",
+                                                      "pairs_rechecked", "results")},
+        "cert_failures": int(infos[-1]["cert_failures"]),
+        "max_rel_err_raw": infos[-1]["max_rel_err_raw"],
+        "max_rel_err_lambda32": infos[-1]["max_rel_err_lambda32"],
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "kernel": "k_topk (fused U.P^T + streaming top-k)",
+                     "flop_per_launch": flop_lambda},
+    }
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], line["parity_sample"] = cpu_baseline(w, k_max, off, ids, args.cpu_sample_users)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(w, k_max, off, ids, sample_users):
+    """The CPU FP64 reference as it stands, on a seeded sample of users: lambda over all
+    items plus membership for every query; extrapolated linearly in users.  Also checks
+    the last GPU step's answers on the sample."""
+    from oracle import oracle as O
+    threads = O.NTHREADS
+    g = np.random.default_rng(20221)
+    if sample_users <= 0:
+        # calibrate on a small sample, then size the timed one to ~15 s of work
+        cal = np.sort(g.choice(w.m, min(w.m, 64), replace=False))
+        t0 = time.perf_counter()
+        lam = O.lambda_table(w.dtype, w.items, w.item_scales, w.users, w.user_scales, k_max, user_idx=cal)
+        O.member(w.dtype, w.users, w.user_scales, w.queries, w.query_scales, w.ks, lam, user_idx=cal)
+        per_user = (time.perf_counter() - t0) / len(cal)
+        sample_users = int(min(w.m, max(64, 15.0 / max(per_user, 1e-9))))
+    sample = np.sort(g.choice(w.m, sample_users, replace=False))
+    t0 = time.perf_counter()
+    lam = O.lambda_table(w.dtype, w.items, w.item_scales, w.users, w.user_scales, k_max, user_idx=sample)
+    mem = O.member(w.dtype, w.users, w.user_scales, w.queries, w.query_scales, w.ks, lam, user_idx=sample)
+    t = time.perf_counter() - t0
+    t_full = t * w.m / len(sample)
+    # parity of the GPU answers on the sample
+    pos = np.full(w.m, -1, np.int64)
+    pos[sample] = np.arange(len(sample))
+    ok = True
+    for qi in range(w.nq):
+        got = np.zeros(len(sample), np.uint8)
+        sel = ids[off[qi]:off[qi + 1]]
+        p = pos[sel]
+        got[p[p >= 0]] = 1
+        if not np.array_equal(got, mem[qi]):
+            ok = False
+            break
+    base = {"value": round(w.nq / t_full, 6), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} of {w.m} users (seeded), lambda over all {w.n} items + membership "
+                      f"for all {w.nq} queries; {t:.2f} s, extrapolated linearly in users "
+                      f"(full job ~{t_full:.0f} s)"}
+    return base, {"users": int(len(sample)), "queries": int(w.nq), "exact_match": ok}
+
+
+if __name__ == "__main__":
+    main()

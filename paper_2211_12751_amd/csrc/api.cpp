@@ -102,27 +102,33 @@ static void validate_params(const rkmips_params& p)
     if (p.mode != 0) fail(RKMIPS_EINVAL, "mode must be 0 (exact)");
 }
 
-// Candidate buffer geometry of the lambda pass.
+// Candidate buffer geometry of the lambda pass: a seeding segment (the P largest- and P
+// smallest-norm items, processed first) and the main segments over the remaining items.
 static void choose_topk(Index& x)
 {
-    int C = x.prm.k_max + x.prm.topk_slack;
+    const int C = x.prm.k_max + x.prm.topk_slack;
     x.C = C;
-    int gpl = 2;
-    while (gpl * 64 < 2 * C || gpl * 64 < C + 32) gpl *= 2;
-    if (gpl > 8) fail(RKMIPS_EINVAL, "k_max + topk_slack too large (at most 224)");
-    x.G = gpl * 64;
-    // item segments: enough workgroups to cover the chip a few times
+    if (C > 224) fail(RKMIPS_EINVAL, "k_max + topk_slack too large (at most 224)");
+    x.P = x.n >= 2048 ? 256 : 0;
+    const int64_t main_items = x.n - 2 * x.P;
     const int upb = topk_users_per_block(x.dtype, x.ld);
     const int64_t tiles = (x.m + upb - 1) / upb;
-    int nseg = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
-    nseg = std::min(nseg, std::max(1, 512 / C));
-    nseg = (int)std::min<int64_t>(nseg, std::max<int64_t>(1, x.n / 256));
-    nseg = std::min(nseg, 8);
-    int64_t seg_len = (x.n + nseg - 1) / nseg;
-    seg_len = (seg_len + 63) / 64 * 64;
-    nseg = (int)((x.n + seg_len - 1) / seg_len);
-    x.nseg = nseg;
+    const int seed = x.P > 0 ? 1 : 0;
+    int nmain = (int)std::max<int64_t>(1, (512 + tiles - 1) / tiles);
+    nmain = (int)std::min<int64_t>(nmain, std::max<int64_t>(1, main_items / 1024));
+    nmain = std::min(nmain, 4 - seed);   // the refine pass gathers at most 4 x 512 entries
+    int64_t seg_len = (main_items + nmain - 1) / nmain;
+    seg_len = std::max<int64_t>(64, (seg_len + 63) / 64 * 64);
+    nmain = (int)((main_items + seg_len - 1) / seg_len);
+    x.nseg_main = nmain;
+    x.nseg = nmain + seed;
     x.seg_len = seg_len;
+    // buffer capacity: large buffers make the wave-wide compactions rare
+    int gpl = 8;
+    while (gpl > 2 && (double)x.m * x.nseg * gpl * 64 * 8 > 24e9) gpl /= 2;
+    while (gpl * 64 < C + 32) gpl *= 2;
+    if (gpl > 8) fail(RKMIPS_ENOMEM, "candidate buffers exceed the memory budget");
+    x.G = gpl * 64;
 }
 
 static void build_lambda(Index& x, hipStream_t s)
@@ -144,11 +150,22 @@ static void build_lambda(Index& x, hipStream_t s)
     TopkArgs ta{};
     ta.items = x.items.p; ta.item_scales = x.item_scales.f(); ta.n = x.n;
     ta.users = x.users.p; ta.user_scales = x.user_scales.f(); ta.m = m;
-    ta.d = x.d; ta.ld = x.ld; ta.nseg = x.nseg; ta.seg_len = x.seg_len; ta.C = x.C; ta.G = x.G;
+    ta.d = x.d; ta.ld = x.ld; ta.P = x.P; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
     ta.buf = (uint2*)buf.p; ta.cnt = (int*)cnt.p; ta.tau = (float*)tau.p;
     Events ev(3);
     HIPC(hipEventRecord(ev.ev[0], s));
-    launch_topk(x.dtype, ta, s);
+    if (x.P > 0) {   // seeding segment: all of it enters, then the C best remain
+        TopkArgs a0 = ta;
+        a0.v0 = 0; a0.v1 = 2 * x.P; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = 2 * x.P;
+        a0.theta_init = nullptr; a0.theta_stride = 0;
+        launch_topk(x.dtype, a0, s);
+    }
+    TopkArgs a1 = ta;
+    a1.v0 = 2 * x.P; a1.v1 = x.n; a1.nseg = x.nseg_main; a1.seg_base = x.P > 0 ? 1 : 0;
+    a1.seg_len = x.seg_len;
+    a1.theta_init = x.P > 0 ? (const float*)tau.p : nullptr;   // tau of the seeding segment
+    a1.theta_stride = x.nseg;
+    launch_topk(x.dtype, a1, s);
     HIPC(hipEventRecord(ev.ev[1], s));
 
     RefineArgs ra{};
@@ -174,8 +191,6 @@ static void build_lambda(Index& x, hipStream_t s)
         launch_fallback(x.dtype, ra, nfail, scratch.d(), rows, s);
         HIPC(hipStreamSynchronize(s));
     }
-    launch_lambda32_err(x.lam64.d(), x.lam32.f(), (int64_t)x.prm.k_max * m,
-                        (unsigned long long*)errbits.p + 1, s);
     HIPC(hipEventRecord(ev.ev[2], s));
     unsigned long long eb[2];
     HIPC(hipMemcpyAsync(eb, errbits.p, sizeof eb, hipMemcpyDeviceToHost, s));

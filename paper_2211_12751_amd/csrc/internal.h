@@ -54,13 +54,19 @@ struct TopkArgs {
     const float* user_scales;
     int64_t m;
     int d, ld;
-    int nseg;               // item segments
+    int64_t P;              // seeding segment: the P largest- and P smallest-norm items
+    int64_t v0, v1;         // virtual item range of this launch
+    int nseg;               // segments of this launch (grid.y)
+    int seg_base;           // buffer segment of this launch's first segment
+    int nseg_total;         // buffer segments per user
     int64_t seg_len;        // items per segment (multiple of the item tile)
     int C;                  // candidates kept per (user, segment)
     int G;                  // buffer capacity per (user, segment)
-    uint2* buf;             // [m x nseg x G] {ord(score), item position}
-    int* cnt;               // [m x nseg]
-    float* tau;             // [m x nseg]
+    const float* theta_init;  // per user starting threshold (stride theta_stride) or null
+    int64_t theta_stride;
+    uint2* buf;             // [m x nseg_total x G] {ord(score), sorted item position}
+    int* cnt;               // [m x nseg_total]
+    float* tau;             // [m x nseg_total]
 };
 void launch_topk(int dtype, const TopkArgs& a, hipStream_t s);
 int topk_users_per_block(int dtype, int ld);
@@ -84,8 +90,6 @@ void launch_refine(int dtype, const RefineArgs& a, hipStream_t s);
 // Full FP64 rescoring of the users in fail_list (device count at fail_count, host copy nfail).
 void launch_fallback(int dtype, const RefineArgs& a, int64_t nfail, double* scratch,
                      int64_t scratch_rows, hipStream_t s);
-void launch_lambda32_err(const double* lam64, const float* lam32, int64_t count,
-                         unsigned long long* max_err_bits, hipStream_t s);
 
 // ---------------------------------------------------------------- cone tree
 struct ConeLevelArgs {

@@ -30,55 +30,69 @@ __device__ __forceinline__ int64_t seg_of(const int64_t* starts, int64_t nseg, i
     return lo;
 }
 
-// Group of LPR lanes computes <a, b> of two unit rows (float4 per lane).
-template <int LPR>
-__device__ __forceinline__ float group_dot(const float* a, const float* b, int ld, int gl)
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// <a, b> of two unit rows, one lane per row (float4 loads, rows stay in L1/L2).
+__device__ __forceinline__ float row_dot(const float* a, const float* b, int ld)
 {
     float acc = 0.f;
-    for (int c = gl * 4; c < ld; c += LPR * 4) {
+    for (int c = 0; c < ld; c += 4) {
         const f32x4 x = *(const f32x4*)(a + c), y = *(const f32x4*)(b + c);
         acc += x[0] * y[0] + x[1] * y[1] + x[2] * y[2] + x[3] * y[3];
     }
-    for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     return acc;
 }
 
+// One lane per position, 64 consecutive positions per wave.  Positions of one segment
+// are contiguous, so a wave meets few segments: the per-segment reduction runs inside
+// the wave and only one atomic per (wave, segment) reaches memory.
 // phase 0: argmin <u, v> -> key1;  phase 1: dot_l and argmin <u, u_l> -> key2;
 // phase 2: side flags and left counts.
-template <int LPR>
 __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
 {
-    constexpr int RPW = 64 / LPR;
     const int l = lane_id();
-    const int gl = l % LPR;
-    const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + l / LPR;
+    const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64 + l;
     const bool in = p < a.m;
-    const int64_t s = in ? seg_of(a.seg_start, a.nseg, p) : 0;
+    const int64_t s = in ? seg_of(a.seg_start, a.nseg, p) : -1;
     const bool act = in && a.seg_active[s];
-    // groups whose position is out of range or inactive skip the dot (whole group agrees)
-    if (!act) {
-        if (phase == 2 && in && gl == 0) a.left[p] = 0;
-        return;
-    }
-    const float* up = a.unit + (int64_t)a.perm[p] * a.ld;
-    if (phase == 0) {
-        const float* v = a.unit + (int64_t)a.perm[a.seg_pivot[s]] * a.ld;
-        const float dv = group_dot<LPR>(up, v, a.ld, gl);
-        if (gl == 0) atomicMin(&a.key1[s], ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p);
-    } else if (phase == 1) {
-        const int64_t pl = (int64_t)(a.key1[s] & 0xffffffffull);
-        const float dl = group_dot<LPR>(up, a.unit + (int64_t)a.perm[pl] * a.ld, a.ld, gl);
-        if (gl == 0) {
+    unsigned long long key = ~0ull;
+    int lf = 0;
+    if (act) {
+        const float* up = a.unit + (int64_t)a.perm[p] * a.ld;
+        if (phase == 0) {
+            const float dv = row_dot(up, a.unit + (int64_t)a.perm[a.seg_pivot[s]] * a.ld, a.ld);
+            key = ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p;
+        } else if (phase == 1) {
+            const int64_t pl = (int64_t)(a.key1[s] & 0xffffffffull);
+            const float dl = row_dot(up, a.unit + (int64_t)a.perm[pl] * a.ld, a.ld);
             a.dot_l[p] = dl;
-            atomicMin(&a.key2[s], ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p);
+            key = ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p;
+        } else {
+            const int64_t pr = (int64_t)(a.key2[s] & 0xffffffffull);
+            const float dr = row_dot(up, a.unit + (int64_t)a.perm[pr] * a.ld, a.ld);
+            lf = a.dot_l[p] >= dr ? 1 : 0;
         }
-    } else {
-        const int64_t pr = (int64_t)(a.key2[s] & 0xffffffffull);
-        const float dr = group_dot<LPR>(up, a.unit + (int64_t)a.perm[pr] * a.ld, a.ld, gl);
-        if (gl == 0) {
-            const int lf = a.dot_l[p] >= dr ? 1 : 0;
-            a.left[p] = lf;
-            if (lf) atomicAdd(&a.nleft[s], 1);
+    }
+    if (phase == 2 && in) a.left[p] = lf;
+    uint64_t rem = ballot64(act);
+    while (rem) {
+        const int leader = __builtin_ctzll(rem);
+        const int64_t s0 = __shfl(s, leader);
+        const bool mine = act && s == s0;
+        rem &= ~ballot64(mine);
+        if (phase < 2) {
+            const unsigned long long mn = wave_min_u64(mine ? key : ~0ull);
+            if (l == leader) atomicMin(phase == 0 ? &a.key1[s0] : &a.key2[s0], mn);
+        } else {
+            const int c = wave_sum(mine ? lf : 0);
+            if (l == leader && c) atomicAdd(&a.nleft[s0], c);
         }
     }
 }
@@ -232,6 +246,16 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     std::vector<int64_t> starts{0, m};   // segment boundaries (sorted), last = m
     std::vector<int> active;
     DevBuf d_starts, d_active, d_pivot, d_key1, d_key2, d_nleft, d_degen;
+    {
+        const int64_t cap = m + 2;
+        d_starts.alloc(sizeof(int64_t) * (cap + 1));
+        d_active.alloc(sizeof(int) * cap);
+        d_pivot.alloc(sizeof(int64_t) * cap);
+        d_key1.alloc(sizeof(uint64_t) * cap);
+        d_key2.alloc(sizeof(uint64_t) * cap);
+        d_nleft.alloc(sizeof(int) * cap);
+        d_degen.alloc(sizeof(int) * cap);
+    }
     int level = 0;
     for (;;) {
         const int64_t nseg = (int64_t)starts.size() - 1;
@@ -248,13 +272,6 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
             }
         }
         if (!any) break;
-        d_starts.alloc(sizeof(int64_t) * (nseg + 1));
-        d_active.alloc(sizeof(int) * nseg);
-        d_pivot.alloc(sizeof(int64_t) * nseg);
-        d_key1.alloc(sizeof(uint64_t) * nseg);
-        d_key2.alloc(sizeof(uint64_t) * nseg);
-        d_nleft.alloc(sizeof(int) * nseg);
-        d_degen.alloc(sizeof(int) * nseg);
         HIPC(hipMemcpyAsync(d_starts.p, starts.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s));
         HIPC(hipMemcpyAsync(d_active.p, active.data(), sizeof(int) * nseg, hipMemcpyHostToDevice, s));
         HIPC(hipMemcpyAsync(d_pivot.p, pivot.data(), sizeof(int64_t) * nseg, hipMemcpyHostToDevice, s));
@@ -267,16 +284,9 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
         a.nseg = nseg; a.m = m;
         a.key1 = (unsigned long long*)d_key1.p; a.key2 = (unsigned long long*)d_key2.p;
         a.dot_l = dot_l.f(); a.left = left.i(); a.nleft = d_nleft.i();
-        const int lpr = std::min(64, ld / 4);
-        const int rpw = 64 / lpr;
-        const unsigned grid = (unsigned)((m + 4 * rpw - 1) / (4 * rpw));
+        const unsigned grid = (unsigned)((m + 255) / 256);
         for (int ph = 0; ph < 3; ph++) {
-            switch (lpr) {
-            case 8: hipLaunchKernelGGL(k_cone_phase<8>, dim3(grid), dim3(256), 0, s, a, ph); break;
-            case 16: hipLaunchKernelGGL(k_cone_phase<16>, dim3(grid), dim3(256), 0, s, a, ph); break;
-            case 32: hipLaunchKernelGGL(k_cone_phase<32>, dim3(grid), dim3(256), 0, s, a, ph); break;
-            default: hipLaunchKernelGGL(k_cone_phase<64>, dim3(grid), dim3(256), 0, s, a, ph); break;
-            }
+            hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
             HIPC(hipGetLastError());
         }
         std::vector<int> nleft(nseg), degen(nseg, 0);

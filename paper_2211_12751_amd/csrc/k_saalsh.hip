@@ -56,17 +56,21 @@ __global__ void k_partitions(const double* n2, int64_t n, float b, int64_t* part
     }
 }
 
-// Centroid sums, one workgroup per (partition, 64-column chunk): 4 row groups accumulate
-// in FP64 in a fixed order, then a fixed-order combine (deterministic).
+// Centroid sums.  Each partition is cut into pieces of at most CEN_PIECE items; one
+// workgroup per (piece, 64-column chunk) sums its piece with 4 interleaved row groups in
+// FP64, combined in a fixed order; a second pass adds the pieces of a partition in
+// order and divides by |S_j|.  The result does not depend on scheduling.
+static constexpr int64_t CEN_PIECE = 2048;
+
 template <int DT>
-__global__ __launch_bounds__(256) void k_centroid(const void* X, const float* scales, const int64_t* part_start,
-                                                  int d, int ld, double* cen64, float* cen32)
+__global__ __launch_bounds__(256) void k_centroid_piece(const void* X, const float* scales, const int64_t* pc_begin,
+                                                        const int64_t* pc_end, int d, int ld, double* psum)
 {
     __shared__ double part[4][64];
-    const int j = blockIdx.x;
+    const int pc = blockIdx.x;
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int g = threadIdx.x >> 6;
-    const int64_t s0 = part_start[j], s1 = part_start[j + 1];
+    const int64_t s0 = pc_begin[pc], s1 = pc_end[pc];
     double acc = 0.0;
     if (c < d)
         for (int64_t p = s0 + g; p < s1; p += 4) {
@@ -76,12 +80,23 @@ __global__ __launch_bounds__(256) void k_centroid(const void* X, const float* sc
         }
     part[g][threadIdx.x & 63] = acc;
     __syncthreads();
-    if (g == 0 && c < ld) {
-        double v = 0.0;
-        if (c < d) v = ((part[0][c & 63] + part[1][c & 63]) + part[2][c & 63] + part[3][c & 63]) / (double)(s1 - s0);
-        cen64[(int64_t)j * ld + c] = v;
-        cen32[(int64_t)j * ld + c] = (float)v;
+    if (g == 0 && c < ld)
+        psum[(int64_t)pc * ld + c] = ((part[0][c & 63] + part[1][c & 63]) + part[2][c & 63]) + part[3][c & 63];
+}
+
+__global__ void k_centroid_final(const double* psum, const int64_t* part_piece, const int64_t* part_start, int t,
+                                 int d, int ld, double* cen64, float* cen32)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)t * ld) return;
+    const int j = (int)(e / ld), c = (int)(e % ld);
+    double v = 0.0;
+    if (c < d) {
+        for (int64_t pc = part_piece[j]; pc < part_piece[j + 1]; pc++) v += psum[pc * ld + c];
+        v /= (double)(part_start[j + 1] - part_start[j]);
     }
+    cen64[e] = v;
+    cen32[e] = (float)v;
 }
 
 // r2[p] = ||p - c_j||^2 (FP64) and the partition radius as max (atomicMax on the bits
@@ -90,8 +105,9 @@ template <int DT>
 __global__ void k_radius(const void* X, const float* scales, const int64_t* part_start, int t, int64_t n, int d,
                          int ld, const double* cen64, double* r2out, unsigned long long* rad2_bits)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = p0 < n;
+    const int64_t p = in ? p0 : n - 1;   // out-of-range lanes repeat the last item (max is unchanged)
     int lo = 0, hi = t - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -105,8 +121,17 @@ __global__ void k_radius(const void* X, const float* scales, const int64_t* part
         const double v = (double)elem_f32<DT>(X, p * ld + i) * sc - c[i];
         r2 = __fma_rn(v, v, r2);
     }
-    r2out[p] = r2;
-    atomicMax(&rad2_bits[lo], (unsigned long long)__double_as_longlong(r2));
+    if (in) r2out[p] = r2;
+    // partitions are contiguous ranges: reduce inside the wave, one atomic per partition
+    uint64_t rem = ballot64(true);
+    while (rem) {
+        const int leader = __builtin_ctzll(rem);
+        const int j0 = __shfl(lo, leader);
+        const bool mine = lo == j0;
+        rem &= ~ballot64(mine);
+        const double mx = wave_max(mine ? r2 : 0.0);
+        if (lane_id() == leader) atomicMax(&rad2_bits[j0], (unsigned long long)__double_as_longlong(mx));
+    }
 }
 
 __global__ void k_radius_final(const unsigned long long* rad2_bits, int t, float* radius, double* rad2)
@@ -276,10 +301,34 @@ void build_saalsh(Index& x, const float* srp, hipStream_t s)
     rad2.alloc(sizeof(double) * t);
     HIPC(hipMemsetAsync(rad2bits.p, 0, sizeof(unsigned long long) * t, s));
     {
-        dim3 g((unsigned)t, (unsigned)((x.ld + 63) / 64));
-        if (x.dtype == DT_F32) hipLaunchKernelGGL(k_centroid<DT_F32>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), x.d, x.ld, cen64.d(), x.centroid.f());
-        else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_centroid<DT_BF16>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), x.d, x.ld, cen64.d(), x.centroid.f());
-        else hipLaunchKernelGGL(k_centroid<DT_FP8>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), x.d, x.ld, cen64.d(), x.centroid.f());
+        // pieces of each partition
+        std::vector<int64_t> pb, pe, pp(t + 1, 0);
+        for (int j = 0; j < t; j++) {
+            pp[j] = (int64_t)pb.size();
+            for (int64_t b0 = x.part_start_h[j]; b0 < x.part_start_h[j + 1]; b0 += CEN_PIECE) {
+                pb.push_back(b0);
+                pe.push_back(std::min(b0 + CEN_PIECE, x.part_start_h[j + 1]));
+            }
+        }
+        pp[t] = (int64_t)pb.size();
+        const int64_t np_ = (int64_t)pb.size();
+        DevBuf d_pb, d_pe, d_pp, psum;
+        d_pb.alloc(sizeof(int64_t) * np_);
+        d_pe.alloc(sizeof(int64_t) * np_);
+        d_pp.alloc(sizeof(int64_t) * (t + 1));
+        psum.alloc(sizeof(double) * (size_t)np_ * x.ld);
+        HIPC(hipMemcpyAsync(d_pb.p, pb.data(), sizeof(int64_t) * np_, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(d_pe.p, pe.data(), sizeof(int64_t) * np_, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(d_pp.p, pp.data(), sizeof(int64_t) * (t + 1), hipMemcpyHostToDevice, s));
+        dim3 g((unsigned)np_, (unsigned)((x.ld + 63) / 64));
+        if (x.dtype == DT_F32) hipLaunchKernelGGL(k_centroid_piece<DT_F32>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), d_pb.i64(), d_pe.i64(), x.d, x.ld, psum.d());
+        else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_centroid_piece<DT_BF16>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), d_pb.i64(), d_pe.i64(), x.d, x.ld, psum.d());
+        else hipLaunchKernelGGL(k_centroid_piece<DT_FP8>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), d_pb.i64(), d_pe.i64(), x.d, x.ld, psum.d());
+        const int64_t tot = (int64_t)t * x.ld;
+        hipLaunchKernelGGL(k_centroid_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, psum.d(),
+                           d_pp.i64(), x.part_start.i64(), t, x.d, x.ld, cen64.d(), x.centroid.f());
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(s));   // host piece tables go out of scope
         dim3 g2((unsigned)((n + 255) / 256));
         if (x.dtype == DT_F32) hipLaunchKernelGGL(k_radius<DT_F32>, g2, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), t, n, x.d, x.ld, cen64.d(), r2.d(), (unsigned long long*)rad2bits.p);
         else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_radius<DT_BF16>, g2, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), t, n, x.d, x.ld, cen64.d(), r2.d(), (unsigned long long*)rad2bits.p);

@@ -23,27 +23,12 @@ static constexpr int TK_WAVES = 4;
 static constexpr int TK_IT = 64;  // items per LDS tile (two 32-row MFMA blocks)
 
 // ------------------------------------------------------------------ wave radix select
-// Compacts the `c` entries of a user's buffer (keys = orderable scores) to its C largest
-// (ties at the threshold kept in buffer order) and returns the C-th largest key.
+// C-th largest of the first c keys held GPL per lane (entry i of lane l is position
+// l + 64 i); *need_eq receives how many keys equal to it belong to the C largest.
 template <int GPL>
-__device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, int C, int* hist)
+__device__ __forceinline__ uint32_t wave_kth_key(const uint32_t (&key)[GPL], int c, int C, int* hist, int* need_eq)
 {
     const int l = lane_id();
-    uint32_t key[GPL], id[GPL];
-#pragma unroll
-    for (int i = 0; i < GPL; i++) {
-        const int idx = l + 64 * i;
-        if (idx < c) {
-            const unsigned long long raw = __hip_atomic_load((unsigned long long*)(region + idx),
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint2 w = make_uint2((uint32_t)raw, (uint32_t)(raw >> 32));
-            key[i] = w.x;
-            id[i] = w.y;
-        } else {
-            key[i] = 0u;
-            id[i] = 0u;
-        }
-    }
     uint32_t prefix = 0u, pmask = 0u;
     int need = C;
     for (int shift = 24; shift >= 0; shift -= 8) {
@@ -66,7 +51,7 @@ __device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, in
             above += h[e];
         }
         const uint64_t bal = ballot64(sel >= 0);
-        const int src = __builtin_ctzll(bal);
+        const int src = bal ? __builtin_ctzll(bal) : 0;
         const int dsel = __shfl(sel, src);
         const int dabove = __shfl(sel_above, src);
         prefix |= (uint32_t)dsel << shift;
@@ -74,9 +59,18 @@ __device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, in
         need -= dabove;
         __builtin_amdgcn_wave_barrier();
     }
-    const uint32_t T = prefix;
+    *need_eq = need;
+    return prefix;
+}
+
+// Output positions (or -1) of the kept entries: keys > T, then keys == T in position
+// order until need_eq of them are kept.
+template <int GPL>
+__device__ __forceinline__ void wave_keep_positions(const uint32_t (&key)[GPL], int c, uint32_t T, int need_eq,
+                                                    int (&outpos)[GPL])
+{
+    const int l = lane_id();
     int eq_before = 0, kept_before = 0;
-    int outpos[GPL];
 #pragma unroll
     for (int i = 0; i < GPL; i++) {
         const bool valid = l + 64 * i < c;
@@ -85,11 +79,37 @@ __device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, in
         const uint64_t eb = ballot64(eq);
         const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
         eq_before += __popcll(eb);
-        const bool keep = gt || (eq && rank_eq < need);
+        const bool keep = gt || (eq && rank_eq < need_eq);
         const uint64_t kb = ballot64(keep);
         outpos[i] = keep ? kept_before + __popcll(kb & lanemask_lt()) : -1;
         kept_before += __popcll(kb);
     }
+}
+
+// Compacts the `c` entries of a user's buffer (keys = orderable scores) to its C largest
+// (ties at the threshold kept in buffer order) and returns the C-th largest key.
+template <int GPL>
+__device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, int C, int* hist)
+{
+    const int l = lane_id();
+    uint32_t key[GPL], id[GPL];
+#pragma unroll
+    for (int i = 0; i < GPL; i++) {
+        const int idx = l + 64 * i;
+        if (idx < c) {
+            const unsigned long long raw = __hip_atomic_load((unsigned long long*)(region + idx),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            key[i] = (uint32_t)raw;
+            id[i] = (uint32_t)(raw >> 32);
+        } else {
+            key[i] = 0u;
+            id[i] = 0u;
+        }
+    }
+    int need_eq;
+    const uint32_t T = wave_kth_key<GPL>(key, c, C, hist, &need_eq);
+    int outpos[GPL];
+    wave_keep_positions<GPL>(key, c, T, need_eq, outpos);
 #pragma unroll
     for (int i = 0; i < GPL; i++)
         if (outpos[i] >= 0) region[outpos[i]] = make_uint2(key[i], id[i]);
@@ -97,30 +117,118 @@ __device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, in
 }
 
 // ------------------------------------------------------------------ fused GEMM + top-k
+// Items are streamed in a virtual order over the norm-sorted array: positions
+// [0, 2P) are the P largest-norm and the P smallest-norm items (a seeding segment
+// that is processed first, so every user starts the main pass with a threshold that
+// suits its direction), then the remaining middle range.
+__device__ __forceinline__ int64_t vmap(int64_t i, int64_t n, int64_t P)
+{
+    return i < P ? i : (i < 2 * P ? n - 2 * P + i : i - P);
+}
+
+// user column blocks per wave: FP32 keeps one (register budget for several waves per
+// SIMD, so one wave's top-k epilogue hides behind another's matrix-core work); the
+// narrow types keep two so each LDS fragment feeds two MFMAs
+constexpr int topk_ubw(int dt, int dpt) { return (dt == DT_F32 || dpt >= 512) ? 1 : 2; }
+
+// Buffer compaction for the streaming pass, staged through LDS so that it needs few
+// registers (it runs rarely, and the main loop keeps its register budget for
+// occupancy): keep the C largest of the c entries (ties at the threshold in buffer
+// order), return the C-th largest key.
+__device__ __forceinline__ uint32_t select_user(uint2* region, int c, int C, int* hist, uint2* stage)
+{
+    const int l = lane_id();
+    for (int i = l; i < c; i += 64) {
+        const unsigned long long raw = __hip_atomic_load((unsigned long long*)(region + i), __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        stage[i] = make_uint2((uint32_t)raw, (uint32_t)(raw >> 32));
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint32_t prefix = 0u, pmask = 0u;
+    int need = C;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = l; b < 256; b += 64) hist[b] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int i = l; i < c; i += 64) {
+            const uint32_t k = stage[i].x;
+            if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        int h[4], x = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) { h[e] = hist[4 * l + e]; x += h[e]; }
+        const int incl = wave_incl_scan(x);
+        const int total = __shfl(incl, 63);
+        int above = total - incl;
+        int sel = -1, sel_above = 0;
+#pragma unroll
+        for (int e = 3; e >= 0; e--) {
+            if (sel < 0 && above < need && need <= above + h[e]) { sel = 4 * l + e; sel_above = above; }
+            above += h[e];
+        }
+        const uint64_t bal = ballot64(sel >= 0);
+        const int src = bal ? __builtin_ctzll(bal) : 0;
+        prefix |= (uint32_t)__shfl(sel, src) << shift;
+        pmask |= 0xffu << shift;
+        need -= __shfl(sel_above, src);
+        __builtin_amdgcn_wave_barrier();
+    }
+    const uint32_t T = prefix;
+    int eq_before = 0, kept_before = 0;
+    for (int i0 = 0; i0 < c; i0 += 64) {
+        const int i = i0 + l;
+        const bool valid = i < c;
+        const uint2 e = valid ? stage[i] : make_uint2(0u, 0u);
+        const bool gt = valid && e.x > T;
+        const bool eq = valid && e.x == T;
+        const uint64_t eb = ballot64(eq);
+        const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
+        eq_before += __popcll(eb);
+        const bool keep = gt || (eq && rank_eq < need);
+        const uint64_t kb = ballot64(keep);
+        if (keep) region[kept_before + __popcll(kb & lanemask_lt())] = e;
+        kept_before += __popcll(kb);
+    }
+    __builtin_amdgcn_wave_barrier();
+    return T;
+}
+
 template <int DT, int DPT, int UBW, int GPL>
-__global__ __launch_bounds__(256) void k_topk(TopkArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F32 ? 2 : 1, 8))) void k_topk(TopkArgs a)
 {
     constexpr int EB = Elt<DT>::bytes;
     constexpr int ROWB = DPT * EB;                // bytes of one stored row
     constexpr int LROW = ROWB + 16;               // padded LDS row (bank spread)
     constexpr int KSTEPS = ROWB / 32;             // 16-byte fragments per half row
+    constexpr int CHUNKS = TK_IT * (ROWB / 16);   // 16-byte chunks per tile
+    constexpr int PF = (CHUNKS + 255) / 256;      // chunks per thread
+    constexpr bool PREFETCH = PF <= 4;
     __shared__ __attribute__((aligned(16))) uint8_t tile[TK_IT * LROW];
     __shared__ float tscale[TK_IT];
     __shared__ int hist_all[TK_WAVES][256];
+    __shared__ uint2 stage_all[TK_WAVES][GPL * 64];
 
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
     const int h = l >> 5;
     int* hist = hist_all[w];
-    const int seg = blockIdx.y;
-    const int64_t seg0 = (int64_t)seg * a.seg_len;
+    uint2* stage = stage_all[w];
+    const int segl = blockIdx.y;
+    const int seg = a.seg_base + segl;
+    const int64_t seg0 = a.v0 + (int64_t)segl * a.seg_len;
     int64_t seg1 = seg0 + a.seg_len;
-    if (seg1 > a.n) seg1 = a.n;
+    if (seg1 > a.v1) seg1 = a.v1;
     const int64_t user0 = (int64_t)blockIdx.x * (TK_WAVES * UBW * 32) + (int64_t)w * (UBW * 32);
 
     // ---- resident user fragments (the B operand), one user column per lane
     i32x4 bfrag[UBW][KSTEPS];
     float theta[UBW], su[UBW];
+    // Threshold raising without compaction: pc counts appended scores above `probe`
+    // since it was set; once C of them exist, no item at or below `probe` can be among
+    // the user's C best, so theta moves up to probe (which then bisects towards vmax,
+    // the largest appended score, in orderable-key space).
+    float probe[UBW], vmax[UBW];
+    int pc[UBW];
     int cnt[UBW];
     int64_t ug[UBW];
     uint2* region[UBW];
@@ -134,27 +242,56 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a)
             i32x4 z = {0, 0, 0, 0};
             bfrag[cb][t] = ok ? *(const i32x4*)(row + t * 32 + h * 16) : z;
         }
-        theta[cb] = ok ? -__builtin_inff() : __builtin_inff();   // +inf: nothing enters
+        float th0 = -__builtin_inff();
+        if (ok && a.theta_init) th0 = a.theta_init[ug[cb] * a.theta_stride];
+        theta[cb] = ok ? th0 : __builtin_inff();   // +inf: nothing enters
+        probe[cb] = __builtin_inff();
+        vmax[cb] = -__builtin_inff();
+        pc[cb] = 0;
         su[cb] = (DT == DT_FP8 && ok) ? a.user_scales[ug[cb]] : 1.0f;
         cnt[cb] = 0;
-        region[cb] = a.buf + ((ok ? ug[cb] : 0) * a.nseg + seg) * (int64_t)a.G;
+        region[cb] = a.buf + ((ok ? ug[cb] : 0) * a.nseg_total + seg) * (int64_t)a.G;
+    }
+
+    auto load_chunk = [&](int64_t t0, int c) -> i32x4 {
+        const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
+        const int64_t v = t0 + r;
+        i32x4 val = {0, 0, 0, 0};
+        if (c < CHUNKS && v < seg1)
+            val = *(const i32x4*)((const uint8_t*)a.items + vmap(v, a.n, a.P) * ROWB + c16 * 16);
+        return val;
+    };
+    i32x4 pf[PREFETCH ? PF : 1];
+    if constexpr (PREFETCH) {
+#pragma unroll
+        for (int e = 0; e < PF; e++) pf[e] = load_chunk(seg0, threadIdx.x + 256 * e);
     }
 
     for (int64_t t0 = seg0; t0 < seg1; t0 += TK_IT) {
-        // ---- stage the item tile
+        // ---- stage the item tile (prefetched into registers during the previous tile)
         __syncthreads();
-        for (int c = threadIdx.x; c < TK_IT * (ROWB / 16); c += 256) {
-            const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
-            const int64_t p = t0 + r;
-            i32x4 v = {0, 0, 0, 0};
-            if (p < seg1) v = *(const i32x4*)((const uint8_t*)a.items + p * ROWB + c16 * 16);
-            *(i32x4*)(tile + r * LROW + c16 * 16) = v;
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int e = 0; e < PF; e++) {
+                const int c = threadIdx.x + 256 * e;
+                if (c < CHUNKS) *(i32x4*)(tile + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = pf[e];
+            }
+        } else {
+            for (int c = threadIdx.x; c < CHUNKS; c += 256)
+                *(i32x4*)(tile + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = load_chunk(t0, c);
         }
         if (DT == DT_FP8 && threadIdx.x < TK_IT) {
-            const int64_t p = t0 + threadIdx.x;
-            tscale[threadIdx.x] = p < seg1 ? a.item_scales[p] : 0.f;
+            const int64_t v = t0 + threadIdx.x;
+            tscale[threadIdx.x] = v < seg1 ? a.item_scales[vmap(v, a.n, a.P)] : 0.f;
         }
         __syncthreads();
+        const uint32_t pbase = (uint32_t)vmap(t0, a.n, a.P);
+        if constexpr (PREFETCH) {
+            if (t0 + TK_IT < seg1) {
+#pragma unroll
+                for (int e = 0; e < PF; e++) pf[e] = load_chunk(t0 + TK_IT, threadIdx.x + 256 * e);
+            }
+        }
 
 #pragma unroll
         for (int rb = 0; rb < TK_IT / 32; rb++) {
@@ -202,14 +339,21 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a)
             for (int cb = 0; cb < UBW; cb++) {
                 float v[16];
                 uint32_t pm = 0u;
+                int cgt = 0;
+                float lmax = -__builtin_inff();
 #pragma unroll
                 for (int r = 0; r < 16; r++) {
                     const int row = rb * 32 + mfma32_row(r, l);
                     float x = acc[cb][r];
                     if constexpr (DT == DT_FP8) x = (su[cb] * tscale[row]) * x;
                     v[r] = x;
-                    if (t0 + row < seg1 && x > theta[cb]) pm |= 1u << r;
+                    const bool pass = t0 + row < seg1 && x > theta[cb];
+                    if (pass) pm |= 1u << r;
+                    cgt += (pass && x > probe[cb]) ? 1 : 0;
+                    lmax = pass ? fmaxf(lmax, x) : lmax;
                 }
+                cgt += __shfl_xor(cgt, 32);
+                lmax = fmaxf(lmax, __shfl_xor(lmax, 32));
                 // every cross-lane read happens with the whole wave active: a permute
                 // from an inactive lane returns 0
                 int np = __popc(pm);
@@ -222,19 +366,25 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a)
                         need &= need - 1;
                         const int c = __shfl(cnt[cb], ul);
                         const int64_t ugl = __shfl(ug[cb], ul);
-                        uint2* rg = a.buf + (ugl * a.nseg + seg) * (int64_t)a.G;
-                        const uint32_t T = wave_select_compact<GPL>(rg, c, a.C, hist);
+                        uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
+                        const uint32_t T = select_user(rg, c, a.C, hist, stage);
                         if ((l & 31) == ul) {
                             theta[cb] = ord_f32(T);
                             cnt[cb] = a.C;
+                            pc[cb] = 0;
+                            probe[cb] = __builtin_inff();
                         }
                     }
                     pm = 0u;
+                    cgt = 0;
 #pragma unroll
                     for (int r = 0; r < 16; r++) {
                         const int row = rb * 32 + mfma32_row(r, l);
-                        if (t0 + row < seg1 && v[r] > theta[cb]) pm |= 1u << r;
+                        const bool pass = t0 + row < seg1 && v[r] > theta[cb];
+                        if (pass) pm |= 1u << r;
+                        cgt += (pass && v[r] > probe[cb]) ? 1 : 0;
                     }
+                    cgt += __shfl_xor(cgt, 32);
                     np = __popc(pm);
                     npo = __shfl_xor(np, 32);
                     tot = np + npo;
@@ -245,41 +395,38 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a)
                     for (int r = 0; r < 16; r++)
                         if (pm & (1u << r)) {
                             const int row = rb * 32 + mfma32_row(r, l);
-                            region[cb][pos++] = make_uint2(f32_ord(v[r]), (uint32_t)(t0 + row));
+                            region[cb][pos++] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)row);
                         }
                     cnt[cb] += tot;
+                    vmax[cb] = fmaxf(vmax[cb], lmax);
+                    pc[cb] += cgt;
+                    if (pc[cb] >= a.C) {
+                        theta[cb] = probe[cb];
+                        pc[cb] = 0;
+                        probe[cb] = __builtin_inff();
+                    }
+                    if (probe[cb] == __builtin_inff() && vmax[cb] > theta[cb]) {
+                        const uint32_t lo = f32_ord(theta[cb]), hi = f32_ord(vmax[cb]);
+                        probe[cb] = ord_f32(lo + ((hi - lo) >> 1));
+                    }
                 }
             }
         }
     }
 
-    // ---- final compaction and outputs
+    // ---- outputs: the buffer may hold up to G entries; the refine pass selects
 #pragma unroll
-    for (int cb = 0; cb < UBW; cb++) {
-        uint64_t need = ballot64(cnt[cb] > a.C) & 0xffffffffull;
-        while (need) {
-            const int ul = __builtin_ctzll(need);
-            need &= need - 1;
-            const int c = __shfl(cnt[cb], ul);
-            const int64_t ugl = __shfl(ug[cb], ul);
-            uint2* rg = a.buf + (ugl * a.nseg + seg) * (int64_t)a.G;
-            const uint32_t T = wave_select_compact<GPL>(rg, c, a.C, hist);
-            if ((l & 31) == ul) {
-                theta[cb] = ord_f32(T);
-                cnt[cb] = a.C;
-            }
-        }
+    for (int cb = 0; cb < UBW; cb++)
         if (l < 32 && ug[cb] < a.m) {
-            a.cnt[ug[cb] * a.nseg + seg] = cnt[cb];
-            a.tau[ug[cb] * a.nseg + seg] = theta[cb];
+            a.cnt[ug[cb] * a.nseg_total + seg] = cnt[cb];
+            a.tau[ug[cb] * a.nseg_total + seg] = theta[cb];
         }
-    }
 }
 
 template <int DT, int DPT>
 static void topk_dispatch_g(const TopkArgs& a, hipStream_t s)
 {
-    constexpr int UBW = (DT == DT_F32 && DPT >= 256) ? 1 : 2;
+    constexpr int UBW = topk_ubw(DT, DPT);
     dim3 grid((unsigned)((a.m + TK_WAVES * UBW * 32 - 1) / (TK_WAVES * UBW * 32)), (unsigned)a.nseg);
     const int gpl = a.G / 64;
     if (gpl == 2) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 2>), grid, dim3(256), 0, s, a);
@@ -288,11 +435,7 @@ static void topk_dispatch_g(const TopkArgs& a, hipStream_t s)
     else fail(RKMIPS_EINVAL, "internal: unsupported candidate buffer size");
 }
 
-int topk_users_per_block(int dtype, int ld)
-{
-    const int ubw = (dtype == DT_F32 && ld >= 256) ? 1 : 2;
-    return TK_WAVES * ubw * 32;
-}
+int topk_users_per_block(int dtype, int ld) { return TK_WAVES * topk_ubw(dtype, ld) * 32; }
 
 template <int DT>
 static void topk_dispatch(const TopkArgs& a, hipStream_t s)
@@ -308,7 +451,7 @@ static void topk_dispatch(const TopkArgs& a, hipStream_t s)
 
 void launch_topk(int dtype, const TopkArgs& a, hipStream_t s)
 {
-    if (a.m <= 0 || a.n <= 0) return;
+    if (a.m <= 0 || a.v1 <= a.v0) return;
     if (dtype == DT_F32) topk_dispatch<DT_F32>(a, s);
     else if (dtype == DT_BF16) topk_dispatch<DT_BF16>(a, s);
     else topk_dispatch<DT_FP8>(a, s);
@@ -316,50 +459,135 @@ void launch_topk(int dtype, const TopkArgs& a, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ FP64 refine + certificate
-static constexpr int RF_MAXN = 512;  // candidates per user across segments
+static constexpr int RF_MAXN = 2048;  // candidates per user across segments
+static constexpr int RF_GPL = RF_MAXN / 64;
 
+// Canonical FP64 score of user row u against item row p (FP32/BF16: index-order sum of
+// exact products; FP8: exact code sum times the scale product), with 16-byte loads.
+template <int DT>
+__device__ __forceinline__ double canon_dot_vec(const void* U, int64_t u, float su, const void* P, int64_t p,
+                                                float sp, int d, int ld)
+{
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int PER = 16 / EB;
+    const uint8_t* ur = (const uint8_t*)U + u * (int64_t)ld * EB;
+    const uint8_t* pr = (const uint8_t*)P + p * (int64_t)ld * EB;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < d; c0 += PER) {
+        const i32x4 a4 = *(const i32x4*)(ur + c0 * EB);
+        const i32x4 b4 = *(const i32x4*)(pr + c0 * EB);
+        const int lim = d - c0 < PER ? d - c0 : PER;
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            if (e >= lim) break;
+            float x, y;
+            if constexpr (DT == DT_F32) {
+                x = __int_as_float(a4[e]);
+                y = __int_as_float(b4[e]);
+            } else if constexpr (DT == DT_BF16) {
+                x = bf16_to_f32((uint16_t)((uint32_t)a4[e >> 1] >> (16 * (e & 1))));
+                y = bf16_to_f32((uint16_t)((uint32_t)b4[e >> 1] >> (16 * (e & 1))));
+            } else {
+                x = e4m3_to_f32((uint8_t)((uint32_t)a4[e >> 2] >> (8 * (e & 3))));
+                y = e4m3_to_f32((uint8_t)((uint32_t)b4[e >> 2] >> (8 * (e & 3))));
+            }
+            acc = __fma_rn((double)x, (double)y, acc);
+        }
+    }
+    if constexpr (DT == DT_FP8) acc = ((double)su * (double)sp) * acc;
+    return acc;
+}
+
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double v)
+{
+    // non-negative doubles order like their bit patterns; skip the atomic when it cannot win
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b > __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(addr, b);
+}
+
+// One wave per user: gather the candidates of all segments, keep the C best by the fast
+// score (wave radix select), rescore those in canonical FP64, rank them, write
+// lambda64/lambda32 for j <= k_max and test the certificate
+//   max(tau_s, cut) + eps(u) <= lambda64^(k_max)
+// where every item outside the rescored set scored at most max(tau_s, cut) in the fast
+// arithmetic (tau_s: segment thresholds of the streaming pass; cut: the C-th best fast
+// score among all candidates when some were dropped here).
 template <int DT>
 __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
 {
-    const double err_rel = a.err_rel;
-    __shared__ uint32_t sid[4][RF_MAXN];
-    __shared__ double s64[4][RF_MAXN];
-    __shared__ float sraw[4][RF_MAXN];
+    __shared__ uint32_t skey[4][256];
+    __shared__ uint32_t sid[4][256];
+    __shared__ double s64[4][256];
+    __shared__ float sraw[4][256];
     __shared__ double lam_row[4][256];
     __shared__ float raw_row[4][256];
+    __shared__ int hist_all[4][256];
     const int l = lane_id(), w = threadIdx.x >> 6;
     const int64_t u = (int64_t)blockIdx.x * 4 + w;
     if (u >= a.m) return;
+    int* hist = hist_all[w];
 
-    // gather candidates of all segments
-    int N = 0;
-    for (int s = 0; s < a.nseg; s++) {
-        const int c = a.cnt[u * a.nseg + s];
-        const uint2* rg = a.buf + (u * a.nseg + s) * (int64_t)a.G;
-        for (int i = l; i < c; i += 64) {
-            uint2 e = rg[i];
-            sid[w][N + i] = e.y;
-            sraw[w][N + i] = ord_f32(e.x);
-        }
-        N += c;
+    // gather every segment's buffer straight into registers (entry j = lane + 64 i)
+    int cum[5];
+    cum[0] = 0;
+    float tau_max = -__builtin_inff();
+    for (int s = 0; s < 4; s++) {
+        const int c = s < a.nseg ? a.cnt[u * a.nseg + s] : 0;
+        cum[s + 1] = cum[s] + c;
+        if (s < a.nseg) tau_max = fmaxf(tau_max, a.tau[u * a.nseg + s]);
     }
+    const int N = cum[4];
+    uint32_t key[RF_GPL], id[RF_GPL];
+#pragma unroll
+    for (int i = 0; i < RF_GPL; i++) {
+        const int j = l + 64 * i;
+        key[i] = 0u;
+        id[i] = 0u;
+        if (j < N) {
+            const int s = (j >= cum[1]) + (j >= cum[2]) + (j >= cum[3]);
+            const uint2 e = a.buf[(u * a.nseg + s) * (int64_t)a.G + (j - cum[s])];
+            key[i] = e.x;
+            id[i] = e.y;
+        }
+    }
+    float cut = -__builtin_inff();
+    int Nk = N;
+    int outpos[RF_GPL];
+    if (N > a.C) {
+        int need_eq;
+        const uint32_t T = wave_kth_key<RF_GPL>(key, N, a.C, hist, &need_eq);
+        wave_keep_positions<RF_GPL>(key, N, T, need_eq, outpos);
+        cut = ord_f32(T);
+        Nk = a.C;
+    } else {
+#pragma unroll
+        for (int i = 0; i < RF_GPL; i++) outpos[i] = (l + 64 * i < N) ? l + 64 * i : -1;
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < RF_GPL; i++)
+        if (outpos[i] >= 0) {
+            skey[w][outpos[i]] = key[i];
+            sid[w][outpos[i]] = id[i];
+        }
     __builtin_amdgcn_wave_barrier();
     const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
-    for (int j = l; j < N; j += 64) {
+    for (int j = l; j < Nk; j += 64) {
         const int64_t p = sid[w][j];
-        if (p >= a.n) {                  // never produced by k_topk; guards the load below
-            s64[w][j] = -__builtin_inf();
-            continue;
+        double v = -__builtin_inf();
+        if (p < a.n) {                 // never produced by k_topk; guards the loads below
+            const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
+            v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
         }
-        const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-        s64[w][j] = canon_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
+        s64[w][j] = v;
+        sraw[w][j] = ord_f32(skey[w][j]);
     }
     __builtin_amdgcn_wave_barrier();
-    for (int j = l; j < N; j += 64) {
+    for (int j = l; j < Nk; j += 64) {
         const double x = s64[w][j];
         const float y = sraw[w][j];
         int r64 = 0, rr = 0;
-        for (int i = 0; i < N; i++) {
+        for (int i = 0; i < Nk; i++) {
             const double xi = s64[w][i];
             const float yi = sraw[w][i];
             r64 += (xi > x) || (xi == x && i < j);
@@ -369,34 +597,31 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
         if (rr < a.k_max) raw_row[w][rr] = y;
     }
     __builtin_amdgcn_wave_barrier();
-    double worst = 0.0;
+    const double un = sqrt(a.user_n2[u]);
+    const double M = sqrt(a.item_n2_sorted[0]);
+    double worst_raw = 0.0, worst32 = 0.0;
     for (int r = l; r < a.k_max; r += 64) {
-        const double lv = r < N ? lam_row[w][r] : -__builtin_inf();
+        const double lv = r < Nk ? lam_row[w][r] : -__builtin_inf();
+        const float l32 = (float)lv;
         a.lam64[(int64_t)r * a.m + u] = lv;
-        a.lam32[(int64_t)r * a.m + u] = (float)lv;
-        if (r < N && lv != 0.0) {
-            const double e = fabs((double)raw_row[w][r] - lv) / fabs(lv);
-            worst = e > worst ? e : worst;
+        a.lam32[(int64_t)r * a.m + u] = l32;
+        if (r < Nk && lv != 0.0 && fabs(lv) >= 1e-3 * un * M) {
+            worst_raw = fmax(worst_raw, fabs((double)raw_row[w][r] - lv) / fabs(lv));
+            worst32 = fmax(worst32, fabs((double)l32 - lv) / fabs(lv));
         }
     }
-    worst = wave_max(worst);
-    if (l == 0 && worst > 0.0) atomicMax(a.max_raw_err_bits, (unsigned long long)__double_as_longlong(worst));
-
-    // certificate: every item left out of segment s scored <= tau_s in the fast
-    // arithmetic, hence <= tau_s + eps in exact arithmetic; it cannot enter the top
-    // k_max if that is <= lambda64^(k_max).
+    worst_raw = wave_max(worst_raw);
+    worst32 = wave_max(worst32);
+    if (l == 0) {
+        if (worst_raw > 0.0) atomic_max_pos(a.max_raw_err_bits, worst_raw);
+        if (worst32 > 0.0) atomic_max_pos(a.max_raw_err_bits + 1, worst32);
+    }
     bool ok = !a.force_fail;
-    if (ok && N < a.n) {
-        const double un = sqrt(a.user_n2[u]);
-        const double lk = N >= a.k_max ? lam_row[w][a.k_max - 1] : -__builtin_inf();
-        for (int s = 0; s < a.nseg; s++) {
-            const float t = a.tau[u * a.nseg + s];
-            if (t == -__builtin_inff()) continue;   // every item of the segment is a candidate
-            const int64_t first = (int64_t)s * a.seg_len;
-            const double Ms = sqrt(a.item_n2_sorted[first]);
-            const double bound = (double)t + err_rel * un * Ms + (double)a.d * 0x1p-125 * (un + Ms + 1.0);
-            if (!(bound <= lk)) ok = false;
-        }
+    const float worst_out = fmaxf(tau_max, cut);
+    if (ok && worst_out > -__builtin_inff()) {
+        const double lk = Nk >= a.k_max ? lam_row[w][a.k_max - 1] : -__builtin_inf();
+        const double bound = (double)worst_out + a.err_rel * un * M + (double)a.d * 0x1p-125 * (un + M + 1.0);
+        ok = bound <= lk;
     }
     if (!ok && l == 0) {
         const int pos = atomicAdd(a.fail_count, 1);
@@ -407,7 +632,7 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s)
 {
     if (a.m <= 0) return;
-    if ((int64_t)a.nseg * a.C > RF_MAXN) fail(RKMIPS_EINVAL, "internal: too many candidates per user");
+    if ((int64_t)a.nseg * a.G > RF_MAXN || a.C > 256) fail(RKMIPS_EINVAL, "internal: too many candidates per user");
     dim3 g((unsigned)((a.m + 3) / 4)), b(256);
     if (dtype == DT_F32) hipLaunchKernelGGL(k_refine<DT_F32>, g, b, 0, s, a);
     else if (dtype == DT_BF16) hipLaunchKernelGGL(k_refine<DT_BF16>, g, b, 0, s, a);
@@ -471,6 +696,7 @@ __global__ __launch_bounds__(256) void k_fallback(RefineArgs a, int64_t nfail, d
             for (int i = 0; i < ng; i++) r += (top[i] > top[j]) || (top[i] == top[j] && i < j);
             a.lam64[(int64_t)r * a.m + u] = top[j];
             a.lam32[(int64_t)r * a.m + u] = (float)top[j];
+            if (top[j] != 0.0) atomic_max_pos(a.max_raw_err_bits + 1, fabs((double)(float)top[j] - top[j]) / fabs(top[j]));
         }
         for (int r = ng + tid; r < a.k_max; r += 256) {
             const double v = r < want ? T : -__builtin_inf();
@@ -489,27 +715,6 @@ void launch_fallback(int dtype, const RefineArgs& a, int64_t nfail, double* scra
     if (dtype == DT_F32) hipLaunchKernelGGL(k_fallback<DT_F32>, dim3(g), dim3(256), 0, s, a, nfail, scratch, scratch_rows);
     else if (dtype == DT_BF16) hipLaunchKernelGGL(k_fallback<DT_BF16>, dim3(g), dim3(256), 0, s, a, nfail, scratch, scratch_rows);
     else hipLaunchKernelGGL(k_fallback<DT_FP8>, dim3(g), dim3(256), 0, s, a, nfail, scratch, scratch_rows);
-    HIPC(hipGetLastError());
-}
-
-__global__ void k_lam32_err(const double* lam64, const float* lam32, int64_t count, unsigned long long* out)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double e = 0.0;
-    if (i < count) {
-        const double x = lam64[i];
-        if (x != 0.0 && x != -__builtin_inf()) e = fabs((double)lam32[i] - x) / fabs(x);
-    }
-    e = wave_max(e);
-    if (lane_id() == 0 && e > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(e));
-}
-
-void launch_lambda32_err(const double* lam64, const float* lam32, int64_t count, unsigned long long* max_err_bits,
-                         hipStream_t s)
-{
-    if (count <= 0) return;
-    hipLaunchKernelGGL(k_lam32_err, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, lam64, lam32, count,
-                       max_err_bits);
     HIPC(hipGetLastError());
 }
 
