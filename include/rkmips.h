@@ -100,7 +100,7 @@ void rkmips_default_params(rkmips_params *p);
  * [(d+1) x num_hash] row-major Gaussian projection matrix (column h is the vector a
  * of one hash function), or NULL to draw it from p->seed inside the library.
  * p: NULL for defaults.  Synchronous: returns after the index is complete.
- * Errors: EINVAL (null pointers, n, m, d < 1, d > 1024, bad params, non-finite
+ * Errors: EINVAL (null pointers, n, m, d < 1, d > 256, bad params, non-finite
  * values), ERANGE (max||u|| * max||p|| beyond 1e30 or a non-zero vector norm below
  * 1e-30, where FP32 bounds would lose exactness), ENOMEM, EDEVICE.
  */
@@ -115,8 +115,10 @@ rkmips_status rkmips_build_index(const void *items, const float *item_scales, in
  * FP8, else NULL).  ks: HOST int32 [nq], 1 <= ks[i] <= k_max.  flags: RKMIPS_FLAG_*
  * added to the index defaults for this call.  The work is enqueued on `stream`;
  * *out receives a result handle whose contents are valid after rkmips_result_wait.
- * nq = 0 is allowed (empty result).  Errors: EINVAL, ERANGE (a k out of range,
- * a query norm outside the exact range), ENOMEM, EDEVICE.
+ * nq = 0 is allowed (empty result).  Errors: EINVAL, ERANGE (a k out of range),
+ * ENOMEM, EDEVICE.  Conditions that need the device data (a non-finite query value:
+ * EINVAL; a query norm outside [1e-30, 1e30]: ERANGE) are returned by
+ * rkmips_result_wait, and the result is then empty.
  */
 rkmips_status rkmips_query_batch(rkmips_index *idx, const void *queries, const float *query_scales,
                                  int64_t nq, const int32_t *ks, int32_t flags, void *stream,
@@ -184,6 +186,21 @@ rkmips_status rkmips_get_candidates(const rkmips_index *idx, int32_t *ids, float
  * ORIGINAL user.  Any pointer may be NULL to skip that array. */
 rkmips_status rkmips_get_saalsh(const rkmips_index *idx, int64_t *part_start, float *centroid,
                                 float *radius, uint32_t *item_codes, uint32_t *user_codes);
+
+/* SA-ALSH query of Alg. 2 for explicit (query, user) pairs, as the paper states it:
+ * partitions in order of M_j; yes if phi > M_j ||u||; SimHash probe of the
+ * ceil(beta |S_j|) items whose K-bit codes agree most with the user's (equal counts:
+ * earlier in the item order first); phi = k-th largest canonical inner product over all
+ * candidates so far; no if <u,q> < phi; yes after the last partition.
+ * queries: device [nq x d] (query_scales device [nq] for FP8); ks: host [nq];
+ * pair_query / pair_user: host int64 [npairs] (query row, ORIGINAL user index);
+ * phi_out: host double [npairs]; answer_out: host int32 [npairs] (1 yes, 0 no).
+ * A "no" is exact (phi is a k-th largest over a subset of the items); a "yes" is the
+ * paper's approximate decision.  Synchronous on `stream`.  Errors: EINVAL, ERANGE. */
+rkmips_status rkmips_saalsh_probe(rkmips_index *idx, const void *queries, const float *query_scales,
+                                  int64_t nq, const int32_t *ks, const int64_t *pair_query,
+                                  const int64_t *pair_user, int64_t npairs, float probe_frac,
+                                  void *stream, double *phi_out, int32_t *answer_out);
 
 /* Cone-Tree blocks of step 4.  leaf_users: host int32 [m] original user indices in
  * leaf order; block_start: host int64 [B+1]; center: host float [B x d] unit block

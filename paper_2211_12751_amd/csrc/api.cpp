@@ -124,7 +124,7 @@ static void choose_topk(Index& x)
     x.nseg = nmain + seed;
     x.seg_len = seg_len;
     // buffer capacity: large buffers make the wave-wide compactions rare
-    int gpl = 8;
+    int gpl = 4;
     while (gpl > 2 && (double)x.m * x.nseg * gpl * 64 * 8 > 24e9) gpl /= 2;
     while (gpl * 64 < C + 32) gpl *= 2;
     if (gpl > 8) fail(RKMIPS_ENOMEM, "candidate buffers exceed the memory budget");

@@ -153,6 +153,22 @@ void launch_saalsh_items(const SaIndexArgs& a, const int64_t* part_start_host, i
 void launch_user_codes(int dtype, const void* users, const float* user_scales, int64_t m, int d,
                        int ld, const float* A, int K, uint32_t* codes, hipStream_t s);
 
+struct SaQueryArgs {
+    int dtype;
+    const void* items; const float* item_scales; int64_t n; int d, ld;   // sorted order
+    const void* users; const float* user_scales;                          // leaf order
+    const void* queries; const float* query_scales;                       // padded copy
+    const double* item_n2; const double* user_n2;
+    const int64_t* part_start; int t;
+    const uint32_t* item_codes; const uint32_t* user_codes; int K;
+    float beta;
+    const unsigned long long* pairs; int64_t npairs;   // (query << 32) | leaf user
+    const int* qk;                                     // k per query
+    double* phi; int* answer;                          // per pair
+};
+// Alg. 2 for each pair; scratch: grid x scratch_stride doubles (>= ceil(beta n) + t).
+void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_stride, int grid, hipStream_t s);
+
 // ---------------------------------------------------------------- query
 struct QueryArgs {
     int dtype;
@@ -183,7 +199,7 @@ struct QueryArgs {
 void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, int ld,
                   float* qnorm, int* bad, hipStream_t s);
 void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
-void launch_recheck(const QueryArgs& a, int64_t namb, hipStream_t s);
+void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s);
 void launch_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets,
                     int32_t* ids, hipStream_t s);
 

@@ -306,10 +306,14 @@ __device__ double canon_dot2(const void* A, int64_t ra, int lda, float sa, const
 }
 
 template <int DT>
-__global__ void k_recheck(QueryArgs a, int64_t namb)
+__global__ void k_recheck(QueryArgs a, int64_t namb, const int* reject)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= namb) return;
+    if (reject && reject[i] == 0) {   // Alg. 2 proved s(u,q) < phi <= lambda_u^(k)
+        atomicAdd(&a.stats[4], 1ull);
+        return;
+    }
     const unsigned long long key = a.amb[i];
     const int64_t q = (int64_t)(key >> 32);
     const int64_t u = (int64_t)(key & 0xffffffffull);
@@ -323,13 +327,13 @@ __global__ void k_recheck(QueryArgs a, int64_t namb)
     }
 }
 
-void launch_recheck(const QueryArgs& a, int64_t namb, hipStream_t s)
+void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s)
 {
     if (namb <= 0) return;
     dim3 g((unsigned)((namb + 255) / 256)), b(256);
-    if (a.dtype == DT_F32) hipLaunchKernelGGL(k_recheck<DT_F32>, g, b, 0, s, a, namb);
-    else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_recheck<DT_BF16>, g, b, 0, s, a, namb);
-    else hipLaunchKernelGGL(k_recheck<DT_FP8>, g, b, 0, s, a, namb);
+    if (a.dtype == DT_F32) hipLaunchKernelGGL(k_recheck<DT_F32>, g, b, 0, s, a, namb, reject);
+    else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_recheck<DT_BF16>, g, b, 0, s, a, namb, reject);
+    else hipLaunchKernelGGL(k_recheck<DT_FP8>, g, b, 0, s, a, namb, reject);
     HIPC(hipGetLastError());
 }
 

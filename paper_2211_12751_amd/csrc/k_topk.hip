@@ -194,7 +194,7 @@ __device__ __forceinline__ uint32_t select_user(uint2* region, int c, int C, int
 }
 
 template <int DT, int DPT, int UBW, int GPL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F32 ? 2 : 1, 8))) void k_topk(TopkArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT < 256) ? 2 : 1, 8))) void k_topk(TopkArgs a)
 {
     constexpr int EB = Elt<DT>::bytes;
     constexpr int ROWB = DPT * EB;                // bytes of one stored row

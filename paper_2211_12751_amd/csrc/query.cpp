@@ -217,6 +217,42 @@ void plan_batch(const Index& x, Workspace& w, const int32_t* ks, int64_t nq)
     (void)x;
 }
 
+SaQueryArgs make_sa_args(const Index& x, const void* queries, const float* qscales, const int* qk,
+                         const unsigned long long* pairs, int64_t npairs, float beta, double* phi, int* answer)
+{
+    SaQueryArgs sa{};
+    sa.dtype = x.dtype;
+    sa.items = x.items.p; sa.item_scales = x.item_scales.f(); sa.n = x.n; sa.d = x.d; sa.ld = x.ld;
+    sa.users = x.users.p; sa.user_scales = x.user_scales.f();
+    sa.queries = queries; sa.query_scales = qscales;
+    sa.item_n2 = x.item_n2.d(); sa.user_n2 = x.user_n2.d();
+    sa.part_start = x.part_start.i64(); sa.t = x.t;
+    sa.item_codes = x.item_codes.u32(); sa.user_codes = x.user_codes.u32(); sa.K = x.prm.num_hash;
+    sa.beta = beta;
+    sa.pairs = pairs; sa.npairs = npairs; sa.qk = qk;
+    sa.phi = phi; sa.answer = answer;
+    return sa;
+}
+
+int64_t saalsh_scratch_stride(const Index& x, float beta)
+{
+    return (int64_t)std::ceil((double)beta * (double)x.n) + x.t + 1;
+}
+
+void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs, hipStream_t s)
+{
+    const int grid = (int)std::min<int64_t>(npairs, 128);
+    const int64_t stride = saalsh_scratch_stride(x, x.prm.probe_frac);
+    if ((int64_t)w.sa_scratch.bytes < (int64_t)sizeof(double) * grid * stride) w.sa_scratch.alloc(sizeof(double) * grid * stride);
+    if ((int64_t)w.sa_answer.bytes < (int64_t)sizeof(int) * w.amb_cap) {
+        w.sa_answer.alloc(sizeof(int) * w.amb_cap);
+        w.sa_phi.alloc(sizeof(double) * w.amb_cap);
+    }
+    SaQueryArgs sa = make_sa_args(x, a.queries, a.query_scales, a.qk, a.amb, npairs, x.prm.probe_frac, w.sa_phi.d(),
+                                  w.sa_answer.i());
+    launch_saalsh_query(sa, w.sa_scratch.d(), stride, grid, s);
+}
+
 // Completion: overflow handling, FP64 recheck, sorted per-query lists, host copies.
 void finish_batch(Index& x, Workspace& w, const void* queries, const float* qscales, int64_t nq, int flags,
                   hipStream_t s, std::vector<int64_t>& offsets, std::vector<int32_t>& ids, rkmips_query_stats& st)
@@ -243,7 +279,14 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     st.pairs_rechecked = namb;
     QueryArgs a = make_query_args(x, w, nq, flags);
     fill_u64((unsigned long long*)w.pool.p + cnt, namb, ~0ull, s);
-    if (namb > 0) launch_recheck(a, namb, s);
+    const int* reject = nullptr;
+    if (namb > 0 && !((flags | x.prm.flags) & RKMIPS_FLAG_NO_SAALSH)) {
+        // Alg. 2 as a proof-only filter on the close calls: a "no" there is exact
+        run_saalsh(x, w, a, namb, s);
+        reject = w.sa_answer.i();
+        st.saalsh_checked = namb;
+    }
+    if (namb > 0) launch_recheck(a, namb, reject, s);
     const int64_t span = cnt + namb;
     if (span > 1) sort_keys((uint64_t*)w.pool.p, span, w.pool_cap, s);
     launch_offsets((const uint64_t*)w.pool.p, std::max<int64_t>(span, 0), nq, w.offsets.i64(), (int32_t*)w.ids.p, s);
@@ -254,8 +297,10 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     if (total > 0) {
         HIPC(hipMemcpyAsync(w.h_ids.p, w.ids.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
     }
+    if (reject) HIPC(hipMemcpyAsync(w.h_ctr.p, w.ctr.p, sizeof(unsigned long long) * 16, hipMemcpyDeviceToHost, s));
     HIPC(hipEventRecord(w.ev1, s));
     HIPC(hipStreamSynchronize(s));
+    if (reject) st.saalsh_rejects = (int64_t)((unsigned long long*)w.h_ctr.p)[12];
     offsets.assign(ho, ho + nq + 1);
     ids.assign((const int32_t*)w.h_ids.p, (const int32_t*)w.h_ids.p + total);
     st.results = total;
@@ -267,22 +312,6 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
 }  // namespace rk
 
 using namespace rk;
-
-struct rkmips_result {
-    Index* idx = nullptr;
-    Workspace* ws = nullptr;
-    hipStream_t s = nullptr;
-    int64_t nq = 0;
-    int flags = 0;
-    const void* queries = nullptr;
-    const float* qscales = nullptr;
-    bool done = false;
-    rkmips_status status = RKMIPS_OK;
-    std::string err;
-    std::vector<int64_t> offsets;
-    std::vector<int32_t> ids;
-    rkmips_query_stats st{};
-};
 
 namespace rk {
 rkmips_status guarded_call(void (*fn)(void*), void* ctx);
@@ -377,6 +406,54 @@ void rkmips_result_free(rkmips_result* r)
     if (!r) return;
     if (!r->done) (void)rkmips_result_wait(r);
     delete r;
+}
+
+rkmips_status rkmips_saalsh_probe(rkmips_index* idx, const void* queries, const float* query_scales, int64_t nq,
+                                  const int32_t* ks, const int64_t* pair_query, const int64_t* pair_user,
+                                  int64_t npairs, float probe_frac, void* stream, double* phi_out, int32_t* answer_out)
+{
+    return qguard([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "index is NULL");
+        Index& x = *(Index*)idx;
+        if (nq < 1 || !queries || !ks) fail(RKMIPS_EINVAL, "queries/ks missing");
+        if (npairs < 0 || (npairs > 0 && (!pair_query || !pair_user || !phi_out || !answer_out)))
+            fail(RKMIPS_EINVAL, "pair arrays missing");
+        if (!(probe_frac > 0.f && probe_frac <= 1.f)) fail(RKMIPS_EINVAL, "probe_frac must be in (0, 1]");
+        const bool fp8 = x.dtype == RKMIPS_FP8_E4M3;
+        if (fp8 != (query_scales != nullptr)) fail(RKMIPS_EINVAL, "scales are required exactly for FP8 data");
+        for (int64_t i = 0; i < nq; i++)
+            if (ks[i] < 1 || ks[i] > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
+        std::vector<uint32_t> perm(x.m), inv(x.m);
+        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < x.m; i++) inv[perm[i]] = (uint32_t)i;
+        std::vector<unsigned long long> pairs(npairs);
+        for (int64_t i = 0; i < npairs; i++) {
+            if (pair_query[i] < 0 || pair_query[i] >= nq || pair_user[i] < 0 || pair_user[i] >= x.m)
+                fail(RKMIPS_EINVAL, "pair index out of range");
+            pairs[i] = ((unsigned long long)pair_query[i] << 32) | inv[pair_user[i]];
+        }
+        if (npairs == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        DevBuf qpad, qsc, qk, dpairs, phi, ans, scratch;
+        qpad.alloc((size_t)nq * x.ld * elt_bytes(x.dtype));
+        if (fp8) qsc.alloc(sizeof(float) * nq);
+        qk.alloc(sizeof(int) * nq);
+        dpairs.alloc(sizeof(unsigned long long) * npairs);
+        phi.alloc(sizeof(double) * npairs);
+        ans.alloc(sizeof(int) * npairs);
+        launch_gather_rows(x.dtype, queries, x.d, query_scales, nullptr, nq, x.d, qpad.p, x.ld, qsc.f(), s);
+        HIPC(hipMemcpyAsync(qk.p, ks, sizeof(int) * nq, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(dpairs.p, pairs.data(), sizeof(unsigned long long) * npairs, hipMemcpyHostToDevice, s));
+        const int grid = (int)std::min<int64_t>(npairs, 128);
+        const int64_t stride = saalsh_scratch_stride(x, probe_frac);
+        scratch.alloc(sizeof(double) * (size_t)grid * stride);
+        SaQueryArgs sa = make_sa_args(x, qpad.p, qsc.f(), qk.i(), (const unsigned long long*)dpairs.p, npairs,
+                                      probe_frac, phi.d(), ans.i());
+        launch_saalsh_query(sa, scratch.d(), stride, grid, s);
+        HIPC(hipMemcpyAsync(phi_out, phi.p, sizeof(double) * npairs, hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(answer_out, ans.p, sizeof(int) * npairs, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    });
 }
 
 rkmips_status rkmips_get_saalsh(const rkmips_index* idx, int64_t* part_start, float* centroid, float* radius,

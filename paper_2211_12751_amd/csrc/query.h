@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "index.h"
@@ -31,6 +32,7 @@ struct Group {
 struct Workspace {
     int64_t nq_cap = 0, pool_cap = 0, amb_cap = 0;
     DevBuf qpad, qsc, qnorm, qslot, qorig, qk, slotk, offsets, pool, ids, amb, ctr;
+    DevBuf sa_scratch, sa_answer, sa_phi;   // SA-ALSH stage
     PinBuf h_qslot, h_qorig, h_qk, h_slotk, h_offsets, h_ids, h_ctr;
     std::vector<Group> groups;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_ctr = nullptr;
@@ -40,6 +42,10 @@ struct Workspace {
     static int64_t bytes_for(const Index& x, int64_t nq, int64_t pool_cap, int64_t amb_cap);
 };
 
+void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs, hipStream_t s);
+SaQueryArgs make_sa_args(const Index& x, const void* queries, const float* qscales, const int* qk,
+                         const unsigned long long* pairs, int64_t npairs, float beta, double* phi, int* answer);
+int64_t saalsh_scratch_stride(const Index& x, float beta);
 QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags);
 void plan_batch(const Index& x, Workspace& w, const int32_t* ks, int64_t nq);
 void enqueue_batch(const Index& x, Workspace& w, const void* queries, const float* qscales, int64_t nq,
@@ -48,4 +54,26 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
                   hipStream_t s, std::vector<int64_t>& offsets, std::vector<int32_t>& ids,
                   rkmips_query_stats& st);
 
+}  // namespace rk
+
+// Outputs of one query batch (owned by the caller through the C handle).
+struct rkmips_result {
+    rk::Index* idx = nullptr;
+    rk::Workspace* ws = nullptr;
+    hipStream_t s = nullptr;
+    int64_t nq = 0;
+    int flags = 0;
+    const void* queries = nullptr;
+    const float* qscales = nullptr;
+    bool done = false;
+    rkmips_status status = RKMIPS_OK;
+    std::string err;
+    std::vector<int64_t> offsets;
+    std::vector<int32_t> ids;
+    rkmips_query_stats st{};
+};
+
+
+namespace rk {
+rkmips_status guarded_call(void (*fn)(void*), void* ctx);
 }  // namespace rk

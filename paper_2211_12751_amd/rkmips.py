@@ -85,6 +85,7 @@ _sig = {
     "rkmips_get_candidates": (C.c_int, [_P, _P, _P, _P]),
     "rkmips_get_saalsh": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "rkmips_get_blocks": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "rkmips_saalsh_probe": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, C.c_float, _P, _P, _P]),
     "rkmips_index_free": (None, [_P]),
     "rkmips_last_error": (C.c_char_p, []),
     "rkmips_serve_replay": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, C.POINTER(rkmips_serve_params), _P,
@@ -223,6 +224,17 @@ def rkmips_get_blocks(idx, m, d, nblocks, k_max):
     return out
 
 
+def rkmips_saalsh_probe(idx, queries, query_scales, nq, ks, pair_query, pair_user, probe_frac, stream=None):
+    ks = np.ascontiguousarray(ks, dtype=np.int32)
+    pq = np.ascontiguousarray(pair_query, dtype=np.int64)
+    pu = np.ascontiguousarray(pair_user, dtype=np.int64)
+    phi = np.empty(len(pq), np.float64)
+    ans = np.empty(len(pq), np.int32)
+    _check(_lib.rkmips_saalsh_probe(idx, _ptr(queries), _ptr(query_scales), nq, _ptr(ks), _ptr(pq), _ptr(pu),
+                                    len(pq), probe_frac, _stream(stream), _ptr(phi), _ptr(ans)))
+    return phi, ans
+
+
 def rkmips_index_free(idx):
     _lib.rkmips_index_free(idx)
 
@@ -303,6 +315,21 @@ class Index:
 
     def blocks(self):
         return rkmips_get_blocks(self.h, self.m, self.d, self.info["num_blocks"], self.params.k_max)
+
+    def serve(self, queries, query_scales, ks, arrival_us, max_batch=256, num_streams=4, mem_budget=0, flags=0):
+        """Replay a timed request stream through the continuous-batching server.
+        queries: host numpy storage array.  Returns (answers, latency_us, stats)."""
+        q = np.ascontiguousarray(queries)
+        q = q.view(np.int16) if q.dtype == np.uint16 else q
+        qs = None if query_scales is None else np.ascontiguousarray(query_scales, dtype=np.float32)
+        sp = rkmips_serve_params(max_batch, num_streams, mem_budget, flags)
+        nq = int(q.shape[0])
+        h, lat, st = rkmips_serve_replay(self.h, q, qs, nq, ks, arrival_us, sp)
+        try:
+            off, ids = rkmips_result_view(h)
+        finally:
+            rkmips_result_free(h)
+        return [ids[off[i]:off[i + 1]] for i in range(nq)], lat, st
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,0 +1,99 @@
+"""SA-ALSH on the GPU against the CPU FP64 reference of Alg. 1 and Alg. 2.
+
+Codes are signs of FP32 projections on the GPU and of FP64 projections in the
+reference, so a bit may differ only where the FP64 projection is within rounding
+of zero; every other bit, the partitions, and -- when all codes agree -- the Alg. 2
+phi values and answers must be identical.  A "no" of Alg. 2 must always be a true no.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_12751_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _proj_margins(P, order, ps, cen, rad, A):
+    """|FP64 projection| / (||x|| ||a||) per (item, hash) of the transformed items."""
+    n, d = P.shape
+    marg = np.empty((n, A.shape[1]))
+    for j in range(len(ps) - 1):
+        mem = order[ps[j]:ps[j + 1]]
+        X = P[mem].astype(np.float64) - cen[j]
+        last = np.sqrt(np.maximum(0.0, rad[j] ** 2 - (X ** 2).sum(1)))
+        Xt = np.concatenate([X, last[:, None]], axis=1)
+        pr = Xt @ A.astype(np.float64)
+        marg[mem] = np.abs(pr) / (np.linalg.norm(Xt, axis=1)[:, None] * np.linalg.norm(A, axis=0)[None, :] + 1e-300)
+    return marg
+
+
+@pytest.mark.parametrize("seed", [3, 8])
+def test_codes_partitions_and_alg2(seed):
+    from paper_2211_12751_amd import rkmips as R
+    w = I.make("c2", n=900, m=700, d=16, nq=30, seed=seed)
+    K, k_max, beta = 64, 10, 0.2
+    A = I.srp_matrix(w.d, K, seed=seed)
+    print(f"\n[case] saalsh n={w.n} m={w.m} d={w.d} K={K} seed={seed}", flush=True)
+    idx = R.Index(w.items, None, w.users, None, dtype="f32", k_max=k_max, num_hash=K, srp=A)
+    try:
+        n2, order = O.item_order("f32", w.items, None)
+        ps = O.partitions(n2, order, 0.5)
+        cen, rad, icodes = O.saalsh_index("f32", w.items, None, order, ps, A)
+        ucodes = O.user_codes("f32", w.users, None, A)
+        gps, gcen, grad, gic, guc = idx.saalsh()
+        assert np.array_equal(gps, ps)
+        assert np.allclose(gcen, cen, rtol=1e-6, atol=1e-6) and np.allclose(grad, rad, rtol=1e-5)
+        # item bits: equal wherever the FP64 projection is clear of zero
+        marg = _proj_margins(w.items, order, ps, cen, rad, A)
+        bits_o = ((icodes[:, :, None] >> np.arange(32)) & 1).reshape(w.n, K)
+        bits_g = ((gic[:, :, None] >> np.arange(32)) & 1).reshape(w.n, K)
+        clear = marg > 1e-4
+        assert np.array_equal(bits_o[clear], bits_g[clear])
+        umarg = np.abs(w.users.astype(np.float64) @ A[:w.d].astype(np.float64)) / (
+            np.linalg.norm(w.users, axis=1)[:, None] * np.linalg.norm(A[:w.d], axis=0)[None, :])
+        ubo = ((ucodes[:, :, None] >> np.arange(32)) & 1).reshape(w.m, K)
+        ubg = ((guc[:, :, None] >> np.arange(32)) & 1).reshape(w.m, K)
+        assert np.array_equal(ubo[umarg > 1e-4], ubg[umarg > 1e-4])
+        codes_equal = np.array_equal(icodes, gic)
+        # Alg. 2 on sampled pairs
+        g = np.random.default_rng(seed)
+        ks = g.integers(1, k_max + 1, w.nq).astype(np.int32)
+        pq = g.integers(0, w.nq, 300)
+        pu = g.integers(0, w.m, 300)
+        lam = O.lambda_table("f32", w.items, None, w.users, None, k_max)
+        mem = O.member("f32", w.users, None, w.queries, None, ks, lam)
+        phi, ans = R.rkmips_saalsh_probe(idx.h, R.to_device(w.queries), None, w.nq, ks, pq, pu, beta)
+        for i in range(len(pq)):
+            if ans[i] == 0:
+                assert mem[pq[i], pu[i]] == 0, "Alg. 2 rejected a true answer"
+            if codes_equal and np.array_equal(ucodes[pu[i]], guc[pu[i]]):
+                a_o, phi_o = O.saalsh_decide("f32", w.items, None, n2, order, ps, icodes, ucodes[pu[i]], beta,
+                                             w.users, None, int(pu[i]), w.queries, None, int(pq[i]), int(ks[pq[i]]))
+                assert a_o == ans[i] and phi_o == phi[i], (i, a_o, ans[i], phi_o, phi[i])
+        print("codes_equal", codes_equal, "rejects", int((ans == 0).sum()), flush=True)
+    finally:
+        idx.close()
+
+
+def test_exact_queries_with_saalsh_stage():
+    """Every close call passes through Alg. 2 (forced recheck): answers unchanged."""
+    from paper_2211_12751_amd import rkmips as R
+    w = I.make("c1", n=800, m=1500, nq=40, seed=21)
+    k_max = 10
+    ks = (np.arange(40) % k_max + 1).astype(np.int32)
+    lam = O.lambda_table("f32", w.items, None, w.users, None, k_max)
+    ref = [np.flatnonzero(r) for r in O.member("f32", w.users, None, w.queries, None, ks, lam)]
+    idx = R.Index(w.items, None, w.users, None, dtype="f32", k_max=k_max, probe_frac=0.3)
+    try:
+        got, st = idx.query(w.queries, None, ks, flags=R.FLAG_FORCE_RECHECK, stats=True)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+        assert st["saalsh_checked"] == st["pairs_rechecked"] > 0
+        assert st["saalsh_rejects"] > 0
+        got2 = idx.query(w.queries, None, ks, flags=R.FLAG_FORCE_RECHECK | R.FLAG_NO_SAALSH)
+        for a, b in zip(got2, ref):
+            assert np.array_equal(a, b)
+        print("stats", st, flush=True)
+    finally:
+        idx.close()

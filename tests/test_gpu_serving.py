@@ -1,0 +1,52 @@
+"""Continuous-batching server: every answer equals the answer of the same request
+alone and the CPU FP64 reference, while batches of mixed k overlap on the device."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_12751_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2211_12751_amd import rkmips as R
+    w = I.make("c1", n=2000, m=5000, d=32, nq=600, seed=17)
+    k_max = 10
+    ks = I.k_draws(w.nq, values=(1, 5, 10), seed=17)
+    lam = O.lambda_table("f32", w.items, None, w.users, None, k_max)
+    mem = O.member("f32", w.users, None, w.queries, None, ks, lam)
+    print(f"\n[case] serving n={w.n} m={w.m} d={w.d} nq={w.nq}", flush=True)
+    idx = R.Index(w.items, None, w.users, None, dtype="f32", k_max=k_max)
+    yield R, w, ks, mem, idx
+    idx.close()
+
+
+@pytest.mark.parametrize("qps,max_batch,streams", [(20000.0, 32, 4), (5000.0, 256, 2), (1e6, 64, 1)])
+def test_serving_matches_alone_and_reference(setup, qps, max_batch, streams):
+    R, w, ks, mem, idx = setup
+    arr = I.poisson_arrivals(w.nq, qps, seed=5)
+    got, lat, st = idx.serve(w.queries, None, ks, arr, max_batch=max_batch, num_streams=streams)
+    print("stats", st, flush=True)
+    alone = idx.query(w.queries[:40], None, ks[:40])
+    for i in range(w.nq):
+        assert np.array_equal(got[i], np.flatnonzero(mem[i])), f"request {i}"
+        if i < 40:
+            assert np.array_equal(got[i], alone[i])
+    assert st["batches"] >= (w.nq + max_batch - 1) // max_batch
+    assert 1 <= st["max_inflight"] <= streams
+    assert (lat > 0).all() and st["p99_us"] >= st["p50_us"] > 0
+
+
+def test_memory_budget_admission(setup):
+    R, w, ks, mem, idx = setup
+    arr = I.poisson_arrivals(w.nq, 50000.0, seed=6)
+    with pytest.raises(R.RkmipsError) as e:
+        idx.serve(w.queries, None, ks, arr, max_batch=64, num_streams=4, mem_budget=1024)
+    assert e.value.status == -2
+    # a budget of about two slots admits two of the four requested streams
+    got, lat, st = idx.serve(w.queries, None, ks, arr, max_batch=64, num_streams=4, mem_budget=2_700_000)
+    assert 1 <= st["slots"] <= 4
+    for i in range(w.nq):
+        assert np.array_equal(got[i], np.flatnonzero(mem[i]))
