@@ -50,6 +50,10 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -61,7 +65,9 @@ def main():
     from paper_2211_12751_amd import rkmips as R
 
     torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
     w = I.make(args.config)
+    log(f"{args.config}: inputs generated in {time.perf_counter() - t_gen:.1f} s")
     k_max = w.k_max
     dtype = R.DTYPES[w.dtype]
     items = R.to_device(w.items)
@@ -95,10 +101,12 @@ def main():
         R.rkmips_index_free(h)
         return info, st, (t1 - t0), off, ids
 
-    def serving(qps_frac=0.5, nreq=4000, max_batch=256, streams=4):
+    def serving(qps_frac=0.5, nreq=None, max_batch=256, streams=4):
         """Continuous-batching replay on one index: Poisson arrivals of fresh item draws
         with k uniform over the workload's k values, at a fraction of the measured
         batch throughput."""
+        if nreq is None:
+            nreq = 20_000 if w.m >= 1_000_000 else 4_000
         g = I.rng("queries", w.seed + 1)
         kind = I.CONFIGS[args.config]["items"]
         Qs = I.draw(kind, nreq, w.d, g)
@@ -130,13 +138,15 @@ def main():
                 "max_inflight": int(st["max_inflight"]),
                 "achieved_qps": round(nreq / (st["wall_ms"] * 1e-3), 1) if st["wall_ms"] > 0 else None}
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        log(f"warmup step {i} done")
     torch.cuda.synchronize()
     infos, sts, qlat = [], [], []
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         info, st, ql, off, ids = step()
+        log(f"step {i}: build {info['ms_total']:.1f} ms, query {st['ms_total']:.1f} ms")
         infos.append(info)
         sts.append(st)
         qlat.append(ql)
@@ -197,14 +207,16 @@ def main():
     }
 
     if not args.no_serving:
+        log("serving replay")
         line["serving"] = serving()
         line["p99_latency_ms"] = line["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         line["cpu_baseline"], line["parity_sample"] = cpu_baseline(w, k_max, off, ids, args.cpu_sample_users)
     print(json.dumps(line), flush=True)
 
 
-TOPK_SOURCES = ("k_topk.hip", "internal.h", "common.h", "api.cpp")
+TOPK_SOURCES = ("k_topk.hip", "internal.h", "common.h")
 
 
 def topk_source_hash():

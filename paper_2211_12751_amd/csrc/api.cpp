@@ -12,6 +12,7 @@
 #include "common.h"
 #include "index.h"
 #include "internal.h"
+#include "mem.h"
 #include "query.h"
 
 namespace rk {
@@ -38,7 +39,7 @@ int padded_dim(int d, int /*dtype*/)
 DevBuf::~DevBuf() { reset(); }
 void DevBuf::reset()
 {
-    if (p) (void)hipFree(p);
+    if (p) mem::device_free(p, bytes);
     p = nullptr;
     bytes = 0;
 }
@@ -46,11 +47,8 @@ void DevBuf::alloc(size_t b)
 {
     reset();
     if (b == 0) b = 16;
-    if (hipMalloc(&p, b) != hipSuccess) {
-        (void)hipGetLastError();
-        p = nullptr;
-        fail(RKMIPS_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
-    }
+    p = mem::device_alloc(b, nullptr);
+    if (!p) fail(RKMIPS_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
     bytes = b;
 }
 
@@ -282,8 +280,12 @@ void range_check(Index& x, const double* n2i, int64_t n, const double* n2u, int6
 
 Index::~Index()
 {
+    // every use of the index's buffers is complete: they go back to the cache as idle
+    // blocks (the members are released after this body, the tail guard ends the scope)
     (void)hipDeviceSynchronize();
+    mem::idle_enter();
 }
+IdleTail::~IdleTail() { mem::idle_leave(); }
 
 }  // namespace rk
 
@@ -358,6 +360,7 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
         x->n = n; x->m = m; x->d = d; x->dtype = dtype; x->prm = prm;
         x->ld = padded_dim(d, dtype);
         HIPC(hipGetDevice(&x->device));
+        mem::StreamScope scope((hipStream_t)stream);
         build_index(*x, items, item_scales, users, user_scales, srp_proj, (hipStream_t)stream);
         *out = (rkmips_index*)x.release();
     });

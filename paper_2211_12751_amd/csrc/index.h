@@ -35,7 +35,15 @@ struct DevBuf {
 
 struct Workspace;
 
+// Ends the idle-release scope that ~Index opens; declared first in Index so that it is
+// destroyed after every buffer member.
+struct IdleTail {
+    IdleTail() = default;
+    ~IdleTail();
+};
+
 struct Index {
+    IdleTail idle_tail;
     int device = 0;
     int64_t n = 0, m = 0;
     int d = 0, ld = 0, dtype = 0;

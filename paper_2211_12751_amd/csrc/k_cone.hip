@@ -11,11 +11,13 @@
 // Users are unit-normalised first (Fact 2: the norm of u does not change its MIPS
 // result), so inner products are cosines.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
 #include "index.h"
 #include "internal.h"
+#include "query.h"
 
 namespace rk {
 
@@ -220,6 +222,17 @@ __global__ void k_block_lb(const double* lam64, const double* user_n2, const int
     lb[(int64_t)j * nblocks + b] = out;
 }
 
+// Per-level reset of the segment reductions.
+__global__ void k_cone_init(ConeLevelArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.nseg) {
+        a.key1[i] = ~0ull;
+        a.key2[i] = ~0ull;
+        a.nleft[i] = 0;
+    }
+}
+
 // ------------------------------------------------------------------ host orchestration
 void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s)
 {
@@ -244,78 +257,89 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
 
     const int N0 = x.prm.leaf_size;
     std::vector<int64_t> starts{0, m};   // segment boundaries (sorted), last = m
-    std::vector<int> active;
-    DevBuf d_starts, d_active, d_pivot, d_key1, d_key2, d_nleft, d_degen;
-    {
-        const int64_t cap = m + 2;
-        d_starts.alloc(sizeof(int64_t) * (cap + 1));
-        d_active.alloc(sizeof(int) * cap);
-        d_pivot.alloc(sizeof(int64_t) * cap);
-        d_key1.alloc(sizeof(uint64_t) * cap);
-        d_key2.alloc(sizeof(uint64_t) * cap);
-        d_nleft.alloc(sizeof(int) * cap);
-        d_degen.alloc(sizeof(int) * cap);
-    }
+    // Per-level tables go to the device in one copy from pinned memory, packed for the
+    // level's nseg: starts [nseg+1] and pivots [nseg] (int64), active flags [nseg] (int);
+    // the degenerate flags [nseg] (int) follow in a second copy after the split.  Two
+    // staging areas alternate between levels: the copies out of one area have completed
+    // by the time it is written again (each level's host part waits on the stream).
+    const int64_t cap = m + 2;
+    const size_t tbl_bytes = sizeof(int64_t) * (2 * cap + 1) + sizeof(int) * 2 * cap;
+    PinBuf stage[2];
+    stage[0].alloc(tbl_bytes);
+    stage[1].alloc(tbl_bytes);
+    PinBuf h_nleft;
+    h_nleft.alloc(sizeof(int) * cap);
+    DevBuf d_tbl, d_key1, d_key2, d_nleft;
+    d_tbl.alloc(tbl_bytes);
+    d_key1.alloc(sizeof(uint64_t) * cap);
+    d_key2.alloc(sizeof(uint64_t) * cap);
+    d_nleft.alloc(sizeof(int) * cap);
     int level = 0;
     for (;;) {
         const int64_t nseg = (int64_t)starts.size() - 1;
-        active.assign(nseg, 0);
-        std::vector<int64_t> pivot(nseg, 0);
+        uint8_t* st = (uint8_t*)stage[level & 1].p;
+        int64_t* h_starts = (int64_t*)st;
+        int64_t* h_pivot = h_starts + nseg + 1;
+        int* h_active = (int*)(h_pivot + nseg);
+        int* h_degen = h_active + nseg;
+        int64_t* t_starts = (int64_t*)d_tbl.p;
+        int64_t* t_pivot = t_starts + nseg + 1;
+        int* t_active = (int*)(t_pivot + nseg);
+        int* t_degen = t_active + nseg;
+        const size_t head_bytes = (size_t)((uint8_t*)h_degen - st);
         bool any = false;
         for (int64_t i = 0; i < nseg; i++) {
             const int64_t sz = starts[i + 1] - starts[i];
+            h_active[i] = 0;
+            h_pivot[i] = 0;
             if (sz > N0) {
-                active[i] = 1;
+                h_active[i] = 1;
                 any = true;
                 const uint64_t r = splitmix64(x.prm.seed ^ splitmix64(((uint64_t)level << 40) ^ (uint64_t)starts[i]));
-                pivot[i] = starts[i] + (int64_t)(r % (uint64_t)sz);
+                h_pivot[i] = starts[i] + (int64_t)(r % (uint64_t)sz);
             }
         }
         if (!any) break;
-        HIPC(hipMemcpyAsync(d_starts.p, starts.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(d_active.p, active.data(), sizeof(int) * nseg, hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(d_pivot.p, pivot.data(), sizeof(int64_t) * nseg, hipMemcpyHostToDevice, s));
-        HIPC(hipMemsetAsync(d_key1.p, 0xff, sizeof(uint64_t) * nseg, s));
-        HIPC(hipMemsetAsync(d_key2.p, 0xff, sizeof(uint64_t) * nseg, s));
-        HIPC(hipMemsetAsync(d_nleft.p, 0, sizeof(int) * nseg, s));
+        std::memcpy(h_starts, starts.data(), sizeof(int64_t) * (nseg + 1));
+        HIPC(hipMemcpyAsync(d_tbl.p, st, head_bytes, hipMemcpyHostToDevice, s));
         ConeLevelArgs a{};
         a.unit = unit.f(); a.ld = ld; a.d = x.d; a.perm = perm_a.u32();
-        a.seg_start = d_starts.i64(); a.seg_active = d_active.i(); a.seg_pivot = d_pivot.i64();
+        a.seg_start = t_starts; a.seg_active = t_active; a.seg_pivot = t_pivot;
         a.nseg = nseg; a.m = m;
         a.key1 = (unsigned long long*)d_key1.p; a.key2 = (unsigned long long*)d_key2.p;
         a.dot_l = dot_l.f(); a.left = left.i(); a.nleft = d_nleft.i();
+        hipLaunchKernelGGL(k_cone_init, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s, a);
         const unsigned grid = (unsigned)((m + 255) / 256);
-        for (int ph = 0; ph < 3; ph++) {
-            hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
-            HIPC(hipGetLastError());
-        }
-        std::vector<int> nleft(nseg), degen(nseg, 0);
-        HIPC(hipMemcpyAsync(nleft.data(), d_nleft.p, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+        for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
+        HIPC(hipGetLastError());
+        int* nleft = (int*)h_nleft.p;
+        HIPC(hipMemcpyAsync(nleft, d_nleft.p, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
         std::vector<int64_t> next;
         next.reserve(2 * starts.size());
         for (int64_t i = 0; i < nseg; i++) {
             next.push_back(starts[i]);
-            if (!active[i]) continue;
+            h_degen[i] = 0;
+            if (!h_active[i]) continue;
             const int64_t sz = starts[i + 1] - starts[i];
             int64_t nl = nleft[i];
             if (nl == 0 || nl == sz) {
-                degen[i] = 1;
+                h_degen[i] = 1;
                 nl = sz / 2;
             }
             next.push_back(starts[i] + nl);
         }
         next.push_back(m);
-        HIPC(hipMemcpyAsync(d_degen.p, degen.data(), sizeof(int) * nseg, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(t_degen, h_degen, sizeof(int) * nseg, hipMemcpyHostToDevice, s));
         exclusive_scan_i32(left.i(), lscan.i(), m, scan_tmp.i(), s);
         hipLaunchKernelGGL(k_cone_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a,
-                           (const int*)lscan.i(), (const int*)d_degen.i(), perm_b.u32());
+                           (const int*)lscan.i(), (const int*)t_degen, perm_b.u32());
         HIPC(hipGetLastError());
         perm_a.swap(perm_b);
-        HIPC(hipStreamSynchronize(s));   // host vectors above are freed at scope end
         starts.swap(next);
         level++;
     }
+    HIPC(hipStreamSynchronize(s));   // the staging areas are released below
 
     // ---- leaves are the blocks; users move into leaf order
     x.nblocks = (int64_t)starts.size() - 1;

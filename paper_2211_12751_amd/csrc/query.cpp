@@ -12,6 +12,7 @@
 #include "common.h"
 #include "index.h"
 #include "internal.h"
+#include "mem.h"
 #include "query.h"
 
 namespace rk {
@@ -21,7 +22,7 @@ static const int kMaxSlots = 8;
 PinBuf::~PinBuf() { reset(); }
 void PinBuf::reset()
 {
-    if (p) (void)hipHostFree(p);
+    if (p) mem::host_free(p, bytes);
     p = nullptr;
     bytes = 0;
 }
@@ -29,11 +30,8 @@ void PinBuf::alloc(size_t b)
 {
     reset();
     if (b == 0) b = 16;
-    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        p = nullptr;
-        fail(RKMIPS_ENOMEM, "pinned host allocation failed");
-    }
+    p = mem::host_alloc(b, nullptr);
+    if (!p) fail(RKMIPS_ENOMEM, "pinned host allocation failed");
     bytes = b;
 }
 
@@ -348,6 +346,7 @@ rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const f
         r->flags = flags;
         r->queries = queries;
         r->qscales = query_scales;
+        mem::StreamScope scope(r->s);
         Workspace* w = x.take_ws();
         try {
             w->ensure(x, nq, std::max<int64_t>(1 << 16, 8 * nq * std::max(1, x.prm.k_max)), std::max<int64_t>(1 << 14, 4 * nq));
@@ -368,6 +367,7 @@ rkmips_status rkmips_result_wait(rkmips_result* r)
     if (!r) return RKMIPS_EINVAL;
     if (r->done) return r->status;
     rkmips_status st = qguard([&] {
+        mem::StreamScope scope(r->s);
         finish_batch(*r->idx, *r->ws, r->queries, r->qscales, r->nq, r->flags | r->idx->prm.flags, r->s, r->offsets,
                      r->ids, r->st);
     });
@@ -434,6 +434,7 @@ rkmips_status rkmips_saalsh_probe(rkmips_index* idx, const void* queries, const 
         }
         if (npairs == 0) return;
         hipStream_t s = (hipStream_t)stream;
+        mem::StreamScope scope(s);
         DevBuf qpad, qsc, qk, dpairs, phi, ans, scratch;
         qpad.alloc((size_t)nq * x.ld * elt_bytes(x.dtype));
         if (fp8) qsc.alloc(sizeof(float) * nq);

@@ -23,6 +23,7 @@
 
 #include "index.h"
 #include "internal.h"
+#include "mem.h"
 #include "query.h"
 
 namespace rk {
@@ -106,6 +107,7 @@ struct Server {
                 if (!s->has_work) return;
             }
             try {
+                mem::StreamScope scope(s->stream);
                 const int64_t B = (int64_t)s->members.size();
                 std::vector<int64_t> off;
                 std::vector<int32_t> ids;
@@ -131,6 +133,7 @@ struct Server {
 
     void dispatch(Slot* s, std::vector<int64_t>& batch)
     {
+        mem::StreamScope scope(s->stream);
         const int64_t B = (int64_t)batch.size();
         uint8_t* hq = (uint8_t*)s->hq.p;
         float* hqs = (float*)s->hqs.p;
@@ -270,7 +273,16 @@ extern "C" rkmips_status rkmips_serve_replay(rkmips_index* idx, const void* quer
             S.t0 = Clock::now();
             S.run();
             for (auto& s : S.slots)
-                if (s->stream) (void)hipStreamDestroy(s->stream);
+                if (s->stream) (void)hipStreamSynchronize(s->stream);
+            {
+                // the slots' buffers are idle now: back to the cache for any stream
+                mem::IdleScope idle;
+                for (auto& s : S.slots) {
+                    if (s->stream) (void)hipStreamDestroy(s->stream);
+                    s->stream = nullptr;
+                }
+                S.slots.clear();
+            }
             if (S.err != RKMIPS_OK) fail(S.err, S.errmsg);
             std::unique_ptr<rkmips_result> r(new rkmips_result());
             r->idx = &x;
