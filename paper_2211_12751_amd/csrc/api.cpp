@@ -107,25 +107,31 @@ static void choose_topk(Index& x)
     const int C = x.prm.k_max + x.prm.topk_slack;
     x.C = C;
     if (C > 224) fail(RKMIPS_EINVAL, "k_max + topk_slack too large (at most 224)");
-    x.P = x.n >= 2048 ? 256 : 0;
-    const int64_t main_items = x.n - 2 * x.P;
+    // Seed pass: a stratified sample of ns items gives each user a threshold that about
+    // target items of the whole set beat (the (2 TK_T)-th best of the sample scaled up),
+    // so the main pass appends about target candidates per user and rarely compacts.
+    const int64_t target = 4 * (int64_t)C;
+    int64_t ns = (2 * TK_T * x.n + target - 1) / target;
+    x.ns = (x.n >= 2048 && 4 * ns <= x.n) ? ns : 0;
+    int gpl = 2;
+    if (x.ns > 0)
+        while (gpl * 64 < 2 * target && gpl < 16) gpl *= 2;
+    while (gpl * 64 < C + 32) gpl *= 2;
+    if (gpl > 16) fail(RKMIPS_EINVAL, "internal: candidate buffer too large");
     const int upb = topk_users_per_block(x.dtype, x.ld);
     const int64_t tiles = (x.m + upb - 1) / upb;
-    const int seed = x.P > 0 ? 1 : 0;
-    int nmain = (int)std::max<int64_t>(1, (512 + tiles - 1) / tiles);
-    nmain = (int)std::min<int64_t>(nmain, std::max<int64_t>(1, main_items / 1024));
-    nmain = std::min(nmain, 4 - seed);   // the refine pass gathers at most 4 x 512 entries
-    int64_t seg_len = (main_items + nmain - 1) / nmain;
+    // item segments (grid.y) when there are few user tiles: about three rounds of
+    // two resident workgroups per compute unit keep the tail of the grid short
+    int nmain = (int)std::max<int64_t>(1, (1536 + tiles - 1) / tiles);
+    nmain = (int)std::min<int64_t>(nmain, std::max<int64_t>(1, x.n / 1024));
+    // the buffers stay within a fixed share of the device memory
+    while (gpl > 2 && gpl * 64 >= 2 * (C + 32) && (double)x.m * nmain * gpl * 64 * 8 > 24e9) gpl /= 2;
+    nmain = std::min(nmain, std::max(1, 2048 / (gpl * 64)));   // the refine gathers at most 2048
+    int64_t seg_len = (x.n + nmain - 1) / nmain;
     seg_len = std::max<int64_t>(64, (seg_len + 63) / 64 * 64);
-    nmain = (int)((main_items + seg_len - 1) / seg_len);
-    x.nseg_main = nmain;
-    x.nseg = nmain + seed;
+    nmain = (int)((x.n + seg_len - 1) / seg_len);
+    x.nseg = nmain;
     x.seg_len = seg_len;
-    // buffer capacity: large buffers make the wave-wide compactions rare
-    int gpl = 4;
-    while (gpl > 2 && (double)x.m * x.nseg * gpl * 64 * 8 > 24e9) gpl /= 2;
-    while (gpl * 64 < C + 32) gpl *= 2;
-    if (gpl > 8) fail(RKMIPS_ENOMEM, "candidate buffers exceed the memory budget");
     x.G = gpl * 64;
 }
 
@@ -133,7 +139,7 @@ static void build_lambda(Index& x, hipStream_t s)
 {
     choose_topk(x);
     const int64_t m = x.m;
-    DevBuf buf, cnt, tau, fail_list, fail_count, errbits;
+    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits;
     buf.alloc(sizeof(uint2) * (size_t)m * x.nseg * x.G);
     cnt.alloc(sizeof(int) * (size_t)m * x.nseg);
     tau.alloc(sizeof(float) * (size_t)m * x.nseg);
@@ -148,21 +154,21 @@ static void build_lambda(Index& x, hipStream_t s)
     TopkArgs ta{};
     ta.items = x.items.p; ta.item_scales = x.item_scales.f(); ta.n = x.n;
     ta.users = x.users.p; ta.user_scales = x.user_scales.f(); ta.m = m;
-    ta.d = x.d; ta.ld = x.ld; ta.P = x.P; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
+    ta.d = x.d; ta.ld = x.ld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
     ta.buf = (uint2*)buf.p; ta.cnt = (int*)cnt.p; ta.tau = (float*)tau.p;
     Events ev(3);
     HIPC(hipEventRecord(ev.ev[0], s));
-    if (x.P > 0) {   // seeding segment: all of it enters, then the C best remain
+    if (x.ns > 0) {   // per-user threshold estimates from the item sample
+        theta.alloc(sizeof(float) * (size_t)m);
         TopkArgs a0 = ta;
-        a0.v0 = 0; a0.v1 = 2 * x.P; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = 2 * x.P;
-        a0.theta_init = nullptr; a0.theta_stride = 0;
-        launch_topk(x.dtype, a0, s);
+        a0.ns = x.ns; a0.v0 = 0; a0.v1 = x.ns; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = x.ns;
+        a0.theta_out = theta.f();
+        launch_topk_seed(x.dtype, a0, s);
     }
     TopkArgs a1 = ta;
-    a1.v0 = 2 * x.P; a1.v1 = x.n; a1.nseg = x.nseg_main; a1.seg_base = x.P > 0 ? 1 : 0;
-    a1.seg_len = x.seg_len;
-    a1.theta_init = x.P > 0 ? (const float*)tau.p : nullptr;   // tau of the seeding segment
-    a1.theta_stride = x.nseg;
+    a1.v0 = 0; a1.v1 = x.n; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
+    a1.theta_init = x.ns > 0 ? theta.f() : nullptr;
+    a1.theta_stride = 1;
     launch_topk(x.dtype, a1, s);
     HIPC(hipEventRecord(ev.ev[1], s));
 
@@ -375,7 +381,7 @@ rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
         const Index& x = *(const Index*)idx;
         std::memset(o, 0, sizeof *o);
         o->n = x.n; o->m = x.m; o->d = x.d; o->dtype = x.dtype; o->k_max = x.prm.k_max;
-        o->cand_per_user = x.C * x.nseg; o->num_hash = x.prm.num_hash; o->leaf_size = x.prm.leaf_size;
+        o->cand_per_user = x.G * x.nseg; o->num_hash = x.prm.num_hash; o->leaf_size = x.prm.leaf_size;
         o->num_partitions = x.t; o->num_blocks = x.nblocks; o->cert_failures = x.cert_failures;
         o->max_rel_err_raw = x.max_rel_err_raw; o->max_rel_err_lambda32 = x.max_rel_err_l32;
         o->ms_norms = x.ms_norms; o->ms_lambda = x.ms_lambda; o->ms_refine = x.ms_refine;
@@ -442,7 +448,7 @@ rkmips_status rkmips_get_candidates(const rkmips_index* idx, int32_t* ids, float
         HIPC(hipMemcpy(tt.data(), x.cand_tau.p, sizeof(float) * tt.size(), hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(iorder.data(), x.item_order.p, sizeof(uint32_t) * x.n, hipMemcpyDeviceToHost));
-        const int CP = x.C * x.nseg;
+        const int CP = x.G * x.nseg;
         for (int64_t u = 0; u < x.m; u++) {
             const int64_t ou = perm[u];
             int k = 0;

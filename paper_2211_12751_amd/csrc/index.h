@@ -72,8 +72,8 @@ struct Index {
 
     // exact lambda table (leaf order, k-major)
     DevBuf lam64, lam32;
-    int C = 0, G = 0, nseg = 1, nseg_main = 1;
-    int64_t P = 0;
+    int C = 0, G = 0, nseg = 1;
+    int64_t ns = 0;              // item sample of the threshold seed pass (0: none)
     int64_t seg_len = 0;
     DevBuf cand, cand_cnt, cand_tau;  // raw candidates of the lambda pass
     int64_t cert_failures = 0;

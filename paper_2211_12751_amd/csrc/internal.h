@@ -54,7 +54,7 @@ struct TopkArgs {
     const float* user_scales;
     int64_t m;
     int d, ld;
-    int64_t P;              // seeding segment: the P largest- and P smallest-norm items
+    int64_t ns;             // seed pass: size of the stratified item sample
     int64_t v0, v1;         // virtual item range of this launch
     int nseg;               // segments of this launch (grid.y)
     int seg_base;           // buffer segment of this launch's first segment
@@ -67,8 +67,12 @@ struct TopkArgs {
     uint2* buf;             // [m x nseg_total x G] {ord(score), sorted item position}
     int* cnt;               // [m x nseg_total]
     float* tau;             // [m x nseg_total]
+    float* theta_out;       // seed pass: [m] threshold estimates
 };
+enum { TK_MAIN = 0, TK_SEED = 1 };
+constexpr int TK_T = 8;     // sample scores kept per lane by the seed pass
 void launch_topk(int dtype, const TopkArgs& a, hipStream_t s);
+void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s);
 int topk_users_per_block(int dtype, int ld);
 
 struct RefineArgs {

@@ -2,18 +2,23 @@
 // product of u over all items (Definition 1; the lower-bound array of Alg. 4 taken
 // over all of P instead of the top-norm subset P').
 //
-// Pass 1 (k_topk): fused U.P^T on the matrix cores with a streaming per-user top-C
-//   (C = k_max + slack).  A workgroup keeps 128-256 users' operand fragments in
-//   registers and streams item tiles (items in descending norm order, so the first
-//   tile already holds the paper's P' and sets a high threshold early) through LDS.
-//   Every MFMA output lane owns one user column; a score enters the user's candidate
-//   buffer only if it beats the user's running threshold (register compare, ballot
-//   gated).  When a buffer fills, the wave compacts it to its C best entries with a
-//   wave-cooperative radix select and raises the threshold.  The threshold tau that
-//   remains bounds every item left out.
+// Pass 0 (k_topk, seed mode): on a stratified sample of the items, the matrix cores
+//   score every user and each lane keeps its few largest scores in registers; their
+//   order statistic estimates a per-user threshold that a fixed multiple of C items
+//   of the whole set exceed.
+// Pass 1 (k_topk, main mode): fused U.P^T on the matrix cores with a streaming per-user
+//   top-C (C = k_max + slack).  A workgroup keeps 128-256 users' operand fragments in
+//   registers and streams 64-item tiles of the norm-sorted items through LDS.  Every
+//   MFMA output lane owns one user column; a score enters the user's candidate buffer
+//   only if it beats the user's register threshold (starting at the seed estimate).
+//   When a buffer fills, the wave compacts it to its C best entries with a wave radix
+//   select and raises the threshold to the running C-th best.  The final threshold tau
+//   bounds every item left out.
 // Pass 2 (k_refine): canonical FP64 rescoring of the candidates, ranking, and a
 //   certificate: tau + eps(u) <= lambda64^(k_max) proves no left-out item can enter
-//   the top k_max.  Users that fail get a full-row FP64 rescoring (k_fallback).
+//   the top k_max (a seed estimate that was too high leaves fewer than k_max
+//   candidates above tau and fails it).  Users that fail get a full-row FP64
+//   rescoring (k_fallback).
 #include "common.h"
 #include "internal.h"
 
@@ -117,15 +122,6 @@ __device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, in
 }
 
 // ------------------------------------------------------------------ fused GEMM + top-k
-// Items are streamed in a virtual order over the norm-sorted array: positions
-// [0, 2P) are the P largest-norm and the P smallest-norm items (a seeding segment
-// that is processed first, so every user starts the main pass with a threshold that
-// suits its direction), then the remaining middle range.
-__device__ __forceinline__ int64_t vmap(int64_t i, int64_t n, int64_t P)
-{
-    return i < P ? i : (i < 2 * P ? n - 2 * P + i : i - P);
-}
-
 // user column blocks per wave: FP32 keeps one (register budget for several waves per
 // SIMD, so one wave's top-k epilogue hides behind another's matrix-core work); the
 // narrow types keep two so each LDS fragment feeds two MFMAs
@@ -193,7 +189,27 @@ __device__ __forceinline__ uint32_t select_user(uint2* region, int c, int C, int
     return T;
 }
 
-template <int DT, int DPT, int UBW, int GPL>
+// Item at virtual position v of a launch: the norm-sorted array itself (main pass), or
+// the stratified sample of `ns` items, one from the middle of each of ns equal slices of
+// the norm-sorted order (seed pass).
+template <int MODE>
+__device__ __forceinline__ int64_t item_at(int64_t v, int64_t n, int64_t ns)
+{
+    if constexpr (MODE == TK_SEED) return ((2 * v + 1) * n) / (2 * ns);
+    else return v;
+}
+
+// Two modes over the same matrix-core pipeline.
+//  TK_MAIN: streaming top-C.  A score enters the user's candidate buffer only if it
+//    beats the user's register threshold (seeded per user); a full buffer is compacted to
+//    its C best by a wave radix select, which also raises the threshold to the running
+//    C-th best.  The final threshold bounds every item left out.
+//  TK_SEED: per user, an estimate of the score that about target items of the whole set
+//    exceed, from a stratified item sample: each lane keeps the TK_T largest of its half
+//    of the sample rows in registers, and the user's estimate is the smaller of its two
+//    lanes' TK_T-th largest (at least 2*TK_T sample items reach it).  The estimate is only
+//    a starting point: the main pass and the refine certificate never rely on it.
+template <int DT, int DPT, int UBW, int GPL, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT < 256) ? 2 : 1, 8))) void k_topk(TopkArgs a)
 {
     constexpr int EB = Elt<DT>::bytes;
@@ -203,10 +219,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     constexpr int CHUNKS = TK_IT * (ROWB / 16);   // 16-byte chunks per tile
     constexpr int PF = (CHUNKS + 255) / 256;      // chunks per thread
     constexpr bool PREFETCH = PF <= 4;
+    constexpr int SGPL = MODE == TK_MAIN ? GPL : 1;
     __shared__ __attribute__((aligned(16))) uint8_t tile[TK_IT * LROW];
     __shared__ float tscale[TK_IT];
-    __shared__ int hist_all[TK_WAVES][256];
-    __shared__ uint2 stage_all[TK_WAVES][GPL * 64];
+    __shared__ int hist_all[TK_WAVES][MODE == TK_MAIN ? 256 : 1];
+    __shared__ uint2 stage_all[TK_WAVES][SGPL * 64];
 
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
@@ -223,12 +240,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     // ---- resident user fragments (the B operand), one user column per lane
     i32x4 bfrag[UBW][KSTEPS];
     float theta[UBW], su[UBW];
-    // Threshold raising without compaction: pc counts appended scores above `probe`
-    // since it was set; once C of them exist, no item at or below `probe` can be among
-    // the user's C best, so theta moves up to probe (which then bisects towards vmax,
-    // the largest appended score, in orderable-key space).
-    float probe[UBW], vmax[UBW];
-    int pc[UBW];
+    float top[UBW][MODE == TK_SEED ? TK_T : 1];
     int cnt[UBW];
     int64_t ug[UBW];
     uint2* region[UBW];
@@ -243,14 +255,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
             bfrag[cb][t] = ok ? *(const i32x4*)(row + t * 32 + h * 16) : z;
         }
         float th0 = -__builtin_inff();
-        if (ok && a.theta_init) th0 = a.theta_init[ug[cb] * a.theta_stride];
+        if (MODE == TK_MAIN && ok && a.theta_init) th0 = a.theta_init[ug[cb] * a.theta_stride];
         theta[cb] = ok ? th0 : __builtin_inff();   // +inf: nothing enters
-        probe[cb] = __builtin_inff();
-        vmax[cb] = -__builtin_inff();
-        pc[cb] = 0;
         su[cb] = (DT == DT_FP8 && ok) ? a.user_scales[ug[cb]] : 1.0f;
         cnt[cb] = 0;
         region[cb] = a.buf + ((ok ? ug[cb] : 0) * a.nseg_total + seg) * (int64_t)a.G;
+#pragma unroll
+        for (int i = 0; i < (MODE == TK_SEED ? TK_T : 1); i++) top[cb][i] = -__builtin_inff();
     }
 
     auto load_chunk = [&](int64_t t0, int c) -> i32x4 {
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         const int64_t v = t0 + r;
         i32x4 val = {0, 0, 0, 0};
         if (c < CHUNKS && v < seg1)
-            val = *(const i32x4*)((const uint8_t*)a.items + vmap(v, a.n, a.P) * ROWB + c16 * 16);
+            val = *(const i32x4*)((const uint8_t*)a.items + item_at<MODE>(v, a.n, a.ns) * ROWB + c16 * 16);
         return val;
     };
     i32x4 pf[PREFETCH ? PF : 1];
@@ -282,16 +293,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         }
         if (DT == DT_FP8 && threadIdx.x < TK_IT) {
             const int64_t v = t0 + threadIdx.x;
-            tscale[threadIdx.x] = v < seg1 ? a.item_scales[vmap(v, a.n, a.P)] : 0.f;
+            tscale[threadIdx.x] = v < seg1 ? a.item_scales[item_at<MODE>(v, a.n, a.ns)] : 0.f;
         }
         __syncthreads();
-        const uint32_t pbase = (uint32_t)vmap(t0, a.n, a.P);
         if constexpr (PREFETCH) {
             if (t0 + TK_IT < seg1) {
 #pragma unroll
                 for (int e = 0; e < PF; e++) pf[e] = load_chunk(t0 + TK_IT, threadIdx.x + 256 * e);
             }
         }
+        const bool tail = t0 + TK_IT > seg1;   // uniform: rows past the end are not items
 
 #pragma unroll
         for (int rb = 0; rb < TK_IT / 32; rb++) {
@@ -334,117 +345,121 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                 }
             }
 
-            // ---- epilogue: threshold filter, buffer append, compaction when full
 #pragma unroll
             for (int cb = 0; cb < UBW; cb++) {
                 float v[16];
-                uint32_t pm = 0u;
-                int cgt = 0;
-                float lmax = -__builtin_inff();
 #pragma unroll
                 for (int r = 0; r < 16; r++) {
                     const int row = rb * 32 + mfma32_row(r, l);
                     float x = acc[cb][r];
                     if constexpr (DT == DT_FP8) x = (su[cb] * tscale[row]) * x;
+                    if (tail && t0 + row >= seg1) x = -__builtin_inff();
                     v[r] = x;
-                    const bool pass = t0 + row < seg1 && x > theta[cb];
-                    if (pass) pm |= 1u << r;
-                    cgt += (pass && x > probe[cb]) ? 1 : 0;
-                    lmax = pass ? fmaxf(lmax, x) : lmax;
                 }
-                cgt += __shfl_xor(cgt, 32);
-                lmax = fmaxf(lmax, __shfl_xor(lmax, 32));
-                // every cross-lane read happens with the whole wave active: a permute
-                // from an inactive lane returns 0
-                int np = __popc(pm);
-                int npo = __shfl_xor(np, 32);
-                int tot = np + npo;
-                uint64_t need = ballot64(cnt[cb] + tot > a.G) & 0xffffffffull;
-                if (need) {
-                    while (need) {
-                        const int ul = __builtin_ctzll(need);
-                        need &= need - 1;
-                        const int c = __shfl(cnt[cb], ul);
-                        const int64_t ugl = __shfl(ug[cb], ul);
-                        uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
-                        const uint32_t T = select_user(rg, c, a.C, hist, stage);
-                        if ((l & 31) == ul) {
-                            theta[cb] = ord_f32(T);
-                            cnt[cb] = a.C;
-                            pc[cb] = 0;
-                            probe[cb] = __builtin_inff();
-                        }
-                    }
-                    pm = 0u;
-                    cgt = 0;
+                if constexpr (MODE == TK_SEED) {
+                    // keep the TK_T largest per lane: one compare-exchange pass per score
 #pragma unroll
                     for (int r = 0; r < 16; r++) {
-                        const int row = rb * 32 + mfma32_row(r, l);
-                        const bool pass = t0 + row < seg1 && v[r] > theta[cb];
-                        if (pass) pm |= 1u << r;
-                        cgt += (pass && v[r] > probe[cb]) ? 1 : 0;
+                        float x = v[r];
+#pragma unroll
+                        for (int i = 0; i < TK_T; i++) {
+                            const float hi = fmaxf(top[cb][i], x);
+                            x = fminf(top[cb][i], x);
+                            top[cb][i] = hi;
+                        }
                     }
-                    cgt += __shfl_xor(cgt, 32);
-                    np = __popc(pm);
-                    npo = __shfl_xor(np, 32);
-                    tot = np + npo;
-                }
-                if (tot) {
-                    int pos = cnt[cb] + (h ? npo : 0);
+                } else {
+                    // ---- threshold filter, buffer append, compaction when full
+                    uint32_t pm = 0u;
 #pragma unroll
                     for (int r = 0; r < 16; r++)
-                        if (pm & (1u << r)) {
-                            const int row = rb * 32 + mfma32_row(r, l);
-                            region[cb][pos++] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)row);
+                        if (v[r] > theta[cb]) pm |= 1u << r;
+                    // every cross-lane read happens with the whole wave active: a permute
+                    // from an inactive lane returns 0
+                    int np = __popc(pm);
+                    int npo = __shfl_xor(np, 32);
+                    int tot = np + npo;
+                    uint64_t need = ballot64(cnt[cb] + tot > a.G) & 0xffffffffull;
+                    if (need) {
+                        while (need) {
+                            const int ul = __builtin_ctzll(need);
+                            need &= need - 1;
+                            const int c = __shfl(cnt[cb], ul);
+                            const int64_t ugl = __shfl(ug[cb], ul);
+                            uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
+                            const uint32_t T = select_user(rg, c, a.C, hist, stage);
+                            if ((l & 31) == ul) {
+                                theta[cb] = ord_f32(T);
+                                cnt[cb] = a.C;
+                            }
                         }
-                    cnt[cb] += tot;
-                    vmax[cb] = fmaxf(vmax[cb], lmax);
-                    pc[cb] += cgt;
-                    if (pc[cb] >= a.C) {
-                        theta[cb] = probe[cb];
-                        pc[cb] = 0;
-                        probe[cb] = __builtin_inff();
+                        pm = 0u;
+#pragma unroll
+                        for (int r = 0; r < 16; r++)
+                            if (v[r] > theta[cb]) pm |= 1u << r;
+                        np = __popc(pm);
+                        npo = __shfl_xor(np, 32);
+                        tot = np + npo;
                     }
-                    if (probe[cb] == __builtin_inff() && vmax[cb] > theta[cb]) {
-                        const uint32_t lo = f32_ord(theta[cb]), hi = f32_ord(vmax[cb]);
-                        probe[cb] = ord_f32(lo + ((hi - lo) >> 1));
+                    if (tot) {
+                        const uint32_t pbase = (uint32_t)(t0 + rb * 32);
+                        int pos = cnt[cb] + (h ? npo : 0);
+#pragma unroll
+                        for (int r = 0; r < 16; r++)
+                            if (pm & (1u << r))
+                                region[cb][pos++] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)mfma32_row(r, l));
+                        cnt[cb] += tot;
                     }
                 }
             }
         }
     }
 
-    // ---- outputs: the buffer may hold up to G entries; the refine pass selects
+    if constexpr (MODE == TK_SEED) {
 #pragma unroll
-    for (int cb = 0; cb < UBW; cb++)
-        if (l < 32 && ug[cb] < a.m) {
-            a.cnt[ug[cb] * a.nseg_total + seg] = cnt[cb];
-            a.tau[ug[cb] * a.nseg_total + seg] = theta[cb];
+        for (int cb = 0; cb < UBW; cb++) {
+            const float mine = top[cb][TK_T - 1];
+            const float other = __shfl_xor(mine, 32);
+            if (l < 32 && ug[cb] < a.m) a.theta_out[ug[cb]] = fminf(mine, other);
         }
+    } else {
+        // ---- outputs: the buffer may hold up to G entries; the refine pass selects
+#pragma unroll
+        for (int cb = 0; cb < UBW; cb++)
+            if (l < 32 && ug[cb] < a.m) {
+                a.cnt[ug[cb] * a.nseg_total + seg] = cnt[cb];
+                a.tau[ug[cb] * a.nseg_total + seg] = theta[cb];
+            }
+    }
 }
 
-template <int DT, int DPT>
+template <int DT, int DPT, int MODE>
 static void topk_dispatch_g(const TopkArgs& a, hipStream_t s)
 {
     constexpr int UBW = topk_ubw(DT, DPT);
     dim3 grid((unsigned)((a.m + TK_WAVES * UBW * 32 - 1) / (TK_WAVES * UBW * 32)), (unsigned)a.nseg);
-    const int gpl = a.G / 64;
-    if (gpl == 2) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 2>), grid, dim3(256), 0, s, a);
-    else if (gpl == 4) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 4>), grid, dim3(256), 0, s, a);
-    else if (gpl == 8) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 8>), grid, dim3(256), 0, s, a);
-    else fail(RKMIPS_EINVAL, "internal: unsupported candidate buffer size");
+    if constexpr (MODE == TK_SEED) {
+        hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 1, TK_SEED>), grid, dim3(256), 0, s, a);
+    } else {
+        const int gpl = a.G / 64;
+        if (gpl == 2) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 2, TK_MAIN>), grid, dim3(256), 0, s, a);
+        else if (gpl == 4) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 4, TK_MAIN>), grid, dim3(256), 0, s, a);
+        else if (gpl == 8) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 8, TK_MAIN>), grid, dim3(256), 0, s, a);
+        else if (gpl == 16) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 16, TK_MAIN>), grid, dim3(256), 0, s, a);
+        else fail(RKMIPS_EINVAL, "internal: unsupported candidate buffer size");
+    }
 }
 
 int topk_users_per_block(int dtype, int ld) { return TK_WAVES * topk_ubw(dtype, ld) * 32; }
 
-template <int DT>
+template <int DT, int MODE>
 static void topk_dispatch(const TopkArgs& a, hipStream_t s)
 {
     switch (a.ld) {
-    case 32: topk_dispatch_g<DT, 32>(a, s); break;
-    case 64: topk_dispatch_g<DT, 64>(a, s); break;
-    case 128: topk_dispatch_g<DT, 128>(a, s); break;
-    case 256: topk_dispatch_g<DT, 256>(a, s); break;
+    case 32: topk_dispatch_g<DT, 32, MODE>(a, s); break;
+    case 64: topk_dispatch_g<DT, 64, MODE>(a, s); break;
+    case 128: topk_dispatch_g<DT, 128, MODE>(a, s); break;
+    case 256: topk_dispatch_g<DT, 256, MODE>(a, s); break;
     default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
     }
 }
@@ -452,9 +467,19 @@ static void topk_dispatch(const TopkArgs& a, hipStream_t s)
 void launch_topk(int dtype, const TopkArgs& a, hipStream_t s)
 {
     if (a.m <= 0 || a.v1 <= a.v0) return;
-    if (dtype == DT_F32) topk_dispatch<DT_F32>(a, s);
-    else if (dtype == DT_BF16) topk_dispatch<DT_BF16>(a, s);
-    else topk_dispatch<DT_FP8>(a, s);
+    if (dtype == DT_F32) topk_dispatch<DT_F32, TK_MAIN>(a, s);
+    else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_MAIN>(a, s);
+    else topk_dispatch<DT_FP8, TK_MAIN>(a, s);
+    HIPC(hipGetLastError());
+}
+
+void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s)
+{
+    if (a.m <= 0 || a.v1 <= a.v0) return;
+    if (a.v1 - a.v0 > a.ns || a.ns > a.n || !a.theta_out) fail(RKMIPS_EINVAL, "internal: bad seed sample");
+    if (dtype == DT_F32) topk_dispatch<DT_F32, TK_SEED>(a, s);
+    else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_SEED>(a, s);
+    else topk_dispatch<DT_FP8, TK_SEED>(a, s);
     HIPC(hipGetLastError());
 }
 
