@@ -186,6 +186,7 @@ struct QueryArgs {
     const float* lam32; const double* lam64; int k_max;
     const void* queries; const float* query_scales; int64_t nq;   // padded copy [nq x ld]
     const float* qnorm;                              // [nq]
+    const float* cphi;                               // [nblocks x nq] cos of the query-centre angle
     const int* qslot;                                // [nq] slot of the query's k
     const uint32_t* qorig;                           // [nq] k-sorted position -> caller index
     const int* qk;                                   // [nq] k of each (k-sorted) query
@@ -202,6 +203,7 @@ struct QueryArgs {
 };
 void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, int ld,
                   float* qnorm, int* bad, hipStream_t s);
+void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s);
 void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
 void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s);
 void launch_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets,

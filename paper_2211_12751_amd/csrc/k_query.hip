@@ -8,9 +8,11 @@
 //   * <u, q> on the matrix cores for the pairs that survive, compared with lambda_u^(k)
 //     (Alg. 5, inner-product test): a margin beyond the derived error bound decides in
 //     the fast arithmetic, anything closer is queued for the canonical FP64 recheck.
-// Users stay resident in registers for the whole query chunk; a 32x32 output block
-// whose pairs are all pruned skips its matrix-core work.  Answers are appended with one
-// atomic per wave and output block (ballot/prefix-sum compaction).
+// Users stay resident in registers for the whole query chunk, with the blocks' cone
+// data and lower bounds in LDS; the next query tile is fetched into registers while
+// the current one is scored.  A 32x32 output block whose pairs are all pruned skips
+// its matrix-core work.  Answers are compacted with wave prefix sums and reserved with
+// one LDS atomic per wave and one global atomic per workgroup and query tile.
 //
 // Soundness of the bounds under rounding: phi comes from an FP32 dot product whose cosine
 // is known within +-e; the bound functions are 1-Lipschitz in the angle, so the angle
@@ -27,41 +29,54 @@ static constexpr int VF_WAVES = 4;
 static constexpr int VF_MAXB = 32;     // blocks with angle data per workgroup
 static constexpr int VF_MAXSLOT = 8;   // distinct k values per launch
 
-template <int DT>
-__device__ __forceinline__ float row_elem(const uint8_t* row, int i)
-{
-    if constexpr (DT == DT_F32) return ((const float*)row)[i];
-    else if constexpr (DT == DT_BF16) return bf16_to_f32(((const uint16_t*)row)[i]);
-    else return e4m3_to_f32(row[i]);
-}
-
 template <int DT, int DPT, int UBW>
-__global__ __launch_bounds__(256) void k_verify(QueryArgs a, int64_t q_begin, int64_t q_end)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT >= 256) ? 1 : 3, 8))) void k_verify(QueryArgs a, int64_t q_begin, int64_t q_end)
 {
     constexpr int EB = Elt<DT>::bytes;
     constexpr int ROWB = DPT * EB;
     constexpr int LROW = ROWB + 16;
     constexpr int KSTEPS = ROWB / 32;
     constexpr int UT = VF_WAVES * UBW * 32;
+    constexpr int CH = 32 * (ROWB / 16);      // 16-byte chunks of one query tile
+    constexpr int PF = (CH + 255) / 256;
+    constexpr bool PREFETCH = PF <= 4;
     __shared__ __attribute__((aligned(16))) uint8_t qt[32 * LROW];
     __shared__ float qn_s[32], qs_s[32];
-    __shared__ int qslot_s[32], qk_s[32];
+    __shared__ int qslot_s[32];
     __shared__ f32x4 phi_s[VF_MAXB][32];
     __shared__ float lam_s[VF_MAXSLOT][UT];
+    __shared__ float bcw[VF_MAXB], bsw[VF_MAXB];
+    __shared__ int bok[VF_MAXB];
+    __shared__ float blb[VF_MAXSLOT][VF_MAXB];
+    __shared__ unsigned int cnt_s[2];
+    __shared__ unsigned long long base_s[2];
 
     const int l = lane_id(), w = threadIdx.x >> 6, h = l >> 5;
     const int64_t u0 = (int64_t)blockIdx.x * UT;
     const int64_t ulast = (u0 + UT - 1 < a.m - 1) ? u0 + UT - 1 : a.m - 1;
     const int bfirst = a.user_block[u0];
     const int nb = a.user_block[ulast] - bfirst + 1;
+    const int nbb = nb < VF_MAXB ? nb : VF_MAXB;
     const bool use_bounds = !(a.flags & RKMIPS_FLAG_NO_BOUNDS);
     const bool use_vec = use_bounds && !(a.flags & RKMIPS_FLAG_NO_VECTOR_BOUND);
     const bool force = (a.flags & RKMIPS_FLAG_FORCE_RECHECK) != 0;
 
+    // ---- per-workgroup tables: lambda rows of the k slots, the blocks' cone data and
+    // lower bounds (the user tile and its blocks are fixed for the whole launch)
     for (int e = threadIdx.x; e < a.nslots * UT; e += 256) {
         const int sl = e / UT, ul = e % UT;
         const int64_t u = u0 + ul;
         lam_s[sl][ul] = u < a.m ? a.lam32[(int64_t)(a.slot_k[sl] - 1) * a.m + u] : 0.f;
+    }
+    for (int b = threadIdx.x; b < nbb; b += 256) {
+        const int bg = bfirst + b;
+        bok[b] = use_bounds && a.block_ok[bg];
+        bcw[b] = a.cos_w[bg];
+        bsw[b] = a.sin_w[bg];
+    }
+    for (int e = threadIdx.x; e < a.nslots * nbb; e += 256) {
+        const int sl = e / nbb, b = e % nbb;
+        blb[sl][b] = a.block_lb[(int64_t)(a.slot_k[sl] - 1) * a.nblocks + bfirst + b];
     }
 
     i32x4 bfrag[UBW][KSTEPS];
@@ -89,50 +104,72 @@ __global__ __launch_bounds__(256) void k_verify(QueryArgs a, int64_t q_begin, in
         ouid[cb] = a.perm[uu];
     }
 
-    unsigned long long n_node = 0, n_vec = 0, n_scored = 0, n_amb = 0;
-
-    for (int64_t qb = q_begin; qb < q_end; qb += 32) {
-        __syncthreads();
-        for (int c = threadIdx.x; c < 32 * (ROWB / 16); c += 256) {
-            const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
-            const int64_t q = qb + r;
-            i32x4 v = {0, 0, 0, 0};
-            if (q < q_end) v = *(const i32x4*)((const uint8_t*)a.queries + q * ROWB + c16 * 16);
-            *(i32x4*)(qt + r * LROW + c16 * 16) = v;
+    // ---- query tiles: registers hold the next tile while the current one is scored
+    auto load_chunk = [&](int64_t qb, int c) -> i32x4 {
+        const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
+        const int64_t q = qb + r;
+        i32x4 v = {0, 0, 0, 0};
+        if (c < CH && q < q_end) v = *(const i32x4*)((const uint8_t*)a.queries + q * ROWB + c16 * 16);
+        return v;
+    };
+    i32x4 pf[PREFETCH ? PF : 1];
+    float pqn = 0.f, pqs = 1.f;
+    int pqsl = 0;
+    auto prefetch = [&](int64_t qb) {
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int e = 0; e < PF; e++) pf[e] = load_chunk(qb, threadIdx.x + 256 * e);
         }
         if (threadIdx.x < 32) {
             const int64_t q = qb + threadIdx.x;
             const bool ok = q < q_end;
-            qn_s[threadIdx.x] = ok ? a.qnorm[q] : 0.f;
-            qs_s[threadIdx.x] = (ok && DT == DT_FP8) ? a.query_scales[q] : 1.f;
-            const int sl = ok ? a.qslot[q] : 0;
-            qslot_s[threadIdx.x] = sl;
-            qk_s[threadIdx.x] = ok ? a.slot_k[sl] : 0;
+            pqn = ok ? a.qnorm[q] : 0.f;
+            pqs = (ok && DT == DT_FP8) ? a.query_scales[q] : 1.f;
+            pqsl = ok ? a.qslot[q] : 0;
+        }
+    };
+    prefetch(q_begin);
+
+    unsigned long long n_node = 0, n_vec = 0, n_scored = 0, n_amb = 0;
+
+    for (int64_t qb = q_begin; qb < q_end; qb += 32) {
+        __syncthreads();
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int e = 0; e < PF; e++) {
+                const int c = threadIdx.x + 256 * e;
+                if (c < CH) *(i32x4*)(qt + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = pf[e];
+            }
+        } else {
+            for (int c = threadIdx.x; c < CH; c += 256)
+                *(i32x4*)(qt + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = load_chunk(qb, c);
+        }
+        if (threadIdx.x < 32) {
+            qn_s[threadIdx.x] = pqn;
+            qs_s[threadIdx.x] = pqs;
+            qslot_s[threadIdx.x] = pqsl;
+        }
+        if (threadIdx.x == 0) {
+            cnt_s[0] = 0u;
+            cnt_s[1] = 0u;
         }
         __syncthreads();
-        // node-level data per (block, query)
-        const int nbb = nb < VF_MAXB ? nb : VF_MAXB;
+        if (qb + 32 < q_end) prefetch(qb + 32);
+
+        // node-level data per (block, query): cos(phi) from the pre-pass, the rest here
         for (int e = threadIdx.x; e < nbb * 32; e += 256) {
             const int b = e >> 5, qi = e & 31;
-            const int bg = bfirst + b;
             f32x4 out = {1.f, 0.f, 0.f, 2.f};     // w = 2: no angle data, never prune
-            if (use_bounds && a.block_ok[bg] && qb + qi < q_end && qn_s[qi] > 0.f) {
-                const float* cen = a.center + (int64_t)bg * a.ld;
-                const uint8_t* qrow = qt + qi * LROW;
-                float dot = 0.f;
-                for (int i = 0; i < a.d; i++) dot += row_elem<DT>(qrow, i) * cen[i];
-                if constexpr (DT == DT_FP8) dot *= qs_s[qi];
-                float c = dot / qn_s[qi];
-                c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
+            if (bok[b] && qb + qi < q_end && qn_s[qi] > 0.f) {
+                const float c = a.cphi[(int64_t)(bfirst + b) * a.nq + qb + qi];
                 const float s = sqrtf(fmaxf(0.f, 1.f - c * c));
                 const float ce = fabsf(c) + a.err_phi;
                 const float rem = 1.f - ce * ce;
                 const float dphi = rem > 4.f * a.err_phi ? a.err_phi / sqrtf(rem) : 2.f * sqrtf(2.f * a.err_phi) + a.err_phi;
-                const float cw = a.cos_w[bg], sw = a.sin_w[bg];
+                const float cw = bcw[b], sw = bsw[b];
                 const float fnode = c >= cw ? 1.f : c * cw + s * sw;
                 const float ub = qn_s[qi] * (fnode + dphi + a.bound_slack);
-                const float lb = a.block_lb[(int64_t)(qk_s[qi] - 1) * a.nblocks + bg];
-                out = f32x4{c, s, dphi, ub < lb ? 1.f : 0.f};
+                out = f32x4{c, s, dphi, ub < blb[qslot_s[qi]][b] ? 1.f : 0.f};
             }
             phi_s[b][qi] = out;
         }
@@ -160,85 +197,107 @@ __global__ __launch_bounds__(256) void k_verify(QueryArgs a, int64_t q_begin, in
             live[cb] = lm;
             any |= lm != 0u;
         }
-        if (!ballot64(any)) continue;
 
-        f32x16 acc[UBW];
+        uint32_t yes[UBW], amb[UBW];
 #pragma unroll
-        for (int cb = 0; cb < UBW; cb++)
+        for (int cb = 0; cb < UBW; cb++) {
+            yes[cb] = 0u;
+            amb[cb] = 0u;
+        }
+        if (ballot64(any)) {
+            f32x16 acc[UBW];
 #pragma unroll
-            for (int r = 0; r < 16; r++) acc[cb][r] = 0.f;
-        const uint8_t* arow = qt + (l & 31) * LROW + h * 16;
+            for (int cb = 0; cb < UBW; cb++)
 #pragma unroll
-        for (int t = 0; t < KSTEPS; t++) {
-            const i32x4 af = *(const i32x4*)(arow + t * 32);
-            if constexpr (DT == DT_F32) {
-                const f32x4 a4 = __builtin_bit_cast(f32x4, af);
+                for (int r = 0; r < 16; r++) acc[cb][r] = 0.f;
+            const uint8_t* arow = qt + (l & 31) * LROW + h * 16;
 #pragma unroll
-                for (int e = 0; e < 4; e++)
+            for (int t = 0; t < KSTEPS; t++) {
+                const i32x4 af = *(const i32x4*)(arow + t * 32);
+                if constexpr (DT == DT_F32) {
+                    const f32x4 a4 = __builtin_bit_cast(f32x4, af);
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+#pragma unroll
+                        for (int cb = 0; cb < UBW; cb++)
+                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], __builtin_bit_cast(f32x4, bfrag[cb][t])[e], acc[cb], 0, 0, 0);
+                } else if constexpr (DT == DT_BF16) {
+                    const bf16x8 a8 = __builtin_bit_cast(bf16x8, af);
 #pragma unroll
                     for (int cb = 0; cb < UBW; cb++)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], __builtin_bit_cast(f32x4, bfrag[cb][t])[e], acc[cb], 0, 0, 0);
-            } else if constexpr (DT == DT_BF16) {
-                const bf16x8 a8 = __builtin_bit_cast(bf16x8, af);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, __builtin_bit_cast(bf16x8, bfrag[cb][t]), acc[cb], 0, 0, 0);
+                } else {
+                    const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[0], af[1]});
+                    const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[2], af[3]});
 #pragma unroll
-                for (int cb = 0; cb < UBW; cb++)
-                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, __builtin_bit_cast(bf16x8, bfrag[cb][t]), acc[cb], 0, 0, 0);
-            } else {
-                const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[0], af[1]});
-                const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[2], af[3]});
-#pragma unroll
-                for (int cb = 0; cb < UBW; cb++) {
-                    const i32x4 bf = bfrag[cb][t];
-                    const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[0], bf[1]});
-                    const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[2], bf[3]});
-                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc[cb], 0, 0, 0);
-                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc[cb], 0, 0, 0);
+                    for (int cb = 0; cb < UBW; cb++) {
+                        const i32x4 bf = bfrag[cb][t];
+                        const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[0], bf[1]});
+                        const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[2], bf[3]});
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc[cb], 0, 0, 0);
+                    }
                 }
+            }
+#pragma unroll
+            for (int cb = 0; cb < UBW; cb++) {
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    if (!(live[cb] & (1u << r))) continue;
+                    const int qi = mfma32_row(r, l);
+                    float x = acc[cb][r];
+                    if constexpr (DT == DT_FP8) x = (su[cb] * qs_s[qi]) * x;
+                    const float lam = lam_s[qslot_s[qi]][ul_[cb]];
+                    if (lam == -__builtin_inff()) { yes[cb] |= 1u << r; continue; }
+                    const float e = (float)a.err_rel * un[cb] * qn_s[qi] + fabsf(lam) * 0x1p-23f + (float)a.d * 0x1p-120f;
+                    const float diff = x - lam;
+                    if (force || !(diff > e || diff < -e)) amb[cb] |= 1u << r;
+                    else if (diff > e) yes[cb] |= 1u << r;
+                }
+                n_scored += __popc(live[cb]);
+                n_amb += __popc(amb[cb]);
             }
         }
 
+        // ---- appends: wave prefix sums, one LDS reservation per wave, one global
+        // reservation per workgroup and tile
+        int ny = 0, na = 0;
 #pragma unroll
         for (int cb = 0; cb < UBW; cb++) {
-            uint32_t yes = 0u, amb = 0u;
+            ny += __popc(yes[cb]);
+            na += __popc(amb[cb]);
+        }
+        const int iy = wave_incl_scan(ny), ia = wave_incl_scan(na);
+        const int ty = __shfl(iy, 63), ta = __shfl(ia, 63);
+        unsigned int wy = 0u, wa = 0u;
+        if (l == 0) {
+            if (ty) wy = atomicAdd(&cnt_s[0], (unsigned int)ty);
+            if (ta) wa = atomicAdd(&cnt_s[1], (unsigned int)ta);
+        }
+        wy = __shfl(wy, 0);
+        wa = __shfl(wa, 0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            base_s[0] = cnt_s[0] ? atomicAdd(a.pool_count, (unsigned long long)cnt_s[0]) : 0ull;
+            base_s[1] = cnt_s[1] ? atomicAdd(a.amb_count, (unsigned long long)cnt_s[1]) : 0ull;
+        }
+        __syncthreads();
+        if (ty | ta) {
+            int64_t py = (int64_t)base_s[0] + wy + iy - ny, pa = (int64_t)base_s[1] + wa + ia - na;
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                if (!(live[cb] & (1u << r))) continue;
-                const int qi = mfma32_row(r, l);
-                float x = acc[cb][r];
-                if constexpr (DT == DT_FP8) x = (su[cb] * qs_s[qi]) * x;
-                const float lam = lam_s[qslot_s[qi]][ul_[cb]];
-                if (lam == -__builtin_inff()) { yes |= 1u << r; continue; }
-                const float e = (float)a.err_rel * un[cb] * qn_s[qi] + fabsf(lam) * 0x1p-23f + (float)a.d * 0x1p-120f;
-                const float diff = x - lam;
-                if (force || !(diff > e || diff < -e)) amb |= 1u << r;
-                else if (diff > e) yes |= 1u << r;
-            }
-            n_scored += __popc(live[cb]);
-            n_amb += __popc(amb);
-            // wave-aggregated appends
-            const int ny = __popc(yes), na = __popc(amb);
-            const int iy = wave_incl_scan(ny), ia = wave_incl_scan(na);
-            const int ty = __shfl(iy, 63), ta = __shfl(ia, 63);
-            unsigned long long by = 0, ba = 0;
-            if (l == 0) {
-                if (ty) by = atomicAdd(a.pool_count, (unsigned long long)ty);
-                if (ta) ba = atomicAdd(a.amb_count, (unsigned long long)ta);
-            }
-            by = __shfl(by, 0);
-            ba = __shfl(ba, 0);
-            int64_t py = (int64_t)by + iy - ny, pa = (int64_t)ba + ia - na;
+            for (int cb = 0; cb < UBW; cb++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                const int64_t q = qb + mfma32_row(r, l);
-                if (yes & (1u << r)) {
-                    if (py < a.pool_cap) a.pool[py] = ((unsigned long long)a.qorig[q] << 32) | ouid[cb];
-                    py++;
+                for (int r = 0; r < 16; r++) {
+                    const int64_t q = qb + mfma32_row(r, l);
+                    if (yes[cb] & (1u << r)) {
+                        if (py < a.pool_cap) a.pool[py] = ((unsigned long long)a.qorig[q] << 32) | ouid[cb];
+                        py++;
+                    }
+                    if (amb[cb] & (1u << r)) {
+                        if (pa < a.amb_cap) a.amb[pa] = ((unsigned long long)q << 32) | (uint32_t)(u0 + ul_[cb]);
+                        pa++;
+                    }
                 }
-                if (amb & (1u << r)) {
-                    if (pa < a.amb_cap) a.amb[pa] = ((unsigned long long)q << 32) | (uint32_t)(u0 + ul_[cb]);
-                    pa++;
-                }
-            }
         }
     }
     n_node = wave_sum(n_node);
@@ -253,10 +312,70 @@ __global__ __launch_bounds__(256) void k_verify(QueryArgs a, int64_t q_begin, in
     }
 }
 
+// cos(phi) of every (block, query) pair: the FP32 inner product of the query with the
+// block's unit centre over the query norm, clamped to [-1, 1] (0 for a zero query).  One
+// thread per pair, 16-byte loads; the result feeds the node-level bound of Lemma 2.
+template <int DT, int DPT>
+__global__ __launch_bounds__(256) void k_phi(QueryArgs a, float* cphi, int64_t b0)
+{
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int PER = 16 / EB;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = b0 + blockIdx.y;
+    if (q >= a.nq) return;
+    const uint8_t* qr = (const uint8_t*)a.queries + q * (int64_t)DPT * EB;
+    const float* cr = a.center + b * (int64_t)DPT;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int c0 = 0; c0 < DPT; c0 += PER) {
+        const i32x4 qv = *(const i32x4*)(qr + c0 * EB);
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            float x;
+            if constexpr (DT == DT_F32) x = __int_as_float(qv[e]);
+            else if constexpr (DT == DT_BF16) x = bf16_to_f32((uint16_t)((uint32_t)qv[e >> 1] >> (16 * (e & 1))));
+            else x = e4m3_to_f32((uint8_t)((uint32_t)qv[e >> 2] >> (8 * (e & 3))));
+            acc[e & 3] = fmaf(x, cr[c0 + e], acc[e & 3]);
+        }
+    }
+    float dot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if constexpr (DT == DT_FP8) dot *= a.query_scales[q];
+    const float qn = a.qnorm[q];
+    float c = qn > 0.f ? dot / qn : 0.f;
+    c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
+    cphi[b * a.nq + q] = c;
+}
+
+template <int DT>
+static void phi_d(const QueryArgs& a, float* cphi, hipStream_t s)
+{
+    for (int64_t b0 = 0; b0 < a.nblocks; b0 += 65535) {
+        dim3 g((unsigned)((a.nq + 255) / 256), (unsigned)std::min<int64_t>(65535, a.nblocks - b0));
+        switch (a.ld) {
+        case 32: hipLaunchKernelGGL((k_phi<DT, 32>), g, dim3(256), 0, s, a, cphi, b0); break;
+        case 64: hipLaunchKernelGGL((k_phi<DT, 64>), g, dim3(256), 0, s, a, cphi, b0); break;
+        case 128: hipLaunchKernelGGL((k_phi<DT, 128>), g, dim3(256), 0, s, a, cphi, b0); break;
+        case 256: hipLaunchKernelGGL((k_phi<DT, 256>), g, dim3(256), 0, s, a, cphi, b0); break;
+        default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
+        }
+    }
+}
+
+void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s)
+{
+    if (a.nq <= 0 || a.nblocks <= 0) return;
+    if (a.dtype == DT_F32) phi_d<DT_F32>(a, cphi, s);
+    else if (a.dtype == DT_BF16) phi_d<DT_BF16>(a, cphi, s);
+    else phi_d<DT_FP8>(a, cphi, s);
+    HIPC(hipGetLastError());
+}
+
 template <int DT, int DPT>
 static void verify_g(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
 {
-    constexpr int UBW = (DT == DT_F32 && DPT >= 256) ? 1 : 2;
+    // one 32-user column block per wave: the register budget goes to occupancy, which
+    // hides the per-tile latencies (the matrix-core share of this pass is small)
+    constexpr int UBW = 1;
     constexpr int UT = VF_WAVES * UBW * 32;
     const int64_t tiles = (a.m + UT - 1) / UT;
     // split the queries so that the grid covers the chip several times

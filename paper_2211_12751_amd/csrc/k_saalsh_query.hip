@@ -27,14 +27,47 @@ namespace rk {
 
 static constexpr int SQ_T = 256;
 
+// Canonical FP64 inner product of two stored rows (index-order sum of the exact
+// products; FP8: exact code sum times the scale product), 16-byte loads.
 template <int DT>
 __device__ double sq_dot(const void* A, int64_t ra, float sa, const void* B, int64_t rb, float sb, int d, int ld)
 {
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int PER = 16 / EB;
+    const uint8_t* ar = (const uint8_t*)A + ra * (int64_t)ld * EB;
+    const uint8_t* br = (const uint8_t*)B + rb * (int64_t)ld * EB;
     double acc = 0.0;
-    for (int i = 0; i < d; i++)
-        acc = __fma_rn((double)elem_f32<DT>(A, ra * ld + i), (double)elem_f32<DT>(B, rb * ld + i), acc);
+    for (int c0 = 0; c0 < d; c0 += PER) {
+        const i32x4 x4 = *(const i32x4*)(ar + c0 * EB);
+        const i32x4 y4 = *(const i32x4*)(br + c0 * EB);
+        const int lim = d - c0 < PER ? d - c0 : PER;
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            if (e >= lim) break;
+            float x, y;
+            if constexpr (DT == DT_F32) {
+                x = __int_as_float(x4[e]);
+                y = __int_as_float(y4[e]);
+            } else if constexpr (DT == DT_BF16) {
+                x = bf16_to_f32((uint16_t)((uint32_t)x4[e >> 1] >> (16 * (e & 1))));
+                y = bf16_to_f32((uint16_t)((uint32_t)y4[e >> 1] >> (16 * (e & 1))));
+            } else {
+                x = e4m3_to_f32((uint8_t)((uint32_t)x4[e >> 2] >> (8 * (e & 3))));
+                y = e4m3_to_f32((uint8_t)((uint32_t)y4[e >> 2] >> (8 * (e & 3))));
+            }
+            acc = __fma_rn((double)x, (double)y, acc);
+        }
+    }
     if constexpr (DT == DT_FP8) acc = ((double)sa * (double)sb) * acc;
     return acc;
+}
+
+// collision count of item p with the user code
+__device__ __forceinline__ int collisions(const uint32_t* codes, int64_t p, const uint32_t* ucode, int W, int K)
+{
+    int diff = 0;
+    for (int w = 0; w < W; w++) diff += __popc(codes[p * W + w] ^ ucode[w]);
+    return K - diff;
 }
 
 // k-th largest of vals[0..cnt) (orderable 64-bit keys, 8 byte-digits), by one workgroup
@@ -103,11 +136,7 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
             // histogram of collision counts over the partition
             for (int b = tid; b <= a.K; b += SQ_T) hist[b] = 0;
             __syncthreads();
-            for (int64_t p = s0 + tid; p < s1; p += SQ_T) {
-                int diff = 0;
-                for (int w = 0; w < W; w++) diff += __popc(a.item_codes[p * W + w] ^ ucode[w]);
-                atomicAdd(&hist[a.K - diff], 1);
-            }
+            for (int64_t p = s0 + tid; p < s1; p += SQ_T) atomicAdd(&hist[collisions(a.item_codes, p, ucode, W, a.K)], 1);
             __syncthreads();
             if (tid == 0) {   // cut count c*: #(count > c*) < take <= #(count >= c*)
                 int64_t above = 0;
@@ -123,35 +152,38 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
             __syncthreads();
             const int cut = sh[0];
             const int need_eq = sh[1];
-            // ordered pass: candidates are the items above the cut and the first need_eq at it
+            // ordered selection: candidates are the items above the cut and the first
+            // need_eq at it (position order).  Each wave owns a contiguous quarter of
+            // the partition: it counts its ties, one block-level prefix orders the
+            // quarters, then every wave takes its items with wave-local ballots.
+            const int wv = tid >> 6, ln = tid & 63;
+            const int64_t qlen = (sz + SQ_T / 64 - 1) / (SQ_T / 64);
+            const int64_t w0 = s0 + wv * qlen;
+            const int64_t w1 = w0 + qlen < s1 ? w0 + qlen : s1;
+            int my_eq = 0;
+            for (int64_t base = w0; base < w1; base += 64) {
+                const int64_t p = base + ln;
+                const bool iseq = p < w1 && collisions(a.item_codes, p, ucode, W, a.K) == cut;
+                my_eq += __popcll(ballot64(iseq));
+            }
+            if (ln == 0) wsum[wv] = my_eq;
+            __syncthreads();
             int eq_before = 0;
-            for (int64_t base = s0; base < s1; base += SQ_T) {
-                const int64_t p = base + tid;
-                int c = -1;
-                if (p < s1) {
-                    int diff = 0;
-                    for (int w = 0; w < W; w++) diff += __popc(a.item_codes[p * W + w] ^ ucode[w]);
-                    c = a.K - diff;
-                }
-                const int iseq = (c == cut) ? 1 : 0;
-                // block-exclusive prefix of iseq in position order
-                const int incl = wave_incl_scan(iseq);
-                if ((tid & 63) == 63) wsum[tid >> 6] = incl;
-                __syncthreads();
-                int off = eq_before;
-                for (int w = 0; w < (tid >> 6); w++) off += wsum[w];
-                int tot = 0;
-                for (int w = 0; w < SQ_T / 64; w++) tot += wsum[w];
-                const int rank_eq = off + incl - iseq;
+            for (int w = 0; w < wv; w++) eq_before += wsum[w];
+            for (int64_t base = w0; base < w1; base += 64) {
+                const int64_t p = base + ln;
+                const int c = p < w1 ? collisions(a.item_codes, p, ucode, W, a.K) : -1;
+                const bool iseq = c == cut;
+                const uint64_t eb = ballot64(iseq);
+                const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
+                eq_before += __popcll(eb);
                 const bool take_it = c > cut || (iseq && rank_eq < need_eq);
-                __syncthreads();
                 // append candidate scores (order inside the candidate multiset is irrelevant)
                 if (take_it) {
                     const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
                     const double v = sq_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
                     cand[atomicAdd(&ccount, 1)] = v;
                 }
-                eq_before += tot;
             }
             __syncthreads();
             ncand = ccount;

@@ -53,7 +53,8 @@ Workspace::~Workspace()
 int64_t Workspace::bytes_for(const Index& x, int64_t nq, int64_t pool_cap, int64_t amb_cap)
 {
     const int64_t eb = elt_bytes(x.dtype);
-    return nq * x.ld * eb + nq * 4 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4) + amb_cap * 8 + 256;
+    return nq * x.ld * eb + nq * 4 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4) + amb_cap * 8 + 256 +
+           nq * x.nblocks * 4;
 }
 
 void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t amb_cap_req)
@@ -77,6 +78,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
         h_qorig.alloc(sizeof(uint32_t) * c);
         h_offsets.alloc(sizeof(int64_t) * (c + 1));
         slotk.alloc(sizeof(int) * kMaxSlots * (c + 1));
+        cphi.alloc(sizeof(float) * (size_t)c * std::max<int64_t>(x.nblocks, 1));
         h_slotk.alloc(sizeof(int) * kMaxSlots * (c + 1));
         nq_cap = c;
     }
@@ -141,7 +143,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.center = x.center.f(); a.cos_w = x.cos_w.f(); a.sin_w = x.sin_w.f(); a.block_ok = x.block_ok.i();
     a.block_lb = x.block_lb.f(); a.nblocks = x.nblocks; a.perm = x.user_perm.u32();
     a.lam32 = x.lam32.f(); a.lam64 = x.lam64.d(); a.k_max = x.prm.k_max;
-    a.queries = w.qpad.p; a.query_scales = w.qsc.f(); a.nq = nq; a.qnorm = w.qnorm.f();
+    a.queries = w.qpad.p; a.query_scales = w.qsc.f(); a.nq = nq; a.qnorm = w.qnorm.f(); a.cphi = w.cphi.f();
     a.qslot = w.qslot.i(); a.qorig = w.qorig.u32(); a.qk = w.qk.i(); a.slot_k = w.slotk.i();
     a.flags = flags | x.prm.flags;
     a.err_rel = fast_err_rel(x.d);
@@ -170,6 +172,7 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
         launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig.u32(), nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
         QueryArgs a = make_query_args(x, w, nq, flags);
         launch_qnorm(x.dtype, w.qpad.p, w.qsc.f(), nq, x.d, x.ld, w.qnorm.f(), a.bad, s);
+        if (!(a.flags & RKMIPS_FLAG_NO_BOUNDS)) launch_phi(a, w.cphi.f(), s);
         for (size_t g = 0; g < w.groups.size(); g++) {
             QueryArgs ag = a;
             ag.slot_k = w.slotk.i() + kMaxSlots * g;
