@@ -240,14 +240,14 @@ def cpu_baseline(w, k_max, off, ids, sample_users):
         # calibrate on a small sample, then size the timed one to ~15 s of work
         per_user = None
         for budget in (None, 1.5):
-            cnt = 64 if budget is None else int(min(w.m, max(64, budget / per_user)))
+            cnt = 4 if budget is None else int(min(w.m, max(4, budget / per_user)))
             cal = np.sort(g.choice(w.m, cnt, replace=False))
             t0 = time.perf_counter()
             lam = O.lambda_table(w.dtype, w.items, w.item_scales, w.users, w.user_scales, k_max,
                                  user_idx=cal)
             O.member(w.dtype, w.users, w.user_scales, w.queries, w.query_scales, w.ks, lam, user_idx=cal)
             per_user = max((time.perf_counter() - t0) / len(cal), 1e-9)
-        sample_users = int(min(w.m, max(64, 15.0 / per_user)))
+        sample_users = int(min(w.m, max(16, 15.0 / per_user)))
     sample = np.sort(g.choice(w.m, sample_users, replace=False))
     t0 = time.perf_counter()
     lam = O.lambda_table(w.dtype, w.items, w.item_scales, w.users, w.user_scales, k_max, user_idx=sample)

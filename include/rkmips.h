@@ -62,10 +62,15 @@ typedef enum {
 enum {
     RKMIPS_FLAG_NO_BOUNDS = 1,      /* skip Cone-Tree pruning (Lemma 2 and Lemma 3 tests)   */
     RKMIPS_FLAG_FORCE_RECHECK = 2,  /* take every unpruned decision in canonical FP64       */
-    RKMIPS_FLAG_NO_SAALSH = 4,      /* skip the SA-ALSH reject stage (Alg. 2)                */
+    RKMIPS_FLAG_NO_SAALSH = 4,      /* never run the SA-ALSH reject stage (overrides 32)     */
     RKMIPS_FLAG_NO_CERT = 8,        /* build: treat every top-k certificate as failed, so
                                        every lambda row comes from the full FP64 rescoring  */
-    RKMIPS_FLAG_NO_VECTOR_BOUND = 16 /* skip only the per-user Lemma 3 test                  */
+    RKMIPS_FLAG_NO_VECTOR_BOUND = 16, /* skip only the per-user Lemma 3 test                 */
+    RKMIPS_FLAG_SAALSH_FILTER = 32  /* run the SA-ALSH stage (Alg. 2) on the close calls
+                                       before the FP64 recheck; its proven "no" answers
+                                       skip the recheck.  Off by default: Alg. 2 scores
+                                       ceil(beta |S_j|) candidates per pair, far more work
+                                       than the O(d) FP64 recheck it can save.           */
 };
 
 typedef struct {

@@ -281,7 +281,8 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     QueryArgs a = make_query_args(x, w, nq, flags);
     fill_u64((unsigned long long*)w.pool.p + cnt, namb, ~0ull, s);
     const int* reject = nullptr;
-    if (namb > 0 && !((flags | x.prm.flags) & RKMIPS_FLAG_NO_SAALSH)) {
+    const int fl = flags | x.prm.flags;
+    if (namb > 0 && (fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH)) {
         // Alg. 2 as a proof-only filter on the close calls: a "no" there is exact
         run_saalsh(x, w, a, namb, s);
         reject = w.sa_answer.i();

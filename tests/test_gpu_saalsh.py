@@ -77,7 +77,8 @@ def test_codes_partitions_and_alg2(seed):
 
 
 def test_exact_queries_with_saalsh_stage():
-    """Every close call passes through Alg. 2 (forced recheck): answers unchanged."""
+    """With the filter on, every close call passes through Alg. 2 (forced recheck):
+    answers unchanged; with it off (the default) or overridden, Alg. 2 never runs."""
     from paper_2211_12751_amd import rkmips as R
     w = I.make("c1", n=800, m=1500, nq=40, seed=21)
     k_max = 10
@@ -86,14 +87,20 @@ def test_exact_queries_with_saalsh_stage():
     ref = [np.flatnonzero(r) for r in O.member("f32", w.users, None, w.queries, None, ks, lam)]
     idx = R.Index(w.items, None, w.users, None, dtype="f32", k_max=k_max, probe_frac=0.3)
     try:
-        got, st = idx.query(w.queries, None, ks, flags=R.FLAG_FORCE_RECHECK, stats=True)
+        got, st = idx.query(w.queries, None, ks, flags=R.FLAG_FORCE_RECHECK | R.FLAG_SAALSH_FILTER, stats=True)
         for a, b in zip(got, ref):
             assert np.array_equal(a, b)
         assert st["saalsh_checked"] == st["pairs_rechecked"] > 0
         assert st["saalsh_rejects"] > 0
-        got2 = idx.query(w.queries, None, ks, flags=R.FLAG_FORCE_RECHECK | R.FLAG_NO_SAALSH)
+        got2, st2 = idx.query(w.queries, None, ks, flags=R.FLAG_FORCE_RECHECK | R.FLAG_SAALSH_FILTER | R.FLAG_NO_SAALSH,
+                              stats=True)
         for a, b in zip(got2, ref):
             assert np.array_equal(a, b)
+        assert st2["saalsh_checked"] == 0
+        got3, st3 = idx.query(w.queries, None, ks, flags=R.FLAG_FORCE_RECHECK, stats=True)   # default: off
+        for a, b in zip(got3, ref):
+            assert np.array_equal(a, b)
+        assert st3["saalsh_checked"] == 0
         print("stats", st, flush=True)
     finally:
         idx.close()
