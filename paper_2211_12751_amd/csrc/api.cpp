@@ -116,7 +116,9 @@ static void choose_topk(Index& x)
     int gpl = 2;
     if (x.ns > 0)
         while (gpl * 64 < 2 * target && gpl < 16) gpl *= 2;
-    while (gpl * 64 < C + 32) gpl *= 2;
+    // each half-wave appends to its own half of a user's buffer; after a compaction the
+    // C survivors sit in one half, which must still take a block's 16 appends
+    while (gpl * 32 < C + 16) gpl *= 2;
     if (gpl > 16) fail(RKMIPS_EINVAL, "internal: candidate buffer too large");
     const int upb = topk_users_per_block(x.dtype, x.ld);
     const int64_t tiles = (x.m + upb - 1) / upb;
@@ -125,7 +127,7 @@ static void choose_topk(Index& x)
     int nmain = (int)std::max<int64_t>(1, (1536 + tiles - 1) / tiles);
     nmain = (int)std::min<int64_t>(nmain, std::max<int64_t>(1, x.n / 1024));
     // the buffers stay within a fixed share of the device memory
-    while (gpl > 2 && gpl * 64 >= 2 * (C + 32) && (double)x.m * nmain * gpl * 64 * 8 > 24e9) gpl /= 2;
+    while (gpl > 2 && gpl * 16 >= C + 16 && (double)x.m * nmain * gpl * 64 * 8 > 24e9) gpl /= 2;
     nmain = std::min(nmain, std::max(1, 2048 / (gpl * 64)));   // the refine gathers at most 2048
     int64_t seg_len = (x.n + nmain - 1) / nmain;
     seg_len = std::max<int64_t>(64, (seg_len + 63) / 64 * 64);
@@ -141,7 +143,7 @@ static void build_lambda(Index& x, hipStream_t s)
     const int64_t m = x.m;
     DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits;
     buf.alloc(sizeof(uint2) * (size_t)m * x.nseg * x.G);
-    cnt.alloc(sizeof(int) * (size_t)m * x.nseg);
+    cnt.alloc(sizeof(int) * (size_t)m * x.nseg * 2);
     tau.alloc(sizeof(float) * (size_t)m * x.nseg);
     fail_list.alloc(sizeof(int) * (size_t)m);
     fail_count.alloc(sizeof(int));
@@ -440,7 +442,7 @@ rkmips_status rkmips_get_candidates(const rkmips_index* idx, int32_t* ids, float
         if (!x.cand.p) fail(RKMIPS_EINVAL, "candidates are not kept by this index");
         const int64_t per = (int64_t)x.nseg * x.G;
         std::vector<uint2> buf((size_t)x.m * per);
-        std::vector<int> cnt((size_t)x.m * x.nseg);
+        std::vector<int> cnt((size_t)x.m * x.nseg * 2);
         std::vector<float> tt((size_t)x.m * x.nseg);
         std::vector<uint32_t> perm(x.m), iorder(x.n);
         HIPC(hipMemcpy(buf.data(), x.cand.p, sizeof(uint2) * buf.size(), hipMemcpyDeviceToHost));
@@ -453,11 +455,12 @@ rkmips_status rkmips_get_candidates(const rkmips_index* idx, int32_t* ids, float
             const int64_t ou = perm[u];
             int k = 0;
             float tmax = -INFINITY;
-            for (int s = 0; s < x.nseg; s++) {
-                const int c = cnt[u * x.nseg + s];
+            for (int p = 0; p < 2 * x.nseg; p++) {
+                const int s = p >> 1;
+                const int c = cnt[(u * x.nseg + s) * 2 + (p & 1)];
                 tmax = std::max(tmax, tt[u * x.nseg + s]);
                 for (int i = 0; i < c; i++, k++) {
-                    const uint2 e = buf[(u * x.nseg + s) * x.G + i];
+                    const uint2 e = buf[(u * x.nseg + s) * x.G + (p & 1) * (x.G / 2) + i];
                     uint32_t o = e.x;
                     uint32_t bits = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
                     float f;

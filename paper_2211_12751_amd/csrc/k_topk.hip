@@ -122,20 +122,24 @@ __device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, in
 }
 
 // ------------------------------------------------------------------ fused GEMM + top-k
-// user column blocks per wave: FP32 keeps one (register budget for several waves per
-// SIMD, so one wave's top-k epilogue hides behind another's matrix-core work); the
-// narrow types keep two so each LDS fragment feeds two MFMAs
-constexpr int topk_ubw(int dt, int dpt) { return (dt == DT_F32 || dpt >= 512) ? 1 : 2; }
+// user column blocks per wave: one, so the register budget goes to resident waves and
+// one wave's filter epilogue hides behind another's matrix-core work (with two, the
+// narrow types fall to one wave per SIMD and run slower although each LDS fragment
+// would feed two MFMAs)
+constexpr int topk_ubw(int, int) { return 1; }
 
 // Buffer compaction for the streaming pass, staged through LDS so that it needs few
 // registers (it runs rarely, and the main loop keeps its register budget for
-// occupancy): keep the C largest of the c entries (ties at the threshold in buffer
-// order), return the C-th largest key.
-__device__ __forceinline__ uint32_t select_user(uint2* region, int c, int C, int* hist, uint2* stage)
+// occupancy): of the c0 entries at r0 and the c1 entries at r1, keep the C largest
+// (ties at the threshold in staging order) in r0[0, C) and return the C-th largest key.
+__device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1, int c1, int C, int* hist,
+                                             uint2* stage)
 {
     const int l = lane_id();
+    const int c = c0 + c1;
     for (int i = l; i < c; i += 64) {
-        const unsigned long long raw = __hip_atomic_load((unsigned long long*)(region + i), __ATOMIC_RELAXED,
+        const uint2* src = i < c0 ? r0 + i : r1 + (i - c0);
+        const unsigned long long raw = __hip_atomic_load((const unsigned long long*)src, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
         stage[i] = make_uint2((uint32_t)raw, (uint32_t)(raw >> 32));
     }
@@ -182,7 +186,7 @@ __device__ __forceinline__ uint32_t select_user(uint2* region, int c, int C, int
         eq_before += __popcll(eb);
         const bool keep = gt || (eq && rank_eq < need);
         const uint64_t kb = ballot64(keep);
-        if (keep) region[kept_before + __popcll(kb & lanemask_lt())] = e;
+        if (keep) r0[kept_before + __popcll(kb & lanemask_lt())] = e;
         kept_before += __popcll(kb);
     }
     __builtin_amdgcn_wave_barrier();
@@ -241,9 +245,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     i32x4 bfrag[UBW][KSTEPS];
     float theta[UBW], su[UBW];
     float top[UBW][MODE == TK_SEED ? TK_T : 1];
-    int cnt[UBW];
+    int cnt[UBW];            // entries this lane appended to its half of the buffer
     int64_t ug[UBW];
-    uint2* region[UBW];
+    uint2* region[UBW];      // this lane's half: half h of the user's G entries
+    const int HG = a.G / 2;
 #pragma unroll
     for (int cb = 0; cb < UBW; cb++) {
         ug[cb] = user0 + cb * 32 + (l & 31);
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         theta[cb] = ok ? th0 : __builtin_inff();   // +inf: nothing enters
         su[cb] = (DT == DT_FP8 && ok) ? a.user_scales[ug[cb]] : 1.0f;
         cnt[cb] = 0;
-        region[cb] = a.buf + ((ok ? ug[cb] : 0) * a.nseg_total + seg) * (int64_t)a.G;
+        region[cb] = a.buf + ((ok ? ug[cb] : 0) * a.nseg_total + seg) * (int64_t)a.G + h * HG;
 #pragma unroll
         for (int i = 0; i < (MODE == TK_SEED ? TK_T : 1); i++) top[cb][i] = -__builtin_inff();
     }
@@ -369,46 +374,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                         }
                     }
                 } else {
-                    // ---- threshold filter, buffer append, compaction when full
-                    uint32_t pm = 0u;
-#pragma unroll
-                    for (int r = 0; r < 16; r++)
-                        if (v[r] > theta[cb]) pm |= 1u << r;
-                    // every cross-lane read happens with the whole wave active: a permute
-                    // from an inactive lane returns 0
-                    int np = __popc(pm);
-                    int npo = __shfl_xor(np, 32);
-                    int tot = np + npo;
-                    uint64_t need = ballot64(cnt[cb] + tot > a.G) & 0xffffffffull;
+                    // ---- compaction of the users whose half-buffer could overflow in this
+                    // block (a lane appends at most 16 entries per block)
+                    const uint64_t need = ballot64(cnt[cb] + 16 > HG);
                     if (need) {
-                        while (need) {
-                            const int ul = __builtin_ctzll(need);
-                            need &= need - 1;
-                            const int c = __shfl(cnt[cb], ul);
+                        uint32_t um = (uint32_t)need | (uint32_t)(need >> 32);
+                        while (um) {
+                            const int ul = __builtin_ctz(um);
+                            um &= um - 1;
+                            const int c0 = __shfl(cnt[cb], ul), c1 = __shfl(cnt[cb], ul + 32);
                             const int64_t ugl = __shfl(ug[cb], ul);
                             uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
-                            const uint32_t T = select_user(rg, c, a.C, hist, stage);
+                            const uint32_t T = select_user(rg, c0, rg + HG, c1, a.C, hist, stage);
                             if ((l & 31) == ul) {
                                 theta[cb] = ord_f32(T);
-                                cnt[cb] = a.C;
+                                cnt[cb] = h ? 0 : a.C;
                             }
                         }
-                        pm = 0u;
-#pragma unroll
-                        for (int r = 0; r < 16; r++)
-                            if (v[r] > theta[cb]) pm |= 1u << r;
-                        np = __popc(pm);
-                        npo = __shfl_xor(np, 32);
-                        tot = np + npo;
                     }
-                    if (tot) {
-                        const uint32_t pbase = (uint32_t)(t0 + rb * 32);
-                        int pos = cnt[cb] + (h ? npo : 0);
+                    // ---- threshold filter and append, one row at a time: each lane owns
+                    // its half of the user's buffer, so appends need no cross-lane counts,
+                    // and a row that no lane passes costs one compare and one branch
+                    const uint32_t pbase = (uint32_t)(t0 + rb * 32);
 #pragma unroll
-                        for (int r = 0; r < 16; r++)
-                            if (pm & (1u << r))
-                                region[cb][pos++] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)mfma32_row(r, l));
-                        cnt[cb] += tot;
+                    for (int r = 0; r < 16; r++) {
+                        const bool pass = v[r] > theta[cb];
+                        if (ballot64(pass)) {
+                            if (pass) {
+                                region[cb][cnt[cb]] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)mfma32_row(r, l));
+                                cnt[cb]++;
+                            }
+                        }
                     }
                 }
             }
@@ -426,9 +422,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         // ---- outputs: the buffer may hold up to G entries; the refine pass selects
 #pragma unroll
         for (int cb = 0; cb < UBW; cb++)
-            if (l < 32 && ug[cb] < a.m) {
-                a.cnt[ug[cb] * a.nseg_total + seg] = cnt[cb];
-                a.tau[ug[cb] * a.nseg_total + seg] = theta[cb];
+            if (ug[cb] < a.m) {
+                a.cnt[(ug[cb] * a.nseg_total + seg) * 2 + h] = cnt[cb];
+                if (h == 0) a.tau[ug[cb] * a.nseg_total + seg] = theta[cb];
             }
     }
 }
@@ -553,15 +549,18 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     int* hist = hist_all[w];
 
     // gather every segment's buffer straight into registers (entry j = lane + 64 i)
-    int cum[5];
+    // part p = 2 s + h: half h of segment s's buffer
+    int cum[9];
     cum[0] = 0;
     float tau_max = -__builtin_inff();
-    for (int s = 0; s < 4; s++) {
-        const int c = s < a.nseg ? a.cnt[u * a.nseg + s] : 0;
-        cum[s + 1] = cum[s] + c;
-        if (s < a.nseg) tau_max = fmaxf(tau_max, a.tau[u * a.nseg + s]);
+    for (int p = 0; p < 8; p++) {
+        const int s = p >> 1;
+        const int c = s < a.nseg ? a.cnt[(u * a.nseg + s) * 2 + (p & 1)] : 0;
+        cum[p + 1] = cum[p] + c;
+        if (s < a.nseg && (p & 1) == 0) tau_max = fmaxf(tau_max, a.tau[u * a.nseg + s]);
     }
-    const int N = cum[4];
+    const int N = cum[8];
+    const int HG = a.G / 2;
     uint32_t key[RF_GPL], id[RF_GPL];
 #pragma unroll
     for (int i = 0; i < RF_GPL; i++) {
@@ -569,8 +568,10 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
         key[i] = 0u;
         id[i] = 0u;
         if (j < N) {
-            const int s = (j >= cum[1]) + (j >= cum[2]) + (j >= cum[3]);
-            const uint2 e = a.buf[(u * a.nseg + s) * (int64_t)a.G + (j - cum[s])];
+            int p = 0;
+#pragma unroll
+            for (int q = 1; q < 8; q++) p += j >= cum[q];
+            const uint2 e = a.buf[(u * a.nseg + (p >> 1)) * (int64_t)a.G + (p & 1) * HG + (j - cum[p])];
             key[i] = e.x;
             id[i] = e.y;
         }
