@@ -100,20 +100,21 @@ struct ConeLevelArgs {
     const float* unit;     // [m x ld] unit users (original order)
     int ld, d;
     const uint32_t* perm;  // position -> user
-    const int64_t* seg_start;  // [nseg+1] all current segments (sorted)
-    const int* seg_active;     // [nseg]
-    const int64_t* seg_pivot;  // [nseg] position of the random point v
-    int64_t nseg, m;
+    const int64_t* seg_start;  // [nseg+1] this level's segments (sorted, last = m)
+    int64_t* next_start;       // [.. + 1] the next level's segments
+    int64_t* ctl;              // [4] nseg of this level, nseg of the next, active segments of the next
+    int ctl_cur;               // index of this level's nseg in ctl (0 or 1)
+    int level, leaf;           // level number (pivot draws), N0
+    uint64_t seed;
+    int64_t m;
     unsigned long long* key1; unsigned long long* key2;  // [nseg]
     float* dot_l;          // [m] per position
     int* left;             // [m] per position
     int* nleft;            // [nseg]
+    int* degen;            // [nseg] split fell back to index halves
+    unsigned long long* next_key1; unsigned long long* next_key2;  // the next level's,
+    int* next_nleft;                                                // reset by k_cone_next
 };
-void cone_level_pivots(const ConeLevelArgs& a, hipStream_t s);
-void cone_level_split(const ConeLevelArgs& a, hipStream_t s);
-// positions: new_perm[newpos(p)] = perm[p] given exclusive scan of left flags.
-void cone_level_scatter(const ConeLevelArgs& a, const int* left_scan, const int* degenerate,
-                        uint32_t* new_perm, hipStream_t s);
 void exclusive_scan_i32(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 

@@ -41,7 +41,16 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
     return v;
 }
 
-// <a, b> of two unit rows, one lane per row (float4 loads, rows stay in L1/L2).
+// Segment s of the current level is split (active) when it holds more than N0 users;
+// its random point v is the user at a counter-based draw inside the segment.
+__device__ __forceinline__ int64_t cone_pivot(const ConeLevelArgs& a, int64_t st, int64_t sz)
+{
+    const uint64_t r = splitmix64(a.seed ^ splitmix64(((uint64_t)a.level << 40) ^ (uint64_t)st));
+    return st + (int64_t)(r % (uint64_t)sz);
+}
+
+// <a, b> of two unit rows, one lane per row (16-byte loads; the rows of a wave are
+// independent, so their loads overlap).
 __device__ __forceinline__ float row_dot(const float* a, const float* b, int ld)
 {
     float acc = 0.f;
@@ -60,26 +69,31 @@ __device__ __forceinline__ float row_dot(const float* a, const float* b, int ld)
 __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
 {
     const int l = lane_id();
+    const int64_t nseg = a.ctl[a.ctl_cur];
     const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64 + l;
     const bool in = p < a.m;
-    const int64_t s = in ? seg_of(a.seg_start, a.nseg, p) : -1;
-    const bool act = in && a.seg_active[s];
+    const int64_t s = in ? seg_of(a.seg_start, nseg, p) : -1;
+    bool act = false;
     unsigned long long key = ~0ull;
     int lf = 0;
-    if (act) {
-        const float* up = a.unit + (int64_t)a.perm[p] * a.ld;
-        if (phase == 0) {
-            const float dv = row_dot(up, a.unit + (int64_t)a.perm[a.seg_pivot[s]] * a.ld, a.ld);
-            key = ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p;
-        } else if (phase == 1) {
-            const int64_t pl = (int64_t)(a.key1[s] & 0xffffffffull);
-            const float dl = row_dot(up, a.unit + (int64_t)a.perm[pl] * a.ld, a.ld);
-            a.dot_l[p] = dl;
-            key = ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p;
-        } else {
-            const int64_t pr = (int64_t)(a.key2[s] & 0xffffffffull);
-            const float dr = row_dot(up, a.unit + (int64_t)a.perm[pr] * a.ld, a.ld);
-            lf = a.dot_l[p] >= dr ? 1 : 0;
+    if (in) {
+        const int64_t st = a.seg_start[s], sz = a.seg_start[s + 1] - st;
+        act = sz > a.leaf;
+        if (act) {
+            const float* up = a.unit + (int64_t)a.perm[p] * a.ld;
+            if (phase == 0) {
+                const float dv = row_dot(up, a.unit + (int64_t)a.perm[cone_pivot(a, st, sz)] * a.ld, a.ld);
+                key = ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p;
+            } else if (phase == 1) {
+                const int64_t pl = (int64_t)(a.key1[s] & 0xffffffffull);
+                const float dl = row_dot(up, a.unit + (int64_t)a.perm[pl] * a.ld, a.ld);
+                a.dot_l[p] = dl;
+                key = ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p;
+            } else {
+                const int64_t pr = (int64_t)(a.key2[s] & 0xffffffffull);
+                const float dr = row_dot(up, a.unit + (int64_t)a.perm[pr] * a.ld, a.ld);
+                lf = a.dot_l[p] >= dr ? 1 : 0;
+            }
         }
     }
     if (phase == 2 && in) a.left[p] = lf;
@@ -99,14 +113,94 @@ __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
     }
 }
 
-__global__ void k_cone_scatter(ConeLevelArgs a, const int* lscan, const int* degenerate, uint32_t* new_perm)
+// Reset of the per-segment reductions of a level.
+__global__ void k_cone_init(ConeLevelArgs a)
+{
+    const int64_t nseg = a.ctl[a.ctl_cur];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += (int64_t)gridDim.x * blockDim.x) {
+        a.key1[i] = ~0ull;
+        a.key2[i] = ~0ull;
+        a.nleft[i] = 0;
+    }
+}
+
+// The next level's segments, by one workgroup: an active segment becomes its left and
+// right parts (index halves when one side is empty), an inactive one stays.  Also
+// counts the next level's active segments.
+__global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
+{
+    __shared__ int64_t wtot[16];
+    __shared__ int64_t carry_s, active_s;
+    const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
+    const int64_t nseg = a.ctl[a.ctl_cur];
+    if (tid == 0) {
+        carry_s = 0;
+        active_s = 0;
+    }
+    __syncthreads();
+    int64_t nact = 0;
+    for (int64_t c0 = 0; c0 < nseg; c0 += 1024) {
+        const int64_t s = c0 + tid;
+        int64_t st = 0, sz = 0, nl = 0;
+        int kids = 0;
+        bool act = false, dg = false;
+        if (s < nseg) {
+            st = a.seg_start[s];
+            sz = a.seg_start[s + 1] - st;
+            act = sz > a.leaf;
+            kids = act ? 2 : 1;
+            if (act) {
+                nl = a.nleft[s];
+                dg = nl == 0 || nl == sz;
+                if (dg) nl = sz / 2;
+                nact += (nl > a.leaf) + (sz - nl > a.leaf);
+            }
+            a.degen[s] = dg ? 1 : 0;
+        }
+        // block-exclusive prefix of kids
+        const int incl = wave_incl_scan(kids);
+        if (l == 63) wtot[w] = incl;
+        __syncthreads();
+        int64_t off = carry_s;
+        for (int q = 0; q < w; q++) off += wtot[q];
+        off += incl - kids;
+        if (s < nseg) {
+            a.next_start[off] = st;
+            if (act) a.next_start[off + 1] = st + nl;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int64_t t = 0;
+            for (int q = 0; q < 16; q++) t += wtot[q];
+            carry_s += t;
+        }
+        __syncthreads();
+    }
+    nact = wave_sum((unsigned long long)nact);
+    if (l == 0 && nact) atomicAdd((unsigned long long*)&active_s, (unsigned long long)nact);
+    __syncthreads();
+    if (tid == 0) {
+        a.next_start[carry_s] = a.m;
+        a.ctl[1 - a.ctl_cur] = carry_s;
+        a.ctl[2] = active_s;
+    }
+    // the next level's reductions start from their identities
+    for (int64_t i = tid; i < carry_s; i += 1024) {
+        a.next_key1[i] = ~0ull;
+        a.next_key2[i] = ~0ull;
+        a.next_nleft[i] = 0;
+    }
+}
+
+__global__ void k_cone_scatter(ConeLevelArgs a, const int* lscan, uint32_t* new_perm)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.m) return;
-    const int64_t s = seg_of(a.seg_start, a.nseg, p);
+    const int64_t nseg = a.ctl[a.ctl_cur];
+    const int64_t s = seg_of(a.seg_start, nseg, p);
     int64_t np = p;
-    if (a.seg_active[s] && !degenerate[s]) {
-        const int64_t st = a.seg_start[s];
+    const int64_t st = a.seg_start[s], sz = a.seg_start[s + 1] - st;
+    if (sz > a.leaf && !a.degen[s]) {
         const int64_t lb = lscan[p] - lscan[st];
         np = a.left[p] ? st + lb : st + a.nleft[s] + (p - st - lb);
     }
@@ -222,17 +316,6 @@ __global__ void k_block_lb(const double* lam64, const double* user_n2, const int
     lb[(int64_t)j * nblocks + b] = out;
 }
 
-// Per-level reset of the segment reductions.
-__global__ void k_cone_init(ConeLevelArgs a)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < a.nseg) {
-        a.key1[i] = ~0ull;
-        a.key2[i] = ~0ull;
-        a.nleft[i] = 0;
-    }
-}
-
 // ------------------------------------------------------------------ host orchestration
 void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s)
 {
@@ -255,91 +338,68 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     scan_tmp.alloc(sizeof(int) * scan_tmp_elems(m));
     hipLaunchKernelGGL(k_iota, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, perm_a.u32(), m);
 
-    const int N0 = x.prm.leaf_size;
-    std::vector<int64_t> starts{0, m};   // segment boundaries (sorted), last = m
-    // Per-level tables go to the device in one copy from pinned memory, packed for the
-    // level's nseg: starts [nseg+1] and pivots [nseg] (int64), active flags [nseg] (int);
-    // the degenerate flags [nseg] (int) follow in a second copy after the split.  Two
-    // staging areas alternate between levels: the copies out of one area have completed
-    // by the time it is written again (each level's host part waits on the stream).
+    // Levels run on the device, four per check of the host: each level's segment table
+    // is built by k_cone_next from the previous one; a level without active segments
+    // changes nothing, so levels past the last split are harmless.
     const int64_t cap = m + 2;
-    const size_t tbl_bytes = sizeof(int64_t) * (2 * cap + 1) + sizeof(int) * 2 * cap;
-    PinBuf stage[2];
-    stage[0].alloc(tbl_bytes);
-    stage[1].alloc(tbl_bytes);
-    PinBuf h_nleft;
-    h_nleft.alloc(sizeof(int) * cap);
-    DevBuf d_tbl, d_key1, d_key2, d_nleft;
-    d_tbl.alloc(tbl_bytes);
-    d_key1.alloc(sizeof(uint64_t) * cap);
-    d_key2.alloc(sizeof(uint64_t) * cap);
-    d_nleft.alloc(sizeof(int) * cap);
-    int level = 0;
-    for (;;) {
-        const int64_t nseg = (int64_t)starts.size() - 1;
-        uint8_t* st = (uint8_t*)stage[level & 1].p;
-        int64_t* h_starts = (int64_t*)st;
-        int64_t* h_pivot = h_starts + nseg + 1;
-        int* h_active = (int*)(h_pivot + nseg);
-        int* h_degen = h_active + nseg;
-        int64_t* t_starts = (int64_t*)d_tbl.p;
-        int64_t* t_pivot = t_starts + nseg + 1;
-        int* t_active = (int*)(t_pivot + nseg);
-        int* t_degen = t_active + nseg;
-        const size_t head_bytes = (size_t)((uint8_t*)h_degen - st);
-        bool any = false;
-        for (int64_t i = 0; i < nseg; i++) {
-            const int64_t sz = starts[i + 1] - starts[i];
-            h_active[i] = 0;
-            h_pivot[i] = 0;
-            if (sz > N0) {
-                h_active[i] = 1;
-                any = true;
-                const uint64_t r = splitmix64(x.prm.seed ^ splitmix64(((uint64_t)level << 40) ^ (uint64_t)starts[i]));
-                h_pivot[i] = starts[i] + (int64_t)(r % (uint64_t)sz);
-            }
-        }
-        if (!any) break;
-        std::memcpy(h_starts, starts.data(), sizeof(int64_t) * (nseg + 1));
-        HIPC(hipMemcpyAsync(d_tbl.p, st, head_bytes, hipMemcpyHostToDevice, s));
+    DevBuf d_start[2], d_ctl, d_key1[2], d_key2[2], d_nleft[2], d_degen;
+    for (int i = 0; i < 2; i++) {
+        d_start[i].alloc(sizeof(int64_t) * (cap + 1));
+        d_key1[i].alloc(sizeof(uint64_t) * cap);
+        d_key2[i].alloc(sizeof(uint64_t) * cap);
+        d_nleft[i].alloc(sizeof(int) * cap);
+    }
+    d_ctl.alloc(sizeof(int64_t) * 4);
+    d_degen.alloc(sizeof(int) * cap);
+    PinBuf h_ctl;
+    h_ctl.alloc(sizeof(int64_t) * 4);
+    auto level_args = [&](int level) {
+        const int c = level & 1, n = c ^ 1;
         ConeLevelArgs a{};
         a.unit = unit.f(); a.ld = ld; a.d = x.d; a.perm = perm_a.u32();
-        a.seg_start = t_starts; a.seg_active = t_active; a.seg_pivot = t_pivot;
-        a.nseg = nseg; a.m = m;
-        a.key1 = (unsigned long long*)d_key1.p; a.key2 = (unsigned long long*)d_key2.p;
-        a.dot_l = dot_l.f(); a.left = left.i(); a.nleft = d_nleft.i();
-        hipLaunchKernelGGL(k_cone_init, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s, a);
-        const unsigned grid = (unsigned)((m + 255) / 256);
-        for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
-        HIPC(hipGetLastError());
-        int* nleft = (int*)h_nleft.p;
-        HIPC(hipMemcpyAsync(nleft, d_nleft.p, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
-        HIPC(hipStreamSynchronize(s));
-        std::vector<int64_t> next;
-        next.reserve(2 * starts.size());
-        for (int64_t i = 0; i < nseg; i++) {
-            next.push_back(starts[i]);
-            h_degen[i] = 0;
-            if (!h_active[i]) continue;
-            const int64_t sz = starts[i + 1] - starts[i];
-            int64_t nl = nleft[i];
-            if (nl == 0 || nl == sz) {
-                h_degen[i] = 1;
-                nl = sz / 2;
-            }
-            next.push_back(starts[i] + nl);
-        }
-        next.push_back(m);
-        HIPC(hipMemcpyAsync(t_degen, h_degen, sizeof(int) * nseg, hipMemcpyHostToDevice, s));
-        exclusive_scan_i32(left.i(), lscan.i(), m, scan_tmp.i(), s);
-        hipLaunchKernelGGL(k_cone_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a,
-                           (const int*)lscan.i(), (const int*)t_degen, perm_b.u32());
-        HIPC(hipGetLastError());
-        perm_a.swap(perm_b);
-        starts.swap(next);
-        level++;
+        a.seg_start = d_start[c].i64(); a.next_start = d_start[n].i64();
+        a.ctl = d_ctl.i64(); a.ctl_cur = c; a.level = level; a.leaf = x.prm.leaf_size;
+        a.seed = x.prm.seed; a.m = m;
+        a.key1 = (unsigned long long*)d_key1[c].p; a.key2 = (unsigned long long*)d_key2[c].p;
+        a.nleft = d_nleft[c].i();
+        a.next_key1 = (unsigned long long*)d_key1[n].p; a.next_key2 = (unsigned long long*)d_key2[n].p;
+        a.next_nleft = d_nleft[n].i();
+        a.dot_l = dot_l.f(); a.left = left.i(); a.degen = d_degen.i();
+        return a;
+    };
+    {
+        int64_t* hc = (int64_t*)h_ctl.p;
+        hc[0] = 1; hc[1] = 0; hc[2] = m > x.prm.leaf_size ? 1 : 0; hc[3] = 0;
+        HIPC(hipMemcpyAsync(d_ctl.p, hc, sizeof(int64_t) * 4, hipMemcpyHostToDevice, s));
+        const int64_t init[2] = {0, m};
+        HIPC(hipMemcpyAsync(d_start[0].p, init, sizeof init, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_cone_init, dim3(1), dim3(64), 0, s, level_args(0));
+        HIPC(hipStreamSynchronize(s));   // the host copies above are in pageable memory
     }
-    HIPC(hipStreamSynchronize(s));   // the staging areas are released below
+    int level = 0;
+    bool more = m > x.prm.leaf_size;
+    const unsigned grid = (unsigned)((m + 255) / 256);
+    // the first batch is the depth of a perfectly balanced tree, later ones are short
+    int batch = 1;
+    while (((int64_t)x.prm.leaf_size << batch) < m) batch++;
+    while (more) {
+        for (int rep = 0; rep < batch; rep++, level++) {
+            const ConeLevelArgs a = level_args(level);
+            for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
+            hipLaunchKernelGGL(k_cone_next, dim3(1), dim3(1024), 0, s, a);
+            exclusive_scan_i32(left.i(), lscan.i(), m, scan_tmp.i(), s);
+            hipLaunchKernelGGL(k_cone_scatter, dim3(grid), dim3(256), 0, s, a, (const int*)lscan.i(), perm_b.u32());
+            HIPC(hipGetLastError());
+            perm_a.swap(perm_b);
+        }
+        HIPC(hipMemcpyAsync(h_ctl.p, d_ctl.p, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        more = ((const int64_t*)h_ctl.p)[2] > 0;
+        batch = 2;
+    }
+    const int64_t nseg_final = ((const int64_t*)h_ctl.p)[level & 1];
+    std::vector<int64_t> starts(nseg_final + 1);
+    HIPC(hipMemcpy(starts.data(), d_start[level & 1].p, sizeof(int64_t) * (nseg_final + 1), hipMemcpyDeviceToHost));
 
     // ---- leaves are the blocks; users move into leaf order
     x.nblocks = (int64_t)starts.size() - 1;
