@@ -222,18 +222,19 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     Events ev(4);
     HIPC(hipEventRecord(ev.ev[0], s));
     // ---- validation + canonical norms of the caller's arrays
-    DevBuf bad, n2_items_orig, n2_users_orig;
-    bad.alloc(sizeof(int));
+    DevBuf nstats, n2_items_orig, n2_users_orig;
+    nstats.alloc(sizeof(unsigned long long) * 4);
     n2_items_orig.alloc(sizeof(double) * n);
     n2_users_orig.alloc(sizeof(double) * m);
-    HIPC(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-    launch_norm2(x.dtype, items, item_scales, n, x.d, x.d, n2_items_orig.d(), (int*)bad.p, s);
-    launch_norm2(x.dtype, users, user_scales, m, x.d, x.d, n2_users_orig.d(), (int*)bad.p, s);
-    int hbad = 0;
-    HIPC(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    unsigned long long* st = (unsigned long long*)nstats.p;
+    launch_norm_stats_init(st, s);
+    launch_norm2(x.dtype, items, item_scales, n, x.d, x.d, n2_items_orig.d(), st, 0, s);
+    launch_norm2(x.dtype, users, user_scales, m, x.d, x.d, n2_users_orig.d(), st, 1, s);
+    PinBuf hst;
+    hst.alloc(sizeof(unsigned long long) * 4);
+    HIPC(hipMemcpyAsync(hst.p, st, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    if (hbad) fail(RKMIPS_EINVAL, "non-finite value (or NaN code / non-finite scale) in items or users");
-    range_check(x, n2_items_orig.d(), n, n2_users_orig.d(), m, s);
+    range_check(x, (const unsigned long long*)hst.p);
 
     // ---- item order (descending canonical norm, ties by index)
     int64_t cap = 2;
@@ -271,15 +272,16 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
 }
 
 // Refuse magnitudes where the FP32 fast path could overflow or lose the error model.
-void range_check(Index& x, const double* n2i, int64_t n, const double* n2u, int64_t m, hipStream_t s)
+// Refuses non-finite inputs and magnitudes where the FP32 fast path could overflow or
+// lose the error model.  st: max item n2, max user n2, min positive n2 (as bits), bad.
+void range_check(Index& x, const unsigned long long* st)
 {
-    std::vector<double> a(n), b(m);
-    HIPC(hipMemcpyAsync(a.data(), n2i, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(b.data(), n2u, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    double mi = 0, mu = 0, lo = INFINITY;
-    for (double v : a) { mi = std::max(mi, v); if (v > 0) lo = std::min(lo, v); }
-    for (double v : b) { mu = std::max(mu, v); if (v > 0) lo = std::min(lo, v); }
+    if (st[3]) fail(RKMIPS_EINVAL, "non-finite value (or NaN code / non-finite scale) in items or users");
+    double mi, mu, lo;
+    std::memcpy(&mi, &st[0], 8);
+    std::memcpy(&mu, &st[1], 8);
+    std::memcpy(&lo, &st[2], 8);
+    if (st[2] == ~0ull) lo = INFINITY;
     if (std::sqrt(mi) * std::sqrt(mu) > 1e30) fail(RKMIPS_ERANGE, "max||u|| * max||p|| exceeds 1e30");
     if (lo < 1e-60) fail(RKMIPS_ERANGE, "a non-zero vector norm is below 1e-30");
     x.max_item_norm = std::sqrt(mi);

@@ -113,7 +113,7 @@ struct Index {
 };
 
 double fast_err_rel(int d);
-void range_check(Index& x, const double* n2i, int64_t n, const double* n2u, int64_t m, hipStream_t s);
+void range_check(Index& x, const unsigned long long* stats);
 void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
                 hipStream_t s);
 void finish_blocks(Index& x, hipStream_t s);

@@ -25,8 +25,9 @@ int elt_bytes(int dtype);
 // ---------------------------------------------------------------- prep (k_prep.hip)
 // n2[r] = canonical FP64 <x_r, x_r>; sets *bad (device int) non-zero on a
 // non-finite element/scale.  rows use leading dimension ld (elements).
+void launch_norm_stats_init(unsigned long long* stats, hipStream_t s);
 void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, int d, int ld,
-                  double* n2, int* bad, hipStream_t s);
+                  double* n2, unsigned long long* stats, int slot, hipStream_t s);
 // Sort (key, val) pairs ascending by key then val; n <= 2^31.  Scratch-free (in place,
 // arrays must have room for the next power of two, padded by the caller or here).
 void sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int64_t cap, hipStream_t s);
@@ -207,7 +208,9 @@ void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, 
 void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s);
 void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
 void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s);
-void launch_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets,
-                    int32_t* ids, hipStream_t s);
+void launch_result_lists(const uint64_t* keys, int64_t span, int64_t nq, int* cnt, int64_t* offsets,
+                         long long* stat, int32_t* tmp, int32_t* ids, hipStream_t s);
+void launch_result_merges(int64_t nq, int64_t max_count, const int64_t* offsets, int32_t* tmp, int32_t* ids,
+                          hipStream_t s);
 
 }  // namespace rk

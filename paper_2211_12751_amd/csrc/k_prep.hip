@@ -8,49 +8,73 @@
 namespace rk {
 
 // ------------------------------------------------------------------ norms + validation
+// Canonical squared norm of every row (index-order FP64 sum of the exact squares; FP8:
+// times the squared scale), plus what validation needs: stats[slot] = max n2 (bits of a
+// non-negative double order like the value), stats[2] = min positive n2, stats[3] = 1
+// on any non-finite value, NaN code or non-finite scale.
 template <int DT>
 __global__ void k_norm2(const void* X, const float* scales, int64_t rows, int d, int ld, double* n2,
-                        int* bad)
+                        unsigned long long* stats, int slot)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool ok = true;
     double acc = 0.0;
-    const int64_t o = r * ld;
-    for (int i = 0; i < d; i++) {
-        if constexpr (DT == DT_F32) {
-            float v = ((const float*)X)[o + i];
-            ok &= (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
-            acc = __fma_rn((double)v, (double)v, acc);
-        } else if constexpr (DT == DT_BF16) {
-            uint16_t b = ((const uint16_t*)X)[o + i];
-            ok &= (b & 0x7f80u) != 0x7f80u;
-            double v = (double)bf16_to_f32(b);
-            acc = __fma_rn(v, v, acc);
-        } else {
-            uint8_t c = ((const uint8_t*)X)[o + i];
-            ok &= (c & 0x7fu) != 0x7fu;
-            double v = (double)e4m3_to_f32(c);
-            acc = __fma_rn(v, v, acc);
+    if (r < rows) {
+        const int64_t o = r * ld;
+        for (int i = 0; i < d; i++) {
+            if constexpr (DT == DT_F32) {
+                float v = ((const float*)X)[o + i];
+                ok &= (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
+                acc = __fma_rn((double)v, (double)v, acc);
+            } else if constexpr (DT == DT_BF16) {
+                uint16_t b = ((const uint16_t*)X)[o + i];
+                ok &= (b & 0x7f80u) != 0x7f80u;
+                double v = (double)bf16_to_f32(b);
+                acc = __fma_rn(v, v, acc);
+            } else {
+                uint8_t c = ((const uint8_t*)X)[o + i];
+                ok &= (c & 0x7fu) != 0x7fu;
+                double v = (double)e4m3_to_f32(c);
+                acc = __fma_rn(v, v, acc);
+            }
         }
+        if constexpr (DT == DT_FP8) {
+            float s = scales[r];
+            ok &= (__float_as_uint(s) & 0x7f800000u) != 0x7f800000u;
+            acc = ((double)s * (double)s) * acc;
+        }
+        n2[r] = acc;
     }
-    if constexpr (DT == DT_FP8) {
-        float s = scales[r];
-        ok &= (__float_as_uint(s) & 0x7f800000u) != 0x7f800000u;
-        acc = ((double)s * (double)s) * acc;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
+    const unsigned long long mx = wave_max((r < rows && ok) ? bits : 0ull);
+    const unsigned long long mn = wave_min((r < rows && ok && acc > 0.0) ? bits : ~0ull);
+    const bool any_bad = ballot64(r < rows && !ok) != 0ull;
+    if (lane_id() == 0) {
+        if (mx) atomicMax(&stats[slot], mx);
+        if (mn != ~0ull) atomicMin(&stats[2], mn);
+        if (any_bad) atomicOr(&stats[3], 1ull);
     }
-    n2[r] = acc;
-    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_norm_stats_init(unsigned long long* stats)
+{
+    if (threadIdx.x < 4) stats[threadIdx.x] = threadIdx.x == 2 ? ~0ull : 0ull;
+}
+
+void launch_norm_stats_init(unsigned long long* stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norm_stats_init, dim3(1), dim3(64), 0, s, stats);
+    HIPC(hipGetLastError());
 }
 
 void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, int d, int ld,
-                  double* n2, int* bad, hipStream_t s)
+                  double* n2, unsigned long long* stats, int slot, hipStream_t s)
 {
     if (rows <= 0) return;
     dim3 g((unsigned)((rows + 255) / 256)), b(256);
-    if (dtype == DT_F32) hipLaunchKernelGGL(k_norm2<DT_F32>, g, b, 0, s, X, scales, rows, d, ld, n2, bad);
-    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_norm2<DT_BF16>, g, b, 0, s, X, scales, rows, d, ld, n2, bad);
-    else hipLaunchKernelGGL(k_norm2<DT_FP8>, g, b, 0, s, X, scales, rows, d, ld, n2, bad);
+    if (dtype == DT_F32) hipLaunchKernelGGL(k_norm2<DT_F32>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_norm2<DT_BF16>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+    else hipLaunchKernelGGL(k_norm2<DT_FP8>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
     HIPC(hipGetLastError());
 }
 

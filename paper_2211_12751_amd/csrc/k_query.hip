@@ -19,6 +19,7 @@
 // uncertainty Delta_phi is added to the cosine factor; a relative slack covers the
 // FP32 evaluation and the stored cos/sin pairs.  Pruning is only ever a strict "<".
 #include <algorithm>
+#include <utility>
 
 #include "common.h"
 #include "internal.h"
@@ -497,31 +498,191 @@ void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, 
 
 // ------------------------------------------------------------------ result lists
 // keys sorted ascending; offsets[q] = first key >= q << 32; ids = low halves.
-__global__ void k_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets)
-{
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q > nq) return;
-    const uint64_t t = (uint64_t)q << 32;
-    int64_t lo = 0, hi = count;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < t) lo = mid + 1;
-        else hi = mid;
-    }
-    offsets[q] = lo;
-}
+// ------------------------------------------------------------------ result lists
+// The result keys (caller's query index << 32 | original user id) become per-query
+// ascending id lists: a count per query, an exclusive scan into offsets, a scatter by
+// query, then one workgroup per query sorts its ids (in LDS up to QS_CHUNK ids; larger
+// lists are sorted in chunks and merged level by level afterwards).  Entries whose query
+// field is out of range are unused slots and are skipped.
+static constexpr int QS_CHUNK = 4096;
 
-__global__ void k_ids(const uint64_t* keys, int64_t count, int32_t* ids)
+__global__ void k_qcount(const uint64_t* keys, int64_t span, int64_t nq, int* cnt)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) ids[i] = (int32_t)(keys[i] & 0xffffffffull);
+    if (i >= span) return;
+    const uint64_t q = keys[i] >> 32;
+    if (q < (uint64_t)nq) atomicAdd(&cnt[q], 1);
 }
 
-void launch_offsets(const uint64_t* keys, int64_t count, int64_t nq, int64_t* offsets, int32_t* ids, hipStream_t s)
+// One workgroup: offsets[0..nq] = exclusive scan of cnt (64-bit), cnt reset to zero (it
+// becomes the scatter cursor), stat[0] = largest count.
+__global__ __launch_bounds__(1024) void k_qscan(int* cnt, int64_t nq, int64_t* offsets, long long* stat)
 {
-    hipLaunchKernelGGL(k_offsets, dim3((unsigned)((nq + 1 + 255) / 256)), dim3(256), 0, s, keys, count, nq, offsets);
-    if (count > 0)
-        hipLaunchKernelGGL(k_ids, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, keys, count, ids);
+    __shared__ long long wtot[16];
+    __shared__ long long carry_s;
+    __shared__ int maxc_s;
+    const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
+    if (tid == 0) {
+        carry_s = 0;
+        maxc_s = 0;
+    }
+    __syncthreads();
+    int mymax = 0;
+    for (int64_t c0 = 0; c0 < nq; c0 += 1024) {
+        const int64_t q = c0 + tid;
+        const int c = q < nq ? cnt[q] : 0;
+        mymax = c > mymax ? c : mymax;
+        // inclusive scan of c within the wave (64-bit)
+        long long v = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long t = __shfl_up(v, o);
+            if (l >= o) v += t;
+        }
+        if (l == 63) wtot[w] = v;
+        __syncthreads();
+        long long off = carry_s;
+        for (int i = 0; i < w; i++) off += wtot[i];
+        if (q < nq) {
+            offsets[q] = off + v - c;
+            cnt[q] = 0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            long long t = 0;
+            for (int i = 0; i < 16; i++) t += wtot[i];
+            carry_s += t;
+        }
+        __syncthreads();
+    }
+    mymax = wave_max(mymax);
+    if (l == 0) atomicMax(&maxc_s, mymax);
+    __syncthreads();
+    if (tid == 0) {
+        offsets[nq] = carry_s;
+        stat[0] = maxc_s;
+    }
+}
+
+__global__ void k_qscatter(const uint64_t* keys, int64_t span, int64_t nq, const int64_t* offsets, int* cursor,
+                           int32_t* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= span) return;
+    const uint64_t key = keys[i];
+    const uint64_t q = key >> 32;
+    if (q >= (uint64_t)nq) return;
+    out[offsets[q] + atomicAdd(&cursor[q], 1)] = (int32_t)(key & 0xffffffffull);
+}
+
+// Ascending sort of up to QS_CHUNK ids in LDS (bitonic over the next power of two,
+// padded with INT_MAX), written to dst.
+__device__ void qs_sort_chunk(const int32_t* src, int32_t* dst, int c, int32_t* sh)
+{
+    int P = 1;
+    while (P < c) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) sh[i] = i < c ? src[i] : 0x7fffffff;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const bool up = (i & k) == 0;
+                    const int32_t x = sh[i], y = sh[p];
+                    if ((x > y) == up) {
+                        sh[i] = y;
+                        sh[p] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < c; i += blockDim.x) dst[i] = sh[i];
+    __syncthreads();
+}
+
+// One workgroup per query: its ids from src sorted into dst (lists longer than
+// QS_CHUNK as sorted chunks, merged by k_qmerge).
+__global__ __launch_bounds__(256) void k_qsort(const int64_t* offsets, const int32_t* src, int32_t* dst)
+{
+    __shared__ int32_t sh[QS_CHUNK];
+    const int64_t q = blockIdx.x;
+    const int64_t b = offsets[q], c = offsets[q + 1] - b;
+    for (int64_t c0 = 0; c0 < c; c0 += QS_CHUNK) {
+        const int len = (int)(c - c0 < QS_CHUNK ? c - c0 : QS_CHUNK);
+        qs_sort_chunk(src + b + c0, dst + b + c0, len, sh);
+    }
+}
+
+// One merge level for the lists longer than `run`: sorted runs of length `run` in src
+// become runs of 2 run in dst (a list not longer than 2 run is complete afterwards).
+// Each of the 256 threads merges one slice of the output, found by a binary search on
+// its diagonal (ids within a list are distinct).
+__global__ __launch_bounds__(256) void k_qmerge(const int64_t* offsets, int64_t run, const int32_t* src,
+                                                int32_t* dst)
+{
+    const int64_t q = blockIdx.x;
+    const int64_t b = offsets[q], c = offsets[q + 1] - b;
+    if (c <= QS_CHUNK) return;   // never chunked: already final in its own buffer
+    for (int64_t s0 = 0; s0 < c; s0 += 2 * run) {
+        const int64_t la = c - s0 < run ? c - s0 : run;
+        const int64_t lb = c - s0 - la < run ? c - s0 - la : run;
+        const int32_t* A = src + b + s0;
+        const int32_t* B = A + la;
+        int32_t* D = dst + b + s0;
+        const int64_t T = la + lb;
+        const int64_t d0 = T * threadIdx.x / 256, d1 = T * (threadIdx.x + 1) / 256;
+        // split of diagonal d0: i from A, d0 - i from B
+        int64_t lo = d0 > lb ? d0 - lb : 0, hi = d0 < la ? d0 : la;
+        while (lo < hi) {
+            const int64_t i = (lo + hi) >> 1;
+            if (A[i] < B[d0 - i - 1]) lo = i + 1;
+            else hi = i;
+        }
+        int64_t i = lo, j = d0 - lo;
+        for (int64_t o = d0; o < d1; o++) {
+            if (j >= lb || (i < la && A[i] < B[j])) D[o] = A[i++];
+            else D[o] = B[j++];
+        }
+    }
+}
+
+// Copies the lists longer than QS_CHUNK from src to dst (after an odd number of merges).
+__global__ __launch_bounds__(256) void k_qcopy_long(const int64_t* offsets, const int32_t* src, int32_t* dst)
+{
+    const int64_t q = blockIdx.x;
+    const int64_t b = offsets[q], c = offsets[q + 1] - b;
+    if (c <= QS_CHUNK) return;
+    for (int64_t i = threadIdx.x; i < c; i += 256) dst[b + i] = src[b + i];
+}
+
+void launch_result_lists(const uint64_t* keys, int64_t span, int64_t nq, int* cnt, int64_t* offsets,
+                         long long* stat, int32_t* tmp, int32_t* ids, hipStream_t s)
+{
+    if (nq <= 0) return;
+    HIPC(hipMemsetAsync(cnt, 0, sizeof(int) * nq, s));
+    if (span > 0)
+        hipLaunchKernelGGL(k_qcount, dim3((unsigned)((span + 255) / 256)), dim3(256), 0, s, keys, span, nq, cnt);
+    hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, s, cnt, nq, offsets, stat);
+    if (span > 0)
+        hipLaunchKernelGGL(k_qscatter, dim3((unsigned)((span + 255) / 256)), dim3(256), 0, s, keys, span, nq,
+                           (const int64_t*)offsets, cnt, tmp);
+    hipLaunchKernelGGL(k_qsort, dim3((unsigned)nq), dim3(256), 0, s, (const int64_t*)offsets, (const int32_t*)tmp, ids);
+    HIPC(hipGetLastError());
+}
+
+void launch_result_merges(int64_t nq, int64_t max_count, const int64_t* offsets, int32_t* tmp, int32_t* ids,
+                          hipStream_t s)
+{
+    if (max_count <= QS_CHUNK) return;
+    int32_t* src = ids;
+    int32_t* dst = tmp;
+    for (int64_t run = QS_CHUNK; run < max_count; run *= 2) {
+        hipLaunchKernelGGL(k_qmerge, dim3((unsigned)nq), dim3(256), 0, s, offsets, run, (const int32_t*)src, dst);
+        std::swap(src, dst);
+    }
+    if (src != ids) hipLaunchKernelGGL(k_qcopy_long, dim3((unsigned)nq), dim3(256), 0, s, offsets, (const int32_t*)src, ids);
     HIPC(hipGetLastError());
 }
 

@@ -40,8 +40,10 @@ __device__ __forceinline__ uint32_t wave_kth_key(const uint32_t (&key)[GPL], int
         for (int b = l; b < 256; b += 64) hist[b] = 0;
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int i = 0; i < GPL; i++)
+        for (int i = 0; i < GPL; i++) {
+            if (64 * i >= c) break;   // wave-uniform: the rest of the slots are empty
             if (l + 64 * i < c && (key[i] & pmask) == prefix) atomicAdd(&hist[(key[i] >> shift) & 255u], 1);
+        }
         __builtin_amdgcn_wave_barrier();
         int h[4], x = 0;
 #pragma unroll
@@ -77,7 +79,10 @@ __device__ __forceinline__ void wave_keep_positions(const uint32_t (&key)[GPL], 
     const int l = lane_id();
     int eq_before = 0, kept_before = 0;
 #pragma unroll
+    for (int i = 0; i < GPL; i++) outpos[i] = -1;
+#pragma unroll
     for (int i = 0; i < GPL; i++) {
+        if (64 * i >= c) break;
         const bool valid = l + 64 * i < c;
         const bool gt = valid && key[i] > T;
         const bool eq = valid && key[i] == T;
@@ -89,36 +94,6 @@ __device__ __forceinline__ void wave_keep_positions(const uint32_t (&key)[GPL], 
         outpos[i] = keep ? kept_before + __popcll(kb & lanemask_lt()) : -1;
         kept_before += __popcll(kb);
     }
-}
-
-// Compacts the `c` entries of a user's buffer (keys = orderable scores) to its C largest
-// (ties at the threshold kept in buffer order) and returns the C-th largest key.
-template <int GPL>
-__device__ __forceinline__ uint32_t wave_select_compact(uint2* region, int c, int C, int* hist)
-{
-    const int l = lane_id();
-    uint32_t key[GPL], id[GPL];
-#pragma unroll
-    for (int i = 0; i < GPL; i++) {
-        const int idx = l + 64 * i;
-        if (idx < c) {
-            const unsigned long long raw = __hip_atomic_load((unsigned long long*)(region + idx),
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            key[i] = (uint32_t)raw;
-            id[i] = (uint32_t)(raw >> 32);
-        } else {
-            key[i] = 0u;
-            id[i] = 0u;
-        }
-    }
-    int need_eq;
-    const uint32_t T = wave_kth_key<GPL>(key, c, C, hist, &need_eq);
-    int outpos[GPL];
-    wave_keep_positions<GPL>(key, c, T, need_eq, outpos);
-#pragma unroll
-    for (int i = 0; i < GPL; i++)
-        if (outpos[i] >= 0) region[outpos[i]] = make_uint2(key[i], id[i]);
-    return T;
 }
 
 // ------------------------------------------------------------------ fused GEMM + top-k
@@ -564,9 +539,13 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     uint32_t key[RF_GPL], id[RF_GPL];
 #pragma unroll
     for (int i = 0; i < RF_GPL; i++) {
-        const int j = l + 64 * i;
         key[i] = 0u;
         id[i] = 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < RF_GPL; i++) {
+        if (64 * i >= N) break;   // wave-uniform
+        const int j = l + 64 * i;
         if (j < N) {
             int p = 0;
 #pragma unroll
@@ -591,11 +570,13 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int i = 0; i < RF_GPL; i++)
+    for (int i = 0; i < RF_GPL; i++) {
+        if (64 * i >= N) break;
         if (outpos[i] >= 0) {
             skey[w][outpos[i]] = key[i];
             sid[w][outpos[i]] = id[i];
         }
+    }
     __builtin_amdgcn_wave_barrier();
     const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
     for (int j = l; j < Nk; j += 64) {

@@ -53,7 +53,7 @@ Workspace::~Workspace()
 int64_t Workspace::bytes_for(const Index& x, int64_t nq, int64_t pool_cap, int64_t amb_cap)
 {
     const int64_t eb = elt_bytes(x.dtype);
-    return nq * x.ld * eb + nq * 4 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4) + amb_cap * 8 + 256 +
+    return nq * x.ld * eb + nq * 5 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4 + 4) + amb_cap * 8 + 256 +
            nq * x.nblocks * 4;
 }
 
@@ -64,7 +64,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
         HIPC(hipEventCreate(&ev1));
         HIPC(hipEventCreateWithFlags(&ev_ctr, hipEventDisableTiming));
     }
-    if (nq > nq_cap) {
+    if (nq > nq_cap || nq_cap == 0) {
         const int64_t c = std::max<int64_t>(nq, 64);
         qpad.alloc((size_t)c * x.ld * elt_bytes(x.dtype));
         if (x.dtype == RKMIPS_FP8_E4M3) qsc.alloc(sizeof(float) * c);
@@ -74,6 +74,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
         qk.alloc(sizeof(int) * c);
         h_qk.alloc(sizeof(int) * c);
         offsets.alloc(sizeof(int64_t) * (c + 1));
+        qcnt.alloc(sizeof(int) * c);
         h_qslot.alloc(sizeof(int) * c);
         h_qorig.alloc(sizeof(uint32_t) * c);
         h_offsets.alloc(sizeof(int64_t) * (c + 1));
@@ -86,6 +87,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
     if (pc > pool_cap) {
         pool.alloc(sizeof(uint64_t) * pc);
         ids.alloc(sizeof(int32_t) * pc);
+        ids2.alloc(sizeof(int32_t) * pc);
         h_ids.alloc(sizeof(int32_t) * pc);
         pool_cap = pc;
     }
@@ -290,12 +292,22 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     }
     if (namb > 0) launch_recheck(a, namb, reject, s);
     const int64_t span = cnt + namb;
-    if (span > 1) sort_keys((uint64_t*)w.pool.p, span, w.pool_cap, s);
-    launch_offsets((const uint64_t*)w.pool.p, std::max<int64_t>(span, 0), nq, w.offsets.i64(), (int32_t*)w.ids.p, s);
-    HIPC(hipMemcpyAsync(w.h_offsets.p, w.offsets.p, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s));
+    long long* maxc = (long long*)((unsigned long long*)w.ctr.p + 13);
+    launch_result_lists((const uint64_t*)w.pool.p, std::max<int64_t>(span, 0), nq, w.qcnt.i(), w.offsets.i64(),
+                        maxc, (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);
+    if (nq > 0) {
+        HIPC(hipMemcpyAsync(w.h_offsets.p, w.offsets.p, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync((unsigned long long*)w.h_ctr.p + 13, maxc, sizeof(long long), hipMemcpyDeviceToHost, s));
+    }
     HIPC(hipStreamSynchronize(s));
+    if (nq == 0) ((int64_t*)w.h_offsets.p)[0] = 0;
     const int64_t* ho = (const int64_t*)w.h_offsets.p;
     const int64_t total = ho[nq];
+    if (nq > 0) {
+        // lists longer than one LDS chunk are merged now that their length is known
+        const long long mc = (long long)((const unsigned long long*)w.h_ctr.p)[13];
+        launch_result_merges(nq, mc, w.offsets.i64(), (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);
+    }
     if (total > 0) {
         HIPC(hipMemcpyAsync(w.h_ids.p, w.ids.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
     }
