@@ -157,9 +157,11 @@ def main():
     value = args.steps * w.nq / t_total
     flop_lambda = 2.0 * w.m * w.n * w.d
     ms_lambda = float(np.mean([i["ms_lambda"] for i in infos]))
+    ms_topk = float(np.mean([i["ms_topk"] for i in infos]))
     ms_build = float(np.mean([i["ms_total"] for i in infos]))
     peak = {"f32": PEAK_FP32_MFMA, "bf16": PEAK_BF16_MFMA, "fp8": PEAK_FP8_MFMA}[w.dtype]
-    achieved = flop_lambda / (ms_lambda * 1e-3) / 1e12
+    # the fused top-k kernel covers all m x n pairs in one launch per build
+    achieved = flop_lambda / (ms_topk * 1e-3) / 1e12
     q_ms = float(np.mean([s["ms_total"] for s in sts]))
 
     traffic = None
@@ -188,11 +190,12 @@ def main():
                                f"{w.nq} queries, k in {list(w.k_values)}, k_max={k_max}",
                    "n": w.n, "m": w.m, "d": w.d, "nq": w.nq, "k_max": k_max},
         "index_tflops": round(flop_lambda / (ms_build * 1e-3) / 1e12, 3),
-        "lambda_kernel_tflops": round(achieved, 3),
+        "lambda_pass_tflops": round(flop_lambda / (ms_lambda * 1e-3) / 1e12, 3),
         "query_only_qps": round(w.nq / (q_ms * 1e-3), 1),
         "batch_latency_p99_ms": round(float(np.percentile(np.array(qlat) * 1e3, 99)), 4),
         "phase_ms": {k: round(float(np.mean([i[k] for i in infos])), 4)
-                     for k in ("ms_norms", "ms_cone", "ms_lambda", "ms_refine", "ms_saalsh", "ms_total")},
+                     for k in ("ms_norms", "ms_cone", "ms_lambda", "ms_seed", "ms_topk", "ms_refine", "ms_saalsh",
+                               "ms_total")},
         "query_ms": round(q_ms, 4),
         "query_stats": {k: int(sts[-1][k]) for k in ("pairs_total", "pairs_block_pruned",
                                                       "pairs_vector_pruned", "pairs_scored",
@@ -202,8 +205,8 @@ def main():
         "max_rel_err_lambda32": infos[-1]["max_rel_err_lambda32"],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": "k_topk (fused U.P^T + streaming top-k)",
-                     "flop_per_launch": flop_lambda},
+                     "kernel": "k_topk main pass (fused U.P^T + streaming top-k), one launch per build",
+                     "flop_per_launch": flop_lambda, "ms_per_launch": round(ms_topk, 4)},
     }
 
     if not args.no_serving:

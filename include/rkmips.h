@@ -165,6 +165,8 @@ typedef struct {
     double max_rel_err_lambda32; /* max |lambda32 - lambda64| / |lambda64| after           */
     double ms_norms, ms_lambda, ms_refine, ms_saalsh, ms_cone, ms_total; /* device times   */
     int64_t device_bytes;        /* device memory held by the index                      */
+    double ms_seed, ms_topk;     /* lambda build: threshold seed pass and fused top-k pass
+                                    (both inside ms_lambda)                              */
 } rkmips_index_info;
 
 rkmips_status rkmips_get_info(const rkmips_index *idx, rkmips_index_info *out);

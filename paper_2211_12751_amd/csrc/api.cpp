@@ -158,7 +158,7 @@ static void build_lambda(Index& x, hipStream_t s)
     ta.users = x.users.p; ta.user_scales = x.user_scales.f(); ta.m = m;
     ta.d = x.d; ta.ld = x.ld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
     ta.buf = (uint2*)buf.p; ta.cnt = (int*)cnt.p; ta.tau = (float*)tau.p;
-    Events ev(3);
+    Events ev(4);
     HIPC(hipEventRecord(ev.ev[0], s));
     if (x.ns > 0) {   // per-user threshold estimates from the item sample
         theta.alloc(sizeof(float) * (size_t)m);
@@ -167,6 +167,7 @@ static void build_lambda(Index& x, hipStream_t s)
         a0.theta_out = theta.f();
         launch_topk_seed(x.dtype, a0, s);
     }
+    HIPC(hipEventRecord(ev.ev[3], s));
     TopkArgs a1 = ta;
     a1.v0 = 0; a1.v1 = x.n; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
     a1.theta_init = x.ns > 0 ? theta.f() : nullptr;
@@ -186,28 +187,22 @@ static void build_lambda(Index& x, hipStream_t s)
     ra.max_raw_err_bits = (unsigned long long*)errbits.p;
     ra.err_rel = fast_err_rel(x.d);
     launch_refine(x.dtype, ra, s);
-    int nfail = 0;
-    HIPC(hipMemcpyAsync(&nfail, fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    x.cert_failures = nfail;
-    if (nfail > 0) {
-        const int64_t rows = std::min<int64_t>(nfail, 256);
+    {
+        // rows whose certificate failed: full FP64 rescoring (the count stays on the
+        // device; with none the fallback workgroups exit at once)
+        const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(256e6 / (8.0 * (double)x.n))));
         DevBuf scratch;
         scratch.alloc(sizeof(double) * (size_t)rows * x.n);
-        launch_fallback(x.dtype, ra, nfail, scratch.d(), rows, s);
-        HIPC(hipStreamSynchronize(s));
+        launch_fallback(x.dtype, ra, scratch.d(), rows, s);
     }
     HIPC(hipEventRecord(ev.ev[2], s));
-    unsigned long long eb[2];
-    HIPC(hipMemcpyAsync(eb, errbits.p, sizeof eb, hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    double e0, e1;
-    std::memcpy(&e0, &eb[0], 8);
-    std::memcpy(&e1, &eb[1], 8);
-    x.max_rel_err_raw = e0;
-    x.max_rel_err_l32 = e1;
-    x.ms_lambda = ev_ms(ev.ev[0], ev.ev[1]);
-    x.ms_refine = ev_ms(ev.ev[1], ev.ev[2]);
+    // build statistics, read by the host after the build's final wait
+    x.h_lam_stats.alloc(sizeof(unsigned long long) * 4);
+    unsigned long long* hs = (unsigned long long*)x.h_lam_stats.p;
+    HIPC(hipMemcpyAsync(hs, errbits.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hs + 2, fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    x.lam_ev.assign(4, nullptr);
+    for (int i = 0; i < 4; i++) std::swap(x.lam_ev[i], ev.ev[i]);
     // keep the raw candidates for inspection (per leaf-order user)
     x.cand.swap(buf);
     x.cand_cnt.swap(cnt);
@@ -266,6 +261,17 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     build_saalsh(x, srp, s);
     HIPC(hipEventRecord(ev.ev[3], s));
     HIPC(hipStreamSynchronize(s));
+    {
+        const unsigned long long* hs = (const unsigned long long*)x.h_lam_stats.p;
+        std::memcpy(&x.max_rel_err_raw, &hs[0], 8);
+        std::memcpy(&x.max_rel_err_l32, &hs[1], 8);
+        x.cert_failures = (int64_t)*(const int*)(hs + 2);
+        const std::vector<hipEvent_t>& le = x.lam_ev;
+        x.ms_seed = ev_ms(le[0], le[3]);
+        x.ms_topk = ev_ms(le[3], le[1]);
+        x.ms_lambda = ev_ms(le[0], le[1]);
+        x.ms_refine = ev_ms(le[1], le[2]);
+    }
     x.ms_norms = ev_ms(ev.ev[0], ev.ev[1]);
     x.ms_cone = ev_ms(ev.ev[1], ev.ev[2]);
     x.ms_total = ev_ms(ev.ev[0], ev.ev[3]);
@@ -293,6 +299,8 @@ Index::~Index()
     // every use of the index's buffers is complete: they go back to the cache as idle
     // blocks (the members are released after this body, the tail guard ends the scope)
     (void)hipDeviceSynchronize();
+    for (hipEvent_t e : lam_ev)
+        if (e) (void)hipEventDestroy(e);
     mem::idle_enter();
 }
 IdleTail::~IdleTail() { mem::idle_leave(); }
@@ -390,6 +398,7 @@ rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
         o->max_rel_err_raw = x.max_rel_err_raw; o->max_rel_err_lambda32 = x.max_rel_err_l32;
         o->ms_norms = x.ms_norms; o->ms_lambda = x.ms_lambda; o->ms_refine = x.ms_refine;
         o->ms_saalsh = x.ms_saalsh; o->ms_cone = x.ms_cone; o->ms_total = x.ms_total;
+        o->ms_seed = x.ms_seed; o->ms_topk = x.ms_topk;
         o->device_bytes = x.device_bytes();
     });
 }

@@ -33,6 +33,17 @@ struct DevBuf {
     int64_t* i64() const { return (int64_t*)p; }
 };
 
+struct PinBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    PinBuf() = default;
+    PinBuf(const PinBuf&) = delete;
+    PinBuf& operator=(const PinBuf&) = delete;
+    ~PinBuf();
+    void alloc(size_t b);
+    void reset();
+};
+
 struct Workspace;
 
 // Ends the idle-release scope that ~Index opens; declared first in Index so that it is
@@ -98,6 +109,9 @@ struct Index {
     ~Index();
 
     double ms_norms = 0, ms_lambda = 0, ms_refine = 0, ms_saalsh = 0, ms_cone = 0, ms_total = 0;
+    double ms_seed = 0, ms_topk = 0;
+    PinBuf h_lam_stats;               // lambda build statistics, read after the final wait
+    std::vector<hipEvent_t> lam_ev;   // seed / top-k / refine boundaries of the build
 
     int64_t device_bytes() const
     {

@@ -93,8 +93,7 @@ struct RefineArgs {
 };
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s);
 // Full FP64 rescoring of the users in fail_list (device count at fail_count, host copy nfail).
-void launch_fallback(int dtype, const RefineArgs& a, int64_t nfail, double* scratch,
-                     int64_t scratch_rows, hipStream_t s);
+void launch_fallback(int dtype, const RefineArgs& a, double* scratch, int64_t scratch_rows, hipStream_t s);
 
 // ---------------------------------------------------------------- cone tree
 struct ConeLevelArgs {

@@ -649,9 +649,9 @@ void launch_refine(int dtype, const RefineArgs& a, hipStream_t s)
 
 // ------------------------------------------------------------------ full FP64 fallback
 template <int DT>
-__global__ __launch_bounds__(256) void k_fallback(RefineArgs a, int64_t nfail, double* scratch,
-                                                  int64_t scratch_rows)
+__global__ __launch_bounds__(256) void k_fallback(RefineArgs a, double* scratch, int64_t scratch_rows)
 {
+    const int64_t nfail = *a.fail_count;   // written by k_refine earlier on the stream
     __shared__ int hist[256];
     __shared__ int s_sel, s_above;
     __shared__ double top[256];
@@ -714,14 +714,13 @@ __global__ __launch_bounds__(256) void k_fallback(RefineArgs a, int64_t nfail, d
     }
 }
 
-void launch_fallback(int dtype, const RefineArgs& a, int64_t nfail, double* scratch, int64_t scratch_rows,
-                     hipStream_t s)
+void launch_fallback(int dtype, const RefineArgs& a, double* scratch, int64_t scratch_rows, hipStream_t s)
 {
-    if (nfail <= 0) return;
-    const unsigned g = (unsigned)(nfail < scratch_rows ? nfail : scratch_rows);
-    if (dtype == DT_F32) hipLaunchKernelGGL(k_fallback<DT_F32>, dim3(g), dim3(256), 0, s, a, nfail, scratch, scratch_rows);
-    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_fallback<DT_BF16>, dim3(g), dim3(256), 0, s, a, nfail, scratch, scratch_rows);
-    else hipLaunchKernelGGL(k_fallback<DT_FP8>, dim3(g), dim3(256), 0, s, a, nfail, scratch, scratch_rows);
+    // one workgroup per scratch row; each takes the failed users in turn (none: no work)
+    const unsigned g = (unsigned)scratch_rows;
+    if (dtype == DT_F32) hipLaunchKernelGGL(k_fallback<DT_F32>, dim3(g), dim3(256), 0, s, a, scratch, scratch_rows);
+    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_fallback<DT_BF16>, dim3(g), dim3(256), 0, s, a, scratch, scratch_rows);
+    else hipLaunchKernelGGL(k_fallback<DT_FP8>, dim3(g), dim3(256), 0, s, a, scratch, scratch_rows);
     HIPC(hipGetLastError());
 }
 

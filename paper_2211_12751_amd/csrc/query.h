@@ -11,16 +11,6 @@
 
 namespace rk {
 
-struct PinBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    PinBuf() = default;
-    PinBuf(const PinBuf&) = delete;
-    PinBuf& operator=(const PinBuf&) = delete;
-    ~PinBuf();
-    void alloc(size_t b);
-    void reset();
-};
 
 // A run of queries (in k order) sharing one table of at most 8 distinct k values.
 struct Group {

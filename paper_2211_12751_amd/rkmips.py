@@ -52,7 +52,8 @@ class rkmips_index_info(C.Structure):
                 ("cert_failures", C.c_int64), ("max_rel_err_raw", C.c_double),
                 ("max_rel_err_lambda32", C.c_double), ("ms_norms", C.c_double),
                 ("ms_lambda", C.c_double), ("ms_refine", C.c_double), ("ms_saalsh", C.c_double),
-                ("ms_cone", C.c_double), ("ms_total", C.c_double), ("device_bytes", C.c_int64)]
+                ("ms_cone", C.c_double), ("ms_total", C.c_double), ("device_bytes", C.c_int64),
+                ("ms_seed", C.c_double), ("ms_topk", C.c_double)]
 
 
 class rkmips_serve_params(C.Structure):
