@@ -122,13 +122,28 @@ static void choose_topk(Index& x)
     if (gpl > 16) fail(RKMIPS_EINVAL, "internal: candidate buffer too large");
     const int upb = topk_users_per_block(x.dtype, x.ld);
     const int64_t tiles = (x.m + upb - 1) / upb;
-    // item segments (grid.y) when there are few user tiles: about three rounds of
-    // two resident workgroups per compute unit keep the tail of the grid short
-    int nmain = (int)std::max<int64_t>(1, (1536 + tiles - 1) / tiles);
-    nmain = (int)std::min<int64_t>(nmain, std::max<int64_t>(1, x.n / 1024));
     // the buffers stay within a fixed share of the device memory
-    while (gpl > 2 && gpl * 16 >= C + 16 && (double)x.m * nmain * gpl * 64 * 8 > 24e9) gpl /= 2;
-    nmain = std::min(nmain, std::max(1, 2048 / (gpl * 64)));   // the refine gathers at most 2048
+    while (gpl > 2 && gpl * 16 >= C + 16 && (double)x.m * gpl * 64 * 8 > 24e9) gpl /= 2;
+    // Item segments (grid.y): the grid runs in rounds of the resident workgroups, so the
+    // segment count is the one that fills its last round best (fewer on near ties).
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x.device) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    const int64_t slots = (int64_t)cus * topk_resident_blocks(x.dtype, x.ld, gpl * 64);
+    int nmax = (int)std::min<int64_t>(std::max<int64_t>(1, x.n / 1024), std::max(1, 2048 / (gpl * 64)));
+    while (nmax > 1 && (double)x.m * nmax * gpl * 64 * 8 > 24e9) nmax--;
+    int nmain = 1;
+    double best = 0.0;
+    for (int nm = 1; nm <= nmax; nm++) {
+        const int64_t wgs = tiles * nm;
+        const double eff = (double)wgs / (double)(((wgs + slots - 1) / slots) * slots);
+        if (eff > best + 0.02) {
+            best = eff;
+            nmain = nm;
+        }
+    }
     int64_t seg_len = (x.n + nmain - 1) / nmain;
     seg_len = std::max<int64_t>(64, (seg_len + 63) / 64 * 64);
     nmain = (int)((x.n + seg_len - 1) / seg_len);

@@ -75,6 +75,7 @@ constexpr int TK_T = 8;     // sample scores kept per lane by the seed pass
 void launch_topk(int dtype, const TopkArgs& a, hipStream_t s);
 void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s);
 int topk_users_per_block(int dtype, int ld);
+int topk_resident_blocks(int dtype, int ld, int G);
 
 struct RefineArgs {
     const void* items; const float* item_scales; int64_t n;

@@ -97,12 +97,6 @@ __device__ __forceinline__ void wave_keep_positions(const uint32_t (&key)[GPL], 
 }
 
 // ------------------------------------------------------------------ fused GEMM + top-k
-// user column blocks per wave: one, so the register budget goes to resident waves and
-// one wave's filter epilogue hides behind another's matrix-core work (with two, the
-// narrow types fall to one wave per SIMD and run slower although each LDS fragment
-// would feed two MFMAs)
-constexpr int topk_ubw(int, int) { return 1; }
-
 // Buffer compaction for the streaming pass, staged through LDS so that it needs few
 // registers (it runs rarely, and the main loop keeps its register budget for
 // occupancy): of the c0 entries at r0 and the c1 entries at r1, keep the C largest
@@ -178,6 +172,43 @@ __device__ __forceinline__ int64_t item_at(int64_t v, int64_t n, int64_t ns)
     else return v;
 }
 
+// 32 x 32 block of scores on the matrix cores: rows = the 32 items of LDS rows
+// [row0, row0 + 32) of a staged tile, columns = the wave's 32 users (register fragments).
+template <int DT, int KSTEPS, int LROW>
+__device__ __forceinline__ f32x16 mfma_block(const uint8_t* tile, int row0, const i32x4 (&bfrag)[KSTEPS])
+{
+    const int l = lane_id(), h = l >> 5;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0.f;
+    const uint8_t* arow = tile + (row0 + (l & 31)) * LROW + h * 16;
+    i32x4 af[KSTEPS];
+#pragma unroll
+    for (int t = 0; t < KSTEPS; t++) af[t] = *(const i32x4*)(arow + t * 32);
+#pragma unroll
+    for (int t = 0; t < KSTEPS; t++) {
+        if constexpr (DT == DT_F32) {
+            const f32x4 a4 = __builtin_bit_cast(f32x4, af[t]);
+            const f32x4 b4 = __builtin_bit_cast(f32x4, bfrag[t]);
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc, 0, 0, 0);
+        } else if constexpr (DT == DT_BF16) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[t]),
+                                                         __builtin_bit_cast(bf16x8, bfrag[t]), acc, 0, 0, 0);
+        } else {
+            // FP8 e4m3: 32x32x16 over 8 codes per lane and MFMA (two per fragment)
+            const i32x4 av = af[t], bv = bfrag[t];
+            const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){av[0], av[1]});
+            const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){av[2], av[3]});
+            const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bv[0], bv[1]});
+            const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bv[2], bv[3]});
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
 // Two modes over the same matrix-core pipeline.
 //  TK_MAIN: streaming top-C.  A score enters the user's candidate buffer only if it
 //    beats the user's register threshold (seeded per user); a full buffer is compacted to
@@ -188,19 +219,27 @@ __device__ __forceinline__ int64_t item_at(int64_t v, int64_t n, int64_t ns)
 //    of the sample rows in registers, and the user's estimate is the smaller of its two
 //    lanes' TK_T-th largest (at least 2*TK_T sample items reach it).  The estimate is only
 //    a starting point: the main pass and the refine certificate never rely on it.
-template <int DT, int DPT, int UBW, int GPL, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT < 256) ? 2 : 1, 8))) void k_topk(TopkArgs a)
+//
+// The item stream is cut into 32-item blocks; a wave's MFMA output for one block is
+// 32 items x the wave's 32 users (one user column per lane).  Item tiles of TK_IT rows
+// are double-buffered in LDS with one barrier per tile; the next tile waits in
+// registers meanwhile.  The epilogue of block b (threshold compares and appends, or
+// the register top-T of the seed pass) runs before block b + 1 is accumulated: the
+// other resident waves keep the matrix cores busy meanwhile.
+template <int DT, int DPT, int GPL, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT >= 256) ? 1 : 2, 8))) void k_topk(TopkArgs a)
 {
     constexpr int EB = Elt<DT>::bytes;
     constexpr int ROWB = DPT * EB;                // bytes of one stored row
     constexpr int LROW = ROWB + 16;               // padded LDS row (bank spread)
     constexpr int KSTEPS = ROWB / 32;             // 16-byte fragments per half row
-    constexpr int CHUNKS = TK_IT * (ROWB / 16);   // 16-byte chunks per tile
+    constexpr int IT = ROWB >= 1024 ? 32 : TK_IT; // items per tile
+    constexpr int BPT = IT / 32;                  // MFMA blocks per tile
+    constexpr int CHUNKS = IT * (ROWB / 16);      // 16-byte chunks per tile
     constexpr int PF = (CHUNKS + 255) / 256;      // chunks per thread
-    constexpr bool PREFETCH = PF <= 4;
     constexpr int SGPL = MODE == TK_MAIN ? GPL : 1;
-    __shared__ __attribute__((aligned(16))) uint8_t tile[TK_IT * LROW];
-    __shared__ float tscale[TK_IT];
+    __shared__ __attribute__((aligned(16))) uint8_t tile[2][IT * LROW];
+    __shared__ float tscale[3][DT == DT_FP8 ? IT : 1];
     __shared__ int hist_all[TK_WAVES][MODE == TK_MAIN ? 256 : 1];
     __shared__ uint2 stage_all[TK_WAVES][SGPL * 64];
 
@@ -214,214 +253,216 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     const int64_t seg0 = a.v0 + (int64_t)segl * a.seg_len;
     int64_t seg1 = seg0 + a.seg_len;
     if (seg1 > a.v1) seg1 = a.v1;
-    const int64_t user0 = (int64_t)blockIdx.x * (TK_WAVES * UBW * 32) + (int64_t)w * (UBW * 32);
+    const int64_t ntiles = seg1 > seg0 ? (seg1 - seg0 + IT - 1) / IT : 0;
+    const int64_t nblk = ntiles * BPT;
 
     // ---- resident user fragments (the B operand), one user column per lane
-    i32x4 bfrag[UBW][KSTEPS];
-    float theta[UBW], su[UBW];
-    float top[UBW][MODE == TK_SEED ? TK_T : 1];
-    int cnt[UBW];            // entries this lane appended to its half of the buffer
-    int64_t ug[UBW];
-    uint2* region[UBW];      // this lane's half: half h of the user's G entries
-    const int HG = a.G / 2;
-#pragma unroll
-    for (int cb = 0; cb < UBW; cb++) {
-        ug[cb] = user0 + cb * 32 + (l & 31);
-        const bool ok = ug[cb] < a.m;
-        const uint8_t* row = (const uint8_t*)a.users + (ok ? ug[cb] : 0) * ROWB;
+    const int64_t ug = (int64_t)blockIdx.x * (TK_WAVES * 32) + (int64_t)w * 32 + (l & 31);
+    const bool uok = ug < a.m;
+    i32x4 bfrag[KSTEPS];
+    {
+        const uint8_t* row = (const uint8_t*)a.users + (uok ? ug : 0) * ROWB;
 #pragma unroll
         for (int t = 0; t < KSTEPS; t++) {
             i32x4 z = {0, 0, 0, 0};
-            bfrag[cb][t] = ok ? *(const i32x4*)(row + t * 32 + h * 16) : z;
+            bfrag[t] = uok ? *(const i32x4*)(row + t * 32 + h * 16) : z;
         }
-        float th0 = -__builtin_inff();
-        if (MODE == TK_MAIN && ok && a.theta_init) th0 = a.theta_init[ug[cb] * a.theta_stride];
-        theta[cb] = ok ? th0 : __builtin_inff();   // +inf: nothing enters
-        su[cb] = (DT == DT_FP8 && ok) ? a.user_scales[ug[cb]] : 1.0f;
-        cnt[cb] = 0;
-        region[cb] = a.buf + ((ok ? ug[cb] : 0) * a.nseg_total + seg) * (int64_t)a.G + h * HG;
-#pragma unroll
-        for (int i = 0; i < (MODE == TK_SEED ? TK_T : 1); i++) top[cb][i] = -__builtin_inff();
     }
+    float theta = -__builtin_inff();
+    if (MODE == TK_MAIN && uok && a.theta_init) theta = a.theta_init[ug * a.theta_stride];
+    if (!uok) theta = __builtin_inff();   // +inf: nothing enters
+    const float su = (DT == DT_FP8 && uok) ? a.user_scales[ug] : 1.0f;
+    int cnt = 0;              // entries this lane appended to its half of the buffer
+    const int HG = a.G / 2;
+    uint2* region = a.buf + ((uok ? ug : 0) * a.nseg_total + seg) * (int64_t)a.G + h * HG;   // half h
+    float top[MODE == TK_SEED ? TK_T : 1];
+#pragma unroll
+    for (int i = 0; i < (MODE == TK_SEED ? TK_T : 1); i++) top[i] = -__builtin_inff();
 
-    auto load_chunk = [&](int64_t t0, int c) -> i32x4 {
+    // ---- item tiles: registers hold tile T + 1 while tile T is scored
+    auto load_chunk = [&](int64_t tt, int c) -> i32x4 {
         const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
-        const int64_t v = t0 + r;
+        const int64_t v = seg0 + tt * IT + r;
         i32x4 val = {0, 0, 0, 0};
         if (c < CHUNKS && v < seg1)
             val = *(const i32x4*)((const uint8_t*)a.items + item_at<MODE>(v, a.n, a.ns) * ROWB + c16 * 16);
         return val;
     };
-    i32x4 pf[PREFETCH ? PF : 1];
-    if constexpr (PREFETCH) {
+    i32x4 pf[PF];
+    auto prefetch = [&](int64_t tt) {
 #pragma unroll
-        for (int e = 0; e < PF; e++) pf[e] = load_chunk(seg0, threadIdx.x + 256 * e);
-    }
+        for (int e = 0; e < PF; e++) pf[e] = load_chunk(tt, threadIdx.x + 256 * e);
+    };
+    auto stage_tile = [&](int64_t tt) {   // registers -> LDS buffer of tile tt
+        uint8_t* dst = tile[tt & 1];
+#pragma unroll
+        for (int e = 0; e < PF; e++) {
+            const int c = threadIdx.x + 256 * e;
+            if (c < CHUNKS) *(i32x4*)(dst + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = pf[e];
+        }
+        if (DT == DT_FP8 && threadIdx.x < IT) {
+            const int64_t v = seg0 + tt * IT + threadIdx.x;
+            tscale[tt % 3][threadIdx.x] = v < seg1 ? a.item_scales[item_at<MODE>(v, a.n, a.ns)] : 0.f;
+        }
+    };
 
-    for (int64_t t0 = seg0; t0 < seg1; t0 += TK_IT) {
-        // ---- stage the item tile (prefetched into registers during the previous tile)
+    // scores of block b as they enter the epilogue (FP8 scaled, rows past the end -inf)
+    auto scores = [&](const f32x16& acc, int64_t b, float (&v)[16]) {
+        const int64_t tt = b / BPT;
+        const int rb = (int)(b % BPT);
+        const int64_t base = seg0 + tt * IT + rb * 32;
+        const bool tail = base + 32 > seg1;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int row = mfma32_row(r, l);
+            float x = acc[r];
+            if constexpr (DT == DT_FP8) x = (su * tscale[tt % 3][rb * 32 + row]) * x;
+            if (tail && base + row >= seg1) x = -__builtin_inff();
+            v[r] = x;
+        }
+    };
+    // branch-free part of the epilogue: the register top-T of the seed pass
+    auto early = [&](const float (&v)[16]) -> uint32_t {
+        uint32_t pm = 0u;
+        if constexpr (MODE == TK_SEED) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                float x = v[r];
+#pragma unroll
+                for (int i = 0; i < TK_T; i++) {
+                    const float hi = fmaxf(top[i], x);
+                    x = fminf(top[i], x);
+                    top[i] = hi;
+                }
+            }
+        }
+        return pm;
+    };
+    // appends of block b (main pass)
+    auto late = [&](const float (&v)[16], uint32_t, int64_t b) {
+        if constexpr (MODE == TK_MAIN) {
+            // compaction of the users whose half-buffer could overflow in this block (a lane
+            // appends at most 16 entries per block)
+            const uint64_t need = ballot64(cnt + 16 > HG);
+            if (need) {
+                uint32_t um = (uint32_t)need | (uint32_t)(need >> 32);
+                while (um) {
+                    const int ul = __builtin_ctz(um);
+                    um &= um - 1;
+                    const int c0 = __shfl(cnt, ul), c1 = __shfl(cnt, ul + 32);
+                    const int64_t ugl = __shfl(ug, ul);
+                    uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
+                    const uint32_t T = select_user(rg, c0, rg + HG, c1, a.C, hist, stage);
+                    if ((l & 31) == ul) {
+                        theta = ord_f32(T);
+                        cnt = h ? 0 : a.C;
+                    }
+                }
+            }
+            // each lane owns its half of the user's buffer: no cross-lane counts; a row
+            // that no lane passes costs one compare and one branch
+            const uint32_t pbase = (uint32_t)(seg0 + (b / BPT) * IT + (b % BPT) * 32);
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const bool pass = v[r] > theta;
+                if (ballot64(pass)) {
+                    if (pass) {
+                        region[cnt] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)mfma32_row(r, l));
+                        cnt++;
+                    }
+                }
+            }
+        }
+    };
+
+    if (nblk > 0) {
+        prefetch(0);
+        stage_tile(0);
         __syncthreads();
-        if constexpr (PREFETCH) {
-#pragma unroll
-            for (int e = 0; e < PF; e++) {
-                const int c = threadIdx.x + 256 * e;
-                if (c < CHUNKS) *(i32x4*)(tile + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = pf[e];
-            }
-        } else {
-            for (int c = threadIdx.x; c < CHUNKS; c += 256)
-                *(i32x4*)(tile + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = load_chunk(t0, c);
-        }
-        if (DT == DT_FP8 && threadIdx.x < TK_IT) {
-            const int64_t v = t0 + threadIdx.x;
-            tscale[threadIdx.x] = v < seg1 ? a.item_scales[item_at<MODE>(v, a.n, a.ns)] : 0.f;
-        }
-        __syncthreads();
-        if constexpr (PREFETCH) {
-            if (t0 + TK_IT < seg1) {
-#pragma unroll
-                for (int e = 0; e < PF; e++) pf[e] = load_chunk(t0 + TK_IT, threadIdx.x + 256 * e);
-            }
-        }
-        const bool tail = t0 + TK_IT > seg1;   // uniform: rows past the end are not items
-
-#pragma unroll
-        for (int rb = 0; rb < TK_IT / 32; rb++) {
-            f32x16 acc[UBW];
-#pragma unroll
-            for (int cb = 0; cb < UBW; cb++)
-#pragma unroll
-                for (int r = 0; r < 16; r++) acc[cb][r] = 0.f;
-            const uint8_t* arow = tile + (rb * 32 + (l & 31)) * LROW + h * 16;
-#pragma unroll
-            for (int t = 0; t < KSTEPS; t++) {
-                const i32x4 af = *(const i32x4*)(arow + t * 32);
-                if constexpr (DT == DT_F32) {
-                    const f32x4 a4 = __builtin_bit_cast(f32x4, af);
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-#pragma unroll
-                        for (int cb = 0; cb < UBW; cb++) {
-                            const f32x4 b4 = __builtin_bit_cast(f32x4, bfrag[cb][t]);
-                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc[cb], 0, 0, 0);
-                        }
-                } else if constexpr (DT == DT_BF16) {
-                    const bf16x8 a8 = __builtin_bit_cast(bf16x8, af);
-#pragma unroll
-                    for (int cb = 0; cb < UBW; cb++)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            a8, __builtin_bit_cast(bf16x8, bfrag[cb][t]), acc[cb], 0, 0, 0);
-                } else {
-                    // FP8 e4m3: 32x32x16 over 8 codes per lane and MFMA (two per fragment)
-                    const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[0], af[1]});
-                    const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[2], af[3]});
-#pragma unroll
-                    for (int cb = 0; cb < UBW; cb++) {
-                        const i32x4 bf = bfrag[cb][t];
-                        const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[0], bf[1]});
-                        const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[2], bf[3]});
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc[cb], 0, 0, 0);
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc[cb], 0, 0, 0);
-                    }
+        if (ntiles > 1) prefetch(1);
+        f32x16 acc = mfma_block<DT, KSTEPS, LROW>(tile[0], 0, bfrag);
+        for (int64_t b = 0; b < nblk; b++) {
+            float v[16];
+            scores(acc, b, v);
+            late(v, early(v), b);
+            if (b + 1 < nblk) {
+                const int64_t tn = (b + 1) / BPT;
+                if ((b + 1) % BPT == 0) {      // block b + 1 opens tile tn
+                    stage_tile(tn);
+                    __syncthreads();
+                    if (tn + 1 < ntiles) prefetch(tn + 1);
                 }
-            }
-
-#pragma unroll
-            for (int cb = 0; cb < UBW; cb++) {
-                float v[16];
-#pragma unroll
-                for (int r = 0; r < 16; r++) {
-                    const int row = rb * 32 + mfma32_row(r, l);
-                    float x = acc[cb][r];
-                    if constexpr (DT == DT_FP8) x = (su[cb] * tscale[row]) * x;
-                    if (tail && t0 + row >= seg1) x = -__builtin_inff();
-                    v[r] = x;
-                }
-                if constexpr (MODE == TK_SEED) {
-                    // keep the TK_T largest per lane: one compare-exchange pass per score
-#pragma unroll
-                    for (int r = 0; r < 16; r++) {
-                        float x = v[r];
-#pragma unroll
-                        for (int i = 0; i < TK_T; i++) {
-                            const float hi = fmaxf(top[cb][i], x);
-                            x = fminf(top[cb][i], x);
-                            top[cb][i] = hi;
-                        }
-                    }
-                } else {
-                    // ---- compaction of the users whose half-buffer could overflow in this
-                    // block (a lane appends at most 16 entries per block)
-                    const uint64_t need = ballot64(cnt[cb] + 16 > HG);
-                    if (need) {
-                        uint32_t um = (uint32_t)need | (uint32_t)(need >> 32);
-                        while (um) {
-                            const int ul = __builtin_ctz(um);
-                            um &= um - 1;
-                            const int c0 = __shfl(cnt[cb], ul), c1 = __shfl(cnt[cb], ul + 32);
-                            const int64_t ugl = __shfl(ug[cb], ul);
-                            uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
-                            const uint32_t T = select_user(rg, c0, rg + HG, c1, a.C, hist, stage);
-                            if ((l & 31) == ul) {
-                                theta[cb] = ord_f32(T);
-                                cnt[cb] = h ? 0 : a.C;
-                            }
-                        }
-                    }
-                    // ---- threshold filter and append, one row at a time: each lane owns
-                    // its half of the user's buffer, so appends need no cross-lane counts,
-                    // and a row that no lane passes costs one compare and one branch
-                    const uint32_t pbase = (uint32_t)(t0 + rb * 32);
-#pragma unroll
-                    for (int r = 0; r < 16; r++) {
-                        const bool pass = v[r] > theta[cb];
-                        if (ballot64(pass)) {
-                            if (pass) {
-                                region[cb][cnt[cb]] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)mfma32_row(r, l));
-                                cnt[cb]++;
-                            }
-                        }
-                    }
-                }
+                acc = mfma_block<DT, KSTEPS, LROW>(tile[tn & 1], (int)((b + 1) % BPT) * 32, bfrag);
             }
         }
     }
 
     if constexpr (MODE == TK_SEED) {
-#pragma unroll
-        for (int cb = 0; cb < UBW; cb++) {
-            const float mine = top[cb][TK_T - 1];
-            const float other = __shfl_xor(mine, 32);
-            if (l < 32 && ug[cb] < a.m) a.theta_out[ug[cb]] = fminf(mine, other);
-        }
+        const float mine = top[TK_T - 1];
+        const float other = __shfl_xor(mine, 32);
+        if (l < 32 && uok) a.theta_out[ug] = fminf(mine, other);
     } else {
-        // ---- outputs: the buffer may hold up to G entries; the refine pass selects
-#pragma unroll
-        for (int cb = 0; cb < UBW; cb++)
-            if (ug[cb] < a.m) {
-                a.cnt[(ug[cb] * a.nseg_total + seg) * 2 + h] = cnt[cb];
-                if (h == 0) a.tau[ug[cb] * a.nseg_total + seg] = theta[cb];
-            }
+        // the buffer halves may hold up to G entries together; the refine pass selects
+        if (uok) {
+            a.cnt[(ug * a.nseg_total + seg) * 2 + h] = cnt;
+            if (h == 0) a.tau[ug * a.nseg_total + seg] = theta;
+        }
     }
 }
 
 template <int DT, int DPT, int MODE>
 static void topk_dispatch_g(const TopkArgs& a, hipStream_t s)
 {
-    constexpr int UBW = topk_ubw(DT, DPT);
-    dim3 grid((unsigned)((a.m + TK_WAVES * UBW * 32 - 1) / (TK_WAVES * UBW * 32)), (unsigned)a.nseg);
+    dim3 grid((unsigned)((a.m + TK_WAVES * 32 - 1) / (TK_WAVES * 32)), (unsigned)a.nseg);
     if constexpr (MODE == TK_SEED) {
-        hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 1, TK_SEED>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_topk<DT, DPT, 1, TK_SEED>), grid, dim3(256), 0, s, a);
     } else {
         const int gpl = a.G / 64;
-        if (gpl == 2) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 2, TK_MAIN>), grid, dim3(256), 0, s, a);
-        else if (gpl == 4) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 4, TK_MAIN>), grid, dim3(256), 0, s, a);
-        else if (gpl == 8) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 8, TK_MAIN>), grid, dim3(256), 0, s, a);
-        else if (gpl == 16) hipLaunchKernelGGL((k_topk<DT, DPT, UBW, 16, TK_MAIN>), grid, dim3(256), 0, s, a);
+        if (gpl == 2) hipLaunchKernelGGL((k_topk<DT, DPT, 2, TK_MAIN>), grid, dim3(256), 0, s, a);
+        else if (gpl == 4) hipLaunchKernelGGL((k_topk<DT, DPT, 4, TK_MAIN>), grid, dim3(256), 0, s, a);
+        else if (gpl == 8) hipLaunchKernelGGL((k_topk<DT, DPT, 8, TK_MAIN>), grid, dim3(256), 0, s, a);
+        else if (gpl == 16) hipLaunchKernelGGL((k_topk<DT, DPT, 16, TK_MAIN>), grid, dim3(256), 0, s, a);
         else fail(RKMIPS_EINVAL, "internal: unsupported candidate buffer size");
     }
 }
 
-int topk_users_per_block(int dtype, int ld) { return TK_WAVES * topk_ubw(dtype, ld) * 32; }
+int topk_users_per_block(int, int) { return TK_WAVES * 32; }
+
+// Workgroups of the main pass that one compute unit holds at once (registers and LDS).
+template <int DT, int DPT>
+static int resident_g(int G)
+{
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    const int gpl = G / 64;
+    if (gpl == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 2, TK_MAIN>, 256, 0);
+    else if (gpl == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 4, TK_MAIN>, 256, 0);
+    else if (gpl == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 8, TK_MAIN>, 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 16, TK_MAIN>, 256, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+template <int DT>
+static int resident_d(int ld, int G)
+{
+    switch (ld) {
+    case 32: return resident_g<DT, 32>(G);
+    case 64: return resident_g<DT, 64>(G);
+    case 128: return resident_g<DT, 128>(G);
+    default: return resident_g<DT, 256>(G);
+    }
+}
+
+int topk_resident_blocks(int dtype, int ld, int G)
+{
+    if (dtype == DT_F32) return resident_d<DT_F32>(ld, G);
+    if (dtype == DT_BF16) return resident_d<DT_BF16>(ld, G);
+    return resident_d<DT_FP8>(ld, G);
+}
 
 template <int DT, int MODE>
 static void topk_dispatch(const TopkArgs& a, hipStream_t s)
