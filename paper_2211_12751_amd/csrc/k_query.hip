@@ -30,6 +30,52 @@ static constexpr int VF_WAVES = 4;
 static constexpr int VF_MAXB = 32;     // blocks with angle data per workgroup
 static constexpr int VF_MAXSLOT = 8;   // distinct k values per launch
 
+// <u, q> for the wave's 32 users (register fragments) and the 32 queries of the tile.
+template <int DT, int KSTEPS, int LROW>
+__device__ __forceinline__ f32x16 verify_block(const uint8_t* qt, const i32x4 (&bfrag)[KSTEPS])
+{
+    const int l = lane_id(), h = l >> 5;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0.f;
+    const uint8_t* arow = qt + (l & 31) * LROW + h * 16;
+#pragma unroll
+    for (int t = 0; t < KSTEPS; t++) {
+        const i32x4 af = *(const i32x4*)(arow + t * 32);
+        if constexpr (DT == DT_F32) {
+            const f32x4 a4 = __builtin_bit_cast(f32x4, af);
+            const f32x4 b4 = __builtin_bit_cast(f32x4, bfrag[t]);
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc, 0, 0, 0);
+        } else if constexpr (DT == DT_BF16) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af),
+                                                         __builtin_bit_cast(bf16x8, bfrag[t]), acc, 0, 0, 0);
+        } else {
+            const i32x4 bf = bfrag[t];
+            const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[0], af[1]});
+            const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[2], af[3]});
+            const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[0], bf[1]});
+            const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[2], bf[3]});
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+// Inner-product test of one pair: x against lambda with the fast-path error bound
+// (relative to ||u|| ||q||): yes beyond +e, no below -e, otherwise a close call for the
+// FP64 recheck.
+__device__ __forceinline__ void decide(float x, float lam, float uq, bool force, int r, const QueryArgs& a,
+                                       uint32_t& yes, uint32_t& amb)
+{
+    if (lam == -__builtin_inff()) { yes |= 1u << r; return; }
+    const float e = (float)a.err_rel * uq + fabsf(lam) * 0x1p-23f + (float)a.d * 0x1p-120f;
+    const float diff = x - lam;
+    if (force || !(diff > e || diff < -e)) amb |= 1u << r;
+    else if (diff > e) yes |= 1u << r;
+}
+
 template <int DT, int DPT, int UBW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT >= 256) ? 1 : 3, 8))) void k_verify(QueryArgs a, int64_t q_begin, int64_t q_end)
 {
@@ -50,6 +96,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     __shared__ int bok[VF_MAXB];
     __shared__ float blb[VF_MAXSLOT][VF_MAXB];
     __shared__ unsigned int cnt_s[2];
+    __shared__ uint32_t live_q[VF_MAXB];   // per block: queries of the tile not pruned by Lemma 2
     __shared__ unsigned long long base_s[2];
 
     const int l = lane_id(), w = threadIdx.x >> 6, h = l >> 5;
@@ -154,6 +201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
             cnt_s[0] = 0u;
             cnt_s[1] = 0u;
         }
+        if (threadIdx.x < VF_MAXB) live_q[threadIdx.x] = 0u;
         __syncthreads();
         if (qb + 32 < q_end) prefetch(qb + 32);
 
@@ -173,101 +221,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                 out = f32x4{c, s, dphi, ub < blb[qslot_s[qi]][b] ? 1.f : 0.f};
             }
             phi_s[b][qi] = out;
+            if (out[3] != 1.f && qb + qi < q_end) atomicOr(&live_q[b], 1u << qi);
         }
         __syncthreads();
 
-        // per-lane survival masks
-        uint32_t live[UBW];
-        bool any = false;
-#pragma unroll
-        for (int cb = 0; cb < UBW; cb++) {
-            uint32_t lm = 0u;
+        uint32_t yes = 0u, amb = 0u;
+        const int ul = ul_[0];
+        const int blk = bl[0];
+        if constexpr (DT == DT_F32) {
+            // FP32: the bounds first, so a 32 x 32 tile whose pairs are all pruned skips its
+            // (comparatively costly) matrix-core work
+            uint32_t live = 0u;
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int qi = mfma32_row(r, l);
-                if (!uok[cb] || qb + qi >= q_end) continue;
-                const f32x4 ph = bl[cb] < VF_MAXB ? phi_s[bl[cb]][qi] : f32x4{1.f, 0.f, 0.f, 2.f};
+                if (!uok[0] || qb + qi >= q_end) continue;
+                const f32x4 ph = blk < VF_MAXB ? phi_s[blk][qi] : f32x4{1.f, 0.f, 0.f, 2.f};
                 if (ph[3] == 1.f) { n_node++; continue; }
                 if (use_vec && ph[3] == 0.f) {
-                    const float lam = lam_s[qslot_s[qi]][ul_[cb]];
-                    const float ubv = qn_s[qi] * un[cb] * (ph[0] * ct[cb] + ph[1] * st[cb] + ph[2] + a.bound_slack);
+                    const float lam = lam_s[qslot_s[qi]][ul];
+                    const float ubv = qn_s[qi] * un[0] * (ph[0] * ct[0] + ph[1] * st[0] + ph[2] + a.bound_slack);
                     if (ubv < lam - fabsf(lam) * 0x1p-22f) { n_vec++; continue; }
                 }
-                lm |= 1u << r;
+                live |= 1u << r;
             }
-            live[cb] = lm;
-            any |= lm != 0u;
-        }
-
-        uint32_t yes[UBW], amb[UBW];
-#pragma unroll
-        for (int cb = 0; cb < UBW; cb++) {
-            yes[cb] = 0u;
-            amb[cb] = 0u;
-        }
-        if (ballot64(any)) {
-            f32x16 acc[UBW];
-#pragma unroll
-            for (int cb = 0; cb < UBW; cb++)
-#pragma unroll
-                for (int r = 0; r < 16; r++) acc[cb][r] = 0.f;
-            const uint8_t* arow = qt + (l & 31) * LROW + h * 16;
-#pragma unroll
-            for (int t = 0; t < KSTEPS; t++) {
-                const i32x4 af = *(const i32x4*)(arow + t * 32);
-                if constexpr (DT == DT_F32) {
-                    const f32x4 a4 = __builtin_bit_cast(f32x4, af);
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-#pragma unroll
-                        for (int cb = 0; cb < UBW; cb++)
-                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], __builtin_bit_cast(f32x4, bfrag[cb][t])[e], acc[cb], 0, 0, 0);
-                } else if constexpr (DT == DT_BF16) {
-                    const bf16x8 a8 = __builtin_bit_cast(bf16x8, af);
-#pragma unroll
-                    for (int cb = 0; cb < UBW; cb++)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, __builtin_bit_cast(bf16x8, bfrag[cb][t]), acc[cb], 0, 0, 0);
-                } else {
-                    const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[0], af[1]});
-                    const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[2], af[3]});
-#pragma unroll
-                    for (int cb = 0; cb < UBW; cb++) {
-                        const i32x4 bf = bfrag[cb][t];
-                        const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[0], bf[1]});
-                        const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[2], bf[3]});
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc[cb], 0, 0, 0);
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc[cb], 0, 0, 0);
-                    }
-                }
-            }
-#pragma unroll
-            for (int cb = 0; cb < UBW; cb++) {
+            if (ballot64(live != 0u)) {
+                const f32x16 acc = verify_block<DT, KSTEPS, LROW>(qt, bfrag[0]);
 #pragma unroll
                 for (int r = 0; r < 16; r++) {
-                    if (!(live[cb] & (1u << r))) continue;
+                    if (!(live & (1u << r))) continue;
                     const int qi = mfma32_row(r, l);
-                    float x = acc[cb][r];
-                    if constexpr (DT == DT_FP8) x = (su[cb] * qs_s[qi]) * x;
-                    const float lam = lam_s[qslot_s[qi]][ul_[cb]];
-                    if (lam == -__builtin_inff()) { yes[cb] |= 1u << r; continue; }
-                    const float e = (float)a.err_rel * un[cb] * qn_s[qi] + fabsf(lam) * 0x1p-23f + (float)a.d * 0x1p-120f;
-                    const float diff = x - lam;
-                    if (force || !(diff > e || diff < -e)) amb[cb] |= 1u << r;
-                    else if (diff > e) yes[cb] |= 1u << r;
+                    const float lam = lam_s[qslot_s[qi]][ul];
+                    decide(acc[r], lam, un[0] * qn_s[qi], force, r, a, yes, amb);
                 }
-                n_scored += __popc(live[cb]);
-                n_amb += __popc(amb[cb]);
+                n_scored += __popc(live);
+                n_amb += __popc(amb);
+            }
+        } else {
+            // narrow types: the matrix cores cost less than the per-pair bound, so every
+            // tile with a query the node-level test leaves alive is multiplied, and the
+            // vector-level test and the inner-product test share one pass
+            const uint32_t qlive = blk < VF_MAXB ? live_q[blk] : 0xffffffffu;
+            if (ballot64(uok[0] && qlive != 0u)) {
+                const f32x16 acc = verify_block<DT, KSTEPS, LROW>(qt, bfrag[0]);
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    const int qi = mfma32_row(r, l);
+                    if (!uok[0] || qb + qi >= q_end) continue;
+                    const f32x4 ph = blk < VF_MAXB ? phi_s[blk][qi] : f32x4{1.f, 0.f, 0.f, 2.f};
+                    if (ph[3] == 1.f) { n_node++; continue; }
+                    const float lam = lam_s[qslot_s[qi]][ul];
+                    const float qn = qn_s[qi];
+                    if (use_vec && ph[3] == 0.f) {
+                        const float ubv = qn * un[0] * (ph[0] * ct[0] + ph[1] * st[0] + ph[2] + a.bound_slack);
+                        if (ubv < lam - fabsf(lam) * 0x1p-22f) { n_vec++; continue; }
+                    }
+                    float x = acc[r];
+                    if constexpr (DT == DT_FP8) x = (su[0] * qs_s[qi]) * x;
+                    n_scored++;
+                    decide(x, lam, un[0] * qn, force, r, a, yes, amb);
+                }
+                n_amb += __popc(amb);
+            } else if (uok[0]) {
+#pragma unroll
+                for (int r = 0; r < 16; r++) n_node += qb + mfma32_row(r, l) < q_end ? 1 : 0;
             }
         }
 
         // ---- appends: wave prefix sums, one LDS reservation per wave, one global
         // reservation per workgroup and tile
-        int ny = 0, na = 0;
-#pragma unroll
-        for (int cb = 0; cb < UBW; cb++) {
-            ny += __popc(yes[cb]);
-            na += __popc(amb[cb]);
-        }
+        const int ny = __popc(yes), na = __popc(amb);
         const int iy = wave_incl_scan(ny), ia = wave_incl_scan(na);
         const int ty = __shfl(iy, 63), ta = __shfl(ia, 63);
         unsigned int wy = 0u, wa = 0u;
@@ -286,19 +309,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         if (ty | ta) {
             int64_t py = (int64_t)base_s[0] + wy + iy - ny, pa = (int64_t)base_s[1] + wa + ia - na;
 #pragma unroll
-            for (int cb = 0; cb < UBW; cb++)
-#pragma unroll
-                for (int r = 0; r < 16; r++) {
-                    const int64_t q = qb + mfma32_row(r, l);
-                    if (yes[cb] & (1u << r)) {
-                        if (py < a.pool_cap) a.pool[py] = ((unsigned long long)a.qorig[q] << 32) | ouid[cb];
-                        py++;
-                    }
-                    if (amb[cb] & (1u << r)) {
-                        if (pa < a.amb_cap) a.amb[pa] = ((unsigned long long)q << 32) | (uint32_t)(u0 + ul_[cb]);
-                        pa++;
-                    }
+            for (int r = 0; r < 16; r++) {
+                const int64_t q = qb + mfma32_row(r, l);
+                if (yes & (1u << r)) {
+                    if (py < a.pool_cap) a.pool[py] = ((unsigned long long)a.qorig[q] << 32) | ouid[0];
+                    py++;
                 }
+                if (amb & (1u << r)) {
+                    if (pa < a.amb_cap) a.amb[pa] = ((unsigned long long)q << 32) | (uint32_t)(u0 + ul_[0]);
+                    pa++;
+                }
+            }
         }
     }
     n_node = wave_sum(n_node);
