@@ -156,14 +156,15 @@ static void build_lambda(Index& x, hipStream_t s)
 {
     choose_topk(x);
     const int64_t m = x.m;
-    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits;
+    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill;
     buf.alloc(sizeof(uint2) * (size_t)m * x.nseg * x.G);
     cnt.alloc(sizeof(int) * (size_t)m * x.nseg * 2);
     tau.alloc(sizeof(float) * (size_t)m * x.nseg);
     fail_list.alloc(sizeof(int) * (size_t)m);
-    fail_count.alloc(sizeof(int));
+    fail_count.alloc(2 * sizeof(int));   // [0] certificate failures, [1] refine spills
     errbits.alloc(2 * sizeof(unsigned long long));
-    HIPC(hipMemsetAsync(fail_count.p, 0, sizeof(int), s));
+    spill.alloc(sizeof(int) * (size_t)m);
+    HIPC(hipMemsetAsync(fail_count.p, 0, 2 * sizeof(int), s));
     HIPC(hipMemsetAsync(errbits.p, 0, 2 * sizeof(unsigned long long), s));
     x.lam64.alloc(sizeof(double) * (size_t)x.prm.k_max * m);
     x.lam32.alloc(sizeof(float) * (size_t)x.prm.k_max * m);
@@ -201,6 +202,8 @@ static void build_lambda(Index& x, hipStream_t s)
     ra.fail_list = (int*)fail_list.p; ra.fail_count = (int*)fail_count.p;
     ra.max_raw_err_bits = (unsigned long long*)errbits.p;
     ra.err_rel = fast_err_rel(x.d);
+    ra.spill = spill.i();
+    ra.spill_count = (int*)fail_count.p + 1;
     launch_refine(x.dtype, ra, s);
     {
         // rows whose certificate failed: full FP64 rescoring (the count stays on the

@@ -91,6 +91,8 @@ struct RefineArgs {
     int* fail_list; int* fail_count;
     unsigned long long* max_raw_err_bits;
     double err_rel;                 // relative error bound of the fast scores
+    int* spill; int* spill_count;   // [m] users with more candidates than the narrow pass holds
+    const int* list; const int* list_count;   // users of a listed pass (null: all users)
 };
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s);
 // Full FP64 rescoring of the users in fail_list (device count at fail_count, host copy nfail).

@@ -19,6 +19,8 @@
 //   the top k_max (a seed estimate that was too high leaves fewer than k_max
 //   candidates above tau and fails it).  Users that fail get a full-row FP64
 //   rescoring (k_fallback).
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -549,21 +551,11 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double 
 // where every item outside the rescored set scored at most max(tau_s, cut) in the fast
 // arithmetic (tau_s: segment thresholds of the streaming pass; cut: the C-th best fast
 // score among all candidates when some were dropped here).
-template <int DT>
-__global__ __launch_bounds__(256) void k_refine(RefineArgs a)
+template <int DT, int GPL, bool FAST>
+__device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint32_t* sid, double* s64,
+                            float* sraw, double* lam_row, float* raw_row, int* hist)
 {
-    __shared__ uint32_t skey[4][256];
-    __shared__ uint32_t sid[4][256];
-    __shared__ double s64[4][256];
-    __shared__ float sraw[4][256];
-    __shared__ double lam_row[4][256];
-    __shared__ float raw_row[4][256];
-    __shared__ int hist_all[4][256];
-    const int l = lane_id(), w = threadIdx.x >> 6;
-    const int64_t u = (int64_t)blockIdx.x * 4 + w;
-    if (u >= a.m) return;
-    int* hist = hist_all[w];
-
+    const int l = lane_id();
     // gather every segment's buffer straight into registers (entry j = lane + 64 i)
     // part p = 2 s + h: half h of segment s's buffer
     int cum[9];
@@ -576,15 +568,19 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
         if (s < a.nseg && (p & 1) == 0) tau_max = fmaxf(tau_max, a.tau[u * a.nseg + s]);
     }
     const int N = cum[8];
+    if (N > GPL * 64) {   // more candidates than this instance holds: the wide pass takes it
+        if (l == 0) a.spill[atomicAdd(a.spill_count, 1)] = (int)u;
+        return;
+    }
     const int HG = a.G / 2;
-    uint32_t key[RF_GPL], id[RF_GPL];
+    uint32_t key[GPL], id[GPL];
 #pragma unroll
-    for (int i = 0; i < RF_GPL; i++) {
+    for (int i = 0; i < GPL; i++) {
         key[i] = 0u;
         id[i] = 0u;
     }
 #pragma unroll
-    for (int i = 0; i < RF_GPL; i++) {
+    for (int i = 0; i < GPL; i++) {
         if (64 * i >= N) break;   // wave-uniform
         const int j = l + 64 * i;
         if (j < N) {
@@ -598,65 +594,107 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     }
     float cut = -__builtin_inff();
     int Nk = N;
-    int outpos[RF_GPL];
+    int outpos[GPL];
     if (N > a.C) {
         int need_eq;
-        const uint32_t T = wave_kth_key<RF_GPL>(key, N, a.C, hist, &need_eq);
-        wave_keep_positions<RF_GPL>(key, N, T, need_eq, outpos);
+        const uint32_t T = wave_kth_key<GPL>(key, N, a.C, hist, &need_eq);
+        wave_keep_positions<GPL>(key, N, T, need_eq, outpos);
         cut = ord_f32(T);
         Nk = a.C;
     } else {
 #pragma unroll
-        for (int i = 0; i < RF_GPL; i++) outpos[i] = (l + 64 * i < N) ? l + 64 * i : -1;
+        for (int i = 0; i < GPL; i++) outpos[i] = (l + 64 * i < N) ? l + 64 * i : -1;
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int i = 0; i < RF_GPL; i++) {
+    for (int i = 0; i < GPL; i++) {
         if (64 * i >= N) break;
         if (outpos[i] >= 0) {
-            skey[w][outpos[i]] = key[i];
-            sid[w][outpos[i]] = id[i];
+            skey[outpos[i]] = key[i];
+            sid[outpos[i]] = id[i];
         }
     }
     __builtin_amdgcn_wave_barrier();
     const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
-    for (int j = l; j < Nk; j += 64) {
-        const int64_t p = sid[w][j];
-        double v = -__builtin_inf();
-        if (p < a.n) {                 // never produced by k_topk; guards the loads below
-            const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-            v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-        }
-        s64[w][j] = v;
-        sraw[w][j] = ord_f32(skey[w][j]);
-    }
-    __builtin_amdgcn_wave_barrier();
-    for (int j = l; j < Nk; j += 64) {
-        const double x = s64[w][j];
-        const float y = sraw[w][j];
-        int r64 = 0, rr = 0;
-        for (int i = 0; i < Nk; i++) {
-            const double xi = s64[w][i];
-            const float yi = sraw[w][i];
-            r64 += (xi > x) || (xi == x && i < j);
-            rr += (yi > y) || (yi == y && i < j);
-        }
-        if (r64 < a.k_max) lam_row[w][r64] = x;
-        if (rr < a.k_max) raw_row[w][rr] = y;
-    }
-    __builtin_amdgcn_wave_barrier();
     const double un = sqrt(a.user_n2[u]);
     const double M = sqrt(a.item_n2_sorted[0]);
     double worst_raw = 0.0, worst32 = 0.0;
-    for (int r = l; r < a.k_max; r += 64) {
-        const double lv = r < Nk ? lam_row[w][r] : -__builtin_inf();
-        const float l32 = (float)lv;
-        a.lam64[(int64_t)r * a.m + u] = lv;
-        a.lam32[(int64_t)r * a.m + u] = l32;
-        if (r < Nk && lv != 0.0 && fabs(lv) >= 1e-3 * un * M) {
-            worst_raw = fmax(worst_raw, fabs((double)raw_row[w][r] - lv) / fabs(lv));
-            worst32 = fmax(worst32, fabs((double)l32 - lv) / fabs(lv));
+    double lk = -__builtin_inf();   // lambda64^(k_max) over the candidates (-inf with fewer)
+    auto stat = [&](double lv, float raw) {
+        if (lv != 0.0 && lv > -__builtin_inf() && fabs(lv) >= 1e-3 * un * M) {
+            worst_raw = fmax(worst_raw, fabs((double)raw - lv) / fabs(lv));
+            worst32 = fmax(worst32, fabs((double)(float)lv - lv) / fabs(lv));
         }
+    };
+    if (FAST || Nk <= 64) {
+        // one candidate per lane; the ranks come from two bitonic sorts across the wave
+        double v = -__builtin_inf();
+        uint32_t rk = 0u;   // orderable fast-score key (0 sorts below every score)
+        int idx = l;
+        if (l < Nk) {
+            const int64_t p = sid[l];
+            if (p < a.n) {   // never produced by k_topk; guards the loads below
+                const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
+                v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
+            }
+            rk = skey[l];
+        }
+#pragma unroll
+        for (int kk = 2; kk <= 64; kk <<= 1)
+#pragma unroll
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                const double ov = __shfl_xor(v, j);
+                const int oi = __shfl_xor(idx, j);
+                const uint32_t ok = __shfl_xor(rk, j);
+                const bool lower = (l & j) == 0, desc = (l & kk) == 0;
+                const bool mine_first = v > ov || (v == ov && idx < oi);
+                if (mine_first != (lower == desc)) {
+                    v = ov;
+                    idx = oi;
+                }
+                if ((rk > ok) != (lower == desc) && rk != ok) rk = ok;
+            }
+        // lane r: the r-th largest canonical score and the r-th largest fast score
+        for (int r = l; r < a.k_max; r += 64) {
+            const double lv = r == l ? v : -__builtin_inf();
+            a.lam64[(int64_t)r * a.m + u] = lv;
+            a.lam32[(int64_t)r * a.m + u] = (float)lv;
+            if (r == l && l < Nk) stat(lv, ord_f32(rk));
+        }
+        lk = a.k_max <= 64 ? __shfl(v, a.k_max - 1) : -__builtin_inf();
+    } else if constexpr (!FAST) {
+        for (int j = l; j < Nk; j += 64) {
+            const int64_t p = sid[j];
+            double v = -__builtin_inf();
+            if (p < a.n) {
+                const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
+                v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
+            }
+            s64[j] = v;
+            sraw[j] = ord_f32(skey[j]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int j = l; j < Nk; j += 64) {
+            const double x = s64[j];
+            const float y = sraw[j];
+            int r64 = 0, rr = 0;
+            for (int i = 0; i < Nk; i++) {
+                const double xi = s64[i];
+                const float yi = sraw[i];
+                r64 += (xi > x) || (xi == x && i < j);
+                rr += (yi > y) || (yi == y && i < j);
+            }
+            if (r64 < a.k_max) lam_row[r64] = x;
+            if (rr < a.k_max) raw_row[rr] = y;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int r = l; r < a.k_max; r += 64) {
+            const double lv = r < Nk ? lam_row[r] : -__builtin_inf();
+            a.lam64[(int64_t)r * a.m + u] = lv;
+            a.lam32[(int64_t)r * a.m + u] = (float)lv;
+            if (r < Nk) stat(lv, raw_row[r]);
+        }
+        lk = Nk >= a.k_max ? lam_row[a.k_max - 1] : -__builtin_inf();
     }
     worst_raw = wave_max(worst_raw);
     worst32 = wave_max(worst32);
@@ -667,7 +705,6 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     bool ok = !a.force_fail;
     const float worst_out = fmaxf(tau_max, cut);
     if (ok && worst_out > -__builtin_inff()) {
-        const double lk = Nk >= a.k_max ? lam_row[w][a.k_max - 1] : -__builtin_inf();
         const double bound = (double)worst_out + a.err_rel * un * M + (double)a.d * 0x1p-125 * (un + M + 1.0);
         ok = bound <= lk;
     }
@@ -677,14 +714,61 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     }
 }
 
+
+// One wave per user (all users, or the users listed in a.list when it is given).  The
+// narrow instance (GPL = 8, C <= 64) keeps its state small for occupancy and hands
+// users with more than 512 candidates to the wide instance through a.spill.
+template <int DT, int GPL, bool FAST>
+__global__ __launch_bounds__(256) void k_refine(RefineArgs a)
+{
+    __shared__ uint32_t skey[4][FAST ? 64 : 256];
+    __shared__ uint32_t sid[4][FAST ? 64 : 256];
+    __shared__ double s64[4][FAST ? 1 : 256];
+    __shared__ float sraw[4][FAST ? 1 : 256];
+    __shared__ double lam_row[4][FAST ? 1 : 256];
+    __shared__ float raw_row[4][FAST ? 1 : 256];
+    __shared__ int hist_all[4][256];
+    const int w = threadIdx.x >> 6;
+    if (!a.list) {
+        const int64_t u = (int64_t)blockIdx.x * 4 + w;
+        if (u < a.m)
+            refine_user<DT, GPL, FAST>(a, u, skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w], hist_all[w]);
+    } else {
+        const int cnt = *a.list_count;
+        for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < cnt; i += (int64_t)gridDim.x * 4)
+            refine_user<DT, GPL, FAST>(a, a.list[i], skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w],
+                                       hist_all[w]);
+    }
+}
+
+template <int DT>
+static void refine_d(const RefineArgs& a, hipStream_t s)
+{
+    if (a.C <= 64) {
+        RefineArgs a0 = a;
+        a0.list = nullptr;
+        hipLaunchKernelGGL((k_refine<DT, 8, true>), dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a0);
+        if ((int64_t)a.nseg * a.G <= 8 * 64) return;   // no user can hold more than 512
+        RefineArgs a1 = a;
+        a1.list = a.spill;
+        a1.list_count = a.spill_count;
+        a1.spill = nullptr;   // the wide instance never spills
+        const unsigned g = (unsigned)std::min<int64_t>((a.m + 3) / 4, 1024);
+        hipLaunchKernelGGL((k_refine<DT, RF_GPL, false>), dim3(g), dim3(256), 0, s, a1);
+    } else {
+        RefineArgs a0 = a;
+        a0.list = nullptr;
+        hipLaunchKernelGGL((k_refine<DT, RF_GPL, false>), dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a0);
+    }
+}
+
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s)
 {
     if (a.m <= 0) return;
     if ((int64_t)a.nseg * a.G > RF_MAXN || a.C > 256) fail(RKMIPS_EINVAL, "internal: too many candidates per user");
-    dim3 g((unsigned)((a.m + 3) / 4)), b(256);
-    if (dtype == DT_F32) hipLaunchKernelGGL(k_refine<DT_F32>, g, b, 0, s, a);
-    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_refine<DT_BF16>, g, b, 0, s, a);
-    else hipLaunchKernelGGL(k_refine<DT_FP8>, g, b, 0, s, a);
+    if (dtype == DT_F32) refine_d<DT_F32>(a, s);
+    else if (dtype == DT_BF16) refine_d<DT_BF16>(a, s);
+    else refine_d<DT_FP8>(a, s);
     HIPC(hipGetLastError());
 }
 
