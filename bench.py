@@ -159,7 +159,10 @@ def main():
     ms_lambda = float(np.mean([i["ms_lambda"] for i in infos]))
     ms_topk = float(np.mean([i["ms_topk"] for i in infos]))
     ms_build = float(np.mean([i["ms_total"] for i in infos]))
-    peak = {"f32": PEAK_FP32_MFMA, "bf16": PEAK_BF16_MFMA, "fp8": PEAK_FP8_MFMA}[w.dtype]
+    # the matrix cores run the operand type the index chose (split BF16 products for FP32
+    # data: three products per coordinate, counted once in the algorithmic FLOP)
+    mma = {0: "f32", 1: "bf16", 2: "fp8"}[int(infos[-1]["mma_dtype"])]
+    peak = {"f32": PEAK_FP32_MFMA, "bf16": PEAK_BF16_MFMA, "fp8": PEAK_FP8_MFMA}[mma]
     # the fused top-k kernel covers all m x n pairs in one launch per build
     achieved = flop_lambda / (ms_topk * 1e-3) / 1e12
     q_ms = float(np.mean([s["ms_total"] for s in sts]))
@@ -206,7 +209,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
                      "kernel": "k_topk main pass (fused U.P^T + streaming top-k), one launch per build",
-                     "flop_per_launch": flop_lambda, "ms_per_launch": round(ms_topk, 4)},
+                     "flop_per_launch": flop_lambda, "ms_per_launch": round(ms_topk, 4),
+                     "mma_dtype": mma, "mma_terms": int(infos[-1]["mma_terms"])},
     }
 
     if not args.no_serving:

@@ -66,11 +66,16 @@ enum {
     RKMIPS_FLAG_NO_CERT = 8,        /* build: treat every top-k certificate as failed, so
                                        every lambda row comes from the full FP64 rescoring  */
     RKMIPS_FLAG_NO_VECTOR_BOUND = 16, /* skip only the per-user Lemma 3 test                 */
-    RKMIPS_FLAG_SAALSH_FILTER = 32  /* run the SA-ALSH stage (Alg. 2) on the close calls
+    RKMIPS_FLAG_SAALSH_FILTER = 32, /* run the SA-ALSH stage (Alg. 2) on the close calls
                                        before the FP64 recheck; its proven "no" answers
                                        skip the recheck.  Off by default: Alg. 2 scores
                                        ceil(beta |S_j|) candidates per pair, far more work
                                        than the O(d) FP64 recheck it can save.           */
+    RKMIPS_FLAG_F32_MATRIX = 64     /* build: score FP32 data on the FP32 matrix cores.
+                                       By default FP32 rows with d <= 64 are scored as
+                                       split BF16 products (h.h + l.h + h.l, h and l the
+                                       BF16 head and tail of each value) with their own
+                                       error bound; either way the exact path decides.   */
 };
 
 typedef struct {
@@ -167,6 +172,10 @@ typedef struct {
     int64_t device_bytes;        /* device memory held by the index                      */
     double ms_seed, ms_topk;     /* lambda build: threshold seed pass and fused top-k pass
                                     (both inside ms_lambda)                              */
+    int32_t mma_dtype;           /* operand type of the lambda build's matrix cores
+                                    (RKMIPS_BF16 for split FP32 data)                    */
+    int32_t mma_terms;           /* products per stored coordinate (3 when split)       */
+    double err_fast;             /* error bound of the fast scores / (||u|| ||p||)       */
 } rkmips_index_info;
 
 rkmips_status rkmips_get_info(const rkmips_index *idx, rkmips_index_info *out);

@@ -14,6 +14,9 @@ or uint8 FP8 e4m3 codes with float32 per-row scales):
 * ``item_order``     canonical squared norms and descending order (Alg. 4 / Alg. 1)
 * ``partitions``, ``saalsh_index``, ``user_codes``, ``saalsh_decide``  (Alg. 1, 2)
 * ``rkmips``         per-query ascending user-ID lists
+* ``values``         stored rows widened to float64 (FP8: code value x row scale)
+* ``cone_block_stats``, ``block_lower_bounds``  per-block cone data of a given
+  partition of the users (Alg. 3 leaves; Lemmas 2 and 3; L^j(B) of Alg. 4)
 """
 from __future__ import annotations
 
@@ -192,3 +195,79 @@ def saalsh_decide(dtype, P, P_scales, norm2, order, part_start, item_codes, ucod
     if r < 0:
         raise MemoryError("oracle saalsh_decide")
     return r, phi.value
+
+
+def values(dtype, X, scales=None):
+    """float64 [rows x d]: the stored rows as exact real numbers (BF16 widened, FP8
+    e4m3 code value times the row's FP32 scale)."""
+    X = np.asarray(X)
+    if dtype == "f32":
+        return X.astype(np.float64)
+    if dtype == "bf16":
+        return (X.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    table = np.array([e4m3_value(c) for c in range(256)], dtype=np.float64)
+    return table[X] * np.asarray(scales, np.float64)[:, None]
+
+
+def cone_block_stats(dtype, U, U_scales, leaf_users, block_start):
+    """Cone data of the blocks of a given user partition (the leaves of Alg. 3).
+
+    The users of block B are leaf_users[block_start[B]:block_start[B+1]].  Per block the
+    centre c_B is the normalised mean of the unit user vectors (Fact 2 makes only the
+    direction of u matter); theta_u is the angle between u and c_B (the vector-level
+    bound of Lemma 3); the cone half-angle omega_B is the largest theta_u of the block
+    (the node-level bound of Lemma 2).  Returns (centre [B x d], cos_theta [m] in leaf
+    order, cos_omega [B]); a block whose mean vanishes, or that holds a zero user, gets
+    a NaN centre row and NaN angles (no cone exists)."""
+    V = values(dtype, U, U_scales)
+    leaf_users = np.asarray(leaf_users, np.int64)
+    block_start = np.asarray(block_start, np.int64)
+    nb = len(block_start) - 1
+    norms = np.sqrt(np.sum(V * V, axis=1))
+    cen = np.full((nb, V.shape[1]), np.nan)
+    cos_t = np.full(len(leaf_users), np.nan)
+    cos_w = np.full(nb, np.nan)
+    for b in range(nb):
+        idx = leaf_users[block_start[b]:block_start[b + 1]]
+        nrm = norms[idx]
+        if np.any(nrm == 0):
+            continue
+        mean = np.mean(V[idx] / nrm[:, None], axis=0)
+        mn = np.sqrt(np.sum(mean * mean))
+        if mn == 0:
+            continue
+        c = mean / mn
+        ct = (V[idx] @ c) / nrm
+        cen[b] = c
+        cos_t[block_start[b]:block_start[b + 1]] = ct
+        cos_w[b] = np.min(ct)
+    return cen, cos_t, cos_w
+
+
+def cos_to_centres(dtype, U, U_scales, leaf_users, block_start, centres):
+    """cos(theta_u) of every user (leaf order) against the given block centres."""
+    V = values(dtype, U, U_scales)
+    leaf_users = np.asarray(leaf_users, np.int64)
+    block_start = np.asarray(block_start, np.int64)
+    C_ = np.asarray(centres, np.float64)
+    out = np.empty(len(leaf_users))
+    for b in range(len(block_start) - 1):
+        idx = leaf_users[block_start[b]:block_start[b + 1]]
+        out[block_start[b]:block_start[b + 1]] = (V[idx] @ C_[b]) / np.sqrt(np.sum(V[idx] * V[idx], axis=1))
+    return out
+
+
+def block_lower_bounds(dtype, U, U_scales, lam, leaf_users, block_start):
+    """float64 [k_max x B]: L^j(B) = min over the users of B of lambda_u^(j) / ||u||
+    (Alg. 4), with lam k-major in original user order."""
+    V = values(dtype, U, U_scales)
+    norms = np.sqrt(np.sum(V * V, axis=1))
+    lam = np.asarray(lam, np.float64)
+    leaf_users = np.asarray(leaf_users, np.int64)
+    block_start = np.asarray(block_start, np.int64)
+    nb = len(block_start) - 1
+    out = np.empty((lam.shape[0], nb))
+    for b in range(nb):
+        idx = leaf_users[block_start[b]:block_start[b + 1]]
+        out[:, b] = np.min(lam[:, idx] / norms[idx][None, :], axis=1)
+    return out

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <vector>
@@ -64,6 +66,23 @@ double fast_err_rel(int d)
     return 2.0 * g + g64;
 }
 
+// Split BF16 products for FP32 storage (items [h | l | h] against users [h | h | l]):
+// the representation error of h.h + l.h + h.l against x.y is at most
+// 3 * 2^-18 (1 + 2^-9)^2 |x_i y_i| per term, plus 2^-28 ||x|| ||y|| for the parts that
+// fall below the BF16 subnormal range (non-zero norms are >= 1e-30 > 2^-100); the
+// 3d BF16 products are exact in FP32 and their accumulation adds at most
+// 2 gamma_{3d+2} times their absolute sum (<= (1 + 4 * 2^-9) sum |x_i y_i|); the FP64
+// reference adds gamma64_d.  Relative to ||x|| ||y||.
+double split_err_rel(int d)
+{
+    const double u = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53), b = std::ldexp(1.0, -9);
+    const double rep = 3.0 * std::ldexp(1.0, -18) * (1.0 + b) * (1.0 + b) + std::ldexp(1.0, -28);
+    const double n = 3.0 * d + 2.0;
+    const double g = n * u / (1.0 - n * u);
+    const double g64 = d * u64 / (1.0 - d * u64);
+    return rep + 2.0 * g * (1.0 + 4.0 * b) + g64;
+}
+
 static float ev_ms(hipEvent_t a, hipEvent_t b)
 {
     float ms = 0.f;
@@ -102,6 +121,23 @@ static void validate_params(const rkmips_params& p)
 
 // Candidate buffer geometry of the lambda pass: a seeding segment (the P largest- and P
 // smallest-norm items, processed first) and the main segments over the remaining items.
+// Compute-unit count of a device (cached: the attribute query is not free).
+static int device_cus(int dev)
+{
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    cache[dev] = cus;
+    return cus;
+}
+
 static void choose_topk(Index& x)
 {
     const int C = x.prm.k_max + x.prm.topk_slack;
@@ -120,18 +156,14 @@ static void choose_topk(Index& x)
     // C survivors sit in one half, which must still take a block's 16 appends
     while (gpl * 32 < C + 16) gpl *= 2;
     if (gpl > 16) fail(RKMIPS_EINVAL, "internal: candidate buffer too large");
-    const int upb = topk_users_per_block(x.dtype, x.ld);
+    const int upb = topk_users_per_block(x.mma_dtype, x.mma_ld);
     const int64_t tiles = (x.m + upb - 1) / upb;
     // the buffers stay within a fixed share of the device memory
     while (gpl > 2 && gpl * 16 >= C + 16 && (double)x.m * gpl * 64 * 8 > 24e9) gpl /= 2;
     // Item segments (grid.y): the grid runs in rounds of the resident workgroups, so the
     // segment count is the one that fills its last round best (fewer on near ties).
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x.device) != hipSuccess || cus < 1) {
-        (void)hipGetLastError();
-        cus = 256;
-    }
-    const int64_t slots = (int64_t)cus * topk_resident_blocks(x.dtype, x.ld, gpl * 64);
+    const int cus = x.num_cus;
+    const int64_t slots = (int64_t)cus * topk_resident_blocks(x.mma_dtype, x.mma_ld, gpl * 64);
     int nmax = (int)std::min<int64_t>(std::max<int64_t>(1, x.n / 1024), std::max(1, 2048 / (gpl * 64)));
     while (nmax > 1 && (double)x.m * nmax * gpl * 64 * 8 > 24e9) nmax--;
     int nmain = 1;
@@ -169,26 +201,38 @@ static void build_lambda(Index& x, hipStream_t s)
     x.lam64.alloc(sizeof(double) * (size_t)x.prm.k_max * m);
     x.lam32.alloc(sizeof(float) * (size_t)x.prm.k_max * m);
 
+    // matrix-core operands: the stored rows, or their split BF16 form for FP32 storage
+    DevBuf items3, users3;
+    const void* mi = x.items.p;
+    const void* mu = x.users.p;
+    if (x.mma_dtype != x.dtype) {
+        items3.alloc(sizeof(uint16_t) * (size_t)x.n * x.mma_ld);
+        users3.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
+        launch_split_bf16(x.items.f(), x.n, x.ld, (uint16_t*)items3.p, 0, s);
+        launch_split_bf16(x.users.f(), m, x.ld, (uint16_t*)users3.p, 1, s);
+        mi = items3.p;
+        mu = users3.p;
+    }
     TopkArgs ta{};
-    ta.items = x.items.p; ta.item_scales = x.item_scales.f(); ta.n = x.n;
-    ta.users = x.users.p; ta.user_scales = x.user_scales.f(); ta.m = m;
-    ta.d = x.d; ta.ld = x.ld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
+    ta.items = mi; ta.item_scales = x.item_scales.f(); ta.n = x.n;
+    ta.users = mu; ta.user_scales = x.user_scales.f(); ta.m = m;
+    ta.d = x.d; ta.ld = x.mma_ld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
     ta.buf = (uint2*)buf.p; ta.cnt = (int*)cnt.p; ta.tau = (float*)tau.p;
-    Events ev(4);
+    Events ev(6);
     HIPC(hipEventRecord(ev.ev[0], s));
     if (x.ns > 0) {   // per-user threshold estimates from the item sample
         theta.alloc(sizeof(float) * (size_t)m);
         TopkArgs a0 = ta;
         a0.ns = x.ns; a0.v0 = 0; a0.v1 = x.ns; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = x.ns;
         a0.theta_out = theta.f();
-        launch_topk_seed(x.dtype, a0, s);
+        launch_topk_seed(x.mma_dtype, a0, s);
     }
     HIPC(hipEventRecord(ev.ev[3], s));
     TopkArgs a1 = ta;
     a1.v0 = 0; a1.v1 = x.n; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
     a1.theta_init = x.ns > 0 ? theta.f() : nullptr;
     a1.theta_stride = 1;
-    launch_topk(x.dtype, a1, s);
+    launch_topk(x.mma_dtype, a1, s);
     HIPC(hipEventRecord(ev.ev[1], s));
 
     RefineArgs ra{};
@@ -201,7 +245,7 @@ static void build_lambda(Index& x, hipStream_t s)
     ra.lam64 = x.lam64.d(); ra.lam32 = x.lam32.f();
     ra.fail_list = (int*)fail_list.p; ra.fail_count = (int*)fail_count.p;
     ra.max_raw_err_bits = (unsigned long long*)errbits.p;
-    ra.err_rel = fast_err_rel(x.d);
+    ra.err_rel = x.err_fast;
     ra.spill = spill.i();
     ra.spill_count = (int*)fail_count.p + 1;
     launch_refine(x.dtype, ra, s);
@@ -232,7 +276,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
 {
     const int64_t n = x.n, m = x.m;
     const int eb = elt_bytes(x.dtype);
-    Events ev(4);
+    Events ev(6);
     HIPC(hipEventRecord(ev.ev[0], s));
     // ---- validation + canonical norms of the caller's arrays
     DevBuf nstats, n2_items_orig, n2_users_orig;
@@ -245,18 +289,20 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     launch_norm2(x.dtype, users, user_scales, m, x.d, x.d, n2_users_orig.d(), st, 1, s);
     PinBuf hst;
     hst.alloc(sizeof(unsigned long long) * 4);
+    // read at the first host wait (inside the Cone-Tree build); until then the build
+    // only runs bounded kernels whose results are discarded on a refusal
     HIPC(hipMemcpyAsync(hst.p, st, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    range_check(x, (const unsigned long long*)hst.p);
 
     // ---- item order (descending canonical norm, ties by index)
     int64_t cap = 2;
     while (cap < n) cap <<= 1;
-    DevBuf keys, vals;
+    DevBuf keys, vals, tkeys, tvals;
     keys.alloc(sizeof(uint64_t) * cap);
     vals.alloc(sizeof(uint32_t) * cap);
+    tkeys.alloc(sizeof(uint64_t) * cap);
+    tvals.alloc(sizeof(uint32_t) * cap);
     launch_norm_keys(n2_items_orig.d(), n, cap, (uint64_t*)keys.p, (uint32_t*)vals.p, s);
-    sort_pairs((uint64_t*)keys.p, (uint32_t*)vals.p, n, cap, s);
+    sort_pairs((uint64_t*)keys.p, (uint32_t*)vals.p, (uint64_t*)tkeys.p, (uint32_t*)tvals.p, n, cap, s);
     x.item_order.alloc(sizeof(uint32_t) * n);
     HIPC(hipMemcpyAsync(x.item_order.p, vals.p, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
     x.item_n2.alloc(sizeof(double) * n);
@@ -265,10 +311,15 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     if (x.dtype == RKMIPS_FP8_E4M3) x.item_scales.alloc(sizeof(float) * n);
     launch_gather_rows(x.dtype, items, x.d, item_scales, x.item_order.u32(), n, x.d, x.items.p, x.ld,
                        x.item_scales.f(), s);
+    PinBuf hnp;
+    hnp.alloc(sizeof(int));
+    start_partitions(x, (int*)hnp.p, s);
     HIPC(hipEventRecord(ev.ev[1], s));
 
     // ---- Cone-Tree over user directions; users are stored in leaf order
     build_cone(x, users, user_scales, n2_users_orig.d(), s);
+    range_check(x, (const unsigned long long*)hst.p);   // the cone build has waited for the copy
+    x.t = *(const int*)hnp.p;
     HIPC(hipEventRecord(ev.ev[2], s));
 
     // ---- exact lambda table
@@ -276,9 +327,12 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
 
     // ---- per-block quantities that need lambda (L^j(B)) and the SA-ALSH index
     finish_blocks(x, s);
+    HIPC(hipEventRecord(ev.ev[4], s));
     build_saalsh(x, srp, s);
+    HIPC(hipEventRecord(ev.ev[5], s));
     HIPC(hipEventRecord(ev.ev[3], s));
     HIPC(hipStreamSynchronize(s));
+    x.ms_saalsh = ev_ms(ev.ev[4], ev.ev[5]);
     {
         const unsigned long long* hs = (const unsigned long long*)x.h_lam_stats.p;
         std::memcpy(&x.max_rel_err_raw, &hs[0], 8);
@@ -395,7 +449,14 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
         std::unique_ptr<Index> x(new Index());
         x->n = n; x->m = m; x->d = d; x->dtype = dtype; x->prm = prm;
         x->ld = padded_dim(d, dtype);
+        // FP32 storage is scored on the BF16 matrix cores as split products where the
+        // tripled rows fit the kernels (ld <= 64), unless the caller asks for FP32 MFMA
+        const bool split = dtype == RKMIPS_F32 && x->ld <= 64 && !(prm.flags & RKMIPS_FLAG_F32_MATRIX);
+        x->mma_dtype = split ? RKMIPS_BF16 : dtype;
+        x->mma_ld = split ? 3 * x->ld : x->ld;
+        x->err_fast = split ? split_err_rel(d) : fast_err_rel(d);
         HIPC(hipGetDevice(&x->device));
+        x->num_cus = device_cus(x->device);
         mem::StreamScope scope((hipStream_t)stream);
         build_index(*x, items, item_scales, users, user_scales, srp_proj, (hipStream_t)stream);
         *out = (rkmips_index*)x.release();
@@ -417,6 +478,7 @@ rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
         o->ms_norms = x.ms_norms; o->ms_lambda = x.ms_lambda; o->ms_refine = x.ms_refine;
         o->ms_saalsh = x.ms_saalsh; o->ms_cone = x.ms_cone; o->ms_total = x.ms_total;
         o->ms_seed = x.ms_seed; o->ms_topk = x.ms_topk;
+        o->mma_dtype = x.mma_dtype; o->mma_terms = x.mma_ld / x.ld; o->err_fast = x.err_fast;
         o->device_bytes = x.device_bytes();
     });
 }

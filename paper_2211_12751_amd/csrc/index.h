@@ -56,6 +56,9 @@ struct IdleTail {
 struct Index {
     IdleTail idle_tail;
     int device = 0;
+    int mma_dtype = 0, mma_ld = 0;   // matrix-core operand type and row length of the lambda build
+    double err_fast = 0;             // error bound of its fast scores, relative to ||u|| ||p||
+    int num_cus = 256;
     int64_t n = 0, m = 0;
     int d = 0, ld = 0, dtype = 0;
     rkmips_params prm{};
@@ -76,7 +79,6 @@ struct Index {
     // blocks (Cone-Tree leaves)
     int64_t nblocks = 0;
     DevBuf block_start;          // int64 [nblocks+1]
-    std::vector<int64_t> block_start_h;
     DevBuf center;               // float [nblocks x ld] unit centres
     DevBuf cos_w, sin_w, block_ok;
     DevBuf block_lb;             // float [k_max x nblocks]
@@ -92,8 +94,8 @@ struct Index {
 
     // SA-ALSH (Alg. 1)
     int t = 0;
-    std::vector<int64_t> part_start_h;
-    DevBuf part_start;           // int64 [t+1]
+    DevBuf part_start;           // int64 [t+1] (room for n+2)
+    DevBuf num_parts;            // int: t
     DevBuf centroid;             // float [t x ld]
     DevBuf radius;               // float [t]
     DevBuf srp;                  // float [(d+1) x K]
@@ -118,7 +120,7 @@ struct Index {
         const DevBuf* all[] = {&items, &item_scales, &item_order, &item_n2, &users, &user_scales,
                                &user_perm, &user_n2, &unorm, &cos_t, &sin_t, &user_block,
                                &block_start, &center, &cos_w, &sin_w, &block_ok, &block_lb,
-                               &lam64, &lam32, &cand, &cand_cnt, &cand_tau, &part_start,
+                               &lam64, &lam32, &cand, &cand_cnt, &cand_tau, &part_start, &num_parts,
                                &centroid, &radius, &srp, &item_codes, &user_codes};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
@@ -127,10 +129,12 @@ struct Index {
 };
 
 double fast_err_rel(int d);
+double split_err_rel(int d);
 void range_check(Index& x, const unsigned long long* stats);
 void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
                 hipStream_t s);
 void finish_blocks(Index& x, hipStream_t s);
+void start_partitions(Index& x, int* h_num_parts, hipStream_t s);
 void build_saalsh(Index& x, const float* srp, hipStream_t s);
 
 }  // namespace rk

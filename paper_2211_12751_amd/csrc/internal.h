@@ -28,11 +28,15 @@ int elt_bytes(int dtype);
 void launch_norm_stats_init(unsigned long long* stats, hipStream_t s);
 void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, int d, int ld,
                   double* n2, unsigned long long* stats, int slot, hipStream_t s);
-// Sort (key, val) pairs ascending by key then val; n <= 2^31.  Scratch-free (in place,
-// arrays must have room for the next power of two, padded by the caller or here).
-void sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int64_t cap, hipStream_t s);
-// Sort uint64 keys ascending in place (cap >= next power of two of n).
-void sort_keys(uint64_t* keys, int64_t n, int64_t cap, hipStream_t s);
+// FP32 rows [rows x ld] -> BF16 rows [rows x 3 ld]: items [h | l | h] (user_layout 0),
+// users and queries [h | h | l] (user_layout 1); their BF16 dot product approximates the
+// FP32 one within split_err_rel.
+void launch_split_bf16(const float* src, int64_t rows, int ld, uint16_t* dst, int user_layout, hipStream_t s);
+// Sort (key, val) pairs ascending by key then val, n <= 2^31.  keys/vals and the
+// scratch arrays tmp_keys/tmp_vals hold cap >= n rounded up to min(2048, next power of
+// two of n) entries; the sorted pairs end in keys/vals[0, n).
+void sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals, int64_t n, int64_t cap,
+                hipStream_t s);
 // dst[r] = src[perm[r]] row copy from leading dim ld_src to ld_dst (zero padded).
 void launch_gather_rows(int dtype, const void* src, int ld_src, const float* src_scales,
                         const uint32_t* perm, int64_t rows, int d, void* dst, int ld_dst,
@@ -110,17 +114,22 @@ struct ConeLevelArgs {
     int level, leaf;           // level number (pivot draws), N0
     uint64_t seed;
     int64_t m;
-    unsigned long long* key1; unsigned long long* key2;  // [nseg]
+    const int* act;        // [nseg] active index of each segment (-1: leaf)
+    int* next_act;         // the next level's
+    unsigned long long* key1; unsigned long long* key2;  // [active x 8] argmin slots
+    unsigned long long* next_key1; unsigned long long* next_key2;  // the next level's
     float* dot_l;          // [m] per position
     int* left;             // [m] per position
-    int* nleft;            // [nseg]
+    int* nleft;            // [nseg] left count of each active segment
     int* degen;            // [nseg] split fell back to index halves
-    unsigned long long* next_key1; unsigned long long* next_key2;  // the next level's,
-    int* next_nleft;                                                // reset by k_cone_next
+    const int* seg;        // [m] position -> segment of this level
+    int* next_seg;         // [m] position -> segment of the next level (written by the scatter)
+    int* next_index;       // [nseg] first next-level segment made from each segment
+    int* lrank;            // [m] left flags before the position inside its 256-position block
+    int* blk_cnt;          // [ceil(m/256)] left flags per block; exclusive prefix after k_cone_next
+    // level-0 set-up only
+    uint32_t* perm_init; int* seg_init; int64_t* seg_start_init; int* act_init;
 };
-void exclusive_scan_i32(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
-int64_t scan_tmp_elems(int64_t n);
-
 struct LeafArgs {
     int dtype;
     const void* users;       // leaf order [m x ld]
@@ -138,29 +147,8 @@ struct LeafArgs {
     int* user_block;                             // [m]
     float* block_lb;                             // [k_max x nblocks]
 };
-void launch_leaf_stats(const LeafArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- SA-ALSH
-struct SaIndexArgs {
-    int dtype;
-    const void* items; const float* item_scales;   // sorted order
-    int64_t n; int d, ld;
-    const double* n2_sorted;
-    float b;
-    int K;
-    const float* A;          // [(d+1) x K]
-    int64_t* part_start;     // [max_parts+1] device
-    int* num_parts;          // device
-    int max_parts;
-};
-void launch_partitions(const SaIndexArgs& a, hipStream_t s);
-// centroids (FP64 accumulation, deterministic), radii, item codes
-void launch_saalsh_items(const SaIndexArgs& a, const int64_t* part_start_host, int t,
-                         double* cen64, float* cen32, float* radius, double* pieces,
-                         uint32_t* item_codes, hipStream_t s);
-void launch_user_codes(int dtype, const void* users, const float* user_scales, int64_t m, int d,
-                       int ld, const float* A, int K, uint32_t* codes, hipStream_t s);
-
 struct SaQueryArgs {
     int dtype;
     const void* items; const float* item_scales; int64_t n; int d, ld;   // sorted order

@@ -21,17 +21,6 @@
 
 namespace rk {
 
-__device__ __forceinline__ int64_t seg_of(const int64_t* starts, int64_t nseg, int64_t p)
-{
-    int64_t lo = 0, hi = nseg - 1;   // largest s with starts[s] <= p
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (starts[mid] <= p) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 {
     for (int o = 32; o > 0; o >>= 1) {
@@ -61,113 +50,131 @@ __device__ __forceinline__ float row_dot(const float* a, const float* b, int ld)
     return acc;
 }
 
-// One lane per position, 64 consecutive positions per wave.  Positions of one segment
-// are contiguous, so a wave meets few segments: the per-segment reduction runs inside
-// the wave and only one atomic per (wave, segment) reaches memory.
+// Argmin keys of an active segment are spread over KEY_WAYS slots (chosen by the
+// workgroup) so that the waves of a large segment do not all meet on one address;
+// readers take the minimum over the slots.
+static constexpr int KEY_WAYS = 8;
+
+__device__ __forceinline__ unsigned long long key_min(const unsigned long long* k, int ai)
+{
+    unsigned long long v = ~0ull;
+#pragma unroll
+    for (int q = 0; q < KEY_WAYS; q++) {
+        const unsigned long long x = k[(int64_t)ai * KEY_WAYS + q];
+        v = x < v ? x : v;
+    }
+    return v;
+}
+
+// One lane per position, 256 consecutive positions per workgroup.  Positions of one
+// segment are contiguous, so a wave meets few segments: the per-segment reduction runs
+// inside the wave and only one atomic per (wave, segment) reaches memory.
 // phase 0: argmin <u, v> -> key1;  phase 1: dot_l and argmin <u, u_l> -> key2;
-// phase 2: side flags and left counts.
+// phase 2: side flags, their ranks inside the workgroup's block of positions and the
+// block's count (the left count of a segment is a difference of two global ranks).
 __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
 {
-    const int l = lane_id();
-    const int64_t nseg = a.ctl[a.ctl_cur];
-    const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64 + l;
+    __shared__ int wt[4];
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool in = p < a.m;
-    const int64_t s = in ? seg_of(a.seg_start, nseg, p) : -1;
-    bool act = false;
+    int ai = -1;   // active index of the position's segment (-1: leaf)
     unsigned long long key = ~0ull;
     int lf = 0;
     if (in) {
-        const int64_t st = a.seg_start[s], sz = a.seg_start[s + 1] - st;
-        act = sz > a.leaf;
-        if (act) {
+        const int s = a.seg[p];
+        ai = a.act[s];
+        if (ai >= 0) {
             const float* up = a.unit + (int64_t)a.perm[p] * a.ld;
             if (phase == 0) {
+                const int64_t st = a.seg_start[s], sz = a.seg_start[s + 1] - st;
                 const float dv = row_dot(up, a.unit + (int64_t)a.perm[cone_pivot(a, st, sz)] * a.ld, a.ld);
                 key = ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p;
             } else if (phase == 1) {
-                const int64_t pl = (int64_t)(a.key1[s] & 0xffffffffull);
+                const int64_t pl = (int64_t)(key_min(a.key1, ai) & 0xffffffffull);
                 const float dl = row_dot(up, a.unit + (int64_t)a.perm[pl] * a.ld, a.ld);
                 a.dot_l[p] = dl;
                 key = ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p;
             } else {
-                const int64_t pr = (int64_t)(a.key2[s] & 0xffffffffull);
+                const int64_t pr = (int64_t)(key_min(a.key2, ai) & 0xffffffffull);
                 const float dr = row_dot(up, a.unit + (int64_t)a.perm[pr] * a.ld, a.ld);
                 lf = a.dot_l[p] >= dr ? 1 : 0;
             }
         }
     }
-    if (phase == 2 && in) a.left[p] = lf;
-    uint64_t rem = ballot64(act);
+    if (phase == 2) {   // uniform over the workgroup
+        const uint64_t bl = ballot64(lf != 0);
+        if (l == 0) wt[w] = __popcll(bl);
+        __syncthreads();
+        int off = 0;
+        for (int q = 0; q < w; q++) off += wt[q];
+        if (in) {
+            a.left[p] = lf;
+            a.lrank[p] = off + __popcll(bl & ((1ull << l) - 1ull));
+        }
+        if (threadIdx.x == 0) a.blk_cnt[blockIdx.x] = wt[0] + wt[1] + wt[2] + wt[3];
+        return;
+    }
+    unsigned long long* keys = phase == 0 ? a.key1 : a.key2;
+    uint64_t rem = ballot64(ai >= 0);
     while (rem) {
         const int leader = __builtin_ctzll(rem);
-        const int64_t s0 = __shfl(s, leader);
-        const bool mine = act && s == s0;
+        const int a0 = __shfl(ai, leader);
+        const bool mine = ai == a0;
         rem &= ~ballot64(mine);
-        if (phase < 2) {
-            const unsigned long long mn = wave_min_u64(mine ? key : ~0ull);
-            if (l == leader) atomicMin(phase == 0 ? &a.key1[s0] : &a.key2[s0], mn);
-        } else {
-            const int c = wave_sum(mine ? lf : 0);
-            if (l == leader && c) atomicAdd(&a.nleft[s0], c);
-        }
+        const unsigned long long mn = wave_min_u64(mine ? key : ~0ull);
+        if (l == leader) atomicMin(&keys[(int64_t)a0 * KEY_WAYS + (blockIdx.x & (KEY_WAYS - 1))], mn);
     }
 }
 
-// Reset of the per-segment reductions of a level.
+// Level 0: one segment [0, m) (active when m > N0), identity permutation, all positions
+// in segment 0, fresh argmin slots.
 __global__ void k_cone_init(ConeLevelArgs a)
 {
-    const int64_t nseg = a.ctl[a.ctl_cur];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.m) {
+        a.perm_init[i] = (uint32_t)i;
+        a.seg_init[i] = 0;
+    }
+    if (i < KEY_WAYS) {
         a.key1[i] = ~0ull;
         a.key2[i] = ~0ull;
-        a.nleft[i] = 0;
+    }
+    if (i == 0) {
+        const bool act = a.m > a.leaf;
+        a.ctl[0] = 1;
+        a.ctl[1] = 0;
+        a.ctl[2] = act ? 1 : 0;
+        a.ctl[3] = 0;
+        a.seg_start_init[0] = 0;
+        a.seg_start_init[1] = a.m;
+        a.act_init[0] = act ? 0 : -1;
     }
 }
 
 // The next level's segments, by one workgroup: an active segment becomes its left and
 // right parts (index halves when one side is empty), an inactive one stays.  Also
-// counts the next level's active segments.
+// numbers the next level's active segments and resets their argmin slots.
 __global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
 {
-    __shared__ int64_t wtot[16];
-    __shared__ int64_t carry_s, active_s;
+    __shared__ int64_t wtot[16], wact[16];
+    __shared__ int64_t carry_s, active_s, total_left;
     const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
     const int64_t nseg = a.ctl[a.ctl_cur];
-    if (tid == 0) {
-        carry_s = 0;
-        active_s = 0;
-    }
+    // exclusive prefix of the per-block left counts: global left rank of a position =
+    // blk_cnt[p >> 8] + lrank[p]
+    const int64_t nblk = (a.m + 255) / 256;
+    if (tid == 0) carry_s = 0;
     __syncthreads();
-    int64_t nact = 0;
-    for (int64_t c0 = 0; c0 < nseg; c0 += 1024) {
-        const int64_t s = c0 + tid;
-        int64_t st = 0, sz = 0, nl = 0;
-        int kids = 0;
-        bool act = false, dg = false;
-        if (s < nseg) {
-            st = a.seg_start[s];
-            sz = a.seg_start[s + 1] - st;
-            act = sz > a.leaf;
-            kids = act ? 2 : 1;
-            if (act) {
-                nl = a.nleft[s];
-                dg = nl == 0 || nl == sz;
-                if (dg) nl = sz / 2;
-                nact += (nl > a.leaf) + (sz - nl > a.leaf);
-            }
-            a.degen[s] = dg ? 1 : 0;
-        }
-        // block-exclusive prefix of kids
-        const int incl = wave_incl_scan(kids);
+    for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
+        const int64_t i = c0 + tid;
+        const int v = i < nblk ? a.blk_cnt[i] : 0;
+        const int incl = wave_incl_scan(v);
         if (l == 63) wtot[w] = incl;
         __syncthreads();
         int64_t off = carry_s;
         for (int q = 0; q < w; q++) off += wtot[q];
-        off += incl - kids;
-        if (s < nseg) {
-            a.next_start[off] = st;
-            if (act) a.next_start[off + 1] = st + nl;
-        }
+        if (i < nblk) a.blk_cnt[i] = (int)(off + incl - v);
         __syncthreads();
         if (tid == 0) {
             int64_t t = 0;
@@ -176,42 +183,112 @@ __global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
         }
         __syncthreads();
     }
-    nact = wave_sum((unsigned long long)nact);
-    if (l == 0 && nact) atomicAdd((unsigned long long*)&active_s, (unsigned long long)nact);
+    if (tid == 0) {
+        total_left = carry_s;
+        carry_s = 0;
+        active_s = 0;
+    }
     __syncthreads();
+    const int64_t tl = total_left;
+    auto lrank_at = [&](int64_t x) -> int64_t { return x < a.m ? (int64_t)a.blk_cnt[x >> 8] + a.lrank[x] : tl; };
+    for (int64_t c0 = 0; c0 < nseg; c0 += 1024) {
+        const int64_t s = c0 + tid;
+        int64_t st = 0, sz = 0, nl = 0;
+        int kids = 0, k0 = 0, k1 = 0;
+        bool act = false, dg = false;
+        if (s < nseg) {
+            st = a.seg_start[s];
+            sz = a.seg_start[s + 1] - st;
+            act = a.act[s] >= 0;
+            kids = act ? 2 : 1;
+            if (act) {
+                nl = lrank_at(st + sz) - lrank_at(st);
+                a.nleft[s] = (int)nl;
+                dg = nl == 0 || nl == sz;
+                if (dg) nl = sz / 2;
+                k0 = nl > a.leaf;
+                k1 = sz - nl > a.leaf;
+            }
+            a.degen[s] = dg ? 1 : 0;
+        }
+        // block-exclusive prefixes of the kids and of the active kids
+        const int incl = wave_incl_scan(kids);
+        const int iact = wave_incl_scan(k0 + k1);
+        if (l == 63) {
+            wtot[w] = incl;
+            wact[w] = iact;
+        }
+        __syncthreads();
+        int64_t off = carry_s, aoff = active_s;
+        for (int q = 0; q < w; q++) {
+            off += wtot[q];
+            aoff += wact[q];
+        }
+        off += incl - kids;
+        aoff += iact - (k0 + k1);
+        if (s < nseg) {
+            a.next_start[off] = st;
+            a.next_index[s] = (int)off;
+            if (act) {
+                a.next_start[off + 1] = st + nl;
+                a.next_act[off] = k0 ? (int)aoff : -1;
+                a.next_act[off + 1] = k1 ? (int)(aoff + k0) : -1;
+            } else {
+                a.next_act[off] = -1;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int64_t t = 0, ta = 0;
+            for (int q = 0; q < 16; q++) {
+                t += wtot[q];
+                ta += wact[q];
+            }
+            carry_s += t;
+            active_s += ta;
+        }
+        __syncthreads();
+    }
     if (tid == 0) {
         a.next_start[carry_s] = a.m;
         a.ctl[1 - a.ctl_cur] = carry_s;
         a.ctl[2] = active_s;
     }
-    // the next level's reductions start from their identities
-    for (int64_t i = tid; i < carry_s; i += 1024) {
+    // the next level's argmin slots start from their identity
+    for (int64_t i = tid; i < active_s * KEY_WAYS; i += 1024) {
         a.next_key1[i] = ~0ull;
         a.next_key2[i] = ~0ull;
-        a.next_nleft[i] = 0;
     }
 }
 
-__global__ void k_cone_scatter(ConeLevelArgs a, const int* lscan, uint32_t* new_perm)
+// Stable split of every active segment (left side first) and the next level's segment
+// of every position.  The left rank of a position inside its segment is the difference
+// of two global left ranks (block prefix + rank inside the block).
+__global__ void k_cone_scatter(ConeLevelArgs a, uint32_t* new_perm)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.m) return;
-    const int64_t nseg = a.ctl[a.ctl_cur];
-    const int64_t s = seg_of(a.seg_start, nseg, p);
-    int64_t np = p;
+    const int s = a.seg[p];
     const int64_t st = a.seg_start[s], sz = a.seg_start[s + 1] - st;
-    if (sz > a.leaf && !a.degen[s]) {
-        const int64_t lb = lscan[p] - lscan[st];
-        np = a.left[p] ? st + lb : st + a.nleft[s] + (p - st - lb);
+    int64_t np = p;
+    int ns = a.next_index[s];
+    if (sz > a.leaf) {
+        if (!a.degen[s]) {
+            const int64_t lb = ((int64_t)a.blk_cnt[p >> 8] + a.lrank[p]) - ((int64_t)a.blk_cnt[st >> 8] + a.lrank[st]);
+            if (a.left[p]) {
+                np = st + lb;
+            } else {
+                np = st + a.nleft[s] + (p - st - lb);
+                ns += 1;
+            }
+        } else if (p - st >= sz / 2) {
+            ns += 1;   // index halves
+        }
     }
     new_perm[np] = a.perm[p];
+    a.next_seg[np] = ns;
 }
 
-__global__ void k_iota(uint32_t* v, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = (uint32_t)i;
-}
 
 template <int DT>
 __global__ void k_unit(const void* X, const float* scales, const double* n2, int64_t rows, int d, int ld,
@@ -291,29 +368,38 @@ __global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
 }
 
 // L^j(B) = min over the block of lambda_u^(j) / ||u||, rounded down to FP32 (-inf for a
-// block without usable angles, so it is never pruned).
-__global__ void k_block_lb(const double* lam64, const double* user_n2, const int64_t* block_start,
-                           const int* block_ok, int64_t nblocks, int64_t m, int k_max, float* lb)
+// block without usable angles, so it is never pruned).  One wave per block, one user
+// per lane (blocks hold at most 64 users), one coalesced row of lambda per j.
+__global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const double* user_n2,
+                                                  const int64_t* block_start, const int* block_ok, int64_t nblocks,
+                                                  int64_t m, int k_max, float* lb)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nblocks * k_max) return;
-    const int64_t b = t % nblocks;
-    const int j = (int)(t / nblocks);
-    float out = -__builtin_inff();
-    if (block_ok[b]) {
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= nblocks) return;
+    const int l = lane_id();
+    const int64_t st = block_start[b], en = block_start[b + 1];
+    const bool ok = block_ok[b] != 0;
+    const double un0 = st + l < en ? sqrt(user_n2[st + l]) : 1.0;
+    for (int j = 0; j < k_max; j++) {
         double mn = __builtin_inf();
-        for (int64_t p = block_start[b]; p < block_start[b + 1]; p++) {
-            const double v = lam64[(int64_t)j * m + p] / sqrt(user_n2[p]);
+        for (int64_t q = st + l; q < en; q += 64) {
+            const double v = lam64[(int64_t)j * m + q] / (q == st + l ? un0 : sqrt(user_n2[q]));
             mn = v < mn ? v : mn;
         }
-        float f = (float)mn;
-        if ((double)f > mn) {   // step one ulp towards -inf
-            const uint32_t u = __float_as_uint(f);
-            f = f == 0.f ? -__uint_as_float(1u) : __uint_as_float(f > 0.f ? u - 1u : u + 1u);
+        mn = wave_min(mn);
+        if (l == 0) {
+            float out = -__builtin_inff();
+            if (ok) {
+                float f = (float)mn;
+                if ((double)f > mn) {   // step one ulp towards -inf
+                    const uint32_t u = __float_as_uint(f);
+                    f = f == 0.f ? -__uint_as_float(1u) : __uint_as_float(f > 0.f ? u - 1u : u + 1u);
+                }
+                out = f;
+            }
+            lb[(int64_t)j * nblocks + b] = out;
         }
-        out = f;
     }
-    lb[(int64_t)j * nblocks + b] = out;
 }
 
 // ------------------------------------------------------------------ host orchestration
@@ -321,7 +407,7 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
 {
     const int64_t m = x.m;
     const int ld = x.ld;
-    DevBuf unit, perm_a, perm_b, dot_l, left, lscan, scan_tmp;
+    DevBuf unit, perm_a, perm_b, seg_a, seg_b, dot_l, left, lrank, blk_cnt;
     unit.alloc(sizeof(float) * (size_t)m * ld);
     {
         const int64_t tot = m * ld;
@@ -334,23 +420,27 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     perm_b.alloc(sizeof(uint32_t) * m);
     dot_l.alloc(sizeof(float) * m);
     left.alloc(sizeof(int) * m);
-    lscan.alloc(sizeof(int) * m);
-    scan_tmp.alloc(sizeof(int) * scan_tmp_elems(m));
-    hipLaunchKernelGGL(k_iota, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, perm_a.u32(), m);
+    lrank.alloc(sizeof(int) * m);
+    blk_cnt.alloc(sizeof(int) * ((m + 255) / 256));
+    seg_a.alloc(sizeof(int) * m);
+    seg_b.alloc(sizeof(int) * m);
 
-    // Levels run on the device, four per check of the host: each level's segment table
-    // is built by k_cone_next from the previous one; a level without active segments
-    // changes nothing, so levels past the last split are harmless.
+    // Levels run on the device, several per check of the host: each level's segment
+    // table is built by k_cone_next from the previous one; a level without active
+    // segments changes nothing, so levels past the last split are harmless.
     const int64_t cap = m + 2;
-    DevBuf d_start[2], d_ctl, d_key1[2], d_key2[2], d_nleft[2], d_degen;
+    const int64_t act_cap = m / ((int64_t)x.prm.leaf_size + 1) + 1;   // active segments hold > N0 users
+    DevBuf d_start[2], d_act[2], d_key1[2], d_key2[2], d_ctl, d_nleft, d_degen, d_next_index;
     for (int i = 0; i < 2; i++) {
         d_start[i].alloc(sizeof(int64_t) * (cap + 1));
-        d_key1[i].alloc(sizeof(uint64_t) * cap);
-        d_key2[i].alloc(sizeof(uint64_t) * cap);
-        d_nleft[i].alloc(sizeof(int) * cap);
+        d_act[i].alloc(sizeof(int) * cap);
+        d_key1[i].alloc(sizeof(uint64_t) * act_cap * KEY_WAYS);
+        d_key2[i].alloc(sizeof(uint64_t) * act_cap * KEY_WAYS);
     }
     d_ctl.alloc(sizeof(int64_t) * 4);
+    d_nleft.alloc(sizeof(int) * cap);
     d_degen.alloc(sizeof(int) * cap);
+    d_next_index.alloc(sizeof(int) * cap);
     PinBuf h_ctl;
     h_ctl.alloc(sizeof(int64_t) * 4);
     auto level_args = [&](int level) {
@@ -360,52 +450,51 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
         a.seg_start = d_start[c].i64(); a.next_start = d_start[n].i64();
         a.ctl = d_ctl.i64(); a.ctl_cur = c; a.level = level; a.leaf = x.prm.leaf_size;
         a.seed = x.prm.seed; a.m = m;
+        a.act = d_act[c].i(); a.next_act = d_act[n].i();
         a.key1 = (unsigned long long*)d_key1[c].p; a.key2 = (unsigned long long*)d_key2[c].p;
-        a.nleft = d_nleft[c].i();
         a.next_key1 = (unsigned long long*)d_key1[n].p; a.next_key2 = (unsigned long long*)d_key2[n].p;
-        a.next_nleft = d_nleft[n].i();
-        a.dot_l = dot_l.f(); a.left = left.i(); a.degen = d_degen.i();
+        a.dot_l = dot_l.f(); a.left = left.i(); a.nleft = d_nleft.i(); a.degen = d_degen.i();
+        a.seg = seg_a.i(); a.next_seg = seg_b.i(); a.next_index = d_next_index.i();
+        a.lrank = lrank.i(); a.blk_cnt = blk_cnt.i();
         return a;
     };
+    const unsigned grid = (unsigned)((m + 255) / 256);
     {
-        int64_t* hc = (int64_t*)h_ctl.p;
-        hc[0] = 1; hc[1] = 0; hc[2] = m > x.prm.leaf_size ? 1 : 0; hc[3] = 0;
-        HIPC(hipMemcpyAsync(d_ctl.p, hc, sizeof(int64_t) * 4, hipMemcpyHostToDevice, s));
-        const int64_t init[2] = {0, m};
-        HIPC(hipMemcpyAsync(d_start[0].p, init, sizeof init, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_cone_init, dim3(1), dim3(64), 0, s, level_args(0));
-        HIPC(hipStreamSynchronize(s));   // the host copies above are in pageable memory
+        ConeLevelArgs a = level_args(0);
+        a.perm_init = perm_a.u32(); a.seg_init = seg_a.i(); a.seg_start_init = d_start[0].i64();
+        a.act_init = d_act[0].i();
+        hipLaunchKernelGGL(k_cone_init, dim3(grid), dim3(256), 0, s, a);
+        HIPC(hipGetLastError());
     }
     int level = 0;
     bool more = m > x.prm.leaf_size;
-    const unsigned grid = (unsigned)((m + 255) / 256);
     // the first batch is the depth of a perfectly balanced tree, later ones are short
     int batch = 1;
     while (((int64_t)x.prm.leaf_size << batch) < m) batch++;
+    int64_t nseg_final = 1;
     while (more) {
         for (int rep = 0; rep < batch; rep++, level++) {
             const ConeLevelArgs a = level_args(level);
             for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
             hipLaunchKernelGGL(k_cone_next, dim3(1), dim3(1024), 0, s, a);
-            exclusive_scan_i32(left.i(), lscan.i(), m, scan_tmp.i(), s);
-            hipLaunchKernelGGL(k_cone_scatter, dim3(grid), dim3(256), 0, s, a, (const int*)lscan.i(), perm_b.u32());
+            hipLaunchKernelGGL(k_cone_scatter, dim3(grid), dim3(256), 0, s, a, perm_b.u32());
             HIPC(hipGetLastError());
             perm_a.swap(perm_b);
+            seg_a.swap(seg_b);
         }
         HIPC(hipMemcpyAsync(h_ctl.p, d_ctl.p, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
         more = ((const int64_t*)h_ctl.p)[2] > 0;
+        nseg_final = ((const int64_t*)h_ctl.p)[level & 1];
         batch = 2;
     }
-    const int64_t nseg_final = ((const int64_t*)h_ctl.p)[level & 1];
-    std::vector<int64_t> starts(nseg_final + 1);
-    HIPC(hipMemcpy(starts.data(), d_start[level & 1].p, sizeof(int64_t) * (nseg_final + 1), hipMemcpyDeviceToHost));
+    if (level == 0) HIPC(hipStreamSynchronize(s));   // the caller reads host copies made before the build
 
     // ---- leaves are the blocks; users move into leaf order
-    x.nblocks = (int64_t)starts.size() - 1;
-    x.block_start_h = starts;
-    x.block_start.alloc(sizeof(int64_t) * starts.size());
-    HIPC(hipMemcpyAsync(x.block_start.p, starts.data(), sizeof(int64_t) * starts.size(), hipMemcpyHostToDevice, s));
+    x.nblocks = nseg_final;
+    x.block_start.alloc(sizeof(int64_t) * (nseg_final + 1));
+    HIPC(hipMemcpyAsync(x.block_start.p, d_start[level & 1].p, sizeof(int64_t) * (nseg_final + 1),
+                        hipMemcpyDeviceToDevice, s));
     x.user_perm.swap(perm_a);
     const int eb = elt_bytes(x.dtype);
     x.users.alloc((size_t)m * ld * eb);
@@ -434,14 +523,13 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_leaf_stats<DT_BF16>, g, b, 0, s, la);
     else hipLaunchKernelGGL(k_leaf_stats<DT_FP8>, g, b, 0, s, la);
     HIPC(hipGetLastError());
-    HIPC(hipStreamSynchronize(s));
 }
 
 void finish_blocks(Index& x, hipStream_t s)
 {
     const int64_t tot = x.nblocks * x.prm.k_max;
     x.block_lb.alloc(sizeof(float) * tot);
-    hipLaunchKernelGGL(k_block_lb, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x.lam64.d(),
+    hipLaunchKernelGGL(k_block_lb, dim3((unsigned)((x.nblocks + 3) / 4)), dim3(256), 0, s, x.lam64.d(),
                        x.user_n2.d(), x.block_start.i64(), x.block_ok.i(), x.nblocks, x.m, x.prm.k_max,
                        x.block_lb.f());
     HIPC(hipGetLastError());

@@ -2,6 +2,8 @@
 // items (Alg. 4 / Alg. 1: sort by descending norm), row gathers into padded copies,
 // unit user directions for the Cone-Tree (Fact 2: only directions matter), and a
 // bitonic sort used for the item order and for the per-query result lists.
+#include <utility>
+
 #include "common.h"
 #include "internal.h"
 
@@ -13,7 +15,7 @@ namespace rk {
 // non-negative double order like the value), stats[2] = min positive n2, stats[3] = 1
 // on any non-finite value, NaN code or non-finite scale.
 template <int DT>
-__global__ void k_norm2(const void* X, const float* scales, int64_t rows, int d, int ld, double* n2,
+__global__ __launch_bounds__(256) void k_norm2(const void* X, const float* scales, int64_t rows, int d, int ld, double* n2,
                         unsigned long long* stats, int slot)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -45,14 +47,33 @@ __global__ void k_norm2(const void* X, const float* scales, int64_t rows, int d,
         }
         n2[r] = acc;
     }
+    // workgroup reduction, then one atomic per statistic that can still change it
+    __shared__ unsigned long long smx[4], smn[4];
+    __shared__ int sbad[4];
     const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
     const unsigned long long mx = wave_max((r < rows && ok) ? bits : 0ull);
     const unsigned long long mn = wave_min((r < rows && ok && acc > 0.0) ? bits : ~0ull);
     const bool any_bad = ballot64(r < rows && !ok) != 0ull;
+    const int w = threadIdx.x >> 6;
     if (lane_id() == 0) {
-        if (mx) atomicMax(&stats[slot], mx);
-        if (mn != ~0ull) atomicMin(&stats[2], mn);
-        if (any_bad) atomicOr(&stats[3], 1ull);
+        smx[w] = mx;
+        smn[w] = mn;
+        sbad[w] = any_bad ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long bx = 0ull, bn = ~0ull;
+        int bad = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); q++) {
+            bx = smx[q] > bx ? smx[q] : bx;
+            bn = smn[q] < bn ? smn[q] : bn;
+            bad |= sbad[q];
+        }
+        if (bx && bx > __hip_atomic_load(&stats[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&stats[slot], bx);
+        if (bn != ~0ull && bn < __hip_atomic_load(&stats[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMin(&stats[2], bn);
+        if (bad) atomicOr(&stats[3], 1ull);
     }
 }
 
@@ -75,6 +96,41 @@ void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, i
     if (dtype == DT_F32) hipLaunchKernelGGL(k_norm2<DT_F32>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
     else if (dtype == DT_BF16) hipLaunchKernelGGL(k_norm2<DT_BF16>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
     else hipLaunchKernelGGL(k_norm2<DT_FP8>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+    HIPC(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ split BF16 operands
+// FP32 rows as BF16 pairs: h = RN_bf16(x), l = RN_bf16(x - h) (x - h is exact in FP32).
+// The row [h | l | h] of an item against the row [h | h | l] of a user gives
+// h.h + l.h + h.l on the BF16 matrix cores, which differs from <x, y> by at most about
+// 3 * 2^-18 sum |x_i y_i| (the dropped l.l term and the parts below l).
+__device__ __forceinline__ uint16_t f32_to_bf16_rn(float x)
+{
+    const uint32_t b = __float_as_uint(x);   // finite input
+    return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+
+__global__ void k_split_bf16(const float* src, int64_t rows, int ld, uint16_t* dst, int user_layout)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * ld) return;
+    const int64_t r = t / ld;
+    const int i = (int)(t - r * ld);
+    const float x = src[t];
+    const uint16_t hb = f32_to_bf16_rn(x);
+    const uint16_t lb = f32_to_bf16_rn(x - bf16_to_f32(hb));
+    uint16_t* row = dst + r * 3 * ld;
+    row[i] = hb;
+    row[ld + i] = user_layout ? hb : lb;
+    row[2 * ld + i] = user_layout ? lb : hb;
+}
+
+void launch_split_bf16(const float* src, int64_t rows, int ld, uint16_t* dst, int user_layout, hipStream_t s)
+{
+    if (rows <= 0) return;
+    const int64_t tot = rows * ld;
+    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, rows, ld, dst,
+                       user_layout);
     HIPC(hipGetLastError());
 }
 
@@ -113,72 +169,75 @@ void launch_permute_f64(const double* src, const uint32_t* perm, int64_t n, doub
     HIPC(hipGetLastError());
 }
 
-// ------------------------------------------------------------------ bitonic sort
-// Ascending by (key, val).  Chunk-local stages run in LDS; longer strides in global.
-static constexpr int SORT_THREADS = 256;
-static constexpr int SORT_CHUNK = 2048;  // elements per workgroup in the LDS stages
+// ------------------------------------------------------------------ pair sort
+// Ascending by (key, val).  Chunks of up to SORT_CHUNK pairs are sorted in LDS by a
+// bitonic network (one compare-exchange per thread per stage); sorted runs are then
+// merged pairwise, level by level: a pair's output position is its index in its own run
+// plus the number of pairs of the partner run that order before it (binary search; a
+// left-run pair counts the partner's strictly smaller pairs, a right-run pair also the
+// equal ones, so positions never collide).
+static constexpr int SORT_CHUNK = 2048;
 
-template <bool HV>
-__device__ __forceinline__ bool gt_pair(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb)
+__device__ __forceinline__ bool lt_pair(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb)
 {
-    if constexpr (HV) return ka > kb || (ka == kb && va > vb);
-    else return ka > kb;
+    return ka < kb || (ka == kb && va < vb);
 }
 
-// Stages (k, j) for k in [k_lo, k_hi] (k doubling) and j from min(k/2, chunk/2) to 1,
-// all inside one chunk of `chunk` elements.
-template <bool HV>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_local(uint64_t* keys, uint32_t* vals,
-                                                               int chunk, int64_t k_lo, int64_t k_hi)
+__global__ __launch_bounds__(SORT_CHUNK / 2) void k_sort_chunk(uint64_t* keys, uint32_t* vals, int chunk)
 {
     __shared__ uint64_t sk[SORT_CHUNK];
-    __shared__ uint32_t sv[HV ? SORT_CHUNK : 1];
+    __shared__ uint32_t sv[SORT_CHUNK];
     const int64_t base = (int64_t)blockIdx.x * chunk;
-    for (int i = threadIdx.x; i < chunk; i += SORT_THREADS) {
-        sk[i] = keys[base + i];
-        if constexpr (HV) sv[i] = vals[base + i];
-    }
+    const int t = threadIdx.x;   // chunk / 2 threads
+    sk[t] = keys[base + t];
+    sv[t] = vals[base + t];
+    sk[t + chunk / 2] = keys[base + t + chunk / 2];
+    sv[t + chunk / 2] = vals[base + t + chunk / 2];
     __syncthreads();
-    for (int64_t k = k_lo; k <= k_hi; k <<= 1) {
-        for (int64_t j = (k >> 1) < (chunk >> 1) ? (k >> 1) : (chunk >> 1); j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < (chunk >> 1); t += SORT_THREADS) {
-                int i = (int)(2 * j * (t / j) + (t % j));
-                int p = i + (int)j;
-                bool asc = (((base + i) & k) == 0);
-                uint64_t ka = sk[i], kb = sk[p];
-                uint32_t va = 0, vb = 0;
-                if constexpr (HV) { va = sv[i]; vb = sv[p]; }
-                bool sw = asc ? gt_pair<HV>(ka, va, kb, vb) : gt_pair<HV>(kb, vb, ka, va);
-                if (sw) {
-                    sk[i] = kb; sk[p] = ka;
-                    if constexpr (HV) { sv[i] = vb; sv[p] = va; }
-                }
+    for (int k = 2; k <= chunk; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int i = 2 * j * (t / j) + (t % j);
+            const int p = i + j;
+            const bool asc = (i & k) == 0;   // the last stage (k = chunk) sorts every chunk ascending
+            const uint64_t ka = sk[i], kb = sk[p];
+            const uint32_t va = sv[i], vb = sv[p];
+            if (lt_pair(kb, vb, ka, va) == asc) {
+                sk[i] = kb; sk[p] = ka;
+                sv[i] = vb; sv[p] = va;
             }
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < chunk; i += SORT_THREADS) {
-        keys[base + i] = sk[i];
-        if constexpr (HV) vals[base + i] = sv[i];
-    }
+    keys[base + t] = sk[t];
+    vals[base + t] = sv[t];
+    keys[base + t + chunk / 2] = sk[t + chunk / 2];
+    vals[base + t + chunk / 2] = sv[t + chunk / 2];
 }
 
-template <bool HV>
-__global__ void k_sort_global(uint64_t* keys, uint32_t* vals, int64_t npairs, int64_t k, int64_t j)
+__global__ void k_merge_runs(const uint64_t* ki, const uint32_t* vi, uint64_t* ko, uint32_t* vo, int64_t len,
+                             int64_t w)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npairs) return;
-    int64_t i = 2 * j * (t / j) + (t % j);
-    int64_t p = i + j;
-    bool asc = ((i & k) == 0);
-    uint64_t ka = keys[i], kb = keys[p];
-    uint32_t va = 0, vb = 0;
-    if constexpr (HV) { va = vals[i]; vb = vals[p]; }
-    bool sw = asc ? gt_pair<HV>(ka, va, kb, vb) : gt_pair<HV>(kb, vb, ka, va);
-    if (sw) {
-        keys[i] = kb; keys[p] = ka;
-        if constexpr (HV) { vals[i] = vb; vals[p] = va; }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= len) return;
+    const int64_t r = t / w, a = t - r * w;
+    const int64_t pair0 = (r & ~(int64_t)1) * w;
+    const int64_t q0 = (r ^ 1) * w;
+    const int64_t q1 = q0 + w < len ? q0 + w : len;
+    const uint64_t kt = ki[t];
+    const uint32_t vt = vi[t];
+    int64_t lo = q0, hi = q0 < len ? q1 : q0;   // a partner run past the end is empty
+    const bool left = (r & 1) == 0;
+    while (lo < hi) {   // first partner position that orders after this pair
+        const int64_t mid = (lo + hi) >> 1;
+        const uint64_t km = ki[mid];
+        const uint32_t vm = vi[mid];
+        const bool before = left ? lt_pair(km, vm, kt, vt) : !lt_pair(kt, vt, km, vm);
+        if (before) lo = mid + 1;
+        else hi = mid;
     }
+    const int64_t pos = pair0 + a + (lo - q0);
+    ko[pos] = kt;
+    vo[pos] = vt;
 }
 
 __global__ void k_fill_pad(uint64_t* keys, uint32_t* vals, int64_t n, int64_t cap)
@@ -186,43 +245,33 @@ __global__ void k_fill_pad(uint64_t* keys, uint32_t* vals, int64_t n, int64_t ca
     int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
     keys[i] = ~0ull;
-    if (vals) vals[i] = 0xffffffffu;
+    vals[i] = 0xffffffffu;
 }
 
-static int64_t pow2ceil(int64_t n)
-{
-    int64_t p = 2;
-    while (p < n) p <<= 1;
-    return p;
-}
-
-template <bool HV>
-static void bitonic(uint64_t* keys, uint32_t* vals, int64_t n, int64_t cap, hipStream_t s)
+void sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals, int64_t n, int64_t cap,
+                hipStream_t s)
 {
     if (n <= 1) return;
-    const int64_t P = pow2ceil(n);
-    if (cap < P) fail(RKMIPS_EINVAL, "internal: sort capacity below the padded size");
-    if (P > n)
-        hipLaunchKernelGGL(k_fill_pad, dim3((unsigned)((P - n + 255) / 256)), dim3(256), 0, s, keys,
-                           HV ? vals : nullptr, n, P);
-    const int chunk = (int)(P < SORT_CHUNK ? P : SORT_CHUNK);
-    const unsigned nch = (unsigned)(P / chunk);
-    hipLaunchKernelGGL(k_sort_local<HV>, dim3(nch), dim3(SORT_THREADS), 0, s, keys, vals, chunk,
-                       (int64_t)2, (int64_t)chunk);
-    for (int64_t k = (int64_t)chunk * 2; k <= P; k <<= 1) {
-        for (int64_t j = k >> 1; j >= chunk; j >>= 1)
-            hipLaunchKernelGGL(k_sort_global<HV>, dim3((unsigned)((P / 2 + 255) / 256)), dim3(256), 0, s,
-                               keys, vals, P / 2, k, j);
-        hipLaunchKernelGGL(k_sort_local<HV>, dim3(nch), dim3(SORT_THREADS), 0, s, keys, vals, chunk, k, k);
+    int chunk = 2;
+    while (chunk < n && chunk < SORT_CHUNK) chunk <<= 1;
+    const int64_t len = (n + chunk - 1) / chunk * chunk;
+    if (cap < len) fail(RKMIPS_EINVAL, "internal: sort capacity below the padded size");
+    if (len > n)
+        hipLaunchKernelGGL(k_fill_pad, dim3((unsigned)((len - n + 255) / 256)), dim3(256), 0, s, keys, vals, n, len);
+    hipLaunchKernelGGL(k_sort_chunk, dim3((unsigned)(len / chunk)), dim3(chunk / 2), 0, s, keys, vals, chunk);
+    uint64_t *k0 = keys, *k1 = tmp_keys;
+    uint32_t *v0 = vals, *v1 = tmp_vals;
+    for (int64_t w = chunk; w < len; w <<= 1) {
+        hipLaunchKernelGGL(k_merge_runs, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, k0, v0, k1, v1, len, w);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    if (k0 != keys) {
+        HIPC(hipMemcpyAsync(keys, k0, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+        HIPC(hipMemcpyAsync(vals, v0, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
     }
     HIPC(hipGetLastError());
 }
-
-void sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int64_t cap, hipStream_t s)
-{
-    bitonic<true>(keys, vals, n, cap, s);
-}
-void sort_keys(uint64_t* keys, int64_t n, int64_t cap, hipStream_t s) { bitonic<false>(keys, nullptr, n, cap, s); }
 
 // ------------------------------------------------------------------ row gather
 // One wave per destination row; bytes copied in 4-byte words when the row lengths
@@ -288,75 +337,6 @@ void launch_unit_rows(int dtype, const void* X, const float* scales, const doubl
     if (dtype == DT_F32) hipLaunchKernelGGL(k_unit_rows<DT_F32>, g, b, 0, s, X, scales, n2, rows, d, ld, out);
     else if (dtype == DT_BF16) hipLaunchKernelGGL(k_unit_rows<DT_BF16>, g, b, 0, s, X, scales, n2, rows, d, ld, out);
     else hipLaunchKernelGGL(k_unit_rows<DT_FP8>, g, b, 0, s, X, scales, n2, rows, d, ld, out);
-    HIPC(hipGetLastError());
-}
-
-// ------------------------------------------------------------------ exclusive scan (int32)
-// Three phases: per-block sums, a single-block scan of the sums, then the add-back.
-static constexpr int SCAN_B = 1024;
-
-__global__ __launch_bounds__(256) void k_scan_blocks(const int* in, int* out, int64_t n, int* sums)
-{
-    __shared__ int ws[4];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_B;
-    int v[4], loc = 0;
-    for (int e = 0; e < 4; e++) {
-        int64_t i = base + threadIdx.x * 4 + e;
-        v[e] = i < n ? in[i] : 0;
-        loc += v[e];
-    }
-    int inc = wave_incl_scan(loc);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 63) ws[w] = inc;
-    __syncthreads();
-    int off = 0;
-    for (int q = 0; q < w; q++) off += ws[q];
-    int run = off + inc - loc;
-    for (int e = 0; e < 4; e++) {
-        int64_t i = base + threadIdx.x * 4 + e;
-        if (i < n) out[i] = run;
-        run += v[e];
-    }
-    if (threadIdx.x == 255) sums[blockIdx.x] = off + inc;
-}
-
-__global__ __launch_bounds__(256) void k_scan_sums(int* sums, int64_t nb)
-{
-    __shared__ int ws[4];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
-        int64_t i = b0 + threadIdx.x;
-        int v = i < nb ? sums[i] : 0;
-        int inc = wave_incl_scan(v);
-        const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 63) ws[w] = inc;
-        __syncthreads();
-        int off = carry;
-        for (int q = 0; q < w; q++) off += ws[q];
-        if (i < nb) sums[i] = off + inc - v;
-        __syncthreads();
-        if (threadIdx.x == 255) carry = off + inc;
-        __syncthreads();
-    }
-}
-
-__global__ void k_scan_add(int* out, int64_t n, const int* sums)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] += sums[i / SCAN_B];
-}
-
-int64_t scan_tmp_elems(int64_t n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
-
-void exclusive_scan_i32(const int* in, int* out, int64_t n, int* tmp, hipStream_t s)
-{
-    if (n <= 0) return;
-    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
-    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(256), 0, s, in, out, n, tmp);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, tmp, nb);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, tmp);
     HIPC(hipGetLastError());
 }
 

@@ -58,45 +58,98 @@ __global__ void k_partitions(const double* n2, int64_t n, float b, int64_t* part
 
 // Centroid sums.  Each partition is cut into pieces of at most CEN_PIECE items; one
 // workgroup per (piece, 64-column chunk) sums its piece with 4 interleaved row groups in
-// FP64, combined in a fixed order; a second pass adds the pieces of a partition in
-// order and divides by |S_j|.  The result does not depend on scheduling.
-static constexpr int64_t CEN_PIECE = 2048;
+// FP64, combined in a fixed order.  A second pass gives one wave to each (partition,
+// column): lane i adds the pieces i, i + 64, ... in order, the wave combines the lanes
+// in a fixed shuffle tree, and the sum is divided by |S_j|.  The result does not
+// depend on scheduling.
+static constexpr int64_t CEN_PIECE = 256;
+
+// Pieces are numbered partition by partition: pp[j] = first piece of partition j,
+// pp[t] = number of pieces (one workgroup, scan over the partitions).
+__global__ __launch_bounds__(1024) void k_pieces(const int64_t* part_start, const int* num_parts, int64_t* pp)
+{
+    __shared__ int64_t wtot[16];
+    __shared__ int64_t carry_s;
+    const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
+    const int t = *num_parts;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < t; c0 += 1024) {
+        const int j = c0 + tid;
+        const int64_t c = j < t ? (part_start[j + 1] - part_start[j] + CEN_PIECE - 1) / CEN_PIECE : 0;
+        int64_t incl = c;   // wave inclusive scan (64-bit)
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(incl, o);
+            if (l >= o) incl += y;
+        }
+        if (l == 63) wtot[w] = incl;
+        __syncthreads();
+        int64_t off = carry_s;
+        for (int q = 0; q < w; q++) off += wtot[q];
+        if (j < t) pp[j] = off + incl - c;
+        __syncthreads();
+        if (tid == 0) {
+            int64_t s = 0;
+            for (int q = 0; q < 16; q++) s += wtot[q];
+            carry_s += s;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) pp[t] = carry_s;
+}
 
 template <int DT>
-__global__ __launch_bounds__(256) void k_centroid_piece(const void* X, const float* scales, const int64_t* pc_begin,
-                                                        const int64_t* pc_end, int d, int ld, double* psum)
+__global__ __launch_bounds__(256) void k_centroid_piece(const void* X, const float* scales, const int64_t* part_start,
+                                                        const int* num_parts, const int64_t* pp, int d, int ld,
+                                                        double* psum)
 {
     __shared__ double part[4][64];
-    const int pc = blockIdx.x;
+    const int t = *num_parts;
+    const int64_t pc = blockIdx.x;
+    if (pc >= pp[t]) return;   // grid sized for the most pieces any partitioning can give
+    int lo = 0, hi = t - 1;    // partition of the piece: largest j with pp[j] <= pc
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pp[mid] <= pc) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t s0 = part_start[lo] + (pc - pp[lo]) * CEN_PIECE;
+    const int64_t s1 = s0 + CEN_PIECE < part_start[lo + 1] ? s0 + CEN_PIECE : part_start[lo + 1];
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int g = threadIdx.x >> 6;
-    const int64_t s0 = pc_begin[pc], s1 = pc_end[pc];
     double acc = 0.0;
-    if (c < d)
+    if (c < d) {
+#pragma unroll 8
         for (int64_t p = s0 + g; p < s1; p += 4) {
             double v = (double)elem_f32<DT>(X, p * ld + c);
             if constexpr (DT == DT_FP8) v *= (double)scales[p];
             acc += v;
         }
+    }
     part[g][threadIdx.x & 63] = acc;
     __syncthreads();
     if (g == 0 && c < ld)
-        psum[(int64_t)pc * ld + c] = ((part[0][c & 63] + part[1][c & 63]) + part[2][c & 63]) + part[3][c & 63];
+        psum[pc * ld + c] = ((part[0][c & 63] + part[1][c & 63]) + part[2][c & 63]) + part[3][c & 63];
 }
 
-__global__ void k_centroid_final(const double* psum, const int64_t* part_piece, const int64_t* part_start, int t,
-                                 int d, int ld, double* cen64, float* cen32)
+__global__ __launch_bounds__(256) void k_centroid_final(const double* psum, const int64_t* part_piece,
+                                                        const int64_t* part_start, int t, int d, int ld,
+                                                        double* cen64, float* cen32)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // (partition, column)
     if (e >= (int64_t)t * ld) return;
+    const int l = lane_id();
     const int j = (int)(e / ld), c = (int)(e % ld);
     double v = 0.0;
     if (c < d) {
-        for (int64_t pc = part_piece[j]; pc < part_piece[j + 1]; pc++) v += psum[pc * ld + c];
+        for (int64_t pc = part_piece[j] + l; pc < part_piece[j + 1]; pc += 64) v += psum[pc * ld + c];
+        v = wave_sum(v);
         v /= (double)(part_start[j + 1] - part_start[j]);
     }
-    cen64[e] = v;
-    cen32[e] = (float)v;
+    if (l == 0) {
+        cen64[e] = v;
+        cen32[e] = (float)v;
+    }
 }
 
 // r2[p] = ||p - c_j||^2 (FP64) and the partition radius as max (atomicMax on the bits
@@ -179,7 +232,12 @@ __global__ __launch_bounds__(256) void k_project(const void* X, const float* sca
         for (int r = 0; r < 16; r++) acc[cb][r] = 0.f;
     for (int k0 = 0; k0 < D; k0 += PJ_KC) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 128 * PJ_KC; e += 256) {
+        // all loads of the chunk are issued before the first LDS store
+        constexpr int XE = 128 * PJ_KC / 256, AE = PJ_KC * KB * 32 / 256;
+        float xv[XE], av[AE];
+#pragma unroll
+        for (int q = 0; q < XE; q++) {
+            const int e = threadIdx.x + 256 * q;
             const int rr = e / PJ_KC, kk = e % PJ_KC;
             const int64_t p = r0 + rr;
             const int i = k0 + kk;
@@ -195,12 +253,24 @@ __global__ __launch_bounds__(256) void k_project(const void* X, const float* sca
                     v = rest > 0.0 ? (float)sqrt(rest) : 0.f;
                 }
             }
-            xs[rr][kk] = v;
+            xv[q] = v;
         }
-        for (int e = threadIdx.x; e < PJ_KC * KB * 32; e += 256) {
+#pragma unroll
+        for (int q = 0; q < AE; q++) {
+            const int e = threadIdx.x + 256 * q;
             const int kk = e / (KB * 32), h = e % (KB * 32);
             const int i = k0 + kk;
-            as[kk][h] = (i < D && h < K) ? A[(int64_t)i * K + h] : 0.f;
+            av[q] = (i < D && h < K) ? A[(int64_t)i * K + h] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < XE; q++) {
+            const int e = threadIdx.x + 256 * q;
+            xs[e / PJ_KC][e % PJ_KC] = xv[q];
+        }
+#pragma unroll
+        for (int q = 0; q < AE; q++) {
+            const int e = threadIdx.x + 256 * q;
+            as[e / (KB * 32)][e % (KB * 32)] = av[q];
         }
         __syncthreads();
 #pragma unroll
@@ -262,14 +332,24 @@ __global__ void k_gen_srp(float* A, int64_t count, uint64_t seed)
     A[i] = (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
 }
 
+// Partition starts of the norm-sorted items; the partition count reaches the host at the
+// build's next synchronisation (h_num_parts).
+void start_partitions(Index& x, int* h_num_parts, hipStream_t s)
+{
+    x.part_start.alloc(sizeof(int64_t) * (x.n + 2));
+    x.num_parts.alloc(sizeof(int));
+    hipLaunchKernelGGL(k_partitions, dim3(1), dim3(64), 0, s, x.item_n2.d(), x.n, x.prm.b, x.part_start.i64(),
+                       x.num_parts.i());
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(h_num_parts, x.num_parts.p, sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+// The rest of Alg. 1 once x.t is known; stream-ordered, no host synchronisation.
 void build_saalsh(Index& x, const float* srp, hipStream_t s)
 {
-    hipEvent_t e0, e1;
-    HIPC(hipEventCreate(&e0));
-    HIPC(hipEventCreate(&e1));
-    HIPC(hipEventRecord(e0, s));
     const int K = x.prm.num_hash, W = K / 32;
     const int64_t n = x.n;
+    const int t = x.t;
     x.srp.alloc(sizeof(float) * (size_t)(x.d + 1) * K);
     if (srp) HIPC(hipMemcpyAsync(x.srp.p, srp, sizeof(float) * (size_t)(x.d + 1) * K, hipMemcpyDeviceToDevice, s));
     else {
@@ -277,20 +357,6 @@ void build_saalsh(Index& x, const float* srp, hipStream_t s)
         hipLaunchKernelGGL(k_gen_srp, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, x.srp.f(), cnt,
                            x.prm.seed ^ 0x53525031ull);
     }
-    // partitions
-    DevBuf ps, np;
-    ps.alloc(sizeof(int64_t) * (n + 2));
-    np.alloc(sizeof(int));
-    hipLaunchKernelGGL(k_partitions, dim3(1), dim3(64), 0, s, x.item_n2.d(), n, x.prm.b, ps.i64(), np.i());
-    HIPC(hipGetLastError());
-    int t = 0;
-    HIPC(hipMemcpyAsync(&t, np.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    x.t = t;
-    x.part_start_h.resize(t + 1);
-    HIPC(hipMemcpy(x.part_start_h.data(), ps.p, sizeof(int64_t) * (t + 1), hipMemcpyDeviceToHost));
-    x.part_start.alloc(sizeof(int64_t) * (t + 1));
-    HIPC(hipMemcpyAsync(x.part_start.p, x.part_start_h.data(), sizeof(int64_t) * (t + 1), hipMemcpyHostToDevice, s));
     // centroids and radii
     DevBuf cen64, r2, rad2bits, rad2;
     cen64.alloc(sizeof(double) * (size_t)t * x.ld);
@@ -301,34 +367,20 @@ void build_saalsh(Index& x, const float* srp, hipStream_t s)
     rad2.alloc(sizeof(double) * t);
     HIPC(hipMemsetAsync(rad2bits.p, 0, sizeof(unsigned long long) * t, s));
     {
-        // pieces of each partition
-        std::vector<int64_t> pb, pe, pp(t + 1, 0);
-        for (int j = 0; j < t; j++) {
-            pp[j] = (int64_t)pb.size();
-            for (int64_t b0 = x.part_start_h[j]; b0 < x.part_start_h[j + 1]; b0 += CEN_PIECE) {
-                pb.push_back(b0);
-                pe.push_back(std::min(b0 + CEN_PIECE, x.part_start_h[j + 1]));
-            }
-        }
-        pp[t] = (int64_t)pb.size();
-        const int64_t np_ = (int64_t)pb.size();
-        DevBuf d_pb, d_pe, d_pp, psum;
-        d_pb.alloc(sizeof(int64_t) * np_);
-        d_pe.alloc(sizeof(int64_t) * np_);
+        const int64_t max_pieces = (n + CEN_PIECE - 1) / CEN_PIECE + t;
+        DevBuf d_pp, psum;
         d_pp.alloc(sizeof(int64_t) * (t + 1));
-        psum.alloc(sizeof(double) * (size_t)np_ * x.ld);
-        HIPC(hipMemcpyAsync(d_pb.p, pb.data(), sizeof(int64_t) * np_, hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(d_pe.p, pe.data(), sizeof(int64_t) * np_, hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(d_pp.p, pp.data(), sizeof(int64_t) * (t + 1), hipMemcpyHostToDevice, s));
-        dim3 g((unsigned)np_, (unsigned)((x.ld + 63) / 64));
-        if (x.dtype == DT_F32) hipLaunchKernelGGL(k_centroid_piece<DT_F32>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), d_pb.i64(), d_pe.i64(), x.d, x.ld, psum.d());
-        else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_centroid_piece<DT_BF16>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), d_pb.i64(), d_pe.i64(), x.d, x.ld, psum.d());
-        else hipLaunchKernelGGL(k_centroid_piece<DT_FP8>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), d_pb.i64(), d_pe.i64(), x.d, x.ld, psum.d());
+        psum.alloc(sizeof(double) * (size_t)max_pieces * x.ld);
+        hipLaunchKernelGGL(k_pieces, dim3(1), dim3(1024), 0, s, x.part_start.i64(), (const int*)x.num_parts.i(), d_pp.i64());
+        dim3 g((unsigned)max_pieces, (unsigned)((x.ld + 63) / 64));
+        const int* npp = x.num_parts.i();
+        if (x.dtype == DT_F32) hipLaunchKernelGGL(k_centroid_piece<DT_F32>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), npp, d_pp.i64(), x.d, x.ld, psum.d());
+        else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_centroid_piece<DT_BF16>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), npp, d_pp.i64(), x.d, x.ld, psum.d());
+        else hipLaunchKernelGGL(k_centroid_piece<DT_FP8>, g, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), npp, d_pp.i64(), x.d, x.ld, psum.d());
         const int64_t tot = (int64_t)t * x.ld;
-        hipLaunchKernelGGL(k_centroid_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, psum.d(),
+        hipLaunchKernelGGL(k_centroid_final, dim3((unsigned)((tot + 3) / 4)), dim3(256), 0, s, psum.d(),
                            d_pp.i64(), x.part_start.i64(), t, x.d, x.ld, cen64.d(), x.centroid.f());
         HIPC(hipGetLastError());
-        HIPC(hipStreamSynchronize(s));   // host piece tables go out of scope
         dim3 g2((unsigned)((n + 255) / 256));
         if (x.dtype == DT_F32) hipLaunchKernelGGL(k_radius<DT_F32>, g2, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), t, n, x.d, x.ld, cen64.d(), r2.d(), (unsigned long long*)rad2bits.p);
         else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_radius<DT_BF16>, g2, dim3(256), 0, s, x.items.p, x.item_scales.f(), x.part_start.i64(), t, n, x.d, x.ld, cen64.d(), r2.d(), (unsigned long long*)rad2bits.p);
@@ -343,13 +395,6 @@ void build_saalsh(Index& x, const float* srp, hipStream_t s)
                rad2.d(), x.srp.f(), x.item_codes.u32(), s);
     project<1>(x.dtype, K, x.users.p, x.user_scales.f(), x.m, x.d, x.ld, nullptr, 1, nullptr, nullptr, nullptr,
                x.srp.f(), x.user_codes.u32(), s);
-    HIPC(hipEventRecord(e1, s));
-    HIPC(hipStreamSynchronize(s));
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    x.ms_saalsh = ms;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
 }
 
 }  // namespace rk

@@ -20,6 +20,9 @@
 //   candidates above tau and fails it).  Users that fail get a full-row FP64
 //   rescoring (k_fallback).
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "common.h"
 #include "internal.h"
@@ -451,6 +454,10 @@ static int resident_g(int G)
 template <int DT>
 static int resident_d(int ld, int G)
 {
+    if constexpr (DT == DT_BF16) {   // split BF16 rows of FP32 data: 3 x 32, 3 x 64
+        if (ld == 96) return resident_g<DT, 96>(G);
+        if (ld == 192) return resident_g<DT, 192>(G);
+    }
     switch (ld) {
     case 32: return resident_g<DT, 32>(G);
     case 64: return resident_g<DT, 64>(G);
@@ -459,16 +466,35 @@ static int resident_d(int ld, int G)
     }
 }
 
+// Cached per (device, dtype, ld, G): the occupancy query costs tens of microseconds.
 int topk_resident_blocks(int dtype, int ld, int G)
 {
-    if (dtype == DT_F32) return resident_d<DT_F32>(ld, G);
-    if (dtype == DT_BF16) return resident_d<DT_BF16>(ld, G);
-    return resident_d<DT_FP8>(ld, G);
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, dtype, ld, G);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int nb;
+    if (dtype == DT_F32) nb = resident_d<DT_F32>(ld, G);
+    else if (dtype == DT_BF16) nb = resident_d<DT_BF16>(ld, G);
+    else nb = resident_d<DT_FP8>(ld, G);
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = nb;
+    return nb;
 }
 
 template <int DT, int MODE>
 static void topk_dispatch(const TopkArgs& a, hipStream_t s)
 {
+    if constexpr (DT == DT_BF16) {
+        if (a.ld == 96) return topk_dispatch_g<DT, 96, MODE>(a, s);
+        if (a.ld == 192) return topk_dispatch_g<DT, 192, MODE>(a, s);
+    }
     switch (a.ld) {
     case 32: topk_dispatch_g<DT, 32, MODE>(a, s); break;
     case 64: topk_dispatch_g<DT, 64, MODE>(a, s); break;

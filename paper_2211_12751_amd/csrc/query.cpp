@@ -480,7 +480,7 @@ rkmips_status rkmips_get_saalsh(const rkmips_index* idx, int64_t* part_start, fl
         if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
         const Index& x = *(const Index*)idx;
         const int W = x.prm.num_hash / 32;
-        if (part_start) std::memcpy(part_start, x.part_start_h.data(), sizeof(int64_t) * (x.t + 1));
+        if (part_start) HIPC(hipMemcpy(part_start, x.part_start.p, sizeof(int64_t) * (x.t + 1), hipMemcpyDeviceToHost));
         if (centroid) {
             std::vector<float> c((size_t)x.t * x.ld);
             HIPC(hipMemcpy(c.data(), x.centroid.p, sizeof(float) * c.size(), hipMemcpyDeviceToHost));
@@ -514,7 +514,8 @@ rkmips_status rkmips_get_blocks(const rkmips_index* idx, int32_t* leaf_users, in
             HIPC(hipMemcpy(o.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
             for (int64_t i = 0; i < x.m; i++) leaf_users[i] = (int32_t)o[i];
         }
-        if (block_start) std::memcpy(block_start, x.block_start_h.data(), sizeof(int64_t) * (x.nblocks + 1));
+        if (block_start)
+            HIPC(hipMemcpy(block_start, x.block_start.p, sizeof(int64_t) * (x.nblocks + 1), hipMemcpyDeviceToHost));
         if (center) {
             std::vector<float> c((size_t)x.nblocks * x.ld);
             HIPC(hipMemcpy(c.data(), x.center.p, sizeof(float) * c.size(), hipMemcpyDeviceToHost));

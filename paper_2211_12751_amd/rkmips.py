@@ -23,6 +23,7 @@ F32, BF16, FP8_E4M3 = 0, 1, 2
 DTYPES = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
 FLAG_NO_BOUNDS, FLAG_FORCE_RECHECK, FLAG_NO_SAALSH, FLAG_NO_CERT, FLAG_NO_VECTOR_BOUND = 1, 2, 4, 8, 16
 FLAG_SAALSH_FILTER = 32
+FLAG_F32_MATRIX = 64
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "EBUSY"}
 
 
@@ -53,7 +54,8 @@ class rkmips_index_info(C.Structure):
                 ("max_rel_err_lambda32", C.c_double), ("ms_norms", C.c_double),
                 ("ms_lambda", C.c_double), ("ms_refine", C.c_double), ("ms_saalsh", C.c_double),
                 ("ms_cone", C.c_double), ("ms_total", C.c_double), ("device_bytes", C.c_int64),
-                ("ms_seed", C.c_double), ("ms_topk", C.c_double)]
+                ("ms_seed", C.c_double), ("ms_topk", C.c_double), ("mma_dtype", C.c_int32),
+                ("mma_terms", C.c_int32), ("err_fast", C.c_double)]
 
 
 class rkmips_serve_params(C.Structure):

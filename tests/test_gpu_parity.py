@@ -88,6 +88,13 @@ def test_toggles_give_identical_sets(R):
         _lists_equal(idx2.query(w.queries, None, ks), ref)
     finally:
         idx2.close()
+    # FP32 data scored on the FP32 matrix cores instead of split BF16 products
+    idx4 = _build(R, w, k_max, flags=R.FLAG_F32_MATRIX)
+    try:
+        _check_lambda(idx4, lam, k_max)
+        _lists_equal(idx4.query(w.queries, None, ks), ref)
+    finally:
+        idx4.close()
     # no slack: the certificate cannot hold, the fallback must give the same table
     idx3 = _build(R, w, k_max, topk_slack=0)
     try:
@@ -135,6 +142,23 @@ def test_zero_and_duplicate_vectors(R):
     try:
         _check_lambda(idx, lam, 10)
         _lists_equal(idx.query(w.queries, None, ks), [np.flatnonzero(r) for r in mem])
+    finally:
+        idx.close()
+
+
+@pytest.mark.parametrize("n", [2049, 5000, 70001])
+def test_item_order_merge_levels(R, n):
+    """Item order past one sort chunk (2048): ragged runs, runs with no partner, equal
+    norms (duplicated rows, ties by index) and zero rows (the largest key)."""
+    w = I.make("c1", n=n, m=300, d=16, nq=1, seed=n)
+    w.items[10:40] = w.items[9]
+    w.items[n - 50:] = w.items[3]
+    w.items[[0, 2048, n // 2]] = 0
+    idx = _build(R, w, 5)
+    try:
+        n2, order = O.item_order("f32", w.items, None)
+        go, gn2 = idx.item_order()
+        assert np.array_equal(go, order) and np.array_equal(gn2, n2[order])
     finally:
         idx.close()
 

@@ -358,3 +358,66 @@ def test_alg2_probe_everything_is_exact_and_no_is_sound():
                                           ucodes[u], 0.1, w.users, None, u, w.queries, None, qi, k)
                 if part == 0:
                     assert mem[qi, u] == 0
+
+
+# ---------------------------------------------------------------- Cone-Tree block data
+def test_cone_stats_single_user_blocks():
+    """A block of one user: the centre is that user's direction, theta = 0, omega = 0."""
+    g = np.random.default_rng(5)
+    U = g.standard_normal((7, 6)).astype(np.float32)
+    cen, ct, cw = O.cone_block_stats("f32", U, None, np.arange(7), np.arange(8))
+    Uv = U.astype(np.float64)
+    assert np.allclose(cen, Uv / np.linalg.norm(Uv, axis=1)[:, None], atol=1e-15)
+    assert np.allclose(ct, 1.0, atol=1e-15) and np.allclose(cw, 1.0, atol=1e-15)
+
+
+def test_cone_stats_symmetric_pair_closed_form():
+    """Users at angles +a and -a from the x axis, with different norms: the centre is the
+    x axis and both angles to it are a (so cos omega = cos a)."""
+    a = 0.3
+    U = np.array([[3 * np.cos(a), 3 * np.sin(a), 0.0], [0.5 * np.cos(a), -0.5 * np.sin(a), 0.0]], np.float32)
+    cen, ct, cw = O.cone_block_stats("f32", U, None, [0, 1], [0, 2])
+    Uv = U.astype(np.float64)
+    ang = np.arctan2(Uv[:, 1], Uv[:, 0])   # the stored (rounded) angles
+    mid = 0.5 * (ang[0] + ang[1])
+    assert np.allclose(cen[0], [np.cos(mid), np.sin(mid), 0.0], atol=1e-12)
+    assert np.allclose(ct, np.cos(0.5 * (ang[0] - ang[1])), atol=1e-12)
+    assert np.isclose(cw[0], ct.min(), atol=0)
+
+
+def test_cone_stats_orthonormal_block():
+    """The d unit axes: the centre is (1, ..., 1)/sqrt(d) and every cos theta is 1/sqrt(d)."""
+    d = 5
+    cen, ct, cw = O.cone_block_stats("f32", np.eye(d, dtype=np.float32) * 2, None, np.arange(d)[::-1], [0, d])
+    assert np.allclose(cen[0], np.full(d, 1 / np.sqrt(d)), atol=1e-15)
+    assert np.allclose(ct, 1 / np.sqrt(d), atol=1e-15) and np.isclose(cw[0], 1 / np.sqrt(d))
+
+
+def test_cone_stats_degenerate_blocks_and_fact2():
+    """A zero user or opposite unit vectors leave no cone; positive rescaling of users
+    (Fact 2) changes nothing."""
+    U = np.array([[1, 0], [-2, 0], [0, 0], [1, 1]], np.float32)
+    cen, ct, cw = O.cone_block_stats("f32", U, None, [0, 1, 2, 3], [0, 2, 4])
+    assert np.isnan(cen).all() and np.isnan(cw).all()
+    g = np.random.default_rng(6)
+    V = g.standard_normal((9, 4)).astype(np.float32)
+    s = np.array([1, 2, 4, 0.5, 8, 1, 2, 16, 0.25], np.float32)[:, None]
+    a = O.cone_block_stats("f32", V, None, np.arange(9), [0, 4, 9])
+    b = O.cone_block_stats("f32", V * s, None, np.arange(9), [0, 4, 9])
+    for x, y in zip(a, b):
+        assert np.allclose(x, y, atol=1e-14)
+
+
+def test_block_lower_bounds_by_hand():
+    """L^j(B) = min over B of lambda_u^(j)/||u||, here with norms 2 and 5."""
+    U = np.array([[2, 0], [3, 4], [1, 0]], np.float32)
+    lam = np.array([[4.0, 5.0, -1.0], [2.0, -10.0, -3.0]])
+    lb = O.block_lower_bounds("f32", U, None, lam, [1, 0, 2], [0, 2, 3])
+    assert np.array_equal(lb, np.array([[1.0, -1.0], [-2.0, -3.0]]))
+
+
+def test_values_widen_storage_formats():
+    bf = np.array([[0x3F80, 0xC040, 0x0000]], np.uint16)   # 1, -3, 0
+    assert np.array_equal(O.values("bf16", bf), [[1.0, -3.0, 0.0]])
+    f8 = np.array([[0x38, 0xB8, 0x7E]], np.uint8)           # 1, -1, 448
+    assert np.array_equal(O.values("fp8", f8, np.array([0.5], np.float32)), [[0.5, -0.5, 224.0]])
