@@ -202,16 +202,17 @@ static void build_lambda(Index& x, hipStream_t s)
     x.lam32.alloc(sizeof(float) * (size_t)x.prm.k_max * m);
 
     // matrix-core operands: the stored rows, or their split BF16 form for FP32 storage
-    DevBuf items3, users3;
+    // (the split user rows stay with the index for the query-side inner-product test)
+    DevBuf items3;
     const void* mi = x.items.p;
     const void* mu = x.users.p;
     if (x.mma_dtype != x.dtype) {
         items3.alloc(sizeof(uint16_t) * (size_t)x.n * x.mma_ld);
-        users3.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
+        x.users_mma.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
         launch_split_bf16(x.items.f(), x.n, x.ld, (uint16_t*)items3.p, 0, s);
-        launch_split_bf16(x.users.f(), m, x.ld, (uint16_t*)users3.p, 1, s);
+        launch_split_bf16(x.users.f(), m, x.ld, x.users_mma.u16(), 1, s);
         mi = items3.p;
-        mu = users3.p;
+        mu = x.users_mma.p;
     }
     TopkArgs ta{};
     ta.items = mi; ta.item_scales = x.item_scales.f(); ta.n = x.n;
@@ -552,10 +553,8 @@ rkmips_status rkmips_get_candidates(const rkmips_index* idx, int32_t* ids, float
                 tmax = std::max(tmax, tt[u * x.nseg + s]);
                 for (int i = 0; i < c; i++, k++) {
                     const uint2 e = buf[(u * x.nseg + s) * x.G + (p & 1) * (x.G / 2) + i];
-                    uint32_t o = e.x;
-                    uint32_t bits = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
-                    float f;
-                    std::memcpy(&f, &bits, 4);
+                    float f;   // raw score bits
+                    std::memcpy(&f, &e.x, 4);
                     if (ids) ids[ou * CP + k] = (int32_t)iorder[e.y];
                     if (scores) scores[ou * CP + k] = f;
                 }

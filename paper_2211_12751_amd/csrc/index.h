@@ -30,6 +30,7 @@ struct DevBuf {
     double* d() const { return (double*)p; }
     int* i() const { return (int*)p; }
     uint32_t* u32() const { return (uint32_t*)p; }
+    uint16_t* u16() const { return (uint16_t*)p; }
     int64_t* i64() const { return (int64_t*)p; }
 };
 
@@ -71,6 +72,7 @@ struct Index {
 
     // users in Cone-Tree leaf order
     DevBuf users, user_scales;   // [m x ld], [m]
+    DevBuf users_mma;            // split BF16 user rows [m x 3 ld] (FP32 data), leaf order
     DevBuf user_perm;            // uint32 [m] leaf position -> original user
     DevBuf user_n2;              // double [m] leaf order
     DevBuf unorm, cos_t, sin_t;  // float [m] leaf order
@@ -117,7 +119,7 @@ struct Index {
 
     int64_t device_bytes() const
     {
-        const DevBuf* all[] = {&items, &item_scales, &item_order, &item_n2, &users, &user_scales,
+        const DevBuf* all[] = {&items, &item_scales, &item_order, &item_n2, &users, &user_scales, &users_mma,
                                &user_perm, &user_n2, &unorm, &cos_t, &sin_t, &user_block,
                                &block_start, &center, &cos_w, &sin_w, &block_ok, &block_lb,
                                &lam64, &lam32, &cand, &cand_cnt, &cand_tau, &part_start, &num_parts,

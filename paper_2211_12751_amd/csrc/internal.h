@@ -177,6 +177,9 @@ struct QueryArgs {
     const uint32_t* perm;                            // leaf -> original
     const float* lam32; const double* lam64; int k_max;
     const void* queries; const float* query_scales; int64_t nq;   // padded copy [nq x ld]
+    // matrix-core operands of the inner-product test: the two arrays above, or their
+    // split BF16 rows [x 3 ld] for FP32 data (users [h | h | l], queries [h | l | h])
+    const void* mma_users; const void* mma_queries; int mma_dtype, mma_ld;
     const float* qnorm;                              // [nq]
     const float* cphi;                               // [nblocks x nq] cos of the query-centre angle
     const int* qslot;                                // [nq] slot of the query's k

@@ -76,8 +76,16 @@ __device__ __forceinline__ void decide(float x, float lam, float uq, bool force,
     else if (diff > e) yes |= 1u << r;
 }
 
+// Waves per SIMD the register budget is cut for: three, except for long fragments
+// (FP32 rows of 256, split BF16 rows of 192) that would spill.
+template <int DT, int DPT>
+constexpr int verify_wpe()
+{
+    return (DT == DT_F32 && DPT >= 256) ? 1 : (DPT * Elt<DT>::bytes >= 384 ? 2 : 3);
+}
+
 template <int DT, int DPT, int UBW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT >= 256) ? 1 : 3, 8))) void k_verify(QueryArgs a, int64_t q_begin, int64_t q_end)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<DT, DPT>(), 8))) void k_verify(QueryArgs a, int64_t q_begin, int64_t q_end)
 {
     constexpr int EB = Elt<DT>::bytes;
     constexpr int ROWB = DPT * EB;
@@ -98,6 +106,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     __shared__ unsigned int cnt_s[2];
     __shared__ uint32_t live_q[VF_MAXB];   // per block: queries of the tile not pruned by Lemma 2
     __shared__ unsigned long long base_s[2];
+    // "yes" answers are staged here and reserved in the global pool once per stage-full
+    // (one contended atomic per workgroup and flush instead of per tile)
+    constexpr int YS = 1024;
+    __shared__ unsigned long long ystage[YS];
+    __shared__ unsigned int ycnt;
+    __shared__ unsigned long long st_s[4];
 
     const int l = lane_id(), w = threadIdx.x >> 6, h = l >> 5;
     const int64_t u0 = (int64_t)blockIdx.x * UT;
@@ -138,7 +152,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         const int64_t u = u0 + ul_[cb];
         uok[cb] = u < a.m;
         const int64_t uu = uok[cb] ? u : u0;
-        const uint8_t* row = (const uint8_t*)a.users + uu * ROWB;
+        const uint8_t* row = (const uint8_t*)a.mma_users + uu * ROWB;
 #pragma unroll
         for (int t = 0; t < KSTEPS; t++) {
             i32x4 z = {0, 0, 0, 0};
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
         const int64_t q = qb + r;
         i32x4 v = {0, 0, 0, 0};
-        if (c < CH && q < q_end) v = *(const i32x4*)((const uint8_t*)a.queries + q * ROWB + c16 * 16);
+        if (c < CH && q < q_end) v = *(const i32x4*)((const uint8_t*)a.mma_queries + q * ROWB + c16 * 16);
         return v;
     };
     i32x4 pf[PREFETCH ? PF : 1];
@@ -177,6 +191,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         }
     };
     prefetch(q_begin);
+    if (threadIdx.x == 0) ycnt = 0u;
+    if (threadIdx.x < 4) st_s[threadIdx.x] = 0ull;
 
     unsigned long long n_node = 0, n_vec = 0, n_scored = 0, n_amb = 0;
 
@@ -301,18 +317,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         wy = __shfl(wy, 0);
         wa = __shfl(wa, 0);
         __syncthreads();
+        const unsigned int T = cnt_s[0];            // yes answers of this tile
+        const unsigned int y0 = ycnt;                // staged before it
+        const bool direct = T > (unsigned int)YS;    // too many for the stage: reserve now
+        const bool flush = !direct && y0 + T > (unsigned int)YS;
         if (threadIdx.x == 0) {
-            base_s[0] = cnt_s[0] ? atomicAdd(a.pool_count, (unsigned long long)cnt_s[0]) : 0ull;
+            unsigned long long b = 0ull;
+            if (direct) b = atomicAdd(a.pool_count, (unsigned long long)T);
+            else if (flush) b = atomicAdd(a.pool_count, (unsigned long long)y0);
+            base_s[0] = b;
             base_s[1] = cnt_s[1] ? atomicAdd(a.amb_count, (unsigned long long)cnt_s[1]) : 0ull;
         }
         __syncthreads();
+        if (flush) {   // workgroup-uniform
+            for (unsigned int i = threadIdx.x; i < y0; i += 256) {
+                const unsigned long long pos = base_s[0] + i;
+                if ((int64_t)pos < a.pool_cap) a.pool[pos] = ystage[i];
+            }
+            __syncthreads();
+        }
+        const unsigned int ybase = flush ? 0u : y0;
         if (ty | ta) {
-            int64_t py = (int64_t)base_s[0] + wy + iy - ny, pa = (int64_t)base_s[1] + wa + ia - na;
+            int64_t py = direct ? (int64_t)base_s[0] + wy + iy - ny : (int64_t)ybase + wy + iy - ny;
+            int64_t pa = (int64_t)base_s[1] + wa + ia - na;
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int64_t q = qb + mfma32_row(r, l);
                 if (yes & (1u << r)) {
-                    if (py < a.pool_cap) a.pool[py] = ((unsigned long long)a.qorig[q] << 32) | ouid[0];
+                    const unsigned long long e = ((unsigned long long)a.qorig[q] << 32) | ouid[0];
+                    if (direct) {
+                        if (py < a.pool_cap) a.pool[py] = e;
+                    } else {
+                        ystage[py] = e;
+                    }
                     py++;
                 }
                 if (amb & (1u << r)) {
@@ -321,17 +358,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                 }
             }
         }
+        if (threadIdx.x == 0) ycnt = direct ? y0 : ybase + T;
+    }
+    // the rest of the stage
+    __syncthreads();
+    const unsigned int yl = ycnt;
+    if (yl) {
+        if (threadIdx.x == 0) base_s[0] = atomicAdd(a.pool_count, (unsigned long long)yl);
+        __syncthreads();
+        for (unsigned int i = threadIdx.x; i < yl; i += 256) {
+            const unsigned long long pos = base_s[0] + i;
+            if ((int64_t)pos < a.pool_cap) a.pool[pos] = ystage[i];
+        }
     }
     n_node = wave_sum(n_node);
     n_vec = wave_sum(n_vec);
     n_scored = wave_sum(n_scored);
     n_amb = wave_sum(n_amb);
     if (l == 0) {
-        if (n_node) atomicAdd(&a.stats[0], n_node);
-        if (n_vec) atomicAdd(&a.stats[1], n_vec);
-        if (n_scored) atomicAdd(&a.stats[2], n_scored);
-        if (n_amb) atomicAdd(&a.stats[3], n_amb);
+        if (n_node) atomicAdd(&st_s[0], n_node);
+        if (n_vec) atomicAdd(&st_s[1], n_vec);
+        if (n_scored) atomicAdd(&st_s[2], n_scored);
+        if (n_amb) atomicAdd(&st_s[3], n_amb);
     }
+    __syncthreads();
+    if (threadIdx.x < 4 && st_s[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], st_s[threadIdx.x]);
 }
 
 // cos(phi) of every (block, query) pair: the FP32 inner product of the query with the
@@ -416,7 +467,11 @@ static void verify_g(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
 template <int DT>
 static void verify_d(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
 {
-    switch (a.ld) {
+    if constexpr (DT == DT_BF16) {   // split BF16 rows of FP32 data
+        if (a.mma_ld == 96) return verify_g<DT, 96>(a, q0, q1, s);
+        if (a.mma_ld == 192) return verify_g<DT, 192>(a, q0, q1, s);
+    }
+    switch (a.mma_ld) {
     case 32: verify_g<DT, 32>(a, q0, q1, s); break;
     case 64: verify_g<DT, 64>(a, q0, q1, s); break;
     case 128: verify_g<DT, 128>(a, q0, q1, s); break;
@@ -429,8 +484,8 @@ void launch_verify_range(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t
 {
     if (q1 <= q0 || a.m <= 0) return;
     if (a.nslots > VF_MAXSLOT) fail(RKMIPS_EINVAL, "internal: too many distinct k in one launch");
-    if (a.dtype == DT_F32) verify_d<DT_F32>(a, q0, q1, s);
-    else if (a.dtype == DT_BF16) verify_d<DT_BF16>(a, q0, q1, s);
+    if (a.mma_dtype == DT_F32) verify_d<DT_F32>(a, q0, q1, s);
+    else if (a.mma_dtype == DT_BF16) verify_d<DT_BF16>(a, q0, q1, s);
     else verify_d<DT_FP8>(a, q0, q1, s);
     HIPC(hipGetLastError());
 }

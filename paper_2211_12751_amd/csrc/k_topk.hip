@@ -105,7 +105,8 @@ __device__ __forceinline__ void wave_keep_positions(const uint32_t (&key)[GPL], 
 // Buffer compaction for the streaming pass, staged through LDS so that it needs few
 // registers (it runs rarely, and the main loop keeps its register budget for
 // occupancy): of the c0 entries at r0 and the c1 entries at r1, keep the C largest
-// (ties at the threshold in staging order) in r0[0, C) and return the C-th largest key.
+// (ties at the threshold in staging order) in r0[0, C) and return the C-th largest key
+// (orderable form; the entries themselves keep the raw score bits).
 __device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1, int c1, int C, int* hist,
                                              uint2* stage)
 {
@@ -115,7 +116,8 @@ __device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1,
         const uint2* src = i < c0 ? r0 + i : r1 + (i - c0);
         const unsigned long long raw = __hip_atomic_load((const unsigned long long*)src, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
-        stage[i] = make_uint2((uint32_t)raw, (uint32_t)(raw >> 32));
+        // buffers hold raw score bits; the selection works on orderable keys
+        stage[i] = make_uint2(f32_ord(__uint_as_float((uint32_t)raw)), (uint32_t)(raw >> 32));
     }
     __builtin_amdgcn_wave_barrier();
     uint32_t prefix = 0u, pmask = 0u;
@@ -160,7 +162,7 @@ __device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1,
         eq_before += __popcll(eb);
         const bool keep = gt || (eq && rank_eq < need);
         const uint64_t kb = ballot64(keep);
-        if (keep) r0[kept_before + __popcll(kb & lanemask_lt())] = e;
+        if (keep) r0[kept_before + __popcll(kb & lanemask_lt())] = make_uint2(__float_as_uint(ord_f32(e.x)), e.y);
         kept_before += __popcll(kb);
     }
     __builtin_amdgcn_wave_barrier();
@@ -279,7 +281,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     const float su = (DT == DT_FP8 && uok) ? a.user_scales[ug] : 1.0f;
     int cnt = 0;              // entries this lane appended to its half of the buffer
     const int HG = a.G / 2;
-    uint2* region = a.buf + ((uok ? ug : 0) * a.nseg_total + seg) * (int64_t)a.G + h * HG;   // half h
+    // the workgroup's users' buffers start at wbuf; this lane's half at wbuf + loff
+    // (a lane past the last user never appends: its threshold is +inf)
+    // (buffer stores: an offset outside the workgroup's records is dropped)
+    const int64_t wusers = std::min<int64_t>(TK_WAVES * 32, a.m - (int64_t)blockIdx.x * (TK_WAVES * 32));
+    const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
+        a.buf + (int64_t)blockIdx.x * (TK_WAVES * 32) * a.nseg_total * a.G, (short)0,
+        (int)(wusers * a.nseg_total * a.G * (int64_t)sizeof(uint2)), 0x00020000);
+    const uint32_t loff8 = 8u * (uint32_t)(((w * 32 + (l & 31)) * a.nseg_total + seg) * a.G + h * HG);
     float top[MODE == TK_SEED ? TK_T : 1];
 #pragma unroll
     for (int i = 0; i < (MODE == TK_SEED ? TK_T : 1); i++) top[i] = -__builtin_inff();
@@ -311,23 +320,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         }
     };
 
-    // scores of block b as they enter the epilogue (FP8 scaled, rows past the end -inf)
-    auto scores = [&](const f32x16& acc, int64_t b, float (&v)[16]) {
+    // scores of block b as they enter the epilogue, in place (FP8 scaled, rows past the
+    // end -inf)
+    auto scores = [&](f32x16& v, int64_t b) {
         const int64_t tt = b / BPT;
         const int rb = (int)(b % BPT);
         const int64_t base = seg0 + tt * IT + rb * 32;
-        const bool tail = base + 32 > seg1;
+        if constexpr (DT == DT_FP8) {
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            const int row = mfma32_row(r, l);
-            float x = acc[r];
-            if constexpr (DT == DT_FP8) x = (su * tscale[tt % 3][rb * 32 + row]) * x;
-            if (tail && base + row >= seg1) x = -__builtin_inff();
-            v[r] = x;
+            for (int r = 0; r < 16; r++) v[r] = (su * tscale[tt % 3][rb * 32 + mfma32_row(r, l)]) * v[r];
+        }
+        if (base + 32 > seg1) {   // wave-uniform: the segment's last block
+            const int rem = (int)(seg1 - base);
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                if (mfma32_row(r, l) >= rem) v[r] = -__builtin_inff();
         }
     };
     // branch-free part of the epilogue: the register top-T of the seed pass
-    auto early = [&](const float (&v)[16]) -> uint32_t {
+    auto early = [&](const f32x16& v) -> uint32_t {
         uint32_t pm = 0u;
         if constexpr (MODE == TK_SEED) {
 #pragma unroll
@@ -344,7 +355,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         return pm;
     };
     // appends of block b (main pass)
-    auto late = [&](const float (&v)[16], uint32_t, int64_t b) {
+    auto late = [&](const f32x16& v, uint32_t, int64_t b) {
         if constexpr (MODE == TK_MAIN) {
             // compaction of the users whose half-buffer could overflow in this block (a lane
             // appends at most 16 entries per block)
@@ -365,16 +376,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                 }
             }
             // each lane owns its half of the user's buffer: no cross-lane counts; a row
-            // that no lane passes costs one compare and one branch
-            const uint32_t pbase = (uint32_t)(seg0 + (b / BPT) * IT + (b % BPT) * 32);
+            // that no lane passes costs one compare and one branch.  Entries are the raw
+            // score bits and the item position, at 32-bit offsets from the workgroup's
+            // buffer base.
+            const uint32_t pbase = (uint32_t)(seg0 + (b / BPT) * IT + (b % BPT) * 32) + 4u * (uint32_t)h;
 #pragma unroll
             for (int r = 0; r < 16; r++) {
-                const bool pass = v[r] > theta;
-                if (ballot64(pass)) {
-                    if (pass) {
-                        region[cnt] = make_uint2(f32_ord(v[r]), pbase + (uint32_t)mfma32_row(r, l));
-                        cnt++;
-                    }
+                if (v[r] > theta) {
+                    const u32x2 e = {__float_as_uint(v[r]), pbase + (uint32_t)(8 * (r / 4) + (r % 4))};
+                    __builtin_amdgcn_raw_buffer_store_b64(e, wrsrc, (int)(loff8 + 8u * (uint32_t)cnt), 0, 0);
+                    cnt++;
                 }
             }
         }
@@ -387,9 +398,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         if (ntiles > 1) prefetch(1);
         f32x16 acc = mfma_block<DT, KSTEPS, LROW>(tile[0], 0, bfrag);
         for (int64_t b = 0; b < nblk; b++) {
-            float v[16];
-            scores(acc, b, v);
-            late(v, early(v), b);
+            scores(acc, b);
+            late(acc, early(acc), b);
             if (b + 1 < nblk) {
                 const int64_t tn = (b + 1) / BPT;
                 if ((b + 1) % BPT == 0) {      // block b + 1 opens tile tn
@@ -614,7 +624,7 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
 #pragma unroll
             for (int q = 1; q < 8; q++) p += j >= cum[q];
             const uint2 e = a.buf[(u * a.nseg + (p >> 1)) * (int64_t)a.G + (p & 1) * HG + (j - cum[p])];
-            key[i] = e.x;
+            key[i] = f32_ord(__uint_as_float(e.x));
             id[i] = e.y;
         }
     }

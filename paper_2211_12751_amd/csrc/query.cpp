@@ -54,7 +54,7 @@ int64_t Workspace::bytes_for(const Index& x, int64_t nq, int64_t pool_cap, int64
 {
     const int64_t eb = elt_bytes(x.dtype);
     return nq * x.ld * eb + nq * 5 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4 + 4) + amb_cap * 8 + 256 +
-           nq * x.nblocks * 4;
+           nq * x.nblocks * 4 + (x.mma_dtype != x.dtype ? nq * x.mma_ld * 2 : 0);
 }
 
 void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t amb_cap_req)
@@ -67,6 +67,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
     if (nq > nq_cap || nq_cap == 0) {
         const int64_t c = std::max<int64_t>(nq, 64);
         qpad.alloc((size_t)c * x.ld * elt_bytes(x.dtype));
+        if (x.mma_dtype != x.dtype) qsplit.alloc(sizeof(uint16_t) * (size_t)c * x.mma_ld);
         if (x.dtype == RKMIPS_FP8_E4M3) qsc.alloc(sizeof(float) * c);
         qnorm.alloc(sizeof(float) * c);
         qslot.alloc(sizeof(int) * c);
@@ -146,9 +147,14 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.block_lb = x.block_lb.f(); a.nblocks = x.nblocks; a.perm = x.user_perm.u32();
     a.lam32 = x.lam32.f(); a.lam64 = x.lam64.d(); a.k_max = x.prm.k_max;
     a.queries = w.qpad.p; a.query_scales = w.qsc.f(); a.nq = nq; a.qnorm = w.qnorm.f(); a.cphi = w.cphi.f();
+    const bool split = x.mma_dtype != x.dtype;
+    a.mma_users = split ? x.users_mma.p : x.users.p;
+    a.mma_queries = split ? w.qsplit.p : w.qpad.p;
+    a.mma_dtype = x.mma_dtype;
+    a.mma_ld = x.mma_ld;
     a.qslot = w.qslot.i(); a.qorig = w.qorig.u32(); a.qk = w.qk.i(); a.slot_k = w.slotk.i();
     a.flags = flags | x.prm.flags;
-    a.err_rel = fast_err_rel(x.d);
+    a.err_rel = x.err_fast;
     a.err_phi = phi_err(x.d);
     a.bound_slack = kBoundSlack;
     unsigned long long* c = (unsigned long long*)w.ctr.p;
@@ -174,6 +180,7 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
         launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig.u32(), nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
         QueryArgs a = make_query_args(x, w, nq, flags);
         launch_qnorm(x.dtype, w.qpad.p, w.qsc.f(), nq, x.d, x.ld, w.qnorm.f(), a.bad, s);
+        if (x.mma_dtype != x.dtype) launch_split_bf16(w.qpad.f(), nq, x.ld, w.qsplit.u16(), 0, s);
         if (!(a.flags & RKMIPS_FLAG_NO_BOUNDS)) launch_phi(a, w.cphi.f(), s);
         for (size_t g = 0; g < w.groups.size(); g++) {
             QueryArgs ag = a;
