@@ -138,6 +138,21 @@ static int device_cus(int dev)
     return cus;
 }
 
+// A second stream per device (default priority) for the build work that does not
+// depend on lambda; it lives as long as the process.
+static hipStream_t aux_stream(int dev)
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    HIPC(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams[dev] = st;
+    return st;
+}
+
 static void choose_topk(Index& x)
 {
     const int C = x.prm.k_max + x.prm.topk_slack;
@@ -184,7 +199,11 @@ static void choose_topk(Index& x)
     x.G = gpl * 64;
 }
 
-static void build_lambda(Index& x, hipStream_t s)
+// Exact lambda table over the users in their ORIGINAL order (users_o: padded copy
+// [m x ld], user_scales_o / user_n2_o in the same order); lambda rows and the raw
+// candidates are indexed by original user.  Stream-ordered, no host synchronisation.
+static void build_lambda(Index& x, const DevBuf& users_o, const float* user_scales_o, const double* user_n2_o,
+                         hipStream_t s)
 {
     choose_topk(x);
     const int64_t m = x.m;
@@ -202,21 +221,20 @@ static void build_lambda(Index& x, hipStream_t s)
     x.lam32.alloc(sizeof(float) * (size_t)x.prm.k_max * m);
 
     // matrix-core operands: the stored rows, or their split BF16 form for FP32 storage
-    // (the split user rows stay with the index for the query-side inner-product test)
-    DevBuf items3;
+    DevBuf items3, users3;
     const void* mi = x.items.p;
-    const void* mu = x.users.p;
+    const void* mu = users_o.p;
     if (x.mma_dtype != x.dtype) {
         items3.alloc(sizeof(uint16_t) * (size_t)x.n * x.mma_ld);
-        x.users_mma.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
-        launch_split_bf16(x.items.f(), x.n, x.ld, (uint16_t*)items3.p, 0, s);
-        launch_split_bf16(x.users.f(), m, x.ld, x.users_mma.u16(), 1, s);
+        users3.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
+        launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n, x.ld, (uint16_t*)items3.p, 0, s);
+        launch_mma_operand(x.mma_dtype, x.dtype, users_o.p, m, x.ld, (uint16_t*)users3.p, 1, s);
         mi = items3.p;
-        mu = x.users_mma.p;
+        mu = users3.p;
     }
     TopkArgs ta{};
     ta.items = mi; ta.item_scales = x.item_scales.f(); ta.n = x.n;
-    ta.users = mu; ta.user_scales = x.user_scales.f(); ta.m = m;
+    ta.users = mu; ta.user_scales = user_scales_o; ta.m = m;
     ta.d = x.d; ta.ld = x.mma_ld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
     ta.buf = (uint2*)buf.p; ta.cnt = (int*)cnt.p; ta.tau = (float*)tau.p;
     Events ev(6);
@@ -238,10 +256,10 @@ static void build_lambda(Index& x, hipStream_t s)
 
     RefineArgs ra{};
     ra.items = x.items.p; ra.item_scales = x.item_scales.f(); ra.n = x.n;
-    ra.users = x.users.p; ra.user_scales = x.user_scales.f(); ra.m = m;
+    ra.users = users_o.p; ra.user_scales = user_scales_o; ra.m = m;
     ra.d = x.d; ra.ld = x.ld; ra.nseg = x.nseg; ra.C = x.C; ra.G = x.G; ra.k_max = x.prm.k_max;
     ra.buf = (const uint2*)buf.p; ra.cnt = (const int*)cnt.p; ra.tau = (const float*)tau.p;
-    ra.item_n2_sorted = x.item_n2.d(); ra.seg_len = x.seg_len; ra.user_n2 = x.user_n2.d();
+    ra.item_n2_sorted = x.item_n2.d(); ra.seg_len = x.seg_len; ra.user_n2 = user_n2_o;
     ra.force_fail = (x.prm.flags & RKMIPS_FLAG_NO_CERT) ? 1 : 0;
     ra.lam64 = x.lam64.d(); ra.lam32 = x.lam32.f();
     ra.fail_list = (int*)fail_list.p; ra.fail_count = (int*)fail_count.p;
@@ -266,7 +284,7 @@ static void build_lambda(Index& x, hipStream_t s)
     HIPC(hipMemcpyAsync(hs + 2, fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
     x.lam_ev.assign(4, nullptr);
     for (int i = 0; i < 4; i++) std::swap(x.lam_ev[i], ev.ev[i]);
-    // keep the raw candidates for inspection (per leaf-order user)
+    // keep the raw candidates for inspection (per original user)
     x.cand.swap(buf);
     x.cand_cnt.swap(cnt);
     x.cand_tau.swap(tau);
@@ -315,22 +333,35 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     PinBuf hnp;
     hnp.alloc(sizeof(int));
     start_partitions(x, (int*)hnp.p, s);
+    // padded copy of the users in their original order for the lambda build
+    DevBuf users_o, uscales_o;
+    users_o.alloc((size_t)m * x.ld * eb);
+    if (x.dtype == RKMIPS_FP8_E4M3) uscales_o.alloc(sizeof(float) * m);
+    launch_gather_rows(x.dtype, users, x.d, user_scales, nullptr, m, x.d, users_o.p, x.ld, uscales_o.f(), s);
     HIPC(hipEventRecord(ev.ev[1], s));
 
-    // ---- Cone-Tree over user directions; users are stored in leaf order
-    build_cone(x, users, user_scales, n2_users_orig.d(), s);
-    range_check(x, (const unsigned long long*)hst.p);   // the cone build has waited for the copy
-    x.t = *(const int*)hnp.p;
-    HIPC(hipEventRecord(ev.ev[2], s));
+    // The exact lambda table (matrix-core bound) runs on the caller's stream while the
+    // Cone-Tree and the SA-ALSH index (latency bound, host-checked) run on a second one;
+    // they meet before the block lower bounds, which need both.
+    build_lambda(x, users_o, uscales_o.f(), n2_users_orig.d(), s);
+    const hipStream_t s2 = aux_stream(x.device);
+    HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
+    {
+        mem::StreamScope scope2(s2);
+        HIPC(hipEventRecord(ev.ev[2], s2));
+        // ---- Cone-Tree over user directions; users are stored in leaf order
+        build_cone(x, users, user_scales, n2_users_orig.d(), s2);
+        range_check(x, (const unsigned long long*)hst.p);   // the cone build has waited for the copy
+        x.t = *(const int*)hnp.p;
+        HIPC(hipEventRecord(ev.ev[4], s2));
+        // ---- SA-ALSH index
+        build_saalsh(x, srp, s2);
+        HIPC(hipEventRecord(ev.ev[5], s2));
+    }
+    HIPC(hipStreamWaitEvent(s, ev.ev[5], 0));
 
-    // ---- exact lambda table
-    build_lambda(x, s);
-
-    // ---- per-block quantities that need lambda (L^j(B)) and the SA-ALSH index
+    // ---- per-block quantities that need lambda (L^j(B))
     finish_blocks(x, s);
-    HIPC(hipEventRecord(ev.ev[4], s));
-    build_saalsh(x, srp, s);
-    HIPC(hipEventRecord(ev.ev[5], s));
     HIPC(hipEventRecord(ev.ev[3], s));
     HIPC(hipStreamSynchronize(s));
     x.ms_saalsh = ev_ms(ev.ev[4], ev.ev[5]);
@@ -346,7 +377,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
         x.ms_refine = ev_ms(le[1], le[2]);
     }
     x.ms_norms = ev_ms(ev.ev[0], ev.ev[1]);
-    x.ms_cone = ev_ms(ev.ev[1], ev.ev[2]);
+    x.ms_cone = ev_ms(ev.ev[2], ev.ev[4]);
     x.ms_total = ev_ms(ev.ev[0], ev.ev[3]);
 }
 
@@ -451,9 +482,12 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
         x->n = n; x->m = m; x->d = d; x->dtype = dtype; x->prm = prm;
         x->ld = padded_dim(d, dtype);
         // FP32 storage is scored on the BF16 matrix cores as split products where the
-        // tripled rows fit the kernels (ld <= 64), unless the caller asks for FP32 MFMA
+        // tripled rows fit the kernels (ld <= 64), unless the caller asks for FP32 MFMA.
+        // FP8 storage is widened to BF16 operands: the FP8 matrix cores' accumulation is
+        // not within an FP32 rounding model (measured error up to 2^-10.6 of the sum of
+        // |terms| per instruction), so no a-priori bound would hold for them.
         const bool split = dtype == RKMIPS_F32 && x->ld <= 64 && !(prm.flags & RKMIPS_FLAG_F32_MATRIX);
-        x->mma_dtype = split ? RKMIPS_BF16 : dtype;
+        x->mma_dtype = split ? RKMIPS_BF16 : (dtype == RKMIPS_FP8_E4M3 ? DT_FP8B : dtype);
         x->mma_ld = split ? 3 * x->ld : x->ld;
         x->err_fast = split ? split_err_rel(d) : fast_err_rel(d);
         HIPC(hipGetDevice(&x->device));
@@ -479,7 +513,9 @@ rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
         o->ms_norms = x.ms_norms; o->ms_lambda = x.ms_lambda; o->ms_refine = x.ms_refine;
         o->ms_saalsh = x.ms_saalsh; o->ms_cone = x.ms_cone; o->ms_total = x.ms_total;
         o->ms_seed = x.ms_seed; o->ms_topk = x.ms_topk;
-        o->mma_dtype = x.mma_dtype; o->mma_terms = x.mma_ld / x.ld; o->err_fast = x.err_fast;
+        o->mma_dtype = x.mma_dtype == DT_FP8B ? RKMIPS_BF16 : x.mma_dtype;
+        o->mma_terms = x.mma_ld / x.ld;
+        o->err_fast = x.err_fast;
         o->device_bytes = x.device_bytes();
     });
 }
@@ -490,11 +526,7 @@ rkmips_status rkmips_get_lambda(const rkmips_index* idx, int32_t k, double* out_
         if (!idx || !out_m) fail(RKMIPS_EINVAL, "NULL argument");
         const Index& x = *(const Index*)idx;
         if (k < 1 || k > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
-        std::vector<double> row(x.m);
-        std::vector<uint32_t> perm(x.m);
-        HIPC(hipMemcpy(row.data(), x.lam64.d() + (int64_t)(k - 1) * x.m, sizeof(double) * x.m, hipMemcpyDeviceToHost));
-        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < x.m; i++) out_m[perm[i]] = row[i];
+        HIPC(hipMemcpy(out_m, x.lam64.d() + (int64_t)(k - 1) * x.m, sizeof(double) * x.m, hipMemcpyDeviceToHost));
     });
 }
 
@@ -504,11 +536,7 @@ rkmips_status rkmips_get_lambda32(const rkmips_index* idx, int32_t k, float* out
         if (!idx || !out_m) fail(RKMIPS_EINVAL, "NULL argument");
         const Index& x = *(const Index*)idx;
         if (k < 1 || k > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
-        std::vector<float> row(x.m);
-        std::vector<uint32_t> perm(x.m);
-        HIPC(hipMemcpy(row.data(), x.lam32.f() + (int64_t)(k - 1) * x.m, sizeof(float) * x.m, hipMemcpyDeviceToHost));
-        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < x.m; i++) out_m[perm[i]] = row[i];
+        HIPC(hipMemcpy(out_m, x.lam32.f() + (int64_t)(k - 1) * x.m, sizeof(float) * x.m, hipMemcpyDeviceToHost));
     });
 }
 
@@ -536,15 +564,14 @@ rkmips_status rkmips_get_candidates(const rkmips_index* idx, int32_t* ids, float
         std::vector<uint2> buf((size_t)x.m * per);
         std::vector<int> cnt((size_t)x.m * x.nseg * 2);
         std::vector<float> tt((size_t)x.m * x.nseg);
-        std::vector<uint32_t> perm(x.m), iorder(x.n);
+        std::vector<uint32_t> iorder(x.n);
         HIPC(hipMemcpy(buf.data(), x.cand.p, sizeof(uint2) * buf.size(), hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(cnt.data(), x.cand_cnt.p, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(tt.data(), x.cand_tau.p, sizeof(float) * tt.size(), hipMemcpyDeviceToHost));
-        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(iorder.data(), x.item_order.p, sizeof(uint32_t) * x.n, hipMemcpyDeviceToHost));
         const int CP = x.G * x.nseg;
-        for (int64_t u = 0; u < x.m; u++) {
-            const int64_t ou = perm[u];
+        for (int64_t u = 0; u < x.m; u++) {   // buffers are kept per original user
+            const int64_t ou = u;
             int k = 0;
             float tmax = -INFINITY;
             for (int p = 0; p < 2 * x.nseg; p++) {

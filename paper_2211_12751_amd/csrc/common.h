@@ -12,7 +12,15 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 #define RK_WAVE 64
 
-enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
+enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2,
+       // matrix-core operand form only: FP8 e4m3 codes widened to BF16 (every e4m3 value
+       // is a BF16 value), with the per-row FP8 scales applied after the product
+       DT_FP8B = 3 };
+
+// operand types whose rows carry a per-row scale
+template <int DT> constexpr bool dt_scaled = DT == DT_FP8 || DT == DT_FP8B;
+// operand types multiplied on the BF16 matrix cores
+template <int DT> constexpr bool dt_bf16_mma = DT == DT_BF16 || DT == DT_FP8B;
 
 // ------------------------------------------------------------------ element decoding
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -31,7 +39,7 @@ template <int DT>
 __device__ __forceinline__ float elem_f32(const void* base, int64_t idx)
 {
     if constexpr (DT == DT_F32) return ((const float*)base)[idx];
-    else if constexpr (DT == DT_BF16) return bf16_to_f32(((const uint16_t*)base)[idx]);
+    else if constexpr (DT == DT_BF16 || DT == DT_FP8B) return bf16_to_f32(((const uint16_t*)base)[idx]);
     else return e4m3_to_f32(((const uint8_t*)base)[idx]);
 }
 
@@ -39,6 +47,7 @@ template <int DT> struct Elt;
 template <> struct Elt<DT_F32> { typedef float T; static constexpr int bytes = 4; };
 template <> struct Elt<DT_BF16> { typedef uint16_t T; static constexpr int bytes = 2; };
 template <> struct Elt<DT_FP8> { typedef uint8_t T; static constexpr int bytes = 1; };
+template <> struct Elt<DT_FP8B> { typedef uint16_t T; static constexpr int bytes = 2; };
 
 // Canonical FP64 inner product of two stored rows over the first d elements:
 // FP32/BF16 data: ((0 + a0 b0) + a1 b1) + ... in index order (products exact in FP64);

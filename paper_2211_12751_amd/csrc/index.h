@@ -57,7 +57,7 @@ struct IdleTail {
 struct Index {
     IdleTail idle_tail;
     int device = 0;
-    int mma_dtype = 0, mma_ld = 0;   // matrix-core operand type and row length of the lambda build
+    int mma_dtype = 0, mma_ld = 0;   // matrix-core operand type (DT_*) and row length
     double err_fast = 0;             // error bound of its fast scores, relative to ||u|| ||p||
     int num_cus = 256;
     int64_t n = 0, m = 0;
@@ -72,7 +72,7 @@ struct Index {
 
     // users in Cone-Tree leaf order
     DevBuf users, user_scales;   // [m x ld], [m]
-    DevBuf users_mma;            // split BF16 user rows [m x 3 ld] (FP32 data), leaf order
+    DevBuf users_mma;            // matrix-core user rows (split FP32 or widened FP8), leaf order
     DevBuf user_perm;            // uint32 [m] leaf position -> original user
     DevBuf user_n2;              // double [m] leaf order
     DevBuf unorm, cos_t, sin_t;  // float [m] leaf order

@@ -32,6 +32,10 @@ void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, i
 // users and queries [h | h | l] (user_layout 1); their BF16 dot product approximates the
 // FP32 one within split_err_rel.
 void launch_split_bf16(const float* src, int64_t rows, int ld, uint16_t* dst, int user_layout, hipStream_t s);
+// Matrix-core operand rows [rows x mma_ld] (BF16 bits) from stored rows [rows x ld]:
+// split FP32 (see launch_split_bf16) or widened FP8 codes.
+void launch_mma_operand(int mma_dtype, int dtype, const void* src, int64_t rows, int ld, uint16_t* dst,
+                        int user_layout, hipStream_t s);
 // Sort (key, val) pairs ascending by key then val, n <= 2^31.  keys/vals and the
 // scratch arrays tmp_keys/tmp_vals hold cap >= n rounded up to min(2048, next power of
 // two of n) entries; the sorted pairs end in keys/vals[0, n).
@@ -104,7 +108,7 @@ void launch_fallback(int dtype, const RefineArgs& a, double* scratch, int64_t sc
 
 // ---------------------------------------------------------------- cone tree
 struct ConeLevelArgs {
-    const float* unit;     // [m x ld] unit users (original order)
+    const uint16_t* unit;  // [m x ld] BF16 unit users (original order)
     int ld, d;
     const uint32_t* perm;  // position -> user
     const int64_t* seg_start;  // [nseg+1] this level's segments (sorted, last = m)
@@ -135,12 +139,11 @@ struct LeafArgs {
     const void* users;       // leaf order [m x ld]
     const float* user_scales;
     const double* user_n2;   // leaf order
-    const float* unit;       // original order unit rows [m x ld]
     const uint32_t* perm;    // leaf position -> original user
     const int64_t* block_start;
     int64_t nblocks, m;
     int d, ld, k_max;
-    const double* lam64;     // [k_max x m] leaf order
+    const double* lam64;     // [k_max x m] original user order
     float* center;           // [nblocks x ld] unit centres
     float* cos_w; float* sin_w; int* block_ok;   // [nblocks]
     float* unorm; float* cos_t; float* sin_t;    // [m] leaf order
@@ -175,7 +178,7 @@ struct QueryArgs {
     const float* center; const float* cos_w; const float* sin_w; const int* block_ok;
     const float* block_lb; int64_t nblocks;
     const uint32_t* perm;                            // leaf -> original
-    const float* lam32; const double* lam64; int k_max;
+    const float* lam32; const double* lam64; int k_max;   // [k_max x m], original user order
     const void* queries; const float* query_scales; int64_t nq;   // padded copy [nq x ld]
     // matrix-core operands of the inner-product test: the two arrays above, or their
     // split BF16 rows [x 3 ld] for FP32 data (users [h | h | l], queries [h | l | h])

@@ -38,14 +38,20 @@ __device__ __forceinline__ int64_t cone_pivot(const ConeLevelArgs& a, int64_t st
     return st + (int64_t)(r % (uint64_t)sz);
 }
 
-// <a, b> of two unit rows, one lane per row (16-byte loads; the rows of a wave are
-// independent, so their loads overlap).
-__device__ __forceinline__ float row_dot(const float* a, const float* b, int ld)
+// <a, b> of two BF16 unit rows, one lane per row (16-byte loads of 8 values; the rows of
+// a wave are independent, so their loads overlap).  The split geometry only shapes the
+// tree (which never changes a result), so BF16 directions suffice and halve the bytes.
+__device__ __forceinline__ float row_dot(const uint16_t* a, const uint16_t* b, int ld)
 {
     float acc = 0.f;
-    for (int c = 0; c < ld; c += 4) {
-        const f32x4 x = *(const f32x4*)(a + c), y = *(const f32x4*)(b + c);
-        acc += x[0] * y[0] + x[1] * y[1] + x[2] * y[2] + x[3] * y[3];
+    for (int c = 0; c < ld; c += 8) {
+        const i32x4 x = *(const i32x4*)(a + c), y = *(const i32x4*)(b + c);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t xu = (uint32_t)x[e], yu = (uint32_t)y[e];
+            acc = fmaf(__uint_as_float(xu << 16), __uint_as_float(yu << 16), acc);
+            acc = fmaf(__uint_as_float(xu & 0xffff0000u), __uint_as_float(yu & 0xffff0000u), acc);
+        }
     }
     return acc;
 }
@@ -85,7 +91,7 @@ __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
         const int s = a.seg[p];
         ai = a.act[s];
         if (ai >= 0) {
-            const float* up = a.unit + (int64_t)a.perm[p] * a.ld;
+            const uint16_t* up = a.unit + (int64_t)a.perm[p] * a.ld;
             if (phase == 0) {
                 const int64_t st = a.seg_start[s], sz = a.seg_start[s + 1] - st;
                 const float dv = row_dot(up, a.unit + (int64_t)a.perm[cone_pivot(a, st, sz)] * a.ld, a.ld);
@@ -290,9 +296,10 @@ __global__ void k_cone_scatter(ConeLevelArgs a, uint32_t* new_perm)
 }
 
 
+// BF16 unit rows (original order) for the split phases.
 template <int DT>
 __global__ void k_unit(const void* X, const float* scales, const double* n2, int64_t rows, int d, int ld,
-                       float* out)
+                       uint16_t* out)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= rows * ld) return;
@@ -304,7 +311,8 @@ __global__ void k_unit(const void* X, const float* scales, const double* n2, int
         if constexpr (DT == DT_FP8) x *= (double)scales[r];
         v = (float)(x / sqrt(n2[r]));
     }
-    out[t] = v;
+    const uint32_t b = __float_as_uint(v);
+    out[t] = (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);   // round to nearest even
 }
 
 // Per block (one wave, one user per lane): unit centre (FP64 mean of the unit user
@@ -321,10 +329,13 @@ __global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
     const int sz = (int)(en - st);
     const bool mine = l < sz;
     const int64_t p = st + l;
-    const uint32_t ou = mine ? a.perm[p] : 0u;
+    // FP64 unit vector of this lane's user, read from the stored row (leaf order)
+    const double un_l = mine ? sqrt(a.user_n2[p]) : 0.0;
+    const double inv = un_l > 0.0 ? 1.0 / un_l : 0.0;
+    const double sc_l = (DT == DT_FP8 && mine) ? (double)a.user_scales[p] : 1.0;
     double cn2 = 0.0;
     for (int i = 0; i < a.d; i++) {
-        double v = mine ? (double)a.unit[(int64_t)ou * a.ld + i] : 0.0;
+        double v = mine ? (double)elem_f32<DT>(a.users, p * a.ld + i) * sc_l * inv : 0.0;
         v = wave_sum(v) / (double)sz;
         cn2 += v * v;
         if (l == 0) cen[w][i] = (float)v;
@@ -369,8 +380,8 @@ __global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
 
 // L^j(B) = min over the block of lambda_u^(j) / ||u||, rounded down to FP32 (-inf for a
 // block without usable angles, so it is never pruned).  One wave per block, one user
-// per lane (blocks hold at most 64 users), one coalesced row of lambda per j.
-__global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const double* user_n2,
+// per lane (blocks hold at most 64 users); lambda rows are in original user order.
+__global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const uint32_t* perm, const double* user_n2,
                                                   const int64_t* block_start, const int* block_ok, int64_t nblocks,
                                                   int64_t m, int k_max, float* lb)
 {
@@ -380,10 +391,12 @@ __global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const dou
     const int64_t st = block_start[b], en = block_start[b + 1];
     const bool ok = block_ok[b] != 0;
     const double un0 = st + l < en ? sqrt(user_n2[st + l]) : 1.0;
+    const int64_t o0 = st + l < en ? (int64_t)perm[st + l] : 0;
     for (int j = 0; j < k_max; j++) {
         double mn = __builtin_inf();
         for (int64_t q = st + l; q < en; q += 64) {
-            const double v = lam64[(int64_t)j * m + q] / (q == st + l ? un0 : sqrt(user_n2[q]));
+            const double v = q == st + l ? lam64[(int64_t)j * m + o0] / un0
+                                         : lam64[(int64_t)j * m + perm[q]] / sqrt(user_n2[q]);
             mn = v < mn ? v : mn;
         }
         mn = wave_min(mn);
@@ -408,13 +421,13 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     const int64_t m = x.m;
     const int ld = x.ld;
     DevBuf unit, perm_a, perm_b, seg_a, seg_b, dot_l, left, lrank, blk_cnt;
-    unit.alloc(sizeof(float) * (size_t)m * ld);
+    unit.alloc(sizeof(uint16_t) * (size_t)m * ld);
     {
         const int64_t tot = m * ld;
         dim3 g((unsigned)((tot + 255) / 256)), b(256);
-        if (x.dtype == DT_F32) hipLaunchKernelGGL(k_unit<DT_F32>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.f());
-        else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_unit<DT_BF16>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.f());
-        else hipLaunchKernelGGL(k_unit<DT_FP8>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.f());
+        if (x.dtype == DT_F32) hipLaunchKernelGGL(k_unit<DT_F32>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());
+        else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_unit<DT_BF16>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());
+        else hipLaunchKernelGGL(k_unit<DT_FP8>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());
     }
     perm_a.alloc(sizeof(uint32_t) * m);
     perm_b.alloc(sizeof(uint32_t) * m);
@@ -446,7 +459,7 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     auto level_args = [&](int level) {
         const int c = level & 1, n = c ^ 1;
         ConeLevelArgs a{};
-        a.unit = unit.f(); a.ld = ld; a.d = x.d; a.perm = perm_a.u32();
+        a.unit = unit.u16(); a.ld = ld; a.d = x.d; a.perm = perm_a.u32();
         a.seg_start = d_start[c].i64(); a.next_start = d_start[n].i64();
         a.ctl = d_ctl.i64(); a.ctl_cur = c; a.level = level; a.leaf = x.prm.leaf_size;
         a.seed = x.prm.seed; a.m = m;
@@ -501,6 +514,10 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     if (x.dtype == RKMIPS_FP8_E4M3) x.user_scales.alloc(sizeof(float) * m);
     launch_gather_rows(x.dtype, users, x.d, user_scales, x.user_perm.u32(), m, x.d, x.users.p, ld,
                        x.user_scales.f(), s);
+    if (x.mma_dtype != x.dtype) {   // matrix-core rows for the query-side inner-product test
+        x.users_mma.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
+        launch_mma_operand(x.mma_dtype, x.dtype, x.users.p, m, x.ld, x.users_mma.u16(), 1, s);
+    }
     x.user_n2.alloc(sizeof(double) * m);
     launch_permute_f64(n2_orig, x.user_perm.u32(), m, x.user_n2.d(), s);
 
@@ -514,7 +531,7 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     x.user_block.alloc(sizeof(int) * m);
     LeafArgs la{};
     la.dtype = x.dtype; la.users = x.users.p; la.user_scales = x.user_scales.f(); la.user_n2 = x.user_n2.d();
-    la.unit = unit.f(); la.perm = x.user_perm.u32(); la.block_start = x.block_start.i64();
+    la.perm = x.user_perm.u32(); la.block_start = x.block_start.i64();
     la.nblocks = x.nblocks; la.m = m; la.d = x.d; la.ld = ld; la.k_max = x.prm.k_max;
     la.center = x.center.f(); la.cos_w = x.cos_w.f(); la.sin_w = x.sin_w.f(); la.block_ok = x.block_ok.i();
     la.unorm = x.unorm.f(); la.cos_t = x.cos_t.f(); la.sin_t = x.sin_t.f(); la.user_block = x.user_block.i();
@@ -530,7 +547,7 @@ void finish_blocks(Index& x, hipStream_t s)
     const int64_t tot = x.nblocks * x.prm.k_max;
     x.block_lb.alloc(sizeof(float) * tot);
     hipLaunchKernelGGL(k_block_lb, dim3((unsigned)((x.nblocks + 3) / 4)), dim3(256), 0, s, x.lam64.d(),
-                       x.user_n2.d(), x.block_start.i64(), x.block_ok.i(), x.nblocks, x.m, x.prm.k_max,
+                       x.user_perm.u32(), x.user_n2.d(), x.block_start.i64(), x.block_ok.i(), x.nblocks, x.m, x.prm.k_max,
                        x.block_lb.f());
     HIPC(hipGetLastError());
 }

@@ -134,6 +134,30 @@ void launch_split_bf16(const float* src, int64_t rows, int ld, uint16_t* dst, in
     HIPC(hipGetLastError());
 }
 
+// FP8 e4m3 codes [rows x ld] -> BF16 [rows x ld] (exact: every e4m3 value is a BF16
+// value), for the BF16 matrix cores; the row scales stay separate.
+__global__ void k_widen_fp8(const uint8_t* src, int64_t count, uint16_t* dst)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) dst[t] = (uint16_t)(__float_as_uint(e4m3_to_f32(src[t])) >> 16);
+}
+
+void launch_mma_operand(int mma_dtype, int dtype, const void* src, int64_t rows, int ld, uint16_t* dst,
+                        int user_layout, hipStream_t s)
+{
+    if (rows <= 0) return;
+    if (dtype == DT_F32 && mma_dtype == DT_BF16) {
+        launch_split_bf16((const float*)src, rows, ld, dst, user_layout, s);
+    } else if (dtype == DT_FP8 && mma_dtype == DT_FP8B) {
+        const int64_t cnt = rows * ld;
+        hipLaunchKernelGGL(k_widen_fp8, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (const uint8_t*)src,
+                           cnt, dst);
+        HIPC(hipGetLastError());
+    } else {
+        fail(RKMIPS_EINVAL, "internal: no matrix-core operand form for this storage type");
+    }
+}
+
 // ------------------------------------------------------------------ norm sort keys
 __global__ void k_norm_keys(const double* n2, int64_t n, int64_t cap, uint64_t* keys, uint32_t* vals)
 {

@@ -47,17 +47,11 @@ __device__ __forceinline__ f32x16 verify_block(const uint8_t* qt, const i32x4 (&
             const f32x4 b4 = __builtin_bit_cast(f32x4, bfrag[t]);
 #pragma unroll
             for (int e = 0; e < 4; e++) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc, 0, 0, 0);
-        } else if constexpr (DT == DT_BF16) {
+        } else if constexpr (dt_bf16_mma<DT>) {
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af),
                                                          __builtin_bit_cast(bf16x8, bfrag[t]), acc, 0, 0, 0);
         } else {
-            const i32x4 bf = bfrag[t];
-            const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[0], af[1]});
-            const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){af[2], af[3]});
-            const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[0], bf[1]});
-            const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bf[2], bf[3]});
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc, 0, 0, 0);
+            static_assert(dt_bf16_mma<DT>, "FP8 codes reach the matrix cores widened to BF16");
         }
     }
     return acc;
@@ -77,11 +71,12 @@ __device__ __forceinline__ void decide(float x, float lam, float uq, bool force,
 }
 
 // Waves per SIMD the register budget is cut for: three, except for long fragments
-// (FP32 rows of 256, split BF16 rows of 192) that would spill.
+// (FP32 rows of 256, split BF16 rows of 192, scaled rows of 256 bytes) that would spill.
 template <int DT, int DPT>
 constexpr int verify_wpe()
 {
-    return (DT == DT_F32 && DPT >= 256) ? 1 : (DPT * Elt<DT>::bytes >= 384 ? 2 : 3);
+    return (DT == DT_F32 && DPT >= 256) ? 1
+                                          : ((DPT * Elt<DT>::bytes >= 384 || (dt_scaled<DT> && DPT * Elt<DT>::bytes >= 256)) ? 2 : 3);
 }
 
 template <int DT, int DPT, int UBW>
@@ -128,7 +123,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
     for (int e = threadIdx.x; e < a.nslots * UT; e += 256) {
         const int sl = e / UT, ul = e % UT;
         const int64_t u = u0 + ul;
-        lam_s[sl][ul] = u < a.m ? a.lam32[(int64_t)(a.slot_k[sl] - 1) * a.m + u] : 0.f;
+        lam_s[sl][ul] = u < a.m ? a.lam32[(int64_t)(a.slot_k[sl] - 1) * a.m + a.perm[u]] : 0.f;
     }
     for (int b = threadIdx.x; b < nbb; b += 256) {
         const int bg = bfirst + b;
@@ -161,7 +156,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
         un[cb] = a.unorm[uu];
         ct[cb] = a.cos_t[uu];
         st[cb] = a.sin_t[uu];
-        su[cb] = DT == DT_FP8 ? a.user_scales[uu] : 1.f;
+        su[cb] = dt_scaled<DT> ? a.user_scales[uu] : 1.f;
         bl[cb] = a.user_block[uu] - bfirst;
         ouid[cb] = a.perm[uu];
     }
@@ -186,7 +181,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
             const int64_t q = qb + threadIdx.x;
             const bool ok = q < q_end;
             pqn = ok ? a.qnorm[q] : 0.f;
-            pqs = (ok && DT == DT_FP8) ? a.query_scales[q] : 1.f;
+            pqs = (ok && dt_scaled<DT>) ? a.query_scales[q] : 1.f;
             pqsl = ok ? a.qslot[q] : 0;
         }
     };
@@ -274,33 +269,66 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
                 n_amb += __popc(amb);
             }
         } else {
-            // narrow types: the matrix cores cost less than the per-pair bound, so every
-            // tile with a query the node-level test leaves alive is multiplied, and the
-            // vector-level test and the inner-product test share one pass
-            const uint32_t qlive = blk < VF_MAXB ? live_q[blk] : 0xffffffffu;
-            if (ballot64(uok[0] && qlive != 0u)) {
+            // narrow types: the matrix cores cost less than any per-pair bound, so every
+            // tile with a query the node-level test leaves alive is multiplied and the
+            // inner-product test decides each of its pairs directly (for a multiplied pair
+            // the vector-level bound of Lemma 3 could only repeat what the product shows).
+            const int nvalid = (int)((q_end - qb) < 32 ? (q_end - qb) : 32);
+            const uint32_t vmask = nvalid == 32 ? 0xffffffffu : ((1u << nvalid) - 1u);
+            const uint32_t hmask = 0x0f0f0f0fu << (4 * h);   // the lane's 16 rows
+            const uint32_t qlive = uok[0] ? (blk < VF_MAXB ? live_q[blk] : vmask) : 0u;
+            if (uok[0]) n_node += __popc(vmask & hmask & ~qlive);
+            if (ballot64(qlive != 0u)) {
                 const f32x16 acc = verify_block<DT, KSTEPS, LROW>(qt, bfrag[0]);
+                const uint32_t mine = qlive & hmask;
+                n_scored += __popc(mine);
+                // queries arrive sorted by k: a tile usually has one k slot, whose lambda
+                // terms then stay in registers
+                const int sl0 = qslot_s[0], sl1 = qslot_s[nvalid - 1];
+                // (err_rel widened by 2^-20 so the regrouped FP32 product cannot undercut it)
+                const float uerr = (float)(a.err_rel * (1.0 + 0x1p-20)) * un[0];
+                // bit r of on16: the lane's row r (query mfma32_row(r, l)) is live
+                const uint32_t mh = mine >> (4 * h);
+                const uint32_t on16 = (mh & 0xfu) | ((mh >> 4) & 0xf0u) | ((mh >> 8) & 0xf00u) | ((mh >> 12) & 0xf000u);
+                if (sl0 == sl1) {
+                    // yes beyond +e, a close call within +-e, no below -e; with lambda = -inf
+                    // every difference is +inf, so every live query is a yes
+                    const float lam = lam_s[sl0][ul];
+                    const bool lam_inf = lam == -__builtin_inff();
+                    const float elam = (lam_inf ? 0.f : fabsf(lam) * 0x1p-23f) + (float)a.d * 0x1p-120f;
 #pragma unroll
-                for (int r = 0; r < 16; r++) {
-                    const int qi = mfma32_row(r, l);
-                    if (!uok[0] || qb + qi >= q_end) continue;
-                    const f32x4 ph = blk < VF_MAXB ? phi_s[blk][qi] : f32x4{1.f, 0.f, 0.f, 2.f};
-                    if (ph[3] == 1.f) { n_node++; continue; }
-                    const float lam = lam_s[qslot_s[qi]][ul];
-                    const float qn = qn_s[qi];
-                    if (use_vec && ph[3] == 0.f) {
-                        const float ubv = qn * un[0] * (ph[0] * ct[0] + ph[1] * st[0] + ph[2] + a.bound_slack);
-                        if (ubv < lam - fabsf(lam) * 0x1p-22f) { n_vec++; continue; }
+                    for (int r = 0; r < 16; r++) {
+                        const int qi = mfma32_row(r, l);
+                        float x = acc[r];
+                        if constexpr (dt_scaled<DT>) x = (su[0] * qs_s[qi]) * x;
+                        const float e = fmaf(uerr, qn_s[qi], elam);
+                        const float diff = x - lam;
+                        yes |= (uint32_t)(diff > e) << r;
+                        amb |= (uint32_t)(fabsf(diff) <= e) << r;
                     }
-                    float x = acc[r];
-                    if constexpr (DT == DT_FP8) x = (su[0] * qs_s[qi]) * x;
-                    n_scored++;
-                    decide(x, lam, un[0] * qn, force, r, a, yes, amb);
+                    yes &= on16;
+                    amb &= on16;
+                    if (force) {
+                        yes = lam_inf ? on16 : 0u;
+                        amb = lam_inf ? 0u : on16;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; r++) {
+                        const int qi = mfma32_row(r, l);
+                        const float lam = lam_s[qslot_s[qi]][ul];
+                        float x = acc[r];
+                        if constexpr (dt_scaled<DT>) x = (su[0] * qs_s[qi]) * x;
+                        const bool li = lam == -__builtin_inff();
+                        const float e = fmaf(uerr, qn_s[qi], (li ? 0.f : fabsf(lam) * 0x1p-23f) + (float)a.d * 0x1p-120f);
+                        const float diff = x - lam;
+                        yes |= (uint32_t)(li || (!force && diff > e)) << r;
+                        amb |= (uint32_t)(!li && (force || fabsf(diff) <= e)) << r;
+                    }
+                    yes &= on16;
+                    amb &= on16;
                 }
                 n_amb += __popc(amb);
-            } else if (uok[0]) {
-#pragma unroll
-                for (int r = 0; r < 16; r++) n_node += qb + mfma32_row(r, l) < q_end ? 1 : 0;
             }
         }
 
@@ -486,7 +514,8 @@ void launch_verify_range(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t
     if (a.nslots > VF_MAXSLOT) fail(RKMIPS_EINVAL, "internal: too many distinct k in one launch");
     if (a.mma_dtype == DT_F32) verify_d<DT_F32>(a, q0, q1, s);
     else if (a.mma_dtype == DT_BF16) verify_d<DT_BF16>(a, q0, q1, s);
-    else verify_d<DT_FP8>(a, q0, q1, s);
+    else if (a.mma_dtype == DT_FP8B) verify_d<DT_FP8B>(a, q0, q1, s);
+    else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());
 }
 
@@ -517,7 +546,7 @@ __global__ void k_recheck(QueryArgs a, int64_t namb, const int* reject)
     const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
     const float sq = DT == DT_FP8 ? a.query_scales[q] : 1.f;
     const double s = canon_dot2<DT>(a.users, u, a.ld, su, a.queries, q, a.ld, sq, a.d);
-    if (s >= a.lam64[(int64_t)(k - 1) * a.m + u]) {
+    if (s >= a.lam64[(int64_t)(k - 1) * a.m + a.perm[u]]) {
         const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
         if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)a.qorig[q] << 32) | a.perm[u];
     }

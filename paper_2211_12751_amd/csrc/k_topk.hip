@@ -199,18 +199,11 @@ __device__ __forceinline__ f32x16 mfma_block(const uint8_t* tile, int row0, cons
             const f32x4 b4 = __builtin_bit_cast(f32x4, bfrag[t]);
 #pragma unroll
             for (int e = 0; e < 4; e++) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc, 0, 0, 0);
-        } else if constexpr (DT == DT_BF16) {
+        } else if constexpr (dt_bf16_mma<DT>) {
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[t]),
                                                          __builtin_bit_cast(bf16x8, bfrag[t]), acc, 0, 0, 0);
         } else {
-            // FP8 e4m3: 32x32x16 over 8 codes per lane and MFMA (two per fragment)
-            const i32x4 av = af[t], bv = bfrag[t];
-            const long a0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){av[0], av[1]});
-            const long a1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){av[2], av[3]});
-            const long b0 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bv[0], bv[1]});
-            const long b1 = __builtin_bit_cast(long, (int __attribute__((ext_vector_type(2)))){bv[2], bv[3]});
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc, 0, 0, 0);
+            static_assert(dt_bf16_mma<DT>, "FP8 codes reach the matrix cores widened to BF16");
         }
     }
     return acc;
@@ -240,13 +233,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     constexpr int ROWB = DPT * EB;                // bytes of one stored row
     constexpr int LROW = ROWB + 16;               // padded LDS row (bank spread)
     constexpr int KSTEPS = ROWB / 32;             // 16-byte fragments per half row
-    constexpr int IT = ROWB >= 1024 ? 32 : TK_IT; // items per tile
+    constexpr int IT = ROWB >= 512 ? 32 : TK_IT;  // items per tile (LDS: two tiles per workgroup)
     constexpr int BPT = IT / 32;                  // MFMA blocks per tile
     constexpr int CHUNKS = IT * (ROWB / 16);      // 16-byte chunks per tile
     constexpr int PF = (CHUNKS + 255) / 256;      // chunks per thread
     constexpr int SGPL = MODE == TK_MAIN ? GPL : 1;
     __shared__ __attribute__((aligned(16))) uint8_t tile[2][IT * LROW];
-    __shared__ float tscale[3][DT == DT_FP8 ? IT : 1];
+    __shared__ float tscale[3][dt_scaled<DT> ? IT : 1];
     __shared__ int hist_all[TK_WAVES][MODE == TK_MAIN ? 256 : 1];
     __shared__ uint2 stage_all[TK_WAVES][SGPL * 64];
 
@@ -278,7 +271,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     float theta = -__builtin_inff();
     if (MODE == TK_MAIN && uok && a.theta_init) theta = a.theta_init[ug * a.theta_stride];
     if (!uok) theta = __builtin_inff();   // +inf: nothing enters
-    const float su = (DT == DT_FP8 && uok) ? a.user_scales[ug] : 1.0f;
+    const float su = (dt_scaled<DT> && uok) ? a.user_scales[ug] : 1.0f;
     int cnt = 0;              // entries this lane appended to its half of the buffer
     const int HG = a.G / 2;
     // the workgroup's users' buffers start at wbuf; this lane's half at wbuf + loff
@@ -314,7 +307,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
             const int c = threadIdx.x + 256 * e;
             if (c < CHUNKS) *(i32x4*)(dst + (c / (ROWB / 16)) * LROW + (c % (ROWB / 16)) * 16) = pf[e];
         }
-        if (DT == DT_FP8 && threadIdx.x < IT) {
+        if (dt_scaled<DT> && threadIdx.x < IT) {
             const int64_t v = seg0 + tt * IT + threadIdx.x;
             tscale[tt % 3][threadIdx.x] = v < seg1 ? a.item_scales[item_at<MODE>(v, a.n, a.ns)] : 0.f;
         }
@@ -326,7 +319,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         const int64_t tt = b / BPT;
         const int rb = (int)(b % BPT);
         const int64_t base = seg0 + tt * IT + rb * 32;
-        if constexpr (DT == DT_FP8) {
+        if constexpr (dt_scaled<DT>) {
 #pragma unroll
             for (int r = 0; r < 16; r++) v[r] = (su * tscale[tt % 3][rb * 32 + mfma32_row(r, l)]) * v[r];
         }
@@ -492,7 +485,8 @@ int topk_resident_blocks(int dtype, int ld, int G)
     int nb;
     if (dtype == DT_F32) nb = resident_d<DT_F32>(ld, G);
     else if (dtype == DT_BF16) nb = resident_d<DT_BF16>(ld, G);
-    else nb = resident_d<DT_FP8>(ld, G);
+    else if (dtype == DT_FP8B) nb = resident_d<DT_FP8B>(ld, G);
+    else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     std::lock_guard<std::mutex> g(mu);
     cache[key] = nb;
     return nb;
@@ -519,7 +513,8 @@ void launch_topk(int dtype, const TopkArgs& a, hipStream_t s)
     if (a.m <= 0 || a.v1 <= a.v0) return;
     if (dtype == DT_F32) topk_dispatch<DT_F32, TK_MAIN>(a, s);
     else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_MAIN>(a, s);
-    else topk_dispatch<DT_FP8, TK_MAIN>(a, s);
+    else if (dtype == DT_FP8B) topk_dispatch<DT_FP8B, TK_MAIN>(a, s);
+    else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());
 }
 
@@ -529,7 +524,8 @@ void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s)
     if (a.v1 - a.v0 > a.ns || a.ns > a.n || !a.theta_out) fail(RKMIPS_EINVAL, "internal: bad seed sample");
     if (dtype == DT_F32) topk_dispatch<DT_F32, TK_SEED>(a, s);
     else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_SEED>(a, s);
-    else topk_dispatch<DT_FP8, TK_SEED>(a, s);
+    else if (dtype == DT_FP8B) topk_dispatch<DT_FP8B, TK_SEED>(a, s);
+    else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());
 }
 

@@ -180,7 +180,7 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
         launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig.u32(), nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
         QueryArgs a = make_query_args(x, w, nq, flags);
         launch_qnorm(x.dtype, w.qpad.p, w.qsc.f(), nq, x.d, x.ld, w.qnorm.f(), a.bad, s);
-        if (x.mma_dtype != x.dtype) launch_split_bf16(w.qpad.f(), nq, x.ld, w.qsplit.u16(), 0, s);
+        if (x.mma_dtype != x.dtype) launch_mma_operand(x.mma_dtype, x.dtype, w.qpad.p, nq, x.ld, w.qsplit.u16(), 0, s);
         if (!(a.flags & RKMIPS_FLAG_NO_BOUNDS)) launch_phi(a, w.cphi.f(), s);
         for (size_t g = 0; g < w.groups.size(); g++) {
             QueryArgs ag = a;

@@ -23,7 +23,7 @@ struct Workspace {
     int64_t nq_cap = 0, pool_cap = 0, amb_cap = 0;
     DevBuf qpad, qsc, qnorm, qslot, qorig, qk, slotk, offsets, pool, ids, amb, ctr;
     DevBuf cphi;                            // [nblocks x nq] query-centre cosines
-    DevBuf qsplit;                          // split BF16 query rows (FP32 data)
+    DevBuf qsplit;                          // matrix-core query rows (split FP32 or widened FP8)
     DevBuf qcnt, ids2;                      // per-query counts, scatter target of the lists
     DevBuf sa_scratch, sa_answer, sa_phi;   // SA-ALSH stage
     PinBuf h_qslot, h_qorig, h_qk, h_slotk, h_offsets, h_ids, h_ctr;
