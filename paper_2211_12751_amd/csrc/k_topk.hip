@@ -14,11 +14,7 @@
 //   When a buffer fills, the wave compacts it to its C best entries with a wave radix
 //   select and raises the threshold to the running C-th best.  The final threshold tau
 //   bounds every item left out.
-// Pass 2 (k_refine): canonical FP64 rescoring of the candidates, ranking, and a
-//   certificate: tau + eps(u) <= lambda64^(k_max) proves no left-out item can enter
-//   the top k_max (a seed estimate that was too high leaves fewer than k_max
-//   candidates above tau and fails it).  Users that fail get a full-row FP64
-//   rescoring (k_fallback).
+// Pass 2 (canonical FP64 rescoring and the certificate) is in k_refine.hip.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -31,75 +27,6 @@ namespace rk {
 
 static constexpr int TK_WAVES = 4;
 static constexpr int TK_IT = 64;  // items per LDS tile (two 32-row MFMA blocks)
-
-// ------------------------------------------------------------------ wave radix select
-// C-th largest of the first c keys held GPL per lane (entry i of lane l is position
-// l + 64 i); *need_eq receives how many keys equal to it belong to the C largest.
-template <int GPL>
-__device__ __forceinline__ uint32_t wave_kth_key(const uint32_t (&key)[GPL], int c, int C, int* hist, int* need_eq)
-{
-    const int l = lane_id();
-    uint32_t prefix = 0u, pmask = 0u;
-    int need = C;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = l; b < 256; b += 64) hist[b] = 0;
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int i = 0; i < GPL; i++) {
-            if (64 * i >= c) break;   // wave-uniform: the rest of the slots are empty
-            if (l + 64 * i < c && (key[i] & pmask) == prefix) atomicAdd(&hist[(key[i] >> shift) & 255u], 1);
-        }
-        __builtin_amdgcn_wave_barrier();
-        int h[4], x = 0;
-#pragma unroll
-        for (int e = 0; e < 4; e++) { h[e] = hist[4 * l + e]; x += h[e]; }
-        const int incl = wave_incl_scan(x);
-        const int total = __shfl(incl, 63);
-        int above = total - incl;  // keys whose digit lies in higher lanes' bins
-        int sel = -1, sel_above = 0;
-#pragma unroll
-        for (int e = 3; e >= 0; e--) {
-            if (sel < 0 && above < need && need <= above + h[e]) { sel = 4 * l + e; sel_above = above; }
-            above += h[e];
-        }
-        const uint64_t bal = ballot64(sel >= 0);
-        const int src = bal ? __builtin_ctzll(bal) : 0;
-        const int dsel = __shfl(sel, src);
-        const int dabove = __shfl(sel_above, src);
-        prefix |= (uint32_t)dsel << shift;
-        pmask |= 0xffu << shift;
-        need -= dabove;
-        __builtin_amdgcn_wave_barrier();
-    }
-    *need_eq = need;
-    return prefix;
-}
-
-// Output positions (or -1) of the kept entries: keys > T, then keys == T in position
-// order until need_eq of them are kept.
-template <int GPL>
-__device__ __forceinline__ void wave_keep_positions(const uint32_t (&key)[GPL], int c, uint32_t T, int need_eq,
-                                                    int (&outpos)[GPL])
-{
-    const int l = lane_id();
-    int eq_before = 0, kept_before = 0;
-#pragma unroll
-    for (int i = 0; i < GPL; i++) outpos[i] = -1;
-#pragma unroll
-    for (int i = 0; i < GPL; i++) {
-        if (64 * i >= c) break;
-        const bool valid = l + 64 * i < c;
-        const bool gt = valid && key[i] > T;
-        const bool eq = valid && key[i] == T;
-        const uint64_t eb = ballot64(eq);
-        const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
-        eq_before += __popcll(eb);
-        const bool keep = gt || (eq && rank_eq < need_eq);
-        const uint64_t kb = ballot64(keep);
-        outpos[i] = keep ? kept_before + __popcll(kb & lanemask_lt()) : -1;
-        kept_before += __popcll(kb);
-    }
-}
 
 // ------------------------------------------------------------------ fused GEMM + top-k
 // Buffer compaction for the streaming pass, staged through LDS so that it needs few
@@ -526,358 +453,6 @@ void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s)
     else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_SEED>(a, s);
     else if (dtype == DT_FP8B) topk_dispatch<DT_FP8B, TK_SEED>(a, s);
     else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
-    HIPC(hipGetLastError());
-}
-
-// ------------------------------------------------------------------ FP64 refine + certificate
-static constexpr int RF_MAXN = 2048;  // candidates per user across segments
-static constexpr int RF_GPL = RF_MAXN / 64;
-
-// Canonical FP64 score of user row u against item row p (FP32/BF16: index-order sum of
-// exact products; FP8: exact code sum times the scale product), with 16-byte loads.
-template <int DT>
-__device__ __forceinline__ double canon_dot_vec(const void* U, int64_t u, float su, const void* P, int64_t p,
-                                                float sp, int d, int ld)
-{
-    constexpr int EB = Elt<DT>::bytes;
-    constexpr int PER = 16 / EB;
-    const uint8_t* ur = (const uint8_t*)U + u * (int64_t)ld * EB;
-    const uint8_t* pr = (const uint8_t*)P + p * (int64_t)ld * EB;
-    double acc = 0.0;
-    for (int c0 = 0; c0 < d; c0 += PER) {
-        const i32x4 a4 = *(const i32x4*)(ur + c0 * EB);
-        const i32x4 b4 = *(const i32x4*)(pr + c0 * EB);
-        const int lim = d - c0 < PER ? d - c0 : PER;
-#pragma unroll
-        for (int e = 0; e < PER; e++) {
-            if (e >= lim) break;
-            float x, y;
-            if constexpr (DT == DT_F32) {
-                x = __int_as_float(a4[e]);
-                y = __int_as_float(b4[e]);
-            } else if constexpr (DT == DT_BF16) {
-                x = bf16_to_f32((uint16_t)((uint32_t)a4[e >> 1] >> (16 * (e & 1))));
-                y = bf16_to_f32((uint16_t)((uint32_t)b4[e >> 1] >> (16 * (e & 1))));
-            } else {
-                x = e4m3_to_f32((uint8_t)((uint32_t)a4[e >> 2] >> (8 * (e & 3))));
-                y = e4m3_to_f32((uint8_t)((uint32_t)b4[e >> 2] >> (8 * (e & 3))));
-            }
-            acc = __fma_rn((double)x, (double)y, acc);
-        }
-    }
-    if constexpr (DT == DT_FP8) acc = ((double)su * (double)sp) * acc;
-    return acc;
-}
-
-__device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double v)
-{
-    // non-negative doubles order like their bit patterns; skip the atomic when it cannot win
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    if (b > __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(addr, b);
-}
-
-// One wave per user: gather the candidates of all segments, keep the C best by the fast
-// score (wave radix select), rescore those in canonical FP64, rank them, write
-// lambda64/lambda32 for j <= k_max and test the certificate
-//   max(tau_s, cut) + eps(u) <= lambda64^(k_max)
-// where every item outside the rescored set scored at most max(tau_s, cut) in the fast
-// arithmetic (tau_s: segment thresholds of the streaming pass; cut: the C-th best fast
-// score among all candidates when some were dropped here).
-template <int DT, int GPL, bool FAST>
-__device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint32_t* sid, double* s64,
-                            float* sraw, double* lam_row, float* raw_row, int* hist)
-{
-    const int l = lane_id();
-    // gather every segment's buffer straight into registers (entry j = lane + 64 i)
-    // part p = 2 s + h: half h of segment s's buffer
-    int cum[9];
-    cum[0] = 0;
-    float tau_max = -__builtin_inff();
-    for (int p = 0; p < 8; p++) {
-        const int s = p >> 1;
-        const int c = s < a.nseg ? a.cnt[(u * a.nseg + s) * 2 + (p & 1)] : 0;
-        cum[p + 1] = cum[p] + c;
-        if (s < a.nseg && (p & 1) == 0) tau_max = fmaxf(tau_max, a.tau[u * a.nseg + s]);
-    }
-    const int N = cum[8];
-    if (N > GPL * 64) {   // more candidates than this instance holds: the wide pass takes it
-        if (l == 0) a.spill[atomicAdd(a.spill_count, 1)] = (int)u;
-        return;
-    }
-    const int HG = a.G / 2;
-    uint32_t key[GPL], id[GPL];
-#pragma unroll
-    for (int i = 0; i < GPL; i++) {
-        key[i] = 0u;
-        id[i] = 0u;
-    }
-#pragma unroll
-    for (int i = 0; i < GPL; i++) {
-        if (64 * i >= N) break;   // wave-uniform
-        const int j = l + 64 * i;
-        if (j < N) {
-            int p = 0;
-#pragma unroll
-            for (int q = 1; q < 8; q++) p += j >= cum[q];
-            const uint2 e = a.buf[(u * a.nseg + (p >> 1)) * (int64_t)a.G + (p & 1) * HG + (j - cum[p])];
-            key[i] = f32_ord(__uint_as_float(e.x));
-            id[i] = e.y;
-        }
-    }
-    float cut = -__builtin_inff();
-    int Nk = N;
-    int outpos[GPL];
-    if (N > a.C) {
-        int need_eq;
-        const uint32_t T = wave_kth_key<GPL>(key, N, a.C, hist, &need_eq);
-        wave_keep_positions<GPL>(key, N, T, need_eq, outpos);
-        cut = ord_f32(T);
-        Nk = a.C;
-    } else {
-#pragma unroll
-        for (int i = 0; i < GPL; i++) outpos[i] = (l + 64 * i < N) ? l + 64 * i : -1;
-    }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int i = 0; i < GPL; i++) {
-        if (64 * i >= N) break;
-        if (outpos[i] >= 0) {
-            skey[outpos[i]] = key[i];
-            sid[outpos[i]] = id[i];
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
-    const double un = sqrt(a.user_n2[u]);
-    const double M = sqrt(a.item_n2_sorted[0]);
-    double worst_raw = 0.0, worst32 = 0.0;
-    double lk = -__builtin_inf();   // lambda64^(k_max) over the candidates (-inf with fewer)
-    auto stat = [&](double lv, float raw) {
-        if (lv != 0.0 && lv > -__builtin_inf() && fabs(lv) >= 1e-3 * un * M) {
-            worst_raw = fmax(worst_raw, fabs((double)raw - lv) / fabs(lv));
-            worst32 = fmax(worst32, fabs((double)(float)lv - lv) / fabs(lv));
-        }
-    };
-    if (FAST || Nk <= 64) {
-        // one candidate per lane; the ranks come from two bitonic sorts across the wave
-        double v = -__builtin_inf();
-        uint32_t rk = 0u;   // orderable fast-score key (0 sorts below every score)
-        int idx = l;
-        if (l < Nk) {
-            const int64_t p = sid[l];
-            if (p < a.n) {   // never produced by k_topk; guards the loads below
-                const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-                v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-            }
-            rk = skey[l];
-        }
-#pragma unroll
-        for (int kk = 2; kk <= 64; kk <<= 1)
-#pragma unroll
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                const double ov = __shfl_xor(v, j);
-                const int oi = __shfl_xor(idx, j);
-                const uint32_t ok = __shfl_xor(rk, j);
-                const bool lower = (l & j) == 0, desc = (l & kk) == 0;
-                const bool mine_first = v > ov || (v == ov && idx < oi);
-                if (mine_first != (lower == desc)) {
-                    v = ov;
-                    idx = oi;
-                }
-                if ((rk > ok) != (lower == desc) && rk != ok) rk = ok;
-            }
-        // lane r: the r-th largest canonical score and the r-th largest fast score
-        for (int r = l; r < a.k_max; r += 64) {
-            const double lv = r == l ? v : -__builtin_inf();
-            a.lam64[(int64_t)r * a.m + u] = lv;
-            a.lam32[(int64_t)r * a.m + u] = (float)lv;
-            if (r == l && l < Nk) stat(lv, ord_f32(rk));
-        }
-        lk = a.k_max <= 64 ? __shfl(v, a.k_max - 1) : -__builtin_inf();
-    } else if constexpr (!FAST) {
-        for (int j = l; j < Nk; j += 64) {
-            const int64_t p = sid[j];
-            double v = -__builtin_inf();
-            if (p < a.n) {
-                const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-                v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-            }
-            s64[j] = v;
-            sraw[j] = ord_f32(skey[j]);
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int j = l; j < Nk; j += 64) {
-            const double x = s64[j];
-            const float y = sraw[j];
-            int r64 = 0, rr = 0;
-            for (int i = 0; i < Nk; i++) {
-                const double xi = s64[i];
-                const float yi = sraw[i];
-                r64 += (xi > x) || (xi == x && i < j);
-                rr += (yi > y) || (yi == y && i < j);
-            }
-            if (r64 < a.k_max) lam_row[r64] = x;
-            if (rr < a.k_max) raw_row[rr] = y;
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int r = l; r < a.k_max; r += 64) {
-            const double lv = r < Nk ? lam_row[r] : -__builtin_inf();
-            a.lam64[(int64_t)r * a.m + u] = lv;
-            a.lam32[(int64_t)r * a.m + u] = (float)lv;
-            if (r < Nk) stat(lv, raw_row[r]);
-        }
-        lk = Nk >= a.k_max ? lam_row[a.k_max - 1] : -__builtin_inf();
-    }
-    worst_raw = wave_max(worst_raw);
-    worst32 = wave_max(worst32);
-    if (l == 0) {
-        if (worst_raw > 0.0) atomic_max_pos(a.max_raw_err_bits, worst_raw);
-        if (worst32 > 0.0) atomic_max_pos(a.max_raw_err_bits + 1, worst32);
-    }
-    bool ok = !a.force_fail;
-    const float worst_out = fmaxf(tau_max, cut);
-    if (ok && worst_out > -__builtin_inff()) {
-        const double bound = (double)worst_out + a.err_rel * un * M + (double)a.d * 0x1p-125 * (un + M + 1.0);
-        ok = bound <= lk;
-    }
-    if (!ok && l == 0) {
-        const int pos = atomicAdd(a.fail_count, 1);
-        a.fail_list[pos] = (int)u;
-    }
-}
-
-
-// One wave per user (all users, or the users listed in a.list when it is given).  The
-// narrow instance (GPL = 8, C <= 64) keeps its state small for occupancy and hands
-// users with more than 512 candidates to the wide instance through a.spill.
-template <int DT, int GPL, bool FAST>
-__global__ __launch_bounds__(256) void k_refine(RefineArgs a)
-{
-    __shared__ uint32_t skey[4][FAST ? 64 : 256];
-    __shared__ uint32_t sid[4][FAST ? 64 : 256];
-    __shared__ double s64[4][FAST ? 1 : 256];
-    __shared__ float sraw[4][FAST ? 1 : 256];
-    __shared__ double lam_row[4][FAST ? 1 : 256];
-    __shared__ float raw_row[4][FAST ? 1 : 256];
-    __shared__ int hist_all[4][256];
-    const int w = threadIdx.x >> 6;
-    if (!a.list) {
-        const int64_t u = (int64_t)blockIdx.x * 4 + w;
-        if (u < a.m)
-            refine_user<DT, GPL, FAST>(a, u, skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w], hist_all[w]);
-    } else {
-        const int cnt = *a.list_count;
-        for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < cnt; i += (int64_t)gridDim.x * 4)
-            refine_user<DT, GPL, FAST>(a, a.list[i], skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w],
-                                       hist_all[w]);
-    }
-}
-
-template <int DT>
-static void refine_d(const RefineArgs& a, hipStream_t s)
-{
-    if (a.C <= 64) {
-        RefineArgs a0 = a;
-        a0.list = nullptr;
-        hipLaunchKernelGGL((k_refine<DT, 8, true>), dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a0);
-        if ((int64_t)a.nseg * a.G <= 8 * 64) return;   // no user can hold more than 512
-        RefineArgs a1 = a;
-        a1.list = a.spill;
-        a1.list_count = a.spill_count;
-        a1.spill = nullptr;   // the wide instance never spills
-        const unsigned g = (unsigned)std::min<int64_t>((a.m + 3) / 4, 1024);
-        hipLaunchKernelGGL((k_refine<DT, RF_GPL, false>), dim3(g), dim3(256), 0, s, a1);
-    } else {
-        RefineArgs a0 = a;
-        a0.list = nullptr;
-        hipLaunchKernelGGL((k_refine<DT, RF_GPL, false>), dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a0);
-    }
-}
-
-void launch_refine(int dtype, const RefineArgs& a, hipStream_t s)
-{
-    if (a.m <= 0) return;
-    if ((int64_t)a.nseg * a.G > RF_MAXN || a.C > 256) fail(RKMIPS_EINVAL, "internal: too many candidates per user");
-    if (dtype == DT_F32) refine_d<DT_F32>(a, s);
-    else if (dtype == DT_BF16) refine_d<DT_BF16>(a, s);
-    else refine_d<DT_FP8>(a, s);
-    HIPC(hipGetLastError());
-}
-
-// ------------------------------------------------------------------ full FP64 fallback
-template <int DT>
-__global__ __launch_bounds__(256) void k_fallback(RefineArgs a, double* scratch, int64_t scratch_rows)
-{
-    const int64_t nfail = *a.fail_count;   // written by k_refine earlier on the stream
-    __shared__ int hist[256];
-    __shared__ int s_sel, s_above;
-    __shared__ double top[256];
-    __shared__ int ntop;
-    const int tid = threadIdx.x;
-    for (int64_t fi = blockIdx.x; fi < nfail; fi += gridDim.x) {
-        const int64_t u = a.fail_list[fi];
-        double* sc = scratch + (int64_t)(blockIdx.x % scratch_rows) * a.n;
-        const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
-        for (int64_t p = tid; p < a.n; p += 256) {
-            const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-            sc[p] = canon_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-        }
-        __syncthreads();
-        const int want = (int)(a.n < a.k_max ? a.n : a.k_max);
-        // radix select of the want-th largest (orderable 64-bit keys, 8 digits)
-        uint64_t prefix = 0, pmask = 0;
-        int need = want;
-        for (int shift = 56; shift >= 0; shift -= 8) {
-            hist[tid] = 0;
-            __syncthreads();
-            for (int64_t p = tid; p < a.n; p += 256) {
-                const uint64_t k = f64_ord(sc[p]);
-                if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1);
-            }
-            __syncthreads();
-            if (tid == 0) {
-                int above = 0;
-                for (int b = 255; b >= 0; b--) {
-                    if (above < need && need <= above + hist[b]) { s_sel = b; s_above = above; break; }
-                    above += hist[b];
-                }
-            }
-            __syncthreads();
-            prefix |= (uint64_t)s_sel << shift;
-            pmask |= 0xffull << shift;
-            need -= s_above;
-            __syncthreads();
-        }
-        const double T = ord_f64(prefix);
-        if (tid == 0) ntop = 0;
-        __syncthreads();
-        for (int64_t p = tid; p < a.n; p += 256)
-            if (sc[p] > T) top[atomicAdd(&ntop, 1)] = sc[p];
-        __syncthreads();
-        const int ng = ntop;   // < want
-        for (int j = tid; j < ng; j += 256) {
-            int r = 0;
-            for (int i = 0; i < ng; i++) r += (top[i] > top[j]) || (top[i] == top[j] && i < j);
-            a.lam64[(int64_t)r * a.m + u] = top[j];
-            a.lam32[(int64_t)r * a.m + u] = (float)top[j];
-            if (top[j] != 0.0) atomic_max_pos(a.max_raw_err_bits + 1, fabs((double)(float)top[j] - top[j]) / fabs(top[j]));
-        }
-        for (int r = ng + tid; r < a.k_max; r += 256) {
-            const double v = r < want ? T : -__builtin_inf();
-            a.lam64[(int64_t)r * a.m + u] = v;
-            a.lam32[(int64_t)r * a.m + u] = (float)v;
-        }
-        __syncthreads();
-    }
-}
-
-void launch_fallback(int dtype, const RefineArgs& a, double* scratch, int64_t scratch_rows, hipStream_t s)
-{
-    // one workgroup per scratch row; each takes the failed users in turn (none: no work)
-    const unsigned g = (unsigned)scratch_rows;
-    if (dtype == DT_F32) hipLaunchKernelGGL(k_fallback<DT_F32>, dim3(g), dim3(256), 0, s, a, scratch, scratch_rows);
-    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_fallback<DT_BF16>, dim3(g), dim3(256), 0, s, a, scratch, scratch_rows);
-    else hipLaunchKernelGGL(k_fallback<DT_FP8>, dim3(g), dim3(256), 0, s, a, scratch, scratch_rows);
     HIPC(hipGetLastError());
 }
 
