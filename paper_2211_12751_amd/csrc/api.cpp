@@ -201,72 +201,80 @@ static void choose_topk(Index& x)
 
 // Exact lambda table over the users in their ORIGINAL order (users_o: padded copy
 // [m x ld], user_scales_o / user_n2_o in the same order); lambda rows and the raw
-// candidates are indexed by original user.  Stream-ordered, no host synchronisation.
-static void build_lambda(Index& x, const DevBuf& users_o, const float* user_scales_o, const double* user_n2_o,
-                         hipStream_t s)
+// candidates are indexed by original user.  Two stream-ordered halves without host
+// synchronisation: the fused top-k passes, then the FP64 refine with the certificate.
+struct LambdaBuild {
+    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill, items3, users3;
+    Events ev{4};   // start, after the main pass, after the refine, after the seed pass
+};
+
+static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const float* user_scales_o,
+                        hipStream_t s)
 {
     choose_topk(x);
     const int64_t m = x.m;
-    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill;
-    buf.alloc(sizeof(uint2) * (size_t)m * x.nseg * x.G);
-    cnt.alloc(sizeof(int) * (size_t)m * x.nseg * 2);
-    tau.alloc(sizeof(float) * (size_t)m * x.nseg);
-    fail_list.alloc(sizeof(int) * (size_t)m);
-    fail_count.alloc(2 * sizeof(int));   // [0] certificate failures, [1] refine spills
-    errbits.alloc(2 * sizeof(unsigned long long));
-    spill.alloc(sizeof(int) * (size_t)m);
-    HIPC(hipMemsetAsync(fail_count.p, 0, 2 * sizeof(int), s));
-    HIPC(hipMemsetAsync(errbits.p, 0, 2 * sizeof(unsigned long long), s));
+    L.buf.alloc(sizeof(uint2) * (size_t)m * x.nseg * x.G);
+    L.cnt.alloc(sizeof(int) * (size_t)m * x.nseg * 2);
+    L.tau.alloc(sizeof(float) * (size_t)m * x.nseg);
+    L.fail_list.alloc(sizeof(int) * (size_t)m);
+    L.fail_count.alloc(2 * sizeof(int));   // [0] certificate failures, [1] refine spills
+    L.errbits.alloc(2 * sizeof(unsigned long long));
+    L.spill.alloc(sizeof(int) * (size_t)m);
+    HIPC(hipMemsetAsync(L.fail_count.p, 0, 2 * sizeof(int), s));
+    HIPC(hipMemsetAsync(L.errbits.p, 0, 2 * sizeof(unsigned long long), s));
     x.lam64.alloc(sizeof(double) * (size_t)x.prm.k_max * m);
     x.lam32.alloc(sizeof(float) * (size_t)x.prm.k_max * m);
 
-    // matrix-core operands: the stored rows, or their split BF16 form for FP32 storage
-    DevBuf items3, users3;
+    // matrix-core operands: the stored rows, or their BF16 forms (split FP32, widened FP8)
     const void* mi = x.items.p;
     const void* mu = users_o.p;
     if (x.mma_dtype != x.dtype) {
-        items3.alloc(sizeof(uint16_t) * (size_t)x.n * x.mma_ld);
-        users3.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
-        launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n, x.ld, (uint16_t*)items3.p, 0, s);
-        launch_mma_operand(x.mma_dtype, x.dtype, users_o.p, m, x.ld, (uint16_t*)users3.p, 1, s);
-        mi = items3.p;
-        mu = users3.p;
+        L.items3.alloc(sizeof(uint16_t) * (size_t)x.n * x.mma_ld);
+        L.users3.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
+        launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n, x.ld, L.items3.u16(), 0, s);
+        launch_mma_operand(x.mma_dtype, x.dtype, users_o.p, m, x.ld, L.users3.u16(), 1, s);
+        mi = L.items3.p;
+        mu = L.users3.p;
     }
     TopkArgs ta{};
     ta.items = mi; ta.item_scales = x.item_scales.f(); ta.n = x.n;
     ta.users = mu; ta.user_scales = user_scales_o; ta.m = m;
     ta.d = x.d; ta.ld = x.mma_ld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
-    ta.buf = (uint2*)buf.p; ta.cnt = (int*)cnt.p; ta.tau = (float*)tau.p;
-    Events ev(6);
-    HIPC(hipEventRecord(ev.ev[0], s));
+    ta.buf = (uint2*)L.buf.p; ta.cnt = L.cnt.i(); ta.tau = L.tau.f();
+    HIPC(hipEventRecord(L.ev.ev[0], s));
     if (x.ns > 0) {   // per-user threshold estimates from the item sample
-        theta.alloc(sizeof(float) * (size_t)m);
+        L.theta.alloc(sizeof(float) * (size_t)m);
         TopkArgs a0 = ta;
         a0.ns = x.ns; a0.v0 = 0; a0.v1 = x.ns; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = x.ns;
-        a0.theta_out = theta.f();
+        a0.theta_out = L.theta.f();
         launch_topk_seed(x.mma_dtype, a0, s);
     }
-    HIPC(hipEventRecord(ev.ev[3], s));
+    HIPC(hipEventRecord(L.ev.ev[3], s));
     TopkArgs a1 = ta;
     a1.v0 = 0; a1.v1 = x.n; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
-    a1.theta_init = x.ns > 0 ? theta.f() : nullptr;
+    a1.theta_init = x.ns > 0 ? L.theta.f() : nullptr;
     a1.theta_stride = 1;
     launch_topk(x.mma_dtype, a1, s);
-    HIPC(hipEventRecord(ev.ev[1], s));
+    HIPC(hipEventRecord(L.ev.ev[1], s));
+}
 
+static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const float* user_scales_o,
+                          const double* user_n2_o, hipStream_t s)
+{
+    const int64_t m = x.m;
     RefineArgs ra{};
     ra.items = x.items.p; ra.item_scales = x.item_scales.f(); ra.n = x.n;
     ra.users = users_o.p; ra.user_scales = user_scales_o; ra.m = m;
     ra.d = x.d; ra.ld = x.ld; ra.nseg = x.nseg; ra.C = x.C; ra.G = x.G; ra.k_max = x.prm.k_max;
-    ra.buf = (const uint2*)buf.p; ra.cnt = (const int*)cnt.p; ra.tau = (const float*)tau.p;
+    ra.buf = (const uint2*)L.buf.p; ra.cnt = L.cnt.i(); ra.tau = L.tau.f();
     ra.item_n2_sorted = x.item_n2.d(); ra.seg_len = x.seg_len; ra.user_n2 = user_n2_o;
     ra.force_fail = (x.prm.flags & RKMIPS_FLAG_NO_CERT) ? 1 : 0;
     ra.lam64 = x.lam64.d(); ra.lam32 = x.lam32.f();
-    ra.fail_list = (int*)fail_list.p; ra.fail_count = (int*)fail_count.p;
-    ra.max_raw_err_bits = (unsigned long long*)errbits.p;
+    ra.fail_list = L.fail_list.i(); ra.fail_count = L.fail_count.i();
+    ra.max_raw_err_bits = (unsigned long long*)L.errbits.p;
     ra.err_rel = x.err_fast;
-    ra.spill = spill.i();
-    ra.spill_count = (int*)fail_count.p + 1;
+    ra.spill = L.spill.i();
+    ra.spill_count = L.fail_count.i() + 1;
     launch_refine(x.dtype, ra, s);
     {
         // rows whose certificate failed: full FP64 rescoring (the count stays on the
@@ -276,18 +284,18 @@ static void build_lambda(Index& x, const DevBuf& users_o, const float* user_scal
         scratch.alloc(sizeof(double) * (size_t)rows * x.n);
         launch_fallback(x.dtype, ra, scratch.d(), rows, s);
     }
-    HIPC(hipEventRecord(ev.ev[2], s));
+    HIPC(hipEventRecord(L.ev.ev[2], s));
     // build statistics, read by the host after the build's final wait
     x.h_lam_stats.alloc(sizeof(unsigned long long) * 4);
     unsigned long long* hs = (unsigned long long*)x.h_lam_stats.p;
-    HIPC(hipMemcpyAsync(hs, errbits.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(hs + 2, fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hs, L.errbits.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hs + 2, L.fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
     x.lam_ev.assign(4, nullptr);
-    for (int i = 0; i < 4; i++) std::swap(x.lam_ev[i], ev.ev[i]);
+    for (int i = 0; i < 4; i++) std::swap(x.lam_ev[i], L.ev.ev[i]);
     // keep the raw candidates for inspection (per original user)
-    x.cand.swap(buf);
-    x.cand_cnt.swap(cnt);
-    x.cand_tau.swap(tau);
+    x.cand.swap(L.buf);
+    x.cand_cnt.swap(L.cnt);
+    x.cand_tau.swap(L.tau);
 }
 
 static void build_index(Index& x, const void* items, const float* item_scales, const void* users,
@@ -340,10 +348,12 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     launch_gather_rows(x.dtype, users, x.d, user_scales, nullptr, m, x.d, users_o.p, x.ld, uscales_o.f(), s);
     HIPC(hipEventRecord(ev.ev[1], s));
 
-    // The exact lambda table (matrix-core bound) runs on the caller's stream while the
-    // Cone-Tree and the SA-ALSH index (latency bound, host-checked) run on a second one;
-    // they meet before the block lower bounds, which need both.
-    build_lambda(x, users_o, uscales_o.f(), n2_users_orig.d(), s);
+    // The fused top-k passes (matrix-core bound) run on the caller's stream while the
+    // Cone-Tree and the SA-ALSH index (latency bound, host-checked) run on a second one.
+    // The refine pass waits for the second stream: enqueued earlier, its grid of one
+    // wave per user would hold the compute units the second stream's kernels need.
+    LambdaBuild L;
+    lambda_topk(x, L, users_o, uscales_o.f(), s);
     const hipStream_t s2 = aux_stream(x.device);
     HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
     {
@@ -359,6 +369,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
         HIPC(hipEventRecord(ev.ev[5], s2));
     }
     HIPC(hipStreamWaitEvent(s, ev.ev[5], 0));
+    lambda_refine(x, L, users_o, uscales_o.f(), n2_users_orig.d(), s);
 
     // ---- per-block quantities that need lambda (L^j(B))
     finish_blocks(x, s);

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "../../include/rkmips.h"
+#include "topk.h"
 
 namespace rk {
 
@@ -50,41 +51,9 @@ void launch_norm_keys(const double* n2, int64_t n, int64_t cap, uint64_t* keys, 
                       hipStream_t s);
 void launch_permute_f64(const double* src, const uint32_t* perm, int64_t n, double* dst,
                         hipStream_t s);
-// U_unit[r] = u_r / sqrt(n2_r) (FP32, 0 row for a zero vector), ld = ldu.
-void launch_unit_rows(int dtype, const void* X, const float* scales, const double* n2,
-                      int64_t rows, int d, int ld, float* out, hipStream_t s);
 
 // ---------------------------------------------------------------- lambda build
-struct TopkArgs {
-    const void* items;      // sorted by norm, [n x ld]
-    const float* item_scales;
-    int64_t n;
-    const void* users;      // leaf order, [m x ld]
-    const float* user_scales;
-    int64_t m;
-    int d, ld;
-    int64_t ns;             // seed pass: size of the stratified item sample
-    int64_t v0, v1;         // virtual item range of this launch
-    int nseg;               // segments of this launch (grid.y)
-    int seg_base;           // buffer segment of this launch's first segment
-    int nseg_total;         // buffer segments per user
-    int64_t seg_len;        // items per segment (multiple of the item tile)
-    int C;                  // candidates kept per (user, segment)
-    int G;                  // buffer capacity per (user, segment)
-    const float* theta_init;  // per user starting threshold (stride theta_stride) or null
-    int64_t theta_stride;
-    uint2* buf;             // [m x nseg_total x G] {ord(score), sorted item position}
-    int* cnt;               // [m x nseg_total]
-    float* tau;             // [m x nseg_total]
-    float* theta_out;       // seed pass: [m] threshold estimates
-};
-enum { TK_MAIN = 0, TK_SEED = 1 };
-constexpr int TK_T = 8;     // sample scores kept per lane by the seed pass
-void launch_topk(int dtype, const TopkArgs& a, hipStream_t s);
-void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s);
-int topk_users_per_block(int dtype, int ld);
-int topk_resident_blocks(int dtype, int ld, int G);
-
+// (the fused top-k pass: topk.h)
 struct RefineArgs {
     const void* items; const float* item_scales; int64_t n;
     const void* users; const float* user_scales; int64_t m;

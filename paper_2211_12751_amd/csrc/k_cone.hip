@@ -80,6 +80,7 @@ __device__ __forceinline__ unsigned long long key_min(const unsigned long long* 
 // block's count (the left count of a segment is a difference of two global ranks).
 __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
 {
+    if (a.ctl[2] == 0) return;   // no active segment at this level (workgroup-uniform)
     __shared__ int wt[4];
     const int l = lane_id(), w = threadIdx.x >> 6;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -158,12 +159,16 @@ __global__ void k_cone_init(ConeLevelArgs a)
     }
 }
 
+// Threads of the single k_cone_next workgroup: four waves, so that it finds room on a
+// compute unit beside the matrix-core kernels of the other stream.
+static constexpr int CN_THREADS = 256;
+
 // The next level's segments, by one workgroup: an active segment becomes its left and
 // right parts (index halves when one side is empty), an inactive one stays.  Also
 // numbers the next level's active segments and resets their argmin slots.
-__global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
+__global__ __launch_bounds__(CN_THREADS) void k_cone_next(ConeLevelArgs a)
 {
-    __shared__ int64_t wtot[16], wact[16];
+    __shared__ int64_t wtot[CN_THREADS / 64], wact[CN_THREADS / 64];
     __shared__ int64_t carry_s, active_s, total_left;
     const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
     const int64_t nseg = a.ctl[a.ctl_cur];
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
     const int64_t nblk = (a.m + 255) / 256;
     if (tid == 0) carry_s = 0;
     __syncthreads();
-    for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
+    for (int64_t c0 = 0; c0 < nblk; c0 += CN_THREADS) {
         const int64_t i = c0 + tid;
         const int v = i < nblk ? a.blk_cnt[i] : 0;
         const int incl = wave_incl_scan(v);
@@ -184,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
         __syncthreads();
         if (tid == 0) {
             int64_t t = 0;
-            for (int q = 0; q < 16; q++) t += wtot[q];
+            for (int q = 0; q < CN_THREADS / 64; q++) t += wtot[q];
             carry_s += t;
         }
         __syncthreads();
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
     __syncthreads();
     const int64_t tl = total_left;
     auto lrank_at = [&](int64_t x) -> int64_t { return x < a.m ? (int64_t)a.blk_cnt[x >> 8] + a.lrank[x] : tl; };
-    for (int64_t c0 = 0; c0 < nseg; c0 += 1024) {
+    for (int64_t c0 = 0; c0 < nseg; c0 += CN_THREADS) {
         const int64_t s = c0 + tid;
         int64_t st = 0, sz = 0, nl = 0;
         int kids = 0, k0 = 0, k1 = 0;
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
         __syncthreads();
         if (tid == 0) {
             int64_t t = 0, ta = 0;
-            for (int q = 0; q < 16; q++) {
+            for (int q = 0; q < CN_THREADS / 64; q++) {
                 t += wtot[q];
                 ta += wact[q];
             }
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(1024) void k_cone_next(ConeLevelArgs a)
         a.ctl[2] = active_s;
     }
     // the next level's argmin slots start from their identity
-    for (int64_t i = tid; i < active_s * KEY_WAYS; i += 1024) {
+    for (int64_t i = tid; i < active_s * KEY_WAYS; i += CN_THREADS) {
         a.next_key1[i] = ~0ull;
         a.next_key2[i] = ~0ull;
     }
@@ -481,15 +486,18 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     }
     int level = 0;
     bool more = m > x.prm.leaf_size;
-    // the first batch is the depth of a perfectly balanced tree, later ones are short
+    // the first batch is the depth of a perfectly balanced tree plus a margin for uneven
+    // splits (levels without an active segment cost one early exit per kernel), so the
+    // host usually checks once; later batches are short
     int batch = 1;
     while (((int64_t)x.prm.leaf_size << batch) < m) batch++;
+    batch += 3;
     int64_t nseg_final = 1;
     while (more) {
         for (int rep = 0; rep < batch; rep++, level++) {
             const ConeLevelArgs a = level_args(level);
             for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
-            hipLaunchKernelGGL(k_cone_next, dim3(1), dim3(1024), 0, s, a);
+            hipLaunchKernelGGL(k_cone_next, dim3(1), dim3(CN_THREADS), 0, s, a);
             hipLaunchKernelGGL(k_cone_scatter, dim3(grid), dim3(256), 0, s, a, perm_b.u32());
             HIPC(hipGetLastError());
             perm_a.swap(perm_b);

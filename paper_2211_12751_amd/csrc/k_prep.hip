@@ -334,34 +334,5 @@ void launch_gather_rows(int dtype, const void* src, int ld_src, const float* src
     HIPC(hipGetLastError());
 }
 
-// ------------------------------------------------------------------ unit rows
-template <int DT>
-__global__ void k_unit_rows(const void* X, const float* scales, const double* n2, int64_t rows, int d,
-                            int ld, float* out)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= rows * ld) return;
-    int64_t r = t / ld;
-    int i = (int)(t - r * ld);
-    float v = 0.f;
-    if (i < d && n2[r] > 0.0) {
-        double x = (double)elem_f32<DT>(X, r * ld + i);
-        if constexpr (DT == DT_FP8) x *= (double)scales[r];
-        v = (float)(x / sqrt(n2[r]));
-    }
-    out[t] = v;
-}
-
-void launch_unit_rows(int dtype, const void* X, const float* scales, const double* n2, int64_t rows,
-                      int d, int ld, float* out, hipStream_t s)
-{
-    if (rows <= 0) return;
-    const int64_t tot = rows * ld;
-    dim3 g((unsigned)((tot + 255) / 256)), b(256);
-    if (dtype == DT_F32) hipLaunchKernelGGL(k_unit_rows<DT_F32>, g, b, 0, s, X, scales, n2, rows, d, ld, out);
-    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_unit_rows<DT_BF16>, g, b, 0, s, X, scales, n2, rows, d, ld, out);
-    else hipLaunchKernelGGL(k_unit_rows<DT_FP8>, g, b, 0, s, X, scales, n2, rows, d, ld, out);
-    HIPC(hipGetLastError());
-}
 
 }  // namespace rk
