@@ -173,8 +173,12 @@ void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, 
 void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s);
 void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
 void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s);
-void launch_result_lists(const uint64_t* keys, int64_t span, int64_t nq, int* cnt, int64_t* offsets,
-                         long long* stat, int32_t* tmp, int32_t* ids, hipStream_t s);
+// the same with the close-call count kept on the device (pool tail cleared, span in ctr[5])
+void launch_recheck_device(const QueryArgs& a, hipStream_t s);
+// span_dev null: the pool span is `span`; otherwise it is read on the device and `span`
+// is its upper bound
+void launch_result_lists(const uint64_t* keys, int64_t span, const unsigned long long* span_dev, int64_t nq, int* cnt,
+                         int64_t* offsets, long long* stat, int32_t* tmp, int32_t* ids, hipStream_t s);
 void launch_result_merges(int64_t nq, int64_t max_count, const int64_t* offsets, int32_t* tmp, int32_t* ids,
                           hipStream_t s);
 

@@ -19,6 +19,7 @@
 // uncertainty Delta_phi is added to the cosine factor; a relative slack covers the
 // FP32 evaluation and the stored cos/sin pairs.  Pruning is only ever a strict "<".
 #include <algorithm>
+#include <climits>
 #include <utility>
 
 #include "common.h"
@@ -530,25 +531,30 @@ __device__ double canon_dot2(const void* A, int64_t ra, int lda, float sa, const
     return acc;
 }
 
+// namb_dev (when given): the close-call count on the device, read here (grid-stride).
 template <int DT>
-__global__ void k_recheck(QueryArgs a, int64_t namb, const int* reject)
+__global__ void k_recheck(QueryArgs a, int64_t namb, const unsigned long long* namb_dev, const int* reject)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= namb) return;
-    if (reject && reject[i] == 0) {   // Alg. 2 proved s(u,q) < phi <= lambda_u^(k)
-        atomicAdd(&a.stats[4], 1ull);
-        return;
+    if (namb_dev) {
+        const int64_t c = (int64_t)*namb_dev;
+        namb = c < a.amb_cap ? c : a.amb_cap;
     }
-    const unsigned long long key = a.amb[i];
-    const int64_t q = (int64_t)(key >> 32);
-    const int64_t u = (int64_t)(key & 0xffffffffull);
-    const int k = a.qk[q];
-    const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
-    const float sq = DT == DT_FP8 ? a.query_scales[q] : 1.f;
-    const double s = canon_dot2<DT>(a.users, u, a.ld, su, a.queries, q, a.ld, sq, a.d);
-    if (s >= a.lam64[(int64_t)(k - 1) * a.m + a.perm[u]]) {
-        const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
-        if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)a.qorig[q] << 32) | a.perm[u];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namb; i += (int64_t)gridDim.x * blockDim.x) {
+        if (reject && reject[i] == 0) {   // Alg. 2 proved s(u,q) < phi <= lambda_u^(k)
+            atomicAdd(&a.stats[4], 1ull);
+            continue;
+        }
+        const unsigned long long key = a.amb[i];
+        const int64_t q = (int64_t)(key >> 32);
+        const int64_t u = (int64_t)(key & 0xffffffffull);
+        const int k = a.qk[q];
+        const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
+        const float sq = DT == DT_FP8 ? a.query_scales[q] : 1.f;
+        const double s = canon_dot2<DT>(a.users, u, a.ld, su, a.queries, q, a.ld, sq, a.d);
+        if (s >= a.lam64[(int64_t)(k - 1) * a.m + a.perm[u]]) {
+            const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
+            if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)a.qorig[q] << 32) | a.perm[u];
+        }
     }
 }
 
@@ -556,9 +562,33 @@ void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStre
 {
     if (namb <= 0) return;
     dim3 g((unsigned)((namb + 255) / 256)), b(256);
-    if (a.dtype == DT_F32) hipLaunchKernelGGL(k_recheck<DT_F32>, g, b, 0, s, a, namb, reject);
-    else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_recheck<DT_BF16>, g, b, 0, s, a, namb, reject);
-    else hipLaunchKernelGGL(k_recheck<DT_FP8>, g, b, 0, s, a, namb, reject);
+    if (a.dtype == DT_F32) hipLaunchKernelGGL(k_recheck<DT_F32>, g, b, 0, s, a, namb, nullptr, reject);
+    else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_recheck<DT_BF16>, g, b, 0, s, a, namb, nullptr, reject);
+    else hipLaunchKernelGGL(k_recheck<DT_FP8>, g, b, 0, s, a, namb, nullptr, reject);
+    HIPC(hipGetLastError());
+}
+
+// Close calls counted on the device: pool[cnt, cnt + namb) is cleared (the recheck
+// appends there), span = cnt + namb (capped) is kept in ctr[5], then the recheck runs
+// over the device count.
+__global__ void k_close_init(unsigned long long* ctr, unsigned long long* pool, int64_t pool_cap, int64_t amb_cap)
+{
+    const int64_t cnt = (int64_t)ctr[0];
+    int64_t namb = (int64_t)ctr[1];
+    namb = namb < amb_cap ? namb : amb_cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[5] = (unsigned long long)(cnt + namb < pool_cap ? cnt + namb : pool_cap);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namb; i += (int64_t)gridDim.x * blockDim.x)
+        if (cnt + i < pool_cap) pool[cnt + i] = ~0ull;
+}
+
+void launch_recheck_device(const QueryArgs& a, hipStream_t s)
+{
+    unsigned long long* ctr = a.pool_count;   // ctr[0] = pool count, ctr[1] = close calls
+    hipLaunchKernelGGL(k_close_init, dim3(64), dim3(256), 0, s, ctr, a.pool, a.pool_cap, a.amb_cap);
+    const unsigned g = (unsigned)std::min<int64_t>((a.amb_cap + 255) / 256, 256);
+    if (a.dtype == DT_F32) hipLaunchKernelGGL(k_recheck<DT_F32>, dim3(g), dim3(256), 0, s, a, (int64_t)0, ctr + 1, nullptr);
+    else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_recheck<DT_BF16>, dim3(g), dim3(256), 0, s, a, (int64_t)0, ctr + 1, nullptr);
+    else hipLaunchKernelGGL(k_recheck<DT_FP8>, dim3(g), dim3(256), 0, s, a, (int64_t)0, ctr + 1, nullptr);
     HIPC(hipGetLastError());
 }
 
@@ -611,12 +641,14 @@ void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, 
 // field is out of range are unused slots and are skipped.
 static constexpr int QS_CHUNK = 4096;
 
-__global__ void k_qcount(const uint64_t* keys, int64_t span, int64_t nq, int* cnt)
+// span_dev (when given): the pool span on the device (grid-stride over it).
+__global__ void k_qcount(const uint64_t* keys, int64_t span, const unsigned long long* span_dev, int64_t nq, int* cnt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= span) return;
-    const uint64_t q = keys[i] >> 32;
-    if (q < (uint64_t)nq) atomicAdd(&cnt[q], 1);
+    if (span_dev) span = (int64_t)*span_dev;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < span; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = keys[i] >> 32;
+        if (q < (uint64_t)nq) atomicAdd(&cnt[q], 1);
+    }
 }
 
 // One workgroup: offsets[0..nq] = exclusive scan of cnt (64-bit), cnt reset to zero (it
@@ -668,15 +700,16 @@ __global__ __launch_bounds__(1024) void k_qscan(int* cnt, int64_t nq, int64_t* o
     }
 }
 
-__global__ void k_qscatter(const uint64_t* keys, int64_t span, int64_t nq, const int64_t* offsets, int* cursor,
-                           int32_t* out)
+__global__ void k_qscatter(const uint64_t* keys, int64_t span, const unsigned long long* span_dev, int64_t nq,
+                           const int64_t* offsets, int* cursor, int32_t* out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= span) return;
-    const uint64_t key = keys[i];
-    const uint64_t q = key >> 32;
-    if (q >= (uint64_t)nq) return;
-    out[offsets[q] + atomicAdd(&cursor[q], 1)] = (int32_t)(key & 0xffffffffull);
+    if (span_dev) span = (int64_t)*span_dev;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < span; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[i];
+        const uint64_t q = key >> 32;
+        if (q >= (uint64_t)nq) continue;
+        out[offsets[q] + atomicAdd(&cursor[q], 1)] = (int32_t)(key & 0xffffffffull);
+    }
 }
 
 // Ascending sort of up to QS_CHUNK ids in LDS (bitonic over the next power of two,
@@ -762,17 +795,18 @@ __global__ __launch_bounds__(256) void k_qcopy_long(const int64_t* offsets, cons
     for (int64_t i = threadIdx.x; i < c; i += 256) dst[b + i] = src[b + i];
 }
 
-void launch_result_lists(const uint64_t* keys, int64_t span, int64_t nq, int* cnt, int64_t* offsets,
-                         long long* stat, int32_t* tmp, int32_t* ids, hipStream_t s)
+void launch_result_lists(const uint64_t* keys, int64_t span, const unsigned long long* span_dev, int64_t nq, int* cnt,
+                         int64_t* offsets, long long* stat, int32_t* tmp, int32_t* ids, hipStream_t s)
 {
     if (nq <= 0) return;
     HIPC(hipMemsetAsync(cnt, 0, sizeof(int) * nq, s));
-    if (span > 0)
-        hipLaunchKernelGGL(k_qcount, dim3((unsigned)((span + 255) / 256)), dim3(256), 0, s, keys, span, nq, cnt);
+    // with a device span, `span` bounds it (the pool capacity) and sizes the grid
+    const unsigned g = (unsigned)std::min<int64_t>((span + 255) / 256, span_dev ? 2048 : INT32_MAX);
+    if (span > 0) hipLaunchKernelGGL(k_qcount, dim3(g), dim3(256), 0, s, keys, span, span_dev, nq, cnt);
     hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, s, cnt, nq, offsets, stat);
     if (span > 0)
-        hipLaunchKernelGGL(k_qscatter, dim3((unsigned)((span + 255) / 256)), dim3(256), 0, s, keys, span, nq,
-                           (const int64_t*)offsets, cnt, tmp);
+        hipLaunchKernelGGL(k_qscatter, dim3(g), dim3(256), 0, s, keys, span, span_dev, nq, (const int64_t*)offsets,
+                           cnt, tmp);
     hipLaunchKernelGGL(k_qsort, dim3((unsigned)nq), dim3(256), 0, s, (const int64_t*)offsets, (const int32_t*)tmp, ids);
     HIPC(hipGetLastError());
 }

@@ -70,18 +70,12 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
         if (x.mma_dtype != x.dtype) qsplit.alloc(sizeof(uint16_t) * (size_t)c * x.mma_ld);
         if (x.dtype == RKMIPS_FP8_E4M3) qsc.alloc(sizeof(float) * c);
         qnorm.alloc(sizeof(float) * c);
-        qslot.alloc(sizeof(int) * c);
-        qorig.alloc(sizeof(uint32_t) * c);
-        qk.alloc(sizeof(int) * c);
-        h_qk.alloc(sizeof(int) * c);
+        meta.alloc(sizeof(int) * (3 * c + kMaxSlots * (c + 1)));
+        h_meta.alloc(sizeof(int) * (3 * c + kMaxSlots * (c + 1)));
         offsets.alloc(sizeof(int64_t) * (c + 1));
         qcnt.alloc(sizeof(int) * c);
-        h_qslot.alloc(sizeof(int) * c);
-        h_qorig.alloc(sizeof(uint32_t) * c);
         h_offsets.alloc(sizeof(int64_t) * (c + 1));
-        slotk.alloc(sizeof(int) * kMaxSlots * (c + 1));
         cphi.alloc(sizeof(float) * (size_t)c * std::max<int64_t>(x.nblocks, 1));
-        h_slotk.alloc(sizeof(int) * kMaxSlots * (c + 1));
         nq_cap = c;
     }
     const int64_t pc = pow2ceil64(std::max<int64_t>(pool_cap_req, 1 << 12));
@@ -152,7 +146,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.mma_queries = split ? w.qsplit.p : w.qpad.p;
     a.mma_dtype = x.mma_dtype;
     a.mma_ld = x.mma_ld;
-    a.qslot = w.qslot.i(); a.qorig = w.qorig.u32(); a.qk = w.qk.i(); a.slot_k = w.slotk.i();
+    a.qslot = w.qslot; a.qorig = w.qorig; a.qk = w.qk; a.slot_k = w.slotk;
     a.flags = flags | x.prm.flags;
     a.err_rel = x.err_fast;
     a.err_phi = phi_err(x.d);
@@ -166,27 +160,35 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
 }
 
 // Enqueue query prep and the fused bound/verify kernels for a batch whose host side
-// (h_qorig, h_qslot, h_slotk, groups) is already filled.
+// (h_meta, groups) is already filled; without the SA-ALSH filter the FP64 recheck and
+// the per-query lists follow on the device, with no host round trip in between.
 void enqueue_batch(const Index& x, Workspace& w, const void* queries, const float* qscales, int64_t nq,
                    int flags, hipStream_t s)
 {
     HIPC(hipMemsetAsync(w.ctr.p, 0, sizeof(unsigned long long) * 16, s));
+    const int fl = flags | x.prm.flags;
+    w.device_tail = nq > 0 && !((fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH));
     if (nq > 0) {
-        HIPC(hipMemcpyAsync(w.qorig.p, w.h_qorig.p, sizeof(uint32_t) * nq, hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(w.qslot.p, w.h_qslot.p, sizeof(int) * nq, hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(w.qk.p, w.h_qk.p, sizeof(int) * nq, hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(w.slotk.p, w.h_slotk.p, sizeof(int) * kMaxSlots * w.groups.size(),
-                            hipMemcpyHostToDevice, s));
-        launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig.u32(), nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
+        HIPC(hipMemcpyAsync(w.meta.p, w.h_meta.p, sizeof(int) * w.meta_ints, hipMemcpyHostToDevice, s));
+        launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig, nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
         QueryArgs a = make_query_args(x, w, nq, flags);
         launch_qnorm(x.dtype, w.qpad.p, w.qsc.f(), nq, x.d, x.ld, w.qnorm.f(), a.bad, s);
         if (x.mma_dtype != x.dtype) launch_mma_operand(x.mma_dtype, x.dtype, w.qpad.p, nq, x.ld, w.qsplit.u16(), 0, s);
         if (!(a.flags & RKMIPS_FLAG_NO_BOUNDS)) launch_phi(a, w.cphi.f(), s);
         for (size_t g = 0; g < w.groups.size(); g++) {
             QueryArgs ag = a;
-            ag.slot_k = w.slotk.i() + kMaxSlots * g;
+            ag.slot_k = w.slotk + kMaxSlots * g;
             ag.nslots = w.groups[g].nslots;
             launch_verify_range(ag, w.groups[g].begin, w.groups[g].end, s);
+        }
+        if (w.device_tail) {
+            // the FP64 recheck and the list building read the counts on the device; the
+            // host checks them (bad values, overflow) once the offsets are back
+            unsigned long long* c = (unsigned long long*)w.ctr.p;
+            launch_recheck_device(a, s);
+            launch_result_lists((const uint64_t*)w.pool.p, w.pool_cap, c + 5, nq, w.qcnt.i(), w.offsets.i64(),
+                                (long long*)(c + 13), (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);
+            HIPC(hipMemcpyAsync(w.h_offsets.p, w.offsets.p, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s));
         }
     }
     HIPC(hipMemcpyAsync(w.h_ctr.p, w.ctr.p, sizeof(unsigned long long) * 16, hipMemcpyDeviceToHost, s));
@@ -200,10 +202,17 @@ void plan_batch(const Index& x, Workspace& w, const int32_t* ks, int64_t nq)
     for (int64_t i = 0; i < nq; i++) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return ks[a] < ks[b]; });
     w.groups.clear();
-    uint32_t* qo = (uint32_t*)w.h_qorig.p;
-    int* qsl = (int*)w.h_qslot.p;
-    int* qkk = (int*)w.h_qk.p;
-    int* sk = (int*)w.h_slotk.p;
+    // packed tables (host and device share the layout)
+    int* hm = (int*)w.h_meta.p;
+    uint32_t* qo = (uint32_t*)hm;
+    int* qsl = hm + nq;
+    int* qkk = hm + 2 * nq;
+    int* sk = hm + 3 * nq;
+    int* dm = w.meta.i();
+    w.qorig = (uint32_t*)dm;
+    w.qslot = dm + nq;
+    w.qk = dm + 2 * nq;
+    w.slotk = dm + 3 * nq;
     int64_t i = 0;
     while (i < nq) {
         Group g{};
@@ -224,6 +233,7 @@ void plan_batch(const Index& x, Workspace& w, const int32_t* ks, int64_t nq)
         g.end = i;
         w.groups.push_back(g);
     }
+    w.meta_ints = 3 * nq + kMaxSlots * (int64_t)w.groups.size();
     (void)x;
 }
 
@@ -287,26 +297,27 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     st.pairs_vector_pruned = (int64_t)hc[9];
     st.pairs_scored = (int64_t)hc[10];
     st.pairs_rechecked = namb;
-    QueryArgs a = make_query_args(x, w, nq, flags);
-    fill_u64((unsigned long long*)w.pool.p + cnt, namb, ~0ull, s);
     const int* reject = nullptr;
-    const int fl = flags | x.prm.flags;
-    if (namb > 0 && (fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH)) {
-        // Alg. 2 as a proof-only filter on the close calls: a "no" there is exact
-        run_saalsh(x, w, a, namb, s);
-        reject = w.sa_answer.i();
-        st.saalsh_checked = namb;
+    if (!w.device_tail) {
+        QueryArgs a = make_query_args(x, w, nq, flags);
+        fill_u64((unsigned long long*)w.pool.p + cnt, namb, ~0ull, s);
+        if (namb > 0 && !w.device_tail) {
+            // Alg. 2 as a proof-only filter on the close calls: a "no" there is exact
+            run_saalsh(x, w, a, namb, s);
+            reject = w.sa_answer.i();
+            st.saalsh_checked = namb;
+        }
+        if (namb > 0) launch_recheck(a, namb, reject, s);
+        const int64_t span = cnt + namb;
+        long long* maxc = (long long*)((unsigned long long*)w.ctr.p + 13);
+        launch_result_lists((const uint64_t*)w.pool.p, std::max<int64_t>(span, 0), nullptr, nq, w.qcnt.i(),
+                            w.offsets.i64(), maxc, (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);
+        if (nq > 0) {
+            HIPC(hipMemcpyAsync(w.h_offsets.p, w.offsets.p, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync((unsigned long long*)w.h_ctr.p + 13, maxc, sizeof(long long), hipMemcpyDeviceToHost, s));
+        }
+        HIPC(hipStreamSynchronize(s));
     }
-    if (namb > 0) launch_recheck(a, namb, reject, s);
-    const int64_t span = cnt + namb;
-    long long* maxc = (long long*)((unsigned long long*)w.ctr.p + 13);
-    launch_result_lists((const uint64_t*)w.pool.p, std::max<int64_t>(span, 0), nq, w.qcnt.i(), w.offsets.i64(),
-                        maxc, (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);
-    if (nq > 0) {
-        HIPC(hipMemcpyAsync(w.h_offsets.p, w.offsets.p, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s));
-        HIPC(hipMemcpyAsync((unsigned long long*)w.h_ctr.p + 13, maxc, sizeof(long long), hipMemcpyDeviceToHost, s));
-    }
-    HIPC(hipStreamSynchronize(s));
     if (nq == 0) ((int64_t*)w.h_offsets.p)[0] = 0;
     const int64_t* ho = (const int64_t*)w.h_offsets.p;
     const int64_t total = ho[nq];

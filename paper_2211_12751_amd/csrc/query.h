@@ -21,12 +21,19 @@ struct Group {
 // Device and pinned host buffers of one in-flight batch.
 struct Workspace {
     int64_t nq_cap = 0, pool_cap = 0, amb_cap = 0;
-    DevBuf qpad, qsc, qnorm, qslot, qorig, qk, slotk, offsets, pool, ids, amb, ctr;
+    DevBuf qpad, qsc, qnorm, offsets, pool, ids, amb, ctr;
+    // per-query tables of a batch, packed for one host-to-device copy: k-sorted position ->
+    // caller index [nq], k slot [nq], k [nq], then the groups' slot tables [8 x groups]
+    DevBuf meta;
+    PinBuf h_meta;
+    uint32_t* qorig = nullptr; int* qslot = nullptr; int* qk = nullptr; int* slotk = nullptr;   // in meta
+    int64_t meta_ints = 0;                  // ints of meta this batch uses
+    bool device_tail = false;               // recheck and lists were enqueued with the batch
     DevBuf cphi;                            // [nblocks x nq] query-centre cosines
     DevBuf qsplit;                          // matrix-core query rows (split FP32 or widened FP8)
     DevBuf qcnt, ids2;                      // per-query counts, scatter target of the lists
     DevBuf sa_scratch, sa_answer, sa_phi;   // SA-ALSH stage
-    PinBuf h_qslot, h_qorig, h_qk, h_slotk, h_offsets, h_ids, h_ctr;
+    PinBuf h_offsets, h_ids, h_ctr;
     std::vector<Group> groups;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_ctr = nullptr;
     Workspace();
