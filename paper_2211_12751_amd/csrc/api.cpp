@@ -153,6 +153,11 @@ static hipStream_t aux_stream(int dev)
     return st;
 }
 
+// Operand form of the top-k passes: FP32 data as BF16 pairs [hi | lo] (three products
+// per k-step on the matrix cores), otherwise the index's matrix-core form.
+static int topk_dtype(const Index& x) { return x.dtype == DT_F32 && x.mma_dtype == DT_BF16 ? DT_SPLIT : x.mma_dtype; }
+static int topk_ld(const Index& x) { return topk_dtype(x) == DT_SPLIT ? 2 * x.ld : x.mma_ld; }
+
 static void choose_topk(Index& x)
 {
     const int C = x.prm.k_max + x.prm.topk_slack;
@@ -171,14 +176,14 @@ static void choose_topk(Index& x)
     // C survivors sit in one half, which must still take a block's 16 appends
     while (gpl * 32 < C + 16) gpl *= 2;
     if (gpl > 16) fail(RKMIPS_EINVAL, "internal: candidate buffer too large");
-    const int upb = topk_users_per_block(x.mma_dtype, x.mma_ld);
+    const int upb = topk_users_per_block(topk_dtype(x), topk_ld(x));
     const int64_t tiles = (x.m + upb - 1) / upb;
     // the buffers stay within a fixed share of the device memory
     while (gpl > 2 && gpl * 16 >= C + 16 && (double)x.m * gpl * 64 * 8 > 24e9) gpl /= 2;
     // Item segments (grid.y): the grid runs in rounds of the resident workgroups, so the
     // segment count is the one that fills its last round best (fewer on near ties).
     const int cus = x.num_cus;
-    const int64_t slots = (int64_t)cus * topk_resident_blocks(x.mma_dtype, x.mma_ld, gpl * 64);
+    const int64_t slots = (int64_t)cus * topk_resident_blocks(topk_dtype(x), topk_ld(x), gpl * 64);
     int nmax = (int)std::min<int64_t>(std::max<int64_t>(1, x.n / 1024), std::max(1, 2048 / (gpl * 64)));
     while (nmax > 1 && (double)x.m * nmax * gpl * 64 * 8 > 24e9) nmax--;
     int nmain = 1;
@@ -228,18 +233,24 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
     // matrix-core operands: the stored rows, or their BF16 forms (split FP32, widened FP8)
     const void* mi = x.items.p;
     const void* mu = users_o.p;
+    const int tdt = topk_dtype(x), tld = topk_ld(x);
     if (x.mma_dtype != x.dtype) {
-        L.items3.alloc(sizeof(uint16_t) * (size_t)x.n * x.mma_ld);
-        L.users3.alloc(sizeof(uint16_t) * (size_t)m * x.mma_ld);
-        launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n, x.ld, L.items3.u16(), 0, s);
-        launch_mma_operand(x.mma_dtype, x.dtype, users_o.p, m, x.ld, L.users3.u16(), 1, s);
+        L.items3.alloc(sizeof(uint16_t) * (size_t)x.n * tld);
+        L.users3.alloc(sizeof(uint16_t) * (size_t)m * tld);
+        if (tdt == DT_SPLIT) {
+            launch_split_bf16((const float*)x.items.p, x.n, x.ld, L.items3.u16(), 2, s);
+            launch_split_bf16((const float*)users_o.p, m, x.ld, L.users3.u16(), 2, s);
+        } else {
+            launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n, x.ld, L.items3.u16(), 0, s);
+            launch_mma_operand(x.mma_dtype, x.dtype, users_o.p, m, x.ld, L.users3.u16(), 1, s);
+        }
         mi = L.items3.p;
         mu = L.users3.p;
     }
     TopkArgs ta{};
     ta.items = mi; ta.item_scales = x.item_scales.f(); ta.n = x.n;
     ta.users = mu; ta.user_scales = user_scales_o; ta.m = m;
-    ta.d = x.d; ta.ld = x.mma_ld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
+    ta.d = x.d; ta.ld = tld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
     ta.buf = (uint2*)L.buf.p; ta.cnt = L.cnt.i(); ta.tau = L.tau.f();
     HIPC(hipEventRecord(L.ev.ev[0], s));
     if (x.ns > 0) {   // per-user threshold estimates from the item sample
@@ -247,14 +258,14 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
         TopkArgs a0 = ta;
         a0.ns = x.ns; a0.v0 = 0; a0.v1 = x.ns; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = x.ns;
         a0.theta_out = L.theta.f();
-        launch_topk_seed(x.mma_dtype, a0, s);
+        launch_topk_seed(tdt, a0, s);
     }
     HIPC(hipEventRecord(L.ev.ev[3], s));
     TopkArgs a1 = ta;
     a1.v0 = 0; a1.v1 = x.n; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
     a1.theta_init = x.ns > 0 ? L.theta.f() : nullptr;
     a1.theta_stride = 1;
-    launch_topk(x.mma_dtype, a1, s);
+    launch_topk(tdt, a1, s);
     HIPC(hipEventRecord(L.ev.ev[1], s));
 }
 

@@ -15,7 +15,11 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2,
        // matrix-core operand form only: FP8 e4m3 codes widened to BF16 (every e4m3 value
        // is a BF16 value), with the per-row FP8 scales applied after the product
-       DT_FP8B = 3 };
+       DT_FP8B = 3,
+       // matrix-core operand form only: FP32 rows split into BF16 pairs [hi | lo]
+       // (hi = RN_bf16(x), lo = RN_bf16(x - hi)); a product takes the three terms
+       // hi.hi + lo.hi + hi.lo, each k-step's hi fragment serving two of them
+       DT_SPLIT = 4 };
 
 // operand types whose rows carry a per-row scale
 template <int DT> constexpr bool dt_scaled = DT == DT_FP8 || DT == DT_FP8B;
@@ -48,6 +52,7 @@ template <> struct Elt<DT_F32> { typedef float T; static constexpr int bytes = 4
 template <> struct Elt<DT_BF16> { typedef uint16_t T; static constexpr int bytes = 2; };
 template <> struct Elt<DT_FP8> { typedef uint8_t T; static constexpr int bytes = 1; };
 template <> struct Elt<DT_FP8B> { typedef uint16_t T; static constexpr int bytes = 2; };
+template <> struct Elt<DT_SPLIT> { typedef uint16_t T; static constexpr int bytes = 2; };
 
 // Canonical FP64 inner product of two stored rows over the first d elements:
 // FP32/BF16 data: ((0 + a0 b0) + a1 b1) + ... in index order (products exact in FP64);

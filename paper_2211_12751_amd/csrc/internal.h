@@ -29,9 +29,10 @@ int elt_bytes(int dtype);
 void launch_norm_stats_init(unsigned long long* stats, hipStream_t s);
 void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, int d, int ld,
                   double* n2, unsigned long long* stats, int slot, hipStream_t s);
-// FP32 rows [rows x ld] -> BF16 rows [rows x 3 ld]: items [h | l | h] (user_layout 0),
-// users and queries [h | h | l] (user_layout 1); their BF16 dot product approximates the
-// FP32 one within split_err_rel.
+// FP32 rows [rows x ld] -> BF16 rows [rows x 3 ld]: [h | l | h] (user_layout 0) against
+// [h | h | l] (user_layout 1), whose BF16 dot product approximates the FP32 one within
+// split_err_rel; user_layout 2 gives the pair rows [rows x 2 ld] = [h | l] that the top-k
+// passes expand to the same three products.
 void launch_split_bf16(const float* src, int64_t rows, int ld, uint16_t* dst, int user_layout, hipStream_t s);
 // Matrix-core operand rows [rows x mma_ld] (BF16 bits) from stored rows [rows x ld]:
 // split FP32 (see launch_split_bf16) or widened FP8 codes.

@@ -119,6 +119,12 @@ __global__ void k_split_bf16(const float* src, int64_t rows, int ld, uint16_t* d
     const float x = src[t];
     const uint16_t hb = f32_to_bf16_rn(x);
     const uint16_t lb = f32_to_bf16_rn(x - bf16_to_f32(hb));
+    if (user_layout == 2) {   // pair form [hi | lo]
+        uint16_t* row = dst + r * 2 * ld;
+        row[i] = hb;
+        row[ld + i] = lb;
+        return;
+    }
     uint16_t* row = dst + r * 3 * ld;
     row[i] = hb;
     row[ld + i] = user_layout ? hb : lb;

@@ -129,6 +129,17 @@ __device__ __forceinline__ f32x16 mfma_block(const uint8_t* tile, int row0, cons
         } else if constexpr (dt_bf16_mma<DT>) {
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[t]),
                                                          __builtin_bit_cast(bf16x8, bfrag[t]), acc, 0, 0, 0);
+        } else if constexpr (DT == DT_SPLIT) {
+            // rows [hi | lo]: k-step t < KSTEPS / 2 of the hi half pairs with step
+            // t + KSTEPS / 2 of the lo half (same elements); three products per pair
+            constexpr int HK = KSTEPS / 2;
+            if (t < HK) {
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, af[t]), al = __builtin_bit_cast(bf16x8, af[t + HK]);
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, bfrag[t]), bl = __builtin_bit_cast(bf16x8, bfrag[t + HK]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+            }
         } else {
             static_assert(dt_bf16_mma<DT>, "FP8 codes reach the matrix cores widened to BF16");
         }
@@ -180,8 +191,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     const int64_t seg0 = a.v0 + (int64_t)segl * a.seg_len;
     int64_t seg1 = seg0 + a.seg_len;
     if (seg1 > a.v1) seg1 = a.v1;
-    const int64_t ntiles = seg1 > seg0 ? (seg1 - seg0 + IT - 1) / IT : 0;
-    const int64_t nblk = ntiles * BPT;
+    const int seg_rows = seg1 > seg0 ? (int)(seg1 - seg0) : 0;   // segment-relative from here on
+    const int ntiles = (seg_rows + IT - 1) / IT;
+    const int nblk = ntiles * BPT;
 
     // ---- resident user fragments (the B operand), one user column per lane
     const int64_t ug = (int64_t)blockIdx.x * (TK_WAVES * 32) + (int64_t)w * 32 + (l & 31);
@@ -199,7 +211,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     if (MODE == TK_MAIN && uok && a.theta_init) theta = a.theta_init[ug * a.theta_stride];
     if (!uok) theta = __builtin_inff();   // +inf: nothing enters
     const float su = (dt_scaled<DT> && uok) ? a.user_scales[ug] : 1.0f;
-    int cnt = 0;              // entries this lane appended to its half of the buffer
     const int HG = a.G / 2;
     // the workgroup's users' buffers start at wbuf; this lane's half at wbuf + loff
     // (a lane past the last user never appends: its threshold is +inf)
@@ -209,12 +220,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         a.buf + (int64_t)blockIdx.x * (TK_WAVES * 32) * a.nseg_total * a.G, (short)0,
         (int)(wusers * a.nseg_total * a.G * (int64_t)sizeof(uint2)), 0x00020000);
     const uint32_t loff8 = 8u * (uint32_t)(((w * 32 + (l & 31)) * a.nseg_total + seg) * a.G + h * HG);
+    uint32_t off = loff8;                                   // byte offset of this lane's next entry
+    const uint32_t off_full = loff8 + 8u * (uint32_t)(HG - 16);   // past it a block may overflow the half
     float top[MODE == TK_SEED ? TK_T : 1];
 #pragma unroll
     for (int i = 0; i < (MODE == TK_SEED ? TK_T : 1); i++) top[i] = -__builtin_inff();
 
     // ---- item tiles: registers hold tile T + 1 while tile T is scored
-    auto load_chunk = [&](int64_t tt, int c) -> i32x4 {
+    auto load_chunk = [&](int tt, int c) -> i32x4 {
         const int r = c / (ROWB / 16), c16 = c % (ROWB / 16);
         const int64_t v = seg0 + tt * IT + r;
         i32x4 val = {0, 0, 0, 0};
@@ -223,11 +236,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         return val;
     };
     i32x4 pf[PF];
-    auto prefetch = [&](int64_t tt) {
+    auto prefetch = [&](int tt) {
+        if constexpr (MODE == TK_MAIN) {
+            // the segment's rows are contiguous: chunk c of the tile lies c * 16 bytes past
+            // its first row, and the descriptor ends with the tile's last row (chunks past
+            // it, in the segment's last tile, read zeros)
+            const int r0 = tt * IT;
+            const int rows = seg_rows - r0 < IT ? seg_rows - r0 : IT;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)((const uint8_t*)a.items + (seg0 + r0) * ROWB), (short)0, rows * ROWB, 0x00020000);
 #pragma unroll
-        for (int e = 0; e < PF; e++) pf[e] = load_chunk(tt, threadIdx.x + 256 * e);
+            for (int e = 0; e < PF; e++)
+                pf[e] = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                      rs, (int)(threadIdx.x + 256 * e) * 16, 0, 0));
+        } else {
+#pragma unroll
+            for (int e = 0; e < PF; e++) pf[e] = load_chunk(tt, threadIdx.x + 256 * e);
+        }
     };
-    auto stage_tile = [&](int64_t tt) {   // registers -> LDS buffer of tile tt
+    auto stage_tile = [&](int tt) {   // registers -> LDS buffer of tile tt
         uint8_t* dst = tile[tt & 1];
 #pragma unroll
         for (int e = 0; e < PF; e++) {
@@ -242,16 +269,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
 
     // scores of block b as they enter the epilogue, in place (FP8 scaled, rows past the
     // end -inf)
-    auto scores = [&](f32x16& v, int64_t b) {
-        const int64_t tt = b / BPT;
-        const int rb = (int)(b % BPT);
-        const int64_t base = seg0 + tt * IT + rb * 32;
+    auto scores = [&](f32x16& v, int b) {
+        const int tt = b / BPT;
+        const int rb = b % BPT;
+        const int base = tt * IT + rb * 32;
         if constexpr (dt_scaled<DT>) {
 #pragma unroll
             for (int r = 0; r < 16; r++) v[r] = (su * tscale[tt % 3][rb * 32 + mfma32_row(r, l)]) * v[r];
         }
-        if (base + 32 > seg1) {   // wave-uniform: the segment's last block
-            const int rem = (int)(seg1 - base);
+        if (base + 32 > seg_rows) {   // wave-uniform: the segment's last block
+            const int rem = seg_rows - base;
 #pragma unroll
             for (int r = 0; r < 16; r++)
                 if (mfma32_row(r, l) >= rem) v[r] = -__builtin_inff();
@@ -275,12 +302,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         return pm;
     };
     // appends of block b (main pass)
-    auto late = [&](const f32x16& v, uint32_t, int64_t b) {
+    auto late = [&](const f32x16& v, uint32_t, int b) {
         if constexpr (MODE == TK_MAIN) {
             // compaction of the users whose half-buffer could overflow in this block (a lane
             // appends at most 16 entries per block)
-            const uint64_t need = ballot64(cnt + 16 > HG);
+            const uint64_t need = ballot64(off > off_full);
             if (need) {
+                const int cnt = (int)((off - loff8) >> 3);
                 uint32_t um = (uint32_t)need | (uint32_t)(need >> 32);
                 while (um) {
                     const int ul = __builtin_ctz(um);
@@ -291,7 +319,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                     const uint32_t T = select_user(rg, c0, rg + HG, c1, a.C, hist, stage);
                     if ((l & 31) == ul) {
                         theta = ord_f32(T);
-                        cnt = h ? 0 : a.C;
+                        off = loff8 + (h ? 0u : 8u * (uint32_t)a.C);
                     }
                 }
             }
@@ -299,13 +327,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
             // that no lane passes costs one compare and one branch.  Entries are the raw
             // score bits and the item position, at 32-bit offsets from the workgroup's
             // buffer base.
-            const uint32_t pbase = (uint32_t)(seg0 + (b / BPT) * IT + (b % BPT) * 32) + 4u * (uint32_t)h;
+            const uint32_t pbase = (uint32_t)seg0 + (uint32_t)(b * 32) + 4u * (uint32_t)h;
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 if (v[r] > theta) {
                     const u32x2 e = {__float_as_uint(v[r]), pbase + (uint32_t)(8 * (r / 4) + (r % 4))};
-                    __builtin_amdgcn_raw_buffer_store_b64(e, wrsrc, (int)(loff8 + 8u * (uint32_t)cnt), 0, 0);
-                    cnt++;
+                    __builtin_amdgcn_raw_buffer_store_b64(e, wrsrc, (int)off, 0, 0);
+                    off += 8u;
                 }
             }
         }
@@ -317,17 +345,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         __syncthreads();
         if (ntiles > 1) prefetch(1);
         f32x16 acc = mfma_block<DT, KSTEPS, LROW>(tile[0], 0, bfrag);
-        for (int64_t b = 0; b < nblk; b++) {
+        for (int b = 0; b < nblk; b++) {
             scores(acc, b);
             late(acc, early(acc), b);
             if (b + 1 < nblk) {
-                const int64_t tn = (b + 1) / BPT;
+                const int tn = (b + 1) / BPT;
                 if ((b + 1) % BPT == 0) {      // block b + 1 opens tile tn
                     stage_tile(tn);
                     __syncthreads();
                     if (tn + 1 < ntiles) prefetch(tn + 1);
                 }
-                acc = mfma_block<DT, KSTEPS, LROW>(tile[tn & 1], (int)((b + 1) % BPT) * 32, bfrag);
+                acc = mfma_block<DT, KSTEPS, LROW>(tile[tn & 1], ((b + 1) % BPT) * 32, bfrag);
             }
         }
     }
@@ -339,7 +367,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     } else {
         // the buffer halves may hold up to G entries together; the refine pass selects
         if (uok) {
-            a.cnt[(ug * a.nseg_total + seg) * 2 + h] = cnt;
+            a.cnt[(ug * a.nseg_total + seg) * 2 + h] = (int)((off - loff8) >> 3);
             if (h == 0) a.tau[ug * a.nseg_total + seg] = theta;
         }
     }
@@ -384,15 +412,15 @@ static int resident_g(int G)
 template <int DT>
 static int resident_d(int ld, int G)
 {
-    if constexpr (DT == DT_BF16) {   // split BF16 rows of FP32 data: 3 x 32, 3 x 64
-        if (ld == 96) return resident_g<DT, 96>(G);
-        if (ld == 192) return resident_g<DT, 192>(G);
-    }
-    switch (ld) {
-    case 32: return resident_g<DT, 32>(G);
-    case 64: return resident_g<DT, 64>(G);
-    case 128: return resident_g<DT, 128>(G);
-    default: return resident_g<DT, 256>(G);
+    if constexpr (DT == DT_SPLIT) {   // pair rows of FP32 data: 2 x 32, 2 x 64
+        return ld == 64 ? resident_g<DT, 64>(G) : resident_g<DT, 128>(G);
+    } else {
+        switch (ld) {
+        case 32: return resident_g<DT, 32>(G);
+        case 64: return resident_g<DT, 64>(G);
+        case 128: return resident_g<DT, 128>(G);
+        default: return resident_g<DT, 256>(G);
+        }
     }
 }
 
@@ -413,6 +441,7 @@ int topk_resident_blocks(int dtype, int ld, int G)
     if (dtype == DT_F32) nb = resident_d<DT_F32>(ld, G);
     else if (dtype == DT_BF16) nb = resident_d<DT_BF16>(ld, G);
     else if (dtype == DT_FP8B) nb = resident_d<DT_FP8B>(ld, G);
+    else if (dtype == DT_SPLIT) nb = resident_d<DT_SPLIT>(ld, G);
     else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     std::lock_guard<std::mutex> g(mu);
     cache[key] = nb;
@@ -422,16 +451,18 @@ int topk_resident_blocks(int dtype, int ld, int G)
 template <int DT, int MODE>
 static void topk_dispatch(const TopkArgs& a, hipStream_t s)
 {
-    if constexpr (DT == DT_BF16) {
-        if (a.ld == 96) return topk_dispatch_g<DT, 96, MODE>(a, s);
-        if (a.ld == 192) return topk_dispatch_g<DT, 192, MODE>(a, s);
-    }
-    switch (a.ld) {
-    case 32: topk_dispatch_g<DT, 32, MODE>(a, s); break;
-    case 64: topk_dispatch_g<DT, 64, MODE>(a, s); break;
-    case 128: topk_dispatch_g<DT, 128, MODE>(a, s); break;
-    case 256: topk_dispatch_g<DT, 256, MODE>(a, s); break;
-    default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
+    if constexpr (DT == DT_SPLIT) {   // pair rows of FP32 data: 2 x 32, 2 x 64
+        if (a.ld == 64) topk_dispatch_g<DT, 64, MODE>(a, s);
+        else if (a.ld == 128) topk_dispatch_g<DT, 128, MODE>(a, s);
+        else fail(RKMIPS_EINVAL, "internal: unsupported split row length");
+    } else {
+        switch (a.ld) {
+        case 32: topk_dispatch_g<DT, 32, MODE>(a, s); break;
+        case 64: topk_dispatch_g<DT, 64, MODE>(a, s); break;
+        case 128: topk_dispatch_g<DT, 128, MODE>(a, s); break;
+        case 256: topk_dispatch_g<DT, 256, MODE>(a, s); break;
+        default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
+        }
     }
 }
 
@@ -441,6 +472,7 @@ void launch_topk(int dtype, const TopkArgs& a, hipStream_t s)
     if (dtype == DT_F32) topk_dispatch<DT_F32, TK_MAIN>(a, s);
     else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_MAIN>(a, s);
     else if (dtype == DT_FP8B) topk_dispatch<DT_FP8B, TK_MAIN>(a, s);
+    else if (dtype == DT_SPLIT) topk_dispatch<DT_SPLIT, TK_MAIN>(a, s);
     else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());
 }
@@ -452,6 +484,7 @@ void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s)
     if (dtype == DT_F32) topk_dispatch<DT_F32, TK_SEED>(a, s);
     else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_SEED>(a, s);
     else if (dtype == DT_FP8B) topk_dispatch<DT_FP8B, TK_SEED>(a, s);
+    else if (dtype == DT_SPLIT) topk_dispatch<DT_SPLIT, TK_SEED>(a, s);
     else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());
 }
