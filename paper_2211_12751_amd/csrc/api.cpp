@@ -314,7 +314,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
 {
     const int64_t n = x.n, m = x.m;
     const int eb = elt_bytes(x.dtype);
-    Events ev(6);
+    Events ev(9);
     HIPC(hipEventRecord(ev.ev[0], s));
     // ---- validation + canonical norms of the caller's arrays
     DevBuf nstats, n2_items_orig, n2_users_orig;
@@ -323,8 +323,9 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     n2_users_orig.alloc(sizeof(double) * m);
     unsigned long long* st = (unsigned long long*)nstats.p;
     launch_norm_stats_init(st, s);
-    launch_norm2(x.dtype, items, item_scales, n, x.d, x.d, n2_items_orig.d(), st, 0, s);
     launch_norm2(x.dtype, users, user_scales, m, x.d, x.d, n2_users_orig.d(), st, 1, s);
+    HIPC(hipEventRecord(ev.ev[8], s));   // the Cone-Tree build needs only the users and their norms
+    launch_norm2(x.dtype, items, item_scales, n, x.d, x.d, n2_items_orig.d(), st, 0, s);
     PinBuf hst;
     hst.alloc(sizeof(unsigned long long) * 4);
     // read at the first host wait (inside the Cone-Tree build); until then the build
@@ -359,27 +360,38 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     launch_gather_rows(x.dtype, users, x.d, user_scales, nullptr, m, x.d, users_o.p, x.ld, uscales_o.f(), s);
     HIPC(hipEventRecord(ev.ev[1], s));
 
-    // The fused top-k passes (matrix-core bound) run on the caller's stream while the
-    // Cone-Tree and the SA-ALSH index (latency bound, host-checked) run on a second one.
-    // The refine pass waits for the second stream: enqueued earlier, its grid of one
-    // wave per user would hold the compute units the second stream's kernels need.
+    // The fused top-k passes (matrix-core bound) run on the caller's stream, followed by
+    // the item side of SA-ALSH; the Cone-Tree (latency bound, host-checked) and the SA-ALSH
+    // user codes run on a second stream.  The refine pass waits for the second stream:
+    // enqueued earlier, its grid of one wave per user would hold the compute units the
+    // second stream's kernels need.
     LambdaBuild L;
     lambda_topk(x, L, users_o, uscales_o.f(), s);
     const hipStream_t s2 = aux_stream(x.device);
-    HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
+    HIPC(hipStreamWaitEvent(s2, ev.ev[8], 0));
     {
         mem::StreamScope scope2(s2);
         HIPC(hipEventRecord(ev.ev[2], s2));
+        saalsh_projections(x, srp, s2);
+        HIPC(hipEventRecord(ev.ev[6], s2));
         // ---- Cone-Tree over user directions; users are stored in leaf order
-        build_cone(x, users, user_scales, n2_users_orig.d(), s2);
-        range_check(x, (const unsigned long long*)hst.p);   // the cone build has waited for the copy
-        x.t = *(const int*)hnp.p;
-        HIPC(hipEventRecord(ev.ev[4], s2));
-        // ---- SA-ALSH index
-        build_saalsh(x, srp, s2);
-        HIPC(hipEventRecord(ev.ev[5], s2));
+        build_cone(x, users, user_scales, n2_users_orig.d(), s2, [&] {
+            // while the first levels run: validation (the input statistics and the
+            // partition count were copied before ev1), then the item side of SA-ALSH
+            // behind the top-k passes
+            HIPC(hipEventSynchronize(ev.ev[1]));
+            range_check(x, (const unsigned long long*)hst.p);
+            x.t = *(const int*)hnp.p;
+            mem::StreamScope scope(s);
+            HIPC(hipStreamWaitEvent(s, ev.ev[6], 0));
+            HIPC(hipEventRecord(ev.ev[4], s));
+            saalsh_items(x, s);
+            HIPC(hipEventRecord(ev.ev[5], s));
+        });
+        saalsh_users(x, s2);
+        HIPC(hipEventRecord(ev.ev[7], s2));
     }
-    HIPC(hipStreamWaitEvent(s, ev.ev[5], 0));
+    HIPC(hipStreamWaitEvent(s, ev.ev[7], 0));
     lambda_refine(x, L, users_o, uscales_o.f(), n2_users_orig.d(), s);
 
     // ---- per-block quantities that need lambda (L^j(B))
@@ -399,7 +411,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
         x.ms_refine = ev_ms(le[1], le[2]);
     }
     x.ms_norms = ev_ms(ev.ev[0], ev.ev[1]);
-    x.ms_cone = ev_ms(ev.ev[2], ev.ev[4]);
+    x.ms_cone = ev_ms(ev.ev[2], ev.ev[7]);
     x.ms_total = ev_ms(ev.ev[0], ev.ev[3]);
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <utility>
@@ -133,10 +134,18 @@ struct Index {
 double fast_err_rel(int d);
 double split_err_rel(int d);
 void range_check(Index& x, const unsigned long long* stats);
+// Cone-Tree over the user directions (users end in leaf order).  `enqueued` runs once on
+// the host after the first batch of levels is on the stream, before the host's first
+// wait for them (work for other streams can be enqueued there).
 void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
-                hipStream_t s);
+                hipStream_t s, const std::function<void()>& enqueued);
 void finish_blocks(Index& x, hipStream_t s);
 void start_partitions(Index& x, int* h_num_parts, hipStream_t s);
-void build_saalsh(Index& x, const float* srp, hipStream_t s);
+// SA-ALSH index (Alg. 1) in three stream-ordered parts: the random projections, the item
+// side (partition centroids, radii, item codes; needs x.t) and the user codes (users in
+// leaf order).
+void saalsh_projections(Index& x, const float* srp, hipStream_t s);
+void saalsh_items(Index& x, hipStream_t s);
+void saalsh_users(Index& x, hipStream_t s);
 
 }  // namespace rk

@@ -421,7 +421,8 @@ __global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const uin
 }
 
 // ------------------------------------------------------------------ host orchestration
-void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s)
+void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s,
+                const std::function<void()>& enqueued)
 {
     const int64_t m = x.m;
     const int ld = x.ld;
@@ -493,6 +494,7 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     while (((int64_t)x.prm.leaf_size << batch) < m) batch++;
     batch += 3;
     int64_t nseg_final = 1;
+    bool hooked = false;
     while (more) {
         for (int rep = 0; rep < batch; rep++, level++) {
             const ConeLevelArgs a = level_args(level);
@@ -504,11 +506,16 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
             seg_a.swap(seg_b);
         }
         HIPC(hipMemcpyAsync(h_ctl.p, d_ctl.p, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
+        if (!hooked) {
+            hooked = true;
+            if (enqueued) enqueued();
+        }
         HIPC(hipStreamSynchronize(s));
         more = ((const int64_t*)h_ctl.p)[2] > 0;
         nseg_final = ((const int64_t*)h_ctl.p)[level & 1];
         batch = 2;
     }
+    if (!hooked && enqueued) enqueued();
     if (level == 0) HIPC(hipStreamSynchronize(s));   // the caller reads host copies made before the build
 
     // ---- leaves are the blocks; users move into leaf order

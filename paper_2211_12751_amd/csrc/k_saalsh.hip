@@ -345,18 +345,26 @@ void start_partitions(Index& x, int* h_num_parts, hipStream_t s)
 }
 
 // The rest of Alg. 1 once x.t is known; stream-ordered, no host synchronisation.
-void build_saalsh(Index& x, const float* srp, hipStream_t s)
+// Random projections of the transformed vectors: the caller's, or drawn from the seed.
+void saalsh_projections(Index& x, const float* srp, hipStream_t s)
 {
-    const int K = x.prm.num_hash, W = K / 32;
-    const int64_t n = x.n;
-    const int t = x.t;
+    const int K = x.prm.num_hash;
     x.srp.alloc(sizeof(float) * (size_t)(x.d + 1) * K);
     if (srp) HIPC(hipMemcpyAsync(x.srp.p, srp, sizeof(float) * (size_t)(x.d + 1) * K, hipMemcpyDeviceToDevice, s));
     else {
         const int64_t cnt = (int64_t)(x.d + 1) * K;
         hipLaunchKernelGGL(k_gen_srp, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, x.srp.f(), cnt,
                            x.prm.seed ^ 0x53525031ull);
+        HIPC(hipGetLastError());
     }
+}
+
+// Item side: partition centroids and radii, then the item codes.
+void saalsh_items(Index& x, hipStream_t s)
+{
+    const int K = x.prm.num_hash, W = K / 32;
+    const int64_t n = x.n;
+    const int t = x.t;
     // centroids and radii
     DevBuf cen64, r2, rad2bits, rad2;
     cen64.alloc(sizeof(double) * (size_t)t * x.ld);
@@ -390,9 +398,15 @@ void build_saalsh(Index& x, const float* srp, hipStream_t s)
         HIPC(hipGetLastError());
     }
     x.item_codes.alloc(sizeof(uint32_t) * (size_t)n * W);
-    x.user_codes.alloc(sizeof(uint32_t) * (size_t)x.m * W);
     project<0>(x.dtype, K, x.items.p, x.item_scales.f(), n, x.d, x.ld, x.part_start.i64(), t, x.centroid.f(), r2.d(),
                rad2.d(), x.srp.f(), x.item_codes.u32(), s);
+}
+
+// User codes, users in leaf order.
+void saalsh_users(Index& x, hipStream_t s)
+{
+    const int K = x.prm.num_hash, W = K / 32;
+    x.user_codes.alloc(sizeof(uint32_t) * (size_t)x.m * W);
     project<1>(x.dtype, K, x.users.p, x.user_scales.f(), x.m, x.d, x.ld, nullptr, 1, nullptr, nullptr, nullptr,
                x.srp.f(), x.user_codes.u32(), s);
 }

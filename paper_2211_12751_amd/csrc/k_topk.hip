@@ -29,22 +29,22 @@ static constexpr int TK_WAVES = 4;
 static constexpr int TK_IT = 64;  // items per LDS tile (two 32-row MFMA blocks)
 
 // ------------------------------------------------------------------ fused GEMM + top-k
-// Buffer compaction for the streaming pass, staged through LDS so that it needs few
-// registers (it runs rarely, and the main loop keeps its register budget for
+// Buffer compaction for the streaming pass, with the keys staged in LDS so that it needs
+// few registers (it runs rarely, and the main loop keeps its register budget for
 // occupancy): of the c0 entries at r0 and the c1 entries at r1, keep the C largest
 // (ties at the threshold in staging order) in r0[0, C) and return the C-th largest key
-// (orderable form; the entries themselves keep the raw score bits).
+// (orderable form; the entries themselves keep the raw score bits).  The kept entries
+// move down in place: entry i lands at a position <= i, and r0 is read in full before r1.
 __device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1, int c1, int C, int* hist,
-                                             uint2* stage)
+                                             uint32_t* stage)
 {
     const int l = lane_id();
     const int c = c0 + c1;
     for (int i = l; i < c; i += 64) {
         const uint2* src = i < c0 ? r0 + i : r1 + (i - c0);
-        const unsigned long long raw = __hip_atomic_load((const unsigned long long*)src, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t raw = __hip_atomic_load((const uint32_t*)src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // buffers hold raw score bits; the selection works on orderable keys
-        stage[i] = make_uint2(f32_ord(__uint_as_float((uint32_t)raw)), (uint32_t)(raw >> 32));
+        stage[i] = f32_ord(__uint_as_float(raw));
     }
     __builtin_amdgcn_wave_barrier();
     uint32_t prefix = 0u, pmask = 0u;
@@ -53,7 +53,7 @@ __device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1,
         for (int b = l; b < 256; b += 64) hist[b] = 0;
         __builtin_amdgcn_wave_barrier();
         for (int i = l; i < c; i += 64) {
-            const uint32_t k = stage[i].x;
+            const uint32_t k = stage[i];
             if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1);
         }
         __builtin_amdgcn_wave_barrier();
@@ -81,15 +81,21 @@ __device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1,
     for (int i0 = 0; i0 < c; i0 += 64) {
         const int i = i0 + l;
         const bool valid = i < c;
-        const uint2 e = valid ? stage[i] : make_uint2(0u, 0u);
-        const bool gt = valid && e.x > T;
-        const bool eq = valid && e.x == T;
+        const uint32_t key = valid ? stage[i] : 0u;
+        const bool gt = valid && key > T;
+        const bool eq = valid && key == T;
         const uint64_t eb = ballot64(eq);
         const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
         eq_before += __popcll(eb);
         const bool keep = gt || (eq && rank_eq < need);
         const uint64_t kb = ballot64(keep);
-        if (keep) r0[kept_before + __popcll(kb & lanemask_lt())] = make_uint2(__float_as_uint(ord_f32(e.x)), e.y);
+        // every lane of the chunk reads its entry before any lane writes
+        unsigned long long e = 0ull;
+        if (keep)
+            e = __hip_atomic_load((const unsigned long long*)(i < c0 ? r0 + i : r1 + (i - c0)), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_wave_barrier();
+        if (keep) r0[kept_before + __popcll(kb & lanemask_lt())] = make_uint2((uint32_t)e, (uint32_t)(e >> 32));
         kept_before += __popcll(kb);
     }
     __builtin_amdgcn_wave_barrier();
@@ -179,13 +185,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     __shared__ __attribute__((aligned(16))) uint8_t tile[2][IT * LROW];
     __shared__ float tscale[3][dt_scaled<DT> ? IT : 1];
     __shared__ int hist_all[TK_WAVES][MODE == TK_MAIN ? 256 : 1];
-    __shared__ uint2 stage_all[TK_WAVES][SGPL * 64];
+    __shared__ uint32_t stage_all[TK_WAVES][SGPL * 64];
 
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
     const int h = l >> 5;
     int* hist = hist_all[w];
-    uint2* stage = stage_all[w];
+    uint32_t* stage = stage_all[w];
     const int segl = blockIdx.y;
     const int seg = a.seg_base + segl;
     const int64_t seg0 = a.v0 + (int64_t)segl * a.seg_len;
