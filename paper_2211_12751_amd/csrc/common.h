@@ -114,6 +114,12 @@ __device__ __forceinline__ T wave_min(T v)
     for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o); v = v < w ? v : w; }
     return v;
 }
+template <typename T>
+__device__ __forceinline__ T wave_or(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
 // inclusive prefix sum over the wave
 __device__ __forceinline__ int wave_incl_scan(int v)
 {

@@ -14,19 +14,33 @@ namespace rk {
 // ------------------------------------------------------------------ wave radix select
 // C-th largest of the first c keys held GPL per lane (entry i of lane l is position
 // l + 64 i); *need_eq receives how many keys equal to it belong to the C largest.
+// Bits that all keys share are settled at once (close scores share their sign, exponent
+// and leading mantissa bits, and a histogram over them would put every key in one bin):
+// the digits of up to 8 bits start at the highest bit where two keys differ.
 template <int GPL>
 __device__ __forceinline__ uint32_t wave_kth_key(const uint32_t (&key)[GPL], int c, int C, int* hist, int* need_eq)
 {
     const int l = lane_id();
-    uint32_t prefix = 0u, pmask = 0u;
+    const uint32_t k0 = __shfl(key[0], 0);   // c > 0: position 0 holds a key
+    uint32_t diff = 0u;
+#pragma unroll
+    for (int i = 0; i < GPL; i++)
+        if (l + 64 * i < c) diff |= key[i] ^ k0;
+    diff = wave_or(diff);
+    int top = diff ? 32 - __builtin_clz(diff) : 0;   // bits [0, top) are still open
+    uint32_t pmask = top >= 32 ? 0u : ~((1u << top) - 1u);
+    uint32_t prefix = k0 & pmask;
     int need = C;
-    for (int shift = 24; shift >= 0; shift -= 8) {
+    while (top > 0) {
+        const int wd = top >= 8 ? 8 : top;
+        const int shift = top - wd;
+        const uint32_t dmask = (1u << wd) - 1u;
         for (int b = l; b < 256; b += 64) hist[b] = 0;
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int i = 0; i < GPL; i++) {
             if (64 * i >= c) break;   // wave-uniform: the rest of the slots are empty
-            if (l + 64 * i < c && (key[i] & pmask) == prefix) atomicAdd(&hist[(key[i] >> shift) & 255u], 1);
+            if (l + 64 * i < c && (key[i] & pmask) == prefix) atomicAdd(&hist[(key[i] >> shift) & dmask], 1);
         }
         __builtin_amdgcn_wave_barrier();
         int h[4], x = 0;
@@ -46,8 +60,9 @@ __device__ __forceinline__ uint32_t wave_kth_key(const uint32_t (&key)[GPL], int
         const int dsel = __shfl(sel, src);
         const int dabove = __shfl(sel_above, src);
         prefix |= (uint32_t)dsel << shift;
-        pmask |= 0xffu << shift;
+        pmask |= dmask << shift;
         need -= dabove;
+        top = shift;
         __builtin_amdgcn_wave_barrier();
     }
     *need_eq = need;
@@ -120,6 +135,82 @@ __device__ __forceinline__ double canon_dot_vec(const void* U, int64_t u, float 
     return acc;
 }
 
+// One 16-byte chunk of the canonical sum: elements c0 .. c0 + 16 / EB - 1 (those below d)
+// of user chunk a4 and item chunk b4, added in index order to acc.
+template <int DT>
+__device__ __forceinline__ double canon_chunk(const i32x4& a4, const i32x4& b4, int c0, int d, double acc)
+{
+    constexpr int PER = 16 / Elt<DT>::bytes;
+    const int lim = d - c0 < PER ? d - c0 : PER;
+#pragma unroll
+    for (int e = 0; e < PER; e++) {
+        if (e >= lim) break;
+        float x, y;
+        if constexpr (DT == DT_F32) {
+            x = __int_as_float(a4[e]);
+            y = __int_as_float(b4[e]);
+        } else if constexpr (DT == DT_BF16) {
+            x = bf16_to_f32((uint16_t)((uint32_t)a4[e >> 1] >> (16 * (e & 1))));
+            y = bf16_to_f32((uint16_t)((uint32_t)b4[e >> 1] >> (16 * (e & 1))));
+        } else {
+            x = e4m3_to_f32((uint8_t)((uint32_t)a4[e >> 2] >> (8 * (e & 3))));
+            y = e4m3_to_f32((uint8_t)((uint32_t)b4[e >> 2] >> (8 * (e & 3))));
+        }
+        acc = __fma_rn((double)x, (double)y, acc);
+    }
+    return acc;
+}
+
+// Canonical scores of user u against the items sid[0, Nk), lane l taking candidate l
+// (lanes past Nk, and positions past n, get -inf).  The candidate rows pass through LDS
+// in 64-byte column slices: four lanes load one row's slice with consecutive 16-byte
+// loads (one request per row and slice instead of one per lane and 16 bytes), then each
+// lane continues its own index-order sum over the slice.
+static constexpr int RF_SLICE = 64;
+static constexpr int RF_PITCH = RF_SLICE + 16;   // LDS row pitch (bank spread)
+
+template <int DT>
+__device__ __forceinline__ double canon_dot_staged(const RefineArgs& a, int64_t u, float su, const uint32_t* sid,
+                                                   int Nk, uint8_t* rows)
+{
+    constexpr int EB = Elt<DT>::bytes;
+    const int l = lane_id();
+    const int RB = a.ld * EB;
+    const uint8_t* ur = (const uint8_t*)a.users + u * (int64_t)RB;
+    const uint32_t mine = l < Nk ? sid[l] : 0xffffffffu;
+    const bool live = l < Nk && (int64_t)mine < a.n;   // positions come from k_topk; the test guards the loads
+    double acc = 0.0;
+    for (int s0 = 0; s0 < RB; s0 += RF_SLICE) {
+        constexpr int CPS = RF_SLICE / 16;   // chunks per row slice
+#pragma unroll
+        for (int i = 0; i < CPS; i++) {
+            const int k = i * 64 + l, r = k / CPS, c = k % CPS;
+            const int off = s0 + c * 16;
+            i32x4 val = {0, 0, 0, 0};
+            if (r < Nk && off < RB) {
+                const uint32_t p = sid[r];
+                if ((int64_t)p < a.n) val = *(const i32x4*)((const uint8_t*)a.items + (int64_t)p * RB + off);
+            }
+            *(i32x4*)(rows + r * RF_PITCH + c * 16) = val;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < CPS; c++) {
+                const int off = s0 + c * 16;
+                if (off >= RB) break;
+                const i32x4 b4 = *(const i32x4*)(rows + l * RF_PITCH + c * 16);
+                const i32x4 a4 = *(const i32x4*)(ur + off);
+                acc = canon_chunk<DT>(a4, b4, off / EB, a.d, acc);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!live) return -__builtin_inf();
+    if constexpr (DT == DT_FP8) acc = ((double)su * (double)a.item_scales[mine]) * acc;
+    return acc;
+}
+
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double v)
 {
     // non-negative doubles order like their bit patterns; skip the atomic when it cannot win
@@ -136,7 +227,7 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double 
 // score among all candidates when some were dropped here).
 template <int DT, int GPL, bool FAST>
 __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint32_t* sid, double* s64,
-                            float* sraw, double* lam_row, float* raw_row, int* hist)
+                            float* sraw, double* lam_row, float* raw_row, int* hist, uint8_t* rows)
 {
     const int l = lane_id();
     // gather every segment's buffer straight into registers (entry j = lane + 64 i)
@@ -211,17 +302,9 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
     };
     if (FAST || Nk <= 64) {
         // one candidate per lane; the ranks come from two bitonic sorts across the wave
-        double v = -__builtin_inf();
-        uint32_t rk = 0u;   // orderable fast-score key (0 sorts below every score)
+        double v = canon_dot_staged<DT>(a, u, su, sid, Nk, rows);
+        uint32_t rk = l < Nk ? skey[l] : 0u;   // orderable fast-score key (0 sorts below every score)
         int idx = l;
-        if (l < Nk) {
-            const int64_t p = sid[l];
-            if (p < a.n) {   // never produced by k_topk; guards the loads below
-                const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-                v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-            }
-            rk = skey[l];
-        }
 #pragma unroll
         for (int kk = 2; kk <= 64; kk <<= 1)
 #pragma unroll
@@ -301,8 +384,10 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
 // One wave per user (all users, or the users listed in a.list when it is given).  The
 // narrow instance (GPL = 8, C <= 64) keeps its state small for occupancy and hands
 // users with more than 512 candidates to the wide instance through a.spill.
+// The narrow instance is latency bound (several dependent global round trips per user):
+// it trades a few spilled registers for six resident waves per SIMD.
 template <int DT, int GPL, bool FAST>
-__global__ __launch_bounds__(256) void k_refine(RefineArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FAST ? 6 : 2, 8))) void k_refine(RefineArgs a)
 {
     __shared__ uint32_t skey[4][FAST ? 64 : 256];
     __shared__ uint32_t sid[4][FAST ? 64 : 256];
@@ -311,16 +396,18 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     __shared__ double lam_row[4][FAST ? 1 : 256];
     __shared__ float raw_row[4][FAST ? 1 : 256];
     __shared__ int hist_all[4][256];
+    __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
     const int w = threadIdx.x >> 6;
     if (!a.list) {
         const int64_t u = (int64_t)blockIdx.x * 4 + w;
         if (u < a.m)
-            refine_user<DT, GPL, FAST>(a, u, skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w], hist_all[w]);
+            refine_user<DT, GPL, FAST>(a, u, skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w], hist_all[w],
+                                       rows_all[w]);
     } else {
         const int cnt = *a.list_count;
         for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < cnt; i += (int64_t)gridDim.x * 4)
             refine_user<DT, GPL, FAST>(a, a.list[i], skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w],
-                                       hist_all[w]);
+                                       hist_all[w], rows_all[w]);
     }
 }
 
