@@ -28,6 +28,15 @@ void hip_check(hipError_t e, const char* what)
     if (e != hipSuccess) fail(RKMIPS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+void host_wait(hipEvent_t e)
+{
+    for (;;) {
+        const hipError_t r = hipEventQuery(e);
+        if (r == hipSuccess) return;
+        if (r != hipErrorNotReady) hip_check(r, "hipEventQuery");
+    }
+}
+
 int elt_bytes(int dtype) { return dtype == RKMIPS_F32 ? 4 : dtype == RKMIPS_BF16 ? 2 : 1; }
 
 int padded_dim(int d, int /*dtype*/)
@@ -312,6 +321,13 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
 static void build_index(Index& x, const void* items, const float* item_scales, const void* users,
                         const float* user_scales, const float* srp, hipStream_t s)
 {
+    // declared first, released last: once the device has finished the build, the buffers
+    // below go back to the cache without per-buffer events
+    struct IdleAfterWait {
+        bool on = false;
+        void enter() { mem::idle_enter(); on = true; }
+        ~IdleAfterWait() { if (on) mem::idle_leave(); }
+    } idle_tail;
     const int64_t n = x.n, m = x.m;
     const int eb = elt_bytes(x.dtype);
     Events ev(9);
@@ -366,6 +382,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     // enqueued earlier, its grid of one wave per user would hold the compute units the
     // second stream's kernels need.
     LambdaBuild L;
+    ConeWork cone_work;
     lambda_topk(x, L, users_o, uscales_o.f(), s);
     const hipStream_t s2 = aux_stream(x.device);
     HIPC(hipStreamWaitEvent(s2, ev.ev[8], 0));
@@ -379,7 +396,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
             // while the first levels run: validation (the input statistics and the
             // partition count were copied before ev1), then the item side of SA-ALSH
             // behind the top-k passes
-            HIPC(hipEventSynchronize(ev.ev[1]));
+            host_wait(ev.ev[1]);
             range_check(x, (const unsigned long long*)hst.p);
             x.t = *(const int*)hnp.p;
             mem::StreamScope scope(s);
@@ -387,7 +404,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
             HIPC(hipEventRecord(ev.ev[4], s));
             saalsh_items(x, s);
             HIPC(hipEventRecord(ev.ev[5], s));
-        });
+        }, cone_work);
         saalsh_users(x, s2);
         HIPC(hipEventRecord(ev.ev[7], s2));
     }
@@ -397,7 +414,8 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     // ---- per-block quantities that need lambda (L^j(B))
     finish_blocks(x, s);
     HIPC(hipEventRecord(ev.ev[3], s));
-    HIPC(hipStreamSynchronize(s));
+    host_wait(ev.ev[3]);   // the second stream's work precedes ev[7], which the caller's stream waited on
+    idle_tail.enter();
     x.ms_saalsh = ev_ms(ev.ev[4], ev.ev[5]);
     {
         const unsigned long long* hs = (const unsigned long long*)x.h_lam_stats.p;

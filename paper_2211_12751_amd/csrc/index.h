@@ -134,11 +134,18 @@ struct Index {
 double fast_err_rel(int d);
 double split_err_rel(int d);
 void range_check(Index& x, const unsigned long long* stats);
+// Working buffers of the Cone-Tree build, owned by the caller so that their release
+// (and its host cost) can wait until the rest of the build is on its streams.
+struct ConeWork {
+    DevBuf unit, perm_a, perm_b, seg_a, seg_b, dot_l, left, lrank, blk_cnt;
+    DevBuf d_start[2], d_act[2], d_key1[2], d_key2[2], d_ctl, d_nleft, d_degen, d_next_index;
+    PinBuf h_ctl;
+};
 // Cone-Tree over the user directions (users end in leaf order).  `enqueued` runs once on
 // the host after the first batch of levels is on the stream, before the host's first
 // wait for them (work for other streams can be enqueued there).
 void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
-                hipStream_t s, const std::function<void()>& enqueued);
+                hipStream_t s, const std::function<void()>& enqueued, ConeWork& cw);
 void finish_blocks(Index& x, hipStream_t s);
 void start_partitions(Index& x, int* h_num_parts, hipStream_t s);
 // SA-ALSH index (Alg. 1) in three stream-ordered parts: the random projections, the item

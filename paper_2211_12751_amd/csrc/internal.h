@@ -18,6 +18,9 @@ struct Error {
 [[noreturn]] void fail(rkmips_status st, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
 #define HIPC(x) ::rk::hip_check((x), #x)
+// Waits on the host until event e has completed, polling it (a blocking wait can add tens
+// of microseconds of wake-up latency to every host round trip).
+void host_wait(hipEvent_t e);
 
 // Padded row length (elements) used for the stored copies of all vector sets.
 int padded_dim(int d, int dtype);

@@ -422,11 +422,12 @@ __global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const uin
 
 // ------------------------------------------------------------------ host orchestration
 void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s,
-                const std::function<void()>& enqueued)
+                const std::function<void()>& enqueued, ConeWork& cw)
 {
     const int64_t m = x.m;
     const int ld = x.ld;
-    DevBuf unit, perm_a, perm_b, seg_a, seg_b, dot_l, left, lrank, blk_cnt;
+    DevBuf &unit = cw.unit, &perm_a = cw.perm_a, &perm_b = cw.perm_b, &seg_a = cw.seg_a, &seg_b = cw.seg_b;
+    DevBuf &dot_l = cw.dot_l, &left = cw.left, &lrank = cw.lrank, &blk_cnt = cw.blk_cnt;
     unit.alloc(sizeof(uint16_t) * (size_t)m * ld);
     {
         const int64_t tot = m * ld;
@@ -449,7 +450,11 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     // segments changes nothing, so levels past the last split are harmless.
     const int64_t cap = m + 2;
     const int64_t act_cap = m / ((int64_t)x.prm.leaf_size + 1) + 1;   // active segments hold > N0 users
-    DevBuf d_start[2], d_act[2], d_key1[2], d_key2[2], d_ctl, d_nleft, d_degen, d_next_index;
+    DevBuf(&d_start)[2] = cw.d_start;
+    DevBuf(&d_act)[2] = cw.d_act;
+    DevBuf(&d_key1)[2] = cw.d_key1;
+    DevBuf(&d_key2)[2] = cw.d_key2;
+    DevBuf &d_ctl = cw.d_ctl, &d_nleft = cw.d_nleft, &d_degen = cw.d_degen, &d_next_index = cw.d_next_index;
     for (int i = 0; i < 2; i++) {
         d_start[i].alloc(sizeof(int64_t) * (cap + 1));
         d_act[i].alloc(sizeof(int) * cap);
@@ -460,8 +465,14 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     d_nleft.alloc(sizeof(int) * cap);
     d_degen.alloc(sizeof(int) * cap);
     d_next_index.alloc(sizeof(int) * cap);
-    PinBuf h_ctl;
+    PinBuf& h_ctl = cw.h_ctl;
     h_ctl.alloc(sizeof(int64_t) * 4);
+    hipEvent_t ev_ctl = nullptr;
+    HIPC(hipEventCreateWithFlags(&ev_ctl, hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t e;
+        ~EvGuard() { (void)hipEventDestroy(e); }
+    } ev_guard{ev_ctl};
     auto level_args = [&](int level) {
         const int c = level & 1, n = c ^ 1;
         ConeLevelArgs a{};
@@ -506,17 +517,21 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
             seg_a.swap(seg_b);
         }
         HIPC(hipMemcpyAsync(h_ctl.p, d_ctl.p, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
+        HIPC(hipEventRecord(ev_ctl, s));
         if (!hooked) {
             hooked = true;
             if (enqueued) enqueued();
         }
-        HIPC(hipStreamSynchronize(s));
+        host_wait(ev_ctl);
         more = ((const int64_t*)h_ctl.p)[2] > 0;
         nseg_final = ((const int64_t*)h_ctl.p)[level & 1];
         batch = 2;
     }
     if (!hooked && enqueued) enqueued();
-    if (level == 0) HIPC(hipStreamSynchronize(s));   // the caller reads host copies made before the build
+    if (level == 0) {   // the caller reads host copies made before the build
+        HIPC(hipEventRecord(ev_ctl, s));
+        host_wait(ev_ctl);
+    }
 
     // ---- leaves are the blocks; users move into leaf order
     x.nblocks = nseg_final;

@@ -277,7 +277,7 @@ void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs
 void finish_batch(Index& x, Workspace& w, const void* queries, const float* qscales, int64_t nq, int flags,
                   hipStream_t s, std::vector<int64_t>& offsets, std::vector<int32_t>& ids, rkmips_query_stats& st)
 {
-    HIPC(hipEventSynchronize(w.ev_ctr));
+    host_wait(w.ev_ctr);
     unsigned long long* hc = (unsigned long long*)w.h_ctr.p;
     if (hc[2] & 1ull) fail(RKMIPS_EINVAL, "non-finite value (or NaN code / non-finite scale) in the queries");
     if (hc[2] & 2ull) fail(RKMIPS_ERANGE, "a query norm is outside [1e-30, 1e30]");
@@ -286,7 +286,7 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
         // the result pool was too small: grow it and run the batch again
         w.ensure(x, nq, 2 * (cnt + namb) + 1, 2 * namb + 1);
         enqueue_batch(x, w, queries, qscales, nq, flags, s);
-        HIPC(hipEventSynchronize(w.ev_ctr));
+        host_wait(w.ev_ctr);
         cnt = (int64_t)hc[0];
         namb = (int64_t)hc[1];
         if (cnt + namb > w.pool_cap || namb > w.amb_cap) fail(RKMIPS_ENOMEM, "result pool overflow");
@@ -331,7 +331,7 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     }
     if (reject) HIPC(hipMemcpyAsync(w.h_ctr.p, w.ctr.p, sizeof(unsigned long long) * 16, hipMemcpyDeviceToHost, s));
     HIPC(hipEventRecord(w.ev1, s));
-    HIPC(hipStreamSynchronize(s));
+    host_wait(w.ev1);
     if (reject) st.saalsh_rejects = (int64_t)((unsigned long long*)w.h_ctr.p)[12];
     offsets.assign(ho, ho + nq + 1);
     ids.assign((const int32_t*)w.h_ids.p, (const int32_t*)w.h_ids.p + total);
