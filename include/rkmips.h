@@ -109,7 +109,12 @@ void rkmips_default_params(rkmips_params *p);
  * device FP32 [n] / [m] for FP8 data, else NULL.  srp_proj: device FP32
  * [(d+1) x num_hash] row-major Gaussian projection matrix (column h is the vector a
  * of one hash function), or NULL to draw it from p->seed inside the library.
- * p: NULL for defaults.  Synchronous: returns after the index is complete.
+ * p: NULL for defaults.  Returns once every host-side check is done and the rest of
+ * the build is queued on `stream` (the last part, FP64 refinement and block bounds,
+ * may still be running): work queued on `stream` afterwards sees the complete index,
+ * query batches on other streams wait for it on the device, and the host-side getters
+ * (info, lambda, blocks, candidates, SA-ALSH data) wait for it on the host.  The input
+ * arrays must stay valid until the build is complete (rkmips_get_info waits for it).
  * Errors: EINVAL (null pointers, n, m, d < 1, d > 256, bad params, non-finite
  * values), ERANGE (max||u|| * max||p|| beyond 1e30 or a non-zero vector norm below
  * 1e-30, where FP32 bounds would lose exactness), ENOMEM, EDEVICE.

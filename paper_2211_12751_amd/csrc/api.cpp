@@ -321,13 +321,6 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
 static void build_index(Index& x, const void* items, const float* item_scales, const void* users,
                         const float* user_scales, const float* srp, hipStream_t s)
 {
-    // declared first, released last: once the device has finished the build, the buffers
-    // below go back to the cache without per-buffer events
-    struct IdleAfterWait {
-        bool on = false;
-        void enter() { mem::idle_enter(); on = true; }
-        ~IdleAfterWait() { if (on) mem::idle_leave(); }
-    } idle_tail;
     const int64_t n = x.n, m = x.m;
     const int eb = elt_bytes(x.dtype);
     Events ev(9);
@@ -413,24 +406,44 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
 
     // ---- per-block quantities that need lambda (L^j(B))
     finish_blocks(x, s);
+    // ev[3] follows every kernel of the build: the second stream's work precedes ev[7],
+    // which the caller's stream waited on.  No host wait here: the temporaries below go
+    // back to the cache tagged with events on the caller's stream, and the caller can
+    // queue its first query batch while the refine pass is still running.
     HIPC(hipEventRecord(ev.ev[3], s));
-    host_wait(ev.ev[3]);   // the second stream's work precedes ev[7], which the caller's stream waited on
-    idle_tail.enter();
-    x.ms_saalsh = ev_ms(ev.ev[4], ev.ev[5]);
-    {
-        const unsigned long long* hs = (const unsigned long long*)x.h_lam_stats.p;
-        std::memcpy(&x.max_rel_err_raw, &hs[0], 8);
-        std::memcpy(&x.max_rel_err_l32, &hs[1], 8);
-        x.cert_failures = (int64_t)*(const int*)(hs + 2);
-        const std::vector<hipEvent_t>& le = x.lam_ev;
-        x.ms_seed = ev_ms(le[0], le[3]);
-        x.ms_topk = ev_ms(le[3], le[1]);
-        x.ms_lambda = ev_ms(le[0], le[1]);
-        x.ms_refine = ev_ms(le[1], le[2]);
-    }
-    x.ms_norms = ev_ms(ev.ev[0], ev.ev[1]);
-    x.ms_cone = ev_ms(ev.ev[2], ev.ev[7]);
-    x.ms_total = ev_ms(ev.ev[0], ev.ev[3]);
+    x.build_ev.swap(ev.ev);
+    x.ready_ev = x.build_ev[3];
+}
+
+// Build statistics, read once the build is complete (the timings need its events done).
+static void take_build_stats(Index& x)
+{
+    const std::vector<hipEvent_t>& ev = x.build_ev;
+    x.ms_saalsh = ev_ms(ev[4], ev[5]);
+    const unsigned long long* hs = (const unsigned long long*)x.h_lam_stats.p;
+    std::memcpy(&x.max_rel_err_raw, &hs[0], 8);
+    std::memcpy(&x.max_rel_err_l32, &hs[1], 8);
+    x.cert_failures = (int64_t)*(const int*)(hs + 2);
+    const std::vector<hipEvent_t>& le = x.lam_ev;
+    x.ms_seed = ev_ms(le[0], le[3]);
+    x.ms_topk = ev_ms(le[3], le[1]);
+    x.ms_lambda = ev_ms(le[0], le[1]);
+    x.ms_refine = ev_ms(le[1], le[2]);
+    x.ms_norms = ev_ms(ev[0], ev[1]);
+    x.ms_cone = ev_ms(ev[2], ev[7]);
+    x.ms_total = ev_ms(ev[0], ev[3]);
+}
+
+void Index::wait_ready()
+{
+    if (!ready_ev) return;
+    host_wait(ready_ev);
+    std::call_once(stats_once, [this] { take_build_stats(*this); });
+}
+
+void Index::ready_on(hipStream_t s) const
+{
+    if (ready_ev) HIPC(hipStreamWaitEvent(s, ready_ev, 0));
 }
 
 // Refuse magnitudes where the FP32 fast path could overflow or lose the error model.
@@ -456,6 +469,8 @@ Index::~Index()
     // blocks (the members are released after this body, the tail guard ends the scope)
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : lam_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : build_ev)
         if (e) (void)hipEventDestroy(e);
     mem::idle_enter();
 }
@@ -556,7 +571,8 @@ rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
 {
     return guarded([&] {
         if (!idx || !o) fail(RKMIPS_EINVAL, "NULL argument");
-        const Index& x = *(const Index*)idx;
+        Index& x = *(Index*)idx;
+        x.wait_ready();
         std::memset(o, 0, sizeof *o);
         o->n = x.n; o->m = x.m; o->d = x.d; o->dtype = x.dtype; o->k_max = x.prm.k_max;
         o->cand_per_user = x.G * x.nseg; o->num_hash = x.prm.num_hash; o->leaf_size = x.prm.leaf_size;
@@ -576,7 +592,8 @@ rkmips_status rkmips_get_lambda(const rkmips_index* idx, int32_t k, double* out_
 {
     return guarded([&] {
         if (!idx || !out_m) fail(RKMIPS_EINVAL, "NULL argument");
-        const Index& x = *(const Index*)idx;
+        Index& x = *(Index*)idx;
+        x.wait_ready();
         if (k < 1 || k > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
         HIPC(hipMemcpy(out_m, x.lam64.d() + (int64_t)(k - 1) * x.m, sizeof(double) * x.m, hipMemcpyDeviceToHost));
     });
@@ -586,7 +603,8 @@ rkmips_status rkmips_get_lambda32(const rkmips_index* idx, int32_t k, float* out
 {
     return guarded([&] {
         if (!idx || !out_m) fail(RKMIPS_EINVAL, "NULL argument");
-        const Index& x = *(const Index*)idx;
+        Index& x = *(Index*)idx;
+        x.wait_ready();
         if (k < 1 || k > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
         HIPC(hipMemcpy(out_m, x.lam32.f() + (int64_t)(k - 1) * x.m, sizeof(float) * x.m, hipMemcpyDeviceToHost));
     });
@@ -596,7 +614,8 @@ rkmips_status rkmips_get_item_order(const rkmips_index* idx, int64_t* order, dou
 {
     return guarded([&] {
         if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
-        const Index& x = *(const Index*)idx;
+        Index& x = *(Index*)idx;
+        x.wait_ready();
         if (order) {
             std::vector<uint32_t> o(x.n);
             HIPC(hipMemcpy(o.data(), x.item_order.p, sizeof(uint32_t) * x.n, hipMemcpyDeviceToHost));
@@ -610,7 +629,8 @@ rkmips_status rkmips_get_candidates(const rkmips_index* idx, int32_t* ids, float
 {
     return guarded([&] {
         if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
-        const Index& x = *(const Index*)idx;
+        Index& x = *(Index*)idx;
+        x.wait_ready();
         if (!x.cand.p) fail(RKMIPS_EINVAL, "candidates are not kept by this index");
         const int64_t per = (int64_t)x.nseg * x.G;
         std::vector<uint2> buf((size_t)x.m * per);

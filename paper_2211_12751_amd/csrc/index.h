@@ -115,8 +115,16 @@ struct Index {
 
     double ms_norms = 0, ms_lambda = 0, ms_refine = 0, ms_saalsh = 0, ms_cone = 0, ms_total = 0;
     double ms_seed = 0, ms_topk = 0;
-    PinBuf h_lam_stats;               // lambda build statistics, read after the final wait
+    PinBuf h_lam_stats;               // lambda build statistics, read once the build is complete
     std::vector<hipEvent_t> lam_ev;   // seed / top-k / refine boundaries of the build
+    std::vector<hipEvent_t> build_ev; // phase boundaries of the build
+    // The build returns once its work is queued: ready_ev follows its last kernel on the
+    // build stream.  Host reads of index data wait for it (wait_ready, which also takes the
+    // build statistics); work on another stream waits for it on the device (ready_on).
+    hipEvent_t ready_ev = nullptr;
+    std::once_flag stats_once;
+    void wait_ready();
+    void ready_on(hipStream_t s) const;
 
     int64_t device_bytes() const
     {

@@ -385,6 +385,7 @@ rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const f
         try {
             w->ensure(x, nq, std::max<int64_t>(1 << 16, 8 * nq * std::max(1, x.prm.k_max)), std::max<int64_t>(1 << 14, 4 * nq));
             plan_batch(x, *w, ks, nq);
+            x.ready_on(r->s);   // a batch on another stream waits for the build on the device
             HIPC(hipEventRecord(w->ev0, r->s));
             enqueue_batch(x, *w, queries, query_scales, nq, flags | x.prm.flags, r->s);
         } catch (...) {
@@ -449,6 +450,7 @@ rkmips_status rkmips_saalsh_probe(rkmips_index* idx, const void* queries, const 
     return qguard([&] {
         if (!idx) fail(RKMIPS_EINVAL, "index is NULL");
         Index& x = *(Index*)idx;
+        x.wait_ready();
         if (nq < 1 || !queries || !ks) fail(RKMIPS_EINVAL, "queries/ks missing");
         if (npairs < 0 || (npairs > 0 && (!pair_query || !pair_user || !phi_out || !answer_out)))
             fail(RKMIPS_EINVAL, "pair arrays missing");
@@ -496,7 +498,8 @@ rkmips_status rkmips_get_saalsh(const rkmips_index* idx, int64_t* part_start, fl
 {
     return qguard([&] {
         if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
-        const Index& x = *(const Index*)idx;
+        Index& x = *(Index*)idx;
+        x.wait_ready();
         const int W = x.prm.num_hash / 32;
         if (part_start) HIPC(hipMemcpy(part_start, x.part_start.p, sizeof(int64_t) * (x.t + 1), hipMemcpyDeviceToHost));
         if (centroid) {
@@ -526,7 +529,8 @@ rkmips_status rkmips_get_blocks(const rkmips_index* idx, int32_t* leaf_users, in
 {
     return qguard([&] {
         if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
-        const Index& x = *(const Index*)idx;
+        Index& x = *(Index*)idx;
+        x.wait_ready();
         if (leaf_users) {
             std::vector<uint32_t> o(x.m);
             HIPC(hipMemcpy(o.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));

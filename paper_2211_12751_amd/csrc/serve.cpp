@@ -227,6 +227,7 @@ extern "C" rkmips_status rkmips_serve_replay(rkmips_index* idx, const void* quer
             *out = nullptr;
             if (!idx || !sp || !lat) fail(RKMIPS_EINVAL, "NULL argument");
             Index& x = *(Index*)idx;
+            x.wait_ready();
             if (nq < 0) fail(RKMIPS_EINVAL, "nq < 0");
             if (nq > 0 && (!queries || !ks || !arr)) fail(RKMIPS_EINVAL, "queries/ks/arrival_us is NULL");
             const bool fp8 = x.dtype == RKMIPS_FP8_E4M3;
