@@ -164,8 +164,8 @@ static hipStream_t aux_stream(int dev)
 
 // Operand form of the top-k passes: FP32 data as BF16 pairs [hi | lo] (three products
 // per k-step on the matrix cores), otherwise the index's matrix-core form.
-static int topk_dtype(const Index& x) { return x.dtype == DT_F32 && x.mma_dtype == DT_BF16 ? DT_SPLIT : x.mma_dtype; }
-static int topk_ld(const Index& x) { return topk_dtype(x) == DT_SPLIT ? 2 * x.ld : x.mma_ld; }
+static int topk_dtype(const Index& x) { return x.mma_dtype; }
+static int topk_ld(const Index& x) { return x.mma_ld; }
 
 static void choose_topk(Index& x)
 {
@@ -554,8 +554,8 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
         // not within an FP32 rounding model (measured error up to 2^-10.6 of the sum of
         // |terms| per instruction), so no a-priori bound would hold for them.
         const bool split = dtype == RKMIPS_F32 && x->ld <= 64 && !(prm.flags & RKMIPS_FLAG_F32_MATRIX);
-        x->mma_dtype = split ? RKMIPS_BF16 : (dtype == RKMIPS_FP8_E4M3 ? DT_FP8B : dtype);
-        x->mma_ld = split ? 3 * x->ld : x->ld;
+        x->mma_dtype = split ? DT_SPLIT : (dtype == RKMIPS_FP8_E4M3 ? DT_FP8B : dtype);
+        x->mma_ld = split ? 2 * x->ld : x->ld;
         x->err_fast = split ? split_err_rel(d) : fast_err_rel(d);
         HIPC(hipGetDevice(&x->device));
         x->num_cus = device_cus(x->device);
@@ -581,8 +581,8 @@ rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
         o->ms_norms = x.ms_norms; o->ms_lambda = x.ms_lambda; o->ms_refine = x.ms_refine;
         o->ms_saalsh = x.ms_saalsh; o->ms_cone = x.ms_cone; o->ms_total = x.ms_total;
         o->ms_seed = x.ms_seed; o->ms_topk = x.ms_topk;
-        o->mma_dtype = x.mma_dtype == DT_FP8B ? RKMIPS_BF16 : x.mma_dtype;
-        o->mma_terms = x.mma_ld / x.ld;
+        o->mma_dtype = (x.mma_dtype == DT_FP8B || x.mma_dtype == DT_SPLIT) ? RKMIPS_BF16 : x.mma_dtype;
+        o->mma_terms = x.mma_dtype == DT_SPLIT ? 3 : 1;
         o->err_fast = x.err_fast;
         o->device_bytes = x.device_bytes();
     });

@@ -152,7 +152,9 @@ void launch_mma_operand(int mma_dtype, int dtype, const void* src, int64_t rows,
                         int user_layout, hipStream_t s)
 {
     if (rows <= 0) return;
-    if (dtype == DT_F32 && mma_dtype == DT_BF16) {
+    if (dtype == DT_F32 && mma_dtype == DT_SPLIT) {
+        launch_split_bf16((const float*)src, rows, ld, dst, 2, s);
+    } else if (dtype == DT_F32 && mma_dtype == DT_BF16) {
         launch_split_bf16((const float*)src, rows, ld, dst, user_layout, s);
     } else if (dtype == DT_FP8 && mma_dtype == DT_FP8B) {
         const int64_t cnt = rows * ld;

@@ -51,6 +51,18 @@ __device__ __forceinline__ f32x16 verify_block(const uint8_t* qt, const i32x4 (&
         } else if constexpr (dt_bf16_mma<DT>) {
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af),
                                                          __builtin_bit_cast(bf16x8, bfrag[t]), acc, 0, 0, 0);
+        } else if constexpr (DT == DT_SPLIT) {
+            // pair rows [hi | lo]: k-step t of the hi half meets step t + KSTEPS / 2 of the
+            // lo half (same elements); q_h.u_h + q_l.u_h + q_h.u_l
+            constexpr int HK = KSTEPS / 2;
+            if (t < HK) {
+                const i32x4 al = *(const i32x4*)(arow + (t + HK) * 32);
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, af), alo = __builtin_bit_cast(bf16x8, al);
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, bfrag[t]), bl = __builtin_bit_cast(bf16x8, bfrag[t + HK]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+            }
         } else {
             static_assert(dt_bf16_mma<DT>, "FP8 codes reach the matrix cores widened to BF16");
         }
@@ -72,10 +84,12 @@ __device__ __forceinline__ void decide(float x, float lam, float uq, bool force,
 }
 
 // Waves per SIMD the register budget is cut for: three, except for long fragments
-// (FP32 rows of 256, split BF16 rows of 192, scaled rows of 256 bytes) that would spill.
+// (FP32 rows of 256, scaled rows of 256 bytes) that would spill, and four for the pair
+// rows of split FP32 data.
 template <int DT, int DPT>
 constexpr int verify_wpe()
 {
+    if (DT == DT_SPLIT) return 4;   // pair rows: eight resident fragments
     return (DT == DT_F32 && DPT >= 256) ? 1
                                           : ((DPT * Elt<DT>::bytes >= 384 || (dt_scaled<DT> && DPT * Elt<DT>::bytes >= 256)) ? 2 : 3);
 }
@@ -496,16 +510,18 @@ static void verify_g(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
 template <int DT>
 static void verify_d(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
 {
-    if constexpr (DT == DT_BF16) {   // split BF16 rows of FP32 data
-        if (a.mma_ld == 96) return verify_g<DT, 96>(a, q0, q1, s);
-        if (a.mma_ld == 192) return verify_g<DT, 192>(a, q0, q1, s);
-    }
-    switch (a.mma_ld) {
-    case 32: verify_g<DT, 32>(a, q0, q1, s); break;
-    case 64: verify_g<DT, 64>(a, q0, q1, s); break;
-    case 128: verify_g<DT, 128>(a, q0, q1, s); break;
-    case 256: verify_g<DT, 256>(a, q0, q1, s); break;
-    default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
+    if constexpr (DT == DT_SPLIT) {   // pair rows of FP32 data: 2 x 32, 2 x 64
+        if (a.mma_ld == 64) verify_g<DT, 64>(a, q0, q1, s);
+        else if (a.mma_ld == 128) verify_g<DT, 128>(a, q0, q1, s);
+        else fail(RKMIPS_EINVAL, "internal: unsupported split row length");
+    } else {
+        switch (a.mma_ld) {
+        case 32: verify_g<DT, 32>(a, q0, q1, s); break;
+        case 64: verify_g<DT, 64>(a, q0, q1, s); break;
+        case 128: verify_g<DT, 128>(a, q0, q1, s); break;
+        case 256: verify_g<DT, 256>(a, q0, q1, s); break;
+        default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
+        }
     }
 }
 
@@ -516,6 +532,7 @@ void launch_verify_range(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t
     if (a.mma_dtype == DT_F32) verify_d<DT_F32>(a, q0, q1, s);
     else if (a.mma_dtype == DT_BF16) verify_d<DT_BF16>(a, q0, q1, s);
     else if (a.mma_dtype == DT_FP8B) verify_d<DT_FP8B>(a, q0, q1, s);
+    else if (a.mma_dtype == DT_SPLIT) verify_d<DT_SPLIT>(a, q0, q1, s);
     else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());
 }
