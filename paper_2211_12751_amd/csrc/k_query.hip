@@ -430,43 +430,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
 
 // cos(phi) of every (block, query) pair: the FP32 inner product of the query with the
 // block's unit centre over the query norm, clamped to [-1, 1] (0 for a zero query).  One
-// thread per pair, 16-byte loads; the result feeds the node-level bound of Lemma 2.
+// thread per query and eight consecutive blocks: the query row is read once, in pieces
+// of up to 64 values held in registers, against each block's centre (a wave-uniform
+// row).  The result feeds the node-level bound of Lemma 2.
+// FP8 codes keep one block per thread: their decoded values would otherwise stay live
+// across the blocks and spill.
+template <int DT> constexpr int phi_nb() { return DT == DT_FP8 ? 1 : 8; }
+
 template <int DT, int DPT>
 __global__ __launch_bounds__(256) void k_phi(QueryArgs a, float* cphi, int64_t b0)
 {
     constexpr int EB = Elt<DT>::bytes;
     constexpr int PER = 16 / EB;
+    constexpr int ROWB = DPT * EB;
+    constexpr int CB = ROWB < 64 * EB ? ROWB : 64 * EB;   // query row bytes in registers at once (64 values)
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t b = b0 + blockIdx.y;
+    constexpr int PHI_NB = phi_nb<DT>();
+    const int64_t bb = b0 + (int64_t)blockIdx.y * PHI_NB;
+    const int nbh = (int)(a.nblocks - bb < PHI_NB ? a.nblocks - bb : PHI_NB);
     if (q >= a.nq) return;
-    const uint8_t* qr = (const uint8_t*)a.queries + q * (int64_t)DPT * EB;
-    const float* cr = a.center + b * (int64_t)DPT;
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-    for (int c0 = 0; c0 < DPT; c0 += PER) {
-        const i32x4 qv = *(const i32x4*)(qr + c0 * EB);
+    const uint8_t* qr = (const uint8_t*)a.queries + q * (int64_t)ROWB;
+    float acc[PHI_NB][4];
 #pragma unroll
-        for (int e = 0; e < PER; e++) {
-            float x;
-            if constexpr (DT == DT_F32) x = __int_as_float(qv[e]);
-            else if constexpr (DT == DT_BF16) x = bf16_to_f32((uint16_t)((uint32_t)qv[e >> 1] >> (16 * (e & 1))));
-            else x = e4m3_to_f32((uint8_t)((uint32_t)qv[e >> 2] >> (8 * (e & 3))));
-            acc[e & 3] = fmaf(x, cr[c0 + e], acc[e & 3]);
+    for (int j = 0; j < PHI_NB; j++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc[j][e] = 0.f;
+    for (int cb0 = 0; cb0 < ROWB; cb0 += CB) {
+        i32x4 qv[CB / 16];
+#pragma unroll
+        for (int i = 0; i < CB / 16; i++) qv[i] = *(const i32x4*)(qr + cb0 + 16 * i);
+#pragma unroll
+        for (int j = 0; j < PHI_NB; j++) {
+            if (j >= nbh) break;   // wave-uniform
+            const float* cr = a.center + (bb + j) * (int64_t)DPT + cb0 / EB;
+#pragma unroll
+            for (int i = 0; i < CB / 16; i++) {
+#pragma unroll
+                for (int e = 0; e < PER; e++) {
+                    float x;
+                    if constexpr (DT == DT_F32) x = __int_as_float(qv[i][e]);
+                    else if constexpr (DT == DT_BF16) x = bf16_to_f32((uint16_t)((uint32_t)qv[i][e >> 1] >> (16 * (e & 1))));
+                    else x = e4m3_to_f32((uint8_t)((uint32_t)qv[i][e >> 2] >> (8 * (e & 3))));
+                    acc[j][e & 3] = fmaf(x, cr[i * PER + e], acc[j][e & 3]);
+                }
+            }
         }
     }
-    float dot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    if constexpr (DT == DT_FP8) dot *= a.query_scales[q];
     const float qn = a.qnorm[q];
-    float c = qn > 0.f ? dot / qn : 0.f;
-    c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
-    cphi[b * a.nq + q] = c;
+    const float qsc = DT == DT_FP8 ? a.query_scales[q] : 1.f;
+#pragma unroll
+    for (int j = 0; j < PHI_NB; j++) {
+        if (j >= nbh) break;
+        float dot = (acc[j][0] + acc[j][1]) + (acc[j][2] + acc[j][3]);
+        if constexpr (DT == DT_FP8) dot *= qsc;
+        float c = qn > 0.f ? dot / qn : 0.f;
+        c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
+        cphi[(bb + j) * a.nq + q] = c;
+    }
 }
 
 template <int DT>
 static void phi_d(const QueryArgs& a, float* cphi, hipStream_t s)
 {
-    for (int64_t b0 = 0; b0 < a.nblocks; b0 += 65535) {
-        dim3 g((unsigned)((a.nq + 255) / 256), (unsigned)std::min<int64_t>(65535, a.nblocks - b0));
+    constexpr int NB = phi_nb<DT>();
+    const int64_t per_launch = (int64_t)65535 * NB;
+    for (int64_t b0 = 0; b0 < a.nblocks; b0 += per_launch) {
+        const int64_t nbl = std::min<int64_t>(per_launch, a.nblocks - b0);
+        dim3 g((unsigned)((a.nq + 255) / 256), (unsigned)((nbl + NB - 1) / NB));
         switch (a.ld) {
         case 32: hipLaunchKernelGGL((k_phi<DT, 32>), g, dim3(256), 0, s, a, cphi, b0); break;
         case 64: hipLaunchKernelGGL((k_phi<DT, 64>), g, dim3(256), 0, s, a, cphi, b0); break;
