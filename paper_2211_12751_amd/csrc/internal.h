@@ -169,6 +169,9 @@ struct QueryArgs {
     float err_phi;                                   // error bound of the FP32 cos(phi)
     float bound_slack;                               // relative slack of the bounds
     unsigned long long* pool; unsigned long long* pool_count; int64_t pool_cap;
+    // yes answers as bits [nq x bm_words] by caller query and original user, in place of
+    // the pool (null: the pool)
+    uint32_t* bitmap; int64_t bm_words;
     unsigned long long* amb; unsigned long long* amb_count; int64_t amb_cap;
     unsigned long long* stats;                       // [8]
 };
@@ -177,6 +180,10 @@ void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, 
 void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s);
 void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
 void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s);
+// Per-query ascending lists from the answer bits: counts, offsets (as launch_result_lists),
+// then the ids (those past ids_cap are dropped: the caller checks offsets[nq]).
+void launch_bitmap_lists(const uint32_t* bitmap, int64_t words, int64_t nq, int* cnt, int64_t* offsets,
+                         long long* stat, int32_t* ids, int64_t ids_cap, hipStream_t s);
 // the same with the close-call count kept on the device (pool tail cleared, span in ctr[5])
 void launch_recheck_device(const QueryArgs& a, hipStream_t s);
 // span_dev null: the pool span is `span`; otherwise it is read on the device and `span`

@@ -347,6 +347,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
             }
         }
 
+        if (a.bitmap) {   // yes answers as bits (workgroup-uniform); the pool takes close calls only
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                if (yes & (1u << r)) {
+                    const int64_t q = qb + mfma32_row(r, l);
+                    atomicOr(&a.bitmap[(int64_t)a.qorig[q] * a.bm_words + (ouid[0] >> 5)], 1u << (ouid[0] & 31u));
+                }
+            yes = 0u;
+        }
         // ---- appends: wave prefix sums, one LDS reservation per wave, one global
         // reservation per workgroup and tile
         const int ny = __popc(yes), na = __popc(amb);
@@ -599,8 +608,13 @@ __global__ void k_recheck(QueryArgs a, int64_t namb, const unsigned long long* n
         const float sq = DT == DT_FP8 ? a.query_scales[q] : 1.f;
         const double s = canon_dot2<DT>(a.users, u, a.ld, su, a.queries, q, a.ld, sq, a.d);
         if (s >= a.lam64[(int64_t)(k - 1) * a.m + a.perm[u]]) {
-            const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
-            if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)a.qorig[q] << 32) | a.perm[u];
+            const uint32_t ou = a.perm[u];
+            if (a.bitmap) {
+                atomicOr(&a.bitmap[(int64_t)a.qorig[q] * a.bm_words + (ou >> 5)], 1u << (ou & 31u));
+            } else {
+                const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
+                if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)a.qorig[q] << 32) | ou;
+            }
         }
     }
 }
@@ -631,7 +645,7 @@ __global__ void k_close_init(unsigned long long* ctr, unsigned long long* pool, 
 void launch_recheck_device(const QueryArgs& a, hipStream_t s)
 {
     unsigned long long* ctr = a.pool_count;   // ctr[0] = pool count, ctr[1] = close calls
-    hipLaunchKernelGGL(k_close_init, dim3(64), dim3(256), 0, s, ctr, a.pool, a.pool_cap, a.amb_cap);
+    if (!a.bitmap) hipLaunchKernelGGL(k_close_init, dim3(64), dim3(256), 0, s, ctr, a.pool, a.pool_cap, a.amb_cap);
     const unsigned g = (unsigned)std::min<int64_t>((a.amb_cap + 255) / 256, 256);
     if (a.dtype == DT_F32) hipLaunchKernelGGL(k_recheck<DT_F32>, dim3(g), dim3(256), 0, s, a, (int64_t)0, ctr + 1, nullptr);
     else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_recheck<DT_BF16>, dim3(g), dim3(256), 0, s, a, (int64_t)0, ctr + 1, nullptr);
@@ -840,6 +854,55 @@ __global__ __launch_bounds__(256) void k_qcopy_long(const int64_t* offsets, cons
     const int64_t b = offsets[q], c = offsets[q + 1] - b;
     if (c <= QS_CHUNK) return;
     for (int64_t i = threadIdx.x; i < c; i += 256) dst[b + i] = src[b + i];
+}
+
+// ---- lists from answer bits: one wave per query, words in order, so the ids come out
+// ascending without a sort
+__global__ __launch_bounds__(256) void k_bm_count(const uint32_t* bm, int64_t words, int64_t nq, int* cnt)
+{
+    const int l = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nq) return;
+    const uint32_t* row = bm + q * words;
+    int c = 0;
+    for (int64_t i = l; i < words; i += 64) c += __popc(row[i]);
+    c = wave_sum(c);
+    if (l == 0) cnt[q] = c;
+}
+
+__global__ __launch_bounds__(256) void k_bm_emit(const uint32_t* bm, int64_t words, int64_t nq, const int64_t* offsets,
+                                                 int32_t* ids, int64_t ids_cap)
+{
+    const int l = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nq) return;
+    const uint32_t* row = bm + q * words;
+    int64_t base = offsets[q];
+    for (int64_t i0 = 0; i0 < words; i0 += 64) {
+        const int64_t i = i0 + l;
+        uint32_t wd = i < words ? row[i] : 0u;
+        const int pc = __popc(wd);
+        const int incl = wave_incl_scan(pc);
+        int64_t pos = base + incl - pc;
+        while (wd) {
+            const int bit = __builtin_ctz(wd);
+            wd &= wd - 1u;
+            if (pos < ids_cap) ids[pos] = (int32_t)(i * 32 + bit);
+            pos++;
+        }
+        base += __shfl(incl, 63);
+    }
+}
+
+void launch_bitmap_lists(const uint32_t* bitmap, int64_t words, int64_t nq, int* cnt, int64_t* offsets,
+                         long long* stat, int32_t* ids, int64_t ids_cap, hipStream_t s)
+{
+    if (nq <= 0) return;
+    const unsigned g = (unsigned)((nq + 3) / 4);
+    hipLaunchKernelGGL(k_bm_count, dim3(g), dim3(256), 0, s, bitmap, words, nq, cnt);
+    hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, s, cnt, nq, offsets, stat);
+    hipLaunchKernelGGL(k_bm_emit, dim3(g), dim3(256), 0, s, bitmap, words, nq, (const int64_t*)offsets, ids, ids_cap);
+    HIPC(hipGetLastError());
 }
 
 void launch_result_lists(const uint64_t* keys, int64_t span, const unsigned long long* span_dev, int64_t nq, int* cnt,

@@ -18,6 +18,9 @@
 namespace rk {
 
 static const int kMaxSlots = 8;
+// largest answer-bit array of one workspace (nq x ceil(m / 32) words); larger batches
+// collect their answers in the pool and sort the lists
+static const int64_t kBitmapBytes = (int64_t)64 << 20;
 
 PinBuf::~PinBuf() { reset(); }
 void PinBuf::reset()
@@ -54,7 +57,8 @@ int64_t Workspace::bytes_for(const Index& x, int64_t nq, int64_t pool_cap, int64
 {
     const int64_t eb = elt_bytes(x.dtype);
     return nq * x.ld * eb + nq * 5 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4 + 4) + amb_cap * 8 + 256 +
-           nq * x.nblocks * 4 + (x.mma_dtype != x.dtype ? nq * x.mma_ld * 2 : 0);
+           nq * x.nblocks * 4 + (x.mma_dtype != x.dtype ? nq * x.mma_ld * 2 : 0) +
+           (nq * ((x.m + 31) / 32) * 4 <= kBitmapBytes ? nq * ((x.m + 31) / 32) * 4 : 0);
 }
 
 void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t amb_cap_req)
@@ -76,6 +80,9 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
         qcnt.alloc(sizeof(int) * c);
         h_offsets.alloc(sizeof(int64_t) * (c + 1));
         cphi.alloc(sizeof(float) * (size_t)c * std::max<int64_t>(x.nblocks, 1));
+        bm_words = (x.m + 31) / 32;
+        if (c * bm_words * 4 <= kBitmapBytes) bitmap.alloc(sizeof(uint32_t) * (size_t)(c * bm_words));
+        else bitmap.reset();
         nq_cap = c;
     }
     const int64_t pc = pow2ceil64(std::max<int64_t>(pool_cap_req, 1 << 12));
@@ -153,6 +160,8 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.bound_slack = kBoundSlack;
     unsigned long long* c = (unsigned long long*)w.ctr.p;
     a.pool = (unsigned long long*)w.pool.p; a.pool_count = c + 0; a.pool_cap = w.pool_cap;
+    a.bitmap = w.bm_mode ? w.bitmap.u32() : nullptr;
+    a.bm_words = w.bm_words;
     a.amb = (unsigned long long*)w.amb.p; a.amb_count = c + 1; a.amb_cap = w.amb_cap;
     a.bad = (int*)(c + 2);
     a.stats = c + 8;
@@ -168,6 +177,8 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
     HIPC(hipMemsetAsync(w.ctr.p, 0, sizeof(unsigned long long) * 16, s));
     const int fl = flags | x.prm.flags;
     w.device_tail = nq > 0 && !((fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH));
+    w.bm_mode = w.device_tail && w.bitmap.p != nullptr;
+    if (w.bm_mode) HIPC(hipMemsetAsync(w.bitmap.p, 0, sizeof(uint32_t) * (size_t)(nq * w.bm_words), s));
     if (nq > 0) {
         HIPC(hipMemcpyAsync(w.meta.p, w.h_meta.p, sizeof(int) * w.meta_ints, hipMemcpyHostToDevice, s));
         launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig, nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
@@ -186,8 +197,12 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
             // host checks them (bad values, overflow) once the offsets are back
             unsigned long long* c = (unsigned long long*)w.ctr.p;
             launch_recheck_device(a, s);
-            launch_result_lists((const uint64_t*)w.pool.p, w.pool_cap, c + 5, nq, w.qcnt.i(), w.offsets.i64(),
-                                (long long*)(c + 13), (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);
+            if (w.bm_mode)
+                launch_bitmap_lists(w.bitmap.u32(), w.bm_words, nq, w.qcnt.i(), w.offsets.i64(), (long long*)(c + 13),
+                                    (int32_t*)w.ids.p, w.pool_cap, s);
+            else
+                launch_result_lists((const uint64_t*)w.pool.p, w.pool_cap, c + 5, nq, w.qcnt.i(), w.offsets.i64(),
+                                    (long long*)(c + 13), (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);
             HIPC(hipMemcpyAsync(w.h_offsets.p, w.offsets.p, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s));
         }
     }
@@ -282,14 +297,17 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     if (hc[2] & 1ull) fail(RKMIPS_EINVAL, "non-finite value (or NaN code / non-finite scale) in the queries");
     if (hc[2] & 2ull) fail(RKMIPS_ERANGE, "a query norm is outside [1e-30, 1e30]");
     int64_t cnt = (int64_t)hc[0], namb = (int64_t)hc[1];
-    if (cnt + namb > w.pool_cap || namb > w.amb_cap) {
+    // with answer bits the pool only holds the lists (offsets[nq] ids), else the yes
+    // answers and the rechecked close calls
+    auto need = [&] { return w.bm_mode ? ((const int64_t*)w.h_offsets.p)[nq] : cnt + namb; };
+    if (need() > w.pool_cap || namb > w.amb_cap) {
         // the result pool was too small: grow it and run the batch again
-        w.ensure(x, nq, 2 * (cnt + namb) + 1, 2 * namb + 1);
+        w.ensure(x, nq, 2 * need() + 1, 2 * namb + 1);
         enqueue_batch(x, w, queries, qscales, nq, flags, s);
         host_wait(w.ev_ctr);
         cnt = (int64_t)hc[0];
         namb = (int64_t)hc[1];
-        if (cnt + namb > w.pool_cap || namb > w.amb_cap) fail(RKMIPS_ENOMEM, "result pool overflow");
+        if (need() > w.pool_cap || namb > w.amb_cap) fail(RKMIPS_ENOMEM, "result pool overflow");
     }
     st = rkmips_query_stats{};
     st.pairs_total = nq * x.m;
@@ -321,7 +339,7 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     if (nq == 0) ((int64_t*)w.h_offsets.p)[0] = 0;
     const int64_t* ho = (const int64_t*)w.h_offsets.p;
     const int64_t total = ho[nq];
-    if (nq > 0) {
+    if (nq > 0 && !w.bm_mode) {
         // lists longer than one LDS chunk are merged now that their length is known
         const long long mc = (long long)((const unsigned long long*)w.h_ctr.p)[13];
         launch_result_merges(nq, mc, w.offsets.i64(), (int32_t*)w.ids2.p, (int32_t*)w.ids.p, s);

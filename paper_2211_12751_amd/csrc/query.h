@@ -29,6 +29,11 @@ struct Workspace {
     uint32_t* qorig = nullptr; int* qslot = nullptr; int* qk = nullptr; int* slotk = nullptr;   // in meta
     int64_t meta_ints = 0;                  // ints of meta this batch uses
     bool device_tail = false;               // recheck and lists were enqueued with the batch
+    // answer bits [nq_cap x bm_words] (one bit per caller query and original user) when
+    // they fit the budget: the lists then come out sorted without a pool or a sort
+    DevBuf bitmap;
+    int64_t bm_words = 0;
+    bool bm_mode = false;                   // this batch uses the bits
     DevBuf cphi;                            // [nblocks x nq] query-centre cosines
     DevBuf qsplit;                          // matrix-core query rows (split FP32 or widened FP8)
     DevBuf qcnt, ids2;                      // per-query counts, scatter target of the lists
