@@ -71,11 +71,14 @@ enum {
                                        skip the recheck.  Off by default: Alg. 2 scores
                                        ceil(beta |S_j|) candidates per pair, far more work
                                        than the O(d) FP64 recheck it can save.           */
-    RKMIPS_FLAG_F32_MATRIX = 64     /* build: score FP32 data on the FP32 matrix cores.
+    RKMIPS_FLAG_F32_MATRIX = 64,    /* build: score FP32 data on the FP32 matrix cores.
                                        By default FP32 rows with d <= 64 are scored as
                                        split BF16 products (h.h + l.h + h.l, h and l the
                                        BF16 head and tail of each value) with their own
                                        error bound; either way the exact path decides.   */
+    RKMIPS_FLAG_POOL_LISTS = 128    /* collect the answers in the result pool and sort
+                                       the lists even when a batch's answer bits (one per
+                                       query and user) fit the 64 MiB budget             */
 };
 
 typedef struct {

@@ -128,8 +128,6 @@ static void validate_params(const rkmips_params& p)
     if (p.mode != 0) fail(RKMIPS_EINVAL, "mode must be 0 (exact)");
 }
 
-// Candidate buffer geometry of the lambda pass: a seeding segment (the P largest- and P
-// smallest-norm items, processed first) and the main segments over the remaining items.
 // Compute-unit count of a device (cached: the attribute query is not free).
 static int device_cus(int dev)
 {

@@ -177,7 +177,7 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
     HIPC(hipMemsetAsync(w.ctr.p, 0, sizeof(unsigned long long) * 16, s));
     const int fl = flags | x.prm.flags;
     w.device_tail = nq > 0 && !((fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH));
-    w.bm_mode = w.device_tail && w.bitmap.p != nullptr;
+    w.bm_mode = w.device_tail && w.bitmap.p != nullptr && !(fl & RKMIPS_FLAG_POOL_LISTS);
     if (w.bm_mode) HIPC(hipMemsetAsync(w.bitmap.p, 0, sizeof(uint32_t) * (size_t)(nq * w.bm_words), s));
     if (nq > 0) {
         HIPC(hipMemcpyAsync(w.meta.p, w.h_meta.p, sizeof(int) * w.meta_ints, hipMemcpyHostToDevice, s));

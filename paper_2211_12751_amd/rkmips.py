@@ -24,6 +24,7 @@ DTYPES = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
 FLAG_NO_BOUNDS, FLAG_FORCE_RECHECK, FLAG_NO_SAALSH, FLAG_NO_CERT, FLAG_NO_VECTOR_BOUND = 1, 2, 4, 8, 16
 FLAG_SAALSH_FILTER = 32
 FLAG_F32_MATRIX = 64
+FLAG_POOL_LISTS = 128
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "EBUSY"}
 
 

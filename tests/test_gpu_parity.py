@@ -75,7 +75,8 @@ def test_toggles_give_identical_sets(R):
     idx = _build(R, w, k_max)
     try:
         for fl in (0, R.FLAG_NO_BOUNDS, R.FLAG_FORCE_RECHECK, R.FLAG_NO_VECTOR_BOUND, R.FLAG_SAALSH_FILTER,
-                   R.FLAG_SAALSH_FILTER | R.FLAG_FORCE_RECHECK):
+                   R.FLAG_SAALSH_FILTER | R.FLAG_FORCE_RECHECK, R.FLAG_POOL_LISTS,
+                   R.FLAG_POOL_LISTS | R.FLAG_FORCE_RECHECK):
             print("flags", fl, flush=True)
             _lists_equal(idx.query(w.queries, None, ks, flags=fl), ref)
     finally:
