@@ -174,7 +174,7 @@ typedef struct {
     int32_t num_partitions;      /* t of Alg. 1                                          */
     int64_t num_blocks;          /* Cone-Tree leaves                                     */
     int64_t cert_failures;       /* users whose lambda row needed the full FP64 rescoring */
-    double max_rel_err_raw;      /* max |lambda32_raw - lambda64| / |lambda64| before refining */
+    double max_rel_err_raw;      /* max |s_fast - s64| / |s64| over the rescored candidates   */
     double max_rel_err_lambda32; /* max |lambda32 - lambda64| / |lambda64| after           */
     double ms_norms, ms_lambda, ms_refine, ms_saalsh, ms_cone, ms_total; /* device times   */
     int64_t device_bytes;        /* device memory held by the index                      */

@@ -216,7 +216,7 @@ static void choose_topk(Index& x)
 // candidates are indexed by original user.  Two stream-ordered halves without host
 // synchronisation: the fused top-k passes, then the FP64 refine with the certificate.
 struct LambdaBuild {
-    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill, items3, users3;
+    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill, items3, users3, sel, sel_meta;
     Events ev{4};   // start, after the main pass, after the refine, after the seed pass
 };
 
@@ -230,10 +230,10 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
     L.tau.alloc(sizeof(float) * (size_t)m * x.nseg);
     L.fail_list.alloc(sizeof(int) * (size_t)m);
     L.fail_count.alloc(2 * sizeof(int));   // [0] certificate failures, [1] refine spills
-    L.errbits.alloc(2 * sizeof(unsigned long long));
+    L.errbits.alloc(2 * kErrSlots * sizeof(unsigned long long));
     L.spill.alloc(sizeof(int) * (size_t)m);
     HIPC(hipMemsetAsync(L.fail_count.p, 0, 2 * sizeof(int), s));
-    HIPC(hipMemsetAsync(L.errbits.p, 0, 2 * sizeof(unsigned long long), s));
+    HIPC(hipMemsetAsync(L.errbits.p, 0, 2 * kErrSlots * sizeof(unsigned long long), s));
     x.lam64.alloc(sizeof(double) * (size_t)x.prm.k_max * m);
     x.lam32.alloc(sizeof(float) * (size_t)x.prm.k_max * m);
 
@@ -293,6 +293,12 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
     ra.err_rel = x.err_fast;
     ra.spill = L.spill.i();
     ra.spill_count = L.fail_count.i() + 1;
+    if (x.C <= 64) {   // the narrow pass in two kernels
+        L.sel.alloc(sizeof(uint2) * (size_t)m * x.C);
+        L.sel_meta.alloc(sizeof(int) * 4 * (size_t)m);
+        ra.sel = (uint2*)L.sel.p;
+        ra.sel_meta = L.sel_meta.i();
+    }
     launch_refine(x.dtype, ra, s);
     {
         // rows whose certificate failed: full FP64 rescoring (the count stays on the
@@ -304,10 +310,10 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
     }
     HIPC(hipEventRecord(L.ev.ev[2], s));
     // build statistics, read by the host after the build's final wait
-    x.h_lam_stats.alloc(sizeof(unsigned long long) * 4);
+    x.h_lam_stats.alloc(sizeof(unsigned long long) * (2 * kErrSlots + 1));
     unsigned long long* hs = (unsigned long long*)x.h_lam_stats.p;
-    HIPC(hipMemcpyAsync(hs, L.errbits.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(hs + 2, L.fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hs, L.errbits.p, 2 * kErrSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hs + 2 * kErrSlots, L.fail_count.p, sizeof(int), hipMemcpyDeviceToHost, s));
     x.lam_ev.assign(4, nullptr);
     for (int i = 0; i < 4; i++) std::swap(x.lam_ev[i], L.ev.ev[i]);
     // keep the raw candidates for inspection (per original user)
@@ -419,9 +425,14 @@ static void take_build_stats(Index& x)
     const std::vector<hipEvent_t>& ev = x.build_ev;
     x.ms_saalsh = ev_ms(ev[4], ev[5]);
     const unsigned long long* hs = (const unsigned long long*)x.h_lam_stats.p;
-    std::memcpy(&x.max_rel_err_raw, &hs[0], 8);
-    std::memcpy(&x.max_rel_err_l32, &hs[1], 8);
-    x.cert_failures = (int64_t)*(const int*)(hs + 2);
+    unsigned long long raw = 0, l32 = 0;   // non-negative doubles order like their bits
+    for (int i = 0; i < kErrSlots; i++) {
+        raw = std::max(raw, hs[i]);
+        l32 = std::max(l32, hs[kErrSlots + i]);
+    }
+    std::memcpy(&x.max_rel_err_raw, &raw, 8);
+    std::memcpy(&x.max_rel_err_l32, &l32, 8);
+    x.cert_failures = (int64_t)*(const int*)(hs + 2 * kErrSlots);
     const std::vector<hipEvent_t>& le = x.lam_ev;
     x.ms_seed = ev_ms(le[0], le[3]);
     x.ms_topk = ev_ms(le[3], le[1]);

@@ -58,6 +58,8 @@ void launch_permute_f64(const double* src, const uint32_t* perm, int64_t n, doub
 
 // ---------------------------------------------------------------- lambda build
 // (the fused top-k pass: topk.h)
+constexpr int kErrSlots = 64;
+
 struct RefineArgs {
     const void* items; const float* item_scales; int64_t n;
     const void* users; const float* user_scales; int64_t m;
@@ -70,10 +72,16 @@ struct RefineArgs {
     double* lam64;                  // [k_max x m]
     float* lam32;                   // [k_max x m]
     int* fail_list; int* fail_count;
+    // build diagnostics as bits of non-negative doubles, kErrSlots slots each (fast-score
+    // error, then lambda32 error): workgroup b takes slot b % kErrSlots, so that the
+    // atomics of 10^5 waves do not all meet on one address; the host takes the maximum
     unsigned long long* max_raw_err_bits;
     double err_rel;                 // relative error bound of the fast scores
     int* spill; int* spill_count;   // [m] users with more candidates than the narrow pass holds
     const int* list; const int* list_count;   // users of a listed pass (null: all users)
+    // split narrow pass: the kept candidates [m x C] (orderable key, item position) and per
+    // user {count (-1: left to the wide pass), cut bits, largest threshold bits, 0}
+    uint2* sel; int* sel_meta;
 };
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s);
 // Full FP64 rescoring of the users in fail_list (device count at fail_count, host copy nfail).

@@ -165,7 +165,8 @@ __device__ __forceinline__ double canon_chunk(const i32x4& a4, const i32x4& b4, 
 // (lanes past Nk, and positions past n, get -inf).  The candidate rows pass through LDS
 // in 64-byte column slices: four lanes load one row's slice with consecutive 16-byte
 // loads (one request per row and slice instead of one per lane and 16 bytes), then each
-// lane continues its own index-order sum over the slice.
+// lane continues its own index-order sum over the slice.  (Issuing several slices' loads
+// together cost registers and occupancy and ran slower.)
 static constexpr int RF_SLICE = 64;
 static constexpr int RF_PITCH = RF_SLICE + 16;   // LDS row pitch (bank spread)
 
@@ -225,9 +226,14 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double 
 // where every item outside the rescored set scored at most max(tau_s, cut) in the fast
 // arithmetic (tau_s: segment thresholds of the streaming pass; cut: the C-th best fast
 // score among all candidates when some were dropped here).
-template <int DT, int GPL, bool FAST>
-__device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint32_t* sid, double* s64,
-                            float* sraw, double* lam_row, float* raw_row, int* hist, uint8_t* rows)
+// Gathers user u's candidates from every segment's buffer and keeps the C best by the
+// fast score (all of them when there are at most C) in skey/sid, in gather order.
+// *cut: the C-th best fast score when some were dropped (else -inf); *tau_max: the
+// largest segment threshold.  Returns false (and lists u for the wide pass) when the
+// candidates do not fit GPL per lane.
+template <int GPL>
+__device__ bool refine_select(const RefineArgs& a, int64_t u, uint32_t* skey, uint32_t* sid, int* hist, int* nk_out,
+                              float* cut_out, float* tau_out)
 {
     const int l = lane_id();
     // gather every segment's buffer straight into registers (entry j = lane + 64 i)
@@ -244,7 +250,7 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
     const int N = cum[8];
     if (N > GPL * 64) {   // more candidates than this instance holds: the wide pass takes it
         if (l == 0) a.spill[atomicAdd(a.spill_count, 1)] = (int)u;
-        return;
+        return false;
     }
     const int HG = a.G / 2;
     uint32_t key[GPL], id[GPL];
@@ -289,21 +295,37 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
         }
     }
     __builtin_amdgcn_wave_barrier();
+    *nk_out = Nk;
+    *cut_out = cut;
+    *tau_out = tau_max;
+    return true;
+}
+
+// Canonical FP64 rescoring of the kept candidates skey/sid [0, Nk), their ranks,
+// lambda64/lambda32 for j <= k_max and the certificate
+//   max(tau_max, cut) + eps(u) <= lambda64^(k_max)
+// where every item outside the rescored set scored at most max(tau_max, cut) in the fast
+// arithmetic.
+template <int DT, bool FAST>
+__device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey, const uint32_t* sid, int Nk,
+                            float cut, float tau_max, double* s64, double* lam_row, uint8_t* rows)
+{
+    const int l = lane_id();
     const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
     const double un = sqrt(a.user_n2[u]);
     const double M = sqrt(a.item_n2_sorted[0]);
     double worst_raw = 0.0, worst32 = 0.0;
     double lk = -__builtin_inf();   // lambda64^(k_max) over the candidates (-inf with fewer)
-    auto stat = [&](double lv, float raw) {
-        if (lv != 0.0 && lv > -__builtin_inf() && fabs(lv) >= 1e-3 * un * M) {
-            worst_raw = fmax(worst_raw, fabs((double)raw - lv) / fabs(lv));
-            worst32 = fmax(worst32, fabs((double)(float)lv - lv) / fabs(lv));
-        }
+    // build diagnostics, reported to FP32 precision (the hardware reciprocal): the relative
+    // error of each rescored candidate's fast score, and of each lambda32 entry
+    auto rel = [&](double lv, double x) -> double {
+        if (lv == 0.0 || !(lv > -__builtin_inf()) || fabs(lv) < 1e-3 * un * M) return 0.0;
+        return (double)((float)fabs(x - lv) * __builtin_amdgcn_rcpf((float)fabs(lv)));
     };
     if (FAST || Nk <= 64) {
-        // one candidate per lane; the ranks come from two bitonic sorts across the wave
+        // one candidate per lane; the ranks come from a bitonic sort across the wave
         double v = canon_dot_staged<DT>(a, u, su, sid, Nk, rows);
-        uint32_t rk = l < Nk ? skey[l] : 0u;   // orderable fast-score key (0 sorts below every score)
+        if (l < Nk) worst_raw = rel(v, (double)ord_f32(skey[l]));
         int idx = l;
 #pragma unroll
         for (int kk = 2; kk <= 64; kk <<= 1)
@@ -311,21 +333,19 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
             for (int j = kk >> 1; j > 0; j >>= 1) {
                 const double ov = __shfl_xor(v, j);
                 const int oi = __shfl_xor(idx, j);
-                const uint32_t ok = __shfl_xor(rk, j);
                 const bool lower = (l & j) == 0, desc = (l & kk) == 0;
                 const bool mine_first = v > ov || (v == ov && idx < oi);
                 if (mine_first != (lower == desc)) {
                     v = ov;
                     idx = oi;
                 }
-                if ((rk > ok) != (lower == desc) && rk != ok) rk = ok;
             }
-        // lane r: the r-th largest canonical score and the r-th largest fast score
+        // lane r: the r-th largest canonical score
         for (int r = l; r < a.k_max; r += 64) {
             const double lv = r == l ? v : -__builtin_inf();
             a.lam64[(int64_t)r * a.m + u] = lv;
             a.lam32[(int64_t)r * a.m + u] = (float)lv;
-            if (r == l && l < Nk) stat(lv, ord_f32(rk));
+            if (r == l && l < Nk) worst32 = rel(lv, (double)(float)lv);
         }
         lk = a.k_max <= 64 ? __shfl(v, a.k_max - 1) : -__builtin_inf();
     } else if constexpr (!FAST) {
@@ -337,36 +357,33 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
                 v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
             }
             s64[j] = v;
-            sraw[j] = ord_f32(skey[j]);
+            worst_raw = fmax(worst_raw, rel(v, (double)ord_f32(skey[j])));
         }
         __builtin_amdgcn_wave_barrier();
         for (int j = l; j < Nk; j += 64) {
             const double x = s64[j];
-            const float y = sraw[j];
-            int r64 = 0, rr = 0;
+            int r64 = 0;
             for (int i = 0; i < Nk; i++) {
                 const double xi = s64[i];
-                const float yi = sraw[i];
                 r64 += (xi > x) || (xi == x && i < j);
-                rr += (yi > y) || (yi == y && i < j);
             }
             if (r64 < a.k_max) lam_row[r64] = x;
-            if (rr < a.k_max) raw_row[rr] = y;
         }
         __builtin_amdgcn_wave_barrier();
         for (int r = l; r < a.k_max; r += 64) {
             const double lv = r < Nk ? lam_row[r] : -__builtin_inf();
             a.lam64[(int64_t)r * a.m + u] = lv;
             a.lam32[(int64_t)r * a.m + u] = (float)lv;
-            if (r < Nk) stat(lv, raw_row[r]);
+            if (r < Nk) worst32 = fmax(worst32, rel(lv, (double)(float)lv));
         }
         lk = Nk >= a.k_max ? lam_row[a.k_max - 1] : -__builtin_inf();
     }
     worst_raw = wave_max(worst_raw);
     worst32 = wave_max(worst32);
     if (l == 0) {
-        if (worst_raw > 0.0) atomic_max_pos(a.max_raw_err_bits, worst_raw);
-        if (worst32 > 0.0) atomic_max_pos(a.max_raw_err_bits + 1, worst32);
+        const int slot = blockIdx.x % kErrSlots;
+        if (worst_raw > 0.0) atomic_max_pos(a.max_raw_err_bits + slot, worst_raw);
+        if (worst32 > 0.0) atomic_max_pos(a.max_raw_err_bits + kErrSlots + slot, worst32);
     }
     bool ok = !a.force_fail;
     const float worst_out = fmaxf(tau_max, cut);
@@ -378,6 +395,16 @@ __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint
         const int pos = atomicAdd(a.fail_count, 1);
         a.fail_list[pos] = (int)u;
     }
+}
+
+template <int DT, int GPL, bool FAST>
+__device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint32_t* sid, double* s64,
+                            double* lam_row, int* hist, uint8_t* rows)
+{
+    int Nk = 0;
+    float cut = 0.f, tau_max = 0.f;
+    if (!refine_select<GPL>(a, u, skey, sid, hist, &Nk, &cut, &tau_max)) return;
+    refine_rank<DT, FAST>(a, u, skey, sid, Nk, cut, tau_max, s64, lam_row, rows);
 }
 
 
@@ -392,23 +419,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FAST ? 6 : 
     __shared__ uint32_t skey[4][FAST ? 64 : 256];
     __shared__ uint32_t sid[4][FAST ? 64 : 256];
     __shared__ double s64[4][FAST ? 1 : 256];
-    __shared__ float sraw[4][FAST ? 1 : 256];
     __shared__ double lam_row[4][FAST ? 1 : 256];
-    __shared__ float raw_row[4][FAST ? 1 : 256];
     __shared__ int hist_all[4][256];
     __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
     const int w = threadIdx.x >> 6;
     if (!a.list) {
         const int64_t u = (int64_t)blockIdx.x * 4 + w;
         if (u < a.m)
-            refine_user<DT, GPL, FAST>(a, u, skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w], hist_all[w],
+            refine_user<DT, GPL, FAST>(a, u, skey[w], sid[w], s64[w], lam_row[w], hist_all[w],
                                        rows_all[w]);
     } else {
         const int cnt = *a.list_count;
         for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < cnt; i += (int64_t)gridDim.x * 4)
-            refine_user<DT, GPL, FAST>(a, a.list[i], skey[w], sid[w], s64[w], sraw[w], lam_row[w], raw_row[w],
+            refine_user<DT, GPL, FAST>(a, a.list[i], skey[w], sid[w], s64[w], lam_row[w],
                                        hist_all[w], rows_all[w]);
     }
+}
+
+// The narrow pass (C <= 64) in two kernels, so that each runs at the occupancy its own
+// registers allow: the selection (gather, radix select) and the rescoring (staged FP64
+// dot products, ranks, lambda rows, certificate).  The kept candidates go through
+// global memory (8 bytes each).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_refine_select(RefineArgs a)
+{
+    __shared__ uint32_t skey_all[4][64], sid_all[4][64];
+    __shared__ int hist_all[4][256];
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const int64_t u = (int64_t)blockIdx.x * 4 + w;
+    if (u >= a.m) return;
+    int Nk = 0;
+    float cut = 0.f, tau_max = 0.f;
+    const bool ok = refine_select<8>(a, u, skey_all[w], sid_all[w], hist_all[w], &Nk, &cut, &tau_max);
+    if (!ok) Nk = -1;
+    if (ok && l < Nk) a.sel[u * a.C + l] = make_uint2(skey_all[w][l], sid_all[w][l]);
+    if (l == 0) {
+        int* mt = a.sel_meta + 4 * u;
+        mt[0] = Nk;
+        mt[1] = __float_as_int(cut);
+        mt[2] = __float_as_int(tau_max);
+        mt[3] = 0;
+    }
+}
+
+// Workgroup b runs on XCD b % 8 (round-robin dispatch); the grid is a multiple of 8 and
+// each XCD takes a contiguous range of users, so that the lambda rows' lines (16
+// consecutive users per 128 bytes) are completed inside one L2 instead of reaching HBM
+// as partial lines from several.
+__device__ __forceinline__ int64_t xcd_user(int w)
+{
+    const int64_t per = gridDim.x / 8;
+    return ((int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8) * 4 + w;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_refine_rank(RefineArgs a)
+{
+    __shared__ uint32_t skey_all[4][64], sid_all[4][64];
+    __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const int64_t u = xcd_user(w);
+    if (u >= a.m) return;
+    const int* mt = a.sel_meta + 4 * u;
+    const int Nk = mt[0];
+    if (Nk < 0) return;   // the wide pass takes this user
+    if (l < Nk) {
+        const uint2 e = a.sel[u * a.C + l];
+        skey_all[w][l] = e.x;
+        sid_all[w][l] = e.y;
+    }
+    __builtin_amdgcn_wave_barrier();
+    refine_rank<DT, true>(a, u, skey_all[w], sid_all[w], Nk, __int_as_float(mt[1]), __int_as_float(mt[2]), nullptr,
+                          nullptr, rows_all[w]);
 }
 
 template <int DT>
@@ -417,7 +498,13 @@ static void refine_d(const RefineArgs& a, hipStream_t s)
     if (a.C <= 64) {
         RefineArgs a0 = a;
         a0.list = nullptr;
-        hipLaunchKernelGGL((k_refine<DT, 8, true>), dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a0);
+        if (a.sel) {
+            const unsigned g = (unsigned)((a.m + 3) / 4);
+            hipLaunchKernelGGL(k_refine_select, dim3(g), dim3(256), 0, s, a0);
+            hipLaunchKernelGGL((k_refine_rank<DT>), dim3((g + 7) / 8 * 8), dim3(256), 0, s, a0);
+        } else {
+            hipLaunchKernelGGL((k_refine<DT, 8, true>), dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a0);
+        }
         if ((int64_t)a.nseg * a.G <= 8 * 64) return;   // no user can hold more than 512
         RefineArgs a1 = a;
         a1.list = a.spill;
@@ -498,7 +585,9 @@ __global__ __launch_bounds__(256) void k_fallback(RefineArgs a, double* scratch,
             for (int i = 0; i < ng; i++) r += (top[i] > top[j]) || (top[i] == top[j] && i < j);
             a.lam64[(int64_t)r * a.m + u] = top[j];
             a.lam32[(int64_t)r * a.m + u] = (float)top[j];
-            if (top[j] != 0.0) atomic_max_pos(a.max_raw_err_bits + 1, fabs((double)(float)top[j] - top[j]) / fabs(top[j]));
+            if (top[j] != 0.0)
+                atomic_max_pos(a.max_raw_err_bits + kErrSlots + blockIdx.x % kErrSlots,
+                               fabs((double)(float)top[j] - top[j]) / fabs(top[j]));
         }
         for (int r = ng + tid; r < a.k_max; r += 256) {
             const double v = r < want ? T : -__builtin_inf();
