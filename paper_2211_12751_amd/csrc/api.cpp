@@ -3,12 +3,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <exception>
+#include <functional>
 #include <map>
-#include <mutex>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -322,6 +327,76 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
     x.cand_tau.swap(L.tau);
 }
 
+// Persistent host threads that queue a build's second-stream work (a thread started per
+// build can take hundreds of microseconds to run).  One job at a time per thread; a
+// build takes an idle one or starts another.  Never destroyed: the threads end with the
+// process.
+struct HostWorker {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::function<void()> job;
+    bool busy = false;
+    HostWorker()
+    {
+        std::thread([this] {
+            for (;;) {
+                std::function<void()> f;
+                {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return (bool)job; });
+                    f.swap(job);
+                }
+                f();   // jobs catch their own exceptions
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    busy = false;
+                }
+                cv.notify_all();
+            }
+        }).detach();
+    }
+    void start(std::function<void()> f)
+    {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            busy = true;
+            job = std::move(f);
+        }
+        cv.notify_all();
+    }
+    void wait()
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return !busy; });
+    }
+};
+
+// The idle workers (never destroyed).
+struct WorkerPool {
+    std::mutex mu;
+    std::vector<HostWorker*> idle;
+    HostWorker* take()
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (idle.empty()) return new HostWorker;
+        HostWorker* w = idle.back();
+        idle.pop_back();
+        return w;
+    }
+    void give(HostWorker* w)
+    {
+        w->wait();
+        std::lock_guard<std::mutex> g(mu);
+        idle.push_back(w);
+    }
+};
+
+static WorkerPool& worker_pool()
+{
+    static WorkerPool* p = new WorkerPool;
+    return *p;
+}
+
 static void build_index(Index& x, const void* items, const float* item_scales, const void* users,
                         const float* user_scales, const float* srp, hipStream_t s)
 {
@@ -338,6 +413,8 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     launch_norm_stats_init(st, s);
     launch_norm2(x.dtype, users, user_scales, m, x.d, x.d, n2_users_orig.d(), st, 1, s);
     HIPC(hipEventRecord(ev.ev[8], s));   // the Cone-Tree build needs only the users and their norms
+    const hipStream_t s2 = aux_stream(x.device);
+    HIPC(hipStreamWaitEvent(s2, ev.ev[8], 0));
     launch_norm2(x.dtype, items, item_scales, n, x.d, x.d, n2_items_orig.d(), st, 0, s);
     PinBuf hst;
     hst.alloc(sizeof(unsigned long long) * 4);
@@ -375,36 +452,79 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
 
     // The fused top-k passes (matrix-core bound) run on the caller's stream, followed by
     // the item side of SA-ALSH; the Cone-Tree (latency bound, host-checked) and the SA-ALSH
-    // user codes run on a second stream.  The refine pass waits for the second stream:
+    // user codes run on a second stream, queued by a second host thread so that neither
+    // stream waits for the other's launches.  The refine pass waits for the second stream:
     // enqueued earlier, its grid of one wave per user would hold the compute units the
     // second stream's kernels need.
     LambdaBuild L;
     ConeWork cone_work;
+    struct Worker {
+        HostWorker* hw = nullptr;
+        std::mutex mu;
+        std::condition_variable cv;
+        bool srp_ready = false;
+        std::atomic<bool> cancel{false};
+        std::exception_ptr err;
+        hipStream_t s2 = nullptr;
+        void ready()
+        {
+            {
+                std::lock_guard<std::mutex> g(mu);
+                srp_ready = true;
+            }
+            cv.notify_all();
+        }
+        void finish()
+        {
+            if (!hw) return;
+            worker_pool().give(hw);   // waits for the job
+            hw = nullptr;
+        }
+        ~Worker()
+        {
+            cancel = true;
+            finish();
+            if (err && s2) (void)hipStreamSynchronize(s2);   // its buffers are released next
+        }
+    } wk;
+    wk.s2 = s2;
+    wk.hw = worker_pool().take();
+    wk.hw->start([&] {
+        try {
+            HIPC(hipSetDevice(x.device));
+            mem::StreamScope scope2(s2);
+            HIPC(hipEventRecord(ev.ev[2], s2));
+            saalsh_projections(x, srp, s2);
+            HIPC(hipEventRecord(ev.ev[6], s2));
+            wk.ready();
+            // ---- Cone-Tree over user directions; users are stored in leaf order
+            build_cone(x, users, user_scales, n2_users_orig.d(), s2, nullptr, cone_work, &wk.cancel);
+            if (wk.cancel.load()) return;
+            saalsh_users(x, s2);
+            HIPC(hipEventRecord(ev.ev[7], s2));
+        } catch (...) {
+            wk.err = std::current_exception();
+            wk.ready();
+        }
+    });
     lambda_topk(x, L, users_o, uscales_o.f(), s);
-    const hipStream_t s2 = aux_stream(x.device);
-    HIPC(hipStreamWaitEvent(s2, ev.ev[8], 0));
+    // validation (the input statistics and the partition count were copied before ev1),
+    // then the item side of SA-ALSH behind the top-k passes
+    host_wait(ev.ev[1]);
+    range_check(x, (const unsigned long long*)hst.p);
+    x.t = *(const int*)hnp.p;
     {
-        mem::StreamScope scope2(s2);
-        HIPC(hipEventRecord(ev.ev[2], s2));
-        saalsh_projections(x, srp, s2);
-        HIPC(hipEventRecord(ev.ev[6], s2));
-        // ---- Cone-Tree over user directions; users are stored in leaf order
-        build_cone(x, users, user_scales, n2_users_orig.d(), s2, [&] {
-            // while the first levels run: validation (the input statistics and the
-            // partition count were copied before ev1), then the item side of SA-ALSH
-            // behind the top-k passes
-            host_wait(ev.ev[1]);
-            range_check(x, (const unsigned long long*)hst.p);
-            x.t = *(const int*)hnp.p;
-            mem::StreamScope scope(s);
-            HIPC(hipStreamWaitEvent(s, ev.ev[6], 0));
-            HIPC(hipEventRecord(ev.ev[4], s));
-            saalsh_items(x, s);
-            HIPC(hipEventRecord(ev.ev[5], s));
-        }, cone_work);
-        saalsh_users(x, s2);
-        HIPC(hipEventRecord(ev.ev[7], s2));
+        std::unique_lock<std::mutex> lk(wk.mu);
+        wk.cv.wait(lk, [&] { return wk.srp_ready; });
     }
+    if (!wk.err) {
+        HIPC(hipStreamWaitEvent(s, ev.ev[6], 0));
+        HIPC(hipEventRecord(ev.ev[4], s));
+        saalsh_items(x, s);
+        HIPC(hipEventRecord(ev.ev[5], s));
+    }
+    wk.finish();
+    if (wk.err) std::rethrow_exception(wk.err);
     HIPC(hipStreamWaitEvent(s, ev.ev[7], 0));
     lambda_refine(x, L, users_o, uscales_o.f(), n2_users_orig.d(), s);
 

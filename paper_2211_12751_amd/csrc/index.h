@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <functional>
 #include <memory>
 #include <mutex>
@@ -152,8 +153,10 @@ struct ConeWork {
 // Cone-Tree over the user directions (users end in leaf order).  `enqueued` runs once on
 // the host after the first batch of levels is on the stream, before the host's first
 // wait for them (work for other streams can be enqueued there).
+// `cancel` (optional) is checked after each host wait: once set, the build stops there.
 void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
-                hipStream_t s, const std::function<void()>& enqueued, ConeWork& cw);
+                hipStream_t s, const std::function<void()>& enqueued, ConeWork& cw,
+                const std::atomic<bool>* cancel = nullptr);
 void finish_blocks(Index& x, hipStream_t s);
 void start_partitions(Index& x, int* h_num_parts, hipStream_t s);
 // SA-ALSH index (Alg. 1) in three stream-ordered parts: the random projections, the item

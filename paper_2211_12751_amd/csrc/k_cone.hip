@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const uin
 
 // ------------------------------------------------------------------ host orchestration
 void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s,
-                const std::function<void()>& enqueued, ConeWork& cw)
+                const std::function<void()>& enqueued, ConeWork& cw, const std::atomic<bool>* cancel)
 {
     const int64_t m = x.m;
     const int ld = x.ld;
@@ -523,6 +523,7 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
             if (enqueued) enqueued();
         }
         host_wait(ev_ctl);
+        if (cancel && cancel->load()) return;
         more = ((const int64_t*)h_ctl.p)[2] > 0;
         nseg_final = ((const int64_t*)h_ctl.p)[level & 1];
         batch = 2;
