@@ -301,6 +301,215 @@ __global__ void k_cone_scatter(ConeLevelArgs a, uint32_t* new_perm)
 }
 
 
+// ------------------------------------------------------------------ local completion
+// Below a few hundred users per segment, a grid-wide level costs more in launches and
+// barriers than in work: one workgroup per segment of the current level then completes
+// its subtree on its own, depth first, with the same split rule (random point drawn from
+// (seed, level, segment start), u_l = argmin <u, v>, u_r = argmin <u, u_l>, stable split
+// by cos(u, u_l) >= cos(u, u_r), index halves when one side is empty).  Leaf starts are
+// flagged per position (is_start); the block table is assembled from the flags.
+static constexpr int CL_STACK = 64;
+static constexpr int CL_TARGET = 512;   // users per segment where the local completion takes over
+
+__device__ __forceinline__ unsigned long long wg_min_u64(unsigned long long v, unsigned long long* red)
+{
+    v = wave_min_u64(v);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    unsigned long long r = red[0];
+    for (int i = 1; i < 4; i++) r = red[i] < r ? red[i] : r;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_cone_local(ConeLevelArgs a, uint32_t* tmp_perm, int* is_start)
+{
+    __shared__ int64_t stk_st[CL_STACK];
+    __shared__ int stk_sz[CL_STACK], stk_lv[CL_STACK];
+    __shared__ int top_s;
+    __shared__ unsigned long long red[4];
+    __shared__ int wcnt[4];
+    const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
+    const int64_t nseg = a.ctl[a.ctl_cur];
+    if ((int64_t)blockIdx.x >= nseg) return;   // the grid is an upper bound (workgroup-uniform)
+    if (tid == 0) {
+        const int64_t st0 = a.seg_start[blockIdx.x];
+        stk_st[0] = st0;
+        stk_sz[0] = (int)(a.seg_start[blockIdx.x + 1] - st0);
+        stk_lv[0] = a.level;
+        top_s = 1;
+    }
+    __syncthreads();
+    uint32_t* perm = (uint32_t*)a.perm;   // this workgroup owns its segment's positions
+    for (;;) {
+        const int t = top_s;
+        if (t == 0) break;
+        const int64_t st = stk_st[t - 1];
+        const int sz = stk_sz[t - 1], lv = stk_lv[t - 1];
+        __syncthreads();
+        if (tid == 0) top_s = t - 1;
+        if (sz <= a.leaf) {
+            if (tid == 0) is_start[st] = 1;
+            __syncthreads();
+            continue;
+        }
+        // random point v, u_l, u_r
+        const uint64_t rr = splitmix64(a.seed ^ splitmix64(((uint64_t)lv << 40) ^ (uint64_t)st));
+        const int64_t pv = st + (int64_t)(rr % (uint64_t)sz);
+        const uint16_t* vrow = a.unit + (int64_t)perm[pv] * a.ld;
+        unsigned long long k = ~0ull;
+        for (int i = tid; i < sz; i += 256) {
+            const int64_t p = st + i;
+            const float dv = row_dot(a.unit + (int64_t)perm[p] * a.ld, vrow, a.ld);
+            const unsigned long long key = ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p;
+            k = key < k ? key : k;
+        }
+        const int64_t pl = (int64_t)(wg_min_u64(k, red) & 0xffffffffull);
+        const uint16_t* lrow = a.unit + (int64_t)perm[pl] * a.ld;
+        k = ~0ull;
+        for (int i = tid; i < sz; i += 256) {
+            const int64_t p = st + i;
+            const float dl = row_dot(a.unit + (int64_t)perm[p] * a.ld, lrow, a.ld);
+            a.dot_l[p] = dl;
+            const unsigned long long key = ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p;
+            k = key < k ? key : k;
+        }
+        const int64_t pr = (int64_t)(wg_min_u64(k, red) & 0xffffffffull);
+        const uint16_t* rrow = a.unit + (int64_t)perm[pr] * a.ld;
+        int nl_mine = 0;
+        for (int i = tid; i < sz; i += 256) {
+            const int64_t p = st + i;
+            const float dr = row_dot(a.unit + (int64_t)perm[p] * a.ld, rrow, a.ld);
+            const int lf = a.dot_l[p] >= dr ? 1 : 0;
+            a.left[p] = lf;
+            nl_mine += lf;
+        }
+        nl_mine = wave_sum(nl_mine);
+        if (l == 0) wcnt[w] = nl_mine;
+        __syncthreads();
+        int nl = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        const bool dg = nl == 0 || nl == sz;
+        if (dg) {
+            nl = sz / 2;   // index halves: the order stays
+        } else {
+            // stable partition, chunk by chunk in position order: lefts first
+            int lb = 0, rb = 0;   // lefts / rights placed by earlier chunks
+            for (int c0 = 0; c0 < sz; c0 += 256) {
+                __syncthreads();   // wcnt reuse
+                const int i = c0 + tid;
+                const bool in = i < sz;
+                const int lf = in ? a.left[st + i] : 0;
+                const uint64_t bl = ballot64(in && lf), br = ballot64(in && !lf);
+                if (l == 0) wcnt[w] = __popcll(bl);
+                __syncthreads();
+                int wl = 0;
+                for (int q = 0; q < w; q++) wl += wcnt[q];
+                const int cl = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+                const int clen = sz - c0 < 256 ? sz - c0 : 256;
+                if (in) {
+                    const int rl = __popcll(bl & lanemask_lt());
+                    const int rw = (w * 64 - wl) + __popcll(br & lanemask_lt());   // rights before, inside the chunk
+                    const int np = lf ? lb + wl + rl : nl + rb + rw;
+                    tmp_perm[st + np] = perm[st + i];
+                }
+                lb += cl;
+                rb += clen - cl;
+            }
+            __syncthreads();
+            for (int i = tid; i < sz; i += 256) perm[st + i] = tmp_perm[st + i];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // the larger part first, so that the smaller one is split next (stack depth
+            // stays below log2 of the segment size)
+            const int64_t s0 = st, s1 = st + nl;
+            const int z0 = nl, z1 = sz - nl;
+            const int tt = top_s;
+            if (tt + 2 > CL_STACK) {
+                // unreachable (the smaller part is split first, so the stack holds fewer
+                // than log2(size) + 2 entries); kept in bounds regardless
+                is_start[s0] = 1;
+                is_start[s1] = 1;
+            } else if (z0 >= z1) {
+                stk_st[tt] = s0; stk_sz[tt] = z0; stk_lv[tt] = lv + 1;
+                stk_st[tt + 1] = s1; stk_sz[tt + 1] = z1; stk_lv[tt + 1] = lv + 1;
+            } else {
+                stk_st[tt] = s1; stk_sz[tt] = z1; stk_lv[tt] = lv + 1;
+                stk_st[tt + 1] = s0; stk_sz[tt + 1] = z0; stk_lv[tt + 1] = lv + 1;
+            }
+            if (tt + 2 <= CL_STACK) top_s = tt + 2;
+        }
+        __syncthreads();
+    }
+}
+
+// Block table from the leaf-start flags: counts per 1024 positions, one workgroup's scan
+// of those counts (nblocks into *nblocks), then the starts in position order and m last.
+__global__ __launch_bounds__(256) void k_flag_count(const int* is_start, int64_t m, int* bcnt)
+{
+    __shared__ int wc[4];
+    const int64_t b = blockIdx.x;
+    int c = 0;
+    for (int i = threadIdx.x; i < 1024; i += 256) {
+        const int64_t p = b * 1024 + i;
+        if (p < m) c += is_start[p];
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) wc[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) bcnt[b] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+__global__ __launch_bounds__(1024) void k_flag_scan(int* bcnt, int64_t nb, int64_t* nblocks)
+{
+    __shared__ int64_t wtot[16];
+    __shared__ int64_t carry_s;
+    const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        const int64_t i = c0 + tid;
+        const int v = i < nb ? bcnt[i] : 0;
+        const int incl = wave_incl_scan(v);
+        if (l == 63) wtot[w] = incl;
+        __syncthreads();
+        int64_t off = carry_s;
+        for (int q = 0; q < w; q++) off += wtot[q];
+        if (i < nb) bcnt[i] = (int)(off + incl - v);
+        __syncthreads();
+        if (tid == 0) {
+            int64_t t = 0;
+            for (int q = 0; q < 16; q++) t += wtot[q];
+            carry_s += t;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *nblocks = carry_s;
+}
+
+__global__ __launch_bounds__(256) void k_flag_emit(const int* is_start, int64_t m, const int* boff,
+                                                   const int64_t* nblocks, int64_t* block_start)
+{
+    __shared__ int wc[4];
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
+    int64_t base = boff[b];
+    for (int c0 = 0; c0 < 1024; c0 += 256) {
+        const int64_t p = b * 1024 + c0 + tid;
+        const bool f = p < m && is_start[p];
+        const uint64_t bal = ballot64(f);
+        if (l == 0) wc[w] = __popcll(bal);
+        __syncthreads();
+        int off = 0;
+        for (int q = 0; q < w; q++) off += wc[q];
+        if (f) block_start[base + off + __popcll(bal & lanemask_lt())] = p;
+        base += wc[0] + wc[1] + wc[2] + wc[3];
+        __syncthreads();
+    }
+    if (b == 0 && tid == 0) block_start[*nblocks] = m;
+}
+
 // BF16 unit rows (original order) for the split phases.
 template <int DT>
 __global__ void k_unit(const void* X, const float* scales, const double* n2, int64_t rows, int d, int ld,
@@ -496,49 +705,49 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
         hipLaunchKernelGGL(k_cone_init, dim3(grid), dim3(256), 0, s, a);
         HIPC(hipGetLastError());
     }
-    int level = 0;
-    bool more = m > x.prm.leaf_size;
-    // the first batch is the depth of a perfectly balanced tree plus a margin for uneven
-    // splits (levels without an active segment cost one early exit per kernel), so the
-    // host usually checks once; later batches are short
-    int batch = 1;
-    while (((int64_t)x.prm.leaf_size << batch) < m) batch++;
-    batch += 3;
-    int64_t nseg_final = 1;
-    bool hooked = false;
-    while (more) {
-        for (int rep = 0; rep < batch; rep++, level++) {
-            const ConeLevelArgs a = level_args(level);
-            for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
-            hipLaunchKernelGGL(k_cone_next, dim3(1), dim3(CN_THREADS), 0, s, a);
-            hipLaunchKernelGGL(k_cone_scatter, dim3(grid), dim3(256), 0, s, a, perm_b.u32());
-            HIPC(hipGetLastError());
-            perm_a.swap(perm_b);
-            seg_a.swap(seg_b);
-        }
-        HIPC(hipMemcpyAsync(h_ctl.p, d_ctl.p, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
-        HIPC(hipEventRecord(ev_ctl, s));
-        if (!hooked) {
-            hooked = true;
-            if (enqueued) enqueued();
-        }
-        host_wait(ev_ctl);
-        if (cancel && cancel->load()) return;
-        more = ((const int64_t*)h_ctl.p)[2] > 0;
-        nseg_final = ((const int64_t*)h_ctl.p)[level & 1];
-        batch = 2;
+    // Grid-wide levels until segments average about CL_TARGET users (one launch per phase
+    // and level: the work of a level is a pass over all users), then one workgroup per
+    // segment completes the tree locally.
+    int L0 = 0;
+    while ((m >> L0) > CL_TARGET) L0++;
+    for (int level = 0; level < L0; level++) {
+        const ConeLevelArgs a = level_args(level);
+        for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
+        hipLaunchKernelGGL(k_cone_next, dim3(1), dim3(CN_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_cone_scatter, dim3(grid), dim3(256), 0, s, a, perm_b.u32());
+        HIPC(hipGetLastError());
+        perm_a.swap(perm_b);
+        seg_a.swap(seg_b);
     }
-    if (!hooked && enqueued) enqueued();
-    if (level == 0) {   // the caller reads host copies made before the build
-        HIPC(hipEventRecord(ev_ctl, s));
-        host_wait(ev_ctl);
+    // local completion; the leaf-start flags reuse the level ranks, the block counts the
+    // level block counts, and ctl[3] receives the block count
+    int* is_start = lrank.i();
+    HIPC(hipMemsetAsync(is_start, 0, sizeof(int) * (size_t)m, s));
+    {
+        const ConeLevelArgs a = level_args(L0);
+        const unsigned lgrid = (unsigned)std::min<int64_t>((int64_t)1 << L0, m);
+        hipLaunchKernelGGL(k_cone_local, dim3(lgrid), dim3(256), 0, s, a, perm_b.u32(), is_start);
+        HIPC(hipGetLastError());
     }
+    x.block_start.alloc(sizeof(int64_t) * (size_t)(m + 1));
+    {
+        const int64_t nb = (m + 1023) / 1024;
+        int64_t* nblocks_dev = d_ctl.i64() + 3;
+        hipLaunchKernelGGL(k_flag_count, dim3((unsigned)nb), dim3(256), 0, s, (const int*)is_start, m, blk_cnt.i());
+        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, blk_cnt.i(), nb, nblocks_dev);
+        hipLaunchKernelGGL(k_flag_emit, dim3((unsigned)nb), dim3(256), 0, s, (const int*)is_start, m,
+                           (const int*)blk_cnt.i(), (const int64_t*)nblocks_dev, x.block_start.i64());
+        HIPC(hipGetLastError());
+    }
+    HIPC(hipMemcpyAsync(h_ctl.p, d_ctl.p, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipEventRecord(ev_ctl, s));
+    if (enqueued) enqueued();
+    host_wait(ev_ctl);
+    if (cancel && cancel->load()) return;
+    const int64_t nseg_final = ((const int64_t*)h_ctl.p)[3];
 
     // ---- leaves are the blocks; users move into leaf order
     x.nblocks = nseg_final;
-    x.block_start.alloc(sizeof(int64_t) * (nseg_final + 1));
-    HIPC(hipMemcpyAsync(x.block_start.p, d_start[level & 1].p, sizeof(int64_t) * (nseg_final + 1),
-                        hipMemcpyDeviceToDevice, s));
     x.user_perm.swap(perm_a);
     const int eb = elt_bytes(x.dtype);
     x.users.alloc((size_t)m * ld * eb);
