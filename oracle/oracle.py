@@ -17,6 +17,8 @@ or uint8 FP8 e4m3 codes with float32 per-row scales):
 * ``values``         stored rows widened to float64 (FP8: code value x row scale)
 * ``cone_block_stats``, ``block_lower_bounds``  per-block cone data of a given
   partition of the users (Alg. 3 leaves; Lemmas 2 and 3; L^j(B) of Alg. 4)
+* ``sah_rkmips``     the approximate SAH method: Alg. 4 with L_i from P' and the
+  SA-ALSH index over P minus P', Alg. 5 per (query, user)
 """
 from __future__ import annotations
 
@@ -142,13 +144,15 @@ def item_order(dtype, P, P_scales):
     return n2, order
 
 
-def partitions(norm2, order, b):
-    """int64 partition starts into ``order`` (length t+1)."""
-    norm2, order = _c(norm2, np.float64), _c(order, np.int64)
+def partitions(norm2, order, b, start=0):
+    """int64 partition starts into ``order`` (length t+1) of the items order[start:]
+    (SAH leaves the first positions, P', out of the SA-ALSH index)."""
+    norm2 = _c(norm2, np.float64)
+    order = _c(np.asarray(order)[start:], np.int64)
     n = len(order)
     ps = np.empty(n + 2, dtype=np.int64)
     t = _L().orc_partitions(_p(norm2), _p(order), C.c_int64(n), C.c_float(b), _p(ps), n + 1)
-    return ps[: t + 1].copy()
+    return ps[: t + 1].copy() + start
 
 
 def saalsh_index(dtype, P, P_scales, order, part_start, A):
@@ -161,7 +165,7 @@ def saalsh_index(dtype, P, P_scales, order, part_start, A):
     t = len(part_start) - 1
     cen = np.empty((t, d), dtype=np.float64)
     rad = np.empty(t, dtype=np.float64)
-    codes = np.empty((n, K // 32), dtype=np.uint32)
+    codes = np.zeros((n, K // 32), dtype=np.uint32)   # items outside every partition keep 0
     _L().orc_saalsh_index(_DT[dtype], d, _p(P), _p(_c(P_scales, np.float32)), C.c_int64(n),
                           _p(order), _p(part_start), t, _p(A), K, _p(cen), _p(rad), _p(codes))
     return cen, rad, codes
@@ -179,9 +183,11 @@ def user_codes(dtype, U, U_scales, A):
 
 
 def saalsh_decide(dtype, P, P_scales, norm2, order, part_start, item_codes, ucode, beta,
-                  U, U_scales, u, Q, Q_scales, qi, k):
-    """(answer 0/1, phi) of Alg. 2 for user u, query qi and k."""
+                  U, U_scales, u, Q, Q_scales, qi, k, init=None):
+    """(answer 0/1, phi) of Alg. 2 for user u, query qi and k.  ``init``: scores that
+    are candidates before the first partition (SAH: u's scores on P')."""
     P, U, Q = _c(P), _c(U), _c(Q)
+    init = _c(np.zeros(0) if init is None else np.asarray(init), np.float64)
     phi = C.c_double(0.0)
     ucode = _c(np.asarray(ucode), np.uint32)
     K = ucode.shape[-1] * 32
@@ -191,7 +197,7 @@ def saalsh_decide(dtype, P, P_scales, norm2, order, part_start, item_codes, ucod
                                _p(_c(item_codes, np.uint32)), _p(ucode), K, C.c_float(beta),
                                _p(U), _p(_c(U_scales, np.float32)), C.c_int64(u),
                                _p(Q), _p(_c(Q_scales, np.float32)), C.c_int64(qi), k,
-                               C.byref(phi))
+                               _p(init), C.c_int64(len(init)), C.byref(phi))
     if r < 0:
         raise MemoryError("oracle saalsh_decide")
     return r, phi.value
@@ -270,4 +276,52 @@ def block_lower_bounds(dtype, U, U_scales, lam, leaf_users, block_start):
     for b in range(nb):
         idx = leaf_users[block_start[b]:block_start[b + 1]]
         out[:, b] = np.min(lam[:, idx] / norms[idx][None, :], axis=1)
+    return out
+
+
+def sah_rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, n_prime, b, beta, A):
+    """The approximate SAH method, per query an ascending user-ID list.
+
+    Index (Alg. 4): items in descending canonical norm; P' = the first ``n_prime`` of
+    them; L_u^j = the j-th largest s(u, p) over P' (k_max-MIPS on P', exact); the
+    SA-ALSH index (Alg. 1: partitions with ratio ``b``, centroids, radii, codes from the
+    projection matrix ``A``) over P minus P'.  Query (Alg. 5), for every user u:
+      s(u,q) < L_u^k                   -> no  (the block and angle tests of Alg. 5 are
+                                              upper bounds of s(u,q): they only skip
+                                              users this test rejects as well);
+      s(u,q) >= ||u|| ||p_k||          -> yes (p_k the k-th item in norm order; taken
+                                              as s >= 0 and s^2 >= n2(u) n2(p_k), with
+                                              n2(p_k) = 0 when k > n);
+      otherwise                        -> Alg. 2 over the partitions of P minus P', its
+                                          candidates starting from u's scores on P'.
+    """
+    P, U, Q = _c(P), _c(U), _c(Q)
+    n = P.shape[0]
+    n2p, order = item_order(dtype, P, P_scales)
+    n2u, _ = item_order(dtype, U, U_scales)
+    top = order[:n_prime]
+    Pp = P[top]
+    Pps = None if P_scales is None else np.asarray(P_scales)[top]
+    lam = lambda_table(dtype, Pp, Pps, U, U_scales, k_max)
+    ps = partitions(n2p, order, b, start=n_prime)
+    _, _, icodes = saalsh_index(dtype, P, P_scales, order, ps, A)
+    ucodes = user_codes(dtype, U, U_scales, A)
+    ks = np.asarray(ks)
+    surv = member(dtype, U, U_scales, Q, Q_scales, ks, lam)
+    out = []
+    for qi in range(Q.shape[0]):
+        k = int(ks[qi])
+        pk2 = float(n2p[order[k - 1]]) if k <= n else 0.0
+        keep = []
+        for u in np.flatnonzero(surv[qi]):
+            s = score(dtype, U, U_scales, int(u), Q, Q_scales, qi)
+            if s >= 0.0 and s * s >= float(n2u[u]) * pk2:
+                keep.append(u)
+                continue
+            init = [score(dtype, U, U_scales, int(u), Pp, Pps, j) for j in range(len(top))]
+            ans, _ = saalsh_decide(dtype, P, P_scales, n2p, order, ps, icodes, ucodes[u], beta,
+                                   U, U_scales, int(u), Q, Q_scales, qi, k, init=init)
+            if ans:
+                keep.append(u)
+        out.append(np.asarray(keep, dtype=np.int32))
     return out

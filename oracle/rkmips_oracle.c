@@ -320,6 +320,9 @@ static int popcount32(uint32_t v)
  * of probed buckets as a fraction beta of the partition.  phi is then the k-th
  * largest s(u,p) over all candidates so far (-inf while fewer than k), and the
  * answer is no when s(u,q) < phi.  After the last partition the answer is yes.
+ * init[0 .. n_init) (may be empty): scores that are candidates before the first
+ * partition -- in SAH (Alg. 5) the scores of u on the items of P' that Alg. 4 set
+ * aside, whose index covers P \ P' only; phi starts as their k-th largest.
  * Returns 1 (yes) or 0 (no); *phi_out receives the final phi. */
 int orc_saalsh_decide(int dtype, int d,
                       const void *P, const float *p_scales, const double *norm2,
@@ -327,16 +330,25 @@ int orc_saalsh_decide(int dtype, int d,
                       const uint32_t *item_codes, const uint32_t *user_code, int K,
                       float beta, const void *U, const float *u_scales, int64_t u,
                       const void *Q, const float *q_scales, int64_t qi, int k,
-                      double *phi_out)
+                      const double *init, int64_t n_init, double *phi_out)
 {
     int W = K / 32;
     int64_t n = part_start[t];
-    double *cand = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *cand = (double *)malloc(sizeof(double) * (size_t)(n + n_init > 0 ? n + n_init : 1));
     int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int *col = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
     if (!cand || !idx || !col) { free(cand); free(idx); free(col); return -1; }
     int64_t nc = 0;
     double phi = -INFINITY;
+    for (int64_t i = 0; i < n_init; i++) cand[nc++] = init[i];
+    if (nc >= k) {
+        double *tmp = (double *)malloc(sizeof(double) * (size_t)nc);
+        if (!tmp) { free(cand); free(idx); free(col); return -1; }
+        memcpy(tmp, cand, sizeof(double) * (size_t)nc);
+        qsort(tmp, (size_t)nc, sizeof(double), cmp_desc);
+        phi = tmp[k - 1];
+        free(tmp);
+    }
     double unorm = sqrt(orc_norm2(dtype, d, U, u_scales, u));
     double suq = orc_score(dtype, d, U, u_scales, u, Q, q_scales, qi);
     int ans = 1;

@@ -421,3 +421,62 @@ def test_values_widen_storage_formats():
     assert np.array_equal(O.values("bf16", bf), [[1.0, -3.0, 0.0]])
     f8 = np.array([[0x38, 0xB8, 0x7E]], np.uint8)           # 1, -1, 448
     assert np.array_equal(O.values("fp8", f8, np.array([0.5], np.float32)), [[0.5, -0.5, 224.0]])
+
+
+# ---------------------------------------------------------------- SAH (approximate) mode
+def _sah_case(seed, n=400, m=60, nq=10, d=16, K=64):
+    w = I.make("c2", n=n, m=m, nq=nq, d=d, seed=seed)
+    A = np.random.default_rng(seed).standard_normal((d + 1, K)).astype(np.float32)
+    ks = np.array([1, 5, 10, 20, 5, 1, 10, 20, 5, 10][:nq], np.int32)
+    return w, A, ks
+
+
+def test_alg2_initial_candidates_set_phi():
+    """With no partition left to visit, phi is the k-th largest initial score: given
+    every item's score it is lambda^(k) itself, and the answer is yes."""
+    w, A, _ = _sah_case(40, n=120, m=6, nq=3)
+    n2, order = O.item_order("f32", w.items, None)
+    lam = O.lambda_table("f32", w.items, None, w.users, None, 20)
+    ps = np.array([w.n], np.int64)
+    ucodes = O.user_codes("f32", w.users, None, A)
+    icodes = np.zeros((w.n, 2), np.uint32)
+    for u in range(6):
+        init = [O.score("f32", w.users, None, u, w.items, None, p) for p in range(w.n)]
+        for k in (1, 7, 20):
+            ans, phi = O.saalsh_decide("f32", w.items, None, n2, order, ps, icodes, ucodes[u], 0.1,
+                                       w.users, None, u, w.queries, None, 0, k, init=init)
+            assert ans == 1 and phi == lam[k - 1, u]
+
+
+def test_sah_with_every_item_in_p_prime_is_exact():
+    """P' = P: L_u is the exact lambda table and no partition remains, so SAH returns
+    exactly the Definition 1 sets."""
+    w, A, ks = _sah_case(41, n=150)
+    exact, _ = O.rkmips("f32", w.items, None, w.users, None, w.queries, None, ks, 20)
+    got = O.sah_rkmips("f32", w.items, None, w.users, None, w.queries, None, ks, 20, w.n, 0.5, 0.1, A)
+    for a, b in zip(got, exact):
+        assert np.array_equal(a, b)
+
+
+def test_sah_full_probe_is_exact_and_partial_probe_is_a_superset():
+    """beta = 1 probes every item of P minus P', so phi reaches lambda^(k) and SAH is
+    exact; with beta = 0.05 every 'no' is still proved, so the SAH set contains the
+    exact one (recall 1) and lies inside the set that passes the L_u^k test."""
+    w, A, ks = _sah_case(42)
+    n_prime = 30
+    exact, _ = O.rkmips("f32", w.items, None, w.users, None, w.queries, None, ks, 20)
+    full = O.sah_rkmips("f32", w.items, None, w.users, None, w.queries, None, ks, 20, n_prime, 0.5, 1.0, A)
+    for a, b in zip(full, exact):
+        assert np.array_equal(a, b)
+    part = O.sah_rkmips("f32", w.items, None, w.users, None, w.queries, None, ks, 20, n_prime, 0.5, 0.05, A)
+    n2, order = O.item_order("f32", w.items, None)
+    lam_p = O.lambda_table("f32", w.items[order[:n_prime]], None, w.users, None, 20)
+    surv = O.member("f32", w.users, None, w.queries, None, ks, lam_p)
+    extra = rejected = 0
+    for qi, (a, b) in enumerate(zip(part, exact)):
+        assert set(b.tolist()) <= set(a.tolist())
+        s = set(np.flatnonzero(surv[qi]).tolist())
+        assert set(a.tolist()) <= s
+        extra += len(a) - len(b)
+        rejected += len(s) - len(a)
+    assert rejected > 0   # Alg. 2 said "no" somewhere: the probe path ran
