@@ -90,11 +90,29 @@ typedef struct {
     float b;             /* interval ratio of the norm partitions (Alg. 1), 0 < b < 1  */
     float probe_frac;    /* beta: fraction of a partition probed by SimHash (Alg. 2)   */
     uint64_t seed;       /* seed of the Cone-Tree pivots (Alg. 3)                       */
-    int32_t mode;        /* 0 = exact (the only mode)                                   */
+    int32_t mode;        /* RKMIPS_MODE_EXACT or RKMIPS_MODE_SAH                        */
     int32_t flags;       /* RKMIPS_FLAG_* defaults for every query of this index        */
+    int32_t sah_items;   /* RKMIPS_MODE_SAH: |P'|, the items of largest norm whose exact
+                            k_max-MIPS gives the lower-bound arrays L_u (Alg. 4); the
+                            SA-ALSH index covers the other n - |P'|.  1 <= |P'| < n;
+                            0 takes min(2 k_max, n - 1).  Ignored in exact mode.       */
 } rkmips_params;
 
-/* Defaults: k_max 50, N0 64, K 128, s 14, b 0.5, beta 0.1, seed 221112751. */
+/* Query semantics of an index (rkmips_params.mode).
+ *   EXACT: lambda_u is the exact k_max-MIPS over all of P; every answer set is the
+ *          Definition 1 set (canonical FP64 scores).
+ *   SAH:   the paper's approximate method.  L_u comes from P' only (Alg. 4) and the
+ *          Alg. 5 decisions follow: s(u,q) < L_u^k -> no; s(u,q) >= ||u|| ||p_k||
+ *          (p_k the k-th item in norm order, tested as s >= 0 and s^2 >= n2(u) n2(p_k)
+ *          in FP64) -> yes; otherwise Alg. 2 over the SA-ALSH partitions of P \ P',
+ *          its candidate set starting from u's scores on P' (phi = L_u^k).  Every "no"
+ *          is proved, so each set contains the exact one; Alg. 2's "yes" may be wrong
+ *          (false positives).  All scores are canonical FP64, so the sets do not
+ *          depend on scheduling.  RKMIPS_FLAG_SAALSH_FILTER has no effect here. */
+enum { RKMIPS_MODE_EXACT = 0, RKMIPS_MODE_SAH = 1 };
+
+/* Defaults: k_max 50, N0 64, K 128, s 14, b 0.5, beta 0.1, seed 221112751, exact mode,
+ * sah_items 0. */
 void rkmips_default_params(rkmips_params *p);
 
 /*
@@ -184,6 +202,8 @@ typedef struct {
                                     (RKMIPS_BF16 for split FP32 data)                    */
     int32_t mma_terms;           /* products per stored coordinate (3 when split)       */
     double err_fast;             /* error bound of the fast scores / (||u|| ||p||)       */
+    int32_t mode;                /* RKMIPS_MODE_*                                        */
+    int32_t lambda_items;        /* items the lambda table covers: n, or |P'| (SAH)      */
 } rkmips_index_info;
 
 rkmips_status rkmips_get_info(const rkmips_index *idx, rkmips_index_info *out);

@@ -130,7 +130,8 @@ static void validate_params(const rkmips_params& p)
     if (p.topk_slack < 0 || p.topk_slack > 256) fail(RKMIPS_EINVAL, "topk_slack must be in [0, 256]");
     if (!(p.b > 0.f && p.b < 1.f)) fail(RKMIPS_EINVAL, "b must be in (0, 1)");
     if (!(p.probe_frac > 0.f && p.probe_frac <= 1.f)) fail(RKMIPS_EINVAL, "probe_frac must be in (0, 1]");
-    if (p.mode != 0) fail(RKMIPS_EINVAL, "mode must be 0 (exact)");
+    if (p.mode != RKMIPS_MODE_EXACT && p.mode != RKMIPS_MODE_SAH) fail(RKMIPS_EINVAL, "mode must be RKMIPS_MODE_EXACT or RKMIPS_MODE_SAH");
+    if (p.sah_items < 0) fail(RKMIPS_EINVAL, "sah_items must be >= 0");
 }
 
 // Compute-unit count of a device (cached: the attribute query is not free).
@@ -179,8 +180,8 @@ static void choose_topk(Index& x)
     // target items of the whole set beat (the (2 TK_T)-th best of the sample scaled up),
     // so the main pass appends about target candidates per user and rarely compacts.
     const int64_t target = 4 * (int64_t)C;
-    int64_t ns = (2 * TK_T * x.n + target - 1) / target;
-    x.ns = (x.n >= 2048 && 4 * ns <= x.n) ? ns : 0;
+    int64_t ns = (2 * TK_T * x.n_lam + target - 1) / target;
+    x.ns = (x.n_lam >= 2048 && 4 * ns <= x.n_lam) ? ns : 0;
     int gpl = 2;
     if (x.ns > 0)
         while (gpl * 64 < 2 * target && gpl < 16) gpl *= 2;
@@ -196,7 +197,7 @@ static void choose_topk(Index& x)
     // segment count is the one that fills its last round best (fewer on near ties).
     const int cus = x.num_cus;
     const int64_t slots = (int64_t)cus * topk_resident_blocks(topk_dtype(x), topk_ld(x), gpl * 64);
-    int nmax = (int)std::min<int64_t>(std::max<int64_t>(1, x.n / 1024), std::max(1, 2048 / (gpl * 64)));
+    int nmax = (int)std::min<int64_t>(std::max<int64_t>(1, x.n_lam / 1024), std::max(1, 2048 / (gpl * 64)));
     while (nmax > 1 && (double)x.m * nmax * gpl * 64 * 8 > 24e9) nmax--;
     int nmain = 1;
     double best = 0.0;
@@ -208,9 +209,9 @@ static void choose_topk(Index& x)
             nmain = nm;
         }
     }
-    int64_t seg_len = (x.n + nmain - 1) / nmain;
+    int64_t seg_len = (x.n_lam + nmain - 1) / nmain;
     seg_len = std::max<int64_t>(64, (seg_len + 63) / 64 * 64);
-    nmain = (int)((x.n + seg_len - 1) / seg_len);
+    nmain = (int)((x.n_lam + seg_len - 1) / seg_len);
     x.nseg = nmain;
     x.seg_len = seg_len;
     x.G = gpl * 64;
@@ -247,20 +248,20 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
     const void* mu = users_o.p;
     const int tdt = topk_dtype(x), tld = topk_ld(x);
     if (x.mma_dtype != x.dtype) {
-        L.items3.alloc(sizeof(uint16_t) * (size_t)x.n * tld);
+        L.items3.alloc(sizeof(uint16_t) * (size_t)x.n_lam * tld);
         L.users3.alloc(sizeof(uint16_t) * (size_t)m * tld);
         if (tdt == DT_SPLIT) {
-            launch_split_bf16((const float*)x.items.p, x.n, x.ld, L.items3.u16(), 2, s);
+            launch_split_bf16((const float*)x.items.p, x.n_lam, x.ld, L.items3.u16(), 2, s);
             launch_split_bf16((const float*)users_o.p, m, x.ld, L.users3.u16(), 2, s);
         } else {
-            launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n, x.ld, L.items3.u16(), 0, s);
+            launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n_lam, x.ld, L.items3.u16(), 0, s);
             launch_mma_operand(x.mma_dtype, x.dtype, users_o.p, m, x.ld, L.users3.u16(), 1, s);
         }
         mi = L.items3.p;
         mu = L.users3.p;
     }
     TopkArgs ta{};
-    ta.items = mi; ta.item_scales = x.item_scales.f(); ta.n = x.n;
+    ta.items = mi; ta.item_scales = x.item_scales.f(); ta.n = x.n_lam;
     ta.users = mu; ta.user_scales = user_scales_o; ta.m = m;
     ta.d = x.d; ta.ld = tld; ta.nseg_total = x.nseg; ta.C = x.C; ta.G = x.G;
     ta.buf = (uint2*)L.buf.p; ta.cnt = L.cnt.i(); ta.tau = L.tau.f();
@@ -274,7 +275,7 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
     }
     HIPC(hipEventRecord(L.ev.ev[3], s));
     TopkArgs a1 = ta;
-    a1.v0 = 0; a1.v1 = x.n; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
+    a1.v0 = 0; a1.v1 = x.n_lam; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
     a1.theta_init = x.ns > 0 ? L.theta.f() : nullptr;
     a1.theta_stride = 1;
     launch_topk(tdt, a1, s);
@@ -286,7 +287,7 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
 {
     const int64_t m = x.m;
     RefineArgs ra{};
-    ra.items = x.items.p; ra.item_scales = x.item_scales.f(); ra.n = x.n;
+    ra.items = x.items.p; ra.item_scales = x.item_scales.f(); ra.n = x.n_lam;
     ra.users = users_o.p; ra.user_scales = user_scales_o; ra.m = m;
     ra.d = x.d; ra.ld = x.ld; ra.nseg = x.nseg; ra.C = x.C; ra.G = x.G; ra.k_max = x.prm.k_max;
     ra.buf = (const uint2*)L.buf.p; ra.cnt = L.cnt.i(); ra.tau = L.tau.f();
@@ -308,9 +309,9 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
     {
         // rows whose certificate failed: full FP64 rescoring (the count stays on the
         // device; with none the fallback workgroups exit at once)
-        const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(256e6 / (8.0 * (double)x.n))));
+        const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(256e6 / (8.0 * (double)x.n_lam))));
         DevBuf scratch;
-        scratch.alloc(sizeof(double) * (size_t)rows * x.n);
+        scratch.alloc(sizeof(double) * (size_t)rows * x.n_lam);
         launch_fallback(x.dtype, ra, scratch.d(), rows, s);
     }
     HIPC(hipEventRecord(L.ev.ev[2], s));
@@ -676,6 +677,16 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
         validate_params(prm);
         std::unique_ptr<Index> x(new Index());
         x->n = n; x->m = m; x->d = d; x->dtype = dtype; x->prm = prm;
+        x->n_lam = n;
+        if (prm.mode == RKMIPS_MODE_SAH) {
+            // Alg. 4: P' = the first O(k_max) items in norm order; the SA-ALSH index
+            // needs at least one item outside it
+            if (n < 2) fail(RKMIPS_EINVAL, "SAH mode needs n >= 2");
+            const int64_t np = prm.sah_items > 0 ? prm.sah_items : std::min<int64_t>(2 * (int64_t)prm.k_max, n - 1);
+            if (np >= n) fail(RKMIPS_EINVAL, "sah_items must be below n");
+            x->n_lam = np;
+            x->prm.sah_items = (int32_t)np;
+        }
         x->ld = padded_dim(d, dtype);
         // FP32 storage is scored on the BF16 matrix cores as split products where the
         // tripled rows fit the kernels (ld <= 64), unless the caller asks for FP32 MFMA.
@@ -713,6 +724,8 @@ rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
         o->mma_dtype = (x.mma_dtype == DT_FP8B || x.mma_dtype == DT_SPLIT) ? RKMIPS_BF16 : x.mma_dtype;
         o->mma_terms = x.mma_dtype == DT_SPLIT ? 3 : 1;
         o->err_fast = x.err_fast;
+        o->mode = x.prm.mode;
+        o->lambda_items = (int32_t)x.n_lam;
         o->device_bytes = x.device_bytes();
     });
 }

@@ -63,6 +63,7 @@ struct Index {
     double err_fast = 0;             // error bound of its fast scores, relative to ||u|| ||p||
     int num_cus = 256;
     int64_t n = 0, m = 0;
+    int64_t n_lam = 0;   // items the lambda table covers: n, or |P'| (the first in norm order) in SAH mode
     int d = 0, ld = 0, dtype = 0;
     rkmips_params prm{};
 

@@ -144,9 +144,21 @@ struct SaQueryArgs {
     float beta;
     const unsigned long long* pairs; int64_t npairs;   // (query << 32) | leaf user
     const int* qk;                                     // k per query
-    double* phi; int* answer;                          // per pair
+    double* phi; int* answer;                          // per pair (may be null)
+    // count on the device (null: npairs), read once per workgroup; npairs is its cap
+    const unsigned long long* npairs_dev;
+    // SAH (Alg. 5): u's scores on P' start the candidate set -- the first min(k, n_init)
+    // entries of its lambda row (lam64 [k_max x m] by original user, null: none)
+    const double* lam64; const uint32_t* perm; int64_t m; int64_t n_init;
+    // SAH: a "yes" goes straight to the answers (bits, else the pool as
+    // (caller query << 32) | original user); a "no" counts in *rejects
+    uint32_t* bitmap; int64_t bm_words;
+    unsigned long long* pool; unsigned long long* pool_count; int64_t pool_cap;
+    const uint32_t* qorig;
+    unsigned long long* rejects;
 };
-// Alg. 2 for each pair; scratch: grid x scratch_stride doubles (>= ceil(beta n) + t).
+// Alg. 2 for each pair; scratch: grid x scratch_stride doubles
+// (>= ceil(beta n) + t + min(k_max, n_init)).
 void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_stride, int grid, hipStream_t s);
 
 // ---------------------------------------------------------------- query
@@ -182,6 +194,13 @@ struct QueryArgs {
     uint32_t* bitmap; int64_t bm_words;
     unsigned long long* amb; unsigned long long* amb_count; int64_t amb_cap;
     unsigned long long* stats;                       // [8]
+    // SAH mode (Alg. 5): the inner-product test hands every pair it does not reject to
+    // the FP64 recheck, which answers yes when s >= ||u|| ||p_k|| and otherwise lists
+    // the pair (same key as amb) for Alg. 2
+    int sah;
+    const double* item_n2; int64_t n_items;          // sorted canonical squared norms
+    const double* user_n2;                           // leaf order
+    unsigned long long* sah_pairs; unsigned long long* sah_count;   // capacity amb_cap
 };
 void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, int ld,
                   float* qnorm, int* bad, hipStream_t s);

@@ -347,6 +347,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
             }
         }
 
+        if (a.sah) {   // SAH: every pair the test does not reject goes on to the recheck
+            n_amb += __popc(yes);
+            amb |= yes;
+            yes = 0u;
+        }
         if (a.bitmap) {   // yes answers as bits (workgroup-uniform); the pool takes close calls only
 #pragma unroll
             for (int r = 0; r < 16; r++)
@@ -609,6 +614,17 @@ __global__ void k_recheck(QueryArgs a, int64_t namb, const unsigned long long* n
         const double s = canon_dot2<DT>(a.users, u, a.ld, su, a.queries, q, a.ld, sq, a.d);
         if (s >= a.lam64[(int64_t)(k - 1) * a.m + a.perm[u]]) {
             const uint32_t ou = a.perm[u];
+            if (a.sah) {
+                // Alg. 5: yes when s(u,q) >= ||u|| ||p_k|| (as s >= 0, s^2 >= n2(u) n2(p_k),
+                // each product rounded once: fma with a zero addend, never fused with
+                // anything else), else Alg. 2 decides
+                const double pk2 = k <= a.n_items ? a.item_n2[k - 1] : 0.0;
+                if (!(s >= 0.0 && __fma_rn(s, s, 0.0) >= __fma_rn(a.user_n2[u], pk2, 0.0))) {
+                    const unsigned long long pos = atomicAdd(a.sah_count, 1ull);
+                    if ((int64_t)pos < a.amb_cap) a.sah_pairs[pos] = key;
+                    continue;
+                }
+            }
             if (a.bitmap) {
                 atomicOr(&a.bitmap[(int64_t)a.qorig[q] * a.bm_words + (ou >> 5)], 1u << (ou & 31u));
             } else {

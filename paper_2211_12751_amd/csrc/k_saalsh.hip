@@ -22,11 +22,11 @@ namespace rk {
 // starts at the first unassigned position s (M_j^2 = n2[s]) and ends at the first
 // position whose n2 <= (b*b) M_j^2 (n2 is non-increasing).  A zero M_j closes the list
 // with one last partition of the remaining (zero-norm) items.
-__global__ void k_partitions(const double* n2, int64_t n, float b, int64_t* part_start, int* num_parts)
+__global__ void k_partitions(const double* n2, int64_t n0, int64_t n, float b, int64_t* part_start, int* num_parts)
 {
     const int l = lane_id();
     const double bb = (double)b * (double)b;
-    int64_t start = 0;
+    int64_t start = n0;
     int t = 0;
     while (start < n) {
         if (l == 0) part_start[t] = start;
@@ -174,6 +174,7 @@ __global__ void k_radius(const void* X, const float* scales, const int64_t* part
         const double v = (double)elem_f32<DT>(X, p * ld + i) * sc - c[i];
         r2 = __fma_rn(v, v, r2);
     }
+    if (p < part_start[0]) r2 = 0.0;   // SAH: P' items belong to no partition
     if (in) r2out[p] = r2;
     // partitions are contiguous ranges: reduce inside the wave, one atomic per partition
     uint64_t rem = ballot64(true);
@@ -338,7 +339,9 @@ void start_partitions(Index& x, int* h_num_parts, hipStream_t s)
 {
     x.part_start.alloc(sizeof(int64_t) * (x.n + 2));
     x.num_parts.alloc(sizeof(int));
-    hipLaunchKernelGGL(k_partitions, dim3(1), dim3(64), 0, s, x.item_n2.d(), x.n, x.prm.b, x.part_start.i64(),
+    // exact mode: all of P; SAH mode: P minus P' (the first n_lam positions), Alg. 4
+    const int64_t n0 = x.prm.mode == RKMIPS_MODE_SAH ? x.n_lam : 0;
+    hipLaunchKernelGGL(k_partitions, dim3(1), dim3(64), 0, s, x.item_n2.d(), n0, x.n, x.prm.b, x.part_start.i64(),
                        x.num_parts.i());
     HIPC(hipGetLastError());
     HIPC(hipMemcpyAsync(h_num_parts, x.num_parts.p, sizeof(int), hipMemcpyDeviceToHost, s));

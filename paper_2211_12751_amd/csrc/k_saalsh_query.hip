@@ -15,7 +15,8 @@
 //
 // In exact mode the stage only rejects: a "no" is proved (phi is the k-th largest
 // over a subset of the items, hence <= lambda_u^(k)), a "yes" is left to the FP64
-// recheck.
+// recheck.  In SAH mode (Alg. 5) the partitions cover P minus P', the candidate set
+// starts from u's scores on P' (phi = L_u^k), and the answer is final.
 #include <algorithm>
 #include <cmath>
 
@@ -111,7 +112,12 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
     __shared__ int ccount;
     const int tid = threadIdx.x;
     const int W = a.K / 32;
-    for (int64_t pi = blockIdx.x; pi < a.npairs; pi += gridDim.x) {
+    int64_t npairs = a.npairs;
+    if (a.npairs_dev) {
+        const int64_t c = (int64_t)*a.npairs_dev;
+        npairs = c < npairs ? c : npairs;
+    }
+    for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
         const uint64_t key = a.pairs[pi];
         const int64_t q = (int64_t)(key >> 32), u = (int64_t)(key & 0xffffffffull);
         const int k = a.qk[q];
@@ -124,7 +130,16 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
         for (int w = 0; w < W; w++) ucode[w] = a.user_codes[u * W + w];
         double phi = -__builtin_inf();
         int64_t ncand = 0;
-        if (tid == 0) ccount = 0;
+        int ninit = 0;
+        if (a.lam64) {
+            // SAH: the candidate set starts as P'; its k-th largest score is the k-th of
+            // u's k best scores on P', i.e. lambda row entries 1..k
+            const uint32_t ou = a.perm[u];
+            ninit = (int)((int64_t)k < a.n_init ? (int64_t)k : a.n_init);
+            for (int i = tid; i < ninit; i += SQ_T) cand[i] = a.lam64[(int64_t)i * a.m + ou];
+            if (ninit >= k) phi = a.lam64[(int64_t)(k - 1) * a.m + ou];
+        }
+        if (tid == 0) ccount = ninit;
         __syncthreads();
         int ans = 1;
         for (int j = 0; j < a.t; j++) {
@@ -192,8 +207,22 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
             if (suq < phi) { ans = 0; break; }
         }
         if (tid == 0) {
-            a.phi[pi] = phi;
-            a.answer[pi] = ans;
+            if (a.phi) a.phi[pi] = phi;
+            if (a.answer) a.answer[pi] = ans;
+            if (a.qorig) {   // SAH: the decision is the answer
+                if (ans) {
+                    const uint32_t ou = a.perm[u];
+                    const uint32_t qo = a.qorig[q];
+                    if (a.bitmap) {
+                        atomicOr(&a.bitmap[(int64_t)qo * a.bm_words + (ou >> 5)], 1u << (ou & 31u));
+                    } else {
+                        const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
+                        if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)qo << 32) | ou;
+                    }
+                } else {
+                    atomicAdd(a.rejects, 1ull);
+                }
+            }
         }
         __syncthreads();
     }

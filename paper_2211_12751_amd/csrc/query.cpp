@@ -96,6 +96,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
     const int64_t ac = std::max<int64_t>(amb_cap_req, 1 << 12);
     if (ac > amb_cap) {
         amb.alloc(sizeof(uint64_t) * ac);
+        if (x.prm.mode == RKMIPS_MODE_SAH) sah_pairs.alloc(sizeof(uint64_t) * ac);
         amb_cap = ac;
     }
     if (!ctr.p) {
@@ -165,6 +166,9 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.amb = (unsigned long long*)w.amb.p; a.amb_count = c + 1; a.amb_cap = w.amb_cap;
     a.bad = (int*)(c + 2);
     a.stats = c + 8;
+    a.sah = x.prm.mode == RKMIPS_MODE_SAH;
+    a.item_n2 = x.item_n2.d(); a.n_items = x.n; a.user_n2 = x.user_n2.d();
+    a.sah_pairs = (unsigned long long*)w.sah_pairs.p; a.sah_count = c + 6;
     return a;
 }
 
@@ -176,7 +180,8 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
 {
     HIPC(hipMemsetAsync(w.ctr.p, 0, sizeof(unsigned long long) * 16, s));
     const int fl = flags | x.prm.flags;
-    w.device_tail = nq > 0 && !((fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH));
+    const bool sah = x.prm.mode == RKMIPS_MODE_SAH;
+    w.device_tail = nq > 0 && (sah || !((fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH)));
     w.bm_mode = w.device_tail && w.bitmap.p != nullptr && !(fl & RKMIPS_FLAG_POOL_LISTS);
     if (w.bm_mode) HIPC(hipMemsetAsync(w.bitmap.p, 0, sizeof(uint32_t) * (size_t)(nq * w.bm_words), s));
     if (nq > 0) {
@@ -197,6 +202,7 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
             // host checks them (bad values, overflow) once the offsets are back
             unsigned long long* c = (unsigned long long*)w.ctr.p;
             launch_recheck_device(a, s);
+            if (sah) run_sah(x, w, a, s);
             if (w.bm_mode)
                 launch_bitmap_lists(w.bitmap.u32(), w.bm_words, nq, w.qcnt.i(), w.offsets.i64(), (long long*)(c + 13),
                                     (int32_t*)w.ids.p, w.pool_cap, s);
@@ -271,7 +277,8 @@ SaQueryArgs make_sa_args(const Index& x, const void* queries, const float* qscal
 
 int64_t saalsh_scratch_stride(const Index& x, float beta)
 {
-    return (int64_t)std::ceil((double)beta * (double)x.n) + x.t + 1;
+    // probed candidates (at most ceil(beta |S_j|) per partition) plus SAH's P' scores
+    return (int64_t)std::ceil((double)beta * (double)x.n) + x.t + 1 + x.prm.k_max;
 }
 
 void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs, hipStream_t s)
@@ -285,6 +292,24 @@ void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs
     }
     SaQueryArgs sa = make_sa_args(x, a.queries, a.query_scales, a.qk, a.amb, npairs, x.prm.probe_frac, w.sa_phi.d(),
                                   w.sa_answer.i());
+    launch_saalsh_query(sa, w.sa_scratch.d(), stride, grid, s);
+}
+
+// SAH mode (Alg. 5): Alg. 2 for the pairs the recheck left undecided, their count read
+// on the device; a "yes" goes to the answers directly.
+void run_sah(const Index& x, Workspace& w, const QueryArgs& a, hipStream_t s)
+{
+    const int grid = (int)std::min<int64_t>(w.amb_cap, 1024);
+    const int64_t stride = saalsh_scratch_stride(x, x.prm.probe_frac);
+    if ((int64_t)w.sa_scratch.bytes < (int64_t)sizeof(double) * grid * stride) w.sa_scratch.alloc(sizeof(double) * grid * stride);
+    SaQueryArgs sa = make_sa_args(x, a.queries, a.query_scales, a.qk, a.sah_pairs, w.amb_cap, x.prm.probe_frac,
+                                  nullptr, nullptr);
+    sa.npairs_dev = a.sah_count;
+    sa.lam64 = x.lam64.d(); sa.perm = x.user_perm.u32(); sa.m = x.m; sa.n_init = x.n_lam;
+    sa.bitmap = a.bitmap; sa.bm_words = a.bm_words;
+    sa.pool = a.pool; sa.pool_count = a.pool_count; sa.pool_cap = a.pool_cap;
+    sa.qorig = a.qorig;
+    sa.rejects = a.stats + 4;
     launch_saalsh_query(sa, w.sa_scratch.d(), stride, grid, s);
 }
 
@@ -315,6 +340,10 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     st.pairs_vector_pruned = (int64_t)hc[9];
     st.pairs_scored = (int64_t)hc[10];
     st.pairs_rechecked = namb;
+    if (x.prm.mode == RKMIPS_MODE_SAH) {
+        st.saalsh_checked = (int64_t)hc[6];
+        st.saalsh_rejects = (int64_t)hc[12];
+    }
     const int* reject = nullptr;
     if (!w.device_tail) {
         QueryArgs a = make_query_args(x, w, nq, flags);

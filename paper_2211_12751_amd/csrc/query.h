@@ -38,6 +38,7 @@ struct Workspace {
     DevBuf qsplit;                          // matrix-core query rows (split FP32 or widened FP8)
     DevBuf qcnt, ids2;                      // per-query counts, scatter target of the lists
     DevBuf sa_scratch, sa_answer, sa_phi;   // SA-ALSH stage
+    DevBuf sah_pairs;                       // SAH mode: pairs left to Alg. 2 (capacity amb_cap)
     PinBuf h_offsets, h_ids, h_ctr;
     std::vector<Group> groups;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_ctr = nullptr;
@@ -48,6 +49,7 @@ struct Workspace {
 };
 
 void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs, hipStream_t s);
+void run_sah(const Index& x, Workspace& w, const QueryArgs& a, hipStream_t s);
 SaQueryArgs make_sa_args(const Index& x, const void* queries, const float* qscales, const int* qk,
                          const unsigned long long* pairs, int64_t npairs, float beta, double* phi, int* answer);
 int64_t saalsh_scratch_stride(const Index& x, float beta);

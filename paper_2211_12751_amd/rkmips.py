@@ -25,6 +25,7 @@ FLAG_NO_BOUNDS, FLAG_FORCE_RECHECK, FLAG_NO_SAALSH, FLAG_NO_CERT, FLAG_NO_VECTOR
 FLAG_SAALSH_FILTER = 32
 FLAG_F32_MATRIX = 64
 FLAG_POOL_LISTS = 128
+MODE_EXACT, MODE_SAH = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "EBUSY"}
 
 
@@ -37,7 +38,8 @@ class RkmipsError(RuntimeError):
 class rkmips_params(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("leaf_size", C.c_int32), ("num_hash", C.c_int32),
                 ("topk_slack", C.c_int32), ("b", C.c_float), ("probe_frac", C.c_float),
-                ("seed", C.c_uint64), ("mode", C.c_int32), ("flags", C.c_int32)]
+                ("seed", C.c_uint64), ("mode", C.c_int32), ("flags", C.c_int32),
+                ("sah_items", C.c_int32)]
 
 
 class rkmips_query_stats(C.Structure):
@@ -56,7 +58,8 @@ class rkmips_index_info(C.Structure):
                 ("ms_lambda", C.c_double), ("ms_refine", C.c_double), ("ms_saalsh", C.c_double),
                 ("ms_cone", C.c_double), ("ms_total", C.c_double), ("device_bytes", C.c_int64),
                 ("ms_seed", C.c_double), ("ms_topk", C.c_double), ("mma_dtype", C.c_int32),
-                ("mma_terms", C.c_int32), ("err_fast", C.c_double)]
+                ("mma_terms", C.c_int32), ("err_fast", C.c_double), ("mode", C.c_int32),
+                ("lambda_items", C.c_int32)]
 
 
 class rkmips_serve_params(C.Structure):

@@ -53,11 +53,17 @@ def test_argument_errors_before_device_work(R):
                                        C.byref(p), None, C.byref(h))
         assert st == -1, bad
     for field, val in (("k_max", 0), ("k_max", 300), ("leaf_size", 65), ("num_hash", 48), ("b", 1.0),
-                       ("probe_frac", 0.0), ("mode", 1)):
+                       ("probe_frac", 0.0), ("mode", 2), ("sah_items", -1)):
         q = R.rkmips_default_params()
         setattr(q, field, val)
         st = R._lib.rkmips_build_index(dummy, None, 10, dummy, None, 10, 8, 0, None, C.byref(q), None, C.byref(h))
         assert st == -1, field
+    # SAH mode: P' must leave at least one item for the SA-ALSH index
+    for n_prime in (10, 11):
+        q = R.rkmips_default_params()
+        q.mode, q.sah_items = R.MODE_SAH, n_prime
+        st = R._lib.rkmips_build_index(dummy, None, 10, dummy, None, 10, 8, 0, None, C.byref(q), None, C.byref(h))
+        assert st == -1 and "sah_items" in R.rkmips_last_error()
     # FP8 without scales, scales without FP8
     st = R._lib.rkmips_build_index(dummy, None, 10, dummy, None, 10, 8, 2, None, C.byref(p), None, C.byref(h))
     assert st == -1
