@@ -144,22 +144,28 @@ struct SaQueryArgs {
     float beta;
     const unsigned long long* pairs; int64_t npairs;   // (query << 32) | leaf user
     const int* qk;                                     // k per query
-    double* phi; int* answer;                          // per pair (may be null)
-    // count on the device (null: npairs), read once per workgroup; npairs is its cap
+    double* phi; int* answer;                          // per pair (k_saalsh_query)
+    // SAH (launch_sah): the pair count on the device (npairs is its cap); u's scores on
+    // P' start the candidate set -- the first entries of its lambda row (lam64
+    // [k_max x m] by original user); a "yes" goes straight to the answers (bits, else
+    // the pool as (caller query << 32) | original user), a "no" counts in *rejects
     const unsigned long long* npairs_dev;
-    // SAH (Alg. 5): u's scores on P' start the candidate set -- the first min(k, n_init)
-    // entries of its lambda row (lam64 [k_max x m] by original user, null: none)
     const double* lam64; const uint32_t* perm; int64_t m; int64_t n_init;
-    // SAH: a "yes" goes straight to the answers (bits, else the pool as
-    // (caller query << 32) | original user); a "no" counts in *rejects
     uint32_t* bitmap; int64_t bm_words;
     unsigned long long* pool; unsigned long long* pool_count; int64_t pool_cap;
     const uint32_t* qorig;
     unsigned long long* rejects;
 };
-// Alg. 2 for each pair; scratch: grid x scratch_stride doubles
-// (>= ceil(beta n) + t + min(k_max, n_init)).
+// Alg. 2 for each pair; scratch: grid x scratch_stride doubles (>= ceil(beta n) + t).
 void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_stride, int grid, hipStream_t s);
+// SAH (Alg. 5) for the listed pairs: slots for the users flagged in need[m] (slot,
+// user_of_slot: int [m]; *nslots zeroed by the caller), per-user tables of kstar
+// (>= every k of the pairs) scores after each partition, chunk slots at a time (tab:
+// chunk x (t + 1) x kstar doubles), then the per-pair decisions; score[i]: s(u,q) of
+// pair i.  scratch: grid x scratch_stride doubles (>= ceil(beta n) + t + 1 + kstar).
+void launch_sah(const SaQueryArgs& a, const unsigned char* need, int* slot, int* user_of_slot, int* nslots,
+                const double* score, int kstar, double* tab, int64_t chunk, double* scratch,
+                int64_t scratch_stride, int grid, hipStream_t s);
 
 // ---------------------------------------------------------------- query
 struct QueryArgs {
@@ -201,6 +207,8 @@ struct QueryArgs {
     const double* item_n2; int64_t n_items;          // sorted canonical squared norms
     const double* user_n2;                           // leaf order
     unsigned long long* sah_pairs; unsigned long long* sah_count;   // capacity amb_cap
+    double* sah_score;                               // s(u,q) of each listed pair
+    unsigned char* sah_need;                         // [m] leaf order: u has a listed pair
 };
 void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, int ld,
                   float* qnorm, int* bad, hipStream_t s);

@@ -621,7 +621,11 @@ __global__ void k_recheck(QueryArgs a, int64_t namb, const unsigned long long* n
                 const double pk2 = k <= a.n_items ? a.item_n2[k - 1] : 0.0;
                 if (!(s >= 0.0 && __fma_rn(s, s, 0.0) >= __fma_rn(a.user_n2[u], pk2, 0.0))) {
                     const unsigned long long pos = atomicAdd(a.sah_count, 1ull);
-                    if ((int64_t)pos < a.amb_cap) a.sah_pairs[pos] = key;
+                    if ((int64_t)pos < a.amb_cap) {
+                        a.sah_pairs[pos] = key;
+                        a.sah_score[pos] = s;
+                    }
+                    a.sah_need[u] = 1;
                     continue;
                 }
             }

@@ -15,8 +15,9 @@
 //
 // In exact mode the stage only rejects: a "no" is proved (phi is the k-th largest
 // over a subset of the items, hence <= lambda_u^(k)), a "yes" is left to the FP64
-// recheck.  In SAH mode (Alg. 5) the partitions cover P minus P', the candidate set
-// starts from u's scores on P' (phi = L_u^k), and the answer is final.
+// recheck.  In SAH mode (Alg. 5; k_sah_user, k_sah_decide below) the partitions cover
+// P minus P', the candidate set starts from u's scores on P' (phi = L_u^k), and the
+// answer is final.
 #include <algorithm>
 #include <cmath>
 
@@ -103,6 +104,73 @@ __device__ double block_kth(const double* vals, int64_t cnt, int k, int* hist, i
     return ord_f64(prefix);
 }
 
+// SimHash probe of partition [s0, s1) for user u (Alg. 2): the ceil(beta sz) items
+// with the most equal code bits (equal counts: earlier position first) are scored and
+// their scores appended to cand at *ccount.  Called by the whole workgroup; ends with a
+// barrier, after which *ccount holds the new count.
+template <int DT>
+__device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const uint32_t* ucode, int W,
+                                int64_t s0, int64_t s1, double* cand, int* hist, int* sh, int* wsum, int* ccount)
+{
+    const int tid = threadIdx.x;
+    const int64_t sz = s1 - s0;
+    int64_t take = (int64_t)ceil((double)a.beta * (double)sz);
+    if (take > sz) take = sz;
+    // histogram of collision counts over the partition
+    for (int b = tid; b <= a.K; b += SQ_T) hist[b] = 0;
+    __syncthreads();
+    for (int64_t p = s0 + tid; p < s1; p += SQ_T) atomicAdd(&hist[collisions(a.item_codes, p, ucode, W, a.K)], 1);
+    __syncthreads();
+    if (tid == 0) {   // cut count c*: #(count > c*) < take <= #(count >= c*)
+        int64_t above = 0;
+        int cut = 0;
+        int64_t need_eq = 0;
+        for (int c = a.K; c >= 0; c--) {
+            if (above + hist[c] >= take) { cut = c; need_eq = take - above; break; }
+            above += hist[c];
+        }
+        sh[0] = cut;
+        sh[1] = (int)need_eq;
+    }
+    __syncthreads();
+    const int cut = sh[0];
+    const int need_eq = sh[1];
+    // ordered selection: candidates are the items above the cut and the first need_eq
+    // at it (position order).  Each wave owns a contiguous quarter of the partition: it
+    // counts its ties, one block-level prefix orders the quarters, then every wave takes
+    // its items with wave-local ballots.
+    const int wv = tid >> 6, ln = tid & 63;
+    const int64_t qlen = (sz + SQ_T / 64 - 1) / (SQ_T / 64);
+    const int64_t w0 = s0 + wv * qlen;
+    const int64_t w1 = w0 + qlen < s1 ? w0 + qlen : s1;
+    int my_eq = 0;
+    for (int64_t base = w0; base < w1; base += 64) {
+        const int64_t p = base + ln;
+        const bool iseq = p < w1 && collisions(a.item_codes, p, ucode, W, a.K) == cut;
+        my_eq += __popcll(ballot64(iseq));
+    }
+    if (ln == 0) wsum[wv] = my_eq;
+    __syncthreads();
+    int eq_before = 0;
+    for (int w = 0; w < wv; w++) eq_before += wsum[w];
+    for (int64_t base = w0; base < w1; base += 64) {
+        const int64_t p = base + ln;
+        const int c = p < w1 ? collisions(a.item_codes, p, ucode, W, a.K) : -1;
+        const bool iseq = c == cut;
+        const uint64_t eb = ballot64(iseq);
+        const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
+        eq_before += __popcll(eb);
+        const bool take_it = c > cut || (iseq && rank_eq < need_eq);
+        // append candidate scores (order inside the candidate multiset is irrelevant)
+        if (take_it) {
+            const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
+            const double v = sq_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
+            cand[atomicAdd(ccount, 1)] = v;
+        }
+    }
+    __syncthreads();
+}
+
 template <int DT>
 __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* scratch, int64_t scratch_stride)
 {
@@ -112,12 +180,7 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
     __shared__ int ccount;
     const int tid = threadIdx.x;
     const int W = a.K / 32;
-    int64_t npairs = a.npairs;
-    if (a.npairs_dev) {
-        const int64_t c = (int64_t)*a.npairs_dev;
-        npairs = c < npairs ? c : npairs;
-    }
-    for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
+    for (int64_t pi = blockIdx.x; pi < a.npairs; pi += gridDim.x) {
         const uint64_t key = a.pairs[pi];
         const int64_t q = (int64_t)(key >> 32), u = (int64_t)(key & 0xffffffffull);
         const int k = a.qk[q];
@@ -129,103 +192,205 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
         uint32_t ucode[8];
         for (int w = 0; w < W; w++) ucode[w] = a.user_codes[u * W + w];
         double phi = -__builtin_inf();
-        int64_t ncand = 0;
-        int ninit = 0;
-        if (a.lam64) {
-            // SAH: the candidate set starts as P'; its k-th largest score is the k-th of
-            // u's k best scores on P', i.e. lambda row entries 1..k
-            const uint32_t ou = a.perm[u];
-            ninit = (int)((int64_t)k < a.n_init ? (int64_t)k : a.n_init);
-            for (int i = tid; i < ninit; i += SQ_T) cand[i] = a.lam64[(int64_t)i * a.m + ou];
-            if (ninit >= k) phi = a.lam64[(int64_t)(k - 1) * a.m + ou];
-        }
-        if (tid == 0) ccount = ninit;
+        if (tid == 0) ccount = 0;
         __syncthreads();
         int ans = 1;
         for (int j = 0; j < a.t; j++) {
-            const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1], sz = s1 - s0;
+            const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
             const double mu = sqrt(a.item_n2[s0]) * unorm;
             if (phi > mu) { ans = 1; break; }
-            int64_t take = (int64_t)ceil((double)a.beta * (double)sz);
-            if (take > sz) take = sz;
-            // histogram of collision counts over the partition
-            for (int b = tid; b <= a.K; b += SQ_T) hist[b] = 0;
-            __syncthreads();
-            for (int64_t p = s0 + tid; p < s1; p += SQ_T) atomicAdd(&hist[collisions(a.item_codes, p, ucode, W, a.K)], 1);
-            __syncthreads();
-            if (tid == 0) {   // cut count c*: #(count > c*) < take <= #(count >= c*)
-                int64_t above = 0;
-                int cut = 0;
-                int64_t need_eq = 0;
-                for (int c = a.K; c >= 0; c--) {
-                    if (above + hist[c] >= take) { cut = c; need_eq = take - above; break; }
-                    above += hist[c];
-                }
-                sh[0] = cut;
-                sh[1] = (int)need_eq;
-            }
-            __syncthreads();
-            const int cut = sh[0];
-            const int need_eq = sh[1];
-            // ordered selection: candidates are the items above the cut and the first
-            // need_eq at it (position order).  Each wave owns a contiguous quarter of
-            // the partition: it counts its ties, one block-level prefix orders the
-            // quarters, then every wave takes its items with wave-local ballots.
-            const int wv = tid >> 6, ln = tid & 63;
-            const int64_t qlen = (sz + SQ_T / 64 - 1) / (SQ_T / 64);
-            const int64_t w0 = s0 + wv * qlen;
-            const int64_t w1 = w0 + qlen < s1 ? w0 + qlen : s1;
-            int my_eq = 0;
-            for (int64_t base = w0; base < w1; base += 64) {
-                const int64_t p = base + ln;
-                const bool iseq = p < w1 && collisions(a.item_codes, p, ucode, W, a.K) == cut;
-                my_eq += __popcll(ballot64(iseq));
-            }
-            if (ln == 0) wsum[wv] = my_eq;
-            __syncthreads();
-            int eq_before = 0;
-            for (int w = 0; w < wv; w++) eq_before += wsum[w];
-            for (int64_t base = w0; base < w1; base += 64) {
-                const int64_t p = base + ln;
-                const int c = p < w1 ? collisions(a.item_codes, p, ucode, W, a.K) : -1;
-                const bool iseq = c == cut;
-                const uint64_t eb = ballot64(iseq);
-                const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
-                eq_before += __popcll(eb);
-                const bool take_it = c > cut || (iseq && rank_eq < need_eq);
-                // append candidate scores (order inside the candidate multiset is irrelevant)
-                if (take_it) {
-                    const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-                    const double v = sq_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-                    cand[atomicAdd(&ccount, 1)] = v;
-                }
-            }
-            __syncthreads();
-            ncand = ccount;
+            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, hist, sh, wsum, &ccount);
+            const int64_t ncand = ccount;
             __syncthreads();
             phi = ncand >= k ? block_kth(cand, ncand, k, hist, sh) : -__builtin_inf();
             if (suq < phi) { ans = 0; break; }
         }
         if (tid == 0) {
-            if (a.phi) a.phi[pi] = phi;
-            if (a.answer) a.answer[pi] = ans;
-            if (a.qorig) {   // SAH: the decision is the answer
-                if (ans) {
-                    const uint32_t ou = a.perm[u];
-                    const uint32_t qo = a.qorig[q];
-                    if (a.bitmap) {
-                        atomicOr(&a.bitmap[(int64_t)qo * a.bm_words + (ou >> 5)], 1u << (ou & 31u));
-                    } else {
-                        const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
-                        if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)qo << 32) | ou;
-                    }
-                } else {
-                    atomicAdd(a.rejects, 1ull);
-                }
-            }
+            a.phi[pi] = phi;
+            a.answer[pi] = ans;
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------------ SAH: Alg. 2 per user
+// In Alg. 2 the candidate sets, and so phi after each partition, depend on the user and
+// k only; the query enters through s(u,q) in the two tests.  A batch therefore runs the
+// probes once per user that has an undecided pair: row j of the user's table holds the
+// kstar largest candidate scores after j partitions (row 0: the scores on P', i.e. the
+// lambda row), so phi_j = row j entry k - 1 for every k <= kstar.  k_sah_decide then
+// walks each pair through the same tests in the same order as the per-pair kernel
+// above, with identical results.
+
+// Users with an undecided pair (flag set by the recheck) get consecutive slots.
+__global__ void k_sah_slots(const unsigned char* need, int64_t m, int* slot, int* nslots)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = u < m && need[u];
+    const uint64_t bal = ballot64(f);
+    int base = 0;
+    if (lane_id() == 0 && bal) base = atomicAdd(nslots, __popcll(bal));
+    base = __shfl(base, 0);
+    if (f) slot[u] = base + __popcll(bal & lanemask_lt());
+}
+
+__global__ void k_sah_invert(const unsigned char* need, const int* slot, int64_t m, int* user_of_slot)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < m && need[u]) user_of_slot[slot[u]] = (int)u;
+}
+
+// Sorted (descending) kstar largest of vals[0, cnt) into top[0, kstar) (-inf past cnt),
+// by one workgroup; vals then holds the same kstar values (cnt becomes min(cnt, kstar)).
+__device__ void block_top_sorted(double* vals, int64_t cnt, int kstar, double* top, int* hist, int* sh, int* tcount)
+{
+    const int tid = threadIdx.x;
+    int P = 1;
+    while (P < kstar) P <<= 1;
+    for (int i = tid; i < P; i += SQ_T) top[i] = -__builtin_inf();
+    if (tid == 0) *tcount = 0;
+    __syncthreads();
+    if (cnt <= kstar) {
+        for (int64_t i = tid; i < cnt; i += SQ_T) top[i] = vals[i];
+    } else {
+        const double T = block_kth(vals, cnt, kstar, hist, sh);   // ends with a barrier
+        for (int64_t i = tid; i < cnt; i += SQ_T)
+            if (vals[i] > T) top[atomicAdd(tcount, 1)] = vals[i];
+        __syncthreads();
+        const int gt = *tcount;   // < kstar; the rest of the kstar are copies of T
+        for (int i = gt + tid; i < kstar; i += SQ_T) top[i] = T;
+    }
+    __syncthreads();
+    // bitonic sort, descending
+    for (int kk = 2; kk <= P; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += SQ_T) {
+                const int o = i ^ j;
+                if (o > i) {
+                    const bool desc = (i & kk) == 0;
+                    const double x = top[i], y = top[o];
+                    if (desc ? x < y : x > y) {
+                        top[i] = y;
+                        top[o] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    const int keep = (int)(cnt < kstar ? cnt : kstar);
+    for (int i = tid; i < keep; i += SQ_T) vals[i] = top[i];
+    __syncthreads();
+}
+
+// One workgroup per slot in [c0, c0 + chunk): the user's table rows, tab[(slot - c0)
+// (t + 1) kstar ...].  The probes stop once row j's kstar-th score exceeds mu_j: every
+// pair of the batch (k <= kstar) is then answered yes at partition j at the latest.
+template <int DT>
+__global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* user_of_slot, const int* nslots,
+                                                  int64_t c0, int64_t chunk, int kstar, double* tab,
+                                                  double* scratch, int64_t scratch_stride)
+{
+    __shared__ int hist[SQ_T + 1];
+    __shared__ int sh[4];
+    __shared__ int wsum[SQ_T / 64];
+    __shared__ int ccount;
+    __shared__ double top[256];
+    const int tid = threadIdx.x;
+    const int W = a.K / 32;
+    int64_t hi = (int64_t)*nslots;
+    hi = hi < c0 + chunk ? hi : c0 + chunk;
+    double* cand = scratch + (int64_t)blockIdx.x * scratch_stride;
+    for (int64_t sl = c0 + blockIdx.x; sl < hi; sl += gridDim.x) {
+        const int64_t u = user_of_slot[sl];
+        const uint32_t ou = a.perm[u];
+        const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
+        const double unorm = sqrt(a.user_n2[u]);
+        uint32_t ucode[8];
+        for (int w = 0; w < W; w++) ucode[w] = a.user_codes[u * W + w];
+        double* row = tab + (sl - c0) * (int64_t)(a.t + 1) * kstar;
+        const int ninit = (int)((int64_t)kstar < a.n_init ? (int64_t)kstar : a.n_init);
+        for (int i = tid; i < kstar; i += SQ_T) {
+            const double v = i < ninit ? a.lam64[(int64_t)i * a.m + ou] : -__builtin_inf();
+            row[i] = v;
+            if (i < ninit) cand[i] = v;
+        }
+        if (tid == 0) ccount = ninit;
+        __syncthreads();
+        double phi_min = ninit >= kstar ? a.lam64[(int64_t)(kstar - 1) * a.m + ou] : -__builtin_inf();
+        for (int j = 0; j < a.t; j++) {
+            const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
+            const double mu = sqrt(a.item_n2[s0]) * unorm;
+            if (phi_min > mu) break;
+            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, hist, sh, wsum, &ccount);
+            const int64_t ncand = ccount;
+            __syncthreads();
+            block_top_sorted(cand, ncand, kstar, top, hist, sh, &wsum[0]);
+            double* rj = row + (int64_t)(j + 1) * kstar;
+            for (int i = tid; i < kstar; i += SQ_T) rj[i] = top[i];
+            phi_min = top[kstar - 1];
+            if (tid == 0) ccount = (int)(ncand < kstar ? ncand : kstar);
+            __syncthreads();
+        }
+    }
+}
+
+// Each pair whose user has its slot in [c0, c0 + chunk): the tests of Alg. 2 against the
+// user's table; a yes goes to the answers, a no counts in *rejects.
+__global__ void k_sah_decide(SaQueryArgs a, const double* score, const int* slot, int64_t c0, int64_t chunk,
+                             int kstar, const double* tab)
+{
+    int64_t np = (int64_t)*a.npairs_dev;
+    np = np < a.npairs ? np : a.npairs;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = a.pairs[i];
+        const int64_t q = (int64_t)(key >> 32), u = (int64_t)(key & 0xffffffffull);
+        const int64_t sl = slot[u];
+        if (sl < c0 || sl >= c0 + chunk) continue;
+        const int k = a.qk[q];
+        const double s = score[i];
+        const double unorm = sqrt(a.user_n2[u]);
+        const double* row = tab + (sl - c0) * (int64_t)(a.t + 1) * kstar;
+        double phi = row[k - 1];
+        bool ans = true;
+        for (int j = 0; j < a.t; j++) {
+            const double mu = sqrt(a.item_n2[a.part_start[j]]) * unorm;
+            if (phi > mu) break;
+            phi = row[(int64_t)(j + 1) * kstar + k - 1];
+            if (s < phi) { ans = false; break; }
+        }
+        if (ans) {
+            const uint32_t ou = a.perm[u];
+            const uint32_t qo = a.qorig[q];
+            if (a.bitmap) {
+                atomicOr(&a.bitmap[(int64_t)qo * a.bm_words + (ou >> 5)], 1u << (ou & 31u));
+            } else {
+                const unsigned long long pos = atomicAdd(a.pool_count, 1ull);
+                if ((int64_t)pos < a.pool_cap) a.pool[pos] = ((unsigned long long)qo << 32) | ou;
+            }
+        } else {
+            atomicAdd(a.rejects, 1ull);
+        }
+    }
+}
+
+void launch_sah(const SaQueryArgs& a, const unsigned char* need, int* slot, int* user_of_slot, int* nslots,
+                const double* score, int kstar, double* tab, int64_t chunk, double* scratch,
+                int64_t scratch_stride, int grid, hipStream_t s)
+{
+    if (a.npairs <= 0 || a.m <= 0) return;
+    if (kstar < 1 || kstar > 256) fail(RKMIPS_EINVAL, "internal: SAH table width");
+    hipLaunchKernelGGL(k_sah_slots, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, need, a.m, slot, nslots);
+    hipLaunchKernelGGL(k_sah_invert, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, need, slot, a.m,
+                       user_of_slot);
+    for (int64_t c0 = 0; c0 < a.m; c0 += chunk) {
+        if (a.dtype == DT_F32) hipLaunchKernelGGL(k_sah_user<DT_F32>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride);
+        else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_sah_user<DT_BF16>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride);
+        else hipLaunchKernelGGL(k_sah_user<DT_FP8>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride);
+        const unsigned gd = (unsigned)std::min<int64_t>((a.npairs + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_sah_decide, dim3(gd), dim3(256), 0, s, a, score, (const int*)slot, c0, chunk, kstar,
+                           (const double*)tab);
+    }
+    HIPC(hipGetLastError());
 }
 
 void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_stride, int grid, hipStream_t s)

@@ -96,12 +96,24 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
     const int64_t ac = std::max<int64_t>(amb_cap_req, 1 << 12);
     if (ac > amb_cap) {
         amb.alloc(sizeof(uint64_t) * ac);
-        if (x.prm.mode == RKMIPS_MODE_SAH) sah_pairs.alloc(sizeof(uint64_t) * ac);
+        if (x.prm.mode == RKMIPS_MODE_SAH) {
+            sah_pairs.alloc(sizeof(uint64_t) * ac);
+            sah_score.alloc(sizeof(double) * ac);
+        }
         amb_cap = ac;
     }
     if (!ctr.p) {
         ctr.alloc(sizeof(unsigned long long) * 16);
         h_ctr.alloc(sizeof(unsigned long long) * 16);
+    }
+    if (x.prm.mode == RKMIPS_MODE_SAH && !sah_need.p) {
+        sah_need.alloc((size_t)x.m);
+        sah_slot.alloc(sizeof(int) * (size_t)x.m);
+        sah_user.alloc(sizeof(int) * (size_t)x.m);
+        // tables of at most 1 GiB: chunk users at a time
+        const int64_t row = (int64_t)(x.t + 1) * x.prm.k_max * (int64_t)sizeof(double);
+        sah_chunk = std::max<int64_t>(1, std::min<int64_t>(x.m, (int64_t(1) << 30) / row));
+        sah_tab.alloc((size_t)(sah_chunk * row));
     }
 }
 
@@ -169,6 +181,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.sah = x.prm.mode == RKMIPS_MODE_SAH;
     a.item_n2 = x.item_n2.d(); a.n_items = x.n; a.user_n2 = x.user_n2.d();
     a.sah_pairs = (unsigned long long*)w.sah_pairs.p; a.sah_count = c + 6;
+    a.sah_score = w.sah_score.d(); a.sah_need = (unsigned char*)w.sah_need.p;
     return a;
 }
 
@@ -184,6 +197,7 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
     w.device_tail = nq > 0 && (sah || !((fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH)));
     w.bm_mode = w.device_tail && w.bitmap.p != nullptr && !(fl & RKMIPS_FLAG_POOL_LISTS);
     if (w.bm_mode) HIPC(hipMemsetAsync(w.bitmap.p, 0, sizeof(uint32_t) * (size_t)(nq * w.bm_words), s));
+    if (sah && nq > 0) HIPC(hipMemsetAsync(w.sah_need.p, 0, (size_t)x.m, s));
     if (nq > 0) {
         HIPC(hipMemcpyAsync(w.meta.p, w.h_meta.p, sizeof(int) * w.meta_ints, hipMemcpyHostToDevice, s));
         launch_gather_rows(x.dtype, queries, x.d, qscales, w.qorig, nq, x.d, w.qpad.p, x.ld, w.qsc.f(), s);
@@ -255,6 +269,7 @@ void plan_batch(const Index& x, Workspace& w, const int32_t* ks, int64_t nq)
         w.groups.push_back(g);
     }
     w.meta_ints = 3 * nq + kMaxSlots * (int64_t)w.groups.size();
+    w.sah_kstar = nq > 0 ? ks[ord[nq - 1]] : 0;   // queries sorted by k
     (void)x;
 }
 
@@ -299,7 +314,7 @@ void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs
 // on the device; a "yes" goes to the answers directly.
 void run_sah(const Index& x, Workspace& w, const QueryArgs& a, hipStream_t s)
 {
-    const int grid = (int)std::min<int64_t>(w.amb_cap, 1024);
+    const int grid = (int)std::min<int64_t>(w.sah_chunk, 2048);
     const int64_t stride = saalsh_scratch_stride(x, x.prm.probe_frac);
     if ((int64_t)w.sa_scratch.bytes < (int64_t)sizeof(double) * grid * stride) w.sa_scratch.alloc(sizeof(double) * grid * stride);
     SaQueryArgs sa = make_sa_args(x, a.queries, a.query_scales, a.qk, a.sah_pairs, w.amb_cap, x.prm.probe_frac,
@@ -310,7 +325,9 @@ void run_sah(const Index& x, Workspace& w, const QueryArgs& a, hipStream_t s)
     sa.pool = a.pool; sa.pool_count = a.pool_count; sa.pool_cap = a.pool_cap;
     sa.qorig = a.qorig;
     sa.rejects = a.stats + 4;
-    launch_saalsh_query(sa, w.sa_scratch.d(), stride, grid, s);
+    unsigned long long* c = (unsigned long long*)w.ctr.p;
+    launch_sah(sa, (const unsigned char*)w.sah_need.p, w.sah_slot.i(), w.sah_user.i(), (int*)(c + 7),
+               w.sah_score.d(), w.sah_kstar, w.sah_tab.d(), w.sah_chunk, w.sa_scratch.d(), stride, grid, s);
 }
 
 // Completion: overflow handling, FP64 recheck, sorted per-query lists, host copies.

@@ -38,7 +38,11 @@ struct Workspace {
     DevBuf qsplit;                          // matrix-core query rows (split FP32 or widened FP8)
     DevBuf qcnt, ids2;                      // per-query counts, scatter target of the lists
     DevBuf sa_scratch, sa_answer, sa_phi;   // SA-ALSH stage
-    DevBuf sah_pairs;                       // SAH mode: pairs left to Alg. 2 (capacity amb_cap)
+    DevBuf sah_pairs, sah_score;            // SAH mode: pairs left to Alg. 2 (capacity amb_cap)
+    DevBuf sah_need, sah_slot, sah_user;    // SAH mode: per-user flags and slots [m]
+    DevBuf sah_tab;                         // SAH mode: per-user Alg. 2 tables, one chunk
+    int64_t sah_chunk = 0;
+    int sah_kstar = 0;                      // largest k of the batch
     PinBuf h_offsets, h_ids, h_ctr;
     std::vector<Group> groups;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_ctr = nullptr;
