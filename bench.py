@@ -10,10 +10,12 @@ Default workload (20,000 x 100,000 x 64, FP32): items |N(0,1)|+0.3, users
 N(0,I) directions with log-normal(0, 0.7) norms, 1,000 fresh item draws as queries
 with k cycling through {1, 5, 10, 20, 50}, k_max = 50.
 
-Prints one JSON line (see README of the contract in the design doc): value = queries/s of
-the whole step, plus the lambda-index TFLOP/s, the roofline of the dominant kernel
-(the fused U.P^T + top-k pass, timed with HIP events on its stream), and the CPU FP64
-reference timed on a bounded user sample.
+Prints one JSON line: value = queries/s of the whole step, plus the lambda-index
+TFLOP/s, the roofline of the dominant kernel (the fused U.P^T + top-k pass, timed with
+HIP events on its stream), the CPU FP64 reference timed on a bounded user sample, and
+an SAH leg: the paper's approximate mode on the same inputs (P' lower bounds, Alg. 5
+decisions), its build and batch times and the precision / recall / F1 of its answers
+against the exact lists of the timed steps.
 """
 from __future__ import annotations
 
@@ -45,6 +47,9 @@ def parse():
                     help="users in the CPU reference sample (0: size it to ~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-sah", action="store_true", help="skip the approximate SAH-mode leg")
+    ap.add_argument("--sah-sweep", action="store_true",
+                    help="SAH leg over K in {64,128,256} x b in {0.3,0.5,0.7} x beta in {0.05,0.1,0.2}")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size before timing (counter scale)")
     return ap.parse_args()
@@ -58,7 +63,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2211_12751_amd import inputs as I
@@ -159,6 +164,38 @@ def main():
                 "max_inflight": int(st["max_inflight"]),
                 "achieved_qps": round(nreq / (st["wall_ms"] * 1e-3), 1) if st["wall_ms"] > 0 else None}
 
+    def sah_leg(ex_off, ex_ids, grid):
+        """The approximate SAH mode on the same inputs: build and batch time (device
+        events), and precision / recall / F1 of its answers against the exact lists."""
+        ex = [ex_ids[ex_off[i]:ex_off[i + 1]] for i in range(w.nq)]
+        ne = int(ex_off[w.nq])
+        out = []
+        for K, b, beta in grid:
+            q = R.rkmips_default_params()
+            q.k_max, q.mode, q.num_hash, q.b, q.probe_frac = k_max, R.MODE_SAH, K, b, beta
+            runs = []
+            for _ in range(3):
+                h = R.rkmips_build_index(items, isc, w.n, users, usc, w.m, w.d, dtype, None, q, stream)
+                r = R.rkmips_query_batch(h, queries, qsc, w.nq, ks, 0, stream)
+                R.rkmips_result_wait(r)
+                info, st = R.rkmips_get_info(h), R.rkmips_result_stats(r)
+                off, ids = R.rkmips_result_view(r)
+                R.rkmips_result_free(r)
+                R.rkmips_index_free(h)
+                runs.append((info, st, off, ids))
+            info, st, off, ids = runs[-1]
+            tp = sum(len(np.intersect1d(ids[off[i]:off[i + 1]], ex[i], assume_unique=True)) for i in range(w.nq))
+            ng = int(off[w.nq])
+            out.append({"K": K, "b": b, "beta": beta, "p_prime": int(info["lambda_items"]),
+                        "partitions": int(info["num_partitions"]),
+                        "build_ms": round(float(np.median([x[0]["ms_total"] for x in runs])), 4),
+                        "query_ms": round(float(np.median([x[1]["ms_total"] for x in runs])), 4),
+                        "results": ng, "exact_results": ne,
+                        "precision": round(tp / ng, 5) if ng else 1.0, "recall": round(tp / ne, 5) if ne else 1.0,
+                        "f1": round(2.0 * tp / (ng + ne), 5) if ng + ne else 1.0,
+                        "pairs_to_alg2": int(st["saalsh_checked"]), "alg2_no": int(st["saalsh_rejects"])})
+        return out
+
     for i in range(args.warmup):
         step()
         log(f"warmup step {i} done")
@@ -234,6 +271,11 @@ def main():
                      "mma_dtype": mma, "mma_terms": int(infos[-1]["mma_terms"])},
     }
 
+    if not args.no_sah:
+        log("SAH leg")
+        grid = ([(K, b, beta) for K in (64, 128, 256) for b in (0.3, 0.5, 0.7) for beta in (0.05, 0.1, 0.2)]
+                if args.sah_sweep else [(128, 0.5, beta) for beta in (0.05, 0.1, 0.2)])
+        line["sah"] = sah_leg(off, ids, grid)
     if not args.no_serving:
         log("serving replay")
         line["serving"] = serving()

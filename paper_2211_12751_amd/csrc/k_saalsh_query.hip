@@ -64,11 +64,21 @@ __device__ double sq_dot(const void* A, int64_t ra, float sa, const void* B, int
     return acc;
 }
 
-// collision count of item p with the user code
+// collision count of item p with the user code (rows of W words; 16-byte loads when
+// the rows are 16-byte multiples)
 __device__ __forceinline__ int collisions(const uint32_t* codes, int64_t p, const uint32_t* ucode, int W, int K)
 {
     int diff = 0;
-    for (int w = 0; w < W; w++) diff += __popc(codes[p * W + w] ^ ucode[w]);
+    const uint32_t* c = codes + p * W;
+    if ((W & 3) == 0) {
+        for (int w = 0; w < W; w += 4) {
+            const uint4 v = *(const uint4*)(c + w);
+            diff += __popc(v.x ^ ucode[w]) + __popc(v.y ^ ucode[w + 1]) + __popc(v.z ^ ucode[w + 2]) +
+                    __popc(v.w ^ ucode[w + 3]);
+        }
+    } else {
+        for (int w = 0; w < W; w++) diff += __popc(c[w] ^ ucode[w]);
+    }
     return K - diff;
 }
 
@@ -108,26 +118,36 @@ __device__ double block_kth(const double* vals, int64_t cnt, int k, int* hist, i
 // with the most equal code bits (equal counts: earlier position first) are scored and
 // their scores appended to cand at *ccount.  Called by the whole workgroup; ends with a
 // barrier, after which *ccount holds the new count.
+// whist: [SQ_T / 64][SQ_T + 1] ints, one collision-count histogram per wave.
 template <int DT>
 __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const uint32_t* ucode, int W,
-                                int64_t s0, int64_t s1, double* cand, int* hist, int* sh, int* wsum, int* ccount)
+                                int64_t s0, int64_t s1, double* cand, int (*whist)[SQ_T + 1], int* sh,
+                                int* ccount)
 {
     const int tid = threadIdx.x;
     const int64_t sz = s1 - s0;
     int64_t take = (int64_t)ceil((double)a.beta * (double)sz);
     if (take > sz) take = sz;
-    // histogram of collision counts over the partition
-    for (int b = tid; b <= a.K; b += SQ_T) hist[b] = 0;
+    // Each wave owns a contiguous quarter of the partition and histograms its collision
+    // counts; the sum over the waves gives the cut, and the waves before a wave hold the
+    // ties that precede its quarter in position order.
+    const int wv = tid >> 6, ln = tid & 63;
+    const int64_t qlen = (sz + SQ_T / 64 - 1) / (SQ_T / 64);
+    const int64_t w0 = s0 + wv * qlen;
+    const int64_t w1 = w0 + qlen < s1 ? w0 + qlen : s1;
+    for (int b = ln; b <= a.K; b += 64) whist[wv][b] = 0;
     __syncthreads();
-    for (int64_t p = s0 + tid; p < s1; p += SQ_T) atomicAdd(&hist[collisions(a.item_codes, p, ucode, W, a.K)], 1);
+    for (int64_t p = w0 + ln; p < w1; p += 64) atomicAdd(&whist[wv][collisions(a.item_codes, p, ucode, W, a.K)], 1);
     __syncthreads();
     if (tid == 0) {   // cut count c*: #(count > c*) < take <= #(count >= c*)
         int64_t above = 0;
         int cut = 0;
         int64_t need_eq = 0;
         for (int c = a.K; c >= 0; c--) {
-            if (above + hist[c] >= take) { cut = c; need_eq = take - above; break; }
-            above += hist[c];
+            int64_t h = 0;
+            for (int w = 0; w < SQ_T / 64; w++) h += whist[w][c];
+            if (above + h >= take) { cut = c; need_eq = take - above; break; }
+            above += h;
         }
         sh[0] = cut;
         sh[1] = (int)need_eq;
@@ -136,23 +156,9 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
     const int cut = sh[0];
     const int need_eq = sh[1];
     // ordered selection: candidates are the items above the cut and the first need_eq
-    // at it (position order).  Each wave owns a contiguous quarter of the partition: it
-    // counts its ties, one block-level prefix orders the quarters, then every wave takes
-    // its items with wave-local ballots.
-    const int wv = tid >> 6, ln = tid & 63;
-    const int64_t qlen = (sz + SQ_T / 64 - 1) / (SQ_T / 64);
-    const int64_t w0 = s0 + wv * qlen;
-    const int64_t w1 = w0 + qlen < s1 ? w0 + qlen : s1;
-    int my_eq = 0;
-    for (int64_t base = w0; base < w1; base += 64) {
-        const int64_t p = base + ln;
-        const bool iseq = p < w1 && collisions(a.item_codes, p, ucode, W, a.K) == cut;
-        my_eq += __popcll(ballot64(iseq));
-    }
-    if (ln == 0) wsum[wv] = my_eq;
-    __syncthreads();
+    // at it (position order), taken by every wave with wave-local ballots
     int eq_before = 0;
-    for (int w = 0; w < wv; w++) eq_before += wsum[w];
+    for (int w = 0; w < wv; w++) eq_before += whist[w][cut];
     for (int64_t base = w0; base < w1; base += 64) {
         const int64_t p = base + ln;
         const int c = p < w1 ? collisions(a.item_codes, p, ucode, W, a.K) : -1;
@@ -174,10 +180,10 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
 template <int DT>
 __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* scratch, int64_t scratch_stride)
 {
-    __shared__ int hist[SQ_T + 1];
+    __shared__ int whist[SQ_T / 64][SQ_T + 1];
     __shared__ int sh[4];
-    __shared__ int wsum[SQ_T / 64];
     __shared__ int ccount;
+    int* hist = whist[0];
     const int tid = threadIdx.x;
     const int W = a.K / 32;
     for (int64_t pi = blockIdx.x; pi < a.npairs; pi += gridDim.x) {
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
             const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
             const double mu = sqrt(a.item_n2[s0]) * unorm;
             if (phi > mu) { ans = 1; break; }
-            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, hist, sh, wsum, &ccount);
+            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount);
             const int64_t ncand = ccount;
             __syncthreads();
             phi = ncand >= k ? block_kth(cand, ncand, k, hist, sh) : -__builtin_inf();
@@ -290,11 +296,12 @@ __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* use
                                                   int64_t c0, int64_t chunk, int kstar, double* tab,
                                                   double* scratch, int64_t scratch_stride)
 {
-    __shared__ int hist[SQ_T + 1];
+    __shared__ int whist[SQ_T / 64][SQ_T + 1];
     __shared__ int sh[4];
-    __shared__ int wsum[SQ_T / 64];
+    __shared__ int tcount;
     __shared__ int ccount;
     __shared__ double top[256];
+    int* hist = whist[0];
     const int tid = threadIdx.x;
     const int W = a.K / 32;
     int64_t hi = (int64_t)*nslots;
@@ -321,10 +328,10 @@ __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* use
             const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
             const double mu = sqrt(a.item_n2[s0]) * unorm;
             if (phi_min > mu) break;
-            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, hist, sh, wsum, &ccount);
+            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount);
             const int64_t ncand = ccount;
             __syncthreads();
-            block_top_sorted(cand, ncand, kstar, top, hist, sh, &wsum[0]);
+            block_top_sorted(cand, ncand, kstar, top, hist, sh, &tcount);
             double* rj = row + (int64_t)(j + 1) * kstar;
             for (int i = tid; i < kstar; i += SQ_T) rj[i] = top[i];
             phi_min = top[kstar - 1];

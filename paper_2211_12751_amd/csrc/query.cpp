@@ -447,7 +447,13 @@ rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const f
         mem::StreamScope scope(r->s);
         Workspace* w = x.take_ws();
         try {
-            w->ensure(x, nq, std::max<int64_t>(1 << 16, 8 * nq * std::max(1, x.prm.k_max)), std::max<int64_t>(1 << 14, 4 * nq));
+            // SAH mode hands every pair that passes the L_u^k test to the recheck: start
+            // its list at a quarter of the pairs (at most 2^25; a longer list reruns the
+            // batch once with room for all, and the workspace keeps that room)
+            const int64_t amb0 = x.prm.mode == RKMIPS_MODE_SAH
+                                     ? std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>(4 * nq, nq * x.m / 4))
+                                     : 4 * nq;
+            w->ensure(x, nq, std::max<int64_t>(1 << 16, 8 * nq * std::max(1, x.prm.k_max)), std::max<int64_t>(1 << 14, amb0));
             plan_batch(x, *w, ks, nq);
             x.ready_on(r->s);   // a batch on another stream waits for the build on the device
             HIPC(hipEventRecord(w->ev0, r->s));
