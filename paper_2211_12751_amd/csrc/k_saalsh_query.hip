@@ -82,6 +82,37 @@ __device__ __forceinline__ int collisions(const uint32_t* codes, int64_t p, cons
     return K - diff;
 }
 
+// Called by one whole wave: the bin that holds the need-th largest key of a histogram
+// over bins [0, nbins) (lane l reads bins PER l .. PER l + PER - 1, nbins <= 64 PER),
+// and the number of keys in higher bins; every lane receives both (bin -1 when the
+// histogram holds fewer than need keys).
+template <int PER>
+__device__ __forceinline__ int2 wave_select_bin(const int* hist, int nbins, int need)
+{
+    const int l = lane_id();
+    int h[PER], x = 0;
+#pragma unroll
+    for (int e = 0; e < PER; e++) {
+        const int b = PER * l + e;
+        h[e] = b < nbins ? hist[b] : 0;
+        x += h[e];
+    }
+    const int incl = wave_incl_scan(x);
+    int above = __shfl(incl, 63) - incl;   // keys in higher lanes' bins
+    int sel = -1, sel_above = 0;
+#pragma unroll
+    for (int e = PER - 1; e >= 0; e--) {
+        if (sel < 0 && above < need && need <= above + h[e]) {
+            sel = PER * l + e;
+            sel_above = above;
+        }
+        above += h[e];
+    }
+    const uint64_t bal = ballot64(sel >= 0);
+    const int src = bal ? __builtin_ctzll(bal) : 0;
+    return make_int2(__shfl(sel, src), __shfl(sel_above, src));
+}
+
 // k-th largest of vals[0..cnt) (orderable 64-bit keys, 8 byte-digits), by one workgroup
 __device__ double block_kth(const double* vals, int64_t cnt, int k, int* hist, int* sh)
 {
@@ -96,13 +127,11 @@ __device__ double block_kth(const double* vals, int64_t cnt, int k, int* hist, i
             if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1);
         }
         __syncthreads();
-        if (tid == 0) {
-            int above = 0;
-            sh[0] = 0;
-            sh[1] = 0;
-            for (int b = 255; b >= 0; b--) {
-                if (above < need && need <= above + hist[b]) { sh[0] = b; sh[1] = above; break; }
-                above += hist[b];
+        if (tid < 64) {
+            const int2 r = wave_select_bin<4>(hist, 256, need);
+            if (tid == 0) {
+                sh[0] = r.x < 0 ? 0 : r.x;
+                sh[1] = r.x < 0 ? 0 : r.y;
             }
         }
         __syncthreads();
@@ -128,6 +157,8 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
     const int64_t sz = s1 - s0;
     int64_t take = (int64_t)ceil((double)a.beta * (double)sz);
     if (take > sz) take = sz;
+    // read before any wave can append (the callers change *ccount only behind a barrier)
+    const int c_begin = *ccount;
     // Each wave owns a contiguous quarter of the partition and histograms its collision
     // counts; the sum over the waves gives the cut, and the waves before a wave hold the
     // ties that precede its quarter in position order.
@@ -139,18 +170,19 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
     __syncthreads();
     for (int64_t p = w0 + ln; p < w1; p += 64) atomicAdd(&whist[wv][collisions(a.item_codes, p, ucode, W, a.K)], 1);
     __syncthreads();
-    if (tid == 0) {   // cut count c*: #(count > c*) < take <= #(count >= c*)
-        int64_t above = 0;
-        int cut = 0;
-        int64_t need_eq = 0;
-        for (int c = a.K; c >= 0; c--) {
-            int64_t h = 0;
-            for (int w = 0; w < SQ_T / 64; w++) h += whist[w][c];
-            if (above + h >= take) { cut = c; need_eq = take - above; break; }
-            above += h;
+    // the waves' sum, then the cut count c*: #(count > c*) < take <= #(count >= c*)
+    for (int b = tid; b <= a.K; b += SQ_T) {
+        int h = 0;
+        for (int w = 0; w < SQ_T / 64; w++) h += whist[w][b];
+        sh[4 + b] = h;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int2 r = wave_select_bin<5>(sh + 4, a.K + 1, (int)take);
+        if (tid == 0) {
+            sh[0] = r.x;
+            sh[1] = (int)take - r.y;
         }
-        sh[0] = cut;
-        sh[1] = (int)need_eq;
     }
     __syncthreads();
     const int cut = sh[0];
@@ -167,12 +199,22 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
         const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
         eq_before += __popcll(eb);
         const bool take_it = c > cut || (iseq && rank_eq < need_eq);
-        // append candidate scores (order inside the candidate multiset is irrelevant)
-        if (take_it) {
-            const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-            const double v = sq_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-            cand[atomicAdd(ccount, 1)] = v;
+        // the candidate's position, in the slot its score will take (the order inside the
+        // candidate multiset is irrelevant)
+        if (take_it) cand[atomicAdd(ccount, 1)] = __longlong_as_double((long long)p);
+    }
+    __syncthreads();
+    // scores of the new candidates, every lane busy (the selection keeps about one item
+    // in 1/beta, so scoring inside its loop would leave most lanes idle)
+    const int c_end = *ccount;
+    for (int i = c_begin + tid; i < c_end; i += SQ_T) {
+        const int64_t p = (int64_t)__double_as_longlong(cand[i]);
+        if (p < s0 || p >= s1) {   // cannot happen: every slot here holds a position of the partition
+            cand[i] = -__builtin_inf();
+            continue;
         }
+        const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
+        cand[i] = sq_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
     }
     __syncthreads();
 }
@@ -181,7 +223,7 @@ template <int DT>
 __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* scratch, int64_t scratch_stride)
 {
     __shared__ int whist[SQ_T / 64][SQ_T + 1];
-    __shared__ int sh[4];
+    __shared__ int sh[4 + SQ_T + 1];   // [0, 4): results; [4, 4 + K + 1]: counts
     __shared__ int ccount;
     int* hist = whist[0];
     const int tid = threadIdx.x;
@@ -297,7 +339,7 @@ __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* use
                                                   double* scratch, int64_t scratch_stride)
 {
     __shared__ int whist[SQ_T / 64][SQ_T + 1];
-    __shared__ int sh[4];
+    __shared__ int sh[4 + SQ_T + 1];   // [0, 4): results; [4, 4 + K + 1]: counts
     __shared__ int tcount;
     __shared__ int ccount;
     __shared__ double top[256];
