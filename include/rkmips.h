@@ -116,7 +116,9 @@ enum { RKMIPS_MODE_EXACT = 0, RKMIPS_MODE_SAH = 1 };
 void rkmips_default_params(rkmips_params *p);
 
 /*
- * Build the index (Alg. 4 with the lower-bound array made exact over all of P).
+ * Build the index (Alg. 4 with the lower-bound array made exact over all of P; in
+ * RKMIPS_MODE_SAH over the |P'| items of largest norm, with the SA-ALSH index over the
+ * rest).
  *   1. item norms and descending order (Alg. 4 first lines; Alg. 1 first line);
  *   2. lambda_u^(j), j = 1..k_max, for every user: a fused U.P^T matrix-core pass
  *      keeps k_max+s approximate candidates per user, FP64 rescoring sorts them
@@ -146,7 +148,8 @@ rkmips_status rkmips_build_index(const void *items, const float *item_scales, in
                                  const rkmips_params *p, void *stream, rkmips_index **out);
 
 /*
- * Answer a batch of queries (Alg. 5 over all blocks, exact decisions).
+ * Answer a batch of queries (Alg. 5 over all blocks: exact decisions, or the SAH
+ * decisions of RKMIPS_MODE_SAH, see rkmips_params.mode).
  * queries: device [nq x d] in the index's dtype (query_scales: device FP32 [nq] for
  * FP8, else NULL).  ks: HOST int32 [nq], 1 <= ks[i] <= k_max.  flags: RKMIPS_FLAG_*
  * added to the index defaults for this call.  The work is enqueued on `stream`;
