@@ -47,7 +47,7 @@ def parse():
                     help="users in the CPU reference sample (0: size it to ~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-sah", action="store_true", help="skip the approximate SAH-mode leg")
+    ap.add_argument("--no-sah", action="store_true", help="skip the SAH-mode and lazy-mode legs")
     ap.add_argument("--sah-sweep", action="store_true",
                     help="SAH leg over K in {64,128,256} x b in {0.3,0.5,0.7} x beta in {0.05,0.1,0.2}")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -196,6 +196,28 @@ def main():
                         "pairs_to_alg2": int(st["saalsh_checked"]), "alg2_no": int(st["saalsh_rejects"])})
         return out
 
+    def lazy_leg(ex_off, ex_ids):
+        """The exact lazy mode on the same inputs (lower bounds from P' only, Alg. 2 with
+        whole partitions at query time): build and batch times, and whether every list
+        equals the exact mode's."""
+        q = R.rkmips_default_params()
+        q.k_max, q.mode = k_max, R.MODE_LAZY
+        runs, same = [], True
+        for _ in range(3):
+            h = R.rkmips_build_index(items, isc, w.n, users, usc, w.m, w.d, dtype, None, q, stream)
+            r = R.rkmips_query_batch(h, queries, qsc, w.nq, ks, 0, stream)
+            R.rkmips_result_wait(r)
+            info, st = R.rkmips_get_info(h), R.rkmips_result_stats(r)
+            off, ids = R.rkmips_result_view(r)
+            same = same and np.array_equal(off, ex_off) and np.array_equal(ids, ex_ids)
+            R.rkmips_result_free(r)
+            R.rkmips_index_free(h)
+            runs.append((info, st))
+        return {"p_prime": int(runs[-1][0]["lambda_items"]),
+                "build_ms": round(float(np.median([x[0]["ms_total"] for x in runs])), 4),
+                "query_ms": round(float(np.median([x[1]["ms_total"] for x in runs])), 4),
+                "pairs_to_alg2": int(runs[-1][1]["saalsh_checked"]), "lists_equal_exact_mode": bool(same)}
+
     for i in range(args.warmup):
         step()
         log(f"warmup step {i} done")
@@ -276,6 +298,8 @@ def main():
         grid = ([(K, b, beta) for K in (64, 128, 256) for b in (0.3, 0.5, 0.7) for beta in (0.05, 0.1, 0.2)]
                 if args.sah_sweep else [(128, 0.5, beta) for beta in (0.05, 0.1, 0.2)])
         line["sah"] = sah_leg(off, ids, grid)
+        log("lazy leg")
+        line["lazy"] = lazy_leg(off, ids)
     if not args.no_serving:
         log("serving replay")
         line["serving"] = serving()

@@ -90,9 +90,9 @@ typedef struct {
     float b;             /* interval ratio of the norm partitions (Alg. 1), 0 < b < 1  */
     float probe_frac;    /* beta: fraction of a partition probed by SimHash (Alg. 2)   */
     uint64_t seed;       /* seed of the Cone-Tree pivots (Alg. 3)                       */
-    int32_t mode;        /* RKMIPS_MODE_EXACT or RKMIPS_MODE_SAH                        */
+    int32_t mode;        /* RKMIPS_MODE_EXACT, RKMIPS_MODE_SAH or RKMIPS_MODE_LAZY      */
     int32_t flags;       /* RKMIPS_FLAG_* defaults for every query of this index        */
-    int32_t sah_items;   /* RKMIPS_MODE_SAH: |P'|, the items of largest norm whose exact
+    int32_t sah_items;   /* SAH and LAZY: |P'|, the items of largest norm whose exact
                             k_max-MIPS gives the lower-bound arrays L_u (Alg. 4); the
                             SA-ALSH index covers the other n - |P'|.  1 <= |P'| < n;
                             0 takes min(2 k_max, n - 1).  Ignored in exact mode.       */
@@ -108,8 +108,14 @@ typedef struct {
  *          its candidate set starting from u's scores on P' (phi = L_u^k).  Every "no"
  *          is proved, so each set contains the exact one; Alg. 2's "yes" may be wrong
  *          (false positives).  All scores are canonical FP64, so the sets do not
- *          depend on scheduling.  RKMIPS_FLAG_SAALSH_FILTER has no effect here. */
-enum { RKMIPS_MODE_EXACT = 0, RKMIPS_MODE_SAH = 1 };
+ *          depend on scheduling.  RKMIPS_FLAG_SAALSH_FILTER has no effect here.
+ *   LAZY:  exact answers from the SAH index (only L_u over P' is built): the SAH steps
+ *          with every item of each partition that Alg. 2 visits scored (probe_frac is
+ *          set to 1).  A "no" is proved as in SAH; a "yes" after the last partition is
+ *          exact because phi is then lambda_u^(k); the early "yes" (phi > mu_j) is exact
+ *          because no unvisited item can score above mu_j < phi <= s(u,q).  This trades
+ *          the 2mnd-FLOP lambda build for per-user work at query time. */
+enum { RKMIPS_MODE_EXACT = 0, RKMIPS_MODE_SAH = 1, RKMIPS_MODE_LAZY = 2 };
 
 /* Defaults: k_max 50, N0 64, K 128, s 14, b 0.5, beta 0.1, seed 221112751, exact mode,
  * sah_items 0. */

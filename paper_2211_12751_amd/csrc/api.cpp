@@ -130,7 +130,8 @@ static void validate_params(const rkmips_params& p)
     if (p.topk_slack < 0 || p.topk_slack > 256) fail(RKMIPS_EINVAL, "topk_slack must be in [0, 256]");
     if (!(p.b > 0.f && p.b < 1.f)) fail(RKMIPS_EINVAL, "b must be in (0, 1)");
     if (!(p.probe_frac > 0.f && p.probe_frac <= 1.f)) fail(RKMIPS_EINVAL, "probe_frac must be in (0, 1]");
-    if (p.mode != RKMIPS_MODE_EXACT && p.mode != RKMIPS_MODE_SAH) fail(RKMIPS_EINVAL, "mode must be RKMIPS_MODE_EXACT or RKMIPS_MODE_SAH");
+    if (p.mode != RKMIPS_MODE_EXACT && p.mode != RKMIPS_MODE_SAH && p.mode != RKMIPS_MODE_LAZY)
+        fail(RKMIPS_EINVAL, "mode must be RKMIPS_MODE_EXACT, RKMIPS_MODE_SAH or RKMIPS_MODE_LAZY");
     if (p.sah_items < 0) fail(RKMIPS_EINVAL, "sah_items must be >= 0");
 }
 
@@ -678,7 +679,7 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
         std::unique_ptr<Index> x(new Index());
         x->n = n; x->m = m; x->d = d; x->dtype = dtype; x->prm = prm;
         x->n_lam = n;
-        if (prm.mode == RKMIPS_MODE_SAH) {
+        if (prm.mode != RKMIPS_MODE_EXACT) {
             // Alg. 4: P' = the first O(k_max) items in norm order; the SA-ALSH index
             // needs at least one item outside it
             if (n < 2) fail(RKMIPS_EINVAL, "SAH mode needs n >= 2");
@@ -686,6 +687,8 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
             if (np >= n) fail(RKMIPS_EINVAL, "sah_items must be below n");
             x->n_lam = np;
             x->prm.sah_items = (int32_t)np;
+            // the lazy mode scores every item of each partition Alg. 2 visits
+            if (prm.mode == RKMIPS_MODE_LAZY) x->prm.probe_frac = 1.f;
         }
         x->ld = padded_dim(d, dtype);
         // FP32 storage is scored on the BF16 matrix cores as split products where the

@@ -155,6 +155,9 @@ struct SaQueryArgs {
     unsigned long long* pool; unsigned long long* pool_count; int64_t pool_cap;
     const uint32_t* qorig;
     unsigned long long* rejects;
+    // SAH: 1; LAZY: 1 + 2^-40, so that mu_j bounds every canonical FP64 score of the
+    // partition despite the rounding of the scores and of mu_j itself
+    double mu_scale;
 };
 // Alg. 2 for each pair; scratch: grid x scratch_stride doubles (>= ceil(beta n) + t).
 void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_stride, int grid, hipStream_t s);

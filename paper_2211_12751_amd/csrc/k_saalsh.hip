@@ -340,7 +340,7 @@ void start_partitions(Index& x, int* h_num_parts, hipStream_t s)
     x.part_start.alloc(sizeof(int64_t) * (x.n + 2));
     x.num_parts.alloc(sizeof(int));
     // exact mode: all of P; SAH mode: P minus P' (the first n_lam positions), Alg. 4
-    const int64_t n0 = x.prm.mode == RKMIPS_MODE_SAH ? x.n_lam : 0;
+    const int64_t n0 = x.prm.mode != RKMIPS_MODE_EXACT ? x.n_lam : 0;
     hipLaunchKernelGGL(k_partitions, dim3(1), dim3(64), 0, s, x.item_n2.d(), n0, x.n, x.prm.b, x.part_start.i64(),
                        x.num_parts.i());
     HIPC(hipGetLastError());

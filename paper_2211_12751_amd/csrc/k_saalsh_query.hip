@@ -159,49 +159,55 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
     if (take > sz) take = sz;
     // read before any wave can append (the callers change *ccount only behind a barrier)
     const int c_begin = *ccount;
-    // Each wave owns a contiguous quarter of the partition and histograms its collision
-    // counts; the sum over the waves gives the cut, and the waves before a wave hold the
-    // ties that precede its quarter in position order.
-    const int wv = tid >> 6, ln = tid & 63;
-    const int64_t qlen = (sz + SQ_T / 64 - 1) / (SQ_T / 64);
-    const int64_t w0 = s0 + wv * qlen;
-    const int64_t w1 = w0 + qlen < s1 ? w0 + qlen : s1;
-    for (int b = ln; b <= a.K; b += 64) whist[wv][b] = 0;
-    __syncthreads();
-    for (int64_t p = w0 + ln; p < w1; p += 64) atomicAdd(&whist[wv][collisions(a.item_codes, p, ucode, W, a.K)], 1);
-    __syncthreads();
-    // the waves' sum, then the cut count c*: #(count > c*) < take <= #(count >= c*)
-    for (int b = tid; b <= a.K; b += SQ_T) {
-        int h = 0;
-        for (int w = 0; w < SQ_T / 64; w++) h += whist[w][b];
-        sh[4 + b] = h;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const int2 r = wave_select_bin<5>(sh + 4, a.K + 1, (int)take);
-        if (tid == 0) {
-            sh[0] = r.x;
-            sh[1] = (int)take - r.y;
+    if (take == sz) {   // every item is a candidate: no selection
+        for (int64_t p = s0 + tid; p < s1; p += SQ_T) cand[c_begin + (p - s0)] = __longlong_as_double((long long)p);
+        __syncthreads();
+        if (tid == 0) *ccount = c_begin + (int)sz;
+    } else {
+        // Each wave owns a contiguous quarter of the partition and histograms its collision
+        // counts; the sum over the waves gives the cut, and the waves before a wave hold the
+        // ties that precede its quarter in position order.
+        const int wv = tid >> 6, ln = tid & 63;
+        const int64_t qlen = (sz + SQ_T / 64 - 1) / (SQ_T / 64);
+        const int64_t w0 = s0 + wv * qlen;
+        const int64_t w1 = w0 + qlen < s1 ? w0 + qlen : s1;
+        for (int b = ln; b <= a.K; b += 64) whist[wv][b] = 0;
+        __syncthreads();
+        for (int64_t p = w0 + ln; p < w1; p += 64) atomicAdd(&whist[wv][collisions(a.item_codes, p, ucode, W, a.K)], 1);
+        __syncthreads();
+        // the waves' sum, then the cut count c*: #(count > c*) < take <= #(count >= c*)
+        for (int b = tid; b <= a.K; b += SQ_T) {
+            int h = 0;
+            for (int w = 0; w < SQ_T / 64; w++) h += whist[w][b];
+            sh[4 + b] = h;
         }
-    }
-    __syncthreads();
-    const int cut = sh[0];
-    const int need_eq = sh[1];
-    // ordered selection: candidates are the items above the cut and the first need_eq
-    // at it (position order), taken by every wave with wave-local ballots
-    int eq_before = 0;
-    for (int w = 0; w < wv; w++) eq_before += whist[w][cut];
-    for (int64_t base = w0; base < w1; base += 64) {
-        const int64_t p = base + ln;
-        const int c = p < w1 ? collisions(a.item_codes, p, ucode, W, a.K) : -1;
-        const bool iseq = c == cut;
-        const uint64_t eb = ballot64(iseq);
-        const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
-        eq_before += __popcll(eb);
-        const bool take_it = c > cut || (iseq && rank_eq < need_eq);
-        // the candidate's position, in the slot its score will take (the order inside the
-        // candidate multiset is irrelevant)
-        if (take_it) cand[atomicAdd(ccount, 1)] = __longlong_as_double((long long)p);
+        __syncthreads();
+        if (tid < 64) {
+            const int2 r = wave_select_bin<5>(sh + 4, a.K + 1, (int)take);
+            if (tid == 0) {
+                sh[0] = r.x;
+                sh[1] = (int)take - r.y;
+            }
+        }
+        __syncthreads();
+        const int cut = sh[0];
+        const int need_eq = sh[1];
+        // ordered selection: candidates are the items above the cut and the first need_eq
+        // at it (position order), taken by every wave with wave-local ballots
+        int eq_before = 0;
+        for (int w = 0; w < wv; w++) eq_before += whist[w][cut];
+        for (int64_t base = w0; base < w1; base += 64) {
+            const int64_t p = base + ln;
+            const int c = p < w1 ? collisions(a.item_codes, p, ucode, W, a.K) : -1;
+            const bool iseq = c == cut;
+            const uint64_t eb = ballot64(iseq);
+            const int rank_eq = eq_before + __popcll(eb & lanemask_lt());
+            eq_before += __popcll(eb);
+            const bool take_it = c > cut || (iseq && rank_eq < need_eq);
+            // the candidate's position, in the slot its score will take (the order inside the
+            // candidate multiset is irrelevant)
+            if (take_it) cand[atomicAdd(ccount, 1)] = __longlong_as_double((long long)p);
+        }
     }
     __syncthreads();
     // scores of the new candidates, every lane busy (the selection keeps about one item
@@ -368,7 +374,7 @@ __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* use
         double phi_min = ninit >= kstar ? a.lam64[(int64_t)(kstar - 1) * a.m + ou] : -__builtin_inf();
         for (int j = 0; j < a.t; j++) {
             const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
-            const double mu = sqrt(a.item_n2[s0]) * unorm;
+            const double mu = sqrt(a.item_n2[s0]) * unorm * a.mu_scale;
             if (phi_min > mu) break;
             probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount);
             const int64_t ncand = ccount;
@@ -402,7 +408,7 @@ __global__ void k_sah_decide(SaQueryArgs a, const double* score, const int* slot
         double phi = row[k - 1];
         bool ans = true;
         for (int j = 0; j < a.t; j++) {
-            const double mu = sqrt(a.item_n2[a.part_start[j]]) * unorm;
+            const double mu = sqrt(a.item_n2[a.part_start[j]]) * unorm * a.mu_scale;
             if (phi > mu) break;
             phi = row[(int64_t)(j + 1) * kstar + k - 1];
             if (s < phi) { ans = false; break; }

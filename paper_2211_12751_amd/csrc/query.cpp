@@ -96,7 +96,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
     const int64_t ac = std::max<int64_t>(amb_cap_req, 1 << 12);
     if (ac > amb_cap) {
         amb.alloc(sizeof(uint64_t) * ac);
-        if (x.prm.mode == RKMIPS_MODE_SAH) {
+        if (x.prm.mode != RKMIPS_MODE_EXACT) {
             sah_pairs.alloc(sizeof(uint64_t) * ac);
             sah_score.alloc(sizeof(double) * ac);
         }
@@ -106,7 +106,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
         ctr.alloc(sizeof(unsigned long long) * 16);
         h_ctr.alloc(sizeof(unsigned long long) * 16);
     }
-    if (x.prm.mode == RKMIPS_MODE_SAH && !sah_need.p) {
+    if (x.prm.mode != RKMIPS_MODE_EXACT && !sah_need.p) {
         sah_need.alloc((size_t)x.m);
         sah_slot.alloc(sizeof(int) * (size_t)x.m);
         sah_user.alloc(sizeof(int) * (size_t)x.m);
@@ -178,7 +178,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.amb = (unsigned long long*)w.amb.p; a.amb_count = c + 1; a.amb_cap = w.amb_cap;
     a.bad = (int*)(c + 2);
     a.stats = c + 8;
-    a.sah = x.prm.mode == RKMIPS_MODE_SAH;
+    a.sah = x.prm.mode != RKMIPS_MODE_EXACT;
     a.item_n2 = x.item_n2.d(); a.n_items = x.n; a.user_n2 = x.user_n2.d();
     a.sah_pairs = (unsigned long long*)w.sah_pairs.p; a.sah_count = c + 6;
     a.sah_score = w.sah_score.d(); a.sah_need = (unsigned char*)w.sah_need.p;
@@ -193,7 +193,7 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
 {
     HIPC(hipMemsetAsync(w.ctr.p, 0, sizeof(unsigned long long) * 16, s));
     const int fl = flags | x.prm.flags;
-    const bool sah = x.prm.mode == RKMIPS_MODE_SAH;
+    const bool sah = x.prm.mode != RKMIPS_MODE_EXACT;
     w.device_tail = nq > 0 && (sah || !((fl & RKMIPS_FLAG_SAALSH_FILTER) && !(fl & RKMIPS_FLAG_NO_SAALSH)));
     w.bm_mode = w.device_tail && w.bitmap.p != nullptr && !(fl & RKMIPS_FLAG_POOL_LISTS);
     if (w.bm_mode) HIPC(hipMemsetAsync(w.bitmap.p, 0, sizeof(uint32_t) * (size_t)(nq * w.bm_words), s));
@@ -314,8 +314,10 @@ void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs
 // on the device; a "yes" goes to the answers directly.
 void run_sah(const Index& x, Workspace& w, const QueryArgs& a, hipStream_t s)
 {
-    const int grid = (int)std::min<int64_t>(w.sah_chunk, 2048);
     const int64_t stride = saalsh_scratch_stride(x, x.prm.probe_frac);
+    // candidate scratch of at most 2 GiB (the lazy mode takes whole partitions)
+    const int grid = (int)std::min<int64_t>(std::min<int64_t>(w.sah_chunk, 2048),
+                                            std::max<int64_t>(64, (int64_t(1) << 31) / (8 * stride)));
     if ((int64_t)w.sa_scratch.bytes < (int64_t)sizeof(double) * grid * stride) w.sa_scratch.alloc(sizeof(double) * grid * stride);
     SaQueryArgs sa = make_sa_args(x, a.queries, a.query_scales, a.qk, a.sah_pairs, w.amb_cap, x.prm.probe_frac,
                                   nullptr, nullptr);
@@ -325,6 +327,7 @@ void run_sah(const Index& x, Workspace& w, const QueryArgs& a, hipStream_t s)
     sa.pool = a.pool; sa.pool_count = a.pool_count; sa.pool_cap = a.pool_cap;
     sa.qorig = a.qorig;
     sa.rejects = a.stats + 4;
+    sa.mu_scale = x.prm.mode == RKMIPS_MODE_LAZY ? 1.0 + 0x1p-40 : 1.0;
     unsigned long long* c = (unsigned long long*)w.ctr.p;
     launch_sah(sa, (const unsigned char*)w.sah_need.p, w.sah_slot.i(), w.sah_user.i(), (int*)(c + 7),
                w.sah_score.d(), w.sah_kstar, w.sah_tab.d(), w.sah_chunk, w.sa_scratch.d(), stride, grid, s);
@@ -357,7 +360,7 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     st.pairs_vector_pruned = (int64_t)hc[9];
     st.pairs_scored = (int64_t)hc[10];
     st.pairs_rechecked = namb;
-    if (x.prm.mode == RKMIPS_MODE_SAH) {
+    if (x.prm.mode != RKMIPS_MODE_EXACT) {
         st.saalsh_checked = (int64_t)hc[6];
         st.saalsh_rejects = (int64_t)hc[12];
     }
@@ -450,7 +453,7 @@ rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const f
             // SAH mode hands every pair that passes the L_u^k test to the recheck: start
             // its list at a quarter of the pairs (at most 2^25; a longer list reruns the
             // batch once with room for all, and the workspace keeps that room)
-            const int64_t amb0 = x.prm.mode == RKMIPS_MODE_SAH
+            const int64_t amb0 = x.prm.mode != RKMIPS_MODE_EXACT
                                      ? std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>(4 * nq, nq * x.m / 4))
                                      : 4 * nq;
             w->ensure(x, nq, std::max<int64_t>(1 << 16, 8 * nq * std::max(1, x.prm.k_max)), std::max<int64_t>(1 << 14, amb0));

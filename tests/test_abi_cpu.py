@@ -53,7 +53,7 @@ def test_argument_errors_before_device_work(R):
                                        C.byref(p), None, C.byref(h))
         assert st == -1, bad
     for field, val in (("k_max", 0), ("k_max", 300), ("leaf_size", 65), ("num_hash", 48), ("b", 1.0),
-                       ("probe_frac", 0.0), ("mode", 2), ("sah_items", -1)):
+                       ("probe_frac", 0.0), ("mode", 3), ("sah_items", -1)):
         q = R.rkmips_default_params()
         setattr(q, field, val)
         st = R._lib.rkmips_build_index(dummy, None, 10, dummy, None, 10, 8, 0, None, C.byref(q), None, C.byref(h))

@@ -106,9 +106,33 @@ def test_sah_full_probe_is_exact(R):
 def test_sah_rejects_bad_sizes(R):
     w = I.make("c2", n=50, m=60, d=8, nq=2, seed=62)
     print("\n[case] sah bad sizes", flush=True)
-    for kw in (dict(sah_items=50), dict(sah_items=-1), dict(mode=2)):
+    for kw in (dict(sah_items=50), dict(sah_items=-1), dict(mode=3)):
         args = dict(mode=R.MODE_SAH)
         args.update(kw)
         with pytest.raises(R.RkmipsError) as e:
             R.Index(w.items, None, w.users, None, dtype="f32", k_max=10, **args)
         assert e.value.status == -1
+
+
+@pytest.mark.parametrize("dtype, n, m, d, n_prime, flags", [
+    ("f32", 700, 900, 16, 30, 0), ("bf16", 640, 1000, 32, 0, 0), ("fp8", 600, 800, 48, 40, 0),
+    ("f32", 700, 900, 16, 30, 128),
+])
+def test_lazy_mode_is_exact(R, dtype, n, m, d, n_prime, flags):
+    """The lazy mode builds only L_u over P' and decides the rest with Alg. 2 scoring every
+    item of each visited partition: its sets are the Definition 1 sets."""
+    w = I.make({"f32": "c2", "bf16": "c3", "fp8": "c5"}[dtype], n=n, m=m, d=d, nq=24, seed=71 + n_prime)
+    ks = np.array([1, 5, 10, 20, 5, 1, 10, 20] * 3, np.int32)
+    print(f"\n[case] lazy dtype={dtype} n={n} m={m} d={d} n'={n_prime} flags={flags}", flush=True)
+    idx = R.Index(w.items, w.item_scales, w.users, w.user_scales, dtype=dtype, k_max=20, num_hash=64,
+                  mode=R.MODE_LAZY, sah_items=n_prime, b=0.5, probe_frac=0.1)
+    try:
+        assert idx.info["mode"] == R.MODE_LAZY
+        got, st = idx.query(w.queries, w.query_scales, ks, flags=flags, stats=True)
+        exact, _ = O.rkmips(dtype, w.items, w.item_scales, w.users, w.user_scales, w.queries, w.query_scales, ks, 20)
+        for qi in range(len(ks)):
+            assert np.array_equal(np.asarray(got[qi]), exact[qi]), f"query {qi}"
+        print(f"stats {st}", flush=True)
+        assert st["saalsh_checked"] > 0
+    finally:
+        idx.close()
