@@ -267,6 +267,22 @@ rkmips_status rkmips_get_blocks(const rkmips_index *idx, int32_t *leaf_users, in
 
 void rkmips_index_free(rkmips_index *idx);
 
+/*
+ * Save a complete index to a file and load it back (not from the paper: the Alg. 4 index
+ * is built once per item and user set, and a server can start from the file instead).
+ * Save waits for the build, copies every array the queries and getters read, the build
+ * statistics and the parameters to `path` (host byte order; the raw candidates of the
+ * lambda build are not kept, so rkmips_get_candidates fails on a loaded index).  Load
+ * reads such a file onto the current device; its arrays are ready when it returns, and
+ * `stream` is the stream its buffers are recycled on.  A loaded index answers every
+ * query exactly as the saved one.
+ * Errors: EINVAL (null pointers, a file that cannot be opened, written or read, a wrong
+ * magic or version, an inconsistent header or a missing array), ENOMEM, EDEVICE.  The
+ * file checks happen before any device call.
+ */
+rkmips_status rkmips_index_save(const rkmips_index *idx, const char *path);
+rkmips_status rkmips_index_load(const char *path, void *stream, rkmips_index **out);
+
 /* Text of the last error on this thread ("" if none). */
 const char *rkmips_last_error(void);
 

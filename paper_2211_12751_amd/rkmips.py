@@ -95,6 +95,8 @@ _sig = {
     "rkmips_get_blocks": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rkmips_saalsh_probe": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, C.c_float, _P, _P, _P]),
     "rkmips_index_free": (None, [_P]),
+    "rkmips_index_save": (C.c_int, [_P, C.c_char_p]),
+    "rkmips_index_load": (C.c_int, [C.c_char_p, _P, C.POINTER(_P)]),
     "rkmips_last_error": (C.c_char_p, []),
     "rkmips_serve_replay": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, C.POINTER(rkmips_serve_params), _P,
                                       C.POINTER(rkmips_serve_stats), C.POINTER(_P)]),
@@ -247,6 +249,16 @@ def rkmips_index_free(idx):
     _lib.rkmips_index_free(idx)
 
 
+def rkmips_index_save(idx, path):
+    _check(_lib.rkmips_index_save(idx, os.fsencode(path)))
+
+
+def rkmips_index_load(path, stream=None):
+    h = _P()
+    _check(_lib.rkmips_index_load(os.fsencode(path), _stream(stream), C.byref(h)))
+    return h
+
+
 def rkmips_last_error():
     return _lib.rkmips_last_error().decode()
 
@@ -338,6 +350,22 @@ class Index:
         finally:
             rkmips_result_free(h)
         return [ids[off[i]:off[i + 1]] for i in range(nq)], lat, st
+
+    def save(self, path):
+        rkmips_index_save(self.h, path)
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """An Index object around an index read from a file written by save()."""
+        self = cls.__new__(cls)
+        self.h = rkmips_index_load(path, stream)
+        self.info = rkmips_get_info(self.h)
+        self.params = rkmips_default_params()
+        self.params.k_max, self.params.num_hash = self.info["k_max"], self.info["num_hash"]
+        self.params.leaf_size, self.params.mode = self.info["leaf_size"], self.info["mode"]
+        self.dtype = int(self.info["dtype"])
+        self.n, self.m, self.d = int(self.info["n"]), int(self.info["m"]), int(self.info["d"])
+        return self
 
     def close(self):
         if getattr(self, "h", None):

@@ -77,3 +77,19 @@ def test_argument_errors_before_device_work(R):
     assert R._lib.rkmips_result_view(None, None, None, None) == -1
     R._lib.rkmips_result_free(None)
     R._lib.rkmips_index_free(None)
+
+
+def test_index_load_rejects_bad_files_before_device_work(R, tmp_path):
+    h = C.c_void_p()
+    st = R._lib.rkmips_index_load(str(tmp_path / "missing.idx").encode(), None, C.byref(h))
+    assert st == -1 and "cannot open" in R.rkmips_last_error()
+    bad = tmp_path / "bad.idx"
+    bad.write_bytes(b"NOTANIDX" + b"\0" * 64)
+    st = R._lib.rkmips_index_load(str(bad).encode(), None, C.byref(h))
+    assert st == -1 and "not an index file" in R.rkmips_last_error()
+    short = tmp_path / "short.idx"
+    short.write_bytes(b"RKMIPSIX" + b"\1\0\0\0")
+    st = R._lib.rkmips_index_load(str(short).encode(), None, C.byref(h))
+    assert st == -1 and "truncated" in R.rkmips_last_error()
+    st = R._lib.rkmips_index_save(None, str(bad).encode())
+    assert st == -1
