@@ -17,6 +17,7 @@ or uint8 FP8 e4m3 codes with float32 per-row scales):
 * ``values``         stored rows widened to float64 (FP8: code value x row scale)
 * ``cone_block_stats``, ``block_lower_bounds``  per-block cone data of a given
   partition of the users (Alg. 3 leaves; Lemmas 2 and 3; L^j(B) of Alg. 4)
+* ``saalsh_kmips``   the k best scores Alg. 2's probes find for a user (no query)
 * ``sah_rkmips``     the approximate SAH method: Alg. 4 with L_i from P' and the
   SA-ALSH index over P minus P', Alg. 5 per (query, user)
 """
@@ -325,3 +326,40 @@ def sah_rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, n_prime,
                 keep.append(u)
         out.append(np.asarray(keep, dtype=np.int32))
     return out
+
+
+def _popcount_rows(x):
+    """Set bits per row of a uint32 matrix."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    return np.unpackbits(x.view(np.uint8), axis=1).sum(axis=1).astype(np.int64)
+
+
+def saalsh_kmips(dtype, P, P_scales, norm2, order, part_start, item_codes, ucode, beta, U, U_scales, u, k,
+                 init=None):
+    """The k best scores that Alg. 2's probes find for user u without a query (float64
+    [k], descending, -inf where fewer were scored).  Partitions in order; before
+    partition j the search stops once the k-th best so far exceeds mu_j = M_j ||u||; each
+    partition adds the ceil(beta |S_j|) items with the most equal code bits (equal counts:
+    earlier in ``order`` first), scored canonically.  ``init``: scores that are candidates
+    from the start (SAH: u's scores on P')."""
+    import math
+    K = np.asarray(ucode).shape[-1] * 32
+    b = float(np.float32(beta))   # the library takes beta as a float
+    unorm = math.sqrt(score(dtype, U, U_scales, u, U, U_scales, u))
+    cand = [float(v) for v in (init if init is not None else [])]
+
+    def kth():
+        return sorted(cand, reverse=True)[k - 1] if len(cand) >= k else -math.inf
+
+    for j in range(len(part_start) - 1):
+        s0, s1 = int(part_start[j]), int(part_start[j + 1])
+        if kth() > math.sqrt(float(norm2[order[s0]])) * unorm:
+            break
+        items = np.asarray(order[s0:s1])
+        agree = K - _popcount_rows(np.asarray(item_codes)[items] ^ np.asarray(ucode, np.uint32)[None, :])
+        sz = s1 - s0
+        take = min(int(math.ceil(b * sz)), sz)
+        sel = sorted(range(sz), key=lambda i: (-int(agree[i]), i))[:take]
+        cand += [score(dtype, U, U_scales, u, P, P_scales, int(items[i])) for i in sel]
+    top = sorted(cand, reverse=True)[:k]
+    return np.array(top + [-math.inf] * (k - len(top)), dtype=np.float64)

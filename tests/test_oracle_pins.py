@@ -480,3 +480,27 @@ def test_sah_full_probe_is_exact_and_partial_probe_is_a_superset():
         extra += len(a) - len(b)
         rejected += len(s) - len(a)
     assert rejected > 0   # Alg. 2 said "no" somewhere: the probe path ran
+
+
+def test_saalsh_kmips_full_probe_is_exact_top_k():
+    """Probing every item of each partition (beta = 1) finds the exact k best scores, with
+    and without P' scores to start from; a partial probe never reports a score above the
+    exact one of the same rank."""
+    w, A, _ = _sah_case(43, n=300, m=12, nq=1)
+    n2, order = O.item_order("f32", w.items, None)
+    lam = O.lambda_table("f32", w.items, None, w.users, None, 20)
+    ps = O.partitions(n2, order, 0.5)
+    _, _, icodes = O.saalsh_index("f32", w.items, None, order, ps, A)
+    ucodes = O.user_codes("f32", w.users, None, A)
+    ps2 = O.partitions(n2, order, 0.5, start=25)
+    _, _, icodes2 = O.saalsh_index("f32", w.items, None, order, ps2, A)
+    for u in range(12):
+        for k in (1, 7, 20):
+            got = O.saalsh_kmips("f32", w.items, None, n2, order, ps, icodes, ucodes[u], 1.0, w.users, None, u, k)
+            assert np.array_equal(got, lam[:k, u])
+            init = [O.score("f32", w.users, None, u, w.items, None, int(p)) for p in order[:25]]
+            got2 = O.saalsh_kmips("f32", w.items, None, n2, order, ps2, icodes2, ucodes[u], 1.0, w.users, None, u,
+                                  k, init=init)
+            assert np.array_equal(got2, lam[:k, u])
+            part = O.saalsh_kmips("f32", w.items, None, n2, order, ps, icodes, ucodes[u], 0.1, w.users, None, u, k)
+            assert np.all(part <= lam[:k, u])
