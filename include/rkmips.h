@@ -268,6 +268,24 @@ rkmips_status rkmips_get_blocks(const rkmips_index *idx, int32_t *leaf_users, in
 void rkmips_index_free(rkmips_index *idx);
 
 /*
+ * SA-ALSH kMIPS (Alg. 2 run without a query, the search that SAH uses inside Alg. 5):
+ * for each of the nu users users[i] (original ids, HOST int64), the k best scores that
+ * the probes find.  Partitions are visited in norm order; each probes the
+ * ceil(probe_frac |S_j|) items with the most equal code bits (ties: earlier in norm
+ * order) and scores them in canonical FP64; the search stops before partition j once the
+ * k-th best found exceeds mu_j = M_j ||u||.  Exact-mode index: the partitions cover all
+ * of P and the search starts empty.  SAH and lazy indexes: they cover P \ P' and the
+ * search starts from u's k best scores on P' (its lambda row), so k <= k_max.
+ * scores_out: HOST double [nu x k], row i descending, -inf where fewer than k items were
+ * scored.  probe_frac = 1 gives the exact k best scores (rkmips_get_lambda on an exact
+ * index).  Synchronous on `stream`.
+ * Errors: EINVAL (null pointers, user id out of range, probe_frac outside (0, 1]),
+ * ERANGE (k outside [1, 256], or above k_max on an SAH or lazy index), ENOMEM, EDEVICE.
+ */
+rkmips_status rkmips_saalsh_kmips(rkmips_index *idx, const int64_t *users, int64_t nu, int32_t k,
+                                  float probe_frac, void *stream, double *scores_out);
+
+/*
  * Save a complete index to a file and load it back (not from the paper: the Alg. 4 index
  * is built once per item and user set, and a server can start from the file instead).
  * Save waits for the build, copies every array the queries and getters read, the build

@@ -166,6 +166,10 @@ void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_
 // (>= every k of the pairs) scores after each partition, chunk slots at a time (tab:
 // chunk x (t + 1) x kstar doubles), then the per-pair decisions; score[i]: s(u,q) of
 // pair i.  scratch: grid x scratch_stride doubles (>= ceil(beta n) + t + 1 + kstar).
+// SA-ALSH kMIPS for nu users (leaf positions user_of_slot, *nslots = nu on the device):
+// tab [nu x (t + 1) x k] per-partition best-k rows, jlast [nu] the last row written.
+void launch_saalsh_kmips(const SaQueryArgs& a, const int* user_of_slot, const int* nslots, int64_t nu, int k,
+                         double* tab, int* jlast, double* scratch, int64_t scratch_stride, int grid, hipStream_t s);
 void launch_sah(const SaQueryArgs& a, const unsigned char* need, int* slot, int* user_of_slot, int* nslots,
                 const double* score, int kstar, double* tab, int64_t chunk, double* scratch,
                 int64_t scratch_stride, int grid, hipStream_t s);

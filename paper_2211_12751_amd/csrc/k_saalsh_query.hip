@@ -342,7 +342,7 @@ __device__ void block_top_sorted(double* vals, int64_t cnt, int kstar, double* t
 template <int DT>
 __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* user_of_slot, const int* nslots,
                                                   int64_t c0, int64_t chunk, int kstar, double* tab,
-                                                  double* scratch, int64_t scratch_stride)
+                                                  double* scratch, int64_t scratch_stride, int* jlast)
 {
     __shared__ int whist[SQ_T / 64][SQ_T + 1];
     __shared__ int sh[4 + SQ_T + 1];   // [0, 4): results; [4, 4 + K + 1]: counts
@@ -372,7 +372,8 @@ __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* use
         if (tid == 0) ccount = ninit;
         __syncthreads();
         double phi_min = ninit >= kstar ? a.lam64[(int64_t)(kstar - 1) * a.m + ou] : -__builtin_inf();
-        for (int j = 0; j < a.t; j++) {
+        int j = 0;
+        for (; j < a.t; j++) {
             const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
             const double mu = sqrt(a.item_n2[s0]) * unorm * a.mu_scale;
             if (phi_min > mu) break;
@@ -386,6 +387,7 @@ __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* use
             if (tid == 0) ccount = (int)(ncand < kstar ? ncand : kstar);
             __syncthreads();
         }
+        if (jlast && tid == 0) jlast[sl - c0] = j;   // rows 0..j are written
     }
 }
 
@@ -438,9 +440,9 @@ void launch_sah(const SaQueryArgs& a, const unsigned char* need, int* slot, int*
     hipLaunchKernelGGL(k_sah_invert, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, need, slot, a.m,
                        user_of_slot);
     for (int64_t c0 = 0; c0 < a.m; c0 += chunk) {
-        if (a.dtype == DT_F32) hipLaunchKernelGGL(k_sah_user<DT_F32>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride);
-        else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_sah_user<DT_BF16>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride);
-        else hipLaunchKernelGGL(k_sah_user<DT_FP8>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride);
+        if (a.dtype == DT_F32) hipLaunchKernelGGL(k_sah_user<DT_F32>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride, (int*)nullptr);
+        else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_sah_user<DT_BF16>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride, (int*)nullptr);
+        else hipLaunchKernelGGL(k_sah_user<DT_FP8>, dim3(grid), dim3(SQ_T), 0, s, a, (const int*)user_of_slot, (const int*)nslots, c0, chunk, kstar, tab, scratch, scratch_stride, (int*)nullptr);
         const unsigned gd = (unsigned)std::min<int64_t>((a.npairs + 255) / 256, 2048);
         hipLaunchKernelGGL(k_sah_decide, dim3(gd), dim3(256), 0, s, a, score, (const int*)slot, c0, chunk, kstar,
                            (const double*)tab);
@@ -454,6 +456,21 @@ void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_
     if (a.dtype == DT_F32) hipLaunchKernelGGL(k_saalsh_query<DT_F32>, dim3(grid), dim3(SQ_T), 0, s, a, scratch, scratch_stride);
     else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_saalsh_query<DT_BF16>, dim3(grid), dim3(SQ_T), 0, s, a, scratch, scratch_stride);
     else hipLaunchKernelGGL(k_saalsh_query<DT_FP8>, dim3(grid), dim3(SQ_T), 0, s, a, scratch, scratch_stride);
+    HIPC(hipGetLastError());
+}
+
+// SA-ALSH kMIPS (Alg. 2 without a query): for the users user_of_slot[0, nu) (leaf
+// positions), the k best scores found by the probes, partitions visited in order until
+// the k-th best exceeds mu_j; tab [nu x (t + 1) x k], jlast [nu]: row jlast of a user is
+// its answer.
+void launch_saalsh_kmips(const SaQueryArgs& a, const int* user_of_slot, const int* nslots, int64_t nu, int k,
+                         double* tab, int* jlast, double* scratch, int64_t scratch_stride, int grid, hipStream_t s)
+{
+    if (nu <= 0) return;
+    if (k < 1 || k > 256) fail(RKMIPS_EINVAL, "internal: kMIPS width");
+    if (a.dtype == DT_F32) hipLaunchKernelGGL(k_sah_user<DT_F32>, dim3(grid), dim3(SQ_T), 0, s, a, user_of_slot, nslots, (int64_t)0, nu, k, tab, scratch, scratch_stride, jlast);
+    else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_sah_user<DT_BF16>, dim3(grid), dim3(SQ_T), 0, s, a, user_of_slot, nslots, (int64_t)0, nu, k, tab, scratch, scratch_stride, jlast);
+    else hipLaunchKernelGGL(k_sah_user<DT_FP8>, dim3(grid), dim3(SQ_T), 0, s, a, user_of_slot, nslots, (int64_t)0, nu, k, tab, scratch, scratch_stride, jlast);
     HIPC(hipGetLastError());
 }
 

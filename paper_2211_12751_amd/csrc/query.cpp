@@ -516,6 +516,66 @@ void rkmips_result_free(rkmips_result* r)
     delete r;
 }
 
+rkmips_status rkmips_saalsh_kmips(rkmips_index* idx, const int64_t* users, int64_t nu, int32_t k, float probe_frac,
+                                  void* stream, double* scores_out)
+{
+    return qguard([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "index is NULL");
+        Index& x = *(Index*)idx;
+        x.wait_ready();
+        if (nu < 0 || (nu > 0 && (!users || !scores_out))) fail(RKMIPS_EINVAL, "user or output array missing");
+        // SAH and lazy indexes know u's scores on P' only to rank k_max
+        const int kcap = x.prm.mode == RKMIPS_MODE_EXACT ? 256 : x.prm.k_max;
+        if (k < 1 || k > kcap) fail(RKMIPS_ERANGE, "k outside [1, 256] (SAH and lazy indexes: [1, k_max])");
+        if (!(probe_frac > 0.f && probe_frac <= 1.f)) fail(RKMIPS_EINVAL, "probe_frac must be in (0, 1]");
+        if (nu == 0) return;
+        std::vector<uint32_t> perm(x.m), inv(x.m);
+        HIPC(hipMemcpy(perm.data(), x.user_perm.p, sizeof(uint32_t) * x.m, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < x.m; i++) inv[perm[i]] = (uint32_t)i;
+        std::vector<int> leaf(nu);
+        for (int64_t i = 0; i < nu; i++) {
+            if (users[i] < 0 || users[i] >= x.m) fail(RKMIPS_EINVAL, "user index out of range");
+            leaf[i] = (int)inv[users[i]];
+        }
+        hipStream_t s = (hipStream_t)stream;
+        mem::StreamScope scope(s);
+        const int64_t row = (int64_t)(x.t + 1) * k;
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nu, (int64_t(1) << 27) / row));   // 1 GiB
+        const int64_t stride = saalsh_scratch_stride(x, probe_frac) + k;
+        const int grid = (int)std::min<int64_t>(std::min<int64_t>(chunk, 2048),
+                                                std::max<int64_t>(64, (int64_t(1) << 31) / (8 * stride)));
+        DevBuf dleaf, dcount, tab, jl, scratch;
+        dleaf.alloc(sizeof(int) * chunk);
+        dcount.alloc(sizeof(int));
+        tab.alloc(sizeof(double) * (size_t)(chunk * row));
+        jl.alloc(sizeof(int) * chunk);
+        scratch.alloc(sizeof(double) * (size_t)grid * stride);
+        SaQueryArgs sa = make_sa_args(x, nullptr, nullptr, nullptr, nullptr, 0, probe_frac, nullptr, nullptr);
+        // exact mode: the partitions cover all of P and the probes start from nothing; SAH
+        // and lazy: they cover P minus P' and start from the scores on P' (the lambda rows)
+        sa.lam64 = x.lam64.d(); sa.perm = x.user_perm.u32(); sa.m = x.m;
+        sa.n_init = x.prm.mode == RKMIPS_MODE_EXACT ? 0 : x.n_lam;
+        sa.mu_scale = 1.0;
+        std::vector<double> htab;
+        std::vector<int> hj;
+        for (int64_t c0 = 0; c0 < nu; c0 += chunk) {
+            const int cn = (int)std::min<int64_t>(chunk, nu - c0);
+            HIPC(hipStreamSynchronize(s));   // the previous chunk's kernel has read them
+            HIPC(hipMemcpy(dleaf.p, leaf.data() + c0, sizeof(int) * cn, hipMemcpyHostToDevice));
+            HIPC(hipMemcpy(dcount.p, &cn, sizeof(int), hipMemcpyHostToDevice));
+            launch_saalsh_kmips(sa, dleaf.i(), dcount.i(), cn, k, tab.d(), jl.i(), scratch.d(), stride, grid, s);
+            htab.resize((size_t)cn * row);
+            hj.resize(cn);
+            HIPC(hipMemcpyAsync(htab.data(), tab.p, sizeof(double) * htab.size(), hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync(hj.data(), jl.p, sizeof(int) * cn, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            for (int i = 0; i < cn; i++)
+                std::memcpy(scores_out + (c0 + i) * k, htab.data() + (size_t)i * row + (size_t)hj[i] * k,
+                            sizeof(double) * k);
+        }
+    });
+}
+
 rkmips_status rkmips_saalsh_probe(rkmips_index* idx, const void* queries, const float* query_scales, int64_t nq,
                                   const int32_t* ks, const int64_t* pair_query, const int64_t* pair_user,
                                   int64_t npairs, float probe_frac, void* stream, double* phi_out, int32_t* answer_out)

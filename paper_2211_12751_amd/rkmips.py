@@ -95,6 +95,7 @@ _sig = {
     "rkmips_get_blocks": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rkmips_saalsh_probe": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, C.c_float, _P, _P, _P]),
     "rkmips_index_free": (None, [_P]),
+    "rkmips_saalsh_kmips": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P]),
     "rkmips_index_save": (C.c_int, [_P, C.c_char_p]),
     "rkmips_index_load": (C.c_int, [C.c_char_p, _P, C.POINTER(_P)]),
     "rkmips_last_error": (C.c_char_p, []),
@@ -249,6 +250,13 @@ def rkmips_index_free(idx):
     _lib.rkmips_index_free(idx)
 
 
+def rkmips_saalsh_kmips(idx, users, k, probe_frac, stream=None):
+    users = np.ascontiguousarray(users, dtype=np.int64)
+    out = np.empty((len(users), k), np.float64)
+    _check(_lib.rkmips_saalsh_kmips(idx, _ptr(users), len(users), k, probe_frac, _stream(stream), _ptr(out)))
+    return out
+
+
 def rkmips_index_save(idx, path):
     _check(_lib.rkmips_index_save(idx, os.fsencode(path)))
 
@@ -350,6 +358,10 @@ class Index:
         finally:
             rkmips_result_free(h)
         return [ids[off[i]:off[i + 1]] for i in range(nq)], lat, st
+
+    def kmips(self, users, k, probe_frac, stream=None):
+        """SA-ALSH kMIPS scores [len(users) x k] (descending, -inf padded)."""
+        return rkmips_saalsh_kmips(self.h, users, k, probe_frac, stream)
 
     def save(self, path):
         rkmips_index_save(self.h, path)

@@ -1,0 +1,51 @@
+"""SA-ALSH kMIPS (Alg. 2 probes without a query) on the GPU against the CPU reference:
+the k best scores found for sampled users are identical (canonical FP64) whenever the
+sign-random-projection codes agree, probing everything gives the exact top-k, and no
+reported score exceeds the exact one of its rank."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_12751_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype, mode", [("f32", 0), ("bf16", 0), ("fp8", 0), ("f32", 1)])
+def test_kmips_matches_reference(dtype, mode):
+    from paper_2211_12751_amd import rkmips as R
+    w = I.make({"f32": "c2", "bf16": "c3", "fp8": "c5"}[dtype], n=800, m=500, d=32, nq=2, seed=91)
+    K, beta, k = 64, 0.1, 10
+    A = I.srp_matrix(w.d, K, seed=9)
+    print(f"\n[case] kmips dtype={dtype} mode={mode}", flush=True)
+    idx = R.Index(w.items, w.item_scales, w.users, w.user_scales, dtype=dtype, k_max=20, num_hash=K, srp=A,
+                  mode=mode, sah_items=30)
+    try:
+        users = np.arange(0, w.m, 7)
+        got = idx.kmips(users, k, beta)
+        full = idx.kmips(users, k, 1.0)
+        lam = O.lambda_table(dtype, w.items, w.item_scales, w.users, w.user_scales, k, user_idx=users)
+        assert np.array_equal(full, lam.T), "probe_frac = 1 must give the exact top-k"
+        assert np.all(got <= lam.T)
+        n2, order = O.item_order(dtype, w.items, w.item_scales)
+        start = 0 if mode == 0 else 30
+        ps = O.partitions(n2, order, 0.5, start=start)
+        _, _, icodes = O.saalsh_index(dtype, w.items, w.item_scales, order, ps, A)
+        ucodes = O.user_codes(dtype, w.users, w.user_scales, A)
+        gic, guc = idx.saalsh()[3], idx.saalsh()[4]
+        inpart = np.zeros(w.n, bool)
+        inpart[order[start:]] = True
+        if not (np.array_equal(icodes[inpart], gic[inpart]) and np.array_equal(ucodes, guc)):
+            pytest.skip("a code bit differs near zero: the probes may differ")   # reported, not compared
+        isc = w.item_scales
+        for i, u in enumerate(users):
+            init = None
+            if mode == 1:
+                init = [O.score(dtype, w.users, w.user_scales, int(u), w.items, isc, int(p)) for p in order[:30]]
+            ref = O.saalsh_kmips(dtype, w.items, isc, n2, order, ps, icodes, ucodes[u], beta, w.users,
+                                 w.user_scales, int(u), k, init=init)
+            assert np.array_equal(got[i], ref), f"user {u}"
+        rec = np.mean([len(np.intersect1d(got[i], lam[:, i])) / k for i in range(len(users))])
+        print(f"recall@{k} at beta={beta}: {rec:.4f}", flush=True)
+    finally:
+        idx.close()
