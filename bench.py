@@ -218,6 +218,45 @@ def main():
                 "query_ms": round(float(np.median([x[1]["ms_total"] for x in runs])), 4),
                 "pairs_to_alg2": int(runs[-1][1]["saalsh_checked"]), "lists_equal_exact_mode": bool(same)}
 
+    def kmips_leg(ex_off, ex_ids):
+        """Side workloads.  (1) SA-ALSH kMIPS on a seeded sample of 5,000 users of an exact
+        index: recall@k of the k best scores found against the exact ones (its lambda rows)
+        and the time per call, for k in {1, 5, 10, 20, 50} and beta in {0.05, 0.1, 0.2}.
+        (2) How well a query's own kMIPS over the users answers RkMIPS: F1 of the k users
+        with the largest <q, u> (numpy FP64 on the host, first 100 queries) against the
+        exact RkMIPS lists of the timed steps."""
+        h = R.rkmips_build_index(items, isc, w.n, users, usc, w.m, w.d, dtype, None, prm, stream)
+        out = {"recall": []}
+        try:
+            exact = np.stack([R.rkmips_get_lambda(h, k, w.m) for k in range(1, k_max + 1)])
+            g = I.rng("queries", w.seed + 2)
+            us = np.sort(g.choice(w.m, min(5000, w.m), replace=False))
+            for beta in (0.05, 0.1, 0.2):
+                for k in [k for k in (1, 5, 10, 20, 50) if k <= k_max]:
+                    R.rkmips_saalsh_kmips(h, us[:64], k, beta, stream)
+                    t0 = time.perf_counter()
+                    sc = R.rkmips_saalsh_kmips(h, us, k, beta, stream)
+                    dt = time.perf_counter() - t0
+                    rec = float(np.mean([len(np.intersect1d(sc[i], exact[:k, u])) / k for i, u in enumerate(us)]))
+                    out["recall"].append({"beta": beta, "k": k, "recall": round(rec, 5),
+                                          "ms_per_call": round(dt * 1e3, 3), "users": int(len(us))})
+        finally:
+            R.rkmips_index_free(h)
+        nqs = min(100, w.nq)
+        Qv = _widen(w.dtype, w.queries[:nqs], None if w.query_scales is None else w.query_scales[:nqs])
+        Uv = _widen(w.dtype, w.users, w.user_scales)
+        S = Qv @ Uv.T
+        f1 = []
+        for qi in range(nqs):
+            k = int(ks[qi])
+            top = np.argpartition(-S[qi], k - 1)[:k]
+            rk = ex_ids[ex_off[qi]:ex_off[qi + 1]]
+            tp = len(np.intersect1d(top, rk))
+            f1.append(1.0 if len(rk) == 0 and k == 0 else 2.0 * tp / (k + len(rk)))
+        out["kmips_as_rkmips_f1"] = round(float(np.mean(f1)), 5)
+        out["kmips_as_rkmips_queries"] = nqs
+        return out
+
     for i in range(args.warmup):
         step()
         log(f"warmup step {i} done")
@@ -300,6 +339,8 @@ def main():
         line["sah"] = sah_leg(off, ids, grid)
         log("lazy leg")
         line["lazy"] = lazy_leg(off, ids)
+        log("kMIPS leg")
+        line["kmips"] = kmips_leg(off, ids)
     if not args.no_serving:
         log("serving replay")
         line["serving"] = serving()
@@ -308,6 +349,19 @@ def main():
         log("cpu baseline")
         line["cpu_baseline"], line["parity_sample"] = cpu_baseline(w, k_max, off, ids, args.cpu_sample_users)
     print(json.dumps(line), flush=True)
+
+
+def _widen(dtype, X, scales):
+    """Stored rows as float64 (BF16 bit patterns, or FP8 e4m3 codes times the row scale)."""
+    if dtype == "f32":
+        return X.astype(np.float64)
+    if dtype == "bf16":
+        return (X.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    c = np.arange(256)
+    e, m = (c >> 3) & 15, c & 7
+    mag = np.where(e == 0, m / 8.0 * 2.0 ** -6, (1 + m / 8.0) * 2.0 ** (e - 7.0))
+    table = np.where(c >= 128, -mag, mag)
+    return table[X] * np.asarray(scales, np.float64)[:, None]
 
 
 TOPK_SOURCES = ("k_topk.hip", "topk.h", "common.h")
