@@ -268,6 +268,23 @@ rkmips_status rkmips_get_blocks(const rkmips_index *idx, int32_t *leaf_users, in
 void rkmips_index_free(rkmips_index *idx);
 
 /*
+ * Insert n_new items into an exact-mode index (not a step of the paper, which builds its
+ * index once; Definition 1 over the grown item set fixes the result).  items: device
+ * [n_new x d] in the index's dtype (item_scales: device FP32 [n_new] for FP8, else NULL);
+ * they receive the ids n, n + 1, ... .  Every user's lambda row takes the canonical scores
+ * of the new items that rank among its k_max best; the item order, the sorted rows, the
+ * SA-ALSH partitions, centroids, radii and codes (same projections) and the block lower
+ * bounds are rebuilt over the grown set.  The result equals a build over the items
+ * [old; new] with the same parameters and projections.  Synchronous on `stream`; no query
+ * batch of the index may run meanwhile.  The raw candidates of the original build are
+ * dropped (rkmips_get_candidates then fails).
+ * Errors: EINVAL (null pointers, n_new < 0, an SAH or lazy index, n beyond 2^30,
+ * non-finite values), ERANGE (magnitudes as in rkmips_build_index), ENOMEM, EDEVICE.
+ */
+rkmips_status rkmips_insert_items(rkmips_index *idx, const void *items, const float *item_scales, int64_t n_new,
+                                  void *stream);
+
+/*
  * SA-ALSH kMIPS (Alg. 2 run without a query, the search that SAH uses inside Alg. 5):
  * for each of the nu users users[i] (original ids, HOST int64), the k best scores that
  * the probes find.  Partitions are visited in norm order; each probes the

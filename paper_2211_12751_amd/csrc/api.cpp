@@ -565,6 +565,96 @@ static void take_build_stats(Index& x)
     x.ms_total = ev_ms(ev[0], ev[3]);
 }
 
+// Item insertion (exact mode).  The new items' canonical scores enter the users' lambda
+// rows (an item changes exactly the rows of the users it would be answered for as a
+// query with k = k_max, ties aside), then the item side of the index is rebuilt as a build
+// over the grown set would make it: norms, order, sorted rows, SA-ALSH partitions,
+// centroids, radii and codes (same projections), and the block lower bounds.  The users,
+// their blocks and codes do not change.
+static void insert_items(Index& x, const void* items, const float* item_scales, int64_t n_new, hipStream_t s)
+{
+    x.wait_ready();
+    const int64_t n0 = x.n, n1 = x.n + n_new;
+    const int eb = elt_bytes(x.dtype);
+    // validation and the range check against the users already in the index
+    DevBuf nstats, n2new;
+    nstats.alloc(sizeof(unsigned long long) * 4);
+    n2new.alloc(sizeof(double) * n_new);
+    unsigned long long* st = (unsigned long long*)nstats.p;
+    launch_norm_stats_init(st, s);
+    launch_norm2(x.dtype, items, item_scales, n_new, x.d, x.d, n2new.d(), st, 0, s);
+    unsigned long long hst[4];
+    HIPC(hipMemcpyAsync(hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    double mi = 0.0;
+    std::memcpy(&mi, &hst[0], 8);
+    mi = std::max(mi, x.max_item_norm * x.max_item_norm);
+    std::memcpy(&hst[0], &mi, 8);
+    const double mu2 = x.max_user_norm * x.max_user_norm;
+    std::memcpy(&hst[1], &mu2, 8);
+    range_check(x, hst);   // also sets max_item_norm over the grown set
+    // the new rows, padded; their scores enter the lambda rows
+    DevBuf newrows, newsc, changed;
+    newrows.alloc((size_t)n_new * x.ld * eb);
+    if (x.dtype == RKMIPS_FP8_E4M3) newsc.alloc(sizeof(float) * n_new);
+    launch_gather_rows(x.dtype, items, x.d, item_scales, nullptr, n_new, x.d, newrows.p, x.ld, newsc.f(), s);
+    changed.alloc(sizeof(unsigned long long));
+    HIPC(hipMemsetAsync(changed.p, 0, sizeof(unsigned long long), s));
+    launch_insert_lambda(x.dtype, x.users.p, x.user_scales.f(), x.user_perm.u32(), x.m, x.d, x.ld, newrows.p,
+                         newsc.f(), n_new, x.lam64.d(), x.lam32.f(), x.prm.k_max, (unsigned long long*)changed.p, s);
+    // every item in original order: the stored rows back at their ids, then the new ones
+    std::vector<uint32_t> order(n0), inv(n0);
+    HIPC(hipMemcpy(order.data(), x.item_order.p, sizeof(uint32_t) * n0, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n0; i++) inv[order[i]] = (uint32_t)i;
+    DevBuf dinv, all, allsc, n2all, st2;
+    dinv.alloc(sizeof(uint32_t) * n0);
+    HIPC(hipMemcpy(dinv.p, inv.data(), sizeof(uint32_t) * n0, hipMemcpyHostToDevice));
+    all.alloc((size_t)n1 * x.ld * eb);
+    if (x.dtype == RKMIPS_FP8_E4M3) allsc.alloc(sizeof(float) * n1);
+    launch_gather_rows(x.dtype, x.items.p, x.ld, x.item_scales.f(), dinv.u32(), n0, x.d, all.p, x.ld, allsc.f(), s);
+    HIPC(hipMemcpyAsync((char*)all.p + (size_t)n0 * x.ld * eb, newrows.p, (size_t)n_new * x.ld * eb,
+                        hipMemcpyDeviceToDevice, s));
+    if (x.dtype == RKMIPS_FP8_E4M3)
+        HIPC(hipMemcpyAsync(allsc.f() + n0, newsc.p, sizeof(float) * n_new, hipMemcpyDeviceToDevice, s));
+    // norms, order and sorted rows as in the build
+    n2all.alloc(sizeof(double) * n1);
+    st2.alloc(sizeof(unsigned long long) * 4);
+    launch_norm_stats_init((unsigned long long*)st2.p, s);
+    launch_norm2(x.dtype, all.p, allsc.f(), n1, x.d, x.ld, n2all.d(), (unsigned long long*)st2.p, 0, s);
+    int64_t cap = 2;
+    while (cap < n1) cap <<= 1;
+    DevBuf keys, vals, tkeys, tvals;
+    keys.alloc(sizeof(uint64_t) * cap);
+    vals.alloc(sizeof(uint32_t) * cap);
+    tkeys.alloc(sizeof(uint64_t) * cap);
+    tvals.alloc(sizeof(uint32_t) * cap);
+    launch_norm_keys(n2all.d(), n1, cap, (uint64_t*)keys.p, (uint32_t*)vals.p, s);
+    sort_pairs((uint64_t*)keys.p, (uint32_t*)vals.p, (uint64_t*)tkeys.p, (uint32_t*)tvals.p, n1, cap, s);
+    x.item_order.alloc(sizeof(uint32_t) * n1);
+    HIPC(hipMemcpyAsync(x.item_order.p, vals.p, sizeof(uint32_t) * n1, hipMemcpyDeviceToDevice, s));
+    x.item_n2.alloc(sizeof(double) * n1);
+    launch_permute_f64(n2all.d(), x.item_order.u32(), n1, x.item_n2.d(), s);
+    x.items.alloc((size_t)n1 * x.ld * eb);
+    if (x.dtype == RKMIPS_FP8_E4M3) x.item_scales.alloc(sizeof(float) * n1);
+    launch_gather_rows(x.dtype, all.p, x.ld, allsc.f(), x.item_order.u32(), n1, x.d, x.items.p, x.ld,
+                       x.item_scales.f(), s);
+    x.n = n1;
+    x.n_lam = n1;
+    // SA-ALSH item side over the grown set, then the block lower bounds
+    PinBuf hnp;
+    hnp.alloc(sizeof(int));
+    start_partitions(x, (int*)hnp.p, s);
+    HIPC(hipStreamSynchronize(s));
+    x.t = *(int*)hnp.p;
+    saalsh_items(x, s);
+    finish_blocks(x, s);
+    // the raw candidates describe the old item set
+    x.cand.reset();
+    x.cand_cnt.reset();
+    x.cand_tau.reset();
+    HIPC(hipStreamSynchronize(s));
+}
+
 void Index::wait_ready()
 {
     if (!ready_ev) return;
@@ -709,6 +799,23 @@ rkmips_status rkmips_build_index(const void* items, const float* item_scales, in
 }
 
 void rkmips_index_free(rkmips_index* idx) { delete (Index*)idx; }
+
+rkmips_status rkmips_insert_items(rkmips_index* idx, const void* items, const float* item_scales, int64_t n_new,
+                                  void* stream)
+{
+    return guarded([&] {
+        if (!idx || (n_new > 0 && !items)) fail(RKMIPS_EINVAL, "NULL argument");
+        Index& x = *(Index*)idx;
+        if (n_new < 0) fail(RKMIPS_EINVAL, "n_new must be >= 0");
+        if (x.prm.mode != RKMIPS_MODE_EXACT) fail(RKMIPS_EINVAL, "item insertion needs an exact-mode index");
+        const bool fp8 = x.dtype == RKMIPS_FP8_E4M3;
+        if (fp8 != (item_scales != nullptr)) fail(RKMIPS_EINVAL, "scales are required exactly for FP8 data");
+        if (x.n + n_new > (int64_t)1 << 30) fail(RKMIPS_EINVAL, "n would exceed 2^30");
+        if (n_new == 0) return;
+        mem::StreamScope scope((hipStream_t)stream);
+        insert_items(x, items, item_scales, n_new, (hipStream_t)stream);
+    });
+}
 
 rkmips_status rkmips_get_info(const rkmips_index* idx, rkmips_index_info* o)
 {

@@ -222,6 +222,11 @@ void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, 
 void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s);
 void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
 void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s);
+// Item insertion: merge the canonical scores of n_new padded item rows into every user's
+// lambda row (users, user_scales, perm: leaf order; lam64/lam32 [k_max x m] by original user).
+void launch_insert_lambda(int dtype, const void* users, const float* user_scales, const uint32_t* perm, int64_t m,
+                          int d, int ld, const void* items, const float* item_scales, int64_t n_new, double* lam64,
+                          float* lam32, int k_max, unsigned long long* changed, hipStream_t s);
 // Per-query ascending lists from the answer bits: counts, offsets (as launch_result_lists),
 // then the ids (those past ids_cap are dropped: the caller checks offsets[nq]).
 void launch_bitmap_lists(const uint32_t* bitmap, int64_t words, int64_t nq, int* cnt, int64_t* offsets,

@@ -639,6 +639,50 @@ __global__ void k_recheck(QueryArgs a, int64_t namb, const unsigned long long* n
     }
 }
 
+// Item insertion: the canonical scores of the new items (rows [n_new x ld]) merged into
+// every user's lambda row (k-major, original user order).  A score above the row's last
+// entry enters at its rank (after equal entries) and the last entry drops out, so the row
+// stays the k_max largest scores over the grown item set.  One thread per user (leaf
+// position u); *changed counts the users whose row changed.
+template <int DT>
+__global__ void k_insert_lambda(const void* users, const float* user_scales, const uint32_t* perm, int64_t m, int d,
+                                int ld, const void* items, const float* item_scales, int64_t n_new, double* lam64,
+                                float* lam32, int k_max, unsigned long long* changed)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= m) return;
+    const int64_t ou = perm[u];
+    const float su = DT == DT_FP8 ? user_scales[u] : 1.f;
+    bool ch = false;
+    for (int64_t j = 0; j < n_new; j++) {
+        const float sp = DT == DT_FP8 ? item_scales[j] : 1.f;
+        const double s = canon_dot2<DT>(users, u, ld, su, items, j, ld, sp, d);
+        if (!(s > lam64[(int64_t)(k_max - 1) * m + ou])) continue;
+        int r = k_max - 1;
+        while (r > 0 && lam64[(int64_t)(r - 1) * m + ou] < s) {
+            lam64[(int64_t)r * m + ou] = lam64[(int64_t)(r - 1) * m + ou];
+            lam32[(int64_t)r * m + ou] = lam32[(int64_t)(r - 1) * m + ou];
+            r--;
+        }
+        lam64[(int64_t)r * m + ou] = s;
+        lam32[(int64_t)r * m + ou] = (float)s;
+        ch = true;
+    }
+    if (ch) atomicAdd(changed, 1ull);
+}
+
+void launch_insert_lambda(int dtype, const void* users, const float* user_scales, const uint32_t* perm, int64_t m,
+                          int d, int ld, const void* items, const float* item_scales, int64_t n_new, double* lam64,
+                          float* lam32, int k_max, unsigned long long* changed, hipStream_t s)
+{
+    if (m <= 0 || n_new <= 0) return;
+    dim3 g((unsigned)((m + 255) / 256)), b(256);
+    if (dtype == DT_F32) hipLaunchKernelGGL(k_insert_lambda<DT_F32>, g, b, 0, s, users, user_scales, perm, m, d, ld, items, item_scales, n_new, lam64, lam32, k_max, changed);
+    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_insert_lambda<DT_BF16>, g, b, 0, s, users, user_scales, perm, m, d, ld, items, item_scales, n_new, lam64, lam32, k_max, changed);
+    else hipLaunchKernelGGL(k_insert_lambda<DT_FP8>, g, b, 0, s, users, user_scales, perm, m, d, ld, items, item_scales, n_new, lam64, lam32, k_max, changed);
+    HIPC(hipGetLastError());
+}
+
 void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s)
 {
     if (namb <= 0) return;

@@ -96,6 +96,7 @@ _sig = {
     "rkmips_saalsh_probe": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, C.c_float, _P, _P, _P]),
     "rkmips_index_free": (None, [_P]),
     "rkmips_saalsh_kmips": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P]),
+    "rkmips_insert_items": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "rkmips_index_save": (C.c_int, [_P, C.c_char_p]),
     "rkmips_index_load": (C.c_int, [C.c_char_p, _P, C.POINTER(_P)]),
     "rkmips_last_error": (C.c_char_p, []),
@@ -257,6 +258,10 @@ def rkmips_saalsh_kmips(idx, users, k, probe_frac, stream=None):
     return out
 
 
+def rkmips_insert_items(idx, items, item_scales, n_new, stream=None):
+    _check(_lib.rkmips_insert_items(idx, _ptr(items), _ptr(item_scales), n_new, _stream(stream)))
+
+
 def rkmips_index_save(idx, path):
     _check(_lib.rkmips_index_save(idx, os.fsencode(path)))
 
@@ -362,6 +367,14 @@ class Index:
     def kmips(self, users, k, probe_frac, stream=None):
         """SA-ALSH kMIPS scores [len(users) x k] (descending, -inf padded)."""
         return rkmips_saalsh_kmips(self.h, users, k, probe_frac, stream)
+
+    def insert(self, items, item_scales=None, stream=None):
+        """Add items (numpy storage arrays or device tensors); they get the next ids."""
+        ti = items if isinstance(items, torch.Tensor) else to_device(items)
+        ts = item_scales if (item_scales is None or isinstance(item_scales, torch.Tensor)) else to_device(item_scales)
+        rkmips_insert_items(self.h, ti, ts, int(ti.shape[0]), stream)
+        self.info = rkmips_get_info(self.h)
+        self.n = int(self.info["n"])
 
     def save(self, path):
         rkmips_index_save(self.h, path)
