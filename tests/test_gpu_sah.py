@@ -136,3 +136,34 @@ def test_lazy_mode_is_exact(R, dtype, n, m, d, n_prime, flags):
         assert st["saalsh_checked"] > 0
     finally:
         idx.close()
+
+
+def test_sah_small_p_prime_empty_batch_and_serving(R):
+    """|P'| = 5 < k for most queries (L_u^k = -inf there, so every user reaches the norm
+    test and Alg. 2 starts with phi = -inf), an empty batch, and the continuous-batching
+    server on an SAH index, all against the reference."""
+    w = I.make("c2", n=400, m=700, d=16, nq=20, seed=63)
+    ks = np.array([1, 5, 10, 20] * 5, np.int32)
+    A = I.srp_matrix(w.d, 64, seed=13)
+    print("\n[case] sah n'=5, empty batch, serving", flush=True)
+    idx = R.Index(w.items, None, w.users, None, dtype="f32", k_max=20, num_hash=64, srp=A, mode=R.MODE_SAH,
+                  sah_items=5, probe_frac=0.1)
+    try:
+        assert idx.query(w.queries[:0], None, np.zeros(0, np.int32)) == []
+        got = idx.query(w.queries, None, ks)
+        n2, order = O.item_order("f32", w.items, None)
+        ps = O.partitions(n2, order, 0.5, start=5)
+        _, _, icodes = O.saalsh_index("f32", w.items, None, order, ps, A)
+        gic, guc = idx.saalsh()[3], idx.saalsh()[4]
+        inpart = np.zeros(w.n, bool)
+        inpart[order[5:]] = True
+        if np.array_equal(icodes[inpart], gic[inpart]) and np.array_equal(O.user_codes("f32", w.users, None, A), guc):
+            ref = O.sah_rkmips("f32", w.items, None, w.users, None, w.queries, None, ks, 20, 5, 0.5, 0.1, A)
+            for qi in range(len(ks)):
+                assert np.array_equal(np.asarray(got[qi]), ref[qi]), f"query {qi}"
+        arr = np.arange(len(ks), dtype=np.int64) * 50
+        served, lat, st = idx.serve(w.queries, None, ks, arr, max_batch=8, num_streams=2)
+        for qi in range(len(ks)):
+            assert np.array_equal(np.asarray(served[qi]), np.asarray(got[qi])), f"served query {qi}"
+    finally:
+        idx.close()
