@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sah", action="store_true", help="skip the SAH-mode and lazy-mode legs")
+    ap.add_argument("--sah-force", action="store_true", help="run the SAH, lazy and kMIPS legs at any size")
     ap.add_argument("--sah-sweep", action="store_true",
                     help="SAH leg over K in {64,128,256} x b in {0.3,0.5,0.7} x beta in {0.05,0.1,0.2}")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -332,7 +333,10 @@ def main():
                      "mma_dtype": mma, "mma_terms": int(infos[-1]["mma_terms"])},
     }
 
-    if not args.no_sah:
+    if not args.no_sah and float(w.m) * w.n > 5e9 and not args.sah_force:
+        # the SAH and lazy batches do per-user work over whole partitions: minutes at c3 size
+        line["sah"] = line["lazy"] = line["kmips"] = "skipped: m*n above 5e9 (--sah-force runs them)"
+    elif not args.no_sah:
         log("SAH leg")
         grid = ([(K, b, beta) for K in (64, 128, 256) for b in (0.3, 0.5, 0.7) for beta in (0.05, 0.1, 0.2)]
                 if args.sah_sweep else [(128, 0.5, beta) for beta in (0.05, 0.1, 0.2)])
