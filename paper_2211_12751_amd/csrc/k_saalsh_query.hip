@@ -147,11 +147,86 @@ __device__ double block_kth(const double* vals, int64_t cnt, int k, int* hist, i
 // with the most equal code bits (equal counts: earlier position first) are scored and
 // their scores appended to cand at *ccount.  Called by the whole workgroup; ends with a
 // barrier, after which *ccount holds the new count.
+// Canonical scores (as sq_dot) of the candidates whose positions fill cand[c_begin,
+// c_end), in place.  Each wave takes 64 candidates at a time, one per lane; their rows
+// pass through LDS in 64-byte column slices, four lanes loading one row's slice with
+// consecutive 16-byte loads (one request per row and slice instead of one per lane and 16
+// bytes), after which each lane continues its own index-order sum.  rows: the calling
+// wave's 64 x SS_PITCH bytes of LDS.
+static constexpr int SS_PITCH = 64 + 16;
+
+template <int DT>
+__device__ void score_staged(const SaQueryArgs& a, int64_t u, float su, double* cand, int c_begin, int c_end,
+                             int64_t s0, int64_t s1, uint8_t* rows)
+{
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int PER = 16 / EB;
+    const int l = lane_id(), wv = threadIdx.x >> 6;
+    const int64_t RB = (int64_t)a.ld * EB;
+    const int nch = (a.d * EB + 15) / 16;   // 16-byte chunks that hold the d elements
+    const uint8_t* ur = (const uint8_t*)a.users + u * RB;
+    for (int base = c_begin + wv * 64; base < c_end; base += SQ_T) {
+        const int idx = base + l;
+        const bool in = idx < c_end;
+        int p = -1;
+        if (in) {
+            const int64_t q = (int64_t)__double_as_longlong(cand[idx]);
+            if (q >= s0 && q < s1) p = (int)q;   // always: every slot holds a position of the partition
+        }
+        double acc = 0.0;
+        for (int ch0 = 0; ch0 < nch; ch0 += 4) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int k = i * 64 + l, r = k >> 2, c = k & 3;
+                const int pr = __shfl(p, r);
+                i32x4 v = {0, 0, 0, 0};
+                if (pr >= 0 && ch0 + c < nch) v = *(const i32x4*)((const uint8_t*)a.items + (int64_t)pr * RB + (ch0 + c) * 16);
+                *(i32x4*)(rows + r * SS_PITCH + c * 16) = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (p >= 0) {
+                for (int c = 0; c < 4; c++) {
+                    const int ch = ch0 + c;
+                    if (ch >= nch) break;
+                    const i32x4 y4 = *(const i32x4*)(rows + l * SS_PITCH + c * 16);
+                    const i32x4 x4 = *(const i32x4*)(ur + ch * 16);
+                    const int lim = a.d - ch * PER < PER ? a.d - ch * PER : PER;
+#pragma unroll
+                    for (int e = 0; e < PER; e++) {
+                        if (e >= lim) break;
+                        float x, y;
+                        if constexpr (DT == DT_F32) {
+                            x = __int_as_float(x4[e]);
+                            y = __int_as_float(y4[e]);
+                        } else if constexpr (DT == DT_BF16) {
+                            x = bf16_to_f32((uint16_t)((uint32_t)x4[e >> 1] >> (16 * (e & 1))));
+                            y = bf16_to_f32((uint16_t)((uint32_t)y4[e >> 1] >> (16 * (e & 1))));
+                        } else {
+                            x = e4m3_to_f32((uint8_t)((uint32_t)x4[e >> 2] >> (8 * (e & 3))));
+                            y = e4m3_to_f32((uint8_t)((uint32_t)y4[e >> 2] >> (8 * (e & 3))));
+                        }
+                        acc = __fma_rn((double)x, (double)y, acc);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (in) {
+            if (p >= 0) {
+                if constexpr (DT == DT_FP8) acc = ((double)su * (double)a.item_scales[p]) * acc;
+                cand[idx] = acc;
+            } else {
+                cand[idx] = -__builtin_inf();
+            }
+        }
+    }
+}
+
 // whist: [SQ_T / 64][SQ_T + 1] ints, one collision-count histogram per wave.
 template <int DT>
 __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const uint32_t* ucode, int W,
                                 int64_t s0, int64_t s1, double* cand, int (*whist)[SQ_T + 1], int* sh,
-                                int* ccount)
+                                int* ccount, uint8_t* rows)
 {
     const int tid = threadIdx.x;
     const int64_t sz = s1 - s0;
@@ -213,15 +288,7 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
     // scores of the new candidates, every lane busy (the selection keeps about one item
     // in 1/beta, so scoring inside its loop would leave most lanes idle)
     const int c_end = *ccount;
-    for (int i = c_begin + tid; i < c_end; i += SQ_T) {
-        const int64_t p = (int64_t)__double_as_longlong(cand[i]);
-        if (p < s0 || p >= s1) {   // cannot happen: every slot here holds a position of the partition
-            cand[i] = -__builtin_inf();
-            continue;
-        }
-        const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-        cand[i] = sq_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
-    }
+    score_staged<DT>(a, u, su, cand, c_begin, c_end, s0, s1, rows + (tid >> 6) * 64 * SS_PITCH);
     __syncthreads();
 }
 
@@ -229,6 +296,7 @@ template <int DT>
 __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* scratch, int64_t scratch_stride)
 {
     __shared__ int whist[SQ_T / 64][SQ_T + 1];
+    __shared__ __attribute__((aligned(16))) uint8_t rows[SQ_T / 64][64 * SS_PITCH];
     __shared__ int sh[4 + SQ_T + 1];   // [0, 4): results; [4, 4 + K + 1]: counts
     __shared__ int ccount;
     int* hist = whist[0];
@@ -253,7 +321,7 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
             const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
             const double mu = sqrt(a.item_n2[s0]) * unorm;
             if (phi > mu) { ans = 1; break; }
-            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount);
+            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount, &rows[0][0]);
             const int64_t ncand = ccount;
             __syncthreads();
             phi = ncand >= k ? block_kth(cand, ncand, k, hist, sh) : -__builtin_inf();
@@ -340,11 +408,12 @@ __device__ void block_top_sorted(double* vals, int64_t cnt, int kstar, double* t
 // (t + 1) kstar ...].  The probes stop once row j's kstar-th score exceeds mu_j: every
 // pair of the batch (k <= kstar) is then answered yes at partition j at the latest.
 template <int DT>
-__global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* user_of_slot, const int* nslots,
+__global__ __launch_bounds__(SQ_T) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_sah_user(SaQueryArgs a, const int* user_of_slot, const int* nslots,
                                                   int64_t c0, int64_t chunk, int kstar, double* tab,
                                                   double* scratch, int64_t scratch_stride, int* jlast)
 {
     __shared__ int whist[SQ_T / 64][SQ_T + 1];
+    __shared__ __attribute__((aligned(16))) uint8_t rows[SQ_T / 64][64 * SS_PITCH];
     __shared__ int sh[4 + SQ_T + 1];   // [0, 4): results; [4, 4 + K + 1]: counts
     __shared__ int tcount;
     __shared__ int ccount;
@@ -377,7 +446,7 @@ __global__ __launch_bounds__(SQ_T) void k_sah_user(SaQueryArgs a, const int* use
             const int64_t s0 = a.part_start[j], s1 = a.part_start[j + 1];
             const double mu = sqrt(a.item_n2[s0]) * unorm * a.mu_scale;
             if (phi_min > mu) break;
-            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount);
+            probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount, &rows[0][0]);
             const int64_t ncand = ccount;
             __syncthreads();
             block_top_sorted(cand, ncand, kstar, top, hist, sh, &tcount);
