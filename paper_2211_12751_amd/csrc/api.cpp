@@ -732,6 +732,7 @@ extern "C" {
 void rkmips_default_params(rkmips_params* p)
 {
     if (!p) return;
+    std::memset(p, 0, sizeof *p);   // every field, including ones added later, starts at 0
     p->k_max = 50;
     p->leaf_size = 64;
     p->num_hash = 128;
@@ -739,8 +740,9 @@ void rkmips_default_params(rkmips_params* p)
     p->b = 0.5f;
     p->probe_frac = 0.1f;
     p->seed = 221112751ull;
-    p->mode = 0;
+    p->mode = RKMIPS_MODE_EXACT;
     p->flags = 0;
+    p->sah_items = 0;
 }
 
 const char* rkmips_last_error(void) { return g_last_error.c_str(); }

@@ -38,6 +38,12 @@ def test_default_params(R):
     p = R.rkmips_default_params()
     assert (p.k_max, p.leaf_size, p.num_hash, p.topk_slack) == (50, 64, 128, 14)
     assert abs(p.b - 0.5) < 1e-7 and p.seed == 221112751
+    # every field is set, whatever the struct held before (C callers may pass stack garbage)
+    q = R.rkmips_params()
+    C.memset(C.byref(q), 0x5A, C.sizeof(q))
+    R._lib.rkmips_default_params(C.byref(q))
+    assert (q.mode, q.flags, q.sah_items) == (R.MODE_EXACT, 0, 0)
+    assert (q.k_max, q.leaf_size, q.num_hash, q.topk_slack) == (50, 64, 128, 14)
 
 
 def test_argument_errors_before_device_work(R):
