@@ -138,12 +138,14 @@ void rkmips_default_params(rkmips_params *p);
  * device FP32 [n] / [m] for FP8 data, else NULL.  srp_proj: device FP32
  * [(d+1) x num_hash] row-major Gaussian projection matrix (column h is the vector a
  * of one hash function), or NULL to draw it from p->seed inside the library.
- * p: NULL for defaults.  Returns once every host-side check is done and the rest of
- * the build is queued on `stream` (the last part, FP64 refinement and block bounds,
- * may still be running): work queued on `stream` afterwards sees the complete index,
- * query batches on other streams wait for it on the device, and the host-side getters
- * (info, lambda, blocks, candidates, SA-ALSH data) wait for it on the host.  The input
- * arrays must stay valid until the build is complete (rkmips_get_info waits for it).
+ * p: NULL for defaults.
+ * Completion (stream-ordered, not synchronous): the call returns once every host-side
+ * check is done and the rest of the build is queued on `stream` (the last part, FP64
+ * refinement and block bounds, may still be running).  Work queued on `stream`
+ * afterwards sees the complete index, query batches on other streams wait for it on the
+ * device, and the host-side getters (info, stats, lambda, blocks, candidates, SA-ALSH
+ * data) wait for it on the host.  rkmips_index_wait gives the synchronous form.  The
+ * input arrays must stay valid until the build is complete.
  * Errors: EINVAL (null pointers, n, m, d < 1, d > 256, bad params, non-finite
  * values), ERANGE (max||u|| * max||p|| beyond 1e30 or a non-zero vector norm below
  * 1e-30, where FP32 bounds would lose exactness), ENOMEM, EDEVICE.
@@ -153,13 +155,19 @@ rkmips_status rkmips_build_index(const void *items, const float *item_scales, in
                                  int32_t d, int32_t dtype, const float *srp_proj,
                                  const rkmips_params *p, void *stream, rkmips_index **out);
 
+/* Wait on the host until the build of idx is complete (the synchronous form of
+ * rkmips_build_index).  Errors: EINVAL (NULL), EDEVICE. */
+rkmips_status rkmips_index_wait(rkmips_index *idx);
+
 /*
  * Answer a batch of queries (Alg. 5 over all blocks: exact decisions, or the SAH
  * decisions of RKMIPS_MODE_SAH, see rkmips_params.mode).
  * queries: device [nq x d] in the index's dtype (query_scales: device FP32 [nq] for
- * FP8, else NULL).  ks: HOST int32 [nq], 1 <= ks[i] <= k_max.  flags: RKMIPS_FLAG_*
- * added to the index defaults for this call.  The work is enqueued on `stream`;
- * *out receives a result handle whose contents are valid after rkmips_result_wait.
+ * FP8, else NULL).  ks: DEVICE int32 [nq], 1 <= ks[i] <= k_max.  flags: RKMIPS_FLAG_*
+ * added to the index defaults for this call.  The host groups the queries by k, so the
+ * call copies ks to the host in order on `stream` and waits for that copy (and so for
+ * the stream's earlier work); the batch itself is then enqueued on `stream`, and *out
+ * receives a result handle whose contents are valid after rkmips_result_wait.
  * nq = 0 is allowed (empty result).  Errors: EINVAL, ERANGE (a k out of range),
  * ENOMEM, EDEVICE.  Conditions that need the device data (a non-finite query value:
  * EINVAL; a query norm outside [1e-30, 1e30]: ERANGE) are returned by
@@ -168,6 +176,13 @@ rkmips_status rkmips_build_index(const void *items, const float *item_scales, in
 rkmips_status rkmips_query_batch(rkmips_index *idx, const void *queries, const float *query_scales,
                                  int64_t nq, const int32_t *ks, int32_t flags, void *stream,
                                  rkmips_result **out);
+
+/* rkmips_query_batch with ks in HOST memory (int32 [nq]): no host wait at all, the
+ * batch queues behind the stream's earlier work (for example a build on the same
+ * stream).  Same outputs and errors. */
+rkmips_status rkmips_query_batch_hostk(rkmips_index *idx, const void *queries, const float *query_scales,
+                                       int64_t nq, const int32_t *ks, int32_t flags, void *stream,
+                                       rkmips_result **out);
 
 /* Block until the batch is complete and its host-side outputs are filled. */
 rkmips_status rkmips_result_wait(rkmips_result *r);
@@ -216,6 +231,22 @@ typedef struct {
 } rkmips_index_info;
 
 rkmips_status rkmips_get_info(const rkmips_index *idx, rkmips_index_info *out);
+
+/* Statistics of the precision pattern: the fast (matrix-core) lambda before and after
+ * the FP64 refinement, the certificate fallbacks of the build, and the counters of
+ * every query batch of this index completed so far (summed over batches). */
+typedef struct {
+    double max_rel_err_raw;      /* max |s_fast - s64| / |s64| over the rescored candidates */
+    double max_rel_err_lambda32; /* max |lambda32 - lambda64| / |lambda64| (refined)         */
+    int64_t cert_failures;       /* users whose lambda row was rescored in full in FP64      */
+    double fallback_rate;        /* cert_failures / m                                       */
+    int64_t batches, queries;    /* completed batches and their queries                     */
+    rkmips_query_stats query;    /* their counters, summed (ms_total: summed device time)   */
+    double recheck_rate;         /* query.pairs_rechecked / query.pairs_scored              */
+} rkmips_stats;
+
+/* Waits for the build on the host.  Errors: EINVAL (NULL). */
+rkmips_status rkmips_get_stats(const rkmips_index *idx, rkmips_stats *out);
 
 /* lambda_u^(k) for every user in ORIGINAL order: host double [m] (k in 1..k_max). */
 rkmips_status rkmips_get_lambda(const rkmips_index *idx, int32_t k, double *out_m);

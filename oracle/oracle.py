@@ -257,16 +257,19 @@ def cos_to_centres(dtype, U, U_scales, leaf_users, block_start, centres):
     leaf_users = np.asarray(leaf_users, np.int64)
     block_start = np.asarray(block_start, np.int64)
     C_ = np.asarray(centres, np.float64)
-    out = np.empty(len(leaf_users))
+    out = np.full(len(leaf_users), np.nan)
     for b in range(len(block_start) - 1):
         idx = leaf_users[block_start[b]:block_start[b + 1]]
-        out[block_start[b]:block_start[b + 1]] = (V[idx] @ C_[b]) / np.sqrt(np.sum(V[idx] * V[idx], axis=1))
+        nrm = np.sqrt(np.sum(V[idx] * V[idx], axis=1))
+        live = nrm > 0          # a zero user has no direction and no angle (NaN)
+        out[block_start[b]:block_start[b + 1]][live] = (V[idx][live] @ C_[b]) / nrm[live]
     return out
 
 
 def block_lower_bounds(dtype, U, U_scales, lam, leaf_users, block_start):
     """float64 [k_max x B]: L^j(B) = min over the users of B of lambda_u^(j) / ||u||
-    (Alg. 4), with lam k-major in original user order."""
+    (Alg. 4), with lam k-major in original user order.  A block that holds a zero user
+    gets -inf: such a user has no direction, so no bound may prune its block."""
     V = values(dtype, U, U_scales)
     norms = np.sqrt(np.sum(V * V, axis=1))
     lam = np.asarray(lam, np.float64)
@@ -276,11 +279,14 @@ def block_lower_bounds(dtype, U, U_scales, lam, leaf_users, block_start):
     out = np.empty((lam.shape[0], nb))
     for b in range(nb):
         idx = leaf_users[block_start[b]:block_start[b + 1]]
+        if np.any(norms[idx] == 0):
+            out[:, b] = -np.inf
+            continue
         out[:, b] = np.min(lam[:, idx] / norms[idx][None, :], axis=1)
     return out
 
 
-def sah_rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, n_prime, b, beta, A):
+def sah_rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, n_prime, b, beta, A, stats=None):
     """The approximate SAH method, per query an ascending user-ID list.
 
     Index (Alg. 4): items in descending canonical norm; P' = the first ``n_prime`` of
@@ -295,6 +301,9 @@ def sah_rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, n_prime,
                                               n2(p_k) = 0 when k > n);
       otherwise                        -> Alg. 2 over the partitions of P minus P', its
                                           candidates starting from u's scores on P'.
+    ``stats`` (a dict, optional) receives how each surviving pair was decided:
+    "norm_yes" and "alg2" are the pair counts, "norm_pairs" and "alg2_pairs" the
+    (query, user) lists.
     """
     P, U, Q = _c(P), _c(U), _c(Q)
     n = P.shape[0]
@@ -309,6 +318,7 @@ def sah_rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, n_prime,
     ucodes = user_codes(dtype, U, U_scales, A)
     ks = np.asarray(ks)
     surv = member(dtype, U, U_scales, Q, Q_scales, ks, lam)
+    norm_pairs, alg2_pairs = [], []
     out = []
     for qi in range(Q.shape[0]):
         k = int(ks[qi])
@@ -318,13 +328,18 @@ def sah_rkmips(dtype, P, P_scales, U, U_scales, Q, Q_scales, ks, k_max, n_prime,
             s = score(dtype, U, U_scales, int(u), Q, Q_scales, qi)
             if s >= 0.0 and s * s >= float(n2u[u]) * pk2:
                 keep.append(u)
+                norm_pairs.append((qi, int(u)))
                 continue
+            alg2_pairs.append((qi, int(u)))
             init = [score(dtype, U, U_scales, int(u), Pp, Pps, j) for j in range(len(top))]
             ans, _ = saalsh_decide(dtype, P, P_scales, n2p, order, ps, icodes, ucodes[u], beta,
                                    U, U_scales, int(u), Q, Q_scales, qi, k, init=init)
             if ans:
                 keep.append(u)
         out.append(np.asarray(keep, dtype=np.int32))
+    if stats is not None:
+        stats.update(norm_yes=len(norm_pairs), alg2=len(alg2_pairs), norm_pairs=norm_pairs,
+                     alg2_pairs=alg2_pairs)
     return out
 
 

@@ -122,7 +122,7 @@ struct Events {
 };
 
 // ---------------------------------------------------------------- build
-static void validate_params(const rkmips_params& p)
+void validate_params(const rkmips_params& p)
 {
     if (p.k_max < 1 || p.k_max > 256) fail(RKMIPS_EINVAL, "k_max must be in [1, 256]");
     if (p.leaf_size < 1 || p.leaf_size > 64) fail(RKMIPS_EINVAL, "leaf_size must be in [1, 64]");
@@ -816,6 +816,33 @@ rkmips_status rkmips_insert_items(rkmips_index* idx, const void* items, const fl
         if (n_new == 0) return;
         mem::StreamScope scope((hipStream_t)stream);
         insert_items(x, items, item_scales, n_new, (hipStream_t)stream);
+    });
+}
+
+rkmips_status rkmips_index_wait(rkmips_index* idx)
+{
+    return guarded([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "NULL argument");
+        ((Index*)idx)->wait_ready();
+    });
+}
+
+rkmips_status rkmips_get_stats(const rkmips_index* idx, rkmips_stats* o)
+{
+    return guarded([&] {
+        if (!idx || !o) fail(RKMIPS_EINVAL, "NULL argument");
+        Index& x = *(Index*)idx;
+        x.wait_ready();
+        std::memset(o, 0, sizeof *o);
+        o->max_rel_err_raw = x.max_rel_err_raw;
+        o->max_rel_err_lambda32 = x.max_rel_err_l32;
+        o->cert_failures = x.cert_failures;
+        o->fallback_rate = (double)x.cert_failures / (double)x.m;
+        std::lock_guard<std::mutex> g(x.stats_mu);
+        o->batches = x.n_batches;
+        o->queries = x.n_queries;
+        o->query = x.qsum;
+        o->recheck_rate = x.qsum.pairs_scored > 0 ? (double)x.qsum.pairs_rechecked / (double)x.qsum.pairs_scored : 0.0;
     });
 }
 

@@ -115,6 +115,21 @@ struct Index {
     void give_ws(Workspace* w);
     ~Index();
 
+    // counters of every batch completed so far (rkmips_get_stats)
+    std::mutex stats_mu;
+    int64_t n_batches = 0, n_queries = 0;
+    rkmips_query_stats qsum{};
+    void add_batch_stats(int64_t nq, const rkmips_query_stats& st)
+    {
+        std::lock_guard<std::mutex> g(stats_mu);
+        n_batches++;
+        n_queries += nq;
+        qsum.pairs_total += st.pairs_total; qsum.pairs_block_pruned += st.pairs_block_pruned;
+        qsum.pairs_vector_pruned += st.pairs_vector_pruned; qsum.pairs_scored += st.pairs_scored;
+        qsum.pairs_rechecked += st.pairs_rechecked; qsum.saalsh_checked += st.saalsh_checked;
+        qsum.saalsh_rejects += st.saalsh_rejects; qsum.results += st.results; qsum.ms_total += st.ms_total;
+    }
+
     double ms_norms = 0, ms_lambda = 0, ms_refine = 0, ms_saalsh = 0, ms_cone = 0, ms_total = 0;
     double ms_seed = 0, ms_topk = 0;
     PinBuf h_lam_stats;               // lambda build statistics, read once the build is complete

@@ -22,6 +22,9 @@ void hip_check(hipError_t e, const char* what);
 // of microseconds of wake-up latency to every host round trip).
 void host_wait(hipEvent_t e);
 
+// Throws EINVAL unless every build parameter is in its documented range.
+void validate_params(const rkmips_params& p);
+
 // Padded row length (elements) used for the stored copies of all vector sets.
 int padded_dim(int d, int dtype);
 int elt_bytes(int dtype);
@@ -211,6 +214,11 @@ struct QueryArgs {
     // the FP64 recheck, which answers yes when s >= ||u|| ||p_k|| and otherwise lists
     // the pair (same key as amb) for Alg. 2
     int sah;
+    // relative widening of n2(u) n2(p_k) in that test: 0 in SAH mode (the paper's test);
+    // 2^-40 in the exact lazy mode, where the canonical scores may exceed ||u|| ||p|| by
+    // their rounding (below (d + 1) 2^-53 relative for d <= 256) and the squared-norm
+    // products round too (both sides below 2^-43 in total)
+    double norm_widen;
     const double* item_n2; int64_t n_items;          // sorted canonical squared norms
     const double* user_n2;                           // leaf order
     unsigned long long* sah_pairs; unsigned long long* sah_count;   // capacity amb_cap

@@ -617,9 +617,11 @@ __global__ void k_recheck(QueryArgs a, int64_t namb, const unsigned long long* n
             if (a.sah) {
                 // Alg. 5: yes when s(u,q) >= ||u|| ||p_k|| (as s >= 0, s^2 >= n2(u) n2(p_k),
                 // each product rounded once: fma with a zero addend, never fused with
-                // anything else), else Alg. 2 decides
+                // anything else; the lazy mode widens the right side), else Alg. 2 decides
                 const double pk2 = k <= a.n_items ? a.item_n2[k - 1] : 0.0;
-                if (!(s >= 0.0 && __fma_rn(s, s, 0.0) >= __fma_rn(a.user_n2[u], pk2, 0.0))) {
+                const double un = __fma_rn(a.user_n2[u], pk2, 0.0);
+                const double thr = a.norm_widen > 0.0 ? __fma_rn(un, a.norm_widen, un) : un;
+                if (!(s >= 0.0 && __fma_rn(s, s, 0.0) >= thr)) {
                     const unsigned long long pos = atomicAdd(a.sah_count, 1ull);
                     if ((int64_t)pos < a.amb_cap) {
                         a.sah_pairs[pos] = key;

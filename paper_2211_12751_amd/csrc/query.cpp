@@ -179,6 +179,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.bad = (int*)(c + 2);
     a.stats = c + 8;
     a.sah = x.prm.mode != RKMIPS_MODE_EXACT;
+    a.norm_widen = x.prm.mode == RKMIPS_MODE_LAZY ? std::ldexp(1.0, -40) : 0.0;
     a.item_n2 = x.item_n2.d(); a.n_items = x.n; a.user_n2 = x.user_n2.d();
     a.sah_pairs = (unsigned long long*)w.sah_pairs.p; a.sah_count = c + 6;
     a.sah_score = w.sah_score.d(); a.sah_need = (unsigned char*)w.sah_need.p;
@@ -425,16 +426,14 @@ static rkmips_status qguard(F&& f)
 
 extern "C" {
 
-rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const float* query_scales, int64_t nq,
-                                 const int32_t* ks, int32_t flags, void* stream, rkmips_result** out)
+}  // extern "C"
+
+// Both query entry points: ks are host values here.
+static void query_batch_host(rkmips_index* idx, const void* queries, const float* query_scales, int64_t nq,
+                             const int32_t* ks, int32_t flags, void* stream, rkmips_result** out)
 {
-    return qguard([&] {
-        if (!out) fail(RKMIPS_EINVAL, "out is NULL");
-        *out = nullptr;
-        if (!idx) fail(RKMIPS_EINVAL, "index is NULL");
+    {
         Index& x = *(Index*)idx;
-        if (nq < 0 || nq > ((int64_t)1 << 31) - 2) fail(RKMIPS_EINVAL, "nq out of range");
-        if (nq > 0 && (!queries || !ks)) fail(RKMIPS_EINVAL, "queries/ks is NULL");
         const bool fp8 = x.dtype == RKMIPS_FP8_E4M3;
         if (nq > 0 && fp8 && !query_scales) fail(RKMIPS_EINVAL, "FP8 queries need scales");
         if (!fp8 && query_scales) fail(RKMIPS_EINVAL, "scales are only for FP8 data");
@@ -467,6 +466,53 @@ rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const f
         }
         r->ws = w;
         *out = r.release();
+    }
+}
+
+static void query_batch_checks(rkmips_index* idx, const void* queries, int64_t nq, const int32_t* ks,
+                               rkmips_result** out)
+{
+    if (!out) fail(RKMIPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!idx) fail(RKMIPS_EINVAL, "index is NULL");
+    if (nq < 0 || nq > ((int64_t)1 << 31) - 2) fail(RKMIPS_EINVAL, "nq out of range");
+    if (nq > 0 && (!queries || !ks)) fail(RKMIPS_EINVAL, "queries/ks is NULL");
+}
+
+extern "C" {
+
+rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const float* query_scales, int64_t nq,
+                                 const int32_t* ks, int32_t flags, void* stream, rkmips_result** out)
+{
+    return qguard([&] {
+        query_batch_checks(idx, queries, nq, ks, out);
+        // the k values are read on the host, which groups the queries by k: a copy
+        // ordered after the stream's earlier work, then a host wait for that copy alone
+        PinBuf hk;
+        if (nq > 0) {
+            hipStream_t s = (hipStream_t)stream;
+            mem::StreamScope scope(s);
+            hk.alloc(sizeof(int32_t) * (size_t)nq);
+            HIPC(hipMemcpyAsync(hk.p, ks, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost, s));
+            struct Ev {
+                hipEvent_t e = nullptr;
+                ~Ev() { if (e) (void)hipEventDestroy(e); }
+            } ev;
+            HIPC(hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
+            HIPC(hipEventRecord(ev.e, s));
+            host_wait(ev.e);
+        }
+        query_batch_host(idx, queries, query_scales, nq, (const int32_t*)hk.p, flags, stream, out);
+    });
+}
+
+rkmips_status rkmips_query_batch_hostk(rkmips_index* idx, const void* queries, const float* query_scales,
+                                       int64_t nq, const int32_t* ks, int32_t flags, void* stream,
+                                       rkmips_result** out)
+{
+    return qguard([&] {
+        query_batch_checks(idx, queries, nq, ks, out);
+        query_batch_host(idx, queries, query_scales, nq, ks, flags, stream, out);
     });
 }
 
@@ -484,6 +530,8 @@ rkmips_status rkmips_result_wait(rkmips_result* r)
     if (st != RKMIPS_OK) {
         r->offsets.assign(r->nq + 1, 0);
         r->ids.clear();
+    } else {
+        r->idx->add_batch_stats(r->nq, r->st);
     }
     r->idx->give_ws(r->ws);
     r->ws = nullptr;

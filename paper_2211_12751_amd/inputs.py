@@ -24,6 +24,9 @@ Storage encodings:
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
+import os
+
 import numpy as np
 
 BASE_SEED = 221112751
@@ -58,24 +61,40 @@ def rng(stream: str, seed: int = BASE_SEED) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, STREAMS[stream]])))
 
 
+def _workers() -> int:
+    return max(1, min(8, os.cpu_count() or 1))
+
+
 def draw(kind, rows: int, d: int, g: np.random.Generator) -> np.ndarray:
-    """rows x d float32 matrix of the given kind, drawn in fixed-size row chunks."""
+    """rows x d float32 matrix of the given kind, drawn in fixed-size row chunks.
+
+    The random numbers are drawn chunk after chunk from the one generator (so any
+    prefix of rows is reproducible); the per-chunk arithmetic that shapes them runs
+    on worker threads."""
     name, par = kind
+    if name not in ("lndir", "shift", "normal"):
+        raise ValueError(f"unknown distribution {name!r}")
     out = np.empty((rows, d), dtype=np.float32)
-    for r0 in range(0, rows, _CHUNK):
-        r1 = min(rows, r0 + _CHUNK)
+
+    def shape(r0, x, rad):
         if name == "lndir":
-            x = g.standard_normal((r1 - r0, d))
             nrm = np.sqrt(np.einsum("ij,ij->i", x, x))
             nrm[nrm == 0] = 1.0
-            rad = np.exp(par * g.standard_normal(r1 - r0))
-            out[r0:r1] = (x * (rad / nrm)[:, None]).astype(np.float32)
+            out[r0:r0 + len(x)] = (x * (np.exp(par * rad) / nrm)[:, None]).astype(np.float32)
         elif name == "shift":
-            out[r0:r1] = (np.abs(g.standard_normal((r1 - r0, d))) + par).astype(np.float32)
-        elif name == "normal":
-            out[r0:r1] = g.standard_normal((r1 - r0, d)).astype(np.float32)
+            out[r0:r0 + len(x)] = (np.abs(x) + par).astype(np.float32)
         else:
-            raise ValueError(f"unknown distribution {name!r}")
+            out[r0:r0 + len(x)] = x.astype(np.float32)
+
+    with cf.ThreadPoolExecutor(_workers()) as ex:
+        futs = []
+        for r0 in range(0, rows, _CHUNK):
+            r1 = min(rows, r0 + _CHUNK)
+            x = g.standard_normal((r1 - r0, d))
+            rad = g.standard_normal(r1 - r0) if name == "lndir" else None
+            futs.append(ex.submit(shape, r0, x, rad))
+        for f in futs:
+            f.result()
     return out
 
 
@@ -112,27 +131,35 @@ def fp8_e4m3_codes(x: np.ndarray):
 
     Returns (codes uint8 [rows x d], scales float32 [rows]) with
     scale = amax/448 (1 for an all-zero row) and code = RNE(x/scale), saturating.
+    The quotient y = |x|/scale is formed in float64; in the normal range
+    (y >= 2^-6) its code is the float64 pattern rounded to three mantissa bits
+    (round to nearest, ties to even, on the bits) and re-biased from 1023 to 7;
+    below it the code is the subnormal count rint(y * 2^9).
     """
     x = np.asarray(x, dtype=np.float32)
     rows, d = x.shape
     codes = np.empty((rows, d), dtype=np.uint8)
     scales = np.empty(rows, dtype=np.float32)
-    for r0 in range(0, rows, _CHUNK):
-        r1 = min(rows, r0 + _CHUNK)
-        blk = x[r0:r1].astype(np.float64)
-        amax = np.abs(blk).max(axis=1)
+
+    def enc(r0, r1):
+        blk = x[r0:r1]
+        amax = np.abs(blk).max(axis=1).astype(np.float64) if d else np.zeros(r1 - r0)
         sc = np.where(amax > 0, amax / E4M3_MAX, 1.0).astype(np.float32)
         scales[r0:r1] = sc
-        y = np.abs(blk) / sc.astype(np.float64)[:, None]
-        y = np.minimum(y, E4M3_MAX)
-        hi = np.searchsorted(_E4M3_POS, y, side="left").clip(0, 126)
-        lo = (hi - 1).clip(0, 126)
-        dlo = np.abs(y - _E4M3_POS[lo])
-        dhi = np.abs(_E4M3_POS[hi] - y)
-        pick_hi = (dhi < dlo) | ((dhi == dlo) & ((hi & 1) == 0))
-        c = np.where(pick_hi, hi, lo).astype(np.uint8)
-        c |= np.where(blk < 0, 0x80, 0).astype(np.uint8) * (c != 0)
+        y = np.abs(blk).astype(np.float64)
+        y /= sc.astype(np.float64)[:, None]
+        np.minimum(y, E4M3_MAX, out=y)
+        b = y.view(np.uint64)
+        r = (b + np.uint64((1 << 48) - 1) + ((b >> np.uint64(49)) & np.uint64(1))) >> np.uint64(49)
+        normal = r.astype(np.int64) - ((1023 - 7) << 3)
+        sub = np.rint(y * 512.0).astype(np.int64)
+        c = np.where(y < 2.0 ** -6, sub, normal).astype(np.uint8)
+        c |= ((blk < 0) & (c != 0)).astype(np.uint8) << 7
         codes[r0:r1] = c
+
+    with cf.ThreadPoolExecutor(_workers()) as ex:
+        for f in [ex.submit(enc, r0, min(rows, r0 + _CHUNK)) for r0 in range(0, rows, _CHUNK)]:
+            f.result()
     return codes, scales
 
 

@@ -62,6 +62,12 @@ class rkmips_index_info(C.Structure):
                 ("lambda_items", C.c_int32)]
 
 
+class rkmips_stats(C.Structure):
+    _fields_ = [("max_rel_err_raw", C.c_double), ("max_rel_err_lambda32", C.c_double),
+                ("cert_failures", C.c_int64), ("fallback_rate", C.c_double), ("batches", C.c_int64),
+                ("queries", C.c_int64), ("query", rkmips_query_stats), ("recheck_rate", C.c_double)]
+
+
 class rkmips_serve_params(C.Structure):
     _fields_ = [("max_batch", C.c_int32), ("num_streams", C.c_int32), ("mem_budget", C.c_int64),
                 ("flags", C.c_int32)]
@@ -82,6 +88,9 @@ _sig = {
     "rkmips_build_index": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.c_int64, C.c_int32, C.c_int32, _P,
                                      C.POINTER(rkmips_params), _P, C.POINTER(_P)]),
     "rkmips_query_batch": (C.c_int, [_P, _P, _P, C.c_int64, _P, C.c_int32, _P, C.POINTER(_P)]),
+    "rkmips_query_batch_hostk": (C.c_int, [_P, _P, _P, C.c_int64, _P, C.c_int32, _P, C.POINTER(_P)]),
+    "rkmips_index_wait": (C.c_int, [_P]),
+    "rkmips_get_stats": (C.c_int, [_P, C.POINTER(rkmips_stats)]),
     "rkmips_result_wait": (C.c_int, [_P]),
     "rkmips_result_view": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(_P), C.POINTER(_P)]),
     "rkmips_result_stats": (C.c_int, [_P, C.POINTER(rkmips_query_stats)]),
@@ -149,11 +158,36 @@ def rkmips_build_index(items, item_scales, n, users, user_scales, m, d, dtype, s
 
 
 def rkmips_query_batch(idx, queries, query_scales, nq, ks, flags=0, stream=None):
-    ks = np.ascontiguousarray(ks, dtype=np.int32)
+    """ks: a device int32 tensor (the C call of this name), or host values (passed on to
+    rkmips_query_batch_hostk)."""
+    if not (isinstance(ks, torch.Tensor) and ks.is_cuda):
+        return rkmips_query_batch_hostk(idx, queries, query_scales, nq, ks, flags, stream)
+    if ks.dtype != torch.int32 or not ks.is_contiguous():
+        raise ValueError("device ks must be a contiguous int32 tensor")
     h = _P()
     _check(_lib.rkmips_query_batch(idx, _ptr(queries), _ptr(query_scales), nq, _ptr(ks), flags,
                                    _stream(stream), C.byref(h)))
     return h
+
+
+def rkmips_query_batch_hostk(idx, queries, query_scales, nq, ks, flags=0, stream=None):
+    ks = np.ascontiguousarray(ks, dtype=np.int32)
+    h = _P()
+    _check(_lib.rkmips_query_batch_hostk(idx, _ptr(queries), _ptr(query_scales), nq, _ptr(ks), flags,
+                                         _stream(stream), C.byref(h)))
+    return h
+
+
+def rkmips_index_wait(idx):
+    _check(_lib.rkmips_index_wait(idx))
+
+
+def rkmips_get_stats(idx):
+    st = rkmips_stats()
+    _check(_lib.rkmips_get_stats(idx, C.byref(st)))
+    out = {f: getattr(st, f) for f, _ in rkmips_stats._fields_ if f != "query"}
+    out["query"] = {f: getattr(st.query, f) for f, _ in rkmips_query_stats._fields_}
+    return out
 
 
 def rkmips_result_wait(r):
@@ -321,7 +355,8 @@ class Index:
         q = queries if isinstance(queries, torch.Tensor) else to_device(queries)
         qs = query_scales if (query_scales is None or isinstance(query_scales, torch.Tensor)) else to_device(query_scales)
         nq = int(q.shape[0])
-        r = rkmips_query_batch(self.h, q, qs, nq, ks, flags, stream)
+        dks = ks if isinstance(ks, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(ks, np.int32)).cuda()
+        r = rkmips_query_batch(self.h, q, qs, nq, dks, flags, stream)
         try:
             rkmips_result_wait(r)
             off, ids = rkmips_result_view(r)

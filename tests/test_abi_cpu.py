@@ -99,3 +99,111 @@ def test_index_load_rejects_bad_files_before_device_work(R, tmp_path):
     assert st == -1 and "truncated" in R.rkmips_last_error()
     st = R._lib.rkmips_index_save(None, str(bad).encode())
     assert st == -1
+
+
+# ------------------------------------------------------------- index files, by hand
+class _Header(C.Structure):
+    """The index file header as the loader reads it (host byte order, natural alignment)."""
+    _fields_ = ([("version", C.c_uint32)] + [(f, C.c_int32) for f in
+                ("d", "ld", "dtype", "mma_dtype", "mma_ld", "t", "C", "G", "nseg", "device_unused")] +
+                [(f, C.c_int64) for f in ("n", "m", "n_lam", "nblocks", "ns", "seg_len", "cert_failures")] +
+                [(f, C.c_double) for f in ("err_fast", "max_item_norm", "max_user_norm", "max_rel_err_raw",
+                                            "max_rel_err_l32", "ms_norms", "ms_lambda", "ms_refine", "ms_saalsh",
+                                            "ms_cone", "ms_total", "ms_seed", "ms_topk")])
+
+
+def _tiny_index(R, **edit):
+    """Header and arrays of a consistent exact-mode FP32 index: n = 3 items, m = 2 users,
+    d = 2 (rows padded to 32), one partition, one block, k_max = 1, K = 128."""
+    class H(C.Structure):
+        _fields_ = [("h", _Header), ("prm", R.rkmips_params)]
+    x = H()
+    p = R.rkmips_default_params()
+    p.k_max = 1
+    x.prm = p
+    h = x.h
+    h.version, h.d, h.ld, h.dtype, h.mma_dtype, h.mma_ld, h.t = 2, 2, 32, 0, 4, 64, 1
+    h.n, h.m, h.n_lam, h.nblocks = 3, 2, 3, 1
+    n, m, ld, W = 3, 2, 32, 4
+    arr = [np.zeros(n * ld, np.float32), None, np.arange(n, dtype=np.uint32), np.ones(n),
+           np.zeros(m * ld, np.float32), None, np.zeros(m * 2 * ld, np.uint16), np.arange(m, dtype=np.uint32),
+           np.ones(m), np.ones(m, np.float32), np.ones(m, np.float32), np.zeros(m, np.float32),
+           np.zeros(m, np.int32), np.array([0, m, 0], np.int64), np.zeros(ld, np.float32),
+           np.zeros(1, np.float32), np.zeros(1, np.float32), np.ones(1, np.int32), np.zeros(1, np.float32),
+           np.zeros(m), np.zeros(m, np.float32), np.array([0, n, 0, 0, 0], np.int64), np.ones(1, np.int32),
+           np.zeros(ld, np.float32), np.zeros(1, np.float32), np.zeros(3 * 128, np.float32),
+           np.zeros(n * W, np.uint32), np.zeros(m * W, np.uint32)]
+    for k, v in edit.items():
+        if k.startswith("prm_"):
+            setattr(x.prm, k[4:], v)
+        elif k.startswith("arr_"):
+            arr[int(k[4:])] = v
+        else:
+            setattr(h, k, v)
+    return x, arr
+
+
+def _write(path, x, arr):
+    with open(path, "wb") as f:
+        f.write(b"RKMIPSIX")
+        f.write(bytes(x))
+        for a in arr:
+            b = b"" if a is None else a.tobytes()
+            f.write(np.uint64(len(b)).tobytes())
+            f.write(b)
+
+
+@pytest.mark.parametrize("edit, msg", [
+    (dict(prm_num_hash=512), "num_hash"),
+    (dict(prm_leaf_size=0), "leaf_size"),
+    (dict(dtype=5), "unknown dtype"),
+    (dict(mma_dtype=0), "operand form"),
+    (dict(ld=64), "inconsistent sizes"),
+    (dict(n_lam=2), "lambda item count"),
+    (dict(t=4), "partition or block count"),
+    (dict(arr_21=np.array([0, 3], np.int64)), "array 21"),             # short partition table
+    (dict(arr_0=np.zeros(2 * 32, np.float32)), "array 0"),             # items of another n
+    (dict(arr_1=np.ones(3, np.float32)), "array 1"),                   # scales without FP8
+    (dict(arr_19=np.zeros(4)), "array 19"),                            # lambda of another k_max
+    (dict(arr_2=np.array([0, 0, 2], np.uint32)), "item order"),
+    (dict(arr_7=np.array([0, 5], np.uint32)), "user order"),
+    (dict(arr_13=np.array([0, 1, 0], np.int64)), "block table"),
+    (dict(arr_12=np.array([0, 1], np.int32)), "user block"),
+    (dict(arr_21=np.array([0, 2, 0, 0, 0], np.int64)), "partitions do not cover"),
+    (dict(arr_22=np.array([2], np.int32)), "partition count"),
+])
+def test_index_load_checks_every_array_before_device_work(R, tmp_path, edit, msg):
+    x, arr = _tiny_index(R, **edit)
+    f = tmp_path / "bad.idx"
+    _write(f, x, arr)
+    h = C.c_void_p()
+    st = R._lib.rkmips_index_load(str(f).encode(), None, C.byref(h))
+    assert st == -1 and msg in R.rkmips_last_error(), R.rkmips_last_error()
+
+
+def test_index_load_passes_a_consistent_file_to_the_device(R, tmp_path):
+    """The unedited tiny file passes every check; without a GPU the first device call
+    then fails (EDEVICE), with one the index loads."""
+    assert C.sizeof(_Header) + C.sizeof(R.rkmips_params) == 256
+    x, arr = _tiny_index(R)
+    f = tmp_path / "ok.idx"
+    _write(f, x, arr)
+    h = C.c_void_p()
+    st = R._lib.rkmips_index_load(str(f).encode(), None, C.byref(h))
+    assert st in (0, -3), R.rkmips_last_error()
+    if st == 0:
+        R._lib.rkmips_index_free(h)
+
+
+def test_new_entry_points_check_arguments_first(R):
+    dummy = C.c_void_p(16)
+    r = C.c_void_p()
+    ks = np.ones(4, np.int32)
+    for fn in (R._lib.rkmips_query_batch, R._lib.rkmips_query_batch_hostk):
+        assert fn(None, dummy, None, 4, ks.ctypes.data, 0, None, C.byref(r)) == -1
+        assert fn(dummy, None, None, 4, ks.ctypes.data, 0, None, C.byref(r)) == -1
+        assert fn(dummy, dummy, None, -1, ks.ctypes.data, 0, None, C.byref(r)) == -1
+        assert fn(dummy, dummy, None, 4, None, 0, None, C.byref(r)) == -1
+        assert fn(dummy, dummy, None, 4, ks.ctypes.data, 0, None, None) == -1
+    assert R._lib.rkmips_index_wait(None) == -1
+    assert R._lib.rkmips_get_stats(None, None) == -1

@@ -504,3 +504,104 @@ def test_saalsh_kmips_full_probe_is_exact_top_k():
             assert np.array_equal(got2, lam[:k, u])
             part = O.saalsh_kmips("f32", w.items, None, n2, order, ps, icodes, ucodes[u], 0.1, w.users, None, u, k)
             assert np.all(part <= lam[:k, u])
+
+
+# ------------------------------------------- Alg. 2 partial probe, computed by hand
+# u = (1, 0) and items (v, 0) with v = 8, 7, ..., 1 already in descending norm order,
+# so s(u, p_i) = v_i and mu_j = M_j.  The K = 32 bit codes are set by hand: the user's
+# code is 0 and item i's code has 32 - agree_i low bits set, so exactly agree_i bits
+# agree.  Every expected value below follows from the reading of the probe (the
+# ceil(beta |S_j|) items of S_j with the most equal bits; equal counts: earlier in the
+# norm order first) and from Alg. 2's tests, worked out by hand.
+_V = np.array([8, 7, 6, 5, 4, 3, 2, 1], np.float64)
+
+
+def _probe_fixture(agree):
+    P = np.stack([_V, np.zeros(8)], axis=1).astype(np.float32)
+    U = np.array([[1, 0]], np.float32)
+    codes = np.array([[(1 << (32 - a)) - 1 if a > 0 else 0xFFFFFFFF] for a in agree], np.uint32)
+    ucode = np.zeros(1, np.uint32)
+    return P, U, codes, ucode, _V * _V, np.arange(8, dtype=np.int64)
+
+
+def _decide(P, U, codes, ucode, n2, order, ps, beta, sq, k, init=None):
+    Q = np.array([[sq, 0]], np.float32)
+    return O.saalsh_decide("f32", P, None, n2, order, np.asarray(ps, np.int64), codes, ucode, beta,
+                           U, None, 0, Q, None, 0, k, init=init)
+
+
+def test_alg2_probe_selection_by_hand():
+    """One partition of 8 items with agreements 10, 30, 20, 30, 5, 25, 30, 1.
+    beta = 0.15: ceil(1.2) = 2 items, the two earliest of the three 30s (positions 1
+    and 3, scores 7 and 5).  A floor (1 item), the later-first tie rule (positions 3
+    and 6: 5 and 2) or the fewest-agreeing items (positions 7 and 4: 1 and 4) each
+    give another phi.  beta = 0.4: ceil(3.2) = 4 items, the three 30s then the 25
+    (scores 7, 5, 2, 3)."""
+    P, U, codes, ucode, n2, order = _probe_fixture([10, 30, 20, 30, 5, 25, 30, 1])
+    ps = [0, 8]
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.15, 6.0, 1) == (0, 7.0)
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.15, 6.0, 2) == (1, 5.0)
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.15, 7.0, 1) == (1, 7.0)   # a tie: q wins
+    ans, phi = _decide(P, U, codes, ucode, n2, order, ps, 0.15, -100.0, 3)
+    assert ans == 1 and phi == -np.inf                        # fewer than k candidates
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.4, 2.5, 3) == (0, 3.0)
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.4, 2.5, 4) == (1, 2.0)
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.25, 6.0, 2) == (1, 5.0)   # exactly 2.0 -> 2
+
+
+def test_alg2_partitions_mu_stop_and_initial_scores_by_hand():
+    """Partitions {8, 7, 6, 5} and {4, 3, 2, 1} (b = 1/2: 4 is not above 8/2), so
+    mu_1 = 4.  Agreements 10, 30, 20, 30 | 31, 2, 31, 9 and beta = 0.25 take one item
+    per partition: position 1 (score 7; the earlier of two 30s) and position 4 (score 4;
+    the earlier of two 31s)."""
+    P, U, codes, ucode, n2, order = _probe_fixture([10, 30, 20, 30, 31, 2, 31, 9])
+    ps = [0, 4, 8]
+    # k = 1: phi = 7 after S_0; 6.5 < 7 is a no, 7.5 passes and phi > mu_1 stops with a yes
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.25, 6.5, 1) == (0, 7.0)
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.25, 7.5, 1) == (1, 7.0)
+    # k = 2: one candidate after S_0 (phi = -inf, no stop at mu_1); S_1 adds 4: phi = 4
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.25, 4.5, 2) == (1, 4.0)
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.25, 3.5, 2) == (0, 4.0)
+    # an initial score 9 (a P' item): after S_0 the candidates are {9, 7}, phi = 7
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.25, 6.5, 2, init=[9.0]) == (0, 7.0)
+    # k = 1 with init 9: phi = 9 > mu_0 = 8 before any probe: yes, whatever s(u,q) is
+    assert _decide(P, U, codes, ucode, n2, order, ps, 0.25, -5.0, 1, init=[9.0]) == (1, 9.0)
+
+
+def test_kmips_probe_selection_by_hand():
+    """The kMIPS form of the same probes (no query): the k best scores found.  One
+    partition, beta = 0.15: scores 7 and 5; two partitions, beta = 0.25: k = 1 stops
+    at mu_1 = 4 < 7 with [7]; k = 2 probes S_1 as well, [7, 4]."""
+    P, U, codes, ucode, n2, order = _probe_fixture([10, 30, 20, 30, 5, 25, 30, 1])
+    got = O.saalsh_kmips("f32", P, None, n2, order, np.array([0, 8]), codes, ucode, 0.15, U, None, 0, 3)
+    assert np.array_equal(got, [7.0, 5.0, -np.inf])
+    got = O.saalsh_kmips("f32", P, None, n2, order, np.array([0, 8]), codes, ucode, 0.4, U, None, 0, 4)
+    assert np.array_equal(got, [7.0, 5.0, 3.0, 2.0])
+    P, U, codes, ucode, n2, order = _probe_fixture([10, 30, 20, 30, 31, 2, 31, 9])
+    ps = np.array([0, 4, 8])
+    assert np.array_equal(O.saalsh_kmips("f32", P, None, n2, order, ps, codes, ucode, 0.25, U, None, 0, 1), [7.0])
+    assert np.array_equal(O.saalsh_kmips("f32", P, None, n2, order, ps, codes, ucode, 0.25, U, None, 0, 2),
+                          [7.0, 4.0])
+    # the initial scores enter before the first partition: 9 > mu_0 = 8 stops at once
+    assert np.array_equal(O.saalsh_kmips("f32", P, None, n2, order, ps, codes, ucode, 0.25, U, None, 0, 1,
+                                         init=[9.0]), [9.0])
+
+
+def test_sah_norm_test_fires_only_at_or_above_u_times_pk():
+    """Alg. 5's ||u|| ||p_k|| test, by hand.  u = (1, 0); items (0, 4), (3, 0), (1, 1),
+    (1/2, 0) in norm order; P' = the first item, so L_u^1 = s(u, (0,4)) = 0, and
+    ||p_1|| = 4.  Queries (9/2, 0), (7/2, 0), (2, 0) and (4, 0) all pass L_u^1 = 0:
+    - 9/2 >= 4 and 4 >= 4: the norm test answers yes;
+    - 7/2 < 4: Alg. 2 (beta = 1) puts 3 in the candidates, phi = 3 <= 7/2, and phi
+      exceeds mu = sqrt(2) before S_1: yes;
+    - 2 < 4: Alg. 2 rejects it (2 < phi = 3).
+    A test against ||p_2|| = 3 instead would answer 7/2 by the norm test."""
+    P = np.array([[0, 4], [3, 0], [1, 1], [0.5, 0]], np.float32)
+    U = np.array([[1, 0]], np.float32)
+    Q = np.array([[4.5, 0], [3.5, 0], [2, 0], [4, 0]], np.float32)
+    A = np.random.default_rng(3).standard_normal((3, 32)).astype(np.float32)
+    st = {}
+    got = O.sah_rkmips("f32", P, None, U, None, Q, None, np.ones(4, np.int32), 1, 1, 0.5, 1.0, A, stats=st)
+    assert [g.tolist() for g in got] == [[0], [0], [], [0]]
+    assert st["norm_pairs"] == [(0, 0), (3, 0)] and st["alg2_pairs"] == [(1, 0), (2, 0)]
+    assert st["norm_yes"] == 2 and st["alg2"] == 2
