@@ -7,13 +7,15 @@
 //   order statistic estimates a per-user threshold that a fixed multiple of C items
 //   of the whole set exceed.
 // Pass 1 (k_topk, main mode): fused U.P^T on the matrix cores with a streaming per-user
-//   top-C (C = k_max + slack).  A workgroup keeps 128-256 users' operand fragments in
-//   registers and streams 64-item tiles of the norm-sorted items through LDS.  Every
-//   MFMA output lane owns one user column; a score enters the user's candidate buffer
-//   only if it beats the user's register threshold (starting at the seed estimate).
-//   When a buffer fills, the wave compacts it to its C best entries with a wave radix
-//   select and raises the threshold to the running C-th best.  The final threshold tau
-//   bounds every item left out.
+//   top-C (C = k_max + slack).  A wave keeps 64 users' operand fragments in registers
+//   (32 where the rows are too long for two groups), so that every item fragment read
+//   from LDS feeds two products; a workgroup of four waves streams the norm-sorted items
+//   through a ring of three padded LDS tiles, filled by direct loads two tiles ahead of
+//   the one being scored.  Every MFMA output lane owns one user column per group; a
+//   score enters the user's candidate buffer only if it beats the user's register
+//   threshold (starting at the seed estimate).  When a buffer fills, the wave compacts
+//   it to its C best entries with a wave radix select and raises the threshold to the
+//   running C-th best.  The final threshold tau bounds every item left out.
 // Pass 2 (canonical FP64 rescoring and the certificate) is in k_refine.hip.
 #include <algorithm>
 #include <map>
@@ -26,16 +28,16 @@
 namespace rk {
 
 static constexpr int TK_WAVES = 4;
-static constexpr int TK_IT = 64;  // items per LDS tile (two 32-row MFMA blocks)
+static constexpr int TK_IT_REG = 64;   // items per tile of the register-prefetch kernel (two blocks)
 
 // ------------------------------------------------------------------ fused GEMM + top-k
 // Buffer compaction for the streaming pass, with the keys staged in LDS so that it needs
-// few registers (it runs rarely, and the main loop keeps its register budget for
-// occupancy): of the c0 entries at r0 and the c1 entries at r1, keep the C largest
+// few registers (it runs rarely; inlined, since a call would make the main loop save its
+// resident fragments around it): of the c0 entries at r0 and the c1 entries at r1, keep the C largest
 // (ties at the threshold in staging order) in r0[0, C) and return the C-th largest key
 // (orderable form; the entries themselves keep the raw score bits).  The kept entries
 // move down in place: entry i lands at a position <= i, and r0 is read in full before r1.
-__device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1, int c1, int C, int* hist,
+__device__ __forceinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1, int c1, int C, int* hist,
                                              uint32_t* stage)
 {
     const int l = lane_id();
@@ -102,6 +104,14 @@ __device__ __noinline__ uint32_t select_user(uint2* r0, int c0, const uint2* r1,
     return T;
 }
 
+// Out-of-line form for the register-prefetch kernel, whose main loop keeps its register
+// budget for occupancy.
+__device__ __noinline__ uint32_t select_user_call(uint2* r0, int c0, const uint2* r1, int c1, int C, int* hist,
+                                                  uint32_t* stage)
+{
+    return select_user(r0, c0, r1, c1, C, hist, stage);
+}
+
 // Item at virtual position v of a launch: the norm-sorted array itself (main pass), or
 // the stratified sample of `ns` items, one from the middle of each of ns equal slices of
 // the norm-sorted order (seed pass).
@@ -112,10 +122,65 @@ __device__ __forceinline__ int64_t item_at(int64_t v, int64_t n, int64_t ns)
     else return v;
 }
 
+// 32 x 32 blocks of scores on the matrix cores, one per user group: rows = the 32 items
+// of LDS rows [row0, row0 + 32) of a staged tile, columns = group g's 32 users (register
+// fragments).  Every A fragment read from LDS feeds the NG groups' products.
+template <int DT, int KSTEPS, int LROW, int NG>
+__device__ __forceinline__ void mfma_block(const uint8_t* tile, int row0, const i32x4 (&bfrag)[NG][KSTEPS],
+                                           f32x16 (&acc)[NG])
+{
+    const int l = lane_id(), h = l >> 5;
+#pragma unroll
+    for (int g = 0; g < NG; g++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[g][r] = 0.f;
+    const uint8_t* arow = tile + (row0 + (l & 31)) * LROW + h * 16;
+#pragma unroll
+    for (int t = 0; t < KSTEPS; t++) {
+        if constexpr (DT == DT_F32) {
+            const f32x4 a4 = __builtin_bit_cast(f32x4, *(const i32x4*)(arow + t * 32));
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], __builtin_bit_cast(f32x4, bfrag[g][t])[e],
+                                                                  acc[g], 0, 0, 0);
+        } else if constexpr (dt_bf16_mma<DT>) {
+            const bf16x8 af = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + t * 32));
+#pragma unroll
+            for (int g = 0; g < NG; g++)
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, __builtin_bit_cast(bf16x8, bfrag[g][t]), acc[g], 0,
+                                                                 0, 0);
+        } else if constexpr (DT == DT_SPLIT) {
+            // rows [hi | lo]: k-step t < KSTEPS / 2 of the hi half pairs with step
+            // t + KSTEPS / 2 of the lo half (same elements); three products per pair
+            constexpr int HK = KSTEPS / 2;
+            if (t < HK) {
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + t * 32));
+                const bf16x8 al = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + (t + HK) * 32));
+#pragma unroll
+                for (int g = 0; g < NG; g++) {
+                    const bf16x8 bh = __builtin_bit_cast(bf16x8, bfrag[g][t]);
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, bfrag[g][t + HK]);
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[g], 0, 0, 0);
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[g], 0, 0, 0);
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[g], 0, 0, 0);
+                }
+            }
+        } else {
+            static_assert(dt_bf16_mma<DT>, "FP8 codes reach the matrix cores widened to BF16");
+        }
+    }
+}
+
+// Two modes over the same matrix-core pipeline (see the file comment).  A wave owns NG
+// groups of 32 users; every MFMA output lane owns one user column per group.  Item tiles
+// reach LDS by direct (DMA) loads into a ring of three padded tile buffers, two tiles
+// ahead of the one being scored; one barrier per tile.
 // 32 x 32 block of scores on the matrix cores: rows = the 32 items of LDS rows
 // [row0, row0 + 32) of a staged tile, columns = the wave's 32 users (register fragments).
 template <int DT, int KSTEPS, int LROW>
-__device__ __forceinline__ f32x16 mfma_block(const uint8_t* tile, int row0, const i32x4 (&bfrag)[KSTEPS])
+__device__ __forceinline__ f32x16 mfma_block1(const uint8_t* tile, int row0, const i32x4 (&bfrag)[KSTEPS])
 {
     const int l = lane_id(), h = l >> 5;
     f32x16 acc;
@@ -153,7 +218,9 @@ __device__ __forceinline__ f32x16 mfma_block(const uint8_t* tile, int row0, cons
     return acc;
 }
 
-// Two modes over the same matrix-core pipeline.
+// Register-prefetch form, used for rows shorter than 512 bytes (one group of 32 users
+// per wave, tiles of 64 items staged through registers).  Two modes over the same
+// matrix-core pipeline.
 //  TK_MAIN: streaming top-C.  A score enters the user's candidate buffer only if it
 //    beats the user's register threshold (seeded per user); a full buffer is compacted to
 //    its C best by a wave radix select, which also raises the threshold to the running
@@ -165,19 +232,19 @@ __device__ __forceinline__ f32x16 mfma_block(const uint8_t* tile, int row0, cons
 //    a starting point: the main pass and the refine certificate never rely on it.
 //
 // The item stream is cut into 32-item blocks; a wave's MFMA output for one block is
-// 32 items x the wave's 32 users (one user column per lane).  Item tiles of TK_IT rows
+// 32 items x the wave's 32 users (one user column per lane).  Item tiles of TK_IT_REG rows
 // are double-buffered in LDS with one barrier per tile; the next tile waits in
 // registers meanwhile.  The epilogue of block b (threshold compares and appends, or
 // the register top-T of the seed pass) runs before block b + 1 is accumulated: the
 // other resident waves keep the matrix cores busy meanwhile.
 template <int DT, int DPT, int GPL, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT >= 256) ? 1 : 2, 8))) void k_topk(TopkArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F32 && DPT >= 256) ? 1 : 2, 8))) void k_topk_reg(TopkArgs a)
 {
     constexpr int EB = Elt<DT>::bytes;
     constexpr int ROWB = DPT * EB;                // bytes of one stored row
     constexpr int LROW = ROWB + 16;               // padded LDS row (bank spread)
     constexpr int KSTEPS = ROWB / 32;             // 16-byte fragments per half row
-    constexpr int IT = ROWB >= 512 ? 32 : TK_IT;  // items per tile (LDS: two tiles per workgroup)
+    constexpr int IT = ROWB >= 512 ? 32 : TK_IT_REG;  // items per tile (LDS: two tiles per workgroup)
     constexpr int BPT = IT / 32;                  // MFMA blocks per tile
     constexpr int CHUNKS = IT * (ROWB / 16);      // 16-byte chunks per tile
     constexpr int PF = (CHUNKS + 255) / 256;      // chunks per thread
@@ -322,7 +389,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                     const int c0 = __shfl(cnt, ul), c1 = __shfl(cnt, ul + 32);
                     const int64_t ugl = __shfl(ug, ul);
                     uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
-                    const uint32_t T = select_user(rg, c0, rg + HG, c1, a.C, hist, stage);
+                    const uint32_t T = select_user_call(rg, c0, rg + HG, c1, a.C, hist, stage);
                     if ((l & 31) == ul) {
                         theta = ord_f32(T);
                         off = loff8 + (h ? 0u : 8u * (uint32_t)a.C);
@@ -350,7 +417,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         stage_tile(0);
         __syncthreads();
         if (ntiles > 1) prefetch(1);
-        f32x16 acc = mfma_block<DT, KSTEPS, LROW>(tile[0], 0, bfrag);
+        f32x16 acc = mfma_block1<DT, KSTEPS, LROW>(tile[0], 0, bfrag);
         for (int b = 0; b < nblk; b++) {
             scores(acc, b);
             late(acc, early(acc), b);
@@ -361,7 +428,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                     __syncthreads();
                     if (tn + 1 < ntiles) prefetch(tn + 1);
                 }
-                acc = mfma_block<DT, KSTEPS, LROW>(tile[tn & 1], ((b + 1) % BPT) * 32, bfrag);
+                acc = mfma_block1<DT, KSTEPS, LROW>(tile[tn & 1], ((b + 1) % BPT) * 32, bfrag);
             }
         }
     }
@@ -379,23 +446,390 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
     }
 }
 
+template <int DT, int DPT>
+constexpr int topk_ng()
+{
+    // Two groups where a block's k-loop is long (rows of 512 bytes and more), so that the
+    // LDS reads per product halve; the two groups' resident fragments (KSTEPS i32x4 each)
+    // must fit in 128 VGPRs.  Shorter rows keep one group and twice the workgroups.
+    constexpr int rowb = DPT * Elt<DT>::bytes;
+    return rowb >= 512 && (rowb / 32) * 4 * 2 <= 128 ? 2 : 1;
+}
+
+// Direct (DMA) load of 16 (or 4) bytes per lane into LDS at lds + 16 * lane (4 * lane),
+// through a buffer descriptor: bytes past num_records read as zero.  Written as one asm
+// block with no register outputs, so that the compiler does not order every later LDS
+// read behind it; the kernel waits for these loads itself (vmcnt, then a barrier).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 tk_rsrc(const void* base, uint32_t bytes)
+{
+    const uint64_t b = (uint64_t)base;
+    u32x4 r;
+    r.x = (uint32_t)b;
+    r.y = (uint32_t)(b >> 32) & 0xffffu;   // stride 0
+    r.z = bytes;
+    r.w = 0x00020000u;
+    return r;
+}
+__device__ __forceinline__ void tk_dma16(u32x4 rsrc, uint32_t lds, uint32_t voff)
+{
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                 :
+                 : "s"(lds), "v"(voff), "s"(rsrc)
+                 : "memory", "m0");
+}
+__device__ __forceinline__ void tk_dma4(u32x4 rsrc, uint32_t lds, uint32_t voff)
+{
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dword %1, %2, 0 offen lds"
+                 :
+                 : "s"(lds), "v"(voff), "s"(rsrc)
+                 : "memory", "m0");
+}
+
+#define TK_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+#define TK_GLB(p) ((__attribute__((address_space(1))) void*)(p))
+
+template <int DT, int DPT, int GPL, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_topk_ring(TopkArgs a)
+{
+    constexpr int NG = topk_ng<DT, DPT>();
+    constexpr int UPW = 32 * NG;                  // users per wave
+    constexpr int UPB = TK_WAVES * UPW;           // users per workgroup
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int ROWB = DPT * EB;
+    constexpr int LROW = ROWB + 16;               // padded LDS row (bank spread)
+    constexpr int CPR = LROW / 16;                // 16-byte chunks per padded row
+    constexpr int KSTEPS = ROWB / 32;
+    constexpr int IT = 32;                        // items per tile: one MFMA block
+    constexpr int BPT = IT / 32;
+    constexpr int NLD = (IT * LROW + 1023) / 1024;   // 1 KB DMA loads per tile
+    constexpr int LPW = (NLD + TK_WAVES - 1) / TK_WAVES;
+    constexpr int TBYTES = NLD * 1024;
+    constexpr int SGPL = MODE == TK_MAIN ? GPL : 1;
+    __shared__ __attribute__((aligned(1024))) uint8_t ring0[TBYTES];
+    __shared__ __attribute__((aligned(1024))) uint8_t ring1[TBYTES];
+    __shared__ __attribute__((aligned(1024))) uint8_t ring2[TBYTES];
+    __shared__ __attribute__((aligned(256))) float sc0[dt_scaled<DT> ? 64 : 1];
+    __shared__ __attribute__((aligned(256))) float sc1[dt_scaled<DT> ? 64 : 1];
+    __shared__ __attribute__((aligned(256))) float sc2[dt_scaled<DT> ? 64 : 1];
+    __shared__ int hist_all[TK_WAVES][MODE == TK_MAIN ? 256 : 1];
+    __shared__ uint32_t stage_all[TK_WAVES][SGPL * 64];
+
+    const int l = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (SGPR)
+    const int h = l >> 5;
+    int* hist = hist_all[w];
+    uint32_t* stage = stage_all[w];
+    const int segl = blockIdx.y;
+    const int seg = a.seg_base + segl;
+    const int64_t seg0 = a.v0 + (int64_t)segl * a.seg_len;
+    int64_t seg1 = seg0 + a.seg_len;
+    if (seg1 > a.v1) seg1 = a.v1;
+    const int seg_rows = seg1 > seg0 ? (int)(seg1 - seg0) : 0;
+    const int ntiles = (seg_rows + IT - 1) / IT;
+
+    // ---- resident user fragments (B operands), one user column per lane and group
+    // user of group g for this lane (recomputed where needed: registers are scarce)
+    auto user_of = [&](int g) -> int64_t {
+        int lw = (l & 31) + w * UPW + g * 32;
+        asm volatile("" : "+v"(lw));
+        return (int64_t)blockIdx.x * UPB + lw;
+    };
+    i32x4 bfrag[NG][KSTEPS];
+    float theta[NG], su[NG];
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+        const int64_t ug = user_of(g);
+        const bool uok = ug < a.m;
+        const uint8_t* row = (const uint8_t*)a.users + (uok ? ug : 0) * ROWB;
+#pragma unroll
+        for (int t = 0; t < KSTEPS; t++) {
+            i32x4 z = {0, 0, 0, 0};
+            bfrag[g][t] = uok ? *(const i32x4*)(row + t * 32 + h * 16) : z;
+        }
+        theta[g] = -__builtin_inff();
+        if (MODE == TK_MAIN && uok && a.theta_init) theta[g] = a.theta_init[ug * a.theta_stride];
+        if (!uok) theta[g] = __builtin_inff();
+        su[g] = (dt_scaled<DT> && uok) ? a.user_scales[ug] : 1.0f;
+    }
+    const int HG = a.G / 2;
+    const int64_t wusers = std::min<int64_t>(UPB, a.m - (int64_t)blockIdx.x * UPB);
+    const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
+        a.buf + (int64_t)blockIdx.x * UPB * a.nseg_total * a.G, (short)0,
+        (int)(wusers * a.nseg_total * a.G * (int64_t)sizeof(uint2)), 0x00020000);
+    uint32_t loff8[NG], off[NG];
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+        loff8[g] = 8u * (uint32_t)(((w * UPW + g * 32 + (l & 31)) * a.nseg_total + seg) * a.G + h * HG);
+        off[g] = loff8[g];
+    }
+    const uint32_t full_rel = 8u * (uint32_t)(HG - 16);
+    float top[NG][MODE == TK_SEED ? TK_T : 1];
+#pragma unroll
+    for (int g = 0; g < NG; g++)
+#pragma unroll
+        for (int i = 0; i < (MODE == TK_SEED ? TK_T : 1); i++) top[g][i] = -__builtin_inff();
+
+    // ---- DMA map: load j of this wave fills LDS bytes [k * 1024, (k + 1) * 1024) of a
+    // slot, k = w * LPW + j; lane l writes 16 bytes at k * 1024 + 16 l, which is chunk
+    // (pos % CPR) of padded row pos / CPR (the padding chunk takes a dummy copy of chunk 0)
+    // byte offset of load j's 16 bytes for this lane within the tile's rows
+    const int pos0 = w * LPW * 64 + l;
+    auto doff = [&](int j) -> unsigned {
+        // recomputed per tile: kept live across the loop they would cost registers
+        int p0 = pos0;
+        asm volatile("" : "+v"(p0));
+        const int pos = p0 + j * 64;
+        const int c = pos % CPR;
+        return (unsigned)((pos / CPR) * ROWB + (c < ROWB / 16 ? c : 0) * 16);
+    };
+    auto issue = [&](uint8_t* ring, float* sc, int tt) {
+        const int r0 = tt * IT;
+        const int rows = seg_rows - r0 < IT ? seg_rows - r0 : IT;
+        if constexpr (MODE == TK_MAIN) {
+            // the tile's rows are contiguous; loads past its last row read zeros
+            const u32x4 rs = tk_rsrc((const uint8_t*)a.items + (seg0 + r0) * ROWB, (uint32_t)(rows * ROWB));
+            const uint32_t lbase = (uint32_t)(uintptr_t)TK_LDS(ring);
+#pragma unroll
+            for (int j = 0; j < LPW; j++) {
+                if (w * LPW + j < NLD) tk_dma16(rs, lbase + (uint32_t)((w * LPW + j) * 1024), doff(j));
+            }
+            if constexpr (dt_scaled<DT>) {
+                if (w == 0) {
+                    const u32x4 rsc = tk_rsrc(a.item_scales + seg0 + r0, (uint32_t)(rows * 4));
+                    tk_dma4(rsc, (uint32_t)(uintptr_t)TK_LDS(sc), (uint32_t)(l * 4));
+                }
+            }
+        } else {
+            // stratified sample: rows are scattered; rows past the last repeat it
+            const int last = rows - 1;
+#pragma unroll
+            for (int j = 0; j < LPW; j++) {
+                if (w * LPW + j < NLD) {
+                    const int pos = (w * LPW + j) * 64 + l;
+                    const int rr = pos / CPR < last ? pos / CPR : last;
+                    const int64_t item = item_at<MODE>(seg0 + r0 + rr, a.n, a.ns);
+                    const uint8_t* src = (const uint8_t*)a.items + item * ROWB + (doff(j) - (unsigned)((pos / CPR) * ROWB));
+                    __builtin_amdgcn_global_load_lds(TK_GLB(src), TK_LDS(ring + (w * LPW + j) * 1024), 16, 0, 0);
+                }
+            }
+            if constexpr (dt_scaled<DT>) {
+                if (w == 0) {
+                    const int rr = l < last ? l : last;
+                    const float* src = a.item_scales + item_at<MODE>(seg0 + r0 + rr, a.n, a.ns);
+                    __builtin_amdgcn_global_load_lds(TK_GLB(src), TK_LDS(sc), 4, 0, 0);
+                }
+            }
+        }
+    };
+    // Before tile tt is read: this wave's loads of tile tt have landed when no more than
+    // its loads of tile tt + 1 (if issued; VMEM operations complete in order) are in
+    // flight.  The counts are per wave: NLD loads are spread LPW to a wave, the last
+    // waves may take fewer, and wave 0 also loads the scales.
+    auto wait_tile = [&](bool next_issued) {
+#define TK_WAITV(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
+        constexpr int n0 = (NLD < LPW ? NLD : LPW) + (dt_scaled<DT> ? 1 : 0);
+        constexpr int n1 = NLD - LPW <= 0 ? 0 : (NLD - LPW < LPW ? NLD - LPW : LPW);
+        constexpr int n2 = NLD - 2 * LPW <= 0 ? 0 : (NLD - 2 * LPW < LPW ? NLD - 2 * LPW : LPW);
+        constexpr int n3 = NLD - 3 * LPW <= 0 ? 0 : (NLD - 3 * LPW < LPW ? NLD - 3 * LPW : LPW);
+        static_assert(TK_WAVES == 4 && n0 < 64, "wait counts assume four waves");
+        if (!next_issued) TK_WAITV(0);
+        else if (w == 0) TK_WAITV(n0);
+        else if (w == 1) TK_WAITV(n1);
+        else if (w == 2) TK_WAITV(n2);
+        else TK_WAITV(n3);
+#undef TK_WAITV
+    };
+
+    // scores of block b in place (FP8 scaled, rows past the end -inf)
+    auto scores = [&](f32x16 (&v)[NG], const float* sc, int tt, int rb) {
+        const int base = tt * IT + rb * 32;
+        if constexpr (dt_scaled<DT>) {
+            const float* ts = sc + rb * 32 + 4 * h;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const f32x4 s4 = *(const f32x4*)(ts + 8 * j);
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) v[g][4 * j + e] = (su[g] * s4[e]) * v[g][4 * j + e];
+            }
+        }
+        if (base + 32 > seg_rows) {
+            const int rem = seg_rows - base;
+#pragma unroll
+            for (int g = 0; g < NG; g++)
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    if (mfma32_row(r, l) >= rem) v[g][r] = -__builtin_inff();
+        }
+    };
+    auto seed_top = [&](const f32x16 (&v)[NG]) {
+        if constexpr (MODE == TK_SEED) {
+#pragma unroll
+            for (int g = 0; g < NG; g++) {
+                float mx = v[g][0];
+#pragma unroll
+                for (int r = 1; r < 16; r++) mx = fmaxf(mx, v[g][r]);
+                if (mx > top[g][TK_T - 1]) {
+#pragma unroll
+                    for (int r = 0; r < 16; r++) {
+                        float x = v[g][r];
+#pragma unroll
+                        for (int i = 0; i < TK_T; i++) {
+                            const float hi = fmaxf(top[g][i], x);
+                            x = fminf(top[g][i], x);
+                            top[g][i] = hi;
+                        }
+                    }
+                }
+            }
+        }
+    };
+    auto appends = [&](const f32x16 (&v)[NG], int b) {
+        if constexpr (MODE == TK_MAIN) {
+#pragma unroll
+            for (int g = 0; g < NG; g++) {
+                const uint64_t need = ballot64(off[g] - loff8[g] > full_rel);
+                if (need) {
+                    const int cnt = (int)((off[g] - loff8[g]) >> 3);
+                    uint32_t um = (uint32_t)need | (uint32_t)(need >> 32);
+                    while (um) {
+                        const int ul = __builtin_ctz(um);
+                        um &= um - 1;
+                        const int c0 = __shfl(cnt, ul), c1 = __shfl(cnt, ul + 32);
+                        const int64_t ugl = (int64_t)blockIdx.x * UPB + w * UPW + g * 32 + ul;
+                        uint2* rg = a.buf + (ugl * a.nseg_total + seg) * (int64_t)a.G;
+                        const uint32_t T = select_user(rg, c0, rg + HG, c1, a.C, hist, stage);
+                        if ((l & 31) == ul) {
+                            theta[g] = ord_f32(T);
+                            off[g] = loff8[g] + (h ? 0u : 8u * (uint32_t)a.C);
+                        }
+                    }
+                    // nothing of the compaction's own loads stays in flight: the waits of
+                    // the tile loop then count the tile loads only
+                    __builtin_amdgcn_s_waitcnt(0);
+                }
+                float mx = v[g][0];
+#pragma unroll
+                for (int r = 1; r < 16; r++) mx = fmaxf(mx, v[g][r]);
+                if (mx > theta[g]) {
+                    const uint32_t pbase = (uint32_t)seg0 + (uint32_t)(b * 32) + 4u * (uint32_t)h;
+#pragma unroll
+                    for (int r = 0; r < 16; r++) {
+                        if (v[g][r] > theta[g]) {
+                            const u32x2 e = {__float_as_uint(v[g][r]), pbase + (uint32_t)(8 * (r / 4) + (r % 4))};
+                            __builtin_amdgcn_raw_buffer_store_b64(e, wrsrc, (int)off[g], 0, 0);
+                            off[g] += 8u;
+                        }
+                    }
+                }
+            }
+        }
+    };
+    // one tile from its ring slot (static per call site, so that the compiler tells the
+    // slots' DMA writes apart)
+    auto tile = [&](uint8_t* ring, float* sc, uint8_t* ring_next2, float* sc_next2, int tt) {
+        wait_tile(tt + 1 < ntiles);
+        __builtin_amdgcn_s_barrier();
+        if (tt + 2 < ntiles) issue(ring_next2, sc_next2, tt + 2);
+#pragma unroll
+        for (int rb = 0; rb < BPT; rb++) {
+            f32x16 acc[NG];
+            mfma_block<DT, KSTEPS, LROW, NG>(ring, rb * 32, bfrag, acc);
+            scores(acc, sc, tt, rb);
+            seed_top(acc);
+            appends(acc, tt * BPT + rb);
+        }
+    };
+
+    // the user fragments and thresholds are in registers before the first tile load: the
+    // in-loop waits then count the tile loads only
+    __builtin_amdgcn_s_waitcnt(0);
+    if (ntiles > 0) {
+        issue(ring0, sc0, 0);
+        if (ntiles > 1) issue(ring1, sc1, 1);
+        for (int tt = 0; tt < ntiles; tt += 3) {
+            tile(ring0, sc0, ring2, sc2, tt);
+            if (tt + 1 < ntiles) tile(ring1, sc1, ring0, sc0, tt + 1);
+            if (tt + 2 < ntiles) tile(ring2, sc2, ring1, sc1, tt + 2);
+        }
+    }
+
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+        const int64_t ug = user_of(g);
+        const bool uok = ug < a.m;
+        if constexpr (MODE == TK_SEED) {
+            const float mine = top[g][TK_T - 1];
+            const float other = __shfl_xor(mine, 32);
+            if (l < 32 && uok) a.theta_out[ug] = fminf(mine, other);
+        } else {
+            if (uok) {
+                a.cnt[(ug * a.nseg_total + seg) * 2 + h] = (int)((off[g] - loff8[g]) >> 3);
+                if (h == 0) a.tau[ug * a.nseg_total + seg] = theta[g];
+            }
+        }
+    }
+}
+
+// The kernel of one instance: the DMA-ring form for rows of 512 bytes and more, the
+// register-prefetch form for shorter rows.
+template <int DT, int DPT>
+constexpr bool topk_ring()
+{
+    return DPT * Elt<DT>::bytes >= 512;
+}
+template <int DT, int DPT, int GPL, int MODE>
+static void (*topk_kernel())(TopkArgs)
+{
+    if constexpr (topk_ring<DT, DPT>()) return &k_topk_ring<DT, DPT, GPL, MODE>;
+    else return &k_topk_reg<DT, DPT, GPL, MODE>;
+}
+template <int DT, int DPT>
+constexpr int topk_upb()
+{
+    return topk_ring<DT, DPT>() ? TK_WAVES * 32 * topk_ng<DT, DPT>() : TK_WAVES * 32;
+}
+
 template <int DT, int DPT, int MODE>
 static void topk_dispatch_g(const TopkArgs& a, hipStream_t s)
 {
-    dim3 grid((unsigned)((a.m + TK_WAVES * 32 - 1) / (TK_WAVES * 32)), (unsigned)a.nseg);
+    constexpr int UPB = topk_upb<DT, DPT>();
+    dim3 grid((unsigned)((a.m + UPB - 1) / UPB), (unsigned)a.nseg);
     if constexpr (MODE == TK_SEED) {
-        hipLaunchKernelGGL((k_topk<DT, DPT, 1, TK_SEED>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((topk_kernel<DT, DPT, 1, TK_SEED>()), grid, dim3(256), 0, s, a);
     } else {
         const int gpl = a.G / 64;
-        if (gpl == 2) hipLaunchKernelGGL((k_topk<DT, DPT, 2, TK_MAIN>), grid, dim3(256), 0, s, a);
-        else if (gpl == 4) hipLaunchKernelGGL((k_topk<DT, DPT, 4, TK_MAIN>), grid, dim3(256), 0, s, a);
-        else if (gpl == 8) hipLaunchKernelGGL((k_topk<DT, DPT, 8, TK_MAIN>), grid, dim3(256), 0, s, a);
-        else if (gpl == 16) hipLaunchKernelGGL((k_topk<DT, DPT, 16, TK_MAIN>), grid, dim3(256), 0, s, a);
+        if (gpl == 2) hipLaunchKernelGGL((topk_kernel<DT, DPT, 2, TK_MAIN>()), grid, dim3(256), 0, s, a);
+        else if (gpl == 4) hipLaunchKernelGGL((topk_kernel<DT, DPT, 4, TK_MAIN>()), grid, dim3(256), 0, s, a);
+        else if (gpl == 8) hipLaunchKernelGGL((topk_kernel<DT, DPT, 8, TK_MAIN>()), grid, dim3(256), 0, s, a);
+        else if (gpl == 16) hipLaunchKernelGGL((topk_kernel<DT, DPT, 16, TK_MAIN>()), grid, dim3(256), 0, s, a);
         else fail(RKMIPS_EINVAL, "internal: unsupported candidate buffer size");
     }
 }
 
-int topk_users_per_block(int, int) { return TK_WAVES * 32; }
+template <int DT>
+static int upb_d(int ld)
+{
+    if constexpr (DT == DT_SPLIT) return ld == 64 ? topk_upb<DT, 64>() : topk_upb<DT, 128>();
+    else {
+        switch (ld) {
+        case 32: return topk_upb<DT, 32>();
+        case 64: return topk_upb<DT, 64>();
+        case 128: return topk_upb<DT, 128>();
+        default: return topk_upb<DT, 256>();
+        }
+    }
+}
+
+int topk_users_per_block(int dtype, int ld)
+{
+    if (dtype == DT_F32) return upb_d<DT_F32>(ld);
+    if (dtype == DT_BF16) return upb_d<DT_BF16>(ld);
+    if (dtype == DT_FP8B) return upb_d<DT_FP8B>(ld);
+    return upb_d<DT_SPLIT>(ld);
+}
 
 // Workgroups of the main pass that one compute unit holds at once (registers and LDS).
 template <int DT, int DPT>
@@ -404,10 +838,10 @@ static int resident_g(int G)
     int nb = 0;
     hipError_t e = hipSuccess;
     const int gpl = G / 64;
-    if (gpl == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 2, TK_MAIN>, 256, 0);
-    else if (gpl == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 4, TK_MAIN>, 256, 0);
-    else if (gpl == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 8, TK_MAIN>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topk<DT, DPT, 16, TK_MAIN>, 256, 0);
+    if (gpl == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, topk_kernel<DT, DPT, 2, TK_MAIN>(), 256, 0);
+    else if (gpl == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, topk_kernel<DT, DPT, 4, TK_MAIN>(), 256, 0);
+    else if (gpl == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, topk_kernel<DT, DPT, 8, TK_MAIN>(), 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, topk_kernel<DT, DPT, 16, TK_MAIN>(), 256, 0);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 1;
