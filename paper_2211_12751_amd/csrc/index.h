@@ -85,6 +85,8 @@ struct Index {
     int64_t nblocks = 0;
     DevBuf block_start;          // int64 [nblocks+1]
     DevBuf center;               // float [nblocks x ld] unit centres
+    DevBuf center_mma;           // BF16 pair rows [nblocks x 2 ld] = [hi | lo] of the centres
+                                 // (matrix-core operand of the block angles; not for FP32 MFMA)
     DevBuf cos_w, sin_w, block_ok;
     DevBuf block_lb;             // float [k_max x nblocks]
 
@@ -147,7 +149,7 @@ struct Index {
     {
         const DevBuf* all[] = {&items, &item_scales, &item_order, &item_n2, &users, &user_scales, &users_mma,
                                &user_perm, &user_n2, &unorm, &cos_t, &sin_t, &user_block,
-                               &block_start, &center, &cos_w, &sin_w, &block_ok, &block_lb,
+                               &block_start, &center, &center_mma, &cos_w, &sin_w, &block_ok, &block_lb,
                                &lam64, &lam32, &cand, &cand_cnt, &cand_tau, &part_start, &num_parts,
                                &centroid, &radius, &srp, &item_codes, &user_codes};
         int64_t s = 0;
@@ -174,6 +176,8 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
                 hipStream_t s, const std::function<void()>& enqueued, ConeWork& cw,
                 const std::atomic<bool>* cancel = nullptr);
 void finish_blocks(Index& x, hipStream_t s);
+// Matrix-core operand of the block centres (x.center_mma), from x.center.
+void make_center_operand(Index& x, hipStream_t s);
 void start_partitions(Index& x, int* h_num_parts, hipStream_t s);
 // SA-ALSH index (Alg. 1) in three stream-ordered parts: the random projections, the item
 // side (partition centroids, radii, item codes; needs x.t) and the user codes (users in

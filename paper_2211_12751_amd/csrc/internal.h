@@ -185,6 +185,7 @@ struct QueryArgs {
     const float* unorm; const float* cos_t; const float* sin_t;
     const int* user_block;
     const float* center; const float* cos_w; const float* sin_w; const int* block_ok;
+    const uint16_t* center_mma;                      // [nblocks x 2 ld] BF16 [hi | lo], or null
     const float* block_lb; int64_t nblocks;
     const uint32_t* perm;                            // leaf -> original
     const float* lam32; const double* lam64; int k_max;   // [k_max x m], original user order

@@ -780,6 +780,14 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_leaf_stats<DT_BF16>, g, b, 0, s, la);
     else hipLaunchKernelGGL(k_leaf_stats<DT_FP8>, g, b, 0, s, la);
     HIPC(hipGetLastError());
+    make_center_operand(x, s);
+}
+
+void make_center_operand(Index& x, hipStream_t s)
+{
+    if (x.mma_dtype == DT_F32) return;   // the FP32 matrix cores take the FP32 centres
+    x.center_mma.alloc(sizeof(uint16_t) * (size_t)x.nblocks * 2 * x.ld);
+    launch_split_bf16(x.center.f(), x.nblocks, x.ld, x.center_mma.u16(), 2, s);
 }
 
 void finish_blocks(Index& x, hipStream_t s)

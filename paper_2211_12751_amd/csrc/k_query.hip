@@ -449,73 +449,99 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
 // row).  The result feeds the node-level bound of Lemma 2.
 // FP8 codes keep one block per thread: their decoded values would otherwise stay live
 // across the blocks and spill.
-template <int DT> constexpr int phi_nb() { return DT == DT_FP8 ? 1 : 8; }
-
-template <int DT, int DPT>
-__global__ __launch_bounds__(256) void k_phi(QueryArgs a, float* cphi, int64_t b0)
+// cos(phi) of every (block, query) pair, phi the angle between the query and the block's
+// centre (Lemma 2; Alg. 5 block test), on the matrix cores: a dense contraction of the
+// centres [nblocks x d] with the queries [nq x d].  A wave computes 32 blocks x 64 queries
+// from operand fragments read straight from global memory (the centres are reused by the
+// four waves of a workgroup through L1/L2).  Operand forms (MDT, the index's matrix-core
+// type): BF16 and widened FP8 queries are exact BF16 rows and meet the centres' BF16 pair
+// rows [hi | lo] as q.hi + q.lo; split FP32 queries (pair rows) take q_h c_h + q_l c_h +
+// q_h c_l; FP32 matrix cores take the FP32 rows.  The error of each form is err_phi.
+// Output cphi[block x nq + query], clamped to [-1, 1].
+template <int MDT, int LD>
+__global__ __launch_bounds__(256) void k_phi(QueryArgs a, float* cphi, int64_t b_base)
 {
-    constexpr int EB = Elt<DT>::bytes;
-    constexpr int PER = 16 / EB;
-    constexpr int ROWB = DPT * EB;
-    constexpr int CB = ROWB < 64 * EB ? ROWB : 64 * EB;   // query row bytes in registers at once (64 values)
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    constexpr int PHI_NB = phi_nb<DT>();
-    const int64_t bb = b0 + (int64_t)blockIdx.y * PHI_NB;
-    const int nbh = (int)(a.nblocks - bb < PHI_NB ? a.nblocks - bb : PHI_NB);
-    if (q >= a.nq) return;
-    const uint8_t* qr = (const uint8_t*)a.queries + q * (int64_t)ROWB;
-    float acc[PHI_NB][4];
+    const int l = lane_id(), w = threadIdx.x >> 6, h = l >> 5;
+    const int64_t b0 = b_base + (int64_t)blockIdx.y * 32;
+    const int64_t q0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+    if (q0 >= a.nq) return;   // wave-uniform
+    const int64_t brow = b0 + (l & 31) < a.nblocks ? b0 + (l & 31) : a.nblocks - 1;
+    int64_t qrow[2];
 #pragma unroll
-    for (int j = 0; j < PHI_NB; j++)
+    for (int g = 0; g < 2; g++) qrow[g] = q0 + g * 32 + (l & 31) < a.nq ? q0 + g * 32 + (l & 31) : a.nq - 1;
+    f32x16 acc[2];
 #pragma unroll
-        for (int e = 0; e < 4; e++) acc[j][e] = 0.f;
-    for (int cb0 = 0; cb0 < ROWB; cb0 += CB) {
-        i32x4 qv[CB / 16];
+    for (int g = 0; g < 2; g++)
 #pragma unroll
-        for (int i = 0; i < CB / 16; i++) qv[i] = *(const i32x4*)(qr + cb0 + 16 * i);
+        for (int r = 0; r < 16; r++) acc[g][r] = 0.f;
+    if constexpr (MDT == DT_F32) {
+        // 32x32x2 FP32 products: the 16 bytes at t * 32 + h * 16 hold elements 8t + 4h + e
+        const uint8_t* crow = (const uint8_t*)(a.center + brow * LD);
+        const uint8_t* qr[2] = {(const uint8_t*)a.mma_queries + qrow[0] * LD * 4,
+                                (const uint8_t*)a.mma_queries + qrow[1] * LD * 4};
+#pragma unroll 4
+        for (int t = 0; t < LD / 8; t++) {
+            const f32x4 c4 = *(const f32x4*)(crow + t * 32 + h * 16);
 #pragma unroll
-        for (int j = 0; j < PHI_NB; j++) {
-            if (j >= nbh) break;   // wave-uniform
-            const float* cr = a.center + (bb + j) * (int64_t)DPT + cb0 / EB;
+            for (int g = 0; g < 2; g++) {
+                const f32x4 q4 = *(const f32x4*)(qr[g] + t * 32 + h * 16);
 #pragma unroll
-            for (int i = 0; i < CB / 16; i++) {
+                for (int e = 0; e < 4; e++) acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c4[e], q4[e], acc[g], 0, 0, 0);
+            }
+        }
+    } else {
+        // BF16 pair rows of the centres: hi at [0, LD), lo at [LD, 2 LD)
+        const uint8_t* crow = (const uint8_t*)(a.center_mma + brow * 2 * LD);
+        constexpr int QLD = MDT == DT_SPLIT ? 2 * LD : LD;   // query operand row (elements)
+        const uint8_t* qr[2] = {(const uint8_t*)a.mma_queries + qrow[0] * QLD * 2,
+                                (const uint8_t*)a.mma_queries + qrow[1] * QLD * 2};
+#pragma unroll 4
+        for (int t = 0; t < LD / 16; t++) {
+            const bf16x8 ch = __builtin_bit_cast(bf16x8, *(const i32x4*)(crow + t * 32 + h * 16));
+            const bf16x8 cl = __builtin_bit_cast(bf16x8, *(const i32x4*)(crow + LD * 2 + t * 32 + h * 16));
 #pragma unroll
-                for (int e = 0; e < PER; e++) {
-                    float x;
-                    if constexpr (DT == DT_F32) x = __int_as_float(qv[i][e]);
-                    else if constexpr (DT == DT_BF16) x = bf16_to_f32((uint16_t)((uint32_t)qv[i][e >> 1] >> (16 * (e & 1))));
-                    else x = e4m3_to_f32((uint8_t)((uint32_t)qv[i][e >> 2] >> (8 * (e & 3))));
-                    acc[j][e & 3] = fmaf(x, cr[i * PER + e], acc[j][e & 3]);
+            for (int g = 0; g < 2; g++) {
+                const bf16x8 qh = __builtin_bit_cast(bf16x8, *(const i32x4*)(qr[g] + t * 32 + h * 16));
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch, qh, acc[g], 0, 0, 0);
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cl, qh, acc[g], 0, 0, 0);
+                if constexpr (MDT == DT_SPLIT) {
+                    const bf16x8 ql = __builtin_bit_cast(bf16x8, *(const i32x4*)(qr[g] + LD * 2 + t * 32 + h * 16));
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch, ql, acc[g], 0, 0, 0);
                 }
             }
         }
     }
-    const float qn = a.qnorm[q];
-    const float qsc = DT == DT_FP8 ? a.query_scales[q] : 1.f;
 #pragma unroll
-    for (int j = 0; j < PHI_NB; j++) {
-        if (j >= nbh) break;
-        float dot = (acc[j][0] + acc[j][1]) + (acc[j][2] + acc[j][3]);
-        if constexpr (DT == DT_FP8) dot *= qsc;
-        float c = qn > 0.f ? dot / qn : 0.f;
-        c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
-        cphi[(bb + j) * a.nq + q] = c;
+    for (int g = 0; g < 2; g++) {
+        const int64_t q = q0 + g * 32 + (l & 31);
+        if (q >= a.nq) continue;
+        const float qn = a.qnorm[q];
+        const float qsc = MDT == DT_FP8B ? a.query_scales[q] : 1.f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int64_t blk = b0 + mfma32_row(r, l);
+            if (blk >= a.nblocks) continue;
+            float dot = acc[g][r];
+            if constexpr (MDT == DT_FP8B) dot *= qsc;
+            float c = qn > 0.f ? dot / qn : 0.f;
+            c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
+            cphi[blk * a.nq + q] = c;
+        }
     }
 }
 
-template <int DT>
+template <int MDT>
 static void phi_d(const QueryArgs& a, float* cphi, hipStream_t s)
 {
-    constexpr int NB = phi_nb<DT>();
-    const int64_t per_launch = (int64_t)65535 * NB;
+    const int64_t per_launch = (int64_t)65535 * 32;
     for (int64_t b0 = 0; b0 < a.nblocks; b0 += per_launch) {
         const int64_t nbl = std::min<int64_t>(per_launch, a.nblocks - b0);
-        dim3 g((unsigned)((a.nq + 255) / 256), (unsigned)((nbl + NB - 1) / NB));
+        dim3 g((unsigned)((a.nq + 255) / 256), (unsigned)((nbl + 31) / 32));
         switch (a.ld) {
-        case 32: hipLaunchKernelGGL((k_phi<DT, 32>), g, dim3(256), 0, s, a, cphi, b0); break;
-        case 64: hipLaunchKernelGGL((k_phi<DT, 64>), g, dim3(256), 0, s, a, cphi, b0); break;
-        case 128: hipLaunchKernelGGL((k_phi<DT, 128>), g, dim3(256), 0, s, a, cphi, b0); break;
-        case 256: hipLaunchKernelGGL((k_phi<DT, 256>), g, dim3(256), 0, s, a, cphi, b0); break;
+        case 32: hipLaunchKernelGGL((k_phi<MDT, 32>), g, dim3(256), 0, s, a, cphi, b0); break;
+        case 64: hipLaunchKernelGGL((k_phi<MDT, 64>), g, dim3(256), 0, s, a, cphi, b0); break;
+        case 128: hipLaunchKernelGGL((k_phi<MDT, 128>), g, dim3(256), 0, s, a, cphi, b0); break;
+        case 256: hipLaunchKernelGGL((k_phi<MDT, 256>), g, dim3(256), 0, s, a, cphi, b0); break;
         default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
         }
     }
@@ -524,9 +550,12 @@ static void phi_d(const QueryArgs& a, float* cphi, hipStream_t s)
 void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s)
 {
     if (a.nq <= 0 || a.nblocks <= 0) return;
-    if (a.dtype == DT_F32) phi_d<DT_F32>(a, cphi, s);
-    else if (a.dtype == DT_BF16) phi_d<DT_BF16>(a, cphi, s);
-    else phi_d<DT_FP8>(a, cphi, s);
+    if (a.mma_dtype != DT_F32 && !a.center_mma) fail(RKMIPS_EINVAL, "internal: centre operand missing");
+    if (a.mma_dtype == DT_F32) phi_d<DT_F32>(a, cphi, s);
+    else if (a.mma_dtype == DT_BF16) phi_d<DT_BF16>(a, cphi, s);
+    else if (a.mma_dtype == DT_FP8B) phi_d<DT_FP8B>(a, cphi, s);
+    else if (a.mma_dtype == DT_SPLIT) phi_d<DT_SPLIT>(a, cphi, s);
+    else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());
 }
 

@@ -231,6 +231,9 @@ Index* load_index(const char* path, hipStream_t s)
         bufs[i]->alloc(host[i].size());
         HIPC(hipMemcpy(bufs[i]->p, host[i].data(), host[i].size(), hipMemcpyHostToDevice));
     }
+    // derived from the stored centres rather than kept in the file
+    make_center_operand(*x, s);
+    HIPC(hipStreamSynchronize(s));
     return x.release();
 }
 

@@ -135,7 +135,25 @@ void Index::give_ws(Workspace* w)
 }
 
 // bound constants
-static float phi_err(int d) { return (float)(fast_err_rel(d) + 2e-6); }
+// Error bound of cos(phi) from the matrix cores (relative to ||q||, centres of unit norm),
+// plus 2e-6 for the query norm, the stored centre and the final division:
+//  - BF16 and widened FP8 queries are exact BF16 values and the centres enter as
+//    hi + lo BF16 pairs: the lost part of a centre is below 2^-18 of it, and the 2d exact
+//    products accumulate in FP32 (factor 2 for the matrix core's order);
+//  - split FP32 queries take the three-product form of the fast scores;
+//  - FP32 matrix cores: the fast-score bound itself.
+static float phi_err(const Index& x)
+{
+    const int d = x.d;
+    double e;
+    if (x.mma_dtype == DT_SPLIT) e = split_err_rel(d);
+    else if (x.mma_dtype == DT_F32) e = fast_err_rel(d);
+    else {
+        const double u = std::ldexp(1.0, -24), n = 2.0 * d + 2.0;
+        e = std::ldexp(1.0, -18) + 2.0 * (n * u / (1.0 - n * u)) * (1.0 + std::ldexp(1.0, -8));
+    }
+    return (float)(e + 2e-6);
+}
 static const float kBoundSlack = 4e-6f;
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
@@ -158,6 +176,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.users = x.users.p; a.user_scales = x.user_scales.f(); a.m = x.m; a.d = x.d; a.ld = x.ld;
     a.unorm = x.unorm.f(); a.cos_t = x.cos_t.f(); a.sin_t = x.sin_t.f(); a.user_block = x.user_block.i();
     a.center = x.center.f(); a.cos_w = x.cos_w.f(); a.sin_w = x.sin_w.f(); a.block_ok = x.block_ok.i();
+    a.center_mma = x.center_mma.u16();
     a.block_lb = x.block_lb.f(); a.nblocks = x.nblocks; a.perm = x.user_perm.u32();
     a.lam32 = x.lam32.f(); a.lam64 = x.lam64.d(); a.k_max = x.prm.k_max;
     a.queries = w.qpad.p; a.query_scales = w.qsc.f(); a.nq = nq; a.qnorm = w.qnorm.f(); a.cphi = w.cphi.f();
@@ -169,7 +188,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.qslot = w.qslot; a.qorig = w.qorig; a.qk = w.qk; a.slot_k = w.slotk;
     a.flags = flags | x.prm.flags;
     a.err_rel = x.err_fast;
-    a.err_phi = phi_err(x.d);
+    a.err_phi = phi_err(x);
     a.bound_slack = kBoundSlack;
     unsigned long long* c = (unsigned long long*)w.ctr.p;
     a.pool = (unsigned long long*)w.pool.p; a.pool_count = c + 0; a.pool_cap = w.pool_cap;
