@@ -9,6 +9,7 @@ Functions (all inputs are numpy arrays in storage format: float32, uint16 BF16 b
 or uint8 FP8 e4m3 codes with float32 per-row scales):
 
 * ``lambda_table``   lambda_u^(j), j = 1..k_max, per user (Def. 1; Alg. 4)
+* ``fp8_scores``     canonical FP8 scores of a user set against a row set (exact)
 * ``member``         membership of user u in R_k(q)   (Def. 1, ">=" tie reading)
 * ``count_beating``  #{p : s(u,p) > s(u,q)}           (Def. 1, count form)
 * ``item_order``     canonical squared norms and descending order (Alg. 4 / Alg. 1)
@@ -87,8 +88,32 @@ def score(dtype, a, a_scales, ra, b, b_scales, rb) -> float:
                           _p(b), _p(_c(b_scales, np.float32)), C.c_int64(rb))
 
 
+def _fp8_codes_f64(X):
+    """Decoded e4m3 code values (unscaled) as float64, through the C decoder's table."""
+    table = np.array([e4m3_value(c) for c in range(256)], dtype=np.float64)
+    return table[np.asarray(X)]
+
+
+def fp8_scores(U, U_scales, X, X_scales, user_idx=None, Xc=None):
+    """Canonical FP8 scores s(u, x) = (s_u s_x) S(u, x) for the selected users (rows) and
+    all rows x (columns), float64.  S, the sum of the decoded code products, is a sum of
+    multiples of 2^-18 below 2^26 in magnitude, so every partial sum is exact in float64
+    and a matrix product in any order gives S exactly; s_u s_x is exact too, so the one
+    rounding is the final product, as in the canonical definition."""
+    ui = np.arange(len(U)) if user_idx is None else np.asarray(user_idx, np.int64)
+    Uc = _fp8_codes_f64(np.asarray(U)[ui])
+    if Xc is None:
+        Xc = _fp8_codes_f64(X)
+    S = Uc @ Xc.T
+    return (np.asarray(U_scales, np.float64)[ui][:, None] * np.asarray(X_scales, np.float64)[None, :]) * S
+
+
 def lambda_table(dtype, P, P_scales, U, U_scales, k_max, user_idx=None, nthreads=None):
-    """float64 [k_max x m_sel] (k-major): row j is lambda^(j+1) of each selected user."""
+    """float64 [k_max x m_sel] (k-major): row j is lambda^(j+1) of each selected user.
+    FP8 data: the scores come from fp8_scores (exact matrix product), the order statistics
+    from a sort; other types: the C reference, one pair at a time."""
+    if dtype == "fp8":
+        return _lambda_fp8(P, P_scales, U, U_scales, k_max, user_idx)
     P, U = _c(P), _c(U)
     ui, ms = _sel(user_idx, U.shape[0])
     lam = np.empty((k_max, ms), dtype=np.float64)
@@ -100,8 +125,30 @@ def lambda_table(dtype, P, P_scales, U, U_scales, k_max, user_idx=None, nthreads
     return lam
 
 
+def _lambda_fp8(P, P_scales, U, U_scales, k_max, user_idx, chunk_bytes=1 << 30):
+    ui = np.arange(len(U)) if user_idx is None else np.asarray(user_idx, np.int64)
+    n = len(P)
+    lam = np.full((k_max, len(ui)), -np.inf)
+    kk = min(k_max, n)
+    rows = max(1, int(chunk_bytes // (8 * max(n, 1))))
+    Pc = _fp8_codes_f64(P)   # decoded once
+    for r0 in range(0, len(ui), rows):
+        sc = fp8_scores(U, U_scales, P, P_scales, user_idx=ui[r0:r0 + rows], Xc=Pc)
+        if kk < n:
+            sc = np.partition(sc, n - kk, axis=1)[:, n - kk:]
+        lam[:kk, r0:r0 + rows] = -np.sort(-sc, axis=1).T[:kk]
+    return lam
+
+
 def member(dtype, U, U_scales, Q, Q_scales, ks, lam, user_idx=None, nthreads=None):
-    """uint8 [nq x m_sel]: 1 iff s(u,q) >= lambda_u^(k_q)."""
+    """uint8 [nq x m_sel]: 1 iff s(u,q) >= lambda_u^(k_q).  FP8 data: scores from
+    fp8_scores (exact); other types: the C reference."""
+    if dtype == "fp8":
+        ks = np.asarray(ks, np.int64)
+        if np.any(ks < 1) or np.any(ks > lam.shape[0]):
+            raise ValueError("k outside [1, k_max]")
+        sc = fp8_scores(U, U_scales, Q, Q_scales, user_idx=user_idx)            # [m_sel x nq]
+        return (sc.T >= np.asarray(lam, np.float64)[ks - 1, :]).astype(np.uint8)
     U, Q = _c(U), _c(Q)
     ui, ms = _sel(user_idx, U.shape[0])
     ks = _c(np.asarray(ks), np.int32)

@@ -605,3 +605,45 @@ def test_sah_norm_test_fires_only_at_or_above_u_times_pk():
     assert [g.tolist() for g in got] == [[0], [0], [], [0]]
     assert st["norm_pairs"] == [(0, 0), (3, 0)] and st["alg2_pairs"] == [(1, 0), (2, 0)]
     assert st["norm_yes"] == 2 and st["alg2"] == 2
+
+
+# ------------------------------------------------ FP8 scores by matrix product
+def test_fp8_matrix_product_scores_equal_the_sequential_canonical_ones():
+    """The matrix-product form of the FP8 scores (any summation order) equals the C
+    reference's index-order sum bit for bit, also with extreme codes (448, the smallest
+    subnormal, signs, zeros) and scales; the lambda table built from it equals the C
+    reference's."""
+    g = np.random.default_rng(44)
+    d = 96
+    P = g.integers(0, 256, (70, d)).astype(np.uint8)
+    U = g.integers(0, 256, (23, d)).astype(np.uint8)
+    P[P == 0x7F] = 0x7E
+    P[P == 0xFF] = 0xFE
+    U[U == 0x7F] = 0x7E
+    U[U == 0xFF] = 0xFE
+    P[0] = 0x7E                   # all 448
+    U[0] = 0x7E
+    P[1] = 0x01                   # smallest subnormal 2^-9
+    U[1, ::2] = 0x81
+    P[2] = 0                      # zero row
+    ps = np.exp(g.standard_normal(70) * 3).astype(np.float32)
+    us = np.exp(g.standard_normal(23) * 3).astype(np.float32)
+    S = O.fp8_scores(U, us, P, ps)
+    for u in range(23):
+        for p in range(70):
+            assert S[u, p] == O.score("fp8", U, us, u, P, ps, p)
+    lam = O.lambda_table("fp8", P, ps, U, us, 9, user_idx=[3, 0, 22, 7])
+    for t, u in enumerate([3, 0, 22, 7]):
+        row = sorted((O.score("fp8", U, us, u, P, ps, p) for p in range(70)), reverse=True)
+        assert np.array_equal(lam[:, t], row[:9])
+
+
+def test_fp8_membership_by_matrix_product_equals_the_count_form():
+    """Membership of FP8 data (matrix-product scores) agrees with the direct count form
+    #{p : s(u,p) > s(u,q)} < k of the C reference."""
+    w = I.make("c5", n=120, m=40, nq=15, d=24, seed=45)
+    ks = (np.arange(15) % 7 + 1).astype(np.int32)
+    lam = O.lambda_table("fp8", w.items, w.item_scales, w.users, w.user_scales, 7)
+    mem = O.member("fp8", w.users, w.user_scales, w.queries, w.query_scales, ks, lam)
+    beats = O.count_beating("fp8", w.items, w.item_scales, w.users, w.user_scales, w.queries, w.query_scales)
+    assert np.array_equal(mem, (beats < ks[:, None]).astype(np.uint8))
