@@ -286,6 +286,21 @@ rkmips_status rkmips_saalsh_probe(rkmips_index *idx, const void *queries, const 
                                   const int64_t *pair_user, int64_t npairs, float probe_frac,
                                   void *stream, double *phi_out, int32_t *answer_out);
 
+/* rkmips_saalsh_probe for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * results and errors; it calls no hipMalloc, hipFree or allocating library routine.  Its
+ * staging (padded queries, k values, packed pairs, phi and answers) and Alg. 2's
+ * candidate scratch come from one 64 MiB device array per GPU, held until the process
+ * ends; a batch that does not fit (nq x row bytes + about 28 bytes per pair + one
+ * candidate row of ceil(probe_frac n) + t + k_max + 1 doubles) is refused with ERANGE
+ * before any device work.  All calls on one GPU share that array and it keeps the last
+ * call's contents: calls that overlap on one GPU (other threads or streams) race and
+ * must be serialised by the caller.  Synchronous on `stream`. */
+rkmips_status rkmips_saalsh_probe_noalloc(rkmips_index *idx, const void *queries, const float *query_scales,
+                                          int64_t nq, const int32_t *ks, const int64_t *pair_query,
+                                          const int64_t *pair_user, int64_t npairs, float probe_frac,
+                                          void *stream, double *phi_out, int32_t *answer_out);
+
 /* Cone-Tree blocks of step 4.  leaf_users: host int32 [m] original user indices in
  * leaf order; block_start: host int64 [B+1]; center: host float [B x d] unit block
  * centres; cos_omega/sin_omega: host float [B] (bounds of the maximum angle); cos_theta

@@ -77,6 +77,7 @@ struct Index {
     DevBuf users, user_scales;   // [m x ld], [m]
     DevBuf users_mma;            // matrix-core user rows (split FP32 or widened FP8), leaf order
     DevBuf user_perm;            // uint32 [m] leaf position -> original user
+    DevBuf user_inv;             // uint32 [m] original user -> leaf position (derived)
     DevBuf user_n2;              // double [m] leaf order
     DevBuf unorm, cos_t, sin_t;  // float [m] leaf order
     DevBuf user_block;           // int [m]
@@ -148,7 +149,7 @@ struct Index {
     int64_t device_bytes() const
     {
         const DevBuf* all[] = {&items, &item_scales, &item_order, &item_n2, &users, &user_scales, &users_mma,
-                               &user_perm, &user_n2, &unorm, &cos_t, &sin_t, &user_block,
+                               &user_perm, &user_inv, &user_n2, &unorm, &cos_t, &sin_t, &user_block,
                                &block_start, &center, &center_mma, &cos_w, &sin_w, &block_ok, &block_lb,
                                &lam64, &lam32, &cand, &cand_cnt, &cand_tau, &part_start, &num_parts,
                                &centroid, &radius, &srp, &item_codes, &user_codes};
@@ -178,6 +179,8 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
 void finish_blocks(Index& x, hipStream_t s);
 // Matrix-core operand of the block centres (x.center_mma), from x.center.
 void make_center_operand(Index& x, hipStream_t s);
+// x.user_inv from x.user_perm.
+void make_user_inverse(Index& x, hipStream_t s);
 void start_partitions(Index& x, int* h_num_parts, hipStream_t s);
 // SA-ALSH index (Alg. 1) in three stream-ordered parts: the random projections, the item
 // side (partition centroids, radii, item codes; needs x.t) and the user codes (users in

@@ -749,6 +749,7 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     // ---- leaves are the blocks; users move into leaf order
     x.nblocks = nseg_final;
     x.user_perm.swap(perm_a);
+    make_user_inverse(x, s);
     const int eb = elt_bytes(x.dtype);
     x.users.alloc((size_t)m * ld * eb);
     if (x.dtype == RKMIPS_FP8_E4M3) x.user_scales.alloc(sizeof(float) * m);
@@ -781,6 +782,20 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     else hipLaunchKernelGGL(k_leaf_stats<DT_FP8>, g, b, 0, s, la);
     HIPC(hipGetLastError());
     make_center_operand(x, s);
+}
+
+__global__ void k_inv_perm(const uint32_t* perm, int64_t m, uint32_t* inv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) inv[perm[i]] = (uint32_t)i;
+}
+
+void make_user_inverse(Index& x, hipStream_t s)
+{
+    x.user_inv.alloc(sizeof(uint32_t) * (size_t)x.m);
+    hipLaunchKernelGGL(k_inv_perm, dim3((unsigned)((x.m + 255) / 256)), dim3(256), 0, s, x.user_perm.u32(), x.m,
+                       x.user_inv.u32());
+    HIPC(hipGetLastError());
 }
 
 void make_center_operand(Index& x, hipStream_t s)

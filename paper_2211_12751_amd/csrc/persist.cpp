@@ -233,6 +233,7 @@ Index* load_index(const char* path, hipStream_t s)
     }
     // derived from the stored centres rather than kept in the file
     make_center_operand(*x, s);
+    make_user_inverse(*x, s);
     HIPC(hipStreamSynchronize(s));
     return x.release();
 }

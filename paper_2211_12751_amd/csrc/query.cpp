@@ -498,6 +498,62 @@ static void query_batch_checks(rkmips_index* idx, const void* queries, int64_t n
     if (nq > 0 && (!queries || !ks)) fail(RKMIPS_EINVAL, "queries/ks is NULL");
 }
 
+// ------------------------------------------------------------ no-allocation Alg. 2 probe
+// rkmips_saalsh_probe_noalloc takes every device buffer it needs from this array: one
+// copy per GPU, held until the process ends.  In host code the array's name is only a
+// stand-in; host code uses the address hipGetSymbolAddress returns for the current
+// device (noalloc_base).
+static constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static unsigned char* noalloc_base()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned char* base[kMaxDevices] = {};
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(RKMIPS_EDEVICE, "device index beyond the no-allocation table");
+    std::lock_guard<std::mutex> g(mu);
+    if (!base[dev]) {   // once per device, with that device current
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(RKMIPS_EDEVICE, std::string("no-allocation scratch: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        }
+        base[dev] = (unsigned char*)p;
+    }
+    return base[dev];
+}
+
+// Consecutive 256-byte aligned pieces of the scratch array.
+struct ScratchCarve {
+    unsigned char* base;
+    size_t used = 0;
+    void* take(size_t bytes)
+    {
+        const size_t o = (used + 255) & ~(size_t)255;
+        if (o > kNoAllocBytes || bytes > kNoAllocBytes - o)
+            fail(RKMIPS_ERANGE, "batch exceeds the 64 MiB no-allocation scratch");
+        used = o + bytes;
+        return base + o;
+    }
+    size_t left() const
+    {
+        const size_t o = (used + 255) & ~(size_t)255;
+        return o < kNoAllocBytes ? kNoAllocBytes - o : 0;
+    }
+};
+
+// (query, original user) -> (query << 32 | leaf position of the user)
+__global__ void k_pack_pairs(const int64_t* pq, const int64_t* pu, const uint32_t* inv, int64_t n,
+                             unsigned long long* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = ((unsigned long long)pq[i] << 32) | inv[pu[i]];
+}
+
 extern "C" {
 
 rkmips_status rkmips_query_batch(rkmips_index* idx, const void* queries, const float* query_scales, int64_t nq,
@@ -640,6 +696,59 @@ rkmips_status rkmips_saalsh_kmips(rkmips_index* idx, const int64_t* users, int64
                 std::memcpy(scores_out + (c0 + i) * k, htab.data() + (size_t)i * row + (size_t)hj[i] * k,
                             sizeof(double) * k);
         }
+    });
+}
+
+rkmips_status rkmips_saalsh_probe_noalloc(rkmips_index* idx, const void* queries, const float* query_scales,
+                                          int64_t nq, const int32_t* ks, const int64_t* pair_query,
+                                          const int64_t* pair_user, int64_t npairs, float probe_frac, void* stream,
+                                          double* phi_out, int32_t* answer_out)
+{
+    return qguard([&] {
+        if (!idx) fail(RKMIPS_EINVAL, "index is NULL");
+        Index& x = *(Index*)idx;
+        x.wait_ready();
+        if (nq < 1 || !queries || !ks) fail(RKMIPS_EINVAL, "queries/ks missing");
+        if (npairs < 0 || (npairs > 0 && (!pair_query || !pair_user || !phi_out || !answer_out)))
+            fail(RKMIPS_EINVAL, "pair arrays missing");
+        if (!(probe_frac > 0.f && probe_frac <= 1.f)) fail(RKMIPS_EINVAL, "probe_frac must be in (0, 1]");
+        const bool fp8 = x.dtype == RKMIPS_FP8_E4M3;
+        if (fp8 != (query_scales != nullptr)) fail(RKMIPS_EINVAL, "scales are required exactly for FP8 data");
+        for (int64_t i = 0; i < nq; i++)
+            if (ks[i] < 1 || ks[i] > x.prm.k_max) fail(RKMIPS_ERANGE, "k outside [1, k_max]");
+        for (int64_t i = 0; i < npairs; i++)
+            if (pair_query[i] < 0 || pair_query[i] >= nq || pair_user[i] < 0 || pair_user[i] >= x.m)
+                fail(RKMIPS_EINVAL, "pair index out of range");
+        if (nq > ((int64_t)1 << 31) - 1) fail(RKMIPS_EINVAL, "nq out of range");
+        if (npairs == 0) return;
+        // every piece is carved (and the sizes checked) before the first device call
+        ScratchCarve sc{noalloc_base()};
+        void* qpad = sc.take((size_t)nq * x.ld * elt_bytes(x.dtype));
+        float* qsc = fp8 ? (float*)sc.take(sizeof(float) * (size_t)nq) : nullptr;
+        int* qk = (int*)sc.take(sizeof(int) * (size_t)nq);
+        int64_t* dq = (int64_t*)sc.take(sizeof(int64_t) * (size_t)npairs);
+        int64_t* du = (int64_t*)sc.take(sizeof(int64_t) * (size_t)npairs);
+        unsigned long long* dpairs = (unsigned long long*)sc.take(sizeof(unsigned long long) * (size_t)npairs);
+        double* phi = (double*)sc.take(sizeof(double) * (size_t)npairs);
+        int* ans = (int*)sc.take(sizeof(int) * (size_t)npairs);
+        const int64_t stride = saalsh_scratch_stride(x, probe_frac);
+        const int64_t fit = (int64_t)(sc.left() / (sizeof(double) * (size_t)stride + 256));
+        const int grid = (int)std::min<int64_t>(std::min<int64_t>(npairs, 128), fit);
+        if (grid < 1) fail(RKMIPS_ERANGE, "batch exceeds the 64 MiB no-allocation scratch");
+        double* cand = (double*)sc.take(sizeof(double) * (size_t)grid * stride);
+        hipStream_t s = (hipStream_t)stream;
+        launch_gather_rows(x.dtype, queries, x.d, query_scales, nullptr, nq, x.d, qpad, x.ld, qsc, s);
+        HIPC(hipMemcpyAsync(qk, ks, sizeof(int) * nq, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(dq, pair_query, sizeof(int64_t) * npairs, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(du, pair_user, sizeof(int64_t) * npairs, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_pack_pairs, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, dq, du,
+                           x.user_inv.u32(), npairs, dpairs);
+        HIPC(hipGetLastError());
+        SaQueryArgs sa = make_sa_args(x, qpad, qsc, qk, dpairs, npairs, probe_frac, phi, ans);
+        launch_saalsh_query(sa, cand, stride, grid, s);
+        HIPC(hipMemcpyAsync(phi_out, phi, sizeof(double) * npairs, hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(answer_out, ans, sizeof(int) * npairs, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
     });
 }
 

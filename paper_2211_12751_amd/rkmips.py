@@ -103,6 +103,7 @@ _sig = {
     "rkmips_get_saalsh": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "rkmips_get_blocks": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rkmips_saalsh_probe": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, C.c_float, _P, _P, _P]),
+    "rkmips_saalsh_probe_noalloc": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, C.c_float, _P, _P, _P]),
     "rkmips_index_free": (None, [_P]),
     "rkmips_saalsh_kmips": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P]),
     "rkmips_insert_items": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
@@ -278,6 +279,18 @@ def rkmips_saalsh_probe(idx, queries, query_scales, nq, ks, pair_query, pair_use
     ans = np.empty(len(pq), np.int32)
     _check(_lib.rkmips_saalsh_probe(idx, _ptr(queries), _ptr(query_scales), nq, _ptr(ks), _ptr(pq), _ptr(pu),
                                     len(pq), probe_frac, _stream(stream), _ptr(phi), _ptr(ans)))
+    return phi, ans
+
+
+def rkmips_saalsh_probe_noalloc(idx, queries, query_scales, nq, ks, pair_query, pair_user, probe_frac,
+                                stream=None):
+    ks = np.ascontiguousarray(ks, dtype=np.int32)
+    pq = np.ascontiguousarray(pair_query, dtype=np.int64)
+    pu = np.ascontiguousarray(pair_user, dtype=np.int64)
+    phi = np.empty(len(pq), np.float64)
+    ans = np.empty(len(pq), np.int32)
+    _check(_lib.rkmips_saalsh_probe_noalloc(idx, _ptr(queries), _ptr(query_scales), nq, _ptr(ks), _ptr(pq),
+                                            _ptr(pu), len(pq), probe_frac, _stream(stream), _ptr(phi), _ptr(ans)))
     return phi, ans
 
 
