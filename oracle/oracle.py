@@ -157,8 +157,10 @@ def member(dtype, U, U_scales, Q, Q_scales, ks, lam, user_idx=None, nthreads=Non
     r = _L().orc_member(_DT[dtype], U.shape[1], _p(U), _p(_c(U_scales, np.float32)), _p(ui),
                         C.c_int64(ms), _p(Q), _p(_c(Q_scales, np.float32)), C.c_int64(Q.shape[0]),
                         _p(ks), _p(lam), lam.shape[0], _p(out), nthreads or NTHREADS)
-    if r:
+    if r == -1:
         raise ValueError("k outside [1, k_max]")
+    if r:
+        raise MemoryError("oracle membership")
     return out
 
 

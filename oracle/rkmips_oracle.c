@@ -107,6 +107,31 @@ static int cmp_desc(const void *a, const void *b)
     return (x < y) - (x > y);
 }
 
+/* The rows of a stored matrix as the exact doubles they denote (FP8: unscaled code
+ * values), decoded once: rows[r*d + i] = elem(X, r, i).  NULL on allocation failure. */
+static double *decode_rows(const void *X, int dtype, const int64_t *row_idx, int64_t nrows, int d)
+{
+    double *out = (double *)malloc(sizeof(double) * (size_t)(nrows > 0 ? nrows : 1) * (size_t)d);
+    if (!out) return NULL;
+    for (int64_t t = 0; t < nrows; t++) {
+        int64_t r = row_idx ? row_idx[t] : t;
+        for (int i = 0; i < d; i++) out[t * d + i] = elem(X, dtype, r, d, i);
+    }
+    return out;
+}
+
+/* The canonical score of two decoded rows: index-order sum, then the scale product for
+ * FP8 (the same arithmetic as orc_score). */
+static double dot_decoded(int dtype, int d, const double *a, double sa, const double *b, double sb)
+{
+    double acc = 0.0;
+    for (int i = 0; i < d; i++)
+        acc = acc + a[i] * b[i];
+    if (dtype == ORC_FP8)
+        acc = (sa * sb) * acc;
+    return acc;
+}
+
 /* lambda[j*m_sel + t] = (j+1)-th largest s(u,p) over all p in P, for the user
  * u = user_idx[t] (or t when user_idx is NULL), j < k_max; -inf for j >= n. */
 int orc_lambda(int dtype, int d,
@@ -116,22 +141,29 @@ int orc_lambda(int dtype, int d,
                int k_max, double *lambda, int nthreads)
 {
     int bad = 0;
+    double *Pd = decode_rows(P, dtype, NULL, n, d);
+    if (!Pd) return -1;
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : bad)
     {
         double *buf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-        if (!buf) bad = 1;
+        double *ur = (double *)malloc(sizeof(double) * (size_t)d);
+        if (!buf || !ur) bad = 1;
 #pragma omp for schedule(dynamic, 16)
         for (int64_t t = 0; t < m_sel; t++) {
-            if (!buf) continue;
+            if (!buf || !ur) continue;
             int64_t u = user_idx ? user_idx[t] : t;
+            for (int i = 0; i < d; i++) ur[i] = elem(U, dtype, u, d, i);
+            double su = row_scale(u_scales, dtype, u);
             for (int64_t p = 0; p < n; p++)
-                buf[p] = orc_score(dtype, d, U, u_scales, u, P, p_scales, p);
+                buf[p] = dot_decoded(dtype, d, ur, su, Pd + p * d, row_scale(p_scales, dtype, p));
             qsort(buf, (size_t)n, sizeof(double), cmp_desc);
             for (int j = 0; j < k_max; j++)
                 lambda[(int64_t)j * m_sel + t] = j < n ? buf[j] : -INFINITY;
         }
         free(buf);
+        free(ur);
     }
+    free(Pd);
     return bad ? -1 : 0;
 }
 
@@ -144,15 +176,21 @@ int orc_member(int dtype, int d,
 {
     for (int64_t qi = 0; qi < nq; qi++)
         if (ks[qi] < 1 || ks[qi] > k_max) return -1;
+    double *Ud = decode_rows(U, dtype, user_idx, m_sel, d);
+    double *Qd = decode_rows(Q, dtype, NULL, nq, d);
+    if (!Ud || !Qd) { free(Ud); free(Qd); return -2; }
 #pragma omp parallel for num_threads(nthreads > 0 ? nthreads : 1) schedule(dynamic, 4)
     for (int64_t qi = 0; qi < nq; qi++) {
         int k = ks[qi];
+        double sq = row_scale(q_scales, dtype, qi);
         for (int64_t t = 0; t < m_sel; t++) {
             int64_t u = user_idx ? user_idx[t] : t;
-            double s = orc_score(dtype, d, U, u_scales, u, Q, q_scales, qi);
+            double s = dot_decoded(dtype, d, Ud + t * d, row_scale(u_scales, dtype, u), Qd + qi * d, sq);
             member[qi * m_sel + t] = s >= lambda[(int64_t)(k - 1) * m_sel + t];
         }
     }
+    free(Ud);
+    free(Qd);
     return 0;
 }
 
