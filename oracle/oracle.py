@@ -36,7 +36,23 @@ _LIB = os.path.join(_HERE, "_build", "liborc.so")
 _DT = {"f32": 0, "bf16": 1, "fp8": 2}
 _lib = None
 
-NTHREADS = int(os.environ.get("RKMIPS_ORACLE_THREADS", "0")) or (os.cpu_count() or 1)
+
+
+def _default_threads() -> int:
+    """Threads for the parallel loops: RKMIPS_ORACLE_THREADS, else the CPUs this process
+    may run on, capped by OMP_NUM_THREADS when that is set."""
+    n = int(os.environ.get("RKMIPS_ORACLE_THREADS", "0") or 0)
+    if n > 0:
+        return n
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return max(1, min(n, omp) if omp > 0 else n)
+
+
+NTHREADS = _default_threads()
 
 
 def build(force: bool = False) -> str:

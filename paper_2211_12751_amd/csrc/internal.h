@@ -161,9 +161,16 @@ struct SaQueryArgs {
     // SAH: 1; LAZY: 1 + 2^-40, so that mu_j bounds every canonical FP64 score of the
     // partition despite the rounding of the scores and of mu_j itself
     double mu_scale;
+    // Candidate appends past a workgroup's scratch row are not written: they set bit 4
+    // of *overflow (if given) and the caller fails the call.  The launchers check the
+    // sizes that make this impossible before every launch; the flag is the backstop.
+    int64_t cand_cap;       // set by the launchers to scratch_stride
+    int* overflow;
 };
-// Alg. 2 for each pair; scratch: grid x scratch_stride doubles (>= ceil(beta n) + t).
-void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_stride, int grid, hipStream_t s);
+// Alg. 2 for each pair; scratch: grid x scratch_stride doubles (>= ceil(beta n) + t),
+// scratch_bytes: its allocation (checked).
+void launch_saalsh_query(const SaQueryArgs& a, double* scratch, size_t scratch_bytes, int64_t scratch_stride,
+                         int grid, hipStream_t s);
 // SAH (Alg. 5) for the listed pairs: slots for the users flagged in need[m] (slot,
 // user_of_slot: int [m]; *nslots zeroed by the caller), per-user tables of kstar
 // (>= every k of the pairs) scores after each partition, chunk slots at a time (tab:
@@ -172,10 +179,12 @@ void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_
 // SA-ALSH kMIPS for nu users (leaf positions user_of_slot, *nslots = nu on the device):
 // tab [nu x (t + 1) x k] per-partition best-k rows, jlast [nu] the last row written.
 void launch_saalsh_kmips(const SaQueryArgs& a, const int* user_of_slot, const int* nslots, int64_t nu, int k,
-                         double* tab, int* jlast, double* scratch, int64_t scratch_stride, int grid, hipStream_t s);
+                         double* tab, int* jlast, double* scratch, size_t scratch_bytes, int64_t scratch_stride,
+                         int grid, hipStream_t s);
 void launch_sah(const SaQueryArgs& a, const unsigned char* need, int* slot, int* user_of_slot, int* nslots,
-                const double* score, int kstar, double* tab, int64_t chunk, double* scratch,
+                const double* score, int kstar, double* tab, int64_t chunk, double* scratch, size_t scratch_bytes,
                 int64_t scratch_stride, int grid, hipStream_t s);
+constexpr int kSaalshOverflowBit = 4;
 
 // ---------------------------------------------------------------- query
 struct QueryArgs {

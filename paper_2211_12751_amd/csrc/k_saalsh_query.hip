@@ -20,6 +20,7 @@
 // answer is final.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "common.h"
 #include "index.h"
@@ -235,9 +236,15 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
     // read before any wave can append (the callers change *ccount only behind a barrier)
     const int c_begin = *ccount;
     if (take == sz) {   // every item is a candidate: no selection
-        for (int64_t p = s0 + tid; p < s1; p += SQ_T) cand[c_begin + (p - s0)] = __longlong_as_double((long long)p);
+        for (int64_t p = s0 + tid; p < s1; p += SQ_T) {
+            const int64_t slot = c_begin + (p - s0);
+            if (slot < a.cand_cap) cand[slot] = __longlong_as_double((long long)p);
+        }
         __syncthreads();
-        if (tid == 0) *ccount = c_begin + (int)sz;
+        if (tid == 0) {
+            *ccount = (int)(c_begin + sz < a.cand_cap ? c_begin + sz : a.cand_cap);
+            if (c_begin + sz > a.cand_cap && a.overflow) atomicOr(a.overflow, kSaalshOverflowBit);
+        }
     } else {
         // Each wave owns a contiguous quarter of the partition and histograms its collision
         // counts; the sum over the waves gives the cut, and the waves before a wave hold the
@@ -281,13 +288,19 @@ __device__ void probe_partition(const SaQueryArgs& a, int64_t u, float su, const
             const bool take_it = c > cut || (iseq && rank_eq < need_eq);
             // the candidate's position, in the slot its score will take (the order inside the
             // candidate multiset is irrelevant)
-            if (take_it) cand[atomicAdd(ccount, 1)] = __longlong_as_double((long long)p);
+            // exactly take items pass (take - need_eq above the cut, need_eq ties), so the
+            // slots stay below c_begin + take <= cand_cap; the test is the backstop
+            if (take_it) {
+                const int slot = atomicAdd(ccount, 1);
+                if (slot < a.cand_cap) cand[slot] = __longlong_as_double((long long)p);
+                else if (a.overflow) atomicOr(a.overflow, kSaalshOverflowBit);
+            }
         }
     }
     __syncthreads();
     // scores of the new candidates, every lane busy (the selection keeps about one item
     // in 1/beta, so scoring inside its loop would leave most lanes idle)
-    const int c_end = *ccount;
+    const int c_end = *ccount < a.cand_cap ? *ccount : (int)a.cand_cap;
     score_staged<DT>(a, u, su, cand, c_begin, c_end, s0, s1, rows + (tid >> 6) * 64 * SS_PITCH);
     __syncthreads();
 }
@@ -322,7 +335,7 @@ __global__ __launch_bounds__(SQ_T) void k_saalsh_query(SaQueryArgs a, double* sc
             const double mu = sqrt(a.item_n2[s0]) * unorm;
             if (phi > mu) { ans = 1; break; }
             probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount, &rows[0][0]);
-            const int64_t ncand = ccount;
+            const int64_t ncand = ccount < a.cand_cap ? ccount : a.cand_cap;
             __syncthreads();
             phi = ncand >= k ? block_kth(cand, ncand, k, hist, sh) : -__builtin_inf();
             if (suq < phi) { ans = 0; break; }
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(SQ_T) __attribute__((amdgpu_waves_per_eu(5, 8))) vo
             const double mu = sqrt(a.item_n2[s0]) * unorm * a.mu_scale;
             if (phi_min > mu) break;
             probe_partition<DT>(a, u, su, ucode, W, s0, s1, cand, whist, sh, &ccount, &rows[0][0]);
-            const int64_t ncand = ccount;
+            const int64_t ncand = ccount < a.cand_cap ? ccount : a.cand_cap;
             __syncthreads();
             block_top_sorted(cand, ncand, kstar, top, hist, sh, &tcount);
             double* rj = row + (int64_t)(j + 1) * kstar;
@@ -499,12 +512,44 @@ __global__ void k_sah_decide(SaQueryArgs a, const double* score, const int* slot
     }
 }
 
-void launch_sah(const SaQueryArgs& a, const unsigned char* need, int* slot, int* user_of_slot, int* nslots,
-                const double* score, int kstar, double* tab, int64_t chunk, double* scratch,
+// The sizes the probe kernels rely on, checked on the host before each launch:
+//   K: whole 32-bit code words, at most 8 of them (ucode[8]); K + 1 histogram bins fit
+//      the SQ_T + 1 per wave;
+//   the candidate row: per-user kernels (k_sah_user) start from at most kstar scores
+//      (the lambda prefix) and add ceil(beta |S_j|) <= ceil(beta n) per partition
+//      before cutting back to kstar, so they need kstar + ceil(beta n); the per-pair
+//      kernel keeps every partition's candidates, sum_j ceil(beta |S_j|) <= ceil(beta n)
+//      + t;
+//   kstar <= 256 (the top[] array of block_top_sorted);
+//   grid rows of scratch_stride doubles inside the scratch allocation.
+static SaQueryArgs checked_args(const SaQueryArgs& a, int64_t kstar, bool per_user, size_t scratch_bytes,
+                                int64_t scratch_stride, int grid)
+{
+    if (a.K < 32 || a.K > 256 || a.K % 32 != 0) fail(RKMIPS_EINVAL, "internal: SA-ALSH code width");
+    static_assert(SQ_T + 1 >= 256 + 1, "collision histogram bins");
+    if (per_user && (kstar < 1 || kstar > 256)) fail(RKMIPS_EINVAL, "internal: SA-ALSH table width");
+    const int64_t picks = (int64_t)std::ceil((double)a.beta * (double)a.n);
+    const int64_t need = per_user ? kstar + picks : picks + a.t;
+    if (scratch_stride < need) fail(RKMIPS_EINVAL, "internal: SA-ALSH candidate row too short");
+    if (scratch_stride > INT32_MAX) fail(RKMIPS_EINVAL, "internal: SA-ALSH candidate row too long");
+    if (grid < 1 || (size_t)grid * (size_t)scratch_stride * sizeof(double) > scratch_bytes)
+        fail(RKMIPS_EINVAL, "internal: SA-ALSH scratch smaller than grid x row");
+    SaQueryArgs b = a;
+    b.cand_cap = scratch_stride;
+    return b;
+}
+
+// LDS of the probe kernels (static): histograms, staged rows, counts, top[256].
+static_assert(sizeof(int) * (SQ_T / 64) * (SQ_T + 1) + (SQ_T / 64) * 64 * SS_PITCH + sizeof(int) * (4 + SQ_T + 1) +
+                      2 * sizeof(int) + sizeof(double) * 256 <= 65536,
+              "probe kernels' LDS");
+
+void launch_sah(const SaQueryArgs& a0, const unsigned char* need, int* slot, int* user_of_slot, int* nslots,
+                const double* score, int kstar, double* tab, int64_t chunk, double* scratch, size_t scratch_bytes,
                 int64_t scratch_stride, int grid, hipStream_t s)
 {
-    if (a.npairs <= 0 || a.m <= 0) return;
-    if (kstar < 1 || kstar > 256) fail(RKMIPS_EINVAL, "internal: SAH table width");
+    if (a0.npairs <= 0 || a0.m <= 0) return;
+    const SaQueryArgs a = checked_args(a0, kstar, true, scratch_bytes, scratch_stride, grid);
     hipLaunchKernelGGL(k_sah_slots, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, need, a.m, slot, nslots);
     hipLaunchKernelGGL(k_sah_invert, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, need, slot, a.m,
                        user_of_slot);
@@ -519,9 +564,11 @@ void launch_sah(const SaQueryArgs& a, const unsigned char* need, int* slot, int*
     HIPC(hipGetLastError());
 }
 
-void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_stride, int grid, hipStream_t s)
+void launch_saalsh_query(const SaQueryArgs& a0, double* scratch, size_t scratch_bytes, int64_t scratch_stride,
+                         int grid, hipStream_t s)
 {
-    if (a.npairs <= 0) return;
+    if (a0.npairs <= 0) return;
+    const SaQueryArgs a = checked_args(a0, 0, false, scratch_bytes, scratch_stride, grid);
     if (a.dtype == DT_F32) hipLaunchKernelGGL(k_saalsh_query<DT_F32>, dim3(grid), dim3(SQ_T), 0, s, a, scratch, scratch_stride);
     else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_saalsh_query<DT_BF16>, dim3(grid), dim3(SQ_T), 0, s, a, scratch, scratch_stride);
     else hipLaunchKernelGGL(k_saalsh_query<DT_FP8>, dim3(grid), dim3(SQ_T), 0, s, a, scratch, scratch_stride);
@@ -532,11 +579,13 @@ void launch_saalsh_query(const SaQueryArgs& a, double* scratch, int64_t scratch_
 // positions), the k best scores found by the probes, partitions visited in order until
 // the k-th best exceeds mu_j; tab [nu x (t + 1) x k], jlast [nu]: row jlast of a user is
 // its answer.
-void launch_saalsh_kmips(const SaQueryArgs& a, const int* user_of_slot, const int* nslots, int64_t nu, int k,
-                         double* tab, int* jlast, double* scratch, int64_t scratch_stride, int grid, hipStream_t s)
+void launch_saalsh_kmips(const SaQueryArgs& a0, const int* user_of_slot, const int* nslots, int64_t nu, int k,
+                         double* tab, int* jlast, double* scratch, size_t scratch_bytes, int64_t scratch_stride,
+                         int grid, hipStream_t s)
 {
     if (nu <= 0) return;
     if (k < 1 || k > 256) fail(RKMIPS_EINVAL, "internal: kMIPS width");
+    const SaQueryArgs a = checked_args(a0, k, true, scratch_bytes, scratch_stride, grid);
     if (a.dtype == DT_F32) hipLaunchKernelGGL(k_sah_user<DT_F32>, dim3(grid), dim3(SQ_T), 0, s, a, user_of_slot, nslots, (int64_t)0, nu, k, tab, scratch, scratch_stride, jlast);
     else if (a.dtype == DT_BF16) hipLaunchKernelGGL(k_sah_user<DT_BF16>, dim3(grid), dim3(SQ_T), 0, s, a, user_of_slot, nslots, (int64_t)0, nu, k, tab, scratch, scratch_stride, jlast);
     else hipLaunchKernelGGL(k_sah_user<DT_FP8>, dim3(grid), dim3(SQ_T), 0, s, a, user_of_slot, nslots, (int64_t)0, nu, k, tab, scratch, scratch_stride, jlast);

@@ -327,7 +327,8 @@ void run_saalsh(const Index& x, Workspace& w, const QueryArgs& a, int64_t npairs
     }
     SaQueryArgs sa = make_sa_args(x, a.queries, a.query_scales, a.qk, a.amb, npairs, x.prm.probe_frac, w.sa_phi.d(),
                                   w.sa_answer.i());
-    launch_saalsh_query(sa, w.sa_scratch.d(), stride, grid, s);
+    sa.overflow = a.bad;
+    launch_saalsh_query(sa, w.sa_scratch.d(), w.sa_scratch.bytes, stride, grid, s);
 }
 
 // SAH mode (Alg. 5): Alg. 2 for the pairs the recheck left undecided, their count read
@@ -347,10 +348,12 @@ void run_sah(const Index& x, Workspace& w, const QueryArgs& a, hipStream_t s)
     sa.pool = a.pool; sa.pool_count = a.pool_count; sa.pool_cap = a.pool_cap;
     sa.qorig = a.qorig;
     sa.rejects = a.stats + 4;
+    sa.overflow = a.bad;
     sa.mu_scale = x.prm.mode == RKMIPS_MODE_LAZY ? 1.0 + 0x1p-40 : 1.0;
     unsigned long long* c = (unsigned long long*)w.ctr.p;
     launch_sah(sa, (const unsigned char*)w.sah_need.p, w.sah_slot.i(), w.sah_user.i(), (int*)(c + 7),
-               w.sah_score.d(), w.sah_kstar, w.sah_tab.d(), w.sah_chunk, w.sa_scratch.d(), stride, grid, s);
+               w.sah_score.d(), w.sah_kstar, w.sah_tab.d(), w.sah_chunk, w.sa_scratch.d(), w.sa_scratch.bytes, stride,
+               grid, s);
 }
 
 // Completion: overflow handling, FP64 recheck, sorted per-query lists, host copies.
@@ -361,6 +364,7 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     unsigned long long* hc = (unsigned long long*)w.h_ctr.p;
     if (hc[2] & 1ull) fail(RKMIPS_EINVAL, "non-finite value (or NaN code / non-finite scale) in the queries");
     if (hc[2] & 2ull) fail(RKMIPS_ERANGE, "a query norm is outside [1e-30, 1e30]");
+    if (hc[2] & (unsigned long long)kSaalshOverflowBit) fail(RKMIPS_EDEVICE, "internal: SA-ALSH candidates overflowed");
     int64_t cnt = (int64_t)hc[0], namb = (int64_t)hc[1];
     // with answer bits the pool only holds the lists (offsets[nq] ids), else the yes
     // answers and the rechecked close calls
@@ -419,6 +423,8 @@ void finish_batch(Index& x, Workspace& w, const void* queries, const float* qsca
     if (reject) HIPC(hipMemcpyAsync(w.h_ctr.p, w.ctr.p, sizeof(unsigned long long) * 16, hipMemcpyDeviceToHost, s));
     HIPC(hipEventRecord(w.ev1, s));
     host_wait(w.ev1);
+    if (reject && (((unsigned long long*)w.h_ctr.p)[2] & (unsigned long long)kSaalshOverflowBit))
+        fail(RKMIPS_EDEVICE, "internal: SA-ALSH candidates overflowed");
     if (reject) st.saalsh_rejects = (int64_t)((unsigned long long*)w.h_ctr.p)[12];
     offsets.assign(ho, ho + nq + 1);
     ids.assign((const int32_t*)w.h_ids.p, (const int32_t*)w.h_ids.p + total);
@@ -669,7 +675,7 @@ rkmips_status rkmips_saalsh_kmips(rkmips_index* idx, const int64_t* users, int64
                                                 std::max<int64_t>(64, (int64_t(1) << 31) / (8 * stride)));
         DevBuf dleaf, dcount, tab, jl, scratch;
         dleaf.alloc(sizeof(int) * chunk);
-        dcount.alloc(sizeof(int));
+        dcount.alloc(sizeof(int) * 2);   // [0]: users of the chunk, [1]: overflow flag
         tab.alloc(sizeof(double) * (size_t)(chunk * row));
         jl.alloc(sizeof(int) * chunk);
         scratch.alloc(sizeof(double) * (size_t)grid * stride);
@@ -679,19 +685,25 @@ rkmips_status rkmips_saalsh_kmips(rkmips_index* idx, const int64_t* users, int64
         sa.lam64 = x.lam64.d(); sa.perm = x.user_perm.u32(); sa.m = x.m;
         sa.n_init = x.prm.mode == RKMIPS_MODE_EXACT ? 0 : x.n_lam;
         sa.mu_scale = 1.0;
+        sa.overflow = dcount.i() + 1;
         std::vector<double> htab;
         std::vector<int> hj;
         for (int64_t c0 = 0; c0 < nu; c0 += chunk) {
             const int cn = (int)std::min<int64_t>(chunk, nu - c0);
             HIPC(hipStreamSynchronize(s));   // the previous chunk's kernel has read them
             HIPC(hipMemcpy(dleaf.p, leaf.data() + c0, sizeof(int) * cn, hipMemcpyHostToDevice));
-            HIPC(hipMemcpy(dcount.p, &cn, sizeof(int), hipMemcpyHostToDevice));
-            launch_saalsh_kmips(sa, dleaf.i(), dcount.i(), cn, k, tab.d(), jl.i(), scratch.d(), stride, grid, s);
+            const int hc[2] = {cn, 0};
+            HIPC(hipMemcpy(dcount.p, hc, sizeof(hc), hipMemcpyHostToDevice));
+            launch_saalsh_kmips(sa, dleaf.i(), dcount.i(), cn, k, tab.d(), jl.i(), scratch.d(), scratch.bytes, stride,
+                                grid, s);
             htab.resize((size_t)cn * row);
             hj.resize(cn);
+            int flag = 0;
             HIPC(hipMemcpyAsync(htab.data(), tab.p, sizeof(double) * htab.size(), hipMemcpyDeviceToHost, s));
             HIPC(hipMemcpyAsync(hj.data(), jl.p, sizeof(int) * cn, hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync(&flag, dcount.i() + 1, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
+            if (flag & kSaalshOverflowBit) fail(RKMIPS_EDEVICE, "internal: SA-ALSH candidates overflowed");
             for (int i = 0; i < cn; i++)
                 std::memcpy(scores_out + (c0 + i) * k, htab.data() + (size_t)i * row + (size_t)hj[i] * k,
                             sizeof(double) * k);
@@ -731,12 +743,14 @@ rkmips_status rkmips_saalsh_probe_noalloc(rkmips_index* idx, const void* queries
         unsigned long long* dpairs = (unsigned long long*)sc.take(sizeof(unsigned long long) * (size_t)npairs);
         double* phi = (double*)sc.take(sizeof(double) * (size_t)npairs);
         int* ans = (int*)sc.take(sizeof(int) * (size_t)npairs);
+        int* dflag = (int*)sc.take(sizeof(unsigned long long));
         const int64_t stride = saalsh_scratch_stride(x, probe_frac);
         const int64_t fit = (int64_t)(sc.left() / (sizeof(double) * (size_t)stride + 256));
         const int grid = (int)std::min<int64_t>(std::min<int64_t>(npairs, 128), fit);
         if (grid < 1) fail(RKMIPS_ERANGE, "batch exceeds the 64 MiB no-allocation scratch");
         double* cand = (double*)sc.take(sizeof(double) * (size_t)grid * stride);
         hipStream_t s = (hipStream_t)stream;
+        fill_u64((unsigned long long*)dflag, 1, 0ull, s);   // a kernel, not a memset node
         launch_gather_rows(x.dtype, queries, x.d, query_scales, nullptr, nq, x.d, qpad, x.ld, qsc, s);
         HIPC(hipMemcpyAsync(qk, ks, sizeof(int) * nq, hipMemcpyHostToDevice, s));
         HIPC(hipMemcpyAsync(dq, pair_query, sizeof(int64_t) * npairs, hipMemcpyHostToDevice, s));
@@ -745,10 +759,14 @@ rkmips_status rkmips_saalsh_probe_noalloc(rkmips_index* idx, const void* queries
                            x.user_inv.u32(), npairs, dpairs);
         HIPC(hipGetLastError());
         SaQueryArgs sa = make_sa_args(x, qpad, qsc, qk, dpairs, npairs, probe_frac, phi, ans);
-        launch_saalsh_query(sa, cand, stride, grid, s);
+        sa.overflow = dflag;
+        launch_saalsh_query(sa, cand, sizeof(double) * (size_t)grid * stride, stride, grid, s);
+        int flag = 0;
         HIPC(hipMemcpyAsync(phi_out, phi, sizeof(double) * npairs, hipMemcpyDeviceToHost, s));
         HIPC(hipMemcpyAsync(answer_out, ans, sizeof(int) * npairs, hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
+        if (flag & kSaalshOverflowBit) fail(RKMIPS_EDEVICE, "internal: SA-ALSH candidates overflowed");
     });
 }
 
@@ -780,7 +798,9 @@ rkmips_status rkmips_saalsh_probe(rkmips_index* idx, const void* queries, const 
         if (npairs == 0) return;
         hipStream_t s = (hipStream_t)stream;
         mem::StreamScope scope(s);
-        DevBuf qpad, qsc, qk, dpairs, phi, ans, scratch;
+        DevBuf qpad, qsc, qk, dpairs, phi, ans, scratch, dflag;
+        dflag.alloc(sizeof(int));
+        HIPC(hipMemsetAsync(dflag.p, 0, sizeof(int), s));
         qpad.alloc((size_t)nq * x.ld * elt_bytes(x.dtype));
         if (fp8) qsc.alloc(sizeof(float) * nq);
         qk.alloc(sizeof(int) * nq);
@@ -795,10 +815,14 @@ rkmips_status rkmips_saalsh_probe(rkmips_index* idx, const void* queries, const 
         scratch.alloc(sizeof(double) * (size_t)grid * stride);
         SaQueryArgs sa = make_sa_args(x, qpad.p, qsc.f(), qk.i(), (const unsigned long long*)dpairs.p, npairs,
                                       probe_frac, phi.d(), ans.i());
-        launch_saalsh_query(sa, scratch.d(), stride, grid, s);
+        sa.overflow = dflag.i();
+        launch_saalsh_query(sa, scratch.d(), scratch.bytes, stride, grid, s);
+        int flag = 0;
         HIPC(hipMemcpyAsync(phi_out, phi.p, sizeof(double) * npairs, hipMemcpyDeviceToHost, s));
         HIPC(hipMemcpyAsync(answer_out, ans.p, sizeof(int) * npairs, hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(&flag, dflag.p, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
+        if (flag & kSaalshOverflowBit) fail(RKMIPS_EDEVICE, "internal: SA-ALSH candidates overflowed");
     });
 }
 

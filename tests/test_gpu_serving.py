@@ -23,19 +23,27 @@ def setup():
     idx.close()
 
 
-@pytest.mark.parametrize("qps,max_batch,streams", [(20000.0, 32, 4), (5000.0, 256, 2), (1e6, 64, 1)])
-def test_serving_matches_alone_and_reference(setup, qps, max_batch, streams):
+@pytest.fixture(scope="module")
+def alone(setup):
+    """Each request answered on its own, as a batch of one."""
     R, w, ks, mem, idx = setup
-    arr = I.poisson_arrivals(w.nq, qps, seed=5)
+    return [idx.query(w.queries[i:i + 1], None, ks[i:i + 1])[0] for i in range(w.nq)]
+
+
+@pytest.mark.parametrize("qps,max_batch,streams", [(20000.0, 32, 4), (5000.0, 256, 2), (1e6, 64, 1), (0.0, 16, 4)])
+def test_serving_matches_alone_and_reference(setup, alone, qps, max_batch, streams):
+    R, w, ks, mem, idx = setup
+    # qps = 0: every request arrives at time 0, so the slots fill back to back
+    arr = I.poisson_arrivals(w.nq, qps, seed=5) if qps > 0 else np.zeros(w.nq, np.int64)
     got, lat, st = idx.serve(w.queries, None, ks, arr, max_batch=max_batch, num_streams=streams)
     print("stats", st, flush=True)
-    alone = idx.query(w.queries[:40], None, ks[:40])
     for i in range(w.nq):
         assert np.array_equal(got[i], np.flatnonzero(mem[i])), f"request {i}"
-        if i < 40:
-            assert np.array_equal(got[i], alone[i])
+        assert np.array_equal(got[i], alone[i]), f"request {i} differs from its lone answer"
     assert st["batches"] >= (w.nq + max_batch - 1) // max_batch
     assert 1 <= st["max_inflight"] <= streams
+    if qps == 0.0:
+        assert st["max_inflight"] >= 2, "batches never overlapped on the device"
     assert (lat > 0).all() and st["p99_us"] >= st["p50_us"] > 0
 
 
