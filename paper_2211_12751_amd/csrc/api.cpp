@@ -223,7 +223,8 @@ static void choose_topk(Index& x)
 // candidates are indexed by original user.  Two stream-ordered halves without host
 // synchronisation: the fused top-k passes, then the FP64 refine with the certificate.
 struct LambdaBuild {
-    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill, items3, users3, sel, sel_meta;
+    DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill, items3, users3, sel, sel_meta, sample,
+        sample_sc;
     Events ev{4};   // start, after the main pass, after the refine, after the seed pass
 };
 
@@ -269,7 +270,15 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
     HIPC(hipEventRecord(L.ev.ev[0], s));
     if (x.ns > 0) {   // per-user threshold estimates from the item sample
         L.theta.alloc(sizeof(float) * (size_t)m);
+        // the sample's rows gathered first, so that the pass streams contiguous tiles
+        L.sample.alloc((size_t)x.ns * topk_row_bytes(tdt, tld));
+        if (x.item_scales.p) L.sample_sc.alloc(sizeof(float) * (size_t)x.ns);
+        launch_gather_sample(tdt, mi, x.item_scales.f(), x.n_lam, x.ns, tld, L.sample.p,
+                             x.item_scales.p ? L.sample_sc.f() : nullptr, s);
         TopkArgs a0 = ta;
+        a0.items = L.sample.p;
+        a0.item_scales = x.item_scales.p ? L.sample_sc.f() : nullptr;
+        a0.n = x.ns;
         a0.ns = x.ns; a0.v0 = 0; a0.v1 = x.ns; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = x.ns;
         a0.theta_out = L.theta.f();
         launch_topk_seed(tdt, a0, s);
@@ -300,7 +309,7 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
     ra.err_rel = x.err_fast;
     ra.spill = L.spill.i();
     ra.spill_count = L.fail_count.i() + 1;
-    if (x.C <= 64) {   // the narrow pass in two kernels
+    {   // the select and rescoring kernels pass the kept candidates through memory
         L.sel.alloc(sizeof(uint2) * (size_t)m * x.C);
         L.sel_meta.alloc(sizeof(int) * 4 * (size_t)m);
         ra.sel = (uint2*)L.sel.p;

@@ -14,30 +14,58 @@ namespace rk {
 // times the squared scale), plus what validation needs: stats[slot] = max n2 (bits of a
 // non-negative double order like the value), stats[2] = min positive n2, stats[3] = 1
 // on any non-finite value, NaN code or non-finite scale.
+// One stored element: adds its exact square to acc in index order, clears ok on a
+// non-finite value or NaN code.
 template <int DT>
+__device__ __forceinline__ void norm_step(uint32_t raw, double& acc, bool& ok)
+{
+    if constexpr (DT == DT_F32) {
+        const float v = __uint_as_float(raw);
+        ok &= (raw & 0x7f800000u) != 0x7f800000u;
+        acc = __fma_rn((double)v, (double)v, acc);
+    } else if constexpr (DT == DT_BF16) {
+        ok &= (raw & 0x7f80u) != 0x7f80u;
+        const double v = (double)bf16_to_f32((uint16_t)raw);
+        acc = __fma_rn(v, v, acc);
+    } else {
+        ok &= (raw & 0x7fu) != 0x7fu;
+        const double v = (double)e4m3_to_f32((uint8_t)raw);
+        acc = __fma_rn(v, v, acc);
+    }
+}
+
+// VEC: rows of a multiple of 16 bytes at a 16-byte aligned base, read 16 bytes at a time
+// (the same index-order sum; one load per 16 bytes instead of one per element).
+template <int DT, bool VEC>
 __global__ __launch_bounds__(256) void k_norm2(const void* X, const float* scales, int64_t rows, int d, int ld, double* n2,
                         unsigned long long* stats, int slot)
 {
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int PER = 16 / EB;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool ok = true;
     double acc = 0.0;
     if (r < rows) {
         const int64_t o = r * ld;
-        for (int i = 0; i < d; i++) {
-            if constexpr (DT == DT_F32) {
-                float v = ((const float*)X)[o + i];
-                ok &= (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
-                acc = __fma_rn((double)v, (double)v, acc);
-            } else if constexpr (DT == DT_BF16) {
-                uint16_t b = ((const uint16_t*)X)[o + i];
-                ok &= (b & 0x7f80u) != 0x7f80u;
-                double v = (double)bf16_to_f32(b);
-                acc = __fma_rn(v, v, acc);
-            } else {
-                uint8_t c = ((const uint8_t*)X)[o + i];
-                ok &= (c & 0x7fu) != 0x7fu;
-                double v = (double)e4m3_to_f32(c);
-                acc = __fma_rn(v, v, acc);
+        if constexpr (VEC) {
+            const i32x4* row = (const i32x4*)((const uint8_t*)X + o * EB);
+            for (int c = 0; c * PER < d; c++) {
+                const i32x4 v = row[c];
+                const int lim = d - c * PER < PER ? d - c * PER : PER;
+#pragma unroll
+                for (int e = 0; e < PER; e++) {
+                    if (e >= lim) break;
+                    const uint32_t w = (uint32_t)v[e * EB / 4];
+                    norm_step<DT>(EB == 4 ? w : (w >> (8 * ((e * EB) & 3))) & (EB == 2 ? 0xffffu : 0xffu), acc, ok);
+                }
+            }
+        } else {
+            for (int i = 0; i < d; i++) {
+                uint32_t raw;
+                if constexpr (DT == DT_F32) raw = ((const uint32_t*)X)[o + i];
+                else if constexpr (DT == DT_BF16) raw = ((const uint16_t*)X)[o + i];
+                else raw = ((const uint8_t*)X)[o + i];
+                norm_step<DT>(raw, acc, ok);
             }
         }
         if constexpr (DT == DT_FP8) {
@@ -93,9 +121,17 @@ void launch_norm2(int dtype, const void* X, const float* scales, int64_t rows, i
 {
     if (rows <= 0) return;
     dim3 g((unsigned)((rows + 255) / 256)), b(256);
-    if (dtype == DT_F32) hipLaunchKernelGGL(k_norm2<DT_F32>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
-    else if (dtype == DT_BF16) hipLaunchKernelGGL(k_norm2<DT_BF16>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
-    else hipLaunchKernelGGL(k_norm2<DT_FP8>, g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+    const int eb = dtype == DT_F32 ? 4 : dtype == DT_BF16 ? 2 : 1;
+    const bool vec = ((int64_t)ld * eb) % 16 == 0 && ((uintptr_t)X & 15u) == 0;
+    if (vec) {
+        if (dtype == DT_F32) hipLaunchKernelGGL((k_norm2<DT_F32, true>), g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+        else if (dtype == DT_BF16) hipLaunchKernelGGL((k_norm2<DT_BF16, true>), g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+        else hipLaunchKernelGGL((k_norm2<DT_FP8, true>), g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+    } else {
+        if (dtype == DT_F32) hipLaunchKernelGGL((k_norm2<DT_F32, false>), g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+        else if (dtype == DT_BF16) hipLaunchKernelGGL((k_norm2<DT_BF16, false>), g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+        else hipLaunchKernelGGL((k_norm2<DT_FP8, false>), g, b, 0, s, X, scales, rows, d, ld, n2, stats, slot);
+    }
     HIPC(hipGetLastError());
 }
 
@@ -148,6 +184,24 @@ __global__ void k_widen_fp8(const uint8_t* src, int64_t count, uint16_t* dst)
     if (t < count) dst[t] = (uint16_t)(__float_as_uint(e4m3_to_f32(src[t])) >> 16);
 }
 
+// Eight codes per thread (8-byte load, 16-byte store); count8 = count / 8.
+__global__ void k_widen_fp8_x8(const uint2* src, int64_t count8, i32x4* dst)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count8) return;
+    const uint2 c = src[t];
+    i32x4 o;
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+        const uint32_t w = h < 2 ? c.x : c.y;
+        const int sh = 16 * (h & 1);
+        const uint32_t lo = __float_as_uint(e4m3_to_f32((uint8_t)(w >> sh))) >> 16;
+        const uint32_t hi = __float_as_uint(e4m3_to_f32((uint8_t)(w >> (sh + 8)))) >> 16;
+        o[h] = (int)(lo | (hi << 16));
+    }
+    dst[t] = o;
+}
+
 void launch_mma_operand(int mma_dtype, int dtype, const void* src, int64_t rows, int ld, uint16_t* dst,
                         int user_layout, hipStream_t s)
 {
@@ -158,8 +212,14 @@ void launch_mma_operand(int mma_dtype, int dtype, const void* src, int64_t rows,
         launch_split_bf16((const float*)src, rows, ld, dst, user_layout, s);
     } else if (dtype == DT_FP8 && mma_dtype == DT_FP8B) {
         const int64_t cnt = rows * ld;
-        hipLaunchKernelGGL(k_widen_fp8, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (const uint8_t*)src,
-                           cnt, dst);
+        if (cnt % 8 == 0 && ((uintptr_t)src & 7u) == 0 && ((uintptr_t)dst & 15u) == 0) {
+            const int64_t c8 = cnt / 8;
+            hipLaunchKernelGGL(k_widen_fp8_x8, dim3((unsigned)((c8 + 255) / 256)), dim3(256), 0, s, (const uint2*)src,
+                               c8, (i32x4*)dst);
+        } else {
+            hipLaunchKernelGGL(k_widen_fp8, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (const uint8_t*)src,
+                               cnt, dst);
+        }
         HIPC(hipGetLastError());
     } else {
         fail(RKMIPS_EINVAL, "internal: no matrix-core operand form for this storage type");

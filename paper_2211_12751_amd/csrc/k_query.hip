@@ -442,13 +442,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
     if (threadIdx.x < 4 && st_s[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], st_s[threadIdx.x]);
 }
 
-// cos(phi) of every (block, query) pair: the FP32 inner product of the query with the
-// block's unit centre over the query norm, clamped to [-1, 1] (0 for a zero query).  One
-// thread per query and eight consecutive blocks: the query row is read once, in pieces
-// of up to 64 values held in registers, against each block's centre (a wave-uniform
-// row).  The result feeds the node-level bound of Lemma 2.
-// FP8 codes keep one block per thread: their decoded values would otherwise stay live
-// across the blocks and spill.
 // cos(phi) of every (block, query) pair, phi the angle between the query and the block's
 // centre (Lemma 2; Alg. 5 block test), on the matrix cores: a dense contraction of the
 // centres [nblocks x d] with the queries [nq x d].  A wave computes 32 blocks x 64 queries

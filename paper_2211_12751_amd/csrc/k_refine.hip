@@ -349,17 +349,17 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
         }
         lk = a.k_max <= 64 ? __shfl(v, a.k_max - 1) : -__builtin_inf();
     } else if constexpr (!FAST) {
-        for (int j = l; j < Nk; j += 64) {
-            const int64_t p = sid[j];
-            double v = -__builtin_inf();
-            if (p < a.n) {
-                const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-                v = canon_dot_vec<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
+        // 64 candidates at a time through the staged dot products
+        for (int j0 = 0; j0 < Nk; j0 += 64) {
+            const double v = canon_dot_staged<DT>(a, u, su, sid + j0, Nk - j0, rows);
+            if (j0 + l < Nk) {
+                s64[j0 + l] = v;
+                worst_raw = fmax(worst_raw, rel(v, (double)ord_f32(skey[j0 + l])));
             }
-            s64[j] = v;
-            worst_raw = fmax(worst_raw, rel(v, (double)ord_f32(skey[j])));
         }
         __builtin_amdgcn_wave_barrier();
+        // rank of each score among all Nk (ties: earlier slot first); the entry of rank
+        // r < k_max is lambda^(r+1), written by the lane that holds it
         for (int j = l; j < Nk; j += 64) {
             const double x = s64[j];
             int r64 = 0;
@@ -367,16 +367,19 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
                 const double xi = s64[i];
                 r64 += (xi > x) || (xi == x && i < j);
             }
-            if (r64 < a.k_max) lam_row[r64] = x;
+            if (r64 < a.k_max) {
+                a.lam64[(int64_t)r64 * a.m + u] = x;
+                a.lam32[(int64_t)r64 * a.m + u] = (float)x;
+                worst32 = fmax(worst32, rel(x, (double)(float)x));
+                if (r64 == a.k_max - 1) lam_row[0] = x;
+            }
+        }
+        for (int r = Nk + l; r < a.k_max; r += 64) {
+            a.lam64[(int64_t)r * a.m + u] = -__builtin_inf();
+            a.lam32[(int64_t)r * a.m + u] = -__builtin_inff();
         }
         __builtin_amdgcn_wave_barrier();
-        for (int r = l; r < a.k_max; r += 64) {
-            const double lv = r < Nk ? lam_row[r] : -__builtin_inf();
-            a.lam64[(int64_t)r * a.m + u] = lv;
-            a.lam32[(int64_t)r * a.m + u] = (float)lv;
-            if (r < Nk) worst32 = fmax(worst32, rel(lv, (double)(float)lv));
-        }
-        lk = Nk >= a.k_max ? lam_row[a.k_max - 1] : -__builtin_inf();
+        lk = Nk >= a.k_max ? lam_row[0] : -__builtin_inf();
     }
     worst_raw = wave_max(worst_raw);
     worst32 = wave_max(worst32);
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FAST ? 6 : 
     __shared__ uint32_t skey[4][FAST ? 64 : 256];
     __shared__ uint32_t sid[4][FAST ? 64 : 256];
     __shared__ double s64[4][FAST ? 1 : 256];
-    __shared__ double lam_row[4][FAST ? 1 : 256];
+    __shared__ double lam_row[4][1];
     __shared__ int hist_all[4][256];
     __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
     const int w = threadIdx.x >> 6;
@@ -440,18 +443,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FAST ? 6 : 
 // registers allow: the selection (gather, radix select) and the rescoring (staged FP64
 // dot products, ranks, lambda rows, certificate).  The kept candidates go through
 // global memory (8 bytes each).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_refine_select(RefineArgs a)
+// GPL = 8 for C <= 64, 16 for C <= 224 (users with more candidates than 64 GPL go to
+// the wide pass).
+template <int GPL, int CMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GPL == 8 ? 6 : 4, 8))) void k_refine_select(RefineArgs a)
 {
-    __shared__ uint32_t skey_all[4][64], sid_all[4][64];
+    __shared__ uint32_t skey_all[4][CMAX], sid_all[4][CMAX];
     __shared__ int hist_all[4][256];
     const int w = threadIdx.x >> 6, l = lane_id();
     const int64_t u = (int64_t)blockIdx.x * 4 + w;
     if (u >= a.m) return;
     int Nk = 0;
     float cut = 0.f, tau_max = 0.f;
-    const bool ok = refine_select<8>(a, u, skey_all[w], sid_all[w], hist_all[w], &Nk, &cut, &tau_max);
+    const bool ok = refine_select<GPL>(a, u, skey_all[w], sid_all[w], hist_all[w], &Nk, &cut, &tau_max);
     if (!ok) Nk = -1;
-    if (ok && l < Nk) a.sel[u * a.C + l] = make_uint2(skey_all[w][l], sid_all[w][l]);
+    if (ok)
+        for (int j = l; j < Nk; j += 64) a.sel[u * a.C + j] = make_uint2(skey_all[w][j], sid_all[w][j]);
     if (l == 0) {
         int* mt = a.sel_meta + 4 * u;
         mt[0] = Nk;
@@ -492,6 +499,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                           nullptr, rows_all[w]);
 }
 
+// The rescoring of 64 < C <= 224 kept candidates: staged FP64 dot products 64 at a
+// time, ranks by a scan over the wave's scores in LDS.
+template <int DT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_refine_rank_wide(RefineArgs a)
+{
+    __shared__ uint32_t skey_all[4][224], sid_all[4][224];
+    __shared__ double s64_all[4][224];
+    __shared__ double lk_all[4][1];
+    __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const int64_t u = xcd_user(w);
+    if (u >= a.m) return;
+    const int* mt = a.sel_meta + 4 * u;
+    const int Nk = mt[0];
+    if (Nk < 0) return;   // the wide pass takes this user
+    for (int j = l; j < Nk; j += 64) {
+        const uint2 e = a.sel[u * a.C + j];
+        skey_all[w][j] = e.x;
+        sid_all[w][j] = e.y;
+    }
+    __builtin_amdgcn_wave_barrier();
+    refine_rank<DT, false>(a, u, skey_all[w], sid_all[w], Nk, __int_as_float(mt[1]), __int_as_float(mt[2]),
+                           s64_all[w], lk_all[w], rows_all[w]);
+}
+
 template <int DT>
 static void refine_d(const RefineArgs& a, hipStream_t s)
 {
@@ -500,7 +532,7 @@ static void refine_d(const RefineArgs& a, hipStream_t s)
         a0.list = nullptr;
         if (a.sel) {
             const unsigned g = (unsigned)((a.m + 3) / 4);
-            hipLaunchKernelGGL(k_refine_select, dim3(g), dim3(256), 0, s, a0);
+            hipLaunchKernelGGL((k_refine_select<8, 64>), dim3(g), dim3(256), 0, s, a0);
             hipLaunchKernelGGL((k_refine_rank<DT>), dim3((g + 7) / 8 * 8), dim3(256), 0, s, a0);
         } else {
             hipLaunchKernelGGL((k_refine<DT, 8, true>), dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a0);
@@ -512,6 +544,21 @@ static void refine_d(const RefineArgs& a, hipStream_t s)
         a1.spill = nullptr;   // the wide instance never spills
         const unsigned g = (unsigned)std::min<int64_t>((a.m + 3) / 4, 1024);
         hipLaunchKernelGGL((k_refine<DT, RF_GPL, false>), dim3(g), dim3(256), 0, s, a1);
+    } else if (a.sel) {
+        // select (up to 1024 candidates per user) and rescoring in two kernels; users
+        // with more candidates go to the wide instance
+        RefineArgs a0 = a;
+        a0.list = nullptr;
+        const unsigned g = (unsigned)((a.m + 3) / 4);
+        hipLaunchKernelGGL((k_refine_select<16, 224>), dim3(g), dim3(256), 0, s, a0);
+        hipLaunchKernelGGL((k_refine_rank_wide<DT>), dim3((g + 7) / 8 * 8), dim3(256), 0, s, a0);
+        if ((int64_t)a.nseg * a.G <= 16 * 64) return;
+        RefineArgs a1 = a;
+        a1.list = a.spill;
+        a1.list_count = a.spill_count;
+        a1.spill = nullptr;
+        const unsigned g1 = (unsigned)std::min<int64_t>((a.m + 3) / 4, 1024);
+        hipLaunchKernelGGL((k_refine<DT, RF_GPL, false>), dim3(g1), dim3(256), 0, s, a1);
     } else {
         RefineArgs a0 = a;
         a0.list = nullptr;

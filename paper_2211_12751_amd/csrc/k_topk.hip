@@ -112,16 +112,6 @@ __device__ __noinline__ uint32_t select_user_call(uint2* r0, int c0, const uint2
     return select_user(r0, c0, r1, c1, C, hist, stage);
 }
 
-// Item at virtual position v of a launch: the norm-sorted array itself (main pass), or
-// the stratified sample of `ns` items, one from the middle of each of ns equal slices of
-// the norm-sorted order (seed pass).
-template <int MODE>
-__device__ __forceinline__ int64_t item_at(int64_t v, int64_t n, int64_t ns)
-{
-    if constexpr (MODE == TK_SEED) return ((2 * v + 1) * n) / (2 * ns);
-    else return v;
-}
-
 // 32 x 32 blocks of scores on the matrix cores, one per user group: rows = the 32 items
 // of LDS rows [row0, row0 + 32) of a staged tile, columns = group g's 32 users (register
 // fragments).  Every A fragment read from LDS feeds the NG groups' products.
@@ -305,7 +295,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         const int64_t v = seg0 + tt * IT + r;
         i32x4 val = {0, 0, 0, 0};
         if (c < CHUNKS && v < seg1)
-            val = *(const i32x4*)((const uint8_t*)a.items + item_at<MODE>(v, a.n, a.ns) * ROWB + c16 * 16);
+            val = *(const i32x4*)((const uint8_t*)a.items + v * ROWB + c16 * 16);
         return val;
     };
     i32x4 pf[PF];
@@ -336,7 +326,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
         }
         if (dt_scaled<DT> && threadIdx.x < IT) {
             const int64_t v = seg0 + tt * IT + threadIdx.x;
-            tscale[tt % 3][threadIdx.x] = v < seg1 ? a.item_scales[item_at<MODE>(v, a.n, a.ns)] : 0.f;
+            tscale[tt % 3][threadIdx.x] = v < seg1 ? a.item_scales[v] : 0.f;
         }
     };
 
@@ -586,8 +576,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     auto issue = [&](uint8_t* ring, float* sc, int tt) {
         const int r0 = tt * IT;
         const int rows = seg_rows - r0 < IT ? seg_rows - r0 : IT;
-        if constexpr (MODE == TK_MAIN) {
-            // the tile's rows are contiguous; loads past its last row read zeros
+        {
+            // the tile's rows are contiguous (the seed pass reads the gathered sample);
+            // loads past its last row read zeros
             const u32x4 rs = tk_rsrc((const uint8_t*)a.items + (seg0 + r0) * ROWB, (uint32_t)(rows * ROWB));
             const uint32_t lbase = (uint32_t)(uintptr_t)TK_LDS(ring);
 #pragma unroll
@@ -598,26 +589,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 if (w == 0) {
                     const u32x4 rsc = tk_rsrc(a.item_scales + seg0 + r0, (uint32_t)(rows * 4));
                     tk_dma4(rsc, (uint32_t)(uintptr_t)TK_LDS(sc), (uint32_t)(l * 4));
-                }
-            }
-        } else {
-            // stratified sample: rows are scattered; rows past the last repeat it
-            const int last = rows - 1;
-#pragma unroll
-            for (int j = 0; j < LPW; j++) {
-                if (w * LPW + j < NLD) {
-                    const int pos = (w * LPW + j) * 64 + l;
-                    const int rr = pos / CPR < last ? pos / CPR : last;
-                    const int64_t item = item_at<MODE>(seg0 + r0 + rr, a.n, a.ns);
-                    const uint8_t* src = (const uint8_t*)a.items + item * ROWB + (doff(j) - (unsigned)((pos / CPR) * ROWB));
-                    __builtin_amdgcn_global_load_lds(TK_GLB(src), TK_LDS(ring + (w * LPW + j) * 1024), 16, 0, 0);
-                }
-            }
-            if constexpr (dt_scaled<DT>) {
-                if (w == 0) {
-                    const int rr = l < last ? l : last;
-                    const float* src = a.item_scales + item_at<MODE>(seg0 + r0 + rr, a.n, a.ns);
-                    __builtin_amdgcn_global_load_lds(TK_GLB(src), TK_LDS(sc), 4, 0, 0);
                 }
             }
         }
@@ -904,6 +875,38 @@ static void topk_dispatch(const TopkArgs& a, hipStream_t s)
         default: fail(RKMIPS_EINVAL, "internal: unsupported padded dimension");
         }
     }
+}
+
+// The stratified sample of the seed pass as contiguous rows: row v of dst is item
+// ((2 v + 1) n) / (2 ns) of the norm-sorted operand rows (the middle of slice v of ns
+// equal slices), with its scale.
+__global__ void k_gather_sample(const i32x4* src, const float* scales, int64_t n, int64_t ns, int chunks,
+                                i32x4* dst, float* dscales)
+{
+    const int64_t total = ns * chunks;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = t / chunks;
+        const int c = (int)(t - v * chunks);
+        const int64_t it = ((2 * v + 1) * n) / (2 * ns);
+        dst[v * chunks + c] = src[it * chunks + c];
+        if (c == 0 && scales) dscales[v] = scales[it];
+    }
+}
+
+int topk_row_bytes(int dtype, int ld) { return ld * (dtype == DT_F32 ? 4 : 2); }
+
+void launch_gather_sample(int dtype, const void* items, const float* scales, int64_t n, int64_t ns, int ld,
+                          void* dst, float* dscales, hipStream_t s)
+{
+    if (ns <= 0) return;
+    const int rowb = topk_row_bytes(dtype, ld);
+    if (rowb % 16 != 0 || ns > n) fail(RKMIPS_EINVAL, "internal: seed sample shape");
+    const int chunks = rowb / 16;
+    const int64_t total = ns * chunks;
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_gather_sample, dim3(g), dim3(256), 0, s, (const i32x4*)items, scales, n, ns, chunks,
+                       (i32x4*)dst, dscales);
+    HIPC(hipGetLastError());
 }
 
 void launch_topk(int dtype, const TopkArgs& a, hipStream_t s)

@@ -14,7 +14,8 @@ struct TopkArgs {
     const float* user_scales;
     int64_t m;
     int d, ld;
-    int64_t ns;             // seed pass: size of the stratified item sample
+    int64_t ns;             // seed pass: size of the stratified item sample (items then
+                            // holds the gathered sample, n = ns)
     int64_t v0, v1;         // virtual item range of this launch
     int nseg;               // segments of this launch (grid.y)
     int seg_base;           // buffer segment of this launch's first segment
@@ -34,6 +35,12 @@ constexpr int TK_T = 8;     // sample scores kept per lane by the seed pass
 void launch_topk(int dtype, const TopkArgs& a, hipStream_t s);
 void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s);
 int topk_users_per_block(int dtype, int ld);
+// Bytes of one operand row of the top-k passes (ld elements of the operand form).
+int topk_row_bytes(int dtype, int ld);
+// The seed pass's stratified sample of ns of the n norm-sorted operand rows, gathered
+// into dst [ns x row bytes] (and the scales into dscales when scales is given).
+void launch_gather_sample(int dtype, const void* items, const float* scales, int64_t n, int64_t ns, int ld,
+                          void* dst, float* dscales, hipStream_t s);
 int topk_resident_blocks(int dtype, int ld, int G);
 
 
