@@ -261,6 +261,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline and parity sample")
         line["cpu_baseline"], line["parity_sample"] = cpu_baseline(w, off, ids, args.cpu_sample_users)
+        if not args.quick:
+            line["cpu_single_thread"] = single_thread_oracle()
     print(json.dumps(line), flush=True)
 
 
@@ -548,6 +550,29 @@ def cpu_baseline(w, off, ids, sample_users):
            "pairs_checked": int((len(sample) + len(ret)) * w.nq), "mismatches": bad_sample + bad_ret,
            "exact_match": bad_sample + bad_ret == 0}
     return base, par
+
+
+def single_thread_oracle():
+    """The oracle on one thread, as the paper times its methods: the whole 2,000 x 5,000 x
+    32 workload (100 queries), and the 20,000 x 100,000 x 64 one on a seeded 400-user
+    sample extrapolated linearly in users (about a second each)."""
+    from oracle import oracle as O
+    from paper_2211_12751_amd import inputs as I
+    out = {}
+    for name, users in (("c1", None), ("c2", 400)):
+        w = I.make(name)
+        sel = None if users is None else np.sort(np.random.default_rng(20222).choice(w.m, users, replace=False))
+        t0 = time.perf_counter()
+        lam = O.lambda_table(w.dtype, w.items, w.item_scales, w.users, w.user_scales, w.k_max, user_idx=sel,
+                             nthreads=1)
+        O.member(w.dtype, w.users, w.user_scales, w.queries, w.query_scales, w.ks, lam, user_idx=sel, nthreads=1)
+        t = time.perf_counter() - t0
+        full = t * (w.m / len(sel) if sel is not None else 1.0)
+        out[name] = {"workload": workload_desc(name, w), "threads": 1, "seconds": round(full, 3),
+                     "queries_per_s": round(w.nq / full, 4),
+                     "sample": "all users" if sel is None else f"{len(sel)} of {w.m} users, extrapolated"}
+        log(f"single-thread oracle {name}: {full:.2f} s for {w.nq} queries")
+    return out
 
 
 if __name__ == "__main__":

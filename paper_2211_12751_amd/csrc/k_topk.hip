@@ -496,6 +496,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     constexpr int LPW = (NLD + TK_WAVES - 1) / TK_WAVES;
     constexpr int TBYTES = NLD * 1024;
     constexpr int SGPL = MODE == TK_MAIN ? GPL : 1;
+    constexpr bool FOLD = MODE == TK_MAIN && dt_scaled<DT>;
     __shared__ __attribute__((aligned(1024))) uint8_t ring0[TBYTES];
     __shared__ __attribute__((aligned(1024))) uint8_t ring1[TBYTES];
     __shared__ __attribute__((aligned(1024))) uint8_t ring2[TBYTES];
@@ -541,7 +542,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         if (MODE == TK_MAIN && uok && a.theta_init) theta[g] = a.theta_init[ug * a.theta_stride];
         if (!uok) theta[g] = __builtin_inff();
         su[g] = (dt_scaled<DT> && uok) ? a.user_scales[ug] : 1.0f;
+        if constexpr (FOLD) {
+            // a negative scale moves into the operand (negating BF16 values is exact)
+            if (su[g] < 0.f) {
+                su[g] = -su[g];
+#pragma unroll
+                for (int t = 0; t < KSTEPS; t++) bfrag[g][t] ^= (int)0x80008000u;
+            }
+        }
     }
+    // FP8 main pass: the user's scale is folded into its threshold.  The pass compares
+    // w = s_p raw against ths = RD(theta / s_u): an item left out has w <= ths, so its
+    // fast score RN(s_u w) <= s_u ths <= theta.  Appended entries carry RN(s_u w).
+    float ths[NG];
+    auto fold = [&](float t, float s) -> float {
+        if (!(s > 0.f)) return 0.f > t ? -__builtin_inff() : __builtin_inff();
+        // one step below the rounded quotient: at most t / s (the rounding error is at
+        // most half a step), infinities stay
+        const float q = __fdiv_rn(t, s);
+        if (!(fabsf(q) < __builtin_inff())) return q;
+        const uint32_t b = __float_as_uint(q);
+        return __uint_as_float(q > 0.f ? b - 1u : (q == 0.f ? 0x80000001u : b + 1u));
+    };
+#pragma unroll
+    for (int g = 0; g < NG; g++) ths[g] = FOLD ? fold(theta[g], su[g]) : theta[g];
     const int HG = a.G / 2;
     const int64_t wusers = std::min<int64_t>(UPB, a.m - (int64_t)blockIdx.x * UPB);
     const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
@@ -567,11 +591,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     const int pos0 = w * LPW * 64 + l;
     auto doff = [&](int j) -> unsigned {
         // recomputed per tile: kept live across the loop they would cost registers
-        int p0 = pos0;
+        // (unsigned: the division by the constant CPR is a multiply-high and a shift)
+        unsigned p0 = (unsigned)pos0;
         asm volatile("" : "+v"(p0));
-        const int pos = p0 + j * 64;
-        const int c = pos % CPR;
-        return (unsigned)((pos / CPR) * ROWB + (c < ROWB / 16 ? c : 0) * 16);
+        const unsigned pos = p0 + (unsigned)j * 64u;
+        const unsigned c = pos % (unsigned)CPR;
+        return (pos / (unsigned)CPR) * (unsigned)ROWB + (c < (unsigned)(ROWB / 16) ? c : 0u) * 16u;
     };
     auto issue = [&](uint8_t* ring, float* sc, int tt) {
         const int r0 = tt * IT;
@@ -623,7 +648,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #pragma unroll
                 for (int g = 0; g < NG; g++)
 #pragma unroll
-                    for (int e = 0; e < 4; e++) v[g][4 * j + e] = (su[g] * s4[e]) * v[g][4 * j + e];
+                    for (int e = 0; e < 4; e++) {
+                        if constexpr (FOLD) v[g][4 * j + e] = s4[e] * v[g][4 * j + e];
+                        else v[g][4 * j + e] = (su[g] * s4[e]) * v[g][4 * j + e];
+                    }
             }
         }
         if (base + 32 > seg_rows) {
@@ -674,6 +702,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                         const uint32_t T = select_user(rg, c0, rg + HG, c1, a.C, hist, stage);
                         if ((l & 31) == ul) {
                             theta[g] = ord_f32(T);
+                            ths[g] = FOLD ? fold(theta[g], su[g]) : theta[g];
                             off[g] = loff8[g] + (h ? 0u : 8u * (uint32_t)a.C);
                         }
                     }
@@ -684,12 +713,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 float mx = v[g][0];
 #pragma unroll
                 for (int r = 1; r < 16; r++) mx = fmaxf(mx, v[g][r]);
-                if (mx > theta[g]) {
+                if (mx > ths[g]) {
                     const uint32_t pbase = (uint32_t)seg0 + (uint32_t)(b * 32) + 4u * (uint32_t)h;
 #pragma unroll
                     for (int r = 0; r < 16; r++) {
-                        if (v[g][r] > theta[g]) {
-                            const u32x2 e = {__float_as_uint(v[g][r]), pbase + (uint32_t)(8 * (r / 4) + (r % 4))};
+                        if (v[g][r] > ths[g]) {
+                            const float fs = FOLD ? su[g] * v[g][r] : v[g][r];
+                            const u32x2 e = {__float_as_uint(fs), pbase + (uint32_t)(8 * (r / 4) + (r % 4))};
                             __builtin_amdgcn_raw_buffer_store_b64(e, wrsrc, (int)off[g], 0, 0);
                             off[g] += 8u;
                         }
