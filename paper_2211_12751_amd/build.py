@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "librkmips.so")
 SOURCES = ["k_prep.hip", "k_topk.hip", "k_refine.hip", "k_cone.hip", "k_saalsh.hip", "k_query.hip", "k_saalsh_query.hip",
-           "api.cpp", "query.cpp", "serve.cpp", "mem.cpp", "persist.cpp"]
+           "k_diag.hip", "api.cpp", "query.cpp", "serve.cpp", "mem.cpp", "persist.cpp"]
 ARCH = os.environ.get("RKMIPS_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fno-gpu-rdc",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

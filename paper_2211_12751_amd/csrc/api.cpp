@@ -756,6 +756,12 @@ void rkmips_default_params(rkmips_params* p)
 
 const char* rkmips_last_error(void) { return g_last_error.c_str(); }
 
+rkmips_status rkmips_diag_mma_probe(int32_t kind, const uint8_t* a_codes, const uint8_t* b_codes, int32_t k,
+                                    float* c_out)
+{
+    return guarded([&] { mma_probe(kind, a_codes, b_codes, k, c_out); });
+}
+
 rkmips_status rkmips_build_index(const void* items, const float* item_scales, int64_t n, const void* users,
                                  const float* user_scales, int64_t m, int32_t d, int32_t dtype,
                                  const float* srp_proj, const rkmips_params* p, void* stream,

@@ -1,0 +1,75 @@
+// Matrix-core accumulation probe.  The library's fast scores assume that a matrix-core
+// product accumulates like FP32 arithmetic (the error model of the fast decisions and of
+// the lambda certificate); this probe measures one 32 x 32 block of products of e4m3
+// codes on the FP8 matrix cores (codes as they are) and on the BF16 matrix cores (codes
+// widened to BF16, which is exact), so that the assumption can be checked against exact
+// sums on the host.  It is the measurement behind multiplying FP8 data on the BF16
+// matrix cores.
+#include <algorithm>
+
+#include "common.h"
+#include "internal.h"
+
+namespace rk {
+
+typedef long fp8x8;   // eight e4m3 codes, one matrix-core operand register pair
+
+// C[i][j] = sum_k A[i][k] B[j][k] for i, j < 32 over K (a multiple of 16), one wave.
+// Lane l supplies row l % 32 of each operand, elements [8 (l / 32), 8 (l / 32) + 8) of
+// every 16-wide k step; accumulator element r of lane l is C[mfma32_row(r, l)][l % 32].
+__global__ __launch_bounds__(64) void k_mma_probe(const uint8_t* A, const uint8_t* B, int K, int kind, float* C)
+{
+    const int l = threadIdx.x;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0.f;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const uint8_t* ar = A + (int64_t)(l & 31) * K + k0 + 8 * (l >> 5);
+        const uint8_t* br = B + (int64_t)(l & 31) * K + k0 + 8 * (l >> 5);
+        if (kind == 1) {
+            fp8x8 a = 0, b = 0;
+            for (int e = 0; e < 8; e++) {
+                a |= (long)ar[e] << (8 * e);
+                b |= (long)br[e] << (8 * e);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, acc, 0, 0, 0);
+        } else {
+            bf16x8 a, b;
+            for (int e = 0; e < 8; e++) {
+                a[e] = __builtin_bit_cast(__bf16, (uint16_t)(__float_as_uint(e4m3_to_f32(ar[e])) >> 16));
+                b[e] = __builtin_bit_cast(__bf16, (uint16_t)(__float_as_uint(e4m3_to_f32(br[e])) >> 16));
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; r++) C[mfma32_row(r, l) * 32 + (l & 31)] = acc[r];
+}
+
+void mma_probe(int kind, const uint8_t* a_host, const uint8_t* b_host, int K, float* c_host)
+{
+    if (kind != 0 && kind != 1) fail(RKMIPS_EINVAL, "kind must be 0 (BF16) or 1 (FP8)");
+    if (K < 16 || K > 4096 || K % 16 != 0) fail(RKMIPS_EINVAL, "K must be a multiple of 16 in [16, 4096]");
+    if (!a_host || !b_host || !c_host) fail(RKMIPS_EINVAL, "null pointer");
+    for (int i = 0; i < 32 * K; i++)
+        if ((a_host[i] & 0x7f) == 0x7f || (b_host[i] & 0x7f) == 0x7f) fail(RKMIPS_EINVAL, "NaN code");
+    uint8_t *a = nullptr, *b = nullptr;
+    float* c = nullptr;
+    const size_t nb = (size_t)32 * K;
+    hipError_t e = hipMalloc(&a, nb);
+    if (e == hipSuccess) e = hipMalloc(&b, nb);
+    if (e == hipSuccess) e = hipMalloc(&c, sizeof(float) * 32 * 32);
+    if (e == hipSuccess) e = hipMemcpy(a, a_host, nb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b, b_host, nb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mma_probe, dim3(1), dim3(64), 0, 0, a, b, K, kind, c);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(c_host, c, sizeof(float) * 32 * 32, hipMemcpyDeviceToHost);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    (void)hipFree(c);
+    HIPC(e);
+}
+
+}  // namespace rk

@@ -110,6 +110,7 @@ _sig = {
     "rkmips_index_save": (C.c_int, [_P, C.c_char_p]),
     "rkmips_index_load": (C.c_int, [C.c_char_p, _P, C.POINTER(_P)]),
     "rkmips_last_error": (C.c_char_p, []),
+    "rkmips_diag_mma_probe": (C.c_int, [C.c_int32, _P, _P, C.c_int32, _P]),
     "rkmips_serve_replay": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, C.POINTER(rkmips_serve_params), _P,
                                       C.POINTER(rkmips_serve_stats), C.POINTER(_P)]),
 }
@@ -321,6 +322,18 @@ def rkmips_index_load(path, stream=None):
 
 def rkmips_last_error():
     return _lib.rkmips_last_error().decode()
+
+
+def rkmips_diag_mma_probe(kind, a_codes, b_codes):
+    """One 32 x 32 block of e4m3 code products on the matrix cores (kind 1: FP8, kind 0:
+    codes widened to BF16), FP32 accumulation: float32 [32 x 32]."""
+    a = np.ascontiguousarray(a_codes, dtype=np.uint8)
+    b = np.ascontiguousarray(b_codes, dtype=np.uint8)
+    if a.shape != b.shape or a.ndim != 2 or a.shape[0] != 32:
+        raise ValueError("a_codes and b_codes must both be [32 x K]")
+    out = np.empty((32, 32), np.float32)
+    _check(_lib.rkmips_diag_mma_probe(int(kind), _ptr(a), _ptr(b), int(a.shape[1]), _ptr(out)))
+    return out
 
 
 def rkmips_serve_replay(idx, queries_host, query_scales_host, nq, ks, arrival_us, sp):

@@ -1,5 +1,5 @@
 """The C ABI library loads on a machine without a GPU, exports every entry point that
-include/rkmips.h declares, and rejects bad arguments before touching a device."""
+the headers under include/ declare, and rejects bad arguments before touching a device."""
 import ctypes as C
 import os
 import re
@@ -8,13 +8,16 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rkmips.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 
 
 def _declared():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(rkmips_[a-z0-9_]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rkmips_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +31,7 @@ def R():
 
 def test_every_declared_symbol_is_exported(R):
     names = _declared()
-    assert len(names) >= 17
+    assert len(names) >= 17 and "rkmips_diag_mma_probe" in names
     for nm in names:
         assert hasattr(R._lib, nm), nm
         assert nm in R.EXPORTED, f"binding lacks {nm}"
@@ -207,3 +210,17 @@ def test_new_entry_points_check_arguments_first(R):
         assert fn(dummy, dummy, None, 4, ks.ctypes.data, 0, None, None) == -1
     assert R._lib.rkmips_index_wait(None) == -1
     assert R._lib.rkmips_get_stats(None, None) == -1
+
+
+def test_mma_probe_rejects_bad_arguments(R):
+    """The matrix-core probe validates on the host before any device call."""
+    a = np.zeros((32, 24), np.uint8)
+    with pytest.raises(R.RkmipsError) as e:
+        R.rkmips_diag_mma_probe(0, a, a)          # K not a multiple of 16
+    assert e.value.status == -1
+    a = np.zeros((32, 16), np.uint8)
+    with pytest.raises(R.RkmipsError):
+        R.rkmips_diag_mma_probe(2, a, a)          # no such kind
+    a[0, 0] = 0x7f
+    with pytest.raises(R.RkmipsError):
+        R.rkmips_diag_mma_probe(1, a, a)          # NaN code
