@@ -33,6 +33,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rkmips_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "liborc.so")
+# RKMIPS_ORACLE_SANITIZE=1: load an AddressSanitizer + UndefinedBehaviorSanitizer build
+# instead (the process must preload gcc's libasan)
+_SAN = os.environ.get("RKMIPS_ORACLE_SANITIZE", "") == "1"
+_LIB_SAN = os.path.join(_HERE, "_build", "liborc_san.so")
 _DT = {"f32": 0, "bf16": 1, "fp8": 2}
 _lib = None
 
@@ -55,21 +59,25 @@ def _default_threads() -> int:
 NTHREADS = _default_threads()
 
 
-def build(force: bool = False) -> str:
-    """Compile the reference with gcc (strict IEEE: no fast-math, no contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the reference with gcc (strict IEEE: no fast-math, no contraction);
+    sanitize=True makes the AddressSanitizer + UndefinedBehaviorSanitizer build."""
+    lib = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(lib), exist_ok=True)
+        tmp = lib + f".tmp{os.getpid()}"
+        extra = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                  "-fno-omit-frame-pointer"] if sanitize else ["-O2"])
+        subprocess.check_call(["gcc", *extra, "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
                                "-std=c99", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 def _L():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(build(sanitize=_SAN))
         _lib.orc_e4m3_value.restype = C.c_double
         _lib.orc_e4m3_value.argtypes = [C.c_uint8]
         _lib.orc_score.restype = C.c_double

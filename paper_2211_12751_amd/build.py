@@ -23,6 +23,51 @@ def _sources():
     return [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
+LIB_SAN = os.path.join(OUT_DIR, "librkmips_san.so")
+# host code only: each sanitizer flag applies to the host compilation (the device code of
+# the .hip objects is the same as in the plain build)
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-g"]
+
+
+def build_sanitized(jobs: int = 8) -> str:
+    """librkmips_san.so: the host-only sources (.cpp: the C ABI, index files, batching,
+    serving, memory) with AddressSanitizer and UndefinedBehaviorSanitizer, linked with the
+    plain build's kernel objects.  Load it with the clang ASan runtime preloaded."""
+    objdir = os.path.join(OUT_DIR, "obj")
+    sandir = os.path.join(OUT_DIR, "obj_san")
+    os.makedirs(sandir, exist_ok=True)
+    srcs = _sources()
+    hip_objs = [os.path.join(objdir, s.rsplit(".", 1)[0] + ".o") for s in srcs if s.endswith(".hip")]
+    if not all(os.path.exists(o) for o in hip_objs):
+        build()
+
+    def compile_one(src):
+        obj = os.path.join(sandir, src.rsplit(".", 1)[0] + ".o")
+        cmd = ["hipcc", *FLAGS, *SAN_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        cpp_objs = list(ex.map(compile_one, [s for s in srcs if s.endswith(".cpp")]))
+    tmp = LIB_SAN + f".tmp{os.getpid()}"
+    subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan",
+                           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                           "-o", tmp, *hip_objs, *cpp_objs])
+    os.replace(tmp, LIB_SAN)
+    return LIB_SAN
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime that librkmips_san.so needs preloaded."""
+    out = subprocess.run(["hipcc", "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                         text=True).stdout.strip()
+    return out
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every source for gfx950 and link librkmips.so (always recompiles)."""
     os.makedirs(OUT_DIR, exist_ok=True)

@@ -17,7 +17,8 @@ import numpy as np
 import torch  # noqa: F401  (must precede the library: one HIP runtime per process)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "librkmips.so")
+# RKMIPS_LIB selects another build of the same library (the sanitized host build)
+LIB_PATH = os.environ.get("RKMIPS_LIB") or os.path.join(_HERE, "lib", "librkmips.so")
 
 F32, BF16, FP8_E4M3 = 0, 1, 2
 DTYPES = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
