@@ -577,7 +577,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         loff8[g] = 8u * (uint32_t)(((w * UPW + g * 32 + (l & 31)) * a.nseg_total + seg) * a.G + h * HG);
         off[g] = loff8[g];
     }
-    const uint32_t full_rel = 8u * (uint32_t)(HG - 16);
+    // Compaction trigger per half-buffer.  A half must keep room for one block's 16
+    // appends; below that, compacting once about C new entries have arrived raises the
+    // threshold to the running C-th best early (the items come in descending norm
+    // order), which cuts the later appends.  After a compaction the C survivors sit in
+    // the first half, so that half triggers at 2C and the second at C.
+    const uint32_t full_rel = 8u * (uint32_t)std::min(HG - 16, h ? a.C : 2 * a.C);
     float top[NG][MODE == TK_SEED ? TK_T : 1];
 #pragma unroll
     for (int g = 0; g < NG; g++)
