@@ -347,18 +347,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((DT == DT_F
                 if (mfma32_row(r, l) >= rem) v[r] = -__builtin_inff();
         }
     };
-    // branch-free part of the epilogue: the register top-T of the seed pass
+    // the register top-T of the seed pass: a row enters only if it beats the list's last
+    // entry (quads and rows that no lane passes are skipped)
     auto early = [&](const f32x16& v) -> uint32_t {
         uint32_t pm = 0u;
         if constexpr (MODE == TK_SEED) {
+            float q4[4];
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                float x = v[r];
+            for (int jq = 0; jq < 4; jq++)
+                q4[jq] = fmaxf(fmaxf(v[4 * jq], v[4 * jq + 1]), fmaxf(v[4 * jq + 2], v[4 * jq + 3]));
+            if (fmaxf(fmaxf(q4[0], q4[1]), fmaxf(q4[2], q4[3])) > top[TK_T - 1]) {
 #pragma unroll
-                for (int i = 0; i < TK_T; i++) {
-                    const float hi = fmaxf(top[i], x);
-                    x = fminf(top[i], x);
-                    top[i] = hi;
+                for (int jq = 0; jq < 4; jq++) {
+                    if (q4[jq] > top[TK_T - 1]) {
+#pragma unroll
+                        for (int e4 = 0; e4 < 4; e4++) {
+                            float x = v[4 * jq + e4];
+                            if (x > top[TK_T - 1]) {
+#pragma unroll
+                                for (int i = 0; i < TK_T; i++) {
+                                    const float hi = fmaxf(top[i], x);
+                                    x = fminf(top[i], x);
+                                    top[i] = hi;
+                                }
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -672,18 +686,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         if constexpr (MODE == TK_SEED) {
 #pragma unroll
             for (int g = 0; g < NG; g++) {
-                float mx = v[g][0];
+                // a row enters the lane's sorted list only if it beats the list's last
+                // entry; quads and rows that no lane of the wave passes are skipped
+                float q4[4];
 #pragma unroll
-                for (int r = 1; r < 16; r++) mx = fmaxf(mx, v[g][r]);
+                for (int jq = 0; jq < 4; jq++)
+                    q4[jq] = fmaxf(fmaxf(v[g][4 * jq], v[g][4 * jq + 1]), fmaxf(v[g][4 * jq + 2], v[g][4 * jq + 3]));
+                const float mx = fmaxf(fmaxf(q4[0], q4[1]), fmaxf(q4[2], q4[3]));
                 if (mx > top[g][TK_T - 1]) {
 #pragma unroll
-                    for (int r = 0; r < 16; r++) {
-                        float x = v[g][r];
+                    for (int jq = 0; jq < 4; jq++) {
+                        if (q4[jq] > top[g][TK_T - 1]) {
 #pragma unroll
-                        for (int i = 0; i < TK_T; i++) {
-                            const float hi = fmaxf(top[g][i], x);
-                            x = fminf(top[g][i], x);
-                            top[g][i] = hi;
+                            for (int e4 = 0; e4 < 4; e4++) {
+                                float x = v[g][4 * jq + e4];
+                                if (x > top[g][TK_T - 1]) {
+#pragma unroll
+                                    for (int i = 0; i < TK_T; i++) {
+                                        const float hi = fmaxf(top[g][i], x);
+                                        x = fminf(top[g][i], x);
+                                        top[g][i] = hi;
+                                    }
+                                }
+                            }
                         }
                     }
                 }
@@ -715,18 +740,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                     // the tile loop then count the tile loads only
                     __builtin_amdgcn_s_waitcnt(0);
                 }
-                float mx = v[g][0];
+                // maxima of the lane's four row quads (rows 8 j + 4 h + e, e < 4): a quad that
+                // no lane of the wave passes is skipped with one scalar branch
+                float q4[4];
 #pragma unroll
-                for (int r = 1; r < 16; r++) mx = fmaxf(mx, v[g][r]);
+                for (int j = 0; j < 4; j++)
+                    q4[j] = fmaxf(fmaxf(v[g][4 * j], v[g][4 * j + 1]), fmaxf(v[g][4 * j + 2], v[g][4 * j + 3]));
+                const float mx = fmaxf(fmaxf(q4[0], q4[1]), fmaxf(q4[2], q4[3]));
                 if (mx > ths[g]) {
                     const uint32_t pbase = (uint32_t)seg0 + (uint32_t)(b * 32) + 4u * (uint32_t)h;
 #pragma unroll
-                    for (int r = 0; r < 16; r++) {
-                        if (v[g][r] > ths[g]) {
-                            const float fs = FOLD ? su[g] * v[g][r] : v[g][r];
-                            const u32x2 e = {__float_as_uint(fs), pbase + (uint32_t)(8 * (r / 4) + (r % 4))};
-                            __builtin_amdgcn_raw_buffer_store_b64(e, wrsrc, (int)off[g], 0, 0);
-                            off[g] += 8u;
+                    for (int j = 0; j < 4; j++) {
+                        if (q4[j] > ths[g]) {
+#pragma unroll
+                            for (int e4 = 0; e4 < 4; e4++) {
+                                const int r = 4 * j + e4;
+                                if (v[g][r] > ths[g]) {
+                                    const float fs = FOLD ? su[g] * v[g][r] : v[g][r];
+                                    const u32x2 e = {__float_as_uint(fs), pbase + (uint32_t)(8 * j + e4)};
+                                    __builtin_amdgcn_raw_buffer_store_b64(e, wrsrc, (int)off[g], 0, 0);
+                                    off[g] += 8u;
+                                }
+                            }
                         }
                     }
                 }
