@@ -99,42 +99,6 @@ __device__ __forceinline__ void wave_keep_positions(const uint32_t (&key)[GPL], 
 static constexpr int RF_MAXN = 2048;  // candidates per user across segments
 static constexpr int RF_GPL = RF_MAXN / 64;
 
-// Canonical FP64 score of user row u against item row p (FP32/BF16: index-order sum of
-// exact products; FP8: exact code sum times the scale product), with 16-byte loads.
-template <int DT>
-__device__ __forceinline__ double canon_dot_vec(const void* U, int64_t u, float su, const void* P, int64_t p,
-                                                float sp, int d, int ld)
-{
-    constexpr int EB = Elt<DT>::bytes;
-    constexpr int PER = 16 / EB;
-    const uint8_t* ur = (const uint8_t*)U + u * (int64_t)ld * EB;
-    const uint8_t* pr = (const uint8_t*)P + p * (int64_t)ld * EB;
-    double acc = 0.0;
-    for (int c0 = 0; c0 < d; c0 += PER) {
-        const i32x4 a4 = *(const i32x4*)(ur + c0 * EB);
-        const i32x4 b4 = *(const i32x4*)(pr + c0 * EB);
-        const int lim = d - c0 < PER ? d - c0 : PER;
-#pragma unroll
-        for (int e = 0; e < PER; e++) {
-            if (e >= lim) break;
-            float x, y;
-            if constexpr (DT == DT_F32) {
-                x = __int_as_float(a4[e]);
-                y = __int_as_float(b4[e]);
-            } else if constexpr (DT == DT_BF16) {
-                x = bf16_to_f32((uint16_t)((uint32_t)a4[e >> 1] >> (16 * (e & 1))));
-                y = bf16_to_f32((uint16_t)((uint32_t)b4[e >> 1] >> (16 * (e & 1))));
-            } else {
-                x = e4m3_to_f32((uint8_t)((uint32_t)a4[e >> 2] >> (8 * (e & 3))));
-                y = e4m3_to_f32((uint8_t)((uint32_t)b4[e >> 2] >> (8 * (e & 3))));
-            }
-            acc = __fma_rn((double)x, (double)y, acc);
-        }
-    }
-    if constexpr (DT == DT_FP8) acc = ((double)su * (double)sp) * acc;
-    return acc;
-}
-
 // One 16-byte chunk of the canonical sum: elements c0 .. c0 + 16 / EB - 1 (those below d)
 // of user chunk a4 and item chunk b4, added in index order to acc.
 template <int DT>
@@ -161,6 +125,35 @@ __device__ __forceinline__ double canon_chunk(const i32x4& a4, const i32x4& b4, 
     return acc;
 }
 
+// FP8 form of canon_chunk: the user's values come decoded from LDS (ux, exact e4m3
+// values as floats, shared by the wave), the item's from its codes.  Two e4m3 values
+// multiply exactly in FP32 (at most 8 significant bits, magnitudes in [2^-18, 2^18]),
+// so acc + (double)(x y) is the canonical step RN(acc + x y), bit for bit.
+__device__ __forceinline__ double canon_chunk_fp8(const float* ux, const i32x4& b4, int c0, int d, double acc)
+{
+    const int lim = d - c0 < 16 ? d - c0 : 16;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const f32x4 x4 = *(const f32x4*)(ux + c0 + 4 * q);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            if (4 * q + e >= lim) break;
+            const float y = e4m3_to_f32((uint8_t)((uint32_t)b4[q] >> (8 * e)));
+            acc = acc + (double)(x4[e] * y);
+        }
+    }
+    return acc;
+}
+
+// The user row's values for canon_chunk_fp8: udec[i] = value of code i (0 past d).
+// Called by the whole wave; ends with a wave barrier.
+__device__ __forceinline__ void decode_user_fp8(const RefineArgs& a, int64_t u, float* udec)
+{
+    const uint8_t* ur = (const uint8_t*)a.users + u * (int64_t)a.ld;
+    for (int i = lane_id(); i < a.ld; i += 64) udec[i] = i < a.d ? e4m3_to_f32(ur[i]) : 0.f;
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Canonical scores of user u against the items sid[0, Nk), lane l taking candidate l
 // (lanes past Nk, and positions past n, get -inf).  The candidate rows pass through LDS
 // in 64-byte column slices: four lanes load one row's slice with consecutive 16-byte
@@ -170,9 +163,10 @@ __device__ __forceinline__ double canon_chunk(const i32x4& a4, const i32x4& b4, 
 static constexpr int RF_SLICE = 64;
 static constexpr int RF_PITCH = RF_SLICE + 16;   // LDS row pitch (bank spread)
 
+// udec (FP8): the user's decoded values (decode_user_fp8).
 template <int DT>
 __device__ __forceinline__ double canon_dot_staged(const RefineArgs& a, int64_t u, float su, const uint32_t* sid,
-                                                   int Nk, uint8_t* rows)
+                                                   int Nk, uint8_t* rows, const float* udec)
 {
     constexpr int EB = Elt<DT>::bytes;
     const int l = lane_id();
@@ -201,8 +195,12 @@ __device__ __forceinline__ double canon_dot_staged(const RefineArgs& a, int64_t 
                 const int off = s0 + c * 16;
                 if (off >= RB) break;
                 const i32x4 b4 = *(const i32x4*)(rows + l * RF_PITCH + c * 16);
-                const i32x4 a4 = *(const i32x4*)(ur + off);
-                acc = canon_chunk<DT>(a4, b4, off / EB, a.d, acc);
+                if constexpr (DT == DT_FP8) {
+                    acc = canon_chunk_fp8(udec, b4, off, a.d, acc);
+                } else {
+                    const i32x4 a4 = *(const i32x4*)(ur + off);
+                    acc = canon_chunk<DT>(a4, b4, off / EB, a.d, acc);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -308,8 +306,9 @@ __device__ bool refine_select(const RefineArgs& a, int64_t u, uint32_t* skey, ui
 // arithmetic.
 template <int DT, bool FAST>
 __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey, const uint32_t* sid, int Nk,
-                            float cut, float tau_max, double* s64, double* lam_row, uint8_t* rows)
+                            float cut, float tau_max, double* s64, double* lam_row, uint8_t* rows, float* udec)
 {
+    if constexpr (DT == DT_FP8) decode_user_fp8(a, u, udec);
     const int l = lane_id();
     const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
     const double un = sqrt(a.user_n2[u]);
@@ -324,7 +323,7 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
     };
     if (FAST || Nk <= 64) {
         // one candidate per lane; the ranks come from a bitonic sort across the wave
-        double v = canon_dot_staged<DT>(a, u, su, sid, Nk, rows);
+        double v = canon_dot_staged<DT>(a, u, su, sid, Nk, rows, udec);
         if (l < Nk) worst_raw = rel(v, (double)ord_f32(skey[l]));
         int idx = l;
 #pragma unroll
@@ -351,7 +350,7 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
     } else if constexpr (!FAST) {
         // 64 candidates at a time through the staged dot products
         for (int j0 = 0; j0 < Nk; j0 += 64) {
-            const double v = canon_dot_staged<DT>(a, u, su, sid + j0, Nk - j0, rows);
+            const double v = canon_dot_staged<DT>(a, u, su, sid + j0, Nk - j0, rows, udec);
             if (j0 + l < Nk) {
                 s64[j0 + l] = v;
                 worst_raw = fmax(worst_raw, rel(v, (double)ord_f32(skey[j0 + l])));
@@ -402,12 +401,12 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
 
 template <int DT, int GPL, bool FAST>
 __device__ void refine_user(const RefineArgs& a, int64_t u, uint32_t* skey, uint32_t* sid, double* s64,
-                            double* lam_row, int* hist, uint8_t* rows)
+                            double* lam_row, int* hist, uint8_t* rows, float* udec)
 {
     int Nk = 0;
     float cut = 0.f, tau_max = 0.f;
     if (!refine_select<GPL>(a, u, skey, sid, hist, &Nk, &cut, &tau_max)) return;
-    refine_rank<DT, FAST>(a, u, skey, sid, Nk, cut, tau_max, s64, lam_row, rows);
+    refine_rank<DT, FAST>(a, u, skey, sid, Nk, cut, tau_max, s64, lam_row, rows, udec);
 }
 
 
@@ -425,17 +424,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FAST ? 6 : 
     __shared__ double lam_row[4][1];
     __shared__ int hist_all[4][256];
     __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
+    __shared__ __attribute__((aligned(16))) float udec_all[4][DT == DT_FP8 ? 256 : 4];
     const int w = threadIdx.x >> 6;
     if (!a.list) {
         const int64_t u = (int64_t)blockIdx.x * 4 + w;
         if (u < a.m)
             refine_user<DT, GPL, FAST>(a, u, skey[w], sid[w], s64[w], lam_row[w], hist_all[w],
-                                       rows_all[w]);
+                                       rows_all[w], udec_all[w]);
     } else {
         const int cnt = *a.list_count;
         for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < cnt; i += (int64_t)gridDim.x * 4)
             refine_user<DT, GPL, FAST>(a, a.list[i], skey[w], sid[w], s64[w], lam_row[w],
-                                       hist_all[w], rows_all[w]);
+                                       hist_all[w], rows_all[w], udec_all[w]);
     }
 }
 
@@ -483,6 +483,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
 {
     __shared__ uint32_t skey_all[4][64], sid_all[4][64];
     __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
+    __shared__ __attribute__((aligned(16))) float udec_all[4][DT == DT_FP8 ? 256 : 4];
     const int w = threadIdx.x >> 6, l = lane_id();
     const int64_t u = xcd_user(w);
     if (u >= a.m) return;
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
     }
     __builtin_amdgcn_wave_barrier();
     refine_rank<DT, true>(a, u, skey_all[w], sid_all[w], Nk, __int_as_float(mt[1]), __int_as_float(mt[2]), nullptr,
-                          nullptr, rows_all[w]);
+                          nullptr, rows_all[w], udec_all[w]);
 }
 
 // The rescoring of 64 < C <= 224 kept candidates: staged FP64 dot products 64 at a
@@ -508,6 +509,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     __shared__ double s64_all[4][224];
     __shared__ double lk_all[4][1];
     __shared__ __attribute__((aligned(16))) uint8_t rows_all[4][64 * RF_PITCH];
+    __shared__ __attribute__((aligned(16))) float udec_all[4][DT == DT_FP8 ? 256 : 4];
     const int w = threadIdx.x >> 6, l = lane_id();
     const int64_t u = xcd_user(w);
     if (u >= a.m) return;
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
     __builtin_amdgcn_wave_barrier();
     refine_rank<DT, false>(a, u, skey_all[w], sid_all[w], Nk, __int_as_float(mt[1]), __int_as_float(mt[2]),
-                           s64_all[w], lk_all[w], rows_all[w]);
+                           s64_all[w], lk_all[w], rows_all[w], udec_all[w]);
 }
 
 template <int DT>
