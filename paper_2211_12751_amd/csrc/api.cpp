@@ -218,6 +218,9 @@ static void choose_topk(Index& x)
     x.G = gpl * 64;
 }
 
+// Items from which the main top-k pass waits for the build's second stream (see below).
+static constexpr int64_t kMainWaitsItems = int64_t(1) << 18;
+
 // Exact lambda table over the users in their ORIGINAL order (users_o: padded copy
 // [m x ld], user_scales_o / user_n2_o in the same order); lambda rows and the raw
 // candidates are indexed by original user.  Two stream-ordered halves without host
@@ -229,7 +232,7 @@ struct LambdaBuild {
 };
 
 static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const float* user_scales_o,
-                        hipStream_t s)
+                        hipStream_t s, const std::function<void()>& before_main)
 {
     choose_topk(x);
     const int64_t m = x.m;
@@ -283,6 +286,7 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
         a0.theta_out = L.theta.f();
         launch_topk_seed(tdt, a0, s);
     }
+    before_main();
     HIPC(hipEventRecord(L.ev.ev[3], s));
     TopkArgs a1 = ta;
     a1.v0 = 0; a1.v1 = x.n_lam; a1.nseg = x.nseg; a1.seg_base = 0; a1.seg_len = x.seg_len;
@@ -474,6 +478,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
         std::mutex mu;
         std::condition_variable cv;
         bool srp_ready = false;
+        bool side_queued = false;   // ev[7] recorded (or the worker failed)
         std::atomic<bool> cancel{false};
         std::exception_ptr err;
         hipStream_t s2 = nullptr;
@@ -482,6 +487,14 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
             {
                 std::lock_guard<std::mutex> g(mu);
                 srp_ready = true;
+            }
+            cv.notify_all();
+        }
+        void queued()
+        {
+            {
+                std::lock_guard<std::mutex> g(mu);
+                side_queued = true;
             }
             cv.notify_all();
         }
@@ -510,15 +523,32 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
             wk.ready();
             // ---- Cone-Tree over user directions; users are stored in leaf order
             build_cone(x, users, user_scales, n2_users_orig.d(), s2, nullptr, cone_work, &wk.cancel);
-            if (wk.cancel.load()) return;
+            if (wk.cancel.load()) {
+                wk.queued();
+                return;
+            }
             saalsh_users(x, s2);
             HIPC(hipEventRecord(ev.ev[7], s2));
+            wk.queued();
         } catch (...) {
             wk.err = std::current_exception();
             wk.ready();
+            wk.queued();
         }
     });
-    lambda_topk(x, L, users_o, uscales_o.f(), s);
+    // With many items the main pass is long (about 2n times the second stream's work per
+    // user): it then waits for the second stream, whose kernels would otherwise be starved
+    // by the main pass's workgroups and stretch across it, taking compute units from it the
+    // whole time.  With few items the two overlap (their lengths are comparable).
+    const bool main_waits = x.n_lam >= kMainWaitsItems;
+    lambda_topk(x, L, users_o, uscales_o.f(), s, [&] {
+        if (!main_waits) return;
+        {
+            std::unique_lock<std::mutex> lk(wk.mu);
+            wk.cv.wait(lk, [&] { return wk.side_queued; });
+        }
+        if (!wk.err && !wk.cancel.load()) HIPC(hipStreamWaitEvent(s, ev.ev[7], 0));
+    });
     // validation (the input statistics and the partition count were copied before ev1),
     // then the item side of SA-ALSH behind the top-k passes
     host_wait(ev.ev[1]);

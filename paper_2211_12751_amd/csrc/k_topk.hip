@@ -510,7 +510,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     constexpr int LPW = (NLD + TK_WAVES - 1) / TK_WAVES;
     constexpr int TBYTES = NLD * 1024;
     constexpr int SGPL = MODE == TK_MAIN ? GPL : 1;
-    constexpr bool FOLD = MODE == TK_MAIN && dt_scaled<DT>;
+    // scaled rows: the user's scale stays out of the per-score work (see below)
+    constexpr bool FOLD = dt_scaled<DT>;
     __shared__ __attribute__((aligned(1024))) uint8_t ring0[TBYTES];
     __shared__ __attribute__((aligned(1024))) uint8_t ring1[TBYTES];
     __shared__ __attribute__((aligned(1024))) uint8_t ring2[TBYTES];
@@ -565,9 +566,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             }
         }
     }
-    // FP8 main pass: the user's scale is folded into its threshold.  The pass compares
+    // FP8: the user's scale is folded into its threshold.  The main pass compares
     // w = s_p raw against ths = RD(theta / s_u): an item left out has w <= ths, so its
-    // fast score RN(s_u w) <= s_u ths <= theta.  Appended entries carry RN(s_u w).
+    // fast score RN(s_u w) <= s_u ths <= theta.  Appended entries carry RN(s_u w).  The
+    // seed pass keeps its lists in w (the order is the same for s_u > 0).
     float ths[NG];
     auto fold = [&](float t, float s) -> float {
         if (!(s > 0.f)) return 0.f > t ? -__builtin_inff() : __builtin_inff();
@@ -804,7 +806,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         if constexpr (MODE == TK_SEED) {
             const float mine = top[g][TK_T - 1];
             const float other = __shfl_xor(mine, 32);
-            if (l < 32 && uok) a.theta_out[ug] = fminf(mine, other);
+            // with the scale folded out the lists hold s_p raw; the estimate is s_u times
+            // its threshold (an estimate only: the certificate does not depend on it)
+            const float t = fminf(mine, other);
+            if (l < 32 && uok) a.theta_out[ug] = (FOLD && su[g] > 0.f) ? su[g] * t : t;
         } else {
             if (uok) {
                 a.cnt[(ug * a.nseg_total + seg) * 2 + h] = (int)((off[g] - loff8[g]) >> 3);
