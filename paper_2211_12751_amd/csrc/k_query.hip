@@ -187,6 +187,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
     i32x4 pf[PREFETCH ? PF : 1];
     float pqn = 0.f, pqs = 1.f;
     int pqsl = 0;
+    // cos(phi) of the tile's (block, query) entries threadIdx.x and threadIdx.x + 256, loaded
+    // one tile ahead with the query rows (entries past 512 are read when used)
+    float pc[2] = {1.f, 1.f};
     auto prefetch = [&](int64_t qb) {
         if constexpr (PREFETCH) {
 #pragma unroll
@@ -198,6 +201,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
             pqn = ok ? a.qnorm[q] : 0.f;
             pqs = (ok && dt_scaled<DT>) ? a.query_scales[q] : 1.f;
             pqsl = ok ? a.qslot[q] : 0;
+        }
+        if (use_bounds) {
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                const int e = threadIdx.x + 256 * i;
+                if (e < nbb * 32 && qb + (e & 31) < q_end)
+                    pc[i] = a.cphi[(int64_t)(bfirst + (e >> 5)) * a.nq + qb + (e & 31)];
+            }
         }
     };
     prefetch(q_begin);
@@ -229,6 +240,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
         }
         if (threadIdx.x < VF_MAXB) live_q[threadIdx.x] = 0u;
         __syncthreads();
+        const float pc0 = pc[0], pc1 = pc[1];   // this tile's; the prefetch below reloads them
         if (qb + 32 < q_end) prefetch(qb + 32);
 
         // node-level data per (block, query): cos(phi) from the pre-pass, the rest here
@@ -236,7 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
             const int b = e >> 5, qi = e & 31;
             f32x4 out = {1.f, 0.f, 0.f, 2.f};     // w = 2: no angle data, never prune
             if (bok[b] && qb + qi < q_end && qn_s[qi] > 0.f) {
-                const float c = a.cphi[(int64_t)(bfirst + b) * a.nq + qb + qi];
+                const float c = e < 256 ? pc0 : e < 512 ? pc1 : a.cphi[(int64_t)(bfirst + b) * a.nq + qb + qi];
                 const float s = sqrtf(fmaxf(0.f, 1.f - c * c));
                 const float ce = fabsf(c) + a.err_phi;
                 const float rem = 1.f - ce * ce;
