@@ -322,8 +322,10 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
     launch_refine(x.dtype, ra, s);
     {
         // rows whose certificate failed: full FP64 rescoring (the count stays on the
-        // device; with none the fallback workgroups exit at once)
-        const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(256e6 / (8.0 * (double)x.n_lam))));
+        // device; with none the fallback workgroups exit at once).  One workgroup per
+        // failed user at a time, up to 256 at once (one per compute unit) within 2 GB of
+        // score rows (c5: 250 users at once; 32 had made 375 failures cost 4.3 s)
+        const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(2e9 / (8.0 * (double)x.n_lam))));
         DevBuf scratch;
         scratch.alloc(sizeof(double) * (size_t)rows * x.n_lam);
         launch_fallback(x.dtype, ra, scratch.d(), rows, s);
