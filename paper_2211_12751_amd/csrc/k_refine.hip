@@ -579,6 +579,39 @@ void launch_refine(int dtype, const RefineArgs& a, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ full FP64 fallback
+// Canonical score of the user whose values sit decoded in ux (LDS, exact as floats) against
+// item row p, read 16 bytes at a time: index-order FP64 sum of the exact products (FP8:
+// a product of two e4m3 values is exact in FP32), then the scale product for FP8.
+template <int DT>
+__device__ __forceinline__ double canon_dot_row(const float* ux, const void* P, int64_t p, float su, float sp, int d,
+                                                int ld)
+{
+    constexpr int EB = Elt<DT>::bytes;
+    constexpr int PER = 16 / EB;
+    const uint8_t* pr = (const uint8_t*)P + p * (int64_t)ld * EB;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < d; c0 += PER) {
+        const i32x4 b4 = *(const i32x4*)(pr + c0 * EB);
+        const int lim = d - c0 < PER ? d - c0 : PER;
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            if (e >= lim) break;
+            const float x = ux[c0 + e];
+            if constexpr (DT == DT_F32) {
+                acc = __fma_rn((double)x, (double)__int_as_float(b4[e]), acc);
+            } else if constexpr (DT == DT_BF16) {
+                const float y = bf16_to_f32((uint16_t)((uint32_t)b4[e >> 1] >> (16 * (e & 1))));
+                acc = __fma_rn((double)x, (double)y, acc);
+            } else {
+                const float y = e4m3_to_f32((uint8_t)((uint32_t)b4[e >> 2] >> (8 * (e & 3))));
+                acc = acc + (double)(x * y);
+            }
+        }
+    }
+    if constexpr (DT == DT_FP8) acc = ((double)su * (double)sp) * acc;
+    return acc;
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_fallback(RefineArgs a, double* scratch, int64_t scratch_rows)
 {
@@ -587,14 +620,17 @@ __global__ __launch_bounds__(256) void k_fallback(RefineArgs a, double* scratch,
     __shared__ int s_sel, s_above;
     __shared__ double top[256];
     __shared__ int ntop;
+    __shared__ __attribute__((aligned(16))) float ux[256];   // the user's values (d <= ld <= 256)
     const int tid = threadIdx.x;
     for (int64_t fi = blockIdx.x; fi < nfail; fi += gridDim.x) {
         const int64_t u = a.fail_list[fi];
         double* sc = scratch + (int64_t)(blockIdx.x % scratch_rows) * a.n;
         const float su = DT == DT_FP8 ? a.user_scales[u] : 1.f;
+        for (int i = tid; i < a.ld; i += 256) ux[i] = i < a.d ? elem_f32<DT>(a.users, u * (int64_t)a.ld + i) : 0.f;
+        __syncthreads();
         for (int64_t p = tid; p < a.n; p += 256) {
             const float sp = DT == DT_FP8 ? a.item_scales[p] : 1.f;
-            sc[p] = canon_dot<DT>(a.users, u, su, a.items, p, sp, a.d, a.ld);
+            sc[p] = canon_dot_row<DT>(ux, a.items, p, su, sp, a.d, a.ld);
         }
         __syncthreads();
         const int want = (int)(a.n < a.k_max ? a.n : a.k_max);
