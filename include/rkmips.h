@@ -76,9 +76,14 @@ enum {
                                        split BF16 products (h.h + l.h + h.l, h and l the
                                        BF16 head and tail of each value) with their own
                                        error bound; either way the exact path decides.   */
-    RKMIPS_FLAG_POOL_LISTS = 128    /* collect the answers in the result pool and sort
+    RKMIPS_FLAG_POOL_LISTS = 128,   /* collect the answers in the result pool and sort
                                        the lists even when a batch's answer bits (one per
                                        query and user) fit the 64 MiB budget             */
+    RKMIPS_FLAG_VERIFY_SIMPLE = 256 /* query: score with the one-group verify kernel
+                                       (register-fed query tiles) where the two-group
+                                       ring form would run (BF16 and FP8 indexes with
+                                       padded rows of 128 or 256 values); both take the
+                                       same decisions                                     */
 };
 
 typedef struct {

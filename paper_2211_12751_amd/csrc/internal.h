@@ -206,6 +206,9 @@ struct QueryArgs {
     const void* mma_users; const void* mma_queries; int mma_dtype, mma_ld;
     const float* qnorm;                              // [nq]
     const float* cphi;                               // [nblocks x nq] cos of the query-centre angle
+    // Lemma 2 prune words [nblocks x ntq]: bit i of word (b, T) is set when the block test
+    // removes block b for query 32 T + i (written with the cosines; read by the ring form)
+    uint32_t* prune; int64_t ntq;
     const int* qslot;                                // [nq] slot of the query's k
     const uint32_t* qorig;                           // [nq] k-sorted position -> caller index
     const int* qk;                                   // [nq] k of each (k-sorted) query
@@ -239,7 +242,11 @@ struct QueryArgs {
 };
 void launch_qnorm(int dtype, const void* Q, const float* qs, int64_t nq, int d, int ld,
                   float* qnorm, int* bad, hipStream_t s);
+// cos(phi) per (block, query) into cphi (null: not stored) and the prune words a.prune
 void launch_phi(const QueryArgs& a, float* cphi, hipStream_t s);
+// true when launch_verify_range takes the ring form for this index (it reads the prune
+// words only, not the cosines)
+bool verify_uses_ring(const QueryArgs& a);
 void launch_verify_range(const QueryArgs& a, int64_t q_begin, int64_t q_end, hipStream_t s);
 void launch_recheck(const QueryArgs& a, int64_t namb, const int* reject, hipStream_t s);
 // Item insertion: merge the canonical scores of n_new padded item rows into every user's

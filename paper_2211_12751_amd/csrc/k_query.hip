@@ -20,9 +20,11 @@
 // FP32 evaluation and the stored cos/sin pairs.  Pruning is only ever a strict "<".
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <utility>
 
 #include "common.h"
+#include "dma.h"
 #include "internal.h"
 
 namespace rk {
@@ -68,6 +70,27 @@ __device__ __forceinline__ f32x16 verify_block(const uint8_t* qt, const i32x4 (&
         }
     }
     return acc;
+}
+
+// Node-level bound of Lemma 2 for one (block, query) pair from c = cos(phi) (FP32, known
+// within +-err_phi): sin(phi), the angle uncertainty dphi and the bound
+// ||q|| (cos({phi - omega}_+) + dphi + slack) on <u, q> / ||u|| over the block's users.
+struct NodeBound {
+    float s, dphi, ub;
+};
+__device__ __forceinline__ NodeBound node_bound(float c, float qn, float cw, float sw, float err_phi, float slack)
+{
+    // each operation rounded on its own (no fused multiply-adds), so that every kernel
+    // that evaluates the bound takes the same decision
+#pragma clang fp contract(off)
+    NodeBound nb;
+    nb.s = sqrtf(fmaxf(0.f, 1.f - c * c));
+    const float ce = fabsf(c) + err_phi;
+    const float rem = 1.f - ce * ce;
+    nb.dphi = rem > 4.f * err_phi ? err_phi / sqrtf(rem) : 2.f * sqrtf(2.f * err_phi) + err_phi;
+    const float fnode = c >= cw ? 1.f : c * cw + nb.s * sw;
+    nb.ub = qn * (fnode + nb.dphi + slack);
+    return nb;
 }
 
 // Inner-product test of one pair: x against lambda with the fast-path error bound
@@ -249,14 +272,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
             f32x4 out = {1.f, 0.f, 0.f, 2.f};     // w = 2: no angle data, never prune
             if (bok[b] && qb + qi < q_end && qn_s[qi] > 0.f) {
                 const float c = e < 256 ? pc0 : e < 512 ? pc1 : a.cphi[(int64_t)(bfirst + b) * a.nq + qb + qi];
-                const float s = sqrtf(fmaxf(0.f, 1.f - c * c));
-                const float ce = fabsf(c) + a.err_phi;
-                const float rem = 1.f - ce * ce;
-                const float dphi = rem > 4.f * a.err_phi ? a.err_phi / sqrtf(rem) : 2.f * sqrtf(2.f * a.err_phi) + a.err_phi;
-                const float cw = bcw[b], sw = bsw[b];
-                const float fnode = c >= cw ? 1.f : c * cw + s * sw;
-                const float ub = qn_s[qi] * (fnode + dphi + a.bound_slack);
-                out = f32x4{c, s, dphi, ub < blb[qslot_s[qi]][b] ? 1.f : 0.f};
+                const NodeBound nd = node_bound(c, qn_s[qi], bcw[b], bsw[b], a.err_phi, a.bound_slack);
+                out = f32x4{c, nd.s, nd.dphi, nd.ub < blb[qslot_s[qi]][b] ? 1.f : 0.f};
             }
             phi_s[b][qi] = out;
             if (out[3] != 1.f && qb + qi < q_end) atomicOr(&live_q[b], 1u << qi);
@@ -454,6 +471,430 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
     if (threadIdx.x < 4 && st_s[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], st_s[threadIdx.x]);
 }
 
+// ------------------------------------------------------------------ ring form
+// BF16 operands (BF16 data, widened FP8 codes) with rows of 256 bytes and more.  A wave
+// holds two groups of 32 users in registers, so that every query fragment read from LDS
+// feeds two products; a workgroup holds 256 users.  The query tiles (32 rows at the
+// absolute positions 32 T .. 32 T + 31; rows outside the launch's range are loaded and
+// masked) reach LDS by direct loads into a ring of three padded buffers, two tiles ahead
+// of the one being scored, together with the tile's per-query data (norm, scale, k slot,
+// caller index) and the Lemma 2 prune words of the workgroup's first 64 blocks (written
+// by k_phi; users of later blocks are never pruned).  One barrier per tile.  Each wave
+// stages its yes answers in LDS and reserves pool space once per stage-full, and a wave
+// with close calls reserves their slots itself, so no step waits for the other waves.
+// The products (same operands, same k order) and the inner-product test are those of
+// k_verify, so both forms take the same decisions.
+static constexpr int VR_UPB = 256;   // users per workgroup
+static constexpr int VR_SW = 128;    // yes answers staged per wave
+static constexpr int VR_HQ = 320;    // per-tile words: norms, scales, slots, prune words, caller indexes
+
+template <int DT, int KSTEPS, int LROW>
+__device__ __forceinline__ void ring_block(const uint8_t* tile, const i32x4 (&bfrag)[2][KSTEPS], f32x16 (&acc)[2])
+{
+    const int l = lane_id(), h = l >> 5;
+#pragma unroll
+    for (int g = 0; g < 2; g++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[g][r] = 0.f;
+    const uint8_t* arow = tile + (l & 31) * LROW + h * 16;
+#pragma unroll
+    for (int t = 0; t < KSTEPS; t++) {
+        const bf16x8 af = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + t * 32));
+#pragma unroll
+        for (int g = 0; g < 2; g++)
+            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, __builtin_bit_cast(bf16x8, bfrag[g][t]), acc[g], 0, 0, 0);
+    }
+}
+
+// Two waves per SIMD: at three, the 168-register budget makes the compiler spill, and a
+// spill reload inside the tile loop waits for every tile load in flight.
+template <int DT, int DPT>
+constexpr int verify_ring_wpe()
+{
+    return 2;
+}
+
+// Grid: (user tile, chunk) pairs, chunk-major; chunk c covers the range's tiles
+// [c per, (c + 1) per) (relative to the first).
+template <int DT, int DPT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_ring_wpe<DT, DPT>(), 8))) void k_verify_ring(QueryArgs a, int64_t q_first, int64_t q_last, int64_t per, int64_t wgs)
+{
+    static_assert(dt_bf16_mma<DT>, "the ring form takes BF16 operands");
+    constexpr int NG = 2;
+    constexpr int UPW = 32 * NG;
+    constexpr int ROWB = DPT * Elt<DT>::bytes;
+    constexpr int LROW = ROWB + 16;               // padded LDS row (bank spread)
+    constexpr int CPR = LROW / 16;
+    constexpr int KSTEPS = ROWB / 32;
+    constexpr int NLD = (32 * LROW + 1023) / 1024;   // 1 KB direct loads per tile
+    constexpr int LPW = (NLD + 3) / 4;
+    constexpr int TBYTES = NLD * 1024;
+    constexpr bool SC = dt_scaled<DT>;
+    __shared__ __attribute__((aligned(1024))) uint8_t ring_all[3 * TBYTES];
+    // per tile: [0, 64) query norms, [64, 128) scales, [128, 192) k slots, [192, 256) prune
+    // words by block (relative to the workgroup's first), [256, 320) caller indexes
+    __shared__ __attribute__((aligned(256))) uint32_t hq_all[3 * VR_HQ];
+    __shared__ float lam_s[VF_MAXSLOT][VR_UPB];
+    // per user of the workgroup: original index, block relative to the first (the loop
+    // reads them from here: registers are scarce, and a spill reload would make the
+    // compiler wait for the tile loads in flight)
+    __shared__ uint32_t ouid_s[VR_UPB];
+    __shared__ int br_s[VR_UPB];
+    __shared__ unsigned long long ystage_all[4][VR_SW];
+    __shared__ unsigned long long st_s[4];
+
+    const int l = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (SGPR)
+    const int h = l >> 5;
+    unsigned long long* ystage = ystage_all[w];
+    const int64_t chunk = (int64_t)blockIdx.x / wgs;
+    const int64_t u0 = ((int64_t)blockIdx.x - chunk * wgs) * VR_UPB;
+    const int64_t tb = ((q_first >> 5) + chunk * per) * 32;
+    const int64_t q_begin = q_first > tb ? q_first : tb;
+    const int64_t q_end = q_last < tb + per * 32 ? q_last : tb + per * 32;
+    const bool use_bounds = !(a.flags & RKMIPS_FLAG_NO_BOUNDS) && a.prune != nullptr;
+    const bool force = (a.flags & RKMIPS_FLAG_FORCE_RECHECK) != 0;
+
+    // lambda rows of the k slots (fixed for the launch)
+    for (int e = threadIdx.x; e < a.nslots * VR_UPB; e += 256) {
+        const int sl = e / VR_UPB, ul = e % VR_UPB;
+        const int64_t u = u0 + ul;
+        lam_s[sl][ul] = u < a.m ? a.lam32[(int64_t)(a.slot_k[sl] - 1) * a.m + a.perm[u]] : 0.f;
+    }
+    if (threadIdx.x < 4) st_s[threadIdx.x] = 0ull;
+    const int bfirst = a.user_block[u0];
+    const int nbw = (int)(a.nblocks - bfirst < 64 ? a.nblocks - bfirst : 64);
+
+    // ---- resident user fragments (B operands), one user column per lane and group
+    i32x4 bfrag[NG][KSTEPS];
+    float su[NG], uerr[NG];
+    bool uok[NG];
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+        const int64_t u = u0 + w * UPW + g * 32 + (l & 31);
+        uok[g] = u < a.m;
+        const int64_t uu = uok[g] ? u : u0;
+        const uint8_t* row = (const uint8_t*)a.mma_users + uu * ROWB;
+#pragma unroll
+        for (int t = 0; t < KSTEPS; t++) {
+            i32x4 z = {0, 0, 0, 0};
+            bfrag[g][t] = uok[g] ? *(const i32x4*)(row + t * 32 + h * 16) : z;
+        }
+        su[g] = SC ? a.user_scales[uu] : 1.f;
+        // (err_rel widened by 2^-20 so the regrouped FP32 product cannot undercut it)
+        uerr[g] = (float)(a.err_rel * (1.0 + 0x1p-20)) * a.unorm[uu];
+        if (h == 0) {
+            br_s[w * UPW + g * 32 + (l & 31)] = a.user_block[uu] - bfirst;
+            ouid_s[w * UPW + g * 32 + (l & 31)] = a.perm[uu];
+        }
+    }
+
+    const int64_t T0 = q_begin >> 5;
+    const int ntiles = (int)(((q_end + 31) >> 5) - T0);
+    const uint32_t pbytes = use_bounds ? (uint32_t)nbw * (uint32_t)a.ntq * 4u : 0u;
+    const uint32_t* pbase = use_bounds ? a.prune + (int64_t)bfirst * a.ntq : (const uint32_t*)a.qnorm;
+
+    // ---- direct loads: load j of this wave fills LDS bytes [k * 1024, (k + 1) * 1024) of
+    // a slot, k = w * LPW + j; lane l writes 16 bytes at k * 1024 + 16 l, which is chunk
+    // (pos % CPR) of padded row pos / CPR (the padding chunk takes a copy of chunk 0)
+    const int pos0 = w * LPW * 64 + l;
+    auto doff = [&](int j) -> unsigned {
+        unsigned p0 = (unsigned)pos0;
+        asm volatile("" : "+v"(p0));
+        const unsigned pos = p0 + (unsigned)j * 64u;
+        const unsigned c = pos % (unsigned)CPR;
+        return (pos / (unsigned)CPR) * (unsigned)ROWB + (c < (unsigned)(ROWB / 16) ? c : 0u) * 16u;
+    };
+    auto issue = [&](uint8_t* ring, uint32_t* hq, int tt) {
+        const int64_t T = T0 + tt;
+        const int64_t r0 = T * 32;
+        const int rows = q_end - r0 < 32 ? (int)(q_end - r0) : 32;
+        // rows past the launch's last query read as zeros
+        const dma_rsrc rs = dma_buffer((const uint8_t*)a.mma_queries + r0 * ROWB, (uint32_t)(rows * ROWB));
+        const uint32_t lb = RK_LDS_ADDR(ring);
+#pragma unroll
+        for (int j = 0; j < LPW; j++)
+            if (w * LPW + j < NLD) dma_load16(rs, lb + (uint32_t)((w * LPW + j) * 1024), doff(j));
+        if (w == 0) {
+            const uint32_t hb = RK_LDS_ADDR(hq);
+            const uint32_t qb4 = (uint32_t)(rows * 4);
+            dma_load4(dma_buffer(a.qnorm + r0, qb4), hb, (uint32_t)(l * 4));
+            if constexpr (SC) dma_load4(dma_buffer(a.query_scales + r0, qb4), hb + 256u, (uint32_t)(l * 4));
+            dma_load4(dma_buffer(a.qslot + r0, qb4), hb + 512u, (uint32_t)(l * 4));
+            // lane i: the word of block bfirst + i (lanes past the staged blocks read 0)
+            uint32_t lt = (uint32_t)l;
+            asm volatile("" : "+v"(lt));   // recomputed per tile, not kept live
+            dma_load4(dma_buffer(pbase, pbytes), hb + 768u, (lt * (uint32_t)a.ntq + (uint32_t)T) * 4u);
+            dma_load4(dma_buffer(a.qorig + r0, qb4), hb + 1024u, (uint32_t)(l * 4));
+        }
+    };
+    // Before tile tt is read: this wave's loads of tile tt have landed when no more than
+    // its loads of tile tt + 1 (if issued) are in flight; anything issued after those
+    // (answer stores) only makes the wait stricter.  Wave 0 also loads the per-query data.
+    auto wait_tile = [&](bool next_issued) {
+        constexpr int n0 = (NLD < LPW ? NLD : LPW) + (SC ? 5 : 4);
+        constexpr int n1 = NLD - LPW <= 0 ? 0 : (NLD - LPW < LPW ? NLD - LPW : LPW);
+        constexpr int n2 = NLD - 2 * LPW <= 0 ? 0 : (NLD - 2 * LPW < LPW ? NLD - 2 * LPW : LPW);
+        constexpr int n3 = NLD - 3 * LPW <= 0 ? 0 : (NLD - 3 * LPW < LPW ? NLD - 3 * LPW : LPW);
+        static_assert(n0 < 64, "wait counts");
+        if (!next_issued) RK_WAIT_VMCNT(0);
+        else if (w == 0) RK_WAIT_VMCNT(n0);
+        else if (w == 1) RK_WAIT_VMCNT(n1);
+        else if (w == 2) RK_WAIT_VMCNT(n2);
+        else RK_WAIT_VMCNT(n3);
+    };
+
+    uint32_t n_node = 0u, n_scored = 0u, n_amb = 0u;
+    int ycnt = 0;   // yes answers staged by this wave (wave-uniform)
+    auto flush = [&]() {
+        if (ycnt == 0) return;
+        unsigned long long b = 0ull;
+        if (l == 0) b = atomicAdd(a.pool_count, (unsigned long long)ycnt);
+        b = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) << 32) |
+            __builtin_amdgcn_readfirstlane((uint32_t)b);
+        __builtin_amdgcn_wave_barrier();
+        for (int i = l; i < ycnt; i += 64)
+            if ((int64_t)(b + i) < a.pool_cap) a.pool[b + i] = ystage[i];
+        __builtin_amdgcn_wave_barrier();
+        ycnt = 0;
+    };
+
+    auto tile = [&](const uint8_t* ring, const uint32_t* hq, int tt) {
+        const int64_t r0 = (T0 + tt) * 32;
+        const int lo = r0 < q_begin ? (int)(q_begin - r0) : 0;
+        const int hi = q_end - r0 < 32 ? (int)(q_end - r0) : 32;
+        const uint32_t vmask = (hi == 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+        // lane terms recomputed per tile (opaque to the compiler): hoisted out of the
+        // loop, the row and user indexes of every output would be kept live, and spill
+        int h4 = 4 * h, lc = l & 31;
+        asm volatile("" : "+v"(h4), "+v"(lc));
+        const uint32_t hmask = 0x0f0f0f0fu << h4;   // the lane's 16 rows
+        auto row_of = [&](int r) -> int { return ((r >> 2) << 3) + h4 + (r & 3); };
+        uint32_t qlive[NG];
+#pragma unroll
+        for (int g = 0; g < NG; g++) {
+            const int br = br_s[w * UPW + g * 32 + lc];
+            const uint32_t pw = br < 64 ? hq[192 + br] : 0u;
+            qlive[g] = uok[g] ? (vmask & ~pw) : 0u;
+            if (uok[g]) n_node += __popc(vmask & hmask & ~qlive[g]);
+        }
+        uint32_t yes[NG] = {0u, 0u}, amb[NG] = {0u, 0u};
+        if (ballot64((qlive[0] | qlive[1]) != 0u)) {
+            f32x16 acc[NG];
+            ring_block<DT, KSTEPS, LROW>(ring, bfrag, acc);
+            const float* hf = (const float*)hq;
+            // bit r of on16: the lane's row r (query mfma32_row(r, l)) is live
+            uint32_t on16[NG];
+#pragma unroll
+            for (int g = 0; g < NG; g++) {
+                const uint32_t mine = qlive[g] & hmask;
+                n_scored += __popc(mine);
+                const uint32_t mh = mine >> h4;
+                on16[g] = (mh & 0xfu) | ((mh >> 4) & 0xf0u) | ((mh >> 8) & 0xf00u) | ((mh >> 12) & 0xf000u);
+            }
+            // queries arrive sorted by k: a tile usually has one k slot
+            const int sl0 = (int)(hq[128 + lo] & 7u), sl1 = (int)(hq[128 + hi - 1] & 7u);
+            if (sl0 == sl1) {
+                // yes beyond +e, a close call within +-e, no below -e; with lambda = -inf
+                // every difference is +inf, so every live query is a yes
+                float lam[NG], elam[NG];
+                bool linf[NG];
+#pragma unroll
+                for (int g = 0; g < NG; g++) {
+                    lam[g] = lam_s[sl0][w * UPW + g * 32 + lc];
+                    linf[g] = lam[g] == -__builtin_inff();
+                    elam[g] = (linf[g] ? 0.f : fabsf(lam[g]) * 0x1p-23f) + (float)a.d * 0x1p-120f;
+                }
+                // Screen: a pair is a yes or a close call only if x - lambda >= -e.  The
+                // screen evaluates x - lambda + 8 e in one rounded step per term; its error
+                // (a few units in the last place of |x| + |lambda|) stays below the extra
+                // 7 e, as e >= |lambda| 2^-23, so a wave whose pairs all fail it has only
+                // "no" answers and skips the test itself (lambda = -inf gives +inf).
+                float mx = -__builtin_inff();
+                {
+                    float u8[NG], c8[NG];
+#pragma unroll
+                    for (int g = 0; g < NG; g++) {
+                        u8[g] = 8.f * uerr[g];
+                        c8[g] = 8.f * elam[g] - lam[g];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const f32x4 qn4 = *(const f32x4*)(hf + 8 * j + h4);
+                        f32x4 qs4 = {1.f, 1.f, 1.f, 1.f};
+                        if constexpr (SC) qs4 = *(const f32x4*)(hf + 64 + 8 * j + h4);
+#pragma unroll
+                        for (int g = 0; g < NG; g++)
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const float b = fmaf(u8[g], qn4[e], c8[g]);
+                                const float t = SC ? fmaf(acc[g][4 * j + e], su[g] * qs4[e], b) : acc[g][4 * j + e] + b;
+                                mx = fmaxf(mx, t);
+                            }
+                    }
+                }
+                if (force || ballot64(mx >= 0.f)) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const f32x4 qn4 = *(const f32x4*)(hf + 8 * j + h4);
+                        f32x4 qs4 = {1.f, 1.f, 1.f, 1.f};
+                        if constexpr (SC) qs4 = *(const f32x4*)(hf + 64 + 8 * j + h4);
+#pragma unroll
+                        for (int g = 0; g < NG; g++)
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const int r = 4 * j + e;
+                                float x = acc[g][r];
+                                if constexpr (SC) x = (su[g] * qs4[e]) * x;
+                                const float ef = fmaf(uerr[g], qn4[e], elam[g]);
+                                const float diff = x - lam[g];
+                                yes[g] |= (uint32_t)(diff > ef) << r;
+                                amb[g] |= (uint32_t)(fabsf(diff) <= ef) << r;
+                            }
+                    }
+#pragma unroll
+                    for (int g = 0; g < NG; g++) {
+                        yes[g] &= on16[g];
+                        amb[g] &= on16[g];
+                        if (force) {
+                            yes[g] = linf[g] ? on16[g] : 0u;
+                            amb[g] = linf[g] ? 0u : on16[g];
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const f32x4 qn4 = *(const f32x4*)(hf + 8 * j + h4);
+                    f32x4 qs4 = {1.f, 1.f, 1.f, 1.f};
+                    if constexpr (SC) qs4 = *(const f32x4*)(hf + 64 + 8 * j + h4);
+                    const i32x4 sl4 = *(const i32x4*)(hq + 128 + 8 * j + h4);
+#pragma unroll
+                    for (int g = 0; g < NG; g++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            const int r = 4 * j + e;
+                            const float lam = lam_s[sl4[e] & 7][w * UPW + g * 32 + lc];
+                            float x = acc[g][r];
+                            if constexpr (SC) x = (su[g] * qs4[e]) * x;
+                            const bool li = lam == -__builtin_inff();
+                            const float ef = fmaf(uerr[g], qn4[e], (li ? 0.f : fabsf(lam) * 0x1p-23f) + (float)a.d * 0x1p-120f);
+                            const float diff = x - lam;
+                            yes[g] |= (uint32_t)(li || (!force && diff > ef)) << r;
+                            amb[g] |= (uint32_t)(!li && (force || fabsf(diff) <= ef)) << r;
+                        }
+                }
+#pragma unroll
+                for (int g = 0; g < NG; g++) {
+                    yes[g] &= on16[g];
+                    amb[g] &= on16[g];
+                }
+            }
+            n_amb += __popc(amb[0]) + __popc(amb[1]);
+        }
+        if (a.sah) {   // SAH: every pair the test does not reject goes on to the recheck
+#pragma unroll
+            for (int g = 0; g < NG; g++) {
+                n_amb += __popc(yes[g]);
+                amb[g] |= yes[g];
+                yes[g] = 0u;
+            }
+        }
+        if (a.bitmap) {   // yes answers as bits; the pool takes close calls only
+#pragma unroll
+            for (int g = 0; g < NG; g++)
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    if (yes[g] & (1u << r)) {
+                        const uint32_t qo = hq[256 + row_of(r)];
+                        const uint32_t ou = ouid_s[w * UPW + g * 32 + lc];
+                        atomicOr(&a.bitmap[(int64_t)qo * a.bm_words + (ou >> 5)], 1u << (ou & 31u));
+                    }
+        } else {
+            const int ny = __popc(yes[0]) + __popc(yes[1]);
+            if (ballot64(ny != 0)) {
+                const int iy = wave_incl_scan(ny);
+                const int ty = __builtin_amdgcn_readlane(iy, 63);
+                if (ycnt + ty > VR_SW) flush();
+                const bool direct = ty > VR_SW;   // more than the stage holds: reserve now
+                int64_t py = (int64_t)ycnt + iy - ny;
+                if (direct) {
+                    unsigned long long b = 0ull;
+                    if (l == 0) b = atomicAdd(a.pool_count, (unsigned long long)ty);
+                    b = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) << 32) |
+                        __builtin_amdgcn_readfirstlane((uint32_t)b);
+                    py = (int64_t)b + iy - ny;
+                }
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+#pragma unroll
+                    for (int r = 0; r < 16; r++)
+                        if (yes[g] & (1u << r)) {
+                            const unsigned long long e =
+                                ((unsigned long long)hq[256 + row_of(r)] << 32) | ouid_s[w * UPW + g * 32 + lc];
+                            if (direct) {
+                                if (py < a.pool_cap) a.pool[py] = e;
+                            } else {
+                                ystage[py] = e;
+                            }
+                            py++;
+                        }
+                if (!direct) ycnt += ty;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        // close calls: one reservation per wave and tile that has any
+        const int na = __popc(amb[0]) + __popc(amb[1]);
+        if (ballot64(na != 0)) {
+            const int ia = wave_incl_scan(na);
+            const int ta = __builtin_amdgcn_readlane(ia, 63);
+            unsigned long long b = 0ull;
+            if (l == 0) b = atomicAdd(a.amb_count, (unsigned long long)ta);
+            b = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) << 32) |
+                __builtin_amdgcn_readfirstlane((uint32_t)b);
+            int64_t pa = (int64_t)b + ia - na;
+#pragma unroll
+            for (int g = 0; g < NG; g++)
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    if (amb[g] & (1u << r)) {
+                        const int64_t q = r0 + row_of(r);
+                        const int64_t u = u0 + w * UPW + g * 32 + lc;
+                        if (pa < a.amb_cap) a.amb[pa] = ((unsigned long long)q << 32) | (uint32_t)u;
+                        pa++;
+                    }
+        }
+    };
+
+    __syncthreads();   // lambda rows and counters
+    // the user data is in registers before the first tile load: the in-loop waits then
+    // count the tile loads (and later stores) only
+    __builtin_amdgcn_s_waitcnt(0);
+    if (ntiles > 0) issue(ring_all, hq_all, 0);
+    if (ntiles > 1) issue(ring_all + TBYTES, hq_all + VR_HQ, 1);
+    int slot = 0, slot2 = 2;   // ring slots of tiles tt and tt + 2
+    for (int tt = 0; tt < ntiles; tt++) {
+        wait_tile(tt + 1 < ntiles);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");   // no LDS read moves above the barrier
+        if (tt + 2 < ntiles) issue(ring_all + slot2 * TBYTES, hq_all + slot2 * VR_HQ, tt + 2);
+        tile(ring_all + slot * TBYTES, hq_all + slot * VR_HQ, tt);
+        slot = slot == 2 ? 0 : slot + 1;
+        slot2 = slot2 == 2 ? 0 : slot2 + 1;
+    }
+    flush();
+    const unsigned long long s0 = wave_sum((unsigned long long)n_node);
+    const unsigned long long s2 = wave_sum((unsigned long long)n_scored);
+    const unsigned long long s3 = wave_sum((unsigned long long)n_amb);
+    if (l == 0) {
+        if (s0) atomicAdd(&st_s[0], s0);
+        if (s2) atomicAdd(&st_s[2], s2);
+        if (s3) atomicAdd(&st_s[3], s3);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && st_s[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], st_s[threadIdx.x]);
+}
+
 // cos(phi) of every (block, query) pair, phi the angle between the query and the block's
 // centre (Lemma 2; Alg. 5 block test), on the matrix cores: a dense contraction of the
 // centres [nblocks x d] with the queries [nq x d].  A wave computes 32 blocks x 64 queries
@@ -519,19 +960,37 @@ __global__ __launch_bounds__(256) void k_phi(QueryArgs a, float* cphi, int64_t b
 #pragma unroll
     for (int g = 0; g < 2; g++) {
         const int64_t q = q0 + g * 32 + (l & 31);
-        if (q >= a.nq) continue;
-        const float qn = a.qnorm[q];
-        const float qsc = MDT == DT_FP8B ? a.query_scales[q] : 1.f;
+        const bool qok = q < a.nq;
+        const int64_t qq = qok ? q : a.nq - 1;
+        const float qn = a.qnorm[qq];
+        const float qsc = MDT == DT_FP8B ? a.query_scales[qq] : 1.f;
+        const int kq = a.qk[qq];
+        // prune word of block row i (lanes 0..31) for this 32-query tile
+        uint32_t word = 0u;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             const int64_t blk = b0 + mfma32_row(r, l);
-            if (blk >= a.nblocks) continue;
+            const bool ok = qok && blk < a.nblocks;
             float dot = acc[g][r];
             if constexpr (MDT == DT_FP8B) dot *= qsc;
             float c = qn > 0.f ? dot / qn : 0.f;
             c = c > 1.f ? 1.f : (c < -1.f ? -1.f : c);
-            cphi[blk * a.nq + q] = c;
+            if (cphi && ok) cphi[blk * a.nq + q] = c;
+            if (a.prune) {
+                bool pr = false;
+                if (ok && qn > 0.f && a.block_ok[blk]) {
+                    const NodeBound nd = node_bound(c, qn, a.cos_w[blk], a.sin_w[blk], a.err_phi, a.bound_slack);
+                    pr = nd.ub < a.block_lb[(int64_t)(kq - 1) * a.nblocks + blk];
+                }
+                // bits 0..31: block row 8 (r / 4) + r % 4, bits 32..63: that row + 4
+                const uint64_t bal = ballot64(pr);
+                const int ra = ((r >> 2) << 3) + (r & 3);
+                if (l == ra) word = (uint32_t)bal;
+                if (l == ra + 4) word = (uint32_t)(bal >> 32);
+            }
         }
+        const int64_t T = (q0 + g * 32) >> 5;
+        if (a.prune && l < 32 && b0 + l < a.nblocks && T < a.ntq) a.prune[(b0 + l) * a.ntq + T] = word;
     }
 }
 
@@ -603,10 +1062,57 @@ static void verify_d(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
     }
 }
 
+bool verify_uses_ring(const QueryArgs& a)
+{
+    return (a.mma_dtype == DT_BF16 || a.mma_dtype == DT_FP8B) && (a.mma_ld == 128 || a.mma_ld == 256) &&
+           !(a.flags & RKMIPS_FLAG_VERIFY_SIMPLE);
+}
+
+template <int DT, int DPT>
+static void verify_ring_g(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
+{
+    const int64_t wgs = (a.m + VR_UPB - 1) / VR_UPB;
+    // the query range in chunks of whole tiles: enough workgroups to fill the chip in
+    // nearly whole rounds (two or three per compute unit), and per-lane counters that
+    // stay far below 2^32
+    constexpr int64_t kSlots = 256 * verify_ring_wpe<DT, DPT>();   // workgroups resident at once
+    const int64_t t0 = q0 >> 5, t1 = (q1 + 31) >> 5, nt = t1 - t0;
+    int64_t best = 1;
+    double best_cost = 1e300;
+    for (int64_t c = 1; c <= 4 && c <= nt; c++) {
+        // rounds of resident workgroups, each a chunk's tiles plus its prologue (user
+        // rows, lambda rows: about three tiles' time)
+        const double rounds = std::ceil((double)(wgs * c) / (double)kSlots);
+        const double cost = rounds * ((double)nt / (double)c + 3.0);
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = c;
+        }
+    }
+    int64_t per = (nt + best - 1) / best;
+    per = std::min<int64_t>(per, int64_t(1) << 15);
+    const int64_t nchunk = (nt + per - 1) / per;
+    if (wgs * nchunk > INT_MAX) fail(RKMIPS_EINVAL, "internal: verify grid too large");
+    hipLaunchKernelGGL((k_verify_ring<DT, DPT>), dim3((unsigned)(wgs * nchunk)), dim3(256), 0, s, a, q0, q1, per, wgs);
+}
+
 void launch_verify_range(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
 {
     if (q1 <= q0 || a.m <= 0) return;
     if (a.nslots > VF_MAXSLOT) fail(RKMIPS_EINVAL, "internal: too many distinct k in one launch");
+    if (verify_uses_ring(a)) {
+        if (a.ntq != (a.nq + 31) / 32 || a.ntq >= (int64_t(1) << 24))
+            fail(RKMIPS_EINVAL, "internal: prune-word table does not match the batch");
+        if (a.mma_dtype == DT_BF16) {
+            if (a.mma_ld == 128) verify_ring_g<DT_BF16, 128>(a, q0, q1, s);
+            else verify_ring_g<DT_BF16, 256>(a, q0, q1, s);
+        } else {
+            if (a.mma_ld == 128) verify_ring_g<DT_FP8B, 128>(a, q0, q1, s);
+            else verify_ring_g<DT_FP8B, 256>(a, q0, q1, s);
+        }
+        HIPC(hipGetLastError());
+        return;
+    }
     if (a.mma_dtype == DT_F32) verify_d<DT_F32>(a, q0, q1, s);
     else if (a.mma_dtype == DT_BF16) verify_d<DT_BF16>(a, q0, q1, s);
     else if (a.mma_dtype == DT_FP8B) verify_d<DT_FP8B>(a, q0, q1, s);

@@ -57,7 +57,7 @@ int64_t Workspace::bytes_for(const Index& x, int64_t nq, int64_t pool_cap, int64
 {
     const int64_t eb = elt_bytes(x.dtype);
     return nq * x.ld * eb + nq * 5 * 4 + (nq + 1) * 8 + pool_cap * (8 + 4 + 4) + amb_cap * 8 + 256 +
-           nq * x.nblocks * 4 + (x.mma_dtype != x.dtype ? nq * x.mma_ld * 2 : 0) +
+           nq * x.nblocks * 4 + ((nq + 31) / 32 + 1) * x.nblocks * 4 + (x.mma_dtype != x.dtype ? nq * x.mma_ld * 2 : 0) +
            (nq * ((x.m + 31) / 32) * 4 <= kBitmapBytes ? nq * ((x.m + 31) / 32) * 4 : 0);
 }
 
@@ -80,6 +80,7 @@ void Workspace::ensure(const Index& x, int64_t nq, int64_t pool_cap_req, int64_t
         qcnt.alloc(sizeof(int) * c);
         h_offsets.alloc(sizeof(int64_t) * (c + 1));
         cphi.alloc(sizeof(float) * (size_t)c * std::max<int64_t>(x.nblocks, 1));
+        prune.alloc(sizeof(uint32_t) * (size_t)((c + 31) / 32) * std::max<int64_t>(x.nblocks, 1));
         bm_words = (x.m + 31) / 32;
         if (c * bm_words * 4 <= kBitmapBytes) bitmap.alloc(sizeof(uint32_t) * (size_t)(c * bm_words));
         else bitmap.reset();
@@ -180,6 +181,7 @@ QueryArgs make_query_args(const Index& x, Workspace& w, int64_t nq, int flags)
     a.block_lb = x.block_lb.f(); a.nblocks = x.nblocks; a.perm = x.user_perm.u32();
     a.lam32 = x.lam32.f(); a.lam64 = x.lam64.d(); a.k_max = x.prm.k_max;
     a.queries = w.qpad.p; a.query_scales = w.qsc.f(); a.nq = nq; a.qnorm = w.qnorm.f(); a.cphi = w.cphi.f();
+    a.prune = w.prune.u32(); a.ntq = (nq + 31) / 32;
     const bool split = x.mma_dtype != x.dtype;
     a.mma_users = split ? x.users_mma.p : x.users.p;
     a.mma_queries = split ? w.qsplit.p : w.qpad.p;
@@ -224,7 +226,8 @@ void enqueue_batch(const Index& x, Workspace& w, const void* queries, const floa
         QueryArgs a = make_query_args(x, w, nq, flags);
         launch_qnorm(x.dtype, w.qpad.p, w.qsc.f(), nq, x.d, x.ld, w.qnorm.f(), a.bad, s);
         if (x.mma_dtype != x.dtype) launch_mma_operand(x.mma_dtype, x.dtype, w.qpad.p, nq, x.ld, w.qsplit.u16(), 0, s);
-        if (!(a.flags & RKMIPS_FLAG_NO_BOUNDS)) launch_phi(a, w.cphi.f(), s);
+        // the ring form of the verify pass reads the prune words only
+        if (!(a.flags & RKMIPS_FLAG_NO_BOUNDS)) launch_phi(a, verify_uses_ring(a) ? nullptr : w.cphi.f(), s);
         for (size_t g = 0; g < w.groups.size(); g++) {
             QueryArgs ag = a;
             ag.slot_k = w.slotk + kMaxSlots * g;

@@ -35,6 +35,7 @@ struct Workspace {
     int64_t bm_words = 0;
     bool bm_mode = false;                   // this batch uses the bits
     DevBuf cphi;                            // [nblocks x nq] query-centre cosines
+    DevBuf prune;                           // [nblocks x ceil(nq / 32)] Lemma 2 prune words
     DevBuf qsplit;                          // matrix-core query rows (split FP32 or widened FP8)
     DevBuf qcnt, ids2;                      // per-query counts, scatter target of the lists
     DevBuf sa_scratch, sa_answer, sa_phi;   // SA-ALSH stage

@@ -26,6 +26,7 @@ FLAG_NO_BOUNDS, FLAG_FORCE_RECHECK, FLAG_NO_SAALSH, FLAG_NO_CERT, FLAG_NO_VECTOR
 FLAG_SAALSH_FILTER = 32
 FLAG_F32_MATRIX = 64
 FLAG_POOL_LISTS = 128
+FLAG_VERIFY_SIMPLE = 256
 MODE_EXACT, MODE_SAH, MODE_LAZY = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "EBUSY"}
 

@@ -1,0 +1,118 @@
+"""The two forms of the verify pass (Alg. 5's block and inner-product tests over a query
+batch) take the same decisions.
+
+BF16 and FP8 indexes with padded rows of 128 or 256 values score a batch with the
+two-group ring kernel: query tiles at absolute positions, the per-query data and the
+Lemma 2 prune words staged in LDS by direct loads.  RKMIPS_FLAG_VERIFY_SIMPLE takes the
+one-group kernel instead.  Both must return the Definition 1 sets and, since they multiply
+the same operands in the same order and apply the same tests, report the same numbers of
+scored pairs and close calls.  Cases: user counts that are not a multiple of the 256-user
+workgroup, more than 8 distinct k (two launches whose boundary falls inside a 32-query
+tile), forced rechecks, bounds off, pool lists, the lazy exact mode, and clustered users
+on which Lemma 2 must prune."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_12751_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2211_12751_amd import rkmips
+    return rkmips
+
+
+def _same_lists(a, b, what):
+    assert len(a) == len(b)
+    for qi in range(len(a)):
+        assert np.array_equal(np.asarray(a[qi]), np.asarray(b[qi])), f"{what}: query {qi}"
+
+
+@pytest.mark.parametrize("dtype, d, n, m", [("bf16", 100, 600, 1000), ("bf16", 256, 500, 777),
+                                            ("fp8", 128, 600, 1300), ("fp8", 200, 400, 513)])
+def test_ring_and_simple_forms_agree(R, dtype, d, n, m):
+    w = I.make({"bf16": "c3", "fp8": "c5"}[dtype], n=n, m=m, d=d, nq=150, seed=300 + d)
+    k_max = 12
+    ks = (np.arange(150) % 12 + 1).astype(np.int32)   # 12 distinct k: two launches
+    srt = np.sort(ks)
+    assert int(np.searchsorted(srt, 9)) % 32 != 0     # their boundary is inside a tile
+    print(f"\n[case] verify ring vs simple dtype={dtype} d={d} n={n} m={m}", flush=True)
+    exact, _ = O.rkmips(dtype, w.items, w.item_scales, w.users, w.user_scales, w.queries, w.query_scales, ks,
+                        k_max)
+    idx = R.Index(w.items, w.item_scales, w.users, w.user_scales, dtype=dtype, k_max=k_max)
+    try:
+        for fl in (0, R.FLAG_FORCE_RECHECK, R.FLAG_NO_BOUNDS, R.FLAG_POOL_LISTS):
+            ring, st_r = idx.query(w.queries, w.query_scales, ks, flags=fl, stats=True)
+            simple, st_s = idx.query(w.queries, w.query_scales, ks, flags=fl | R.FLAG_VERIFY_SIMPLE, stats=True)
+            _same_lists(ring, exact, f"ring flags={fl}")
+            _same_lists(simple, exact, f"simple flags={fl}")
+            print(f"flags={fl} ring {st_r} simple {st_s}", flush=True)
+            for key in ("pairs_total", "pairs_block_pruned", "pairs_scored", "pairs_rechecked"):
+                assert st_r[key] == st_s[key], (fl, key)
+            if fl == R.FLAG_FORCE_RECHECK:
+                assert st_r["pairs_rechecked"] > 0
+    finally:
+        idx.close()
+
+
+def test_ring_form_in_lazy_mode(R):
+    """Lazy exact mode: every pair the inner-product test does not reject goes on to the
+    FP64 recheck and Alg. 2; both forms give the Definition 1 sets."""
+    w = I.make("c3", n=700, m=900, d=128, nq=40, seed=331)
+    ks = np.array([1, 5, 10, 20] * 10, np.int32)
+    print("\n[case] verify ring lazy mode bf16 d=128", flush=True)
+    exact, _ = O.rkmips("bf16", w.items, None, w.users, None, w.queries, None, ks, 20)
+    idx = R.Index(w.items, None, w.users, None, dtype="bf16", k_max=20, num_hash=64, mode=R.MODE_LAZY,
+                  sah_items=30, b=0.5, probe_frac=0.1)
+    try:
+        for fl in (0, R.FLAG_VERIFY_SIMPLE):
+            got = idx.query(w.queries, None, ks, flags=fl)
+            _same_lists(got, exact, f"lazy flags={fl}")
+    finally:
+        idx.close()
+
+
+def _clustered(seed, n=1800, m=2600, nq=90, d=128, nclusters=6, spread=0.02, outliers=0.03):
+    g = np.random.default_rng(seed)
+    cen = g.standard_normal((nclusters, d))
+    cen /= np.linalg.norm(cen, axis=1, keepdims=True)
+    lab = g.integers(0, nclusters, m)
+    U = cen[lab] + spread * g.standard_normal((m, d))
+    out = g.random(m) < outliers
+    U[out] = g.standard_normal((int(out.sum()), d))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    U *= np.exp(0.5 * g.standard_normal(m))[:, None]
+    P = g.standard_normal((n, d))
+    Q = g.standard_normal((nq, d))
+    return (I.bf16_bits(P.astype(np.float32)), I.bf16_bits(U.astype(np.float32)),
+            I.bf16_bits(Q.astype(np.float32)))
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_ring_form_prunes_with_lemma2_and_stays_exact(R, seed):
+    P, U, Q = _clustered(seed)
+    k_max = 10
+    ks = (np.arange(len(Q)) % k_max + 1).astype(np.int32)
+    print(f"\n[case] verify ring clustered bf16 seed={seed}", flush=True)
+    lam = O.lambda_table("bf16", P, None, U, None, k_max)
+    mem = O.member("bf16", U, None, Q, None, ks, lam)
+    idx = R.Index(P, None, U, None, dtype="bf16", k_max=k_max)
+    try:
+        got, st = idx.query(Q, None, ks, stats=True)
+        off, st_off = idx.query(Q, None, ks, flags=R.FLAG_NO_BOUNDS, stats=True)
+        simple, st_s = idx.query(Q, None, ks, flags=R.FLAG_VERIFY_SIMPLE, stats=True)
+        for qi in range(len(Q)):
+            assert np.array_equal(got[qi], np.flatnonzero(mem[qi])), qi
+        _same_lists(off, got, "bounds off")
+        _same_lists(simple, got, "simple form")
+        print(f"ring {st}\nsimple {st_s}", flush=True)
+        assert st["pairs_block_pruned"] > 0
+        assert st_off["pairs_block_pruned"] == 0
+        # the ring form stages the prune words of up to 64 blocks per workgroup, the
+        # simple form 32 per (smaller) workgroup: on 64-user leaves both see every block
+        assert st["pairs_block_pruned"] == st_s["pairs_block_pruned"]
+    finally:
+        idx.close()
