@@ -542,6 +542,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_ring
     __shared__ int br_s[VR_UPB];
     __shared__ unsigned long long ystage_all[4][VR_SW];
     __shared__ unsigned long long st_s[4];
+    __shared__ uint32_t doff_all[4][LPW][64];   // each lane's direct-load offsets (fixed)
 
     const int l = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (SGPR)
@@ -596,15 +597,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_ring
 
     // ---- direct loads: load j of this wave fills LDS bytes [k * 1024, (k + 1) * 1024) of
     // a slot, k = w * LPW + j; lane l writes 16 bytes at k * 1024 + 16 l, which is chunk
-    // (pos % CPR) of padded row pos / CPR (the padding chunk takes a copy of chunk 0)
-    const int pos0 = w * LPW * 64 + l;
-    auto doff = [&](int j) -> unsigned {
-        unsigned p0 = (unsigned)pos0;
-        asm volatile("" : "+v"(p0));
-        const unsigned pos = p0 + (unsigned)j * 64u;
+    // (pos % CPR) of padded row pos / CPR (the padding chunk takes a copy of chunk 0).
+    // The offsets are the same for every tile: kept in LDS, not in registers.
+#pragma unroll
+    for (int j = 0; j < LPW; j++) {
+        const unsigned pos = (unsigned)(w * LPW * 64 + l) + (unsigned)j * 64u;
         const unsigned c = pos % (unsigned)CPR;
-        return (pos / (unsigned)CPR) * (unsigned)ROWB + (c < (unsigned)(ROWB / 16) ? c : 0u) * 16u;
-    };
+        doff_all[w][j][l] = (pos / (unsigned)CPR) * (unsigned)ROWB + (c < (unsigned)(ROWB / 16) ? c : 0u) * 16u;
+    }
     auto issue = [&](uint8_t* ring, uint32_t* hq, int tt) {
         const int64_t T = T0 + tt;
         const int64_t r0 = T * 32;
@@ -612,9 +612,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_ring
         // rows past the launch's last query read as zeros
         const dma_rsrc rs = dma_buffer((const uint8_t*)a.mma_queries + r0 * ROWB, (uint32_t)(rows * ROWB));
         const uint32_t lb = RK_LDS_ADDR(ring);
+        // all offsets read before the first load: the loads' asm blocks order every later
+        // LDS read behind them
+        uint32_t dv[LPW];
+#pragma unroll
+        for (int j = 0; j < LPW; j++) dv[j] = doff_all[w][j][l];
 #pragma unroll
         for (int j = 0; j < LPW; j++)
-            if (w * LPW + j < NLD) dma_load16(rs, lb + (uint32_t)((w * LPW + j) * 1024), doff(j));
+            if (w * LPW + j < NLD) dma_load16(rs, lb + (uint32_t)((w * LPW + j) * 1024), dv[j]);
         if (w == 0) {
             const uint32_t hb = RK_LDS_ADDR(hq);
             const uint32_t qb4 = (uint32_t)(rows * 4);

@@ -520,6 +520,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     __shared__ __attribute__((aligned(256))) float sc2[dt_scaled<DT> ? 64 : 1];
     __shared__ int hist_all[TK_WAVES][MODE == TK_MAIN ? 256 : 1];
     __shared__ uint32_t stage_all[TK_WAVES][SGPL * 64];
+    __shared__ uint32_t doff_all[TK_WAVES][LPW][64];   // each lane's direct-load offsets
 
     const int l = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (SGPR)
@@ -607,18 +608,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 
     // ---- DMA map: load j of this wave fills LDS bytes [k * 1024, (k + 1) * 1024) of a
     // slot, k = w * LPW + j; lane l writes 16 bytes at k * 1024 + 16 l, which is chunk
-    // (pos % CPR) of padded row pos / CPR (the padding chunk takes a dummy copy of chunk 0)
-    // byte offset of load j's 16 bytes for this lane within the tile's rows
-    const int pos0 = w * LPW * 64 + l;
-    auto doff = [&](int j) -> unsigned {
-        // recomputed per tile: kept live across the loop they would cost registers
-        // (unsigned: the division by the constant CPR is a multiply-high and a shift)
-        unsigned p0 = (unsigned)pos0;
-        asm volatile("" : "+v"(p0));
-        const unsigned pos = p0 + (unsigned)j * 64u;
+    // (pos % CPR) of padded row pos / CPR (the padding chunk takes a dummy copy of chunk 0).
+    // The byte offsets of a lane's loads within the tile's rows are the same for every
+    // tile: computed once into LDS (in registers they would cost five VGPRs, recomputed
+    // per tile about forty vector instructions; unsigned: the division by the constant
+    // CPR is a multiply-high and a shift)
+#pragma unroll
+    for (int j = 0; j < LPW; j++) {
+        const unsigned pos = (unsigned)(w * LPW * 64 + l) + (unsigned)j * 64u;
         const unsigned c = pos % (unsigned)CPR;
-        return (pos / (unsigned)CPR) * (unsigned)ROWB + (c < (unsigned)(ROWB / 16) ? c : 0u) * 16u;
-    };
+        doff_all[w][j][l] = (pos / (unsigned)CPR) * (unsigned)ROWB + (c < (unsigned)(ROWB / 16) ? c : 0u) * 16u;
+    }
     auto issue = [&](uint8_t* ring, float* sc, int tt) {
         const int r0 = tt * IT;
         const int rows = seg_rows - r0 < IT ? seg_rows - r0 : IT;
@@ -627,9 +627,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             // loads past its last row read zeros
             const u32x4 rs = tk_rsrc((const uint8_t*)a.items + (seg0 + r0) * ROWB, (uint32_t)(rows * ROWB));
             const uint32_t lbase = (uint32_t)(uintptr_t)TK_LDS(ring);
+            // all offsets read before the first load: the loads' asm blocks order every
+            // later LDS read behind them
+            uint32_t dv[LPW];
+#pragma unroll
+            for (int j = 0; j < LPW; j++) dv[j] = doff_all[w][j][l];
 #pragma unroll
             for (int j = 0; j < LPW; j++) {
-                if (w * LPW + j < NLD) tk_dma16(rs, lbase + (uint32_t)((w * LPW + j) * 1024), doff(j));
+                if (w * LPW + j < NLD) tk_dma16(rs, lbase + (uint32_t)((w * LPW + j) * 1024), dv[j]);
             }
             if constexpr (dt_scaled<DT>) {
                 if (w == 0) {
