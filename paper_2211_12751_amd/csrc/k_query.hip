@@ -504,6 +504,16 @@ __device__ __forceinline__ void ring_block(const uint8_t* tile, const i32x4 (&bf
         for (int g = 0; g < 2; g++)
             acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, __builtin_bit_cast(bf16x8, bfrag[g][t]), acc[g], 0, 0, 0);
     }
+    // schedule: the first three fragment reads, then per k-step two products and the read
+    // three steps ahead (left alone, the scheduler keeps two reads in flight and each pair
+    // of k-steps waits for LDS)
+    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+#pragma unroll
+    for (int t = 0; t < KSTEPS - 3; t++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
 }
 
 // Two waves per SIMD: at three, the 168-register budget makes the compiler spill, and a

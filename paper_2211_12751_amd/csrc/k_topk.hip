@@ -161,6 +161,18 @@ __device__ __forceinline__ void mfma_block(const uint8_t* tile, int row0, const 
             static_assert(dt_bf16_mma<DT>, "FP8 codes reach the matrix cores widened to BF16");
         }
     }
+    if constexpr (dt_bf16_mma<DT> && NG == 2 && KSTEPS >= 4) {
+        // schedule: three fragment reads ahead, then per k-step two products and the read
+        // three steps ahead (left alone, the scheduler keeps two reads in flight, and each
+        // pair of k-steps waits for LDS)
+        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+#pragma unroll
+        for (int t = 0; t < KSTEPS - 3; t++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
+    }
 }
 
 // Two modes over the same matrix-core pipeline (see the file comment).  A wave owns NG
