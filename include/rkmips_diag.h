@@ -26,6 +26,16 @@ extern "C" {
 rkmips_status rkmips_diag_mma_probe(int32_t kind, const uint8_t *a_codes, const uint8_t *b_codes, int32_t k,
                                     float *c_out);
 
+/* OCP e4m3 decoding with the hardware conversion instruction (v_cvt_pk_f32_fp8, two codes
+ * per instruction), which the canonical FP8 rescoring of the lambda build uses: every e4m3
+ * value is exact in FP32, so the conversion must reproduce the format's definition (sign,
+ * four exponent bits with bias 7, three mantissa bits, subnormals m 2^-9, codes 0x7f and
+ * 0xff NaN).  codes: host uint8 [n]; out: host float [n], out[i] the value of codes[i].
+ * n a multiple of 4 in [4, 2^20].  The caller owns both arrays.  Synchronous on the
+ * current device's default stream; allocates and frees its own device buffers.
+ * Errors: EINVAL (NULL pointer, bad n), EDEVICE. */
+rkmips_status rkmips_diag_fp8_decode(const uint8_t *codes, int32_t n, float *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -794,6 +794,11 @@ rkmips_status rkmips_diag_mma_probe(int32_t kind, const uint8_t* a_codes, const 
     return guarded([&] { mma_probe(kind, a_codes, b_codes, k, c_out); });
 }
 
+rkmips_status rkmips_diag_fp8_decode(const uint8_t* codes, int32_t n, float* out)
+{
+    return guarded([&] { fp8_decode(codes, n, out); });
+}
+
 rkmips_status rkmips_build_index(const void* items, const float* item_scales, int64_t n, const void* users,
                                  const float* user_scales, int64_t m, int32_t d, int32_t dtype,
                                  const float* srp_proj, const rkmips_params* p, void* stream,

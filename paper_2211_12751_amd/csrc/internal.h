@@ -89,6 +89,7 @@ struct RefineArgs {
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s);
 // Matrix-core accumulation probe (k_diag.hip): host arrays, synchronous.
 void mma_probe(int kind, const uint8_t* a_host, const uint8_t* b_host, int K, float* c_host);
+void fp8_decode(const uint8_t* codes_host, int n, float* out_host);
 // Full FP64 rescoring of the users in fail_list (device count at fail_count, host copy nfail).
 void launch_fallback(int dtype, const RefineArgs& a, double* scratch, int64_t scratch_rows, hipStream_t s);
 

@@ -1,4 +1,4 @@
-// Matrix-core accumulation probe.  The library's fast scores assume that a matrix-core
+// Hardware diagnostics.  Matrix-core accumulation probe.  The library's fast scores assume that a matrix-core
 // product accumulates like FP32 arithmetic (the error model of the fast decisions and of
 // the lambda certificate); this probe measures one 32 x 32 block of products of e4m3
 // codes on the FP8 matrix cores (codes as they are) and on the BF16 matrix cores (codes
@@ -13,6 +13,7 @@
 namespace rk {
 
 typedef long fp8x8;   // eight e4m3 codes, one matrix-core operand register pair
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // C[i][j] = sum_k A[i][k] B[j][k] for i, j < 32 over K (a multiple of 16), one wave.
 // Lane l supplies row l % 32 of each operand, elements [8 (l / 32), 8 (l / 32) + 8) of
@@ -69,6 +70,40 @@ void mma_probe(int kind, const uint8_t* a_host, const uint8_t* b_host, int K, fl
     (void)hipFree(a);
     (void)hipFree(b);
     (void)hipFree(c);
+    HIPC(e);
+}
+
+// e4m3 decoding with the hardware conversion (v_cvt_pk_f32_fp8, two codes per instruction):
+// word i holds codes 4i .. 4i + 3 in byte order; out[4i + j] = value of code j of word i.
+__global__ __launch_bounds__(256) void k_fp8_decode(const uint32_t* w, int64_t nw, float* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+    const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
+    out[4 * i + 0] = lo[0];
+    out[4 * i + 1] = lo[1];
+    out[4 * i + 2] = hi[0];
+    out[4 * i + 3] = hi[1];
+}
+
+void fp8_decode(const uint8_t* codes_host, int n, float* out_host)
+{
+    if (!codes_host || !out_host) fail(RKMIPS_EINVAL, "null pointer");
+    if (n < 4 || n > (1 << 20) || n % 4 != 0) fail(RKMIPS_EINVAL, "n must be a multiple of 4 in [4, 2^20]");
+    uint32_t* w = nullptr;
+    float* out = nullptr;
+    hipError_t e = hipMalloc(&w, (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&out, sizeof(float) * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpy(w, codes_host, (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        const int64_t nw = n / 4;
+        hipLaunchKernelGGL(k_fp8_decode, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, 0, w, nw, out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out_host, out, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost);
+    (void)hipFree(w);
+    (void)hipFree(out);
     HIPC(e);
 }
 

@@ -129,17 +129,23 @@ __device__ __forceinline__ double canon_chunk(const i32x4& a4, const i32x4& b4, 
 // values as floats, shared by the wave), the item's from its codes.  Two e4m3 values
 // multiply exactly in FP32 (at most 8 significant bits, magnitudes in [2^-18, 2^18]),
 // so acc + (double)(x y) is the canonical step RN(acc + x y), bit for bit.
+// The item codes are decoded by the hardware conversion (two codes per instruction; every
+// e4m3 value is exact in FP32, and rkmips_diag_fp8_decode checks the conversion against
+// the format's definition code by code).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double canon_chunk_fp8(const float* ux, const i32x4& b4, int c0, int d, double acc)
 {
     const int lim = d - c0 < 16 ? d - c0 : 16;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const f32x4 x4 = *(const f32x4*)(ux + c0 + 4 * q);
+        const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(b4[q], false);   // bytes 0, 1
+        const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(b4[q], true);    // bytes 2, 3
+        const float y[4] = {lo[0], lo[1], hi[0], hi[1]};
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             if (4 * q + e >= lim) break;
-            const float y = e4m3_to_f32((uint8_t)((uint32_t)b4[q] >> (8 * e)));
-            acc = acc + (double)(x4[e] * y);
+            acc = acc + (double)(x4[e] * y[e]);
         }
     }
     return acc;
@@ -304,6 +310,51 @@ __device__ bool refine_select(const RefineArgs& a, int64_t u, uint32_t* skey, ui
 //   max(tau_max, cut) + eps(u) <= lambda64^(k_max)
 // where every item outside the rescored set scored at most max(tau_max, cut) in the fast
 // arithmetic.
+// Bitonic sort of 64 * NPL (score, slot) pairs held NPL per lane (element i = 64 s + lane
+// in v[s], ix[s]) into descending score order, equal scores by ascending slot; pairs that
+// are 64 apart or more meet inside a lane, the others across lanes by shuffles.
+template <int NPL>
+__device__ __forceinline__ void wave_sort_desc(double (&v)[4], int (&ix)[4])
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int kk = 2; kk <= 64 * NPL; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+#pragma unroll
+                for (int s = 0; s < NPL; s++) {
+                    const int p = s ^ (j >> 6);
+                    if (p > s) {
+                        const bool desc = ((64 * s + l) & kk) == 0;
+                        const bool first = v[s] > v[p] || (v[s] == v[p] && ix[s] < ix[p]);
+                        if (first != desc) {
+                            const double tv = v[s];
+                            v[s] = v[p];
+                            v[p] = tv;
+                            const int ti = ix[s];
+                            ix[s] = ix[p];
+                            ix[p] = ti;
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NPL; s++) {
+                    const double ov = __shfl_xor(v[s], j);
+                    const int oi = __shfl_xor(ix[s], j);
+                    const bool lower = (l & j) == 0, desc = ((64 * s + l) & kk) == 0;
+                    const bool mine_first = v[s] > ov || (v[s] == ov && ix[s] < oi);
+                    if (mine_first != (lower == desc)) {
+                        v[s] = ov;
+                        ix[s] = oi;
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <int DT, bool FAST>
 __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey, const uint32_t* sid, int Nk,
                             float cut, float tau_max, double* s64, double* lam_row, uint8_t* rows, float* udec)
@@ -348,34 +399,35 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
         }
         lk = a.k_max <= 64 ? __shfl(v, a.k_max - 1) : -__builtin_inf();
     } else if constexpr (!FAST) {
-        // 64 candidates at a time through the staged dot products
+        // 64 candidates at a time through the staged dot products, then a bitonic sort of
+        // the scores (padded with -inf to 128 or 256) across the wave: sorted position r
+        // (ties: earlier slot first) holds lambda^(r+1)
         for (int j0 = 0; j0 < Nk; j0 += 64) {
-            const double v = canon_dot_staged<DT>(a, u, su, sid + j0, Nk - j0, rows, udec);
+            const double x = canon_dot_staged<DT>(a, u, su, sid + j0, Nk - j0, rows, udec);
             if (j0 + l < Nk) {
-                s64[j0 + l] = v;
-                worst_raw = fmax(worst_raw, rel(v, (double)ord_f32(skey[j0 + l])));
+                s64[j0 + l] = x;
+                worst_raw = fmax(worst_raw, rel(x, (double)ord_f32(skey[j0 + l])));
             }
         }
         __builtin_amdgcn_wave_barrier();
-        // rank of each score among all Nk (ties: earlier slot first); the entry of rank
-        // r < k_max is lambda^(r+1), written by the lane that holds it
-        for (int j = l; j < Nk; j += 64) {
-            const double x = s64[j];
-            int r64 = 0;
-            for (int i = 0; i < Nk; i++) {
-                const double xi = s64[i];
-                r64 += (xi > x) || (xi == x && i < j);
-            }
-            if (r64 < a.k_max) {
-                a.lam64[(int64_t)r64 * a.m + u] = x;
-                a.lam32[(int64_t)r64 * a.m + u] = (float)x;
-                worst32 = fmax(worst32, rel(x, (double)(float)x));
-                if (r64 == a.k_max - 1) lam_row[0] = x;
-            }
+        double v[4];
+        int ix[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; s4++) {
+            ix[s4] = 64 * s4 + l;
+            v[s4] = ix[s4] < Nk ? s64[ix[s4]] : -__builtin_inf();
         }
-        for (int r = Nk + l; r < a.k_max; r += 64) {
-            a.lam64[(int64_t)r * a.m + u] = -__builtin_inf();
-            a.lam32[(int64_t)r * a.m + u] = -__builtin_inff();
+        if (Nk <= 128) wave_sort_desc<2>(v, ix);
+        else wave_sort_desc<4>(v, ix);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; s4++) {
+            const int r = 64 * s4 + l;
+            if (r < a.k_max) {
+                a.lam64[(int64_t)r * a.m + u] = v[s4];
+                a.lam32[(int64_t)r * a.m + u] = (float)v[s4];
+                if (r < Nk) worst32 = fmax(worst32, rel(v[s4], (double)(float)v[s4]));
+                if (r == a.k_max - 1) lam_row[0] = v[s4];
+            }
         }
         __builtin_amdgcn_wave_barrier();
         lk = Nk >= a.k_max ? lam_row[0] : -__builtin_inf();

@@ -113,6 +113,7 @@ _sig = {
     "rkmips_index_load": (C.c_int, [C.c_char_p, _P, C.POINTER(_P)]),
     "rkmips_last_error": (C.c_char_p, []),
     "rkmips_diag_mma_probe": (C.c_int, [C.c_int32, _P, _P, C.c_int32, _P]),
+    "rkmips_diag_fp8_decode": (C.c_int, [_P, C.c_int32, _P]),
     "rkmips_serve_replay": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, C.POINTER(rkmips_serve_params), _P,
                                       C.POINTER(rkmips_serve_stats), C.POINTER(_P)]),
 }
@@ -335,6 +336,14 @@ def rkmips_diag_mma_probe(kind, a_codes, b_codes):
         raise ValueError("a_codes and b_codes must both be [32 x K]")
     out = np.empty((32, 32), np.float32)
     _check(_lib.rkmips_diag_mma_probe(int(kind), _ptr(a), _ptr(b), int(a.shape[1]), _ptr(out)))
+    return out
+
+
+def rkmips_diag_fp8_decode(codes):
+    """e4m3 codes decoded by the hardware conversion instruction: float32 [n]."""
+    c = np.ascontiguousarray(codes, dtype=np.uint8).ravel()
+    out = np.empty(c.shape[0], np.float32)
+    _check(_lib.rkmips_diag_fp8_decode(_ptr(c), int(c.shape[0]), _ptr(out)))
     return out
 
 

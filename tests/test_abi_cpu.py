@@ -224,3 +224,14 @@ def test_mma_probe_rejects_bad_arguments(R):
     a[0, 0] = 0x7f
     with pytest.raises(R.RkmipsError):
         R.rkmips_diag_mma_probe(1, a, a)          # NaN code
+
+
+def test_fp8_decode_probe_rejects_bad_arguments(R):
+    """The hardware-conversion probe validates on the host before any device call."""
+    with pytest.raises(R.RkmipsError) as e:
+        R.rkmips_diag_fp8_decode(np.zeros(6, np.uint8))      # n not a multiple of 4
+    assert e.value.status == -1
+    with pytest.raises(R.RkmipsError):
+        R.rkmips_diag_fp8_decode(np.zeros(0, np.uint8))      # empty
+    out = np.zeros(4, np.float32)
+    assert R._lib.rkmips_diag_fp8_decode(None, 4, out.ctypes.data) == -1

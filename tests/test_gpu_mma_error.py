@@ -66,3 +66,20 @@ def test_bf16_matrix_cores_accumulate_like_fp32_and_fp8_measured(pattern):
     print(f"[mma] {pattern}: max |c - S| / sum|terms|  BF16 path {worst_bf16:.3e} ({lg(worst_bf16)})  "
           f"FP8 path {worst_fp8:.3e} ({lg(worst_fp8)})  model bound {bound:.3e} ({lg(bound)})", flush=True)
     assert worst_bf16 <= bound
+
+
+def test_hardware_fp8_conversion_decodes_ocp_e4m3():
+    """The canonical FP8 rescoring decodes item codes with the hardware conversion: every
+    code (each in all four byte positions of a word) must give the format's value, and the
+    two NaN codes NaN."""
+    from paper_2211_12751_amd import rkmips as R
+    print("\n[case] fp8 hardware decode, 256 codes x 4 byte positions", flush=True)
+    codes = np.arange(256, dtype=np.uint8)
+    words = np.stack([np.roll(codes, s) for s in range(4)], axis=1).ravel()   # every code at every position
+    got = R.rkmips_diag_fp8_decode(words).astype(np.float64)
+    want = O._fp8_codes_f64(words)
+    nan = (words & 0x7f) == 0x7f
+    assert np.all(np.isnan(got[nan]))
+    assert np.array_equal(got[~nan], want[~nan])
+    # signed zeros keep their sign
+    assert np.signbit(got[words == 0x80]).all() and not np.signbit(got[words == 0x00]).any()

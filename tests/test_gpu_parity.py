@@ -104,6 +104,26 @@ def test_toggles_give_identical_sets(R):
         idx3.close()
 
 
+@pytest.mark.parametrize("cfg, d, k_max", [("c2", 64, 120), ("c3", 100, 120), ("c5", 128, 100),
+                                           ("c3", 64, 200), ("c5", 200, 210)])
+def test_wide_refine_with_tied_scores(R, cfg, d, k_max):
+    """C = k_max + slack above 64: the rescoring runs 64 candidates at a time and ranks up
+    to 128 or 256 canonical scores with a sort across the wave.  Every item appears twice,
+    so equal canonical scores occur throughout the lambda rows; the table must equal
+    Definition 1's bit for bit."""
+    w = I.make(cfg, n=380, m=900, d=d, nq=4, seed=k_max + d)
+    items = np.concatenate([w.items, w.items[::-1]])
+    isc = None if w.item_scales is None else np.concatenate([w.item_scales, w.item_scales[::-1]])
+    print(f"\n[case] wide refine {cfg} dtype={w.dtype} n={len(items)} m={w.m} d={d} k_max={k_max}", flush=True)
+    lam = O.lambda_table(w.dtype, items, isc, w.users, w.user_scales, k_max)
+    idx = R.Index(items, isc, w.users, w.user_scales, dtype=w.dtype, k_max=k_max)
+    try:
+        assert idx.info["cert_failures"] < w.m   # the certified path ran
+        _check_lambda(idx, lam, k_max)
+    finally:
+        idx.close()
+
+
 @pytest.mark.parametrize("n,m,d,k_max", [(7, 33, 20, 10), (1, 1, 1, 1), (300, 777, 64, 50), (129, 257, 100, 16)])
 def test_ragged_and_degenerate_shapes(R, n, m, d, k_max):
     w = I.make("c2", n=n, m=m, d=d, nq=45, seed=n + m)

@@ -138,6 +138,43 @@ def test_lazy_mode_is_exact(R, dtype, n, m, d, n_prime, flags):
         idx.close()
 
 
+def test_lazy_mode_near_ties_with_the_norm_test(R):
+    """Users that are power-of-two multiples of the largest-norm items, and queries equal to
+    those items or one ulp away from them: s(u,q) sits at or next to ||u|| ||p_k||, where the
+    lazy mode's norm test (Alg. 5) must not answer yes on rounding alone.  The sets must
+    still be the Definition 1 sets."""
+    g = np.random.default_rng(515)
+    n, d = 300, 16
+    P = g.standard_normal((n, d)).astype(np.float32)
+    P *= np.exp(0.4 * g.standard_normal(n)).astype(np.float32)[:, None]
+    top = np.argsort(-np.einsum("ij,ij->i", P.astype(np.float64), P.astype(np.float64)), kind="stable")[:6]
+    users = [P[top[j]] * np.float32(2.0 ** e) for j in range(6) for e in (-3, -1, 0, 2)]
+    users = np.concatenate([np.stack(users), g.standard_normal((200, d)).astype(np.float32)])
+    qs = []
+    for j in range(6):
+        base = P[top[j]]
+        qs.append(base.copy())
+        for sgn in (1.0, -1.0):
+            q = base.copy()
+            i = int(np.argmax(np.abs(q)))
+            q[i] = np.nextafter(q[i], np.float32(sgn * np.inf))
+            qs.append(q)
+    Q = np.stack(qs).astype(np.float32)
+    ks = np.array([1, 2, 3, 5, 1, 2] * 3, np.int32)[:len(Q)]
+    print("\n[case] lazy near ties with the norm test", flush=True)
+    exact, _ = O.rkmips("f32", P, None, users, None, Q, None, ks, 5)
+    idx = R.Index(P, None, users, None, dtype="f32", k_max=5, num_hash=64, mode=R.MODE_LAZY,
+                  sah_items=3, b=0.5, probe_frac=0.1)
+    try:
+        got, st = idx.query(Q, None, ks, stats=True)
+        for qi in range(len(ks)):
+            assert np.array_equal(np.asarray(got[qi]), exact[qi]), f"query {qi}"
+        print(f"stats {st}", flush=True)
+        assert st["saalsh_checked"] > 0
+    finally:
+        idx.close()
+
+
 def test_sah_small_p_prime_empty_batch_and_serving(R):
     """|P'| = 5 < k for most queries (L_u^k = -inf there, so every user reaches the norm
     test and Alg. 2 starts with phi = -inf), an empty batch, and the continuous-batching
