@@ -15,14 +15,15 @@ extern "C" {
 #endif
 
 /* One 32 x 32 block C[i][j] = sum_k A[i][k] B[j][k] of OCP e4m3 codes over k < K, on
- * the FP8 matrix cores (kind 1: v_mfma_f32_32x32x16_fp8_fp8 on the codes) or on the
+ * the FP8 matrix cores (kind 1: v_mfma_f32_32x32x16_fp8_fp8 on the codes; kind 2:
+ * v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales, K a multiple of 64) or on the
  * BF16 matrix cores (kind 0: the codes widened to BF16, which is exact, and
- * v_mfma_f32_32x32x16_bf16), FP32 accumulation in both, K / 16 instructions in index
- * order.  a_codes, b_codes: host uint8 [32 x K] row-major; c_out: host float [32 x 32]
+ * v_mfma_f32_32x32x16_bf16), FP32 accumulation in all, K / 16 (K / 64) instructions in
+ * index order.  a_codes, b_codes: host uint8 [32 x K] row-major; c_out: host float [32 x 32]
  * row-major (row of A, row of B).  The caller owns every array.  Synchronous on the
  * current device's default stream; allocates and frees its own device buffers.
- * Errors: EINVAL (kind not 0/1, K not a multiple of 16 in [16, 4096], a NULL pointer,
- * a NaN code), EDEVICE. */
+ * Errors: EINVAL (kind not 0/1/2, K not a multiple of 16 in [16, 4096] (of 64 for kind
+ * 2), a NULL pointer, a NaN code), EDEVICE. */
 rkmips_status rkmips_diag_mma_probe(int32_t kind, const uint8_t *a_codes, const uint8_t *b_codes, int32_t k,
                                     float *c_out);
 

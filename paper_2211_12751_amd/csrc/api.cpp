@@ -273,18 +273,27 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
     HIPC(hipEventRecord(L.ev.ev[0], s));
     if (x.ns > 0) {   // per-user threshold estimates from the item sample
         L.theta.alloc(sizeof(float) * (size_t)m);
+        // FP8 rows of 256 codes: the estimate runs on the FP8 matrix cores with the codes as
+        // they are (half the matrix-core time; the estimate needs no error bound, as the
+        // certificate does not depend on it); otherwise on the main pass's operand form
+        const bool f8 = x.dtype == RKMIPS_FP8_E4M3 && x.ld == 256;
+        const int sdt = f8 ? DT_FP8 : tdt, sld = f8 ? x.ld : tld;
         // the sample's rows gathered first, so that the pass streams contiguous tiles
-        L.sample.alloc((size_t)x.ns * topk_row_bytes(tdt, tld));
+        L.sample.alloc((size_t)x.ns * topk_row_bytes(sdt, sld));
         if (x.item_scales.p) L.sample_sc.alloc(sizeof(float) * (size_t)x.ns);
-        launch_gather_sample(tdt, mi, x.item_scales.f(), x.n_lam, x.ns, tld, L.sample.p,
+        launch_gather_sample(sdt, f8 ? x.items.p : mi, x.item_scales.f(), x.n_lam, x.ns, sld, L.sample.p,
                              x.item_scales.p ? L.sample_sc.f() : nullptr, s);
         TopkArgs a0 = ta;
+        if (f8) {
+            a0.users = users_o.p;
+            a0.ld = sld;
+        }
         a0.items = L.sample.p;
         a0.item_scales = x.item_scales.p ? L.sample_sc.f() : nullptr;
         a0.n = x.ns;
         a0.ns = x.ns; a0.v0 = 0; a0.v1 = x.ns; a0.nseg = 1; a0.seg_base = 0; a0.seg_len = x.ns;
         a0.theta_out = L.theta.f();
-        launch_topk_seed(tdt, a0, s);
+        launch_topk_seed(sdt, a0, s);
     }
     before_main();
     HIPC(hipEventRecord(L.ev.ev[3], s));

@@ -14,6 +14,9 @@ namespace rk {
 
 typedef long fp8x8;   // eight e4m3 codes, one matrix-core operand register pair
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+// E8M0 block scale 2^(127 - 127) = 1 for the scaled FP8 matrix-core instruction
+constexpr int kUnitScale = 127;
 
 // C[i][j] = sum_k A[i][k] B[j][k] for i, j < 32 over K (a multiple of 16), one wave.
 // Lane l supplies row l % 32 of each operand, elements [8 (l / 32), 8 (l / 32) + 8) of
@@ -24,6 +27,26 @@ __global__ __launch_bounds__(64) void k_mma_probe(const uint8_t* A, const uint8_
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[r] = 0.f;
+    if (kind == 2) {
+        // 32x32x64 steps: lane l supplies 32 codes of row l % 32, bytes [32 (l / 32), +32)
+        // of every 64-wide k step, the same for both operands (any order the instruction
+        // gives those bytes applies to both, so the sum covers every k once); unit scales
+        for (int k0 = 0; k0 < K; k0 += 64) {
+            const uint8_t* ar = A + (int64_t)(l & 31) * K + k0 + 32 * (l >> 5);
+            const uint8_t* br = B + (int64_t)(l & 31) * K + k0 + 32 * (l >> 5);
+            i32x8 a, b;
+            for (int e = 0; e < 8; e++) {
+                a[e] = (int)((uint32_t)ar[4 * e] | ((uint32_t)ar[4 * e + 1] << 8) | ((uint32_t)ar[4 * e + 2] << 16) |
+                             ((uint32_t)ar[4 * e + 3] << 24));
+                b[e] = (int)((uint32_t)br[4 * e] | ((uint32_t)br[4 * e + 1] << 8) | ((uint32_t)br[4 * e + 2] << 16) |
+                             ((uint32_t)br[4 * e + 3] << 24));
+            }
+            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, kUnitScale, 0, kUnitScale);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; r++) C[mfma32_row(r, l) * 32 + (l & 31)] = acc[r];
+        return;
+    }
     for (int k0 = 0; k0 < K; k0 += 16) {
         const uint8_t* ar = A + (int64_t)(l & 31) * K + k0 + 8 * (l >> 5);
         const uint8_t* br = B + (int64_t)(l & 31) * K + k0 + 8 * (l >> 5);
@@ -49,8 +72,9 @@ __global__ __launch_bounds__(64) void k_mma_probe(const uint8_t* A, const uint8_
 
 void mma_probe(int kind, const uint8_t* a_host, const uint8_t* b_host, int K, float* c_host)
 {
-    if (kind != 0 && kind != 1) fail(RKMIPS_EINVAL, "kind must be 0 (BF16) or 1 (FP8)");
+    if (kind < 0 || kind > 2) fail(RKMIPS_EINVAL, "kind must be 0 (BF16), 1 (FP8) or 2 (FP8, K = 64 steps)");
     if (K < 16 || K > 4096 || K % 16 != 0) fail(RKMIPS_EINVAL, "K must be a multiple of 16 in [16, 4096]");
+    if (kind == 2 && K % 64 != 0) fail(RKMIPS_EINVAL, "kind 2 needs K a multiple of 64");
     if (!a_host || !b_host || !c_host) fail(RKMIPS_EINVAL, "null pointer");
     for (int i = 0; i < 32 * K; i++)
         if ((a_host[i] & 0x7f) == 0x7f || (b_host[i] & 0x7f) == 0x7f) fail(RKMIPS_EINVAL, "NaN code");

@@ -157,8 +157,25 @@ __device__ __forceinline__ void mfma_block(const uint8_t* tile, int row0, const 
                     acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[g], 0, 0, 0);
                 }
             }
+        } else if constexpr (DT == DT_FP8) {
+            // e4m3 codes as they are, 64-wide k steps (two 32-byte units t, t + 1): lane
+            // half h supplies bytes [64 s + 32 h, + 32) of step s, for both operands, so the
+            // instruction pairs every k once whatever order it gives those bytes; unit
+            // scales.  Only the seed pass, an estimate, runs here: its sums carry the FP8
+            // matrix cores' own rounding, outside the fast-score error model.
+            if ((t & 1) == 0) {
+                const uint8_t* a8 = tile + (row0 + (l & 31)) * LROW + h * 32 + (t >> 1) * 64;
+                const i32x4 a0 = *(const i32x4*)a8, a1 = *(const i32x4*)(a8 + 16);
+                const i32x8 av = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+#pragma unroll
+                for (int g = 0; g < NG; g++) {
+                    const i32x4 b0 = bfrag[g][t], b1 = bfrag[g][t + 1];
+                    const i32x8 bv = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+                    acc[g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[g], 0, 0, 0, 127, 0, 127);
+                }
+            }
         } else {
-            static_assert(dt_bf16_mma<DT>, "FP8 codes reach the matrix cores widened to BF16");
+            static_assert(dt_bf16_mma<DT>, "unsupported matrix-core operand");
         }
     }
     if constexpr (dt_bf16_mma<DT> && NG == 2 && KSTEPS >= 4) {
@@ -469,7 +486,7 @@ constexpr int topk_ng()
     // LDS reads per product halve; the two groups' resident fragments (KSTEPS i32x4 each)
     // must fit in 128 VGPRs.  Shorter rows keep one group and twice the workgroups.
     constexpr int rowb = DPT * Elt<DT>::bytes;
-    return rowb >= 512 && (rowb / 32) * 4 * 2 <= 128 ? 2 : 1;
+    return (rowb >= 512 || DT == DT_FP8) && (rowb / 32) * 4 * 2 <= 128 ? 2 : 1;
 }
 
 // Direct (DMA) load of 16 (or 4) bytes per lane into LDS at lds + 16 * lane (4 * lane),
@@ -564,7 +581,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #pragma unroll
         for (int t = 0; t < KSTEPS; t++) {
             i32x4 z = {0, 0, 0, 0};
-            bfrag[g][t] = uok ? *(const i32x4*)(row + t * 32 + h * 16) : z;
+            // BF16 forms: unit t is bytes [32 t + 16 h, + 16); FP8 codes: units t, t + 1 (t
+            // even) are the 32 bytes [64 (t / 2) + 32 h, + 32) of a 64-wide k step
+            const int fo = DT == DT_FP8 ? (t >> 1) * 64 + h * 32 + (t & 1) * 16 : t * 32 + h * 16;
+            bfrag[g][t] = uok ? *(const i32x4*)(row + fo) : z;
         }
         theta[g] = -__builtin_inff();
         if (MODE == TK_MAIN && uok && a.theta_init) theta[g] = a.theta_init[ug * a.theta_stride];
@@ -575,7 +595,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             if (su[g] < 0.f) {
                 su[g] = -su[g];
 #pragma unroll
-                for (int t = 0; t < KSTEPS; t++) bfrag[g][t] ^= (int)0x80008000u;
+                for (int t = 0; t < KSTEPS; t++) bfrag[g][t] ^= (int)(DT == DT_FP8 ? 0x80808080u : 0x80008000u);
             }
         }
     }
@@ -841,7 +861,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 template <int DT, int DPT>
 constexpr bool topk_ring()
 {
-    return DPT * Elt<DT>::bytes >= 512;
+    return DPT * Elt<DT>::bytes >= 512 || DT == DT_FP8;
 }
 template <int DT, int DPT, int GPL, int MODE>
 static void (*topk_kernel())(TopkArgs)
@@ -985,7 +1005,7 @@ __global__ void k_gather_sample(const i32x4* src, const float* scales, int64_t n
     }
 }
 
-int topk_row_bytes(int dtype, int ld) { return ld * (dtype == DT_F32 ? 4 : 2); }
+int topk_row_bytes(int dtype, int ld) { return ld * (dtype == DT_F32 ? 4 : dtype == DT_FP8 ? 1 : 2); }
 
 void launch_gather_sample(int dtype, const void* items, const float* scales, int64_t n, int64_t ns, int ld,
                           void* dst, float* dscales, hipStream_t s)
@@ -1019,6 +1039,7 @@ void launch_topk_seed(int dtype, const TopkArgs& a, hipStream_t s)
     if (dtype == DT_F32) topk_dispatch<DT_F32, TK_SEED>(a, s);
     else if (dtype == DT_BF16) topk_dispatch<DT_BF16, TK_SEED>(a, s);
     else if (dtype == DT_FP8B) topk_dispatch<DT_FP8B, TK_SEED>(a, s);
+    else if (dtype == DT_FP8 && a.ld == 256) topk_dispatch_g<DT_FP8, 256, TK_SEED>(a, s);
     else if (dtype == DT_SPLIT) topk_dispatch<DT_SPLIT, TK_SEED>(a, s);
     else fail(RKMIPS_EINVAL, "internal: no matrix-core path for this operand type");
     HIPC(hipGetLastError());

@@ -328,8 +328,9 @@ def rkmips_last_error():
 
 
 def rkmips_diag_mma_probe(kind, a_codes, b_codes):
-    """One 32 x 32 block of e4m3 code products on the matrix cores (kind 1: FP8, kind 0:
-    codes widened to BF16), FP32 accumulation: float32 [32 x 32]."""
+    """One 32 x 32 block of e4m3 code products on the matrix cores (kind 0: codes widened
+    to BF16; kind 1: FP8, 16-wide k steps; kind 2: FP8, 64-wide k steps, unit scales), FP32
+    accumulation: float32 [32 x 32]."""
     a = np.ascontiguousarray(a_codes, dtype=np.uint8)
     b = np.ascontiguousarray(b_codes, dtype=np.uint8)
     if a.shape != b.shape or a.ndim != 2 or a.shape[0] != 32:

@@ -220,7 +220,9 @@ def test_mma_probe_rejects_bad_arguments(R):
     assert e.value.status == -1
     a = np.zeros((32, 16), np.uint8)
     with pytest.raises(R.RkmipsError):
-        R.rkmips_diag_mma_probe(2, a, a)          # no such kind
+        R.rkmips_diag_mma_probe(3, a, a)          # no such kind
+    with pytest.raises(R.RkmipsError):
+        R.rkmips_diag_mma_probe(2, a, a)          # 64-wide steps need K a multiple of 64
     a[0, 0] = 0x7f
     with pytest.raises(R.RkmipsError):
         R.rkmips_diag_mma_probe(1, a, a)          # NaN code

@@ -56,16 +56,21 @@ def test_bf16_matrix_cores_accumulate_like_fp32_and_fp8_measured(pattern):
     from paper_2211_12751_amd import rkmips as R
     g = np.random.default_rng({"uniform": 1, "spread": 2, "cancel": 3}[pattern])
     bound = 2.0 * _gamma(K + 2)
-    worst_bf16, worst_fp8 = 0.0, 0.0
+    worst_bf16, worst_fp8, worst_f8k64 = 0.0, 0.0, 0.0
     print(f"\n[case] mma probe pattern={pattern} K={K}", flush=True)
     for trial in range(8):
         a, b = _codes(g, (32, K), pattern), _codes(g, (32, K), pattern)
         worst_bf16 = max(worst_bf16, _ratios(R, 0, a, b))
         worst_fp8 = max(worst_fp8, _ratios(R, 1, a, b))
+        worst_f8k64 = max(worst_f8k64, _ratios(R, 2, a, b))
     lg = lambda x: f"2^{np.log2(x):.1f}" if x > 0 else "0"
     print(f"[mma] {pattern}: max |c - S| / sum|terms|  BF16 path {worst_bf16:.3e} ({lg(worst_bf16)})  "
-          f"FP8 path {worst_fp8:.3e} ({lg(worst_fp8)})  model bound {bound:.3e} ({lg(bound)})", flush=True)
+          f"FP8 path {worst_fp8:.3e} ({lg(worst_fp8)})  FP8 K=64 path {worst_f8k64:.3e} ({lg(worst_f8k64)})  "
+          f"model bound {bound:.3e} ({lg(bound)})", flush=True)
     assert worst_bf16 <= bound
+    # the 32x32x64 instruction with the operand layout the seed pass uses: a wrong layout
+    # or scale would leave sums far from the exact ones
+    assert worst_f8k64 <= 2.0 ** -8
 
 
 def test_hardware_fp8_conversion_decodes_ocp_e4m3():
