@@ -82,7 +82,8 @@ enum {
     RKMIPS_FLAG_VERIFY_SIMPLE = 256 /* query: score with the one-group verify kernel
                                        (register-fed query tiles) where the two-group
                                        ring form would run (BF16 and FP8 indexes with
-                                       padded rows of 128 or 256 values); both take the
+                                       padded rows of 128 or 256 values, FP32 indexes
+                                       scored as split BF16 products); both take the
                                        same decisions                                     */
 };
 

@@ -472,7 +472,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_wpe<
 }
 
 // ------------------------------------------------------------------ ring form
-// BF16 operands (BF16 data, widened FP8 codes) with rows of 256 bytes and more.  A wave
+// BF16 operands (BF16 data, widened FP8 codes) with rows of 256 bytes and more, and the
+// BF16 pair rows of split FP32 data with d <= 64 (256 bytes).  A wave
 // holds two groups of 32 users in registers, so that every query fragment read from LDS
 // feeds two products; a workgroup holds 256 users.  The query tiles (32 rows at the
 // absolute positions 32 T .. 32 T + 31; rows outside the launch's range are loaded and
@@ -497,27 +498,44 @@ __device__ __forceinline__ void ring_block(const uint8_t* tile, const i32x4 (&bf
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[g][r] = 0.f;
     const uint8_t* arow = tile + (l & 31) * LROW + h * 16;
+    if constexpr (DT == DT_SPLIT) {
+        // pair rows [hi | lo]: k-step t of the hi half meets step t + KSTEPS / 2 of the lo
+        // half; q_h u_h + q_l u_h + q_h u_l in the one-group kernel's order
+        constexpr int HK = KSTEPS / 2;
 #pragma unroll
-    for (int t = 0; t < KSTEPS; t++) {
-        const bf16x8 af = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + t * 32));
+        for (int t = 0; t < HK; t++) {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + t * 32));
+            const bf16x8 al = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + (t + HK) * 32));
 #pragma unroll
-        for (int g = 0; g < 2; g++)
-            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, __builtin_bit_cast(bf16x8, bfrag[g][t]), acc[g], 0, 0, 0);
+            for (int g = 0; g < 2; g++) {
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, bfrag[g][t]);
+                const bf16x8 bl = __builtin_bit_cast(bf16x8, bfrag[g][t + HK]);
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[g], 0, 0, 0);
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[g], 0, 0, 0);
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[g], 0, 0, 0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < KSTEPS; t++) {
+            const bf16x8 af = __builtin_bit_cast(bf16x8, *(const i32x4*)(arow + t * 32));
+#pragma unroll
+            for (int g = 0; g < 2; g++)
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, __builtin_bit_cast(bf16x8, bfrag[g][t]), acc[g], 0, 0, 0);
+        }
+        // schedule: the first three fragment reads, then per k-step two products and the
+        // read three steps ahead (left alone, the scheduler keeps two reads in flight and
+        // each pair of k-steps waits for LDS)
+        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+#pragma unroll
+        for (int t = 0; t < KSTEPS - 3; t++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
     }
-    // schedule: the first three fragment reads, then per k-step two products and the read
-    // three steps ahead (left alone, the scheduler keeps two reads in flight and each pair
-    // of k-steps waits for LDS)
-    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
-#pragma unroll
-    for (int t = 0; t < KSTEPS - 3; t++) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
 }
 
-// Two waves per SIMD: at three, the 168-register budget makes the compiler spill, and a
-// spill reload inside the tile loop waits for every tile load in flight.
 template <int DT, int DPT>
 constexpr int verify_ring_wpe()
 {
@@ -529,7 +547,7 @@ constexpr int verify_ring_wpe()
 template <int DT, int DPT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(verify_ring_wpe<DT, DPT>(), 8))) void k_verify_ring(QueryArgs a, int64_t q_first, int64_t q_last, int64_t per, int64_t wgs)
 {
-    static_assert(dt_bf16_mma<DT>, "the ring form takes BF16 operands");
+    static_assert(dt_bf16_mma<DT> || DT == DT_SPLIT, "the ring form takes BF16 operands");
     constexpr int NG = 2;
     constexpr int UPW = 32 * NG;
     constexpr int ROWB = DPT * Elt<DT>::bytes;
@@ -1079,7 +1097,8 @@ static void verify_d(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t s)
 
 bool verify_uses_ring(const QueryArgs& a)
 {
-    return (a.mma_dtype == DT_BF16 || a.mma_dtype == DT_FP8B) && (a.mma_ld == 128 || a.mma_ld == 256) &&
+    return (((a.mma_dtype == DT_BF16 || a.mma_dtype == DT_FP8B) && (a.mma_ld == 128 || a.mma_ld == 256)) ||
+            (a.mma_dtype == DT_SPLIT && a.mma_ld == 128)) &&
            !(a.flags & RKMIPS_FLAG_VERIFY_SIMPLE);
 }
 
@@ -1118,7 +1137,9 @@ void launch_verify_range(const QueryArgs& a, int64_t q0, int64_t q1, hipStream_t
     if (verify_uses_ring(a)) {
         if (a.ntq != (a.nq + 31) / 32 || a.ntq >= (int64_t(1) << 24))
             fail(RKMIPS_EINVAL, "internal: prune-word table does not match the batch");
-        if (a.mma_dtype == DT_BF16) {
+        if (a.mma_dtype == DT_SPLIT) {
+            verify_ring_g<DT_SPLIT, 128>(a, q0, q1, s);
+        } else if (a.mma_dtype == DT_BF16) {
             if (a.mma_ld == 128) verify_ring_g<DT_BF16, 128>(a, q0, q1, s);
             else verify_ring_g<DT_BF16, 256>(a, q0, q1, s);
         } else {

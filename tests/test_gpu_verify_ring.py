@@ -1,10 +1,10 @@
 """The two forms of the verify pass (Alg. 5's block and inner-product tests over a query
 batch) take the same decisions.
 
-BF16 and FP8 indexes with padded rows of 128 or 256 values score a batch with the
-two-group ring kernel: query tiles at absolute positions, the per-query data and the
-Lemma 2 prune words staged in LDS by direct loads.  RKMIPS_FLAG_VERIFY_SIMPLE takes the
-one-group kernel instead.  Both must return the Definition 1 sets and, since they multiply
+BF16 and FP8 indexes with padded rows of 128 or 256 values, and FP32 indexes scored as
+split BF16 products (d <= 64), score a batch with the two-group ring kernel: query tiles
+at absolute positions, the per-query data and the Lemma 2 prune words staged in LDS by
+direct loads.  RKMIPS_FLAG_VERIFY_SIMPLE takes the one-group kernel instead.  Both must return the Definition 1 sets and, since they multiply
 the same operands in the same order and apply the same tests, report the same numbers of
 scored pairs and close calls.  Cases: user counts that are not a multiple of the 256-user
 workgroup, more than 8 distinct k (two launches whose boundary falls inside a 32-query
@@ -32,9 +32,10 @@ def _same_lists(a, b, what):
 
 
 @pytest.mark.parametrize("dtype, d, n, m", [("bf16", 100, 600, 1000), ("bf16", 256, 500, 777),
-                                            ("fp8", 128, 600, 1300), ("fp8", 200, 400, 513)])
+                                            ("fp8", 128, 600, 1300), ("fp8", 200, 400, 513),
+                                            ("f32", 64, 700, 1100), ("f32", 40, 500, 300)])
 def test_ring_and_simple_forms_agree(R, dtype, d, n, m):
-    w = I.make({"bf16": "c3", "fp8": "c5"}[dtype], n=n, m=m, d=d, nq=150, seed=300 + d)
+    w = I.make({"f32": "c2", "bf16": "c3", "fp8": "c5"}[dtype], n=n, m=m, d=d, nq=150, seed=300 + d)
     k_max = 12
     ks = (np.arange(150) % 12 + 1).astype(np.int32)   # 12 distinct k: two launches
     srt = np.sort(ks)
