@@ -227,7 +227,7 @@ static constexpr int64_t kMainWaitsItems = int64_t(1) << 18;
 // synchronisation: the fused top-k passes, then the FP64 refine with the certificate.
 struct LambdaBuild {
     DevBuf buf, cnt, tau, theta, fail_list, fail_count, errbits, spill, items3, users3, sel, sel_meta, sample,
-        sample_sc;
+        sample_sc, lb_rows;
     Events ev{4};   // start, after the main pass, after the refine, after the seed pass
 };
 
@@ -322,6 +322,10 @@ static void lambda_refine(Index& x, LambdaBuild& L, const DevBuf& users_o, const
     ra.err_rel = x.err_fast;
     ra.spill = L.spill.i();
     ra.spill_count = L.fail_count.i() + 1;
+    // lambda / ||u|| per user in Cone-Tree leaf order, for the block lower bounds
+    L.lb_rows.alloc(sizeof(double) * (size_t)m * x.prm.k_max);
+    ra.lb_rows = L.lb_rows.d();
+    ra.leaf_of = x.user_inv.u32();
     {   // the select and rescoring kernels pass the kept candidates through memory
         L.sel.alloc(sizeof(uint2) * (size_t)m * x.C);
         L.sel_meta.alloc(sizeof(int) * 4 * (size_t)m);
@@ -581,7 +585,7 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
     lambda_refine(x, L, users_o, uscales_o.f(), n2_users_orig.d(), s);
 
     // ---- per-block quantities that need lambda (L^j(B))
-    finish_blocks(x, s);
+    finish_blocks(x, s, L.lb_rows.d());
     // ev[3] follows every kernel of the build: the second stream's work precedes ev[7],
     // which the caller's stream waited on.  No host wait here: the temporaries below go
     // back to the cache tagged with events on the caller's stream, and the caller can

@@ -176,7 +176,9 @@ struct ConeWork {
 void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
                 hipStream_t s, const std::function<void()>& enqueued, ConeWork& cw,
                 const std::atomic<bool>* cancel = nullptr);
-void finish_blocks(Index& x, hipStream_t s);
+// L^j(B) for every block; lb_rows (optional): the lambda refine's leaf-order rows of
+// lambda_u^(j) / ||u|| ([m x k_max]), else gathered from the lambda table
+void finish_blocks(Index& x, hipStream_t s, const double* lb_rows = nullptr);
 // Matrix-core operand of the block centres (x.center_mma), from x.center.
 void make_center_operand(Index& x, hipStream_t s);
 // x.user_inv from x.user_perm.

@@ -85,6 +85,10 @@ struct RefineArgs {
     // split narrow pass: the kept candidates [m x C] (orderable key, item position) and per
     // user {count (-1: left to the wide pass), cut bits, largest threshold bits, 0}
     uint2* sel; int* sel_meta;
+    // the block lower bounds' input, when given: lb_rows[leaf_of[u] x k_max + r] =
+    // lambda_u^(r+1) / ||u|| (FP64), user-major in Cone-Tree leaf order, so that the
+    // blocks (runs of leaf positions) read it contiguously
+    double* lb_rows; const uint32_t* leaf_of;
 };
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s);
 // Matrix-core accumulation probe (k_diag.hip): host arrays, synchronous.

@@ -593,8 +593,20 @@ __global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
 }
 
 // L^j(B) = min over the block of lambda_u^(j) / ||u||, rounded down to FP32 (-inf for a
-// block without usable angles, so it is never pruned).  One wave per block, one user
-// per lane (blocks hold at most 64 users); lambda rows are in original user order.
+// block without usable angles, so it is never pruned).
+__device__ __forceinline__ float block_lb_round(double mn, bool ok)
+{
+    if (!ok) return -__builtin_inff();
+    float f = (float)mn;
+    if ((double)f > mn) {   // step one ulp towards -inf
+        const uint32_t u = __float_as_uint(f);
+        f = f == 0.f ? -__uint_as_float(1u) : __uint_as_float(f > 0.f ? u - 1u : u + 1u);
+    }
+    return f;
+}
+
+// From the lambda rows in original user order: one wave per block, one user per lane
+// (blocks hold at most 64 users), gathering each lambda_u^(j) from row j.
 __global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const uint32_t* perm, const double* user_n2,
                                                   const int64_t* block_start, const int* block_ok, int64_t nblocks,
                                                   int64_t m, int k_max, float* lb)
@@ -614,18 +626,31 @@ __global__ __launch_bounds__(256) void k_block_lb(const double* lam64, const uin
             mn = v < mn ? v : mn;
         }
         mn = wave_min(mn);
-        if (l == 0) {
-            float out = -__builtin_inff();
-            if (ok) {
-                float f = (float)mn;
-                if ((double)f > mn) {   // step one ulp towards -inf
-                    const uint32_t u = __float_as_uint(f);
-                    f = f == 0.f ? -__uint_as_float(1u) : __uint_as_float(f > 0.f ? u - 1u : u + 1u);
-                }
-                out = f;
-            }
-            lb[(int64_t)j * nblocks + b] = out;
+        if (l == 0) lb[(int64_t)j * nblocks + b] = block_lb_round(mn, ok);
+    }
+}
+
+// From rows[q x k_max + j] = lambda^(j+1) / ||u|| of the user at leaf position q (written
+// by the lambda refine): a block's rows are contiguous, so one wave per block reads them
+// in order, lane j keeping the minimum of column j.  The quotients are the ones the
+// gathering form computes (same operands, same operations), so the bounds are the same.
+__global__ __launch_bounds__(256) void k_block_lb_rows(const double* rows, const int64_t* block_start,
+                                                       const int* block_ok, int64_t nblocks, int k_max, float* lb)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= nblocks) return;
+    const int l = lane_id();
+    const int64_t st = block_start[b], en = block_start[b + 1];
+    const bool ok = block_ok[b] != 0;
+    for (int j = l; j < k_max; j += 64) {
+        double mn = __builtin_inf();
+        const double* r = rows + st * k_max + j;
+#pragma unroll 8
+        for (int64_t q = st; q < en; q++, r += k_max) {
+            const double v = *r;
+            mn = v < mn ? v : mn;
         }
+        lb[(int64_t)j * nblocks + b] = block_lb_round(mn, ok);
     }
 }
 
@@ -805,13 +830,17 @@ void make_center_operand(Index& x, hipStream_t s)
     launch_split_bf16(x.center.f(), x.nblocks, x.ld, x.center_mma.u16(), 2, s);
 }
 
-void finish_blocks(Index& x, hipStream_t s)
+void finish_blocks(Index& x, hipStream_t s, const double* lb_rows)
 {
     const int64_t tot = x.nblocks * x.prm.k_max;
     x.block_lb.alloc(sizeof(float) * tot);
-    hipLaunchKernelGGL(k_block_lb, dim3((unsigned)((x.nblocks + 3) / 4)), dim3(256), 0, s, x.lam64.d(),
-                       x.user_perm.u32(), x.user_n2.d(), x.block_start.i64(), x.block_ok.i(), x.nblocks, x.m, x.prm.k_max,
-                       x.block_lb.f());
+    const dim3 g((unsigned)((x.nblocks + 3) / 4)), b(256);
+    if (lb_rows)
+        hipLaunchKernelGGL(k_block_lb_rows, g, b, 0, s, lb_rows, x.block_start.i64(), x.block_ok.i(), x.nblocks,
+                           x.prm.k_max, x.block_lb.f());
+    else
+        hipLaunchKernelGGL(k_block_lb, g, b, 0, s, x.lam64.d(), x.user_perm.u32(), x.user_n2.d(), x.block_start.i64(),
+                           x.block_ok.i(), x.nblocks, x.m, x.prm.k_max, x.block_lb.f());
     HIPC(hipGetLastError());
 }
 

@@ -395,6 +395,7 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
             const double lv = r == l ? v : -__builtin_inf();
             a.lam64[(int64_t)r * a.m + u] = lv;
             a.lam32[(int64_t)r * a.m + u] = (float)lv;
+            if (a.lb_rows) a.lb_rows[(int64_t)a.leaf_of[u] * a.k_max + r] = lv / un;
             if (r == l && l < Nk) worst32 = rel(lv, (double)(float)lv);
         }
         lk = a.k_max <= 64 ? __shfl(v, a.k_max - 1) : -__builtin_inf();
@@ -425,6 +426,7 @@ __device__ void refine_rank(const RefineArgs& a, int64_t u, const uint32_t* skey
             if (r < a.k_max) {
                 a.lam64[(int64_t)r * a.m + u] = v[s4];
                 a.lam32[(int64_t)r * a.m + u] = (float)v[s4];
+                if (a.lb_rows) a.lb_rows[(int64_t)a.leaf_of[u] * a.k_max + r] = v[s4] / un;
                 if (r < Nk) worst32 = fmax(worst32, rel(v[s4], (double)(float)v[s4]));
                 if (r == a.k_max - 1) lam_row[0] = v[s4];
             }
@@ -722,6 +724,7 @@ __global__ __launch_bounds__(256) void k_fallback(RefineArgs a, double* scratch,
             for (int i = 0; i < ng; i++) r += (top[i] > top[j]) || (top[i] == top[j] && i < j);
             a.lam64[(int64_t)r * a.m + u] = top[j];
             a.lam32[(int64_t)r * a.m + u] = (float)top[j];
+            if (a.lb_rows) a.lb_rows[(int64_t)a.leaf_of[u] * a.k_max + r] = top[j] / sqrt(a.user_n2[u]);
             if (top[j] != 0.0)
                 atomic_max_pos(a.max_raw_err_bits + kErrSlots + blockIdx.x % kErrSlots,
                                fabs((double)(float)top[j] - top[j]) / fabs(top[j]));
@@ -730,6 +733,7 @@ __global__ __launch_bounds__(256) void k_fallback(RefineArgs a, double* scratch,
             const double v = r < want ? T : -__builtin_inf();
             a.lam64[(int64_t)r * a.m + u] = v;
             a.lam32[(int64_t)r * a.m + u] = (float)v;
+            if (a.lb_rows) a.lb_rows[(int64_t)a.leaf_of[u] * a.k_max + r] = v / sqrt(a.user_n2[u]);
         }
         __syncthreads();
     }

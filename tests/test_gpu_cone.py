@@ -14,15 +14,21 @@ from paper_2211_12751_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dtype, n, m, d, k_max", [("f32", 500, 3001, 24, 10), ("bf16", 400, 2000, 64, 8),
-                                                    ("fp8", 300, 1500, 40, 5)])
-def test_blocks_valid_and_bound_data_exact(dtype, n, m, d, k_max):
+@pytest.mark.parametrize("dtype, n, m, d, k_max, cert", [("f32", 500, 3001, 24, 10, True),
+                                                          ("bf16", 400, 2000, 64, 8, True),
+                                                          ("fp8", 300, 1500, 40, 5, True),
+                                                          ("bf16", 400, 1200, 64, 100, True),
+                                                          ("fp8", 300, 900, 128, 70, False)])
+def test_blocks_valid_and_bound_data_exact(dtype, n, m, d, k_max, cert):
+    """k_max above 64 takes more than one column per lane in the bound pass; without the
+    certificate every lambda row (and its bound row) comes from the full rescoring."""
     from paper_2211_12751_amd import rkmips as R
     name = {"f32": "c1", "bf16": "c3", "fp8": "c5"}[dtype]
     w = I.make(name, n=n, m=m, d=d, nq=1, seed=m)
     w.users[[5, 77]] = 0 if dtype != "fp8" else w.users[[5, 77]]
-    print(f"\n[case] cone {dtype} n={n} m={m} d={d} k_max={k_max}", flush=True)
-    idx = R.Index(w.items, w.item_scales, w.users, w.user_scales, dtype=dtype, k_max=k_max)
+    print(f"\n[case] cone {dtype} n={n} m={m} d={d} k_max={k_max} cert={cert}", flush=True)
+    idx = R.Index(w.items, w.item_scales, w.users, w.user_scales, dtype=dtype, k_max=k_max,
+                  flags=0 if cert else R.FLAG_NO_CERT)
     try:
         b = idx.blocks()
         leaf, bs = b["leaf_users"].astype(np.int64), b["block_start"]
