@@ -53,13 +53,19 @@ size_t device_cap(Cache& c, int dev)
 {
     auto it = c.dev_cap.find(dev);
     if (it != c.dev_cap.end()) return it->second;
-    size_t cap = size_t(32) << 30;
+    // an index build over a million items and a few million users cycles through about
+    // 40 GB of buffers: below that, every build would give blocks back with hipFree and
+    // allocate them again
+    size_t cap = size_t(64) << 30;
     if (const char* s = std::getenv("RKMIPS_CACHE_MB")) {
         cap = (size_t)std::strtoull(s, nullptr, 10) << 20;
     } else {
         size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) == hipSuccess && tot / 8 < cap) cap = tot / 8;
-        else (void)hipGetLastError();
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+            if (tot / 4 < cap) cap = tot / 4;
+        } else {
+            (void)hipGetLastError();
+        }
     }
     c.dev_cap[dev] = cap;
     return cap;

@@ -10,8 +10,8 @@
 //   * a block released inside an IdleScope (the device was synchronised first) is free
 //     for any stream at once.
 // Blocks released with no scope at all are returned to the runtime with hipFree.
-// Cached bytes are capped (RKMIPS_CACHE_MB, default 1/8 of the device memory, at most
-// 32 GiB); the oldest blocks are returned first, after their event has completed.  An
+// Cached bytes are capped (RKMIPS_CACHE_MB, default 1/4 of the device memory, at most
+// 64 GiB); the oldest blocks are returned first, after their event has completed.  An
 // allocation that fails empties the cache and is tried once more.
 //
 // Pinned host blocks are cached the same way, without events: they are released only
