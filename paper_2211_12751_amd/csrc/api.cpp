@@ -252,9 +252,9 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
     const void* mi = x.items.p;
     const void* mu = users_o.p;
     const int tdt = topk_dtype(x), tld = topk_ld(x);
-    if (x.mma_dtype != x.dtype) {
-        L.items3.alloc(sizeof(uint16_t) * (size_t)x.n_lam * tld);
-        L.users3.alloc(sizeof(uint16_t) * (size_t)m * tld);
+    // FP8 rows of 256 codes: the seed pass below runs on the codes as they are (see there)
+    const bool f8 = x.ns > 0 && x.dtype == RKMIPS_FP8_E4M3 && x.ld == 256;
+    auto operands = [&] {
         if (tdt == DT_SPLIT) {
             launch_split_bf16((const float*)x.items.p, x.n_lam, x.ld, L.items3.u16(), 2, s);
             launch_split_bf16((const float*)users_o.p, m, x.ld, L.users3.u16(), 2, s);
@@ -262,6 +262,11 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
             launch_mma_operand(x.mma_dtype, x.dtype, x.items.p, x.n_lam, x.ld, L.items3.u16(), 0, s);
             launch_mma_operand(x.mma_dtype, x.dtype, users_o.p, m, x.ld, L.users3.u16(), 1, s);
         }
+    };
+    if (x.mma_dtype != x.dtype) {
+        L.items3.alloc(sizeof(uint16_t) * (size_t)x.n_lam * tld);
+        L.users3.alloc(sizeof(uint16_t) * (size_t)m * tld);
+        if (!f8) operands();   // otherwise after the seed pass, which does not read them
         mi = L.items3.p;
         mu = L.users3.p;
     }
@@ -276,7 +281,6 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
         // FP8 rows of 256 codes: the estimate runs on the FP8 matrix cores with the codes as
         // they are (half the matrix-core time; the estimate needs no error bound, as the
         // certificate does not depend on it); otherwise on the main pass's operand form
-        const bool f8 = x.dtype == RKMIPS_FP8_E4M3 && x.ld == 256;
         const int sdt = f8 ? DT_FP8 : tdt, sld = f8 ? x.ld : tld;
         // the sample's rows gathered first, so that the pass streams contiguous tiles
         L.sample.alloc((size_t)x.ns * topk_row_bytes(sdt, sld));
@@ -295,6 +299,7 @@ static void lambda_topk(Index& x, LambdaBuild& L, const DevBuf& users_o, const f
         a0.theta_out = L.theta.f();
         launch_topk_seed(sdt, a0, s);
     }
+    if (f8 && x.mma_dtype != x.dtype) operands();
     before_main();
     HIPC(hipEventRecord(L.ev.ev[3], s));
     TopkArgs a1 = ta;
@@ -536,7 +541,10 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
             saalsh_projections(x, srp, s2);
             HIPC(hipEventRecord(ev.ev[6], s2));
             wk.ready();
-            // ---- Cone-Tree over user directions; users are stored in leaf order
+            // ---- Cone-Tree over user directions; users are stored in leaf order.  It
+            // starts once the item order and the padded copies are done: its row gathers
+            // would slow those copies several times over and delay the seed pass.
+            HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
             build_cone(x, users, user_scales, n2_users_orig.d(), s2, nullptr, cone_work, &wk.cancel);
             if (wk.cancel.load()) {
                 wk.queued();

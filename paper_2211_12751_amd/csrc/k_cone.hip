@@ -510,23 +510,36 @@ __global__ __launch_bounds__(256) void k_flag_emit(const int* is_start, int64_t 
     if (b == 0 && tid == 0) block_start[*nblocks] = m;
 }
 
-// BF16 unit rows (original order) for the split phases.
+// BF16 unit rows (original order) for the split phases: eight values of one row per
+// thread (ld is a power of two, at least 32), one 16-byte store.
 template <int DT>
 __global__ void k_unit(const void* X, const float* scales, const double* n2, int64_t rows, int d, int ld,
                        uint16_t* out)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= rows * ld) return;
-    const int64_t r = t / ld;
-    const int i = (int)(t - r * ld);
-    float v = 0.f;
-    if (i < d && n2[r] > 0.0) {
-        double x = (double)elem_f32<DT>(X, r * d + i);
-        if constexpr (DT == DT_FP8) x *= (double)scales[r];
-        v = (float)(x / sqrt(n2[r]));
+    const int sh = __builtin_ctz((unsigned)ld >> 3);   // log2 of the 8-value groups per row
+    if (t >= (rows * ld) >> 3) return;
+    const int64_t r = t >> sh;
+    const int i0 = (int)(t - (r << sh)) * 8;
+    const double nn = n2[r];
+    const double un = nn > 0.0 ? sqrt(nn) : 1.0;
+    const double sc = DT == DT_FP8 ? (double)scales[r] : 1.0;
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int i = i0 + e;
+        float v = 0.f;
+        if (i < d && nn > 0.0) {
+            double x = (double)elem_f32<DT>(X, r * d + i);
+            if constexpr (DT == DT_FP8) x *= sc;
+            v = (float)(x / un);
+        }
+        const uint32_t b = __float_as_uint(v);
+        const uint32_t h = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;   // round to nearest even
+        if (e & 1) o[e >> 1] |= h << 16;
+        else o[e >> 1] = h;
     }
-    const uint32_t b = __float_as_uint(v);
-    out[t] = (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);   // round to nearest even
+    *(i32x4*)(out + t * 8) = i32x4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
 }
 
 // Per block (one wave, one user per lane): unit centre (FP64 mean of the unit user
@@ -664,7 +677,7 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     DevBuf &dot_l = cw.dot_l, &left = cw.left, &lrank = cw.lrank, &blk_cnt = cw.blk_cnt;
     unit.alloc(sizeof(uint16_t) * (size_t)m * ld);
     {
-        const int64_t tot = m * ld;
+        const int64_t tot = m * ld / 8;
         dim3 g((unsigned)((tot + 255) / 256)), b(256);
         if (x.dtype == DT_F32) hipLaunchKernelGGL(k_unit<DT_F32>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());
         else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_unit<DT_BF16>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());

@@ -169,10 +169,20 @@ __global__ void k_radius(const void* X, const float* scales, const int64_t* part
     }
     const double* c = cen64 + (int64_t)lo * ld;
     const double sc = DT == DT_FP8 ? (double)scales[p] : 1.0;
+    // the lane's row in 16-byte loads (rows are 16-byte aligned: ld >= 32), the terms in
+    // index order
+    constexpr int VPL = 16 / Elt<DT>::bytes;
+    const uint8_t* row = (const uint8_t*)X + p * ld * Elt<DT>::bytes;
     double r2 = 0.0;
-    for (int i = 0; i < d; i++) {
-        const double v = (double)elem_f32<DT>(X, p * ld + i) * sc - c[i];
-        r2 = __fma_rn(v, v, r2);
+    for (int i0 = 0; i0 < d; i0 += VPL) {
+        const i32x4 q = *(const i32x4*)(row + i0 * Elt<DT>::bytes);
+#pragma unroll
+        for (int e = 0; e < VPL; e++) {
+            if (i0 + e < d) {
+                const double v = (double)elem_f32<DT>(&q, e) * sc - c[i0 + e];
+                r2 = __fma_rn(v, v, r2);
+            }
+        }
     }
     if (p < part_start[0]) r2 = 0.0;   // SAH: P' items belong to no partition
     if (in) r2out[p] = r2;
