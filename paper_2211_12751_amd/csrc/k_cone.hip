@@ -549,6 +549,7 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
 {
     __shared__ float cen[4][256];
+    __shared__ double fac[4][64];
     const int l = lane_id(), w = threadIdx.x >> 6;
     const int64_t b = (int64_t)blockIdx.x * 4 + w;
     if (b >= a.nblocks) return;
@@ -556,17 +557,34 @@ __global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
     const int sz = (int)(en - st);
     const bool mine = l < sz;
     const int64_t p = st + l;
-    // FP64 unit vector of this lane's user, read from the stored row (leaf order)
+    // FP64 unit vector of each user, from the stored row (leaf order): the block's rows are
+    // contiguous, so lane l sums dimensions l, l + 64, ... over the users in order (64
+    // consecutive elements per load), each user's factors taken from LDS
     const double un_l = mine ? sqrt(a.user_n2[p]) : 0.0;
     const double inv = un_l > 0.0 ? 1.0 / un_l : 0.0;
-    const double sc_l = (DT == DT_FP8 && mine) ? (double)a.user_scales[p] : 1.0;
-    double cn2 = 0.0;
-    for (int i = 0; i < a.d; i++) {
-        double v = mine ? (double)elem_f32<DT>(a.users, p * a.ld + i) * sc_l * inv : 0.0;
-        v = wave_sum(v) / (double)sz;
-        cn2 += v * v;
-        if (l == 0) cen[w][i] = (float)v;
+    fac[w][l] = inv;
+    __builtin_amdgcn_wave_barrier();
+    double cs[4] = {0.0, 0.0, 0.0, 0.0};   // dimensions l + 64 c (d <= 256)
+    for (int q = 0; q < sz; q++) {
+        const double iq = fac[w][q];
+        const double sq = DT == DT_FP8 ? (double)a.user_scales[st + q] : 1.0;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const int i = l + 64 * c;
+            if (i < a.d) cs[c] += (double)elem_f32<DT>(a.users, (st + q) * a.ld + i) * sq * iq;
+        }
     }
+    double cn2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const int i = l + 64 * c;
+        if (i < a.d) {
+            const double v = cs[c] / (double)sz;
+            cn2 += v * v;
+            cen[w][i] = (float)v;
+        }
+    }
+    cn2 = wave_sum(cn2);
     __builtin_amdgcn_wave_barrier();
     const double cnorm = sqrt(cn2);
     bool ok = cnorm > 1e-6;
@@ -582,8 +600,16 @@ __global__ __launch_bounds__(256) void k_leaf_stats(LeafArgs a)
         const double un2 = a.user_n2[p];
         zero_user = !(un2 > 0.0);
         const float su = DT == DT_FP8 ? a.user_scales[p] : 1.f;
+        // the lane's row in 16-byte loads (rows are 16-byte aligned), the terms in index order
+        constexpr int VPL = 16 / Elt<DT>::bytes;
+        const uint8_t* row = (const uint8_t*)a.users + p * a.ld * Elt<DT>::bytes;
         double acc = 0.0;
-        for (int i = 0; i < a.d; i++) acc = __fma_rn((double)elem_f32<DT>(a.users, p * a.ld + i), (double)cen[w][i], acc);
+        for (int i0 = 0; i0 < a.d; i0 += VPL) {
+            const i32x4 q = *(const i32x4*)(row + i0 * Elt<DT>::bytes);
+#pragma unroll
+            for (int e = 0; e < VPL; e++)
+                if (i0 + e < a.d) acc = __fma_rn((double)elem_f32<DT>(&q, e), (double)cen[w][i0 + e], acc);
+        }
         if constexpr (DT == DT_FP8) acc *= (double)su;
         const double un = sqrt(un2);
         ct = zero_user ? 1.0 : acc / un;

@@ -246,16 +246,25 @@ __global__ __launch_bounds__(256) void k_project(const void* X, const float* sca
         // all loads of the chunk are issued before the first LDS store
         constexpr int XE = 128 * PJ_KC / 256, AE = PJ_KC * KB * 32 / 256;
         float xv[XE], av[AE];
+        // thread: row rr, the XE consecutive values from column kb of the chunk, read in
+        // 16-byte loads where they lie inside the padded row
+        static_assert(XE == 16 && PJ_KC == 32, "chunk map: two threads per row");
+        const int rr = threadIdx.x >> 1, kb = (threadIdx.x & 1) * XE;
+        const int64_t p = r0 + rr;
+        i32x4 raw[Elt<DT>::bytes];
+        const bool vec = p < rows && k0 + kb + XE <= ld && k0 + kb < d;
+#pragma unroll
+        for (int j = 0; j < Elt<DT>::bytes; j++) {
+            raw[j] = i32x4{0, 0, 0, 0};
+            if (vec) raw[j] = *(const i32x4*)((const uint8_t*)X + (p * ld + k0 + kb) * Elt<DT>::bytes + 16 * j);
+        }
 #pragma unroll
         for (int q = 0; q < XE; q++) {
-            const int e = threadIdx.x + 256 * q;
-            const int rr = e / PJ_KC, kk = e % PJ_KC;
-            const int64_t p = r0 + rr;
-            const int i = k0 + kk;
+            const int i = k0 + kb + q;
             float v = 0.f;
             if (p < rows) {
                 if (i < d) {
-                    float x = elem_f32<DT>(X, p * ld + i);
+                    float x = elem_f32<DT>(raw, q);
                     if constexpr (DT == DT_FP8) x *= scales[p];
                     if (MODE == 0) x -= cen32[(int64_t)pj[rr] * ld + i];
                     v = x;
@@ -274,10 +283,7 @@ __global__ __launch_bounds__(256) void k_project(const void* X, const float* sca
             av[q] = (i < D && h < K) ? A[(int64_t)i * K + h] : 0.f;
         }
 #pragma unroll
-        for (int q = 0; q < XE; q++) {
-            const int e = threadIdx.x + 256 * q;
-            xs[e / PJ_KC][e % PJ_KC] = xv[q];
-        }
+        for (int q = 0; q < XE; q++) xs[rr][kb + q] = xv[q];
 #pragma unroll
         for (int q = 0; q < AE; q++) {
             const int e = threadIdx.x + 256 * q;
