@@ -236,28 +236,39 @@ __global__ __launch_bounds__(256) void k_project(const void* X, const float* sca
             }
         pj[threadIdx.x] = lo;
     }
+    __syncthreads();   // pj is read before the first tile store
     f32x16 acc[KB];
 #pragma unroll
     for (int cb = 0; cb < KB; cb++)
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[cb][r] = 0.f;
-    for (int k0 = 0; k0 < D; k0 += PJ_KC) {
-        __syncthreads();
-        // all loads of the chunk are issued before the first LDS store
-        constexpr int XE = 128 * PJ_KC / 256, AE = PJ_KC * KB * 32 / 256;
-        float xv[XE], av[AE];
-        // thread: row rr, the XE consecutive values from column kb of the chunk, read in
-        // 16-byte loads where they lie inside the padded row
-        static_assert(XE == 16 && PJ_KC == 32, "chunk map: two threads per row");
-        const int rr = threadIdx.x >> 1, kb = (threadIdx.x & 1) * XE;
-        const int64_t p = r0 + rr;
-        i32x4 raw[Elt<DT>::bytes];
+    // Chunk k0 + PJ_KC is loaded from global memory while the products of chunk k0 run.
+    // Thread map: row rr, the XE consecutive values from column kb of the chunk, read in
+    // 16-byte loads where they lie inside the padded row.
+    constexpr int XE = 128 * PJ_KC / 256, AE = PJ_KC * KB * 32 / 256;
+    static_assert(XE == 16 && PJ_KC == 32, "chunk map: two threads per row");
+    const int rr = threadIdx.x >> 1, kb = (threadIdx.x & 1) * XE;
+    const int64_t p = r0 + rr;
+    i32x4 raw[Elt<DT>::bytes];
+    float av[AE];
+    auto fetch = [&](int k0) {
         const bool vec = p < rows && k0 + kb + XE <= ld && k0 + kb < d;
 #pragma unroll
         for (int j = 0; j < Elt<DT>::bytes; j++) {
             raw[j] = i32x4{0, 0, 0, 0};
             if (vec) raw[j] = *(const i32x4*)((const uint8_t*)X + (p * ld + k0 + kb) * Elt<DT>::bytes + 16 * j);
         }
+#pragma unroll
+        for (int q = 0; q < AE; q++) {
+            const int e = threadIdx.x + 256 * q;
+            const int kk = e / (KB * 32), h = e % (KB * 32);
+            const int i = k0 + kk;
+            av[q] = (i < D && h < K) ? A[(int64_t)i * K + h] : 0.f;
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < D; k0 += PJ_KC) {
+        float xv[XE];
 #pragma unroll
         for (int q = 0; q < XE; q++) {
             const int i = k0 + kb + q;
@@ -275,13 +286,7 @@ __global__ __launch_bounds__(256) void k_project(const void* X, const float* sca
             }
             xv[q] = v;
         }
-#pragma unroll
-        for (int q = 0; q < AE; q++) {
-            const int e = threadIdx.x + 256 * q;
-            const int kk = e / (KB * 32), h = e % (KB * 32);
-            const int i = k0 + kk;
-            av[q] = (i < D && h < K) ? A[(int64_t)i * K + h] : 0.f;
-        }
+        __syncthreads();   // the previous chunk's products have read the LDS tiles
 #pragma unroll
         for (int q = 0; q < XE; q++) xs[rr][kb + q] = xv[q];
 #pragma unroll
@@ -290,6 +295,7 @@ __global__ __launch_bounds__(256) void k_project(const void* X, const float* sca
             as[e / (KB * 32)][e % (KB * 32)] = av[q];
         }
         __syncthreads();
+        if (k0 + PJ_KC < D) fetch(k0 + PJ_KC);
 #pragma unroll
         for (int kk = 0; kk < PJ_KC; kk += 2) {
             const float a = xs[w * 32 + (l & 31)][kk + (l >> 5)];
