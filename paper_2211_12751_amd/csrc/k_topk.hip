@@ -738,14 +738,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                         if (q4[jq] > top[g][TK_T - 1]) {
 #pragma unroll
                             for (int e4 = 0; e4 < 4; e4++) {
-                                float x = v[g][4 * jq + e4];
+                                const float x = v[g][4 * jq + e4];
                                 if (x > top[g][TK_T - 1]) {
+                                    // sorted insertion, the last entry dropped: entry i becomes
+                                    // max(t_i, min(x, t_(i-1))), the median of the three
 #pragma unroll
-                                    for (int i = 0; i < TK_T; i++) {
-                                        const float hi = fmaxf(top[g][i], x);
-                                        x = fminf(top[g][i], x);
-                                        top[g][i] = hi;
-                                    }
+                                    for (int i = TK_T - 1; i > 0; i--)
+                                        top[g][i] = __builtin_amdgcn_fmed3f(top[g][i - 1], top[g][i], x);
+                                    top[g][0] = fmaxf(top[g][0], x);
                                 }
                             }
                         }
