@@ -541,10 +541,11 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
             saalsh_projections(x, srp, s2);
             HIPC(hipEventRecord(ev.ev[6], s2));
             wk.ready();
-            // ---- Cone-Tree over user directions; users are stored in leaf order.  It
-            // starts once the item order and the padded copies are done: its row gathers
-            // would slow those copies several times over and delay the seed pass.
-            HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
+            // ---- Cone-Tree over user directions; users are stored in leaf order.  With
+            // many items it starts once the item order and the padded copies are done: its
+            // row gathers would slow those copies several times over and delay the seed
+            // pass (with few items the copies are short and the Cone-Tree sets the build).
+            if (x.n_lam >= kMainWaitsItems) HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
             build_cone(x, users, user_scales, n2_users_orig.d(), s2, nullptr, cone_work, &wk.cancel);
             if (wk.cancel.load()) {
                 wk.queued();

@@ -41,12 +41,25 @@ __device__ __forceinline__ int64_t cone_pivot(const ConeLevelArgs& a, int64_t st
 // <a, b> of two BF16 unit rows, one lane per row (16-byte loads of 8 values; the rows of
 // a wave are independent, so their loads overlap).  The split geometry only shapes the
 // tree (which never changes a result), so BF16 directions suffice and halve the bytes.
-// Each step loads one 128-byte line of both rows before it uses any of it: requests for a
-// line arrive together, so the line is fetched once (loads spread over the whole loop
-// find it evicted again when many waves gather rows at once).
+// Rows of 256 bytes and more: each step loads one 128-byte line of both rows before it uses
+// any of it, so that requests for a line arrive together and the line is fetched once
+// (loads spread over the whole loop find it evicted again when many waves gather rows from
+// HBM at once).  Shorter rows keep one load pair per step, which needs fewer registers.
 __device__ __forceinline__ float row_dot(const uint16_t* a, const uint16_t* b, int ld)
 {
     float acc = 0.f;
+    if (ld < 128) {
+        for (int c = 0; c < ld; c += 8) {
+            const i32x4 x = *(const i32x4*)(a + c), y = *(const i32x4*)(b + c);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t xu = (uint32_t)x[e], yu = (uint32_t)y[e];
+                acc = fmaf(__uint_as_float(xu << 16), __uint_as_float(yu << 16), acc);
+                acc = fmaf(__uint_as_float(xu & 0xffff0000u), __uint_as_float(yu & 0xffff0000u), acc);
+            }
+        }
+        return acc;
+    }
     for (int c0 = 0; c0 < ld; c0 += 64) {
         const int nv = ld - c0 < 64 ? (ld - c0) / 8 : 8;   // ld: 32, 64, 128 or 256
         i32x4 x[8], y[8];
