@@ -240,18 +240,20 @@ __device__ bool refine_select(const RefineArgs& a, int64_t u, uint32_t* skey, ui
                               float* cut_out, float* tau_out)
 {
     const int l = lane_id();
-    // gather every segment's buffer straight into registers (entry j = lane + 64 i)
-    // part p = 2 s + h: half h of segment s's buffer
-    int cum[9];
-    cum[0] = 0;
-    float tau_max = -__builtin_inff();
-    for (int p = 0; p < 8; p++) {
-        const int s = p >> 1;
-        const int c = s < a.nseg ? a.cnt[(u * a.nseg + s) * 2 + (p & 1)] : 0;
-        cum[p + 1] = cum[p] + c;
-        if (s < a.nseg && (p & 1) == 0) tau_max = fmaxf(tau_max, a.tau[u * a.nseg + s]);
-    }
-    const int N = cum[8];
+    // gather every segment's buffer straight into registers (entry j = lane + 64 i).
+    // Part p = 2 s + h is half h of segment s's buffer; there are P = 2 nseg <= 64 parts
+    // (nseg G <= RF_MAXN with G >= 128 gives at most 16 segments).  Lane p reads part p's
+    // count; the running totals cum[0..P] go to the wave's LDS scratch (hist, which the
+    // selection below reuses once the gather is done).
+    const int P = 2 * a.nseg;
+    int* cum = hist;
+    const int c = l < P ? a.cnt[(u * a.nseg + (l >> 1)) * 2 + (l & 1)] : 0;
+    const int incl = wave_incl_scan(c);
+    if (l < P) cum[l + 1] = incl;
+    if (l == 0) cum[0] = 0;
+    const int N = __shfl(incl, P - 1);
+    const float tau_max = wave_max(l < a.nseg ? a.tau[u * a.nseg + l] : -__builtin_inff());
+    __builtin_amdgcn_wave_barrier();
     if (N > GPL * 64) {   // more candidates than this instance holds: the wide pass takes it
         if (l == 0) a.spill[atomicAdd(a.spill_count, 1)] = (int)u;
         return false;
@@ -268,9 +270,15 @@ __device__ bool refine_select(const RefineArgs& a, int64_t u, uint32_t* skey, ui
         if (64 * i >= N) break;   // wave-uniform
         const int j = l + 64 * i;
         if (j < N) {
-            int p = 0;
-#pragma unroll
-            for (int q = 1; q < 8; q++) p += j >= cum[q];
+            // part of entry j: the first q in [1, P) with cum[q] > j, minus one (empty
+            // parts have cum[q] == cum[q + 1] and are passed over)
+            int lo = 1, hi = P;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (cum[mid] > j) hi = mid;
+                else lo = mid + 1;
+            }
+            const int p = lo - 1;
             const uint2 e = a.buf[(u * a.nseg + (p >> 1)) * (int64_t)a.G + (p & 1) * HG + (j - cum[p])];
             key[i] = f32_ord(__uint_as_float(e.x));
             id[i] = e.y;
@@ -625,7 +633,8 @@ static void refine_d(const RefineArgs& a, hipStream_t s)
 void launch_refine(int dtype, const RefineArgs& a, hipStream_t s)
 {
     if (a.m <= 0) return;
-    if ((int64_t)a.nseg * a.G > RF_MAXN || a.C > 256) fail(RKMIPS_EINVAL, "internal: too many candidates per user");
+    if ((int64_t)a.nseg * a.G > RF_MAXN || a.C > 256 || a.nseg > 32)
+        fail(RKMIPS_EINVAL, "internal: too many candidates per user");
     if (dtype == DT_F32) refine_d<DT_F32>(a, s);
     else if (dtype == DT_BF16) refine_d<DT_BF16>(a, s);
     else refine_d<DT_FP8>(a, s);

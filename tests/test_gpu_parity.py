@@ -124,6 +124,28 @@ def test_wide_refine_with_tied_scores(R, cfg, d, k_max):
         idx.close()
 
 
+@pytest.mark.parametrize("cfg, n, m, d, k_max", [("c5", 1 << 18, 2000, 32, 4), ("c3", 150_000, 1500, 32, 10),
+                                                ("c2", 100_000, 1000, 16, 4)])
+def test_many_item_segments(R, cfg, n, m, d, k_max):
+    """Few users and many items: the top-k pass splits the items into up to 16 segments to
+    fill the GPU (small k gives small per-user buffers), and the refine must gather the
+    candidates and thresholds of every segment.  (Reading only the first four once gave
+    lambda values below Definition 1's, with the certificate passing.)"""
+    w = I.make(cfg, n=n, m=m, d=d, nq=6, seed=n + k_max)
+    ks = np.array([1, k_max, 2, k_max, 1, k_max], np.int32)
+    lam, mem = _oracle_sets(w, ks, k_max)
+    idx = _build(R, w, k_max)
+    try:
+        print("candidates per user", idx.info["cand_per_user"], "certificate failures", idx.info["cert_failures"],
+              flush=True)
+        assert idx.info["cert_failures"] < w.m   # the certified path ran
+        _check_lambda(idx, lam, k_max)
+        got = idx.query(w.queries, w.query_scales, ks)
+        _lists_equal(got, [np.flatnonzero(mem[i]) for i in range(len(ks))])
+    finally:
+        idx.close()
+
+
 @pytest.mark.parametrize("n,m,d,k_max", [(7, 33, 20, 10), (1, 1, 1, 1), (300, 777, 64, 50), (129, 257, 100, 16)])
 def test_ragged_and_degenerate_shapes(R, n, m, d, k_max):
     w = I.make("c2", n=n, m=m, d=d, nq=45, seed=n + m)
