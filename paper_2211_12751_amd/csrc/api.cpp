@@ -545,8 +545,13 @@ static void build_index(Index& x, const void* items, const float* item_scales, c
             // many items it starts once the item order and the padded copies are done: its
             // row gathers would slow those copies several times over and delay the seed
             // pass (with few items the copies are short and the Cone-Tree sets the build).
-            if (x.n_lam >= kMainWaitsItems) HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
-            build_cone(x, users, user_scales, n2_users_orig.d(), s2, nullptr, cone_work, &wk.cancel);
+            // After that wait the padded FP8 codes are complete, and the split products run
+            // on them (half the bytes of BF16 unit rows).
+            const bool after_copies = x.n_lam >= kMainWaitsItems;
+            if (after_copies) HIPC(hipStreamWaitEvent(s2, ev.ev[1], 0));
+            const bool codes = after_copies && x.dtype == RKMIPS_FP8_E4M3;
+            build_cone(x, users, user_scales, n2_users_orig.d(), s2, nullptr, cone_work, &wk.cancel,
+                       codes ? (const uint8_t*)users_o.p : nullptr);
             if (wk.cancel.load()) {
                 wk.queued();
                 return;

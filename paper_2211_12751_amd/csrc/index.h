@@ -173,9 +173,11 @@ struct ConeWork {
 // the host after the first batch of levels is on the stream, before the host's first
 // wait for them (work for other streams can be enqueued there).
 // `cancel` (optional) is checked after each host wait: once set, the build stops there.
+// `codes_padded` (optional, FP8 data): the users' codes in original order with rows of
+// x.ld bytes, complete on `s`; the split products then run on them instead of BF16 unit rows.
 void build_cone(Index& x, const void* users, const float* user_scales, const double* user_n2_orig,
                 hipStream_t s, const std::function<void()>& enqueued, ConeWork& cw,
-                const std::atomic<bool>* cancel = nullptr);
+                const std::atomic<bool>* cancel = nullptr, const uint8_t* codes_padded = nullptr);
 // L^j(B) for every block; lb_rows (optional): the lambda refine's leaf-order rows of
 // lambda_u^(j) / ||u|| ([m x k_max]), else gathered from the lambda table
 void finish_blocks(Index& x, hipStream_t s, const double* lb_rows = nullptr);

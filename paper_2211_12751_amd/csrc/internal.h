@@ -99,7 +99,9 @@ void launch_fallback(int dtype, const RefineArgs& a, double* scratch, int64_t sc
 
 // ---------------------------------------------------------------- cone tree
 struct ConeLevelArgs {
-    const uint16_t* unit;  // [m x ld] BF16 unit users (original order)
+    const uint16_t* unit;  // [m x ld] BF16 unit users (original order), or
+    const uint8_t* codes;  // [m x ld] FP8 codes (original order) with
+    const float* fac;      // [m] scale / ||u|| per user: the unit vector is fac x codes
     int ld, d;
     const uint32_t* perm;  // position -> user
     const int64_t* seg_start;  // [nseg+1] this level's segments (sorted, last = m)

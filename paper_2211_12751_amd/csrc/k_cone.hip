@@ -83,6 +83,49 @@ __device__ __forceinline__ float row_dot(const uint16_t* a, const uint16_t* b, i
     return acc;
 }
 
+typedef float cone_f32x2 __attribute__((ext_vector_type(2)));
+
+// <a, b> of two rows of FP8 codes (ld of 32, 64, 128 or 256 bytes) in FP32: the code
+// products are exact, their sum rounds.  One 128-byte line of both rows per step, as above.
+__device__ __forceinline__ float row_dot_fp8(const uint8_t* a, const uint8_t* b, int ld)
+{
+    float acc = 0.f;
+    for (int c0 = 0; c0 < ld; c0 += 128) {
+        const int nv = ld - c0 < 128 ? (ld - c0) / 16 : 8;
+        i32x4 x[8], y[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            if (j < nv) {
+                x[j] = *(const i32x4*)(a + c0 + 16 * j);
+                y[j] = *(const i32x4*)(b + c0 + 16 * j);
+            }
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            if (j < nv) {
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const cone_f32x2 xl = __builtin_amdgcn_cvt_pk_f32_fp8(x[j][e], false);
+                    const cone_f32x2 xh = __builtin_amdgcn_cvt_pk_f32_fp8(x[j][e], true);
+                    const cone_f32x2 yl = __builtin_amdgcn_cvt_pk_f32_fp8(y[j][e], false);
+                    const cone_f32x2 yh = __builtin_amdgcn_cvt_pk_f32_fp8(y[j][e], true);
+                    acc = fmaf(xl[0], yl[0], acc);
+                    acc = fmaf(xl[1], yl[1], acc);
+                    acc = fmaf(xh[0], yh[0], acc);
+                    acc = fmaf(xh[1], yh[1], acc);
+                }
+            }
+    }
+    return acc;
+}
+
+// cos(u_a, u_b) of two users (original indices) from the level's row form
+template <bool F8>
+__device__ __forceinline__ float cone_dot(const ConeLevelArgs& a, int64_t ua, int64_t ub)
+{
+    if constexpr (F8) return (a.fac[ua] * a.fac[ub]) * row_dot_fp8(a.codes + ua * a.ld, a.codes + ub * a.ld, a.ld);
+    else return row_dot(a.unit + ua * a.ld, a.unit + ub * a.ld, a.ld);
+}
+
 // Argmin keys of an active segment are spread over KEY_WAYS slots (chosen by the
 // workgroup) so that the waves of a large segment do not all meet on one address;
 // readers take the minimum over the slots.
@@ -105,6 +148,7 @@ __device__ __forceinline__ unsigned long long key_min(const unsigned long long* 
 // phase 0: argmin <u, v> -> key1;  phase 1: dot_l and argmin <u, u_l> -> key2;
 // phase 2: side flags, their ranks inside the workgroup's block of positions and the
 // block's count (the left count of a segment is a difference of two global ranks).
+template <bool F8>
 __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
 {
     if (a.ctl[2] == 0) return;   // no active segment at this level (workgroup-uniform)
@@ -119,19 +163,19 @@ __global__ __launch_bounds__(256) void k_cone_phase(ConeLevelArgs a, int phase)
         const int s = a.seg[p];
         ai = a.act[s];
         if (ai >= 0) {
-            const uint16_t* up = a.unit + (int64_t)a.perm[p] * a.ld;
+            const int64_t up = a.perm[p];
             if (phase == 0) {
                 const int64_t st = a.seg_start[s], sz = a.seg_start[s + 1] - st;
-                const float dv = row_dot(up, a.unit + (int64_t)a.perm[cone_pivot(a, st, sz)] * a.ld, a.ld);
+                const float dv = cone_dot<F8>(a, up, a.perm[cone_pivot(a, st, sz)]);
                 key = ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p;
             } else if (phase == 1) {
                 const int64_t pl = (int64_t)(key_min(a.key1, ai) & 0xffffffffull);
-                const float dl = row_dot(up, a.unit + (int64_t)a.perm[pl] * a.ld, a.ld);
+                const float dl = cone_dot<F8>(a, up, a.perm[pl]);
                 a.dot_l[p] = dl;
                 key = ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p;
             } else {
                 const int64_t pr = (int64_t)(key_min(a.key2, ai) & 0xffffffffull);
-                const float dr = row_dot(up, a.unit + (int64_t)a.perm[pr] * a.ld, a.ld);
+                const float dr = cone_dot<F8>(a, up, a.perm[pr]);
                 lf = a.dot_l[p] >= dr ? 1 : 0;
             }
         }
@@ -350,6 +394,7 @@ __device__ __forceinline__ unsigned long long wg_min_u64(unsigned long long v, u
     return r;
 }
 
+template <bool F8>
 __global__ __launch_bounds__(256) void k_cone_local(ConeLevelArgs a, uint32_t* tmp_perm, int* is_start)
 {
     __shared__ int64_t stk_st[CL_STACK];
@@ -384,30 +429,30 @@ __global__ __launch_bounds__(256) void k_cone_local(ConeLevelArgs a, uint32_t* t
         // random point v, u_l, u_r
         const uint64_t rr = splitmix64(a.seed ^ splitmix64(((uint64_t)lv << 40) ^ (uint64_t)st));
         const int64_t pv = st + (int64_t)(rr % (uint64_t)sz);
-        const uint16_t* vrow = a.unit + (int64_t)perm[pv] * a.ld;
+        const int64_t vrow = perm[pv];
         unsigned long long k = ~0ull;
         for (int i = tid; i < sz; i += 256) {
             const int64_t p = st + i;
-            const float dv = row_dot(a.unit + (int64_t)perm[p] * a.ld, vrow, a.ld);
+            const float dv = cone_dot<F8>(a, perm[p], vrow);
             const unsigned long long key = ((unsigned long long)f32_ord(dv) << 32) | (unsigned long long)p;
             k = key < k ? key : k;
         }
         const int64_t pl = (int64_t)(wg_min_u64(k, red) & 0xffffffffull);
-        const uint16_t* lrow = a.unit + (int64_t)perm[pl] * a.ld;
+        const int64_t lrow = perm[pl];
         k = ~0ull;
         for (int i = tid; i < sz; i += 256) {
             const int64_t p = st + i;
-            const float dl = row_dot(a.unit + (int64_t)perm[p] * a.ld, lrow, a.ld);
+            const float dl = cone_dot<F8>(a, perm[p], lrow);
             a.dot_l[p] = dl;
             const unsigned long long key = ((unsigned long long)f32_ord(dl) << 32) | (unsigned long long)p;
             k = key < k ? key : k;
         }
         const int64_t pr = (int64_t)(wg_min_u64(k, red) & 0xffffffffull);
-        const uint16_t* rrow = a.unit + (int64_t)perm[pr] * a.ld;
+        const int64_t rrow = perm[pr];
         int nl_mine = 0;
         for (int i = tid; i < sz; i += 256) {
             const int64_t p = st + i;
-            const float dr = row_dot(a.unit + (int64_t)perm[p] * a.ld, rrow, a.ld);
+            const float dr = cone_dot<F8>(a, perm[p], rrow);
             const int lf = a.dot_l[p] >= dr ? 1 : 0;
             a.left[p] = lf;
             nl_mine += lf;
@@ -569,6 +614,15 @@ __global__ void k_unit(const void* X, const float* scales, const double* n2, int
     *(i32x4*)(out + t * 8) = i32x4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
 }
 
+// scale / ||u|| per user (0 for a zero user), the factor of its FP8 code row
+__global__ void k_unit_fac(const float* scales, const double* n2, int64_t rows, float* fac)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const double nn = n2[r];
+    fac[r] = nn > 0.0 ? (float)((double)scales[r] / sqrt(nn)) : 0.f;
+}
+
 // Per block (one wave, one user per lane): unit centre (FP64 mean of the unit user
 // rows, normalised), per-user cos/sin of the angle theta_u between u and the centre
 // (FP64 from the stored values), and cos/sin of a cone angle omega >= max theta_u.
@@ -722,20 +776,29 @@ __global__ __launch_bounds__(256) void k_block_lb_rows(const double* rows, const
 
 // ------------------------------------------------------------------ host orchestration
 void build_cone(Index& x, const void* users, const float* user_scales, const double* n2_orig, hipStream_t s,
-                const std::function<void()>& enqueued, ConeWork& cw, const std::atomic<bool>* cancel)
+                const std::function<void()>& enqueued, ConeWork& cw, const std::atomic<bool>* cancel,
+                const uint8_t* codes_padded)
 {
     const int64_t m = x.m;
     const int ld = x.ld;
     DevBuf &unit = cw.unit, &perm_a = cw.perm_a, &perm_b = cw.perm_b, &seg_a = cw.seg_a, &seg_b = cw.seg_b;
     DevBuf &dot_l = cw.dot_l, &left = cw.left, &lrank = cw.lrank, &blk_cnt = cw.blk_cnt;
-    unit.alloc(sizeof(uint16_t) * (size_t)m * ld);
-    {
+    // FP8 users with their padded code rows at hand: the split products run on the codes
+    // (half the bytes of BF16 unit rows), each row's factor scale / ||u|| applied after
+    const bool f8 = x.dtype == DT_FP8 && codes_padded;
+    if (f8) {
+        unit.alloc(sizeof(float) * (size_t)m);
+        hipLaunchKernelGGL(k_unit_fac, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, user_scales, n2_orig, m,
+                           unit.f());
+    } else {
+        unit.alloc(sizeof(uint16_t) * (size_t)m * ld);
         const int64_t tot = m * ld / 8;
         dim3 g((unsigned)((tot + 255) / 256)), b(256);
         if (x.dtype == DT_F32) hipLaunchKernelGGL(k_unit<DT_F32>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());
         else if (x.dtype == DT_BF16) hipLaunchKernelGGL(k_unit<DT_BF16>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());
         else hipLaunchKernelGGL(k_unit<DT_FP8>, g, b, 0, s, users, user_scales, n2_orig, m, x.d, ld, unit.u16());
     }
+    HIPC(hipGetLastError());
     perm_a.alloc(sizeof(uint32_t) * m);
     perm_b.alloc(sizeof(uint32_t) * m);
     dot_l.alloc(sizeof(float) * m);
@@ -776,7 +839,13 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     auto level_args = [&](int level) {
         const int c = level & 1, n = c ^ 1;
         ConeLevelArgs a{};
-        a.unit = unit.u16(); a.ld = ld; a.d = x.d; a.perm = perm_a.u32();
+        if (f8) {
+            a.codes = codes_padded;
+            a.fac = unit.f();
+        } else {
+            a.unit = unit.u16();
+        }
+        a.ld = ld; a.d = x.d; a.perm = perm_a.u32();
         a.seg_start = d_start[c].i64(); a.next_start = d_start[n].i64();
         a.ctl = d_ctl.i64(); a.ctl_cur = c; a.level = level; a.leaf = x.prm.leaf_size;
         a.seed = x.prm.seed; a.m = m;
@@ -803,7 +872,10 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     while ((m >> L0) > CL_TARGET) L0++;
     for (int level = 0; level < L0; level++) {
         const ConeLevelArgs a = level_args(level);
-        for (int ph = 0; ph < 3; ph++) hipLaunchKernelGGL(k_cone_phase, dim3(grid), dim3(256), 0, s, a, ph);
+        for (int ph = 0; ph < 3; ph++) {
+            if (f8) hipLaunchKernelGGL(k_cone_phase<true>, dim3(grid), dim3(256), 0, s, a, ph);
+            else hipLaunchKernelGGL(k_cone_phase<false>, dim3(grid), dim3(256), 0, s, a, ph);
+        }
         hipLaunchKernelGGL(k_cone_next, dim3(1), dim3(CN_THREADS), 0, s, a);
         hipLaunchKernelGGL(k_cone_scatter, dim3(grid), dim3(256), 0, s, a, perm_b.u32());
         HIPC(hipGetLastError());
@@ -817,7 +889,8 @@ void build_cone(Index& x, const void* users, const float* user_scales, const dou
     {
         const ConeLevelArgs a = level_args(L0);
         const unsigned lgrid = (unsigned)std::min<int64_t>((int64_t)1 << L0, m);
-        hipLaunchKernelGGL(k_cone_local, dim3(lgrid), dim3(256), 0, s, a, perm_b.u32(), is_start);
+        if (f8) hipLaunchKernelGGL(k_cone_local<true>, dim3(lgrid), dim3(256), 0, s, a, perm_b.u32(), is_start);
+        else hipLaunchKernelGGL(k_cone_local<false>, dim3(lgrid), dim3(256), 0, s, a, perm_b.u32(), is_start);
         HIPC(hipGetLastError());
     }
     x.block_start.alloc(sizeof(int64_t) * (size_t)(m + 1));

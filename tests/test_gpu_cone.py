@@ -18,10 +18,13 @@ pytestmark = pytest.mark.gpu
                                                           ("bf16", 400, 2000, 64, 8, True),
                                                           ("fp8", 300, 1500, 40, 5, True),
                                                           ("bf16", 400, 1200, 64, 100, True),
-                                                          ("fp8", 300, 900, 128, 70, False)])
+                                                          ("fp8", 300, 900, 128, 70, False),
+                                                          ("fp8", 1 << 18, 2000, 32, 4, True)])
 def test_blocks_valid_and_bound_data_exact(dtype, n, m, d, k_max, cert):
     """k_max above 64 takes more than one column per lane in the bound pass; without the
-    certificate every lambda row (and its bound row) comes from the full rescoring."""
+    certificate every lambda row (and its bound row) comes from the full rescoring.  With
+    2^18 items and more, FP8 builds split the tree on the users' padded code rows and
+    per-user factors instead of BF16 unit rows."""
     from paper_2211_12751_amd import rkmips as R
     name = {"f32": "c1", "bf16": "c3", "fp8": "c5"}[dtype]
     w = I.make(name, n=n, m=m, d=d, nq=1, seed=m)
