@@ -125,7 +125,8 @@ def test_wide_refine_with_tied_scores(R, cfg, d, k_max):
 
 
 @pytest.mark.parametrize("cfg, n, m, d, k_max", [("c5", 1 << 18, 2000, 32, 4), ("c3", 150_000, 1500, 32, 10),
-                                                ("c2", 100_000, 1000, 16, 4)])
+                                                ("c2", 100_000, 1000, 16, 4), ("c2", 20_000, 300, 16, 2),
+                                                ("c3", 30_000, 200, 64, 8), ("c5", 12_000, 100, 128, 1)])
 def test_many_item_segments(R, cfg, n, m, d, k_max):
     """Few users and many items: the top-k pass splits the items into up to 16 segments to
     fill the GPU (small k gives small per-user buffers), and the refine must gather the
