@@ -133,7 +133,7 @@ def test_many_item_segments(R, cfg, n, m, d, k_max):
     candidates and thresholds of every segment.  (Reading only the first four once gave
     lambda values below Definition 1's, with the certificate passing.)"""
     w = I.make(cfg, n=n, m=m, d=d, nq=6, seed=n + k_max)
-    ks = np.array([1, k_max, 2, k_max, 1, k_max], np.int32)
+    ks = np.minimum(np.array([1, k_max, 2, k_max, 1, k_max], np.int32), k_max)
     lam, mem = _oracle_sets(w, ks, k_max)
     idx = _build(R, w, k_max)
     try:
