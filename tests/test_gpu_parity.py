@@ -147,6 +147,29 @@ def test_many_item_segments(R, cfg, n, m, d, k_max):
         idx.close()
 
 
+@pytest.mark.parametrize("cfg, n, m, d, k_max, slack", [
+    ("c5", 70_000, 300, 200, 3, 14),     # FP8 rows of 256 codes: the FP8 seed pass, many segments
+    ("c5", 40_000, 500, 129, 60, 14),    # C = 74 > 64: the wide rescoring, two segments
+    ("c3", 20_000, 700, 7, 1, 0),        # C = 1, no slack
+    ("c3", 60_000, 90, 33, 17, 40),      # one user tile, the most segments
+    ("c2", 9_000, 3000, 1, 5, 14),       # d = 1: scores are products of two numbers, many ties
+    ("c2", 25_000, 1200, 64, 120, 14),   # C = 134 with the split FP32 operands
+])
+def test_config_sweep_lambda(R, cfg, n, m, d, k_max, slack):
+    """Shapes across the top-k pass's structural thresholds (seed on or off, FP8 seed
+    rows, candidate buffers of 128 to 1,024 entries, one to sixteen item segments, the
+    narrow and wide rescoring): lambda64 and lambda32 equal Definition 1's."""
+    w = I.make(cfg, n=n, m=m, d=d, nq=1, seed=7 * n + m + d)
+    lam = O.lambda_table(w.dtype, w.items, w.item_scales, w.users, w.user_scales, k_max)
+    idx = _build(R, w, k_max, topk_slack=slack)
+    try:
+        print("candidates per user", idx.info["cand_per_user"], "certificate failures", idx.info["cert_failures"],
+              flush=True)
+        _check_lambda(idx, lam, k_max)
+    finally:
+        idx.close()
+
+
 @pytest.mark.parametrize("n,m,d,k_max", [(7, 33, 20, 10), (1, 1, 1, 1), (300, 777, 64, 50), (129, 257, 100, 16)])
 def test_ragged_and_degenerate_shapes(R, n, m, d, k_max):
     w = I.make("c2", n=n, m=m, d=d, nq=45, seed=n + m)
