@@ -170,6 +170,27 @@ def test_config_sweep_lambda(R, cfg, n, m, d, k_max, slack):
         idx.close()
 
 
+@pytest.mark.parametrize("cfg, n, m, d, k_max, nq, flags", [
+    ("c5", 3000, 5000, 256, 30, 1500, 0),    # FP8 rows of 256 codes, 30 distinct k (four launches)
+    ("c3", 200, 100, 1, 5, 77, 0),           # fewer users than one workgroup's tile, d = 1
+    ("c2", 5000, 4097, 64, 50, 33, 0),       # a ragged user tile, one k for every query
+    ("c3", 4000, 2600, 128, 64, 300, 128),   # the pool list path
+])
+def test_query_sweep_sets(R, cfg, n, m, d, k_max, nq, flags):
+    """Query batches across the verify pass's thresholds (user tiles, query tiles, k groups,
+    the answer-bit and pool list paths): every list equals Definition 1's set."""
+    w = I.make(cfg, n=n, m=m, d=d, nq=nq, seed=3 * n + m + nq)
+    g = np.random.default_rng(nq + d)
+    ks = (g.integers(0, k_max, nq) + 1).astype(np.int32) if nq != 33 else np.full(nq, k_max, np.int32)
+    lam, mem = _oracle_sets(w, ks, k_max)
+    idx = _build(R, w, k_max)
+    try:
+        got = idx.query(w.queries, w.query_scales, ks, flags=flags)
+        _lists_equal(got, [np.flatnonzero(mem[i]) for i in range(nq)])
+    finally:
+        idx.close()
+
+
 @pytest.mark.parametrize("n,m,d,k_max", [(7, 33, 20, 10), (1, 1, 1, 1), (300, 777, 64, 50), (129, 257, 100, 16)])
 def test_ragged_and_degenerate_shapes(R, n, m, d, k_max):
     w = I.make("c2", n=n, m=m, d=d, nq=45, seed=n + m)
