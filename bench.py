@@ -324,10 +324,10 @@ def serving_leg(args, w):
     h = run.build()
     try:
         R.rkmips_index_wait(h)
-        # saturation: every request at time 0, after one untimed replay (the server's first
-        # call allocates its slot buffers)
+        # saturation: every request at time 0, after one untimed replay of the whole request
+        # set (the server's first call allocates its slot buffers and result space)
         sp = R.rkmips_serve_params(max_batch, streams, 0, 0)
-        hr, lat, st = R.rkmips_serve_replay(h, Qh[:2048], None, 2048, kk[:2048], np.zeros(2048, np.int64), sp)
+        hr, lat, st = R.rkmips_serve_replay(h, Qh, None, nreq, kk, np.zeros(nreq, np.int64), sp)
         R.rkmips_result_free(hr)
         hr, lat, st = R.rkmips_serve_replay(h, Qh[:8192], None, 8192, kk[:8192], np.zeros(8192, np.int64), sp)
         R.rkmips_result_free(hr)
