@@ -29,7 +29,9 @@ def test_insert_equals_fresh_build(dtype, n0, n_new):
             assert np.array_equal(a.lam(k), b.lam(k)), f"lambda k={k}"
             assert np.array_equal(a.lam32(k), b.lam32(k))
         assert np.array_equal(a.item_order(), b.item_order())
-        for x, y in list(zip(a.saalsh(), b.saalsh())) + list(zip(a.blocks(), b.blocks())):
+        ab, bb = a.blocks(), b.blocks()   # dicts of arrays: compare the arrays, key by key
+        assert ab.keys() == bb.keys()
+        for x, y in list(zip(a.saalsh(), b.saalsh())) + [(ab[k], bb[k]) for k in ab]:
             x, y = np.asarray(x), np.asarray(y)
             assert x.shape == y.shape and x.tobytes() == y.tobytes()
         lam = O.lambda_table(dtype, w.items, sc, w.users, w.user_scales, k_max)

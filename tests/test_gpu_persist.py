@@ -34,7 +34,9 @@ def test_save_load_round_trip(tmp_path, dtype, mode):
                     assert np.array_equal(gb[qi], np.flatnonzero(mem[qi]))
             for k in (1, 10):
                 assert np.array_equal(a.lam(k), b.lam(k)) and np.array_equal(a.lam32(k), b.lam32(k))
-            for x, y in list(zip(a.blocks(), b.blocks())) + list(zip(a.saalsh(), b.saalsh())):
+            ab, bb = a.blocks(), b.blocks()   # dicts of arrays: compare the arrays, key by key
+            assert ab.keys() == bb.keys()
+            for x, y in [(ab[k], bb[k]) for k in ab] + list(zip(a.saalsh(), b.saalsh())):
                 x, y = np.asarray(x), np.asarray(y)   # bit patterns (NaN centres of degenerate blocks)
                 assert x.shape == y.shape and x.tobytes() == y.tobytes()
             assert np.array_equal(a.item_order(), b.item_order())
